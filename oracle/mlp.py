@@ -1,0 +1,146 @@
+"""Stencil-prediction network (oracle, FP64).  TEST INFRASTRUCTURE ONLY.
+
+Project extension, not in the paper.  The paper's stencils depend only on
+the position class (Section 3.2); the medium-weighted per-point fit
+(oracle.stencil.fit_point_weighted) makes them depend on the local medium,
+and this small network predicts that dependence from the 5^3 patch of m
+around an interior point:
+
+  features : Re, Im of m on the 5^3 patch (last dimension fastest, m = 0 off
+             the grid), divided by 0.3                         -> 250 inputs
+  network  : 250 -> 256 (GELU) -> 256 (GELU) -> 468, GELU(x) = x Phi(x)
+             (exact erf form)
+  target   : the 26 off-centre 3x3 complex blocks of the gauge-fixed
+             correction alpha~_i - alpha~_class (centre block = I), entries
+             [block, c, r] with real and imaginary parts interleaved -> 468
+  loss     : mean of squared errors over batch and outputs
+  optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights
+
+Pins: central finite differences of the loss against backward(); a BF16
+weight mode compares at BF16 resolution (tests/test_oracle_mlp.py).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erf
+
+from .stencil import centre_index
+
+D_IN, D_HID, D_OUT = 250, 256, 468
+PATCH_RADIUS = 2
+M_SCALE = 0.3
+
+
+def patch_features(m: np.ndarray, points) -> np.ndarray:
+    """(len(points), 250) features of the 5^3 patches around 0-based points."""
+    n = m.shape[0]
+    pad = np.zeros((n + 4, n + 4, n + 4), dtype=np.complex128)
+    pad[2:-2, 2:-2, 2:-2] = m
+    out = np.empty((len(points), D_IN))
+    for t, (i1, i2, i3) in enumerate(points):
+        p = pad[i1:i1 + 5, i2:i2 + 5, i3:i3 + 5].reshape(-1) / M_SCALE
+        out[t, 0::2] = p.real
+        out[t, 1::2] = p.imag
+    return out
+
+
+def encode_target(alpha_tilde: np.ndarray, alpha_tilde_class: np.ndarray) -> np.ndarray:
+    """468 reals from the off-centre blocks of alpha~ - alpha~_class (interior class)."""
+    c0 = centre_index(13)
+    d = alpha_tilde - alpha_tilde_class
+    blocks = [d[3 * a:3 * a + 3, :] for a in range(27) if a != c0]     # [c, r]
+    z = np.concatenate([b.reshape(-1) for b in blocks])                # 234 complex
+    out = np.empty(D_OUT)
+    out[0::2] = z.real
+    out[1::2] = z.imag
+    return out
+
+
+def decode_output(y: np.ndarray, alpha_tilde_class: np.ndarray) -> np.ndarray:
+    """alpha^ = alpha~_class + correction; centre block stays I.  y has 468 entries."""
+    c0 = centre_index(13)
+    z = y[0::2] + 1j * y[1::2]
+    out = alpha_tilde_class.astype(np.complex128).copy()
+    t = 0
+    for a in range(27):
+        if a == c0:
+            continue
+        out[3 * a:3 * a + 3, :] += z[9 * t:9 * t + 9].reshape(3, 3)
+        t += 1
+    return out
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+
+
+def gelu_grad(x):
+    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def init_params(seed: int):
+    """He-normal weights (seeded), zero biases.  W_l has shape (fan_in, fan_out)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    dims = [(D_IN, D_HID), (D_HID, D_HID), (D_HID, D_OUT)]
+    params = {}
+    for l, (fi, fo) in enumerate(dims, start=1):
+        params[f"W{l}"] = g.standard_normal((fi, fo)) * math.sqrt(2.0 / fi)
+        params[f"b{l}"] = np.zeros(fo)
+    return params
+
+
+def forward(params, x):
+    """Returns (y, cache) for a batch x of shape (B, 250)."""
+    z1 = x @ params["W1"] + params["b1"]
+    h1 = gelu(z1)
+    z2 = h1 @ params["W2"] + params["b2"]
+    h2 = gelu(z2)
+    y = h2 @ params["W3"] + params["b3"]
+    return y, (x, z1, h1, z2, h2)
+
+
+def loss(y, t):
+    return float(np.mean((y - t) ** 2))
+
+
+def backward(params, cache, y, t):
+    """Gradients of loss(y, t) with respect to every parameter."""
+    x, z1, h1, z2, h2 = cache
+    dy = 2.0 * (y - t) / y.size
+    grads = {"W3": h2.T @ dy, "b3": dy.sum(axis=0)}
+    dh2 = dy @ params["W3"].T
+    dz2 = dh2 * gelu_grad(z2)
+    grads["W2"] = h1.T @ dz2
+    grads["b2"] = dz2.sum(axis=0)
+    dh1 = dz2 @ params["W2"].T
+    dz1 = dh1 * gelu_grad(z1)
+    grads["W1"] = x.T @ dz1
+    grads["b1"] = dz1.sum(axis=0)
+    return grads
+
+
+def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update in place; state holds m, v and the step count."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for key in params:
+        mk, vk = "m_" + key, "v_" + key
+        state.setdefault(mk, np.zeros_like(params[key]))
+        state.setdefault(vk, np.zeros_like(params[key]))
+        state[mk] = b1 * state[mk] + (1 - b1) * grads[key]
+        state[vk] = b2 * state[vk] + (1 - b2) * grads[key] ** 2
+        mhat = state[mk] / (1 - b1 ** t)
+        vhat = state[vk] / (1 - b2 ** t)
+        params[key] = params[key] - lr * mhat / (np.sqrt(vhat) + eps)
+    return params
+
+
+def round_bf16(a: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
