@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark: Munknowns/s of the Lippmann-Schwinger (Nystrom) apply at 128^3.
+
+One step = one application y = x + K * (m x) (Eq. (5)) to a batch of 8
+right-hand sides on the 128^3 grid (6.29M unknowns each; padded FFT 256^3),
+with FP32 FFTs (complex64 fields), through the C ABI.  Inputs are seeded
+synthetic fields and a sum-of-Gaussians contrast, resident in HBM before the
+timed region starts.
+
+Prints one JSON line with the throughput, a roofline entry for the dominant
+kernel (algorithmic bytes per launch / average launch time, from HIP events
+recorded between the passes on the stream the kernels run on), the FP64 and
+mixed-precision rates, and the CPU oracle's apply timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+PASS_NAMES = ["dim1_fwd_mscale", "dim2_fwd", "dim3_fft_symbol_ifft", "dim2_inv", "dim1_inv_identity"]
+KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kernel",
+                "col_fft_kernel (mode 2)", "col_fft_kernel (mode 3)"]
+
+
+def pass_bytes(n: int, P: int, B: int, s: int, s_io: int) -> list[float]:
+    """Algorithmic HBM bytes of each pass for B right-hand sides.
+
+    s: bytes per complex in the FFT passes, s_io: bytes per complex of x and y.
+    pass 1 reads x and m (once per component) and writes P n^2 per component;
+    pass 3 also reads the octant symbol (6 (P/2+1)^3 values) once per launch.
+    """
+    n3 = n ** 3
+    H = P // 2 + 1
+    c = 3 * B
+    return [
+        c * (n3 * s_io + n3 * s + P * n * n * s),
+        c * (P * n * n * s + P * P * n * s),
+        c * (2 * P * P * n * s) + 6 * H ** 3 * s,
+        c * (P * P * n * s + P * n * n * s),
+        c * (P * n * n * s + 2 * n3 * s_io),
+    ]
+
+
+def cpu_baseline(n: int, seconds: float = 15.0):
+    """The oracle's FFT apply on the host, one rhs at a time, ~seconds of work."""
+    import numpy as np
+    from oracle import operator as op
+    from paper_1804_02297_amd import inputs as I
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 3)
+    x = I.random_field(1, n, 5)
+    t0 = time.perf_counter()
+    Kh = op.kernel_symbol(n, k)
+    t_setup = time.perf_counter() - t0
+    reps, t_apply = 0, 0.0
+    while t_apply < seconds and reps < 20:
+        t0 = time.perf_counter()
+        op.apply_fft(n, k, m, x, Kh)
+        t_apply += time.perf_counter() - t0
+        reps += 1
+    per = t_apply / reps
+    return {"value": round(3 * n ** 3 / per / 1e6, 3), "unit": "Munknowns/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"oracle FFT apply (scipy.fft, 1 worker, FP64) of 1 rhs at n={n}, "
+                      f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the apply shards by right-hand side, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1804_02297_amd import binding
+    from paper_1804_02297_amd import inputs as I
+
+    binding.load()
+    dev = torch.device("cuda:0")
+    n, B = args.n, args.nrhs
+    k = I.wavenumber_for(n)
+    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
+    plan = binding.Plan(n, k, m, max_rhs=B)
+    P = plan.P
+    g = torch.Generator(device=dev).manual_seed(1234)
+    x64 = torch.randn((B, 3, n, n, n), dtype=torch.complex128, device=dev, generator=g)
+    x32 = x64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    y64 = torch.empty_like(x64)
+    torch.cuda.synchronize()
+
+    def timed(prec, x, y, steps, warmup):
+        for _ in range(warmup):
+            plan.apply(x, y, prec=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            plan.apply(x, y, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / steps, wall
+
+    ms32, wall32 = timed("c64", x32, y32, args.steps, args.warmup)
+    # per-pass times over the same number of steps
+    pms = np.zeros(5)
+    for _ in range(max(3, min(args.steps, 20))):
+        pms += np.array(plan.apply_timed(x32, y32, prec="c64"))
+    pms /= max(3, min(args.steps, 20))
+    ms64, _ = timed("c128", x64, y64, max(5, args.steps // 2), 2)
+    msmx, _ = timed("mixed", x64, y64, max(5, args.steps // 2), 2)
+
+    unknowns = B * 3 * n ** 3
+    value = unknowns / (ms32 * 1e-3) / 1e6
+    pb = pass_bytes(n, P, B, 8, 8)
+    dom = int(np.argmax(pms))
+    achieved = pb[dom] / (pms[dom] * 1e-3) / 1e9
+    whole = sum(pb) / (ms32 * 1e-3) / 1e9
+
+    out = {
+        "metric": "Munknowns/s of LS apply at 128^3",
+        "value": round(value, 1),
+        "unit": "Munknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic: seeded sum-of-6-Gaussians contrast, random complex fields",
+        "config": {"workload": f"LS apply, n={n} (P={P}), {B} rhs, FP32 FFTs",
+                   "n": n, "fft_size": P, "nrhs": B, "unknowns_per_rhs": 3 * n ** 3},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "pass": PASS_NAMES[dom],
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "apply_whole_GBps": round(whole, 1),
+        "apply_whole_frac": round(whole / HBM_PEAK_GBS, 4),
+        "pass_ms": [round(v, 4) for v in pms],
+        "pass_GBps": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(pb, pms)],
+        "c128_Munknowns_per_s": round(unknowns / (ms64 * 1e-3) / 1e6, 1),
+        "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
+        "wall_s_timed": round(wall32, 3),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

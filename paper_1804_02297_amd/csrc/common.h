@@ -1,0 +1,85 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ls.h"
+#include "cplx.h"
+
+namespace ls {
+
+#define LS_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return LS_EHIP;              \
+  } while (0)
+
+#define LS_TRY(call)                                   \
+  do {                                                 \
+    ls_status s_ = (call);                             \
+    if (s_ != LS_OK) return s_;                        \
+  } while (0)
+
+// Supported padded FFT lengths (even, 2^a 3^b); P is the smallest of these >= 2n - 1.
+int choose_fft_size(int n);
+bool fft_size_supported(int P);
+
+// Device buffer with RAII release.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  ls_status alloc(size_t b) {
+    release();
+    if (b == 0) return LS_OK;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      return LS_ENOMEM;
+    }
+    bytes = b;
+    return LS_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Operator data owned by a plan: contrast, Khat in both precisions, twiddles
+// and the pass workspace of the FFT apply.
+struct ApplyPlan {
+  int n = 0, P = 0, H = 0;       // H = P/2 + 1 (octant extent)
+  double k = 0.0, h = 0.0;
+  int max_rhs = 1;
+  DevBuf m64, m32;               // contrast, complex128 / complex64, [n][n][n]
+  DevBuf kh64, kh32;             // octant symbol / P^3: [H][H][6][H]
+  DevBuf tw64, tw32;             // exp(-2 pi i t / P), t in [0, P)
+  DevBuf work;                   // pass intermediates
+  size_t work_per_rhs64 = 0;     // bytes per rhs in FP64
+};
+
+ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const void* m_dev,
+                          hipStream_t s);
+// y = x + K*(m x), or y = -K*(m x) when minus_conv; prec selects the kernel set.
+// nrhs <= max_rhs.  ev, when given, holds 6 events recorded around the 5 passes.
+ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
+                    bool minus_conv = false, hipEvent_t* ev = nullptr);
+
+}  // namespace ls
+
+struct ls_plan {
+  ls::ApplyPlan ap;
+  std::string tune_cache;
+  size_t host_mem_cap = 0;
+};

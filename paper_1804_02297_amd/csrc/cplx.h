@@ -1,0 +1,193 @@
+// Complex arithmetic and in-register small DFTs for the gfx950 FFT kernels.
+//
+// The small DFTs are unrolled completely at compile time: a length-N DFT on
+// an array held in VGPRs, decimation in time over its first factor (4, 2 or
+// 3), with the internal twiddles W_N^k = exp(-+2 pi i k / N) folded in as
+// compile-time constants.  Those constants come from a constexpr Taylor
+// series evaluated on an argument reduced to |phi| <= pi/4 with exact
+// integer arithmetic, so every constant is correctly rounded to about one
+// ulp of double.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ls {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) C {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ C<R> cmk(R a, R b) {
+  C<R> z;
+  z.re = a;
+  z.im = b;
+  return z;
+}
+template <typename R>
+__host__ __device__ __forceinline__ C<R> operator+(C<R> a, C<R> b) { return cmk(a.re + b.re, a.im + b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ C<R> operator-(C<R> a, C<R> b) { return cmk(a.re - b.re, a.im - b.im); }
+template <typename R>
+__host__ __device__ __forceinline__ C<R> operator*(C<R> a, C<R> b) {
+  return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ C<R> cscale(C<R> a, R s) { return cmk(a.re * s, a.im * s); }
+template <typename R>
+__host__ __device__ __forceinline__ C<R> cconj(C<R> a) { return cmk(a.re, -a.im); }
+// a * (-i) and a * (+i)
+template <typename R>
+__host__ __device__ __forceinline__ C<R> mul_mi(C<R> a) { return cmk(a.im, -a.re); }
+template <typename R>
+__host__ __device__ __forceinline__ C<R> mul_pi(C<R> a) { return cmk(-a.im, a.re); }
+// fused a + b*c
+template <typename R>
+__host__ __device__ __forceinline__ C<R> cfma(C<R> b, C<R> c, C<R> a) {
+  return cmk(a.re + b.re * c.re - b.im * c.im, a.im + b.re * c.im + b.im * c.re);
+}
+
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ C<To> ccast(C<Ti> a) { return cmk((To)a.re, (To)a.im); }
+
+// ---- compile-time twiddles -------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ct_sin_small(double x) {  // |x| <= pi/4
+  double t = x, s = x;
+  for (int i = 1; i < 14; ++i) {
+    t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double ct_cos_small(double x) {
+  double t = 1.0, s = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+// cos / sin of 2 pi k / N, exact quadrant reduction on integers.
+constexpr double ct_cos2pi(long k, long N) {
+  k %= N;
+  if (k < 0) k += N;
+  long q = (4 * k + N / 2) / N;            // nearest quarter turn
+  long r = 4 * k - q * N;                  // |r| <= N/2
+  double phi = (kPi / 2.0) * (double)r / (double)N;
+  double c = ct_cos_small(phi), s = ct_sin_small(phi);
+  switch (q & 3) {
+    case 0: return c;
+    case 1: return -s;
+    case 2: return -c;
+    default: return s;
+  }
+}
+constexpr double ct_sin2pi(long k, long N) {
+  k %= N;
+  if (k < 0) k += N;
+  long q = (4 * k + N / 2) / N;
+  long r = 4 * k - q * N;
+  double phi = (kPi / 2.0) * (double)r / (double)N;
+  double c = ct_cos_small(phi), s = ct_sin_small(phi);
+  switch (q & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+  }
+}
+
+// W_N^k for direction DIR (-1: forward exp(-2 pi i k/N), +1: inverse).
+template <typename R, int N, int DIR>
+__device__ __forceinline__ C<R> ctw(int k) {
+  return cmk<R>((R)ct_cos2pi(k, N), (R)(DIR * ct_sin2pi(k, N)));
+}
+
+// ---- in-register DFTs --------------------------------------------------------
+template <int N>
+struct FirstFactor {
+  static constexpr int value = (N % 4 == 0 && N > 8) ? 4 : (N % 2 == 0 ? 2 : (N % 3 == 0 ? 3 : N));
+};
+
+template <int N, int DIR, typename R>
+struct Dft;
+
+template <int DIR, typename R>
+struct Dft<1, DIR, R> {
+  static __device__ __forceinline__ void run(C<R>*) {}
+};
+
+template <int DIR, typename R>
+struct Dft<2, DIR, R> {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    C<R> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <int DIR, typename R>
+struct Dft<3, DIR, R> {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    // X0 = a+b+c; X1,2 = a - (b+c)/2 -+ i DIR... with s = sin(2pi/3)
+    const R s = (R)(0.86602540378443864676372317075293618);
+    C<R> a = v[0], b = v[1], c = v[2];
+    C<R> t = b + c;
+    C<R> d = b - c;
+    C<R> m = cmk<R>(a.re - (R)0.5 * t.re, a.im - (R)0.5 * t.im);
+    // DIR = -1: X1 = m - i s d ; X2 = m + i s d
+    C<R> isd = cmk<R>(-s * d.im, s * d.re);  // i s d
+    v[0] = a + t;
+    if (DIR < 0) {
+      v[1] = m - isd;
+      v[2] = m + isd;
+    } else {
+      v[1] = m + isd;
+      v[2] = m - isd;
+    }
+  }
+};
+
+template <int DIR, typename R>
+struct Dft<4, DIR, R> {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    C<R> a0 = v[0] + v[2], a1 = v[0] - v[2];
+    C<R> b0 = v[1] + v[3], b1 = v[1] - v[3];
+    C<R> jb1 = (DIR < 0) ? mul_mi(b1) : mul_pi(b1);
+    v[0] = a0 + b0;
+    v[2] = a0 - b0;
+    v[1] = a1 + jb1;
+    v[3] = a1 - jb1;
+  }
+};
+
+// Generic: N = F * M, input index f + F m, output index q + M s.
+template <int N, int DIR, typename R>
+struct Dft {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    constexpr int F = FirstFactor<N>::value;
+    constexpr int M = N / F;
+    static_assert(F * M == N && F > 1 && M > 1, "unsupported DFT length");
+    C<R> sub[F][M];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int m = 0; m < M; ++m) sub[f][m] = v[f + F * m];
+#pragma unroll
+    for (int f = 0; f < F; ++f) Dft<M, DIR, R>::run(sub[f]);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      C<R> t[F];
+#pragma unroll
+      for (int f = 0; f < F; ++f) t[f] = (f * q == 0) ? sub[f][q] : sub[f][q] * ctw<R, N, DIR>(f * q);
+      Dft<F, DIR, R>::run(t);
+#pragma unroll
+      for (int s = 0; s < F; ++s) v[q + M * s] = t[s];
+    }
+  }
+};
+
+}  // namespace ls

@@ -1,0 +1,550 @@
+// FFT-based Nystrom apply  y = x + K * (m x)  on gfx950.
+//
+// Paper: Eq. (5) and Eq. (6) - the convolution (Toeplitz) matrices are
+// applied by FFT on the uniform grid (Section 2; Section 3.3 gives the
+// O(N log N) cost).  Here the 3x3 dyadic tensor K is embedded in a circulant
+// of length P >= 2n - 1 per dimension, its FFT Khat is computed once per
+// plan in FP64, and every apply runs five HBM-streaming passes:
+//
+//   pass 1  dim 1 forward  (x, m) -> X1[b][c][q1][i2 i3]   n rows in, P out, u = m x fused
+//   pass 2  dim 2 forward  X1 -> X2[b][c][q1][q2][i3]       n rows in, P out
+//   pass 3  dim 3 forward, 3x3 multiply by Khat(q), dim 3 inverse, in place in X2
+//   pass 4  dim 2 inverse  X2 -> Y1[b][c][q1][i2][i3]       P rows in, n out
+//   pass 5  dim 1 inverse  y = x + Y1                      P rows in, n out, identity fused
+//
+// Zero padding is never materialised: forward passes read only the n
+// non-zero rows, inverse passes write only the n rows that are kept.
+//
+// Every 1-D transform is a four-step FFT of length P = N1 N2 held in
+// registers: a length-N2 DFT per thread, a twiddle by W_P^{j q}, one LDS
+// exchange, a length-N1 DFT per thread.  Passes 1, 2, 4, 5 transform along a
+// strided dimension: a workgroup owns T consecutive lines, so every global
+// access is a run of T consecutive elements (T = 16 or 32, 256 B) and the LDS
+// exchange is bank-conflict free (the line index is the fastest lane index).
+// Pass 3 transforms along the contiguous dimension; a workgroup owns one
+// octant line (f1, f2) of Khat and the up-to-four grid lines
+// (+-f1, +-f2) that share it, so Khat is read from HBM once per apply.
+#include <cmath>
+#include <cstdio>
+
+#include "common.h"
+
+namespace ls {
+
+enum ColMode { COL_P1 = 0, COL_FWD = 1, COL_INV = 2, COL_P5 = 3 };
+
+// ---- factor tables ----------------------------------------------------------
+struct Fac {
+  int n1, n2;
+};
+constexpr Fac col_factors(int P) {
+  switch (P) {
+    case 8: return {2, 4};
+    case 12: return {3, 4};
+    case 16: return {4, 4};
+    case 24: return {4, 6};
+    case 32: return {4, 8};
+    case 48: return {6, 8};
+    case 64: return {8, 8};
+    case 96: return {8, 12};
+    case 128: return {8, 16};
+    case 192: return {12, 16};
+    case 256: return {16, 16};
+    case 384: return {16, 24};
+    case 512: return {16, 32};
+    case 768: return {24, 32};
+    default: return {0, 0};
+  }
+}
+// Pass 3 uses the same factorisation (its 3x3 multiply runs out of LDS slots).
+template <typename R>
+constexpr Fac row_factors(int P) {
+  return col_factors(P);
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// Lines per workgroup of the strided passes: a 256-byte run per row, LDS <= 64 KB.
+template <typename R>
+constexpr int col_tile(int P) {
+  int t = (sizeof(R) == 8) ? 16 : 32;
+  while (t > 8 && (long)P * t * 2 * (long)sizeof(R) > 65536) t /= 2;
+  return t;
+}
+
+static const int kSizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768};
+
+int choose_fft_size(int n) {
+  for (int P : kSizes)
+    if (P >= 2 * n - 1) return P;
+  return 0;
+}
+bool fft_size_supported(int P) {
+  for (int s : kSizes)
+    if (s == P) return true;
+  return false;
+}
+
+// ---- strided-dimension four-step FFT ----------------------------------------
+// Lines are contiguous (index `line` in [0, L)); the transform runs along rows
+// with stride L.  Block = T lines x TPL threads, blockIdx.x = batch * ntiles + tile.
+template <typename R, typename IO, int P, int N1, int N2, int T, int MODE>
+__global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
+    const void* __restrict__ in_, void* __restrict__ out_, const C<R>* __restrict__ mfac,
+    const C<R>* __restrict__ tw, int rows_in, int rows_out, long L, long in_bstride,
+    long out_bstride, int ntiles, R scale) {
+  constexpr int DIR = (MODE == COL_P1 || MODE == COL_FWD) ? -1 : 1;
+  __shared__ C<R> ex[N1 * N2 * T];
+  const int tid = threadIdx.x;
+  const int t = tid % T;
+  const int j = tid / T;
+  const long batch = blockIdx.x / ntiles;
+  const int tile = blockIdx.x % ntiles;
+  const long line = (long)tile * T + t;
+  const bool live = line < L;
+
+  if (j < N1) {
+    C<R> v[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) {
+      const int row = j + N1 * k;
+      C<R> z = cmk<R>(0, 0);
+      if (live && row < rows_in) {
+        const long off = batch * in_bstride + (long)row * L + line;
+        if (MODE == COL_P1) {
+          C<IO> xv = reinterpret_cast<const C<IO>*>(in_)[off];
+          z = ccast<R>(xv) * mfac[(long)row * L + line];
+        } else {
+          z = reinterpret_cast<const C<R>*>(in_)[off];
+        }
+      }
+      v[k] = z;
+    }
+    Dft<N2, DIR, R>::run(v);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) {
+      C<R> w = tw[j * q];
+      if (DIR > 0) w = cconj(w);
+      ex[(j * N2 + q) * T + t] = (j * q == 0) ? v[q] : v[q] * w;
+    }
+  }
+  __syncthreads();
+  if (j < N2) {
+    C<R> w[N1];
+#pragma unroll
+    for (int jj = 0; jj < N1; ++jj) w[jj] = ex[(jj * N2 + j) * T + t];
+    Dft<N1, DIR, R>::run(w);
+    if (live) {
+#pragma unroll
+      for (int q1 = 0; q1 < N1; ++q1) {
+        const int row = j + N2 * q1;
+        if (row < rows_out) {
+          const long off = batch * out_bstride + (long)row * L + line;
+          if (MODE == COL_P5) {
+            C<IO>* y = reinterpret_cast<C<IO>*>(out_);
+            const C<IO>* x = reinterpret_cast<const C<IO>*>(mfac);  // identity term, or none
+            C<IO> xv = x ? x[off] : cmk<IO>(0, 0);
+            y[off] = cmk<IO>(xv.re + (IO)(w[q1].re * scale), xv.im + (IO)(w[q1].im * scale));
+          } else {
+            reinterpret_cast<C<R>*>(out_)[off] = w[q1];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---- pass 3: contiguous-dimension FFT, 3x3 Khat multiply, inverse -----------
+// X: [B][3][P][P][n] (q1, q2, i3).  Kh: octant [H][H][6][H], components
+// (xx, yy, zz, xy, xz, yz), already divided by P^3.  Block = 4 jobs x TPL.
+template <typename R, int P, int N1, int N2>
+__global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict__ X,
+                                                                const C<R>* __restrict__ Kh,
+                                                                const C<R>* __restrict__ tw,
+                                                                int n, int B) {
+  constexpr int H = P / 2 + 1;
+  constexpr int TPL = cmax(N1, N2);
+  constexpr int EXS = N1 * N2 + N2;          // padded exchange stride per component
+  __shared__ C<R> kl[6 * H];
+  __shared__ C<R> ex[4 * 3 * EXS];
+  const int f1 = blockIdx.x / H;
+  const int f2 = blockIdx.x % H;
+  const int tid = threadIdx.x;
+  const int job = tid / TPL;
+  const int j = tid % TPL;
+  const int s1 = job & 1, s2 = job >> 1;
+  const bool edge1 = (f1 == 0) || (2 * f1 == P);
+  const bool edge2 = (f2 == 0) || (2 * f2 == P);
+  const bool active = !((s1 && edge1) || (s2 && edge2));
+  const int q1 = s1 ? P - f1 : f1;
+  const int q2 = s2 ? P - f2 : f2;
+  const long plane = (long)P * P * n;         // one component of one rhs
+  const long lineoff = ((long)q1 * P + q2) * n;
+
+  const C<R>* kg = Kh + ((long)f1 * H + f2) * 6 * H;
+  for (int e = tid; e < 6 * H; e += 4 * TPL) kl[e] = kg[e];
+  // sign flips of the odd components for a mirrored line
+  const R sxy = (s1 != s2) ? (R)-1 : (R)1;   // xy odd in q1 and q2
+  const R sx = s1 ? (R)-1 : (R)1;            // xz odd in q1 (and q3)
+  const R sy = s2 ? (R)-1 : (R)1;            // yz odd in q2 (and q3)
+  __syncthreads();
+
+  C<R>* myex = ex + job * 3 * EXS;
+  for (int b = 0; b < B; ++b) {
+    C<R>* base = X + (long)b * 3 * plane + lineoff;
+    // forward step 1, one component at a time: thread j < N1 owns t = j + N1 k
+    if (active && j < N1) {
+#pragma unroll 1
+      for (int c = 0; c < 3; ++c) {
+        C<R> v[N2];
+#pragma unroll
+        for (int k = 0; k < N2; ++k) {
+          const int tt = j + N1 * k;
+          v[k] = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+        }
+        Dft<N2, -1, R>::run(v);
+#pragma unroll
+        for (int q = 0; q < N2; ++q)
+          myex[c * EXS + q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * tw[j * q];
+      }
+    }
+    __syncthreads();
+    // thread q2 = j < N2 owns the slots j (N1 + 1) + [0, N1) of every component:
+    // forward step 3, the 3x3 multiply at q3 = j + N2 a, inverse step 1'.
+    if (active && j < N2) {
+      C<R>* own = myex + j * (N1 + 1);
+#pragma unroll 1
+      for (int c = 0; c < 3; ++c) {
+        C<R> w[N1];
+#pragma unroll
+        for (int a = 0; a < N1; ++a) w[a] = own[c * EXS + a];
+        Dft<N1, -1, R>::run(w);
+#pragma unroll
+        for (int a = 0; a < N1; ++a) own[c * EXS + a] = w[a];
+      }
+#pragma unroll 2
+      for (int a = 0; a < N1; ++a) {
+        const int q3 = j + N2 * a;
+        const bool fl3 = 2 * q3 > P;
+        const int f3 = fl3 ? P - q3 : q3;
+        const R s3 = fl3 ? (R)-1 : (R)1;
+        const C<R> kxx = kl[0 * H + f3], kyy = kl[1 * H + f3], kzz = kl[2 * H + f3];
+        const C<R> kxy = cscale(kl[3 * H + f3], sxy);
+        const C<R> kxz = cscale(kl[4 * H + f3], sx * s3);
+        const C<R> kyz = cscale(kl[5 * H + f3], sy * s3);
+        const C<R> ux = own[a], uy = own[EXS + a], uz = own[2 * EXS + a];
+        own[a] = kxx * ux + kxy * uy + kxz * uz;
+        own[EXS + a] = kxy * ux + kyy * uy + kyz * uz;
+        own[2 * EXS + a] = kxz * ux + kyz * uy + kzz * uz;
+      }
+#pragma unroll 1
+      for (int c = 0; c < 3; ++c) {
+        C<R> w[N1];
+#pragma unroll
+        for (int a = 0; a < N1; ++a) w[a] = own[c * EXS + a];
+        Dft<N1, 1, R>::run(w);
+#pragma unroll
+        for (int t2 = 0; t2 < N1; ++t2) own[c * EXS + t2] = (j * t2 == 0) ? w[t2] : w[t2] * cconj(tw[j * t2]);
+      }
+    }
+    __syncthreads();
+    // inverse step 3': thread t2 = j < N1 produces t = j + N1 t1
+    if (active && j < N1) {
+#pragma unroll 1
+      for (int c = 0; c < 3; ++c) {
+        C<R> v[N2];
+#pragma unroll
+        for (int q = 0; q < N2; ++q) v[q] = myex[c * EXS + q * (N1 + 1) + j];
+        Dft<N2, 1, R>::run(v);
+#pragma unroll
+        for (int t1 = 0; t1 < N2; ++t1) {
+          const int tt = j + N1 * t1;
+          if (tt < n) base[c * plane + tt] = v[t1];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- plain row FFT along the contiguous dimension (plan set-up only) --------
+// X: nlines lines of length P, transformed in place (forward).
+template <typename R, int P, int N1, int N2>
+__global__ __launch_bounds__(4 * cmax(N1, N2)) void rowfft_kernel(C<R>* __restrict__ X,
+                                                                  const C<R>* __restrict__ tw,
+                                                                  long nlines) {
+  constexpr int TPL = cmax(N1, N2);
+  constexpr int EXS = N1 * N2 + N2;
+  __shared__ C<R> ex[4 * EXS];
+  const int job = threadIdx.x / TPL;
+  const int j = threadIdx.x % TPL;
+  const long line = (long)blockIdx.x * 4 + job;
+  const bool live = line < nlines;
+  C<R>* base = X + line * P;
+  C<R>* myex = ex + job * EXS;
+  if (live && j < N1) {
+    C<R> v[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) v[k] = base[j + N1 * k];
+    Dft<N2, -1, R>::run(v);
+#pragma unroll
+    for (int q = 0; q < N2; ++q) myex[q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * tw[j * q];
+  }
+  __syncthreads();
+  if (live && j < N2) {
+    C<R> w[N1];
+#pragma unroll
+    for (int jj = 0; jj < N1; ++jj) w[jj] = myex[j * (N1 + 1) + jj];
+    Dft<N1, -1, R>::run(w);
+#pragma unroll
+    for (int a = 0; a < N1; ++a) base[j + N2 * a] = w[a];
+  }
+}
+
+// ---- Nystrom weights ----------------------------------------------------------
+// Component cidx of K(r) on the P^3 circulant embedding: index r mod P for
+// |r_d| <= n-1, zero elsewhere.  cidx: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz.
+__global__ void embed_kernel_component(C<double>* __restrict__ E, int n, int P, double k, double h,
+                                       int cidx) {
+  const long tot = (long)P * P * P;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= tot) return;
+  const int e3 = (int)(id % P);
+  const int e2 = (int)((id / P) % P);
+  const int e1 = (int)(id / ((long)P * P));
+  const int r1 = e1 <= P / 2 ? e1 : e1 - P;
+  const int r2 = e2 <= P / 2 ? e2 : e2 - P;
+  const int r3 = e3 <= P / 2 ? e3 : e3 - P;
+  C<double> val = cmk(0.0, 0.0);
+  if (abs(r1) <= n - 1 && abs(r2) <= n - 1 && abs(r3) <= n - 1) {
+    const int ia = (cidx < 3) ? cidx : (cidx == 5 ? 1 : 0);
+    const int ib = (cidx < 3) ? cidx : (cidx == 3 ? 1 : 2);
+    if (r1 == 0 && r2 == 0 && r3 == 0) {
+      if (ia == ib) {
+        // equal-volume ball: a = h (3/(4 pi))^(1/3); K(0) = (2/3)[(1 - ika)e^{ika} - 1] - 1/3
+        const double a = h * cbrt(3.0 / (4.0 * kPi));
+        double sn, cs;
+        sincos(k * a, &sn, &cs);
+        // (1 - i k a)(cs + i sn) = (cs + k a sn) + i (sn - k a cs)
+        const double br = cs + k * a * sn - 1.0, bi = sn - k * a * cs;
+        val = cmk((2.0 / 3.0) * br - 1.0 / 3.0, (2.0 / 3.0) * bi);
+      }
+    } else {
+      const double x[3] = {h * r1, h * r2, h * r3};
+      const double R2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+      const double R = sqrt(R2);
+      double sn, cs;
+      sincos(k * R, &sn, &cs);
+      const double g = 1.0 / (4.0 * kPi * R);
+      const C<double> G = cmk(cs * g, sn * g);
+      const C<double> ciso = G * cmk(k * k - 1.0 / R2, k / R);
+      const C<double> crad = G * cmk(-k * k + 3.0 / R2, -3.0 * k / R);
+      const double xa = x[ia] / R, xb = x[ib] / R;
+      const double h3 = h * h * h;
+      C<double> v = cscale(crad, xa * xb);
+      if (ia == ib) v = v + ciso;
+      val = cscale(v, h3);
+    }
+  }
+  E[id] = val;
+}
+
+// Octant gather: Kh[f1][f2][cidx][f3] = E[f1][f2][f3] * inv
+__global__ void gather_octant(const C<double>* __restrict__ E, C<double>* __restrict__ kh64,
+                              C<float>* __restrict__ kh32, int P, int cidx, double inv) {
+  const int H = P / 2 + 1;
+  const long tot = (long)H * H * H;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= tot) return;
+  const int f3 = (int)(id % H);
+  const int f2 = (int)((id / H) % H);
+  const int f1 = (int)(id / ((long)H * H));
+  C<double> v = cscale(E[((long)f1 * P + f2) * P + f3], inv);
+  const long o = (((long)f1 * H + f2) * 6 + cidx) * H + f3;
+  kh64[o] = v;
+  kh32[o] = ccast<float>(v);
+}
+
+__global__ void to_c64(const C<double>* __restrict__ a, C<float>* __restrict__ b, long cnt) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < cnt) b[id] = ccast<float>(a[id]);
+}
+
+// ---- launch helpers -----------------------------------------------------------
+template <typename R, typename IO, int P, int MODE>
+static ls_status launch_col(const void* in, void* out, const void* aux, const C<R>* tw, int rows_in,
+                            int rows_out, long L, long in_bs, long out_bs, long nbatch, R scale,
+                            hipStream_t s) {
+  constexpr Fac f = col_factors(P);
+  constexpr int T = col_tile<R>(P);
+  const long ntiles = (L + T - 1) / T;
+  const long blocks = nbatch * ntiles;
+  if (blocks <= 0) return LS_OK;
+  if (blocks > 0x7fffffffL) return LS_EINVAL;
+  hipLaunchKernelGGL((col_fft_kernel<R, IO, P, f.n1, f.n2, T, MODE>), dim3((unsigned)blocks),
+                     dim3(T * cmax(f.n1, f.n2)), 0, s, in, out,
+                     reinterpret_cast<const C<R>*>(aux), tw, rows_in, rows_out, L, in_bs, out_bs,
+                     (int)ntiles, scale);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+template <typename R, int P>
+static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, hipStream_t s) {
+  constexpr Fac f = row_factors<R>(P);
+  constexpr int H = P / 2 + 1;
+  hipLaunchKernelGGL((kmul_kernel<R, P, f.n1, f.n2>), dim3(H * H), dim3(4 * cmax(f.n1, f.n2)), 0, s,
+                     X, Kh, tw, n, B);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+template <typename R, int P>
+static ls_status launch_rowfft(C<R>* X, const C<R>* tw, long nlines, hipStream_t s) {
+  constexpr Fac f = col_factors(P);
+  const long blocks = (nlines + 3) / 4;
+  hipLaunchKernelGGL((rowfft_kernel<R, P, f.n1, f.n2>), dim3((unsigned)blocks),
+                     dim3(4 * cmax(f.n1, f.n2)), 0, s, X, tw, nlines);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+// Full forward 3-D FFT of a P^3 FP64 array (plan set-up), scratch of P^3.
+template <int P>
+static ls_status fft3d_f64(C<double>* E, C<double>* scratch, const C<double>* tw, hipStream_t s) {
+  const long P2 = (long)P * P;
+  // dim 1: lines = P^2 (dims 2,3), rows = dim 1
+  LS_TRY((launch_col<double, double, P, COL_FWD>(E, scratch, nullptr, tw, P, P, P2, 0, 0, 1, 1.0, s)));
+  // dim 2: batch over dim 1, lines = P (dim 3)
+  LS_TRY((launch_col<double, double, P, COL_FWD>(scratch, E, nullptr, tw, P, P, P, P2, P2, P, 1.0, s)));
+  // dim 3: contiguous
+  LS_TRY((launch_rowfft<double, P>(E, tw, P2, s)));
+  return LS_OK;
+}
+
+template <int P>
+static ls_status build_symbol(ApplyPlan& ap, hipStream_t s) {
+  const long P3 = (long)P * P * P;
+  DevBuf E, scr;
+  LS_TRY(E.alloc(P3 * sizeof(C<double>)));
+  LS_TRY(scr.alloc(P3 * sizeof(C<double>)));
+  const int H = P / 2 + 1;
+  const long H3 = (long)H * H * H;
+  const double inv = 1.0 / (double)P3;
+  for (int c = 0; c < 6; ++c) {
+    hipLaunchKernelGGL(embed_kernel_component, dim3((unsigned)((P3 + 255) / 256)), dim3(256), 0, s,
+                       E.as<C<double>>(), ap.n, P, ap.k, ap.h, c);
+    LS_HIP(hipGetLastError());
+    LS_TRY(fft3d_f64<P>(E.as<C<double>>(), scr.as<C<double>>(), ap.tw64.as<C<double>>(), s));
+    hipLaunchKernelGGL(gather_octant, dim3((unsigned)((H3 + 255) / 256)), dim3(256), 0, s,
+                       E.as<C<double>>(), ap.kh64.as<C<double>>(), ap.kh32.as<C<float>>(), P, c, inv);
+    LS_HIP(hipGetLastError());
+  }
+  LS_HIP(hipStreamSynchronize(s));   // E and scr are released on return
+  return LS_OK;
+}
+
+template <typename R, typename IO, int P>
+static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, const C<R>* m,
+                            const C<R>* kh, const C<R>* tw, bool minus_conv, hipStream_t s,
+                            hipEvent_t* ev) {
+  const int n = ap.n;
+  const long n2 = (long)n * n, n3 = n2 * n;
+  C<R>* X1 = ap.work.as<C<R>>();                          // [B][3][P][n^2]  (also Y1)
+  C<R>* X2 = X1 + (long)nrhs * 3 * P * n2;                 // [B][3][P][P][n]
+  const long nb = (long)nrhs * 3;
+#define LS_MARK(i) \
+  if (ev) LS_HIP(hipEventRecord(ev[i], s))
+  LS_MARK(0);
+  // pass 1: along dim 1, lines = n^2
+  LS_TRY((launch_col<R, IO, P, COL_P1>(x, X1, m, tw, n, P, n2, n3, (long)P * n2, nb, (R)1, s)));
+  LS_MARK(1);
+  // pass 2: along dim 2, batch (b, c, q1), lines = n
+  LS_TRY((launch_col<R, R, P, COL_FWD>(X1, X2, nullptr, tw, n, P, n, n2, (long)P * n, nb * P, (R)1, s)));
+  LS_MARK(2);
+  // pass 3: along dim 3 with the 3x3 multiply
+  LS_TRY((launch_kmul<R, P>(X2, kh, tw, n, nrhs, s)));
+  LS_MARK(3);
+  // pass 4: inverse along dim 2
+  LS_TRY((launch_col<R, R, P, COL_INV>(X2, X1, nullptr, tw, P, n, n, (long)P * n, n2, nb * P, (R)1, s)));
+  LS_MARK(4);
+  // pass 5: inverse along dim 1, y = x + v
+  if (minus_conv)   // y = -K*(m x)
+    LS_TRY((launch_col<R, IO, P, COL_P5>(X1, y, nullptr, tw, P, n, n2, (long)P * n2, n3, nb, (R)-1, s)));
+  else
+    LS_TRY((launch_col<R, IO, P, COL_P5>(X1, y, x, tw, P, n, n2, (long)P * n2, n3, nb, (R)1, s)));
+  LS_MARK(5);
+#undef LS_MARK
+  return LS_OK;
+}
+
+template <int P>
+static ls_status apply_dispatch(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec,
+                                bool minus_conv, hipStream_t s, hipEvent_t* ev) {
+  switch (prec) {
+    case LS_C128:
+      return run_passes<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(),
+                                           ap.kh64.as<C<double>>(), ap.tw64.as<C<double>>(), minus_conv, s, ev);
+    case LS_C64:
+      return run_passes<float, float, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(),
+                                         ap.kh32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+    case LS_MIXED:
+      return run_passes<float, double, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(),
+                                          ap.kh32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+  }
+  return LS_EINVAL;
+}
+
+#define LS_FOR_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384)
+
+ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const void* m_dev,
+                          hipStream_t s) {
+  const int P = choose_fft_size(n);
+  if (P == 0 || P > 384) return LS_EINVAL;
+  ap.n = n;
+  ap.P = P;
+  ap.H = P / 2 + 1;
+  ap.k = k;
+  ap.h = 1.0 / (n + 1);
+  ap.max_rhs = max_rhs;
+  const long n3 = (long)n * n * n;
+  const long H3 = (long)ap.H * ap.H * ap.H;
+  LS_TRY(ap.m64.alloc(n3 * sizeof(C<double>)));
+  LS_TRY(ap.m32.alloc(n3 * sizeof(C<float>)));
+  LS_TRY(ap.kh64.alloc(H3 * 6 * sizeof(C<double>)));
+  LS_TRY(ap.kh32.alloc(H3 * 6 * sizeof(C<float>)));
+  LS_TRY(ap.tw64.alloc(P * sizeof(C<double>)));
+  LS_TRY(ap.tw32.alloc(P * sizeof(C<float>)));
+  ap.work_per_rhs64 = (size_t)3 * ((size_t)P * n * n + (size_t)P * P * n) * sizeof(C<double>);
+  LS_TRY(ap.work.alloc(ap.work_per_rhs64 * (size_t)max_rhs));
+  // twiddles exp(-2 pi i t / P), evaluated in long double on the host
+  std::vector<C<double>> t64(P);
+  std::vector<C<float>> t32(P);
+  for (int t = 0; t < P; ++t) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / P;
+    t64[t] = cmk((double)cosl(ang), (double)sinl(ang));
+    t32[t] = cmk((float)cosl(ang), (float)sinl(ang));
+  }
+  LS_HIP(hipMemcpyAsync(ap.tw64.p, t64.data(), P * sizeof(C<double>), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(ap.tw32.p, t32.data(), P * sizeof(C<float>), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(ap.m64.p, m_dev, n3 * sizeof(C<double>), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(to_c64, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s,
+                     ap.m64.as<C<double>>(), ap.m32.as<C<float>>(), n3);
+  LS_HIP(hipGetLastError());
+  switch (P) {
+#define X(SZ) \
+  case SZ: return build_symbol<SZ>(ap, s);
+    LS_FOR_SIZES(X)
+#undef X
+  }
+  return LS_EINVAL;
+}
+
+ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
+                    bool minus_conv, hipEvent_t* ev) {
+  if (nrhs < 1 || nrhs > ap.max_rhs) return LS_EINVAL;
+  switch (ap.P) {
+#define X(SZ) \
+  case SZ: return apply_dispatch<SZ>(ap, x, y, nrhs, prec, minus_conv, s, ev);
+    LS_FOR_SIZES(X)
+#undef X
+  }
+  return LS_EINVAL;
+}
+
+}  // namespace ls
