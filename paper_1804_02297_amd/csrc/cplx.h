@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ls {
 
 template <typename R>
@@ -186,6 +188,68 @@ struct Dft {
       Dft<F, DIR, R>::run(t);
 #pragma unroll
       for (int s = 0; s < F; ++s) v[q + M * s] = t[s];
+    }
+  }
+};
+
+// ---- DFTs with known-zero inputs ---------------------------------------------
+// DftZ<N, DIR, R, NIN>: the same transform when v[k] = 0 for k >= NIN (those
+// entries are never read).  The zero-padded halves of the circulant
+// embedding make NIN = N/2 in the forward passes; IEEE arithmetic forbids
+// the compiler from folding x + 0 and 0 * w itself, so the pruning is spelt
+// out here.  Outputs that a caller never reads are removed by dead-code
+// elimination, so no output pruning is needed.
+template <int I, int E, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (I < E) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, E>(fn);
+  }
+}
+
+template <int N, int DIR, typename R, int NIN>
+struct DftZ {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    if constexpr (NIN >= N) {
+      Dft<N, DIR, R>::run(v);
+    } else if constexpr (NIN <= 0) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) v[q] = cmk<R>(0, 0);
+    } else if constexpr (NIN == 1) {
+#pragma unroll
+      for (int q = 1; q < N; ++q) v[q] = v[0];
+    } else if constexpr (N == 4 && NIN == 2) {
+      const C<R> a = v[0], b = v[1];
+      const C<R> jb = (DIR < 0) ? mul_mi(b) : mul_pi(b);
+      v[0] = a + b;
+      v[1] = a + jb;
+      v[2] = a - b;
+      v[3] = a - jb;
+    } else if constexpr (N <= 4) {
+#pragma unroll
+      for (int k = NIN; k < N; ++k) v[k] = cmk<R>(0, 0);
+      Dft<N, DIR, R>::run(v);
+    } else {
+      constexpr int F = FirstFactor<N>::value;
+      constexpr int M = N / F;
+      C<R> sub[F][M];
+      static_for<0, F>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        constexpr int nin = (NIN > f) ? (NIN - f + F - 1) / F : 0;
+#pragma unroll
+        for (int m = 0; m < nin; ++m) sub[f][m] = v[f + F * m];
+        DftZ<M, DIR, R, nin>::run(sub[f]);
+      });
+      constexpr int FIN = NIN < F ? NIN : F;     // sub-transforms that are not all zero
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        C<R> t[F];
+#pragma unroll
+        for (int f = 0; f < FIN; ++f) t[f] = (f * q == 0) ? sub[f][q] : sub[f][q] * ctw<R, N, DIR>(f * q);
+        DftZ<F, DIR, R, FIN>::run(t);
+#pragma unroll
+        for (int s = 0; s < F; ++s) v[q + M * s] = t[s];
+      }
     }
   }
 };

@@ -62,10 +62,14 @@ constexpr Fac row_factors(int P) {
   return col_factors(P);
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-// Lines per workgroup of the strided passes: a 256-byte run per row, LDS <= 64 KB.
+// Lines per workgroup of the strided passes: a LS_COL_RUN_BYTES run per row
+// (one or two 128-byte cache lines), LDS <= 64 KB.
+#ifndef LS_COL_RUN_BYTES
+#define LS_COL_RUN_BYTES 256
+#endif
 template <typename R>
 constexpr int col_tile(int P) {
-  int t = (sizeof(R) == 8) ? 16 : 32;
+  int t = LS_COL_RUN_BYTES / (2 * (int)sizeof(R));
   while (t > 8 && (long)P * t * 2 * (long)sizeof(R) > 65536) t /= 2;
   return t;
 }
@@ -86,12 +90,15 @@ bool fft_size_supported(int P) {
 // ---- strided-dimension four-step FFT ----------------------------------------
 // Lines are contiguous (index `line` in [0, L)); the transform runs along rows
 // with stride L.  Block = T lines x TPL threads, blockIdx.x = batch * ntiles + tile.
-template <typename R, typename IO, int P, int N1, int N2, int T, int MODE>
+template <typename R, typename IO, int P, int N1, int N2, int T, int MODE, bool PAD>
 __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
     const void* __restrict__ in_, void* __restrict__ out_, const C<R>* __restrict__ mfac,
     const C<R>* __restrict__ tw, int rows_in, int rows_out, long L, long in_bstride,
     long out_bstride, int ntiles, R scale) {
   constexpr int DIR = (MODE == COL_P1 || MODE == COL_FWD) ? -1 : 1;
+  // PAD: a forward pass reads at most P/2 rows, an inverse pass keeps at most P/2
+  constexpr int KIN = (PAD && DIR < 0) ? (N2 + 1) / 2 : N2;
+  constexpr int QOUT = (PAD && DIR > 0) ? (N1 + 1) / 2 : N1;
   __shared__ C<R> ex[N1 * N2 * T];
   const int tid = threadIdx.x;
   const int t = tid % T;
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
   if (j < N1) {
     C<R> v[N2];
 #pragma unroll
-    for (int k = 0; k < N2; ++k) {
+    for (int k = 0; k < KIN; ++k) {
       const int row = j + N1 * k;
       C<R> z = cmk<R>(0, 0);
       if (live && row < rows_in) {
@@ -118,7 +125,7 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
       }
       v[k] = z;
     }
-    Dft<N2, DIR, R>::run(v);
+    DftZ<N2, DIR, R, KIN>::run(v);
 #pragma unroll
     for (int q = 0; q < N2; ++q) {
       C<R> w = tw[j * q];
@@ -134,7 +141,7 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
     Dft<N1, DIR, R>::run(w);
     if (live) {
 #pragma unroll
-      for (int q1 = 0; q1 < N1; ++q1) {
+      for (int q1 = 0; q1 < QOUT; ++q1) {
         const int row = j + N2 * q1;
         if (row < rows_out) {
           const long off = batch * out_bstride + (long)row * L + line;
@@ -154,22 +161,43 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
 
 // ---- pass 3: contiguous-dimension FFT, 3x3 Khat multiply, inverse -----------
 // X: [B][3][P][P][n] (q1, q2, i3).  Kh: octant [H][H][6][H], components
-// (xx, yy, zz, xy, xz, yz), already divided by P^3.  Block = 4 jobs x TPL.
-template <typename R, int P, int N1, int N2>
-__global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict__ X,
-                                                                const C<R>* __restrict__ Kh,
-                                                                const C<R>* __restrict__ tw,
-                                                                int n, int B) {
+// (xx, yy, zz, xy, xz, yz), already divided by P^3.
+//
+// A team is 4 jobs x TPL threads: the up-to-four lines (+-f1, +-f2) of one
+// right-hand side.  A workgroup holds W teams that share one octant line of
+// Khat in LDS and take right-hand sides b = team, team + W, ...  When a team
+// is exactly one wavefront its exchanges need only wavefront-level ordering
+// (LDS operations of one wave complete in order), so teams never wait for
+// each other; otherwise W = 1 and the exchange uses a workgroup barrier.
+// The three components of a line stay in registers from the forward
+// transform through the 3x3 multiply into the inverse transform; the LDS
+// exchange buffer holds one component at a time.
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename R, int P, int N1, int N2, int W>
+__global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict__ X,
+                                                                    const C<R>* __restrict__ Kh,
+                                                                    const C<R>* __restrict__ tw,
+                                                                    int n, int B) {
   constexpr int H = P / 2 + 1;
   constexpr int TPL = cmax(N1, N2);
-  constexpr int EXS = N1 * N2 + N2;          // padded exchange stride per component
+  constexpr int TEAM = 4 * TPL;
+  constexpr bool WAVE_TEAM = (TEAM == 64);
+  static_assert(WAVE_TEAM || W == 1, "multi-team workgroups need one-wave teams");
+  constexpr int EXS = N1 * N2 + N2;          // padded exchange stride of one job
   __shared__ C<R> kl[6 * H];
-  __shared__ C<R> ex[4 * 3 * EXS];
+  __shared__ C<R> twl[P];
+  __shared__ C<R> ex[W * 4 * EXS];
   const int f1 = blockIdx.x / H;
   const int f2 = blockIdx.x % H;
   const int tid = threadIdx.x;
-  const int job = tid / TPL;
-  const int j = tid % TPL;
+  const int team = tid / TEAM;
+  const int lt = tid % TEAM;
+  const int job = lt / TPL;
+  const int j = lt % TPL;
   const int s1 = job & 1, s2 = job >> 1;
   const bool edge1 = (f1 == 0) || (2 * f1 == P);
   const bool edge2 = (f2 == 0) || (2 * f2 == P);
@@ -180,47 +208,65 @@ __global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict
   const long lineoff = ((long)q1 * P + q2) * n;
 
   const C<R>* kg = Kh + ((long)f1 * H + f2) * 6 * H;
-  for (int e = tid; e < 6 * H; e += 4 * TPL) kl[e] = kg[e];
+  for (int e = tid; e < 6 * H; e += W * TEAM) kl[e] = kg[e];
+  for (int e = tid; e < P; e += W * TEAM) twl[e] = tw[e];
   // sign flips of the odd components for a mirrored line
   const R sxy = (s1 != s2) ? (R)-1 : (R)1;   // xy odd in q1 and q2
   const R sx = s1 ? (R)-1 : (R)1;            // xz odd in q1 (and q3)
   const R sy = s2 ? (R)-1 : (R)1;            // yz odd in q2 (and q3)
   __syncthreads();
 
-  C<R>* myex = ex + job * 3 * EXS;
-  for (int b = 0; b < B; ++b) {
+  C<R>* myex = ex + (team * 4 + job) * EXS;
+  auto tsync = [&]() {
+    if (WAVE_TEAM)
+      wave_lds_sync();
+    else
+      __syncthreads();
+  };
+
+  constexpr int KIN = (N2 + 1) / 2;     // t = j + N1 k < n <= P/2
+  for (int b = team; b < B; b += W) {
     C<R>* base = X + (long)b * 3 * plane + lineoff;
-    // forward step 1, one component at a time: thread j < N1 owns t = j + N1 k
-    if (active && j < N1) {
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c) {
+    // FP32: all loads of the three components are issued before any
+    // arithmetic (FP64 has no registers to spare for it)
+    constexpr bool PREFETCH = sizeof(R) == 4;
+    C<R> pre[3][KIN];
+    if (PREFETCH && active && j < N1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < KIN; ++k) {
+          const int tt = j + N1 * k;
+          pre[c][k] = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+        }
+    }
+    C<R> u[3][N1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // forward step 1: thread j < N1 owns t = j + N1 k
+      if (active && j < N1) {
         C<R> v[N2];
 #pragma unroll
-        for (int k = 0; k < N2; ++k) {
+        for (int k = 0; k < KIN; ++k) {
           const int tt = j + N1 * k;
-          v[k] = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+          v[k] = PREFETCH ? pre[c][k] : ((tt < n) ? base[c * plane + tt] : cmk<R>(0, 0));
         }
-        Dft<N2, -1, R>::run(v);
+        DftZ<N2, -1, R, KIN>::run(v);
 #pragma unroll
         for (int q = 0; q < N2; ++q)
-          myex[c * EXS + q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * tw[j * q];
+          myex[q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * twl[j * q];
       }
+      tsync();
+      // forward step 3: thread q2 = j < N2 gets X[j + N2 a], a in [0, N1)
+      if (active && j < N2) {
+#pragma unroll
+        for (int a = 0; a < N1; ++a) u[c][a] = myex[j * (N1 + 1) + a];
+        Dft<N1, -1, R>::run(u[c]);
+      }
+      tsync();
     }
-    __syncthreads();
-    // thread q2 = j < N2 owns the slots j (N1 + 1) + [0, N1) of every component:
-    // forward step 3, the 3x3 multiply at q3 = j + N2 a, inverse step 1'.
     if (active && j < N2) {
-      C<R>* own = myex + j * (N1 + 1);
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c) {
-        C<R> w[N1];
 #pragma unroll
-        for (int a = 0; a < N1; ++a) w[a] = own[c * EXS + a];
-        Dft<N1, -1, R>::run(w);
-#pragma unroll
-        for (int a = 0; a < N1; ++a) own[c * EXS + a] = w[a];
-      }
-#pragma unroll 2
       for (int a = 0; a < N1; ++a) {
         const int q3 = j + N2 * a;
         const bool fl3 = 2 * q3 > P;
@@ -230,38 +276,37 @@ __global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict
         const C<R> kxy = cscale(kl[3 * H + f3], sxy);
         const C<R> kxz = cscale(kl[4 * H + f3], sx * s3);
         const C<R> kyz = cscale(kl[5 * H + f3], sy * s3);
-        const C<R> ux = own[a], uy = own[EXS + a], uz = own[2 * EXS + a];
-        own[a] = kxx * ux + kxy * uy + kxz * uz;
-        own[EXS + a] = kxy * ux + kyy * uy + kyz * uz;
-        own[2 * EXS + a] = kxz * ux + kyz * uy + kzz * uz;
-      }
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c) {
-        C<R> w[N1];
-#pragma unroll
-        for (int a = 0; a < N1; ++a) w[a] = own[c * EXS + a];
-        Dft<N1, 1, R>::run(w);
-#pragma unroll
-        for (int t2 = 0; t2 < N1; ++t2) own[c * EXS + t2] = (j * t2 == 0) ? w[t2] : w[t2] * cconj(tw[j * t2]);
+        const C<R> ux = u[0][a], uy = u[1][a], uz = u[2][a];
+        u[0][a] = kxx * ux + kxy * uy + kxz * uz;
+        u[1][a] = kxy * ux + kyy * uy + kyz * uz;
+        u[2][a] = kxz * ux + kyz * uy + kzz * uz;
+        if ((a & 3) == 3) asm volatile("" ::: "memory");   // bound the LDS prefetch depth
       }
     }
-    __syncthreads();
-    // inverse step 3': thread t2 = j < N1 produces t = j + N1 t1
-    if (active && j < N1) {
-#pragma unroll 1
-      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // inverse step 1': thread q2 = j < N2 transforms its N1 values
+      if (active && j < N2) {
+        Dft<N1, 1, R>::run(u[c]);
+#pragma unroll
+        for (int t2 = 0; t2 < N1; ++t2)
+          myex[j * (N1 + 1) + t2] = (j * t2 == 0) ? u[c][t2] : u[c][t2] * cconj(twl[j * t2]);
+      }
+      tsync();
+      // inverse step 3': thread t2 = j < N1 produces t = j + N1 t1
+      if (active && j < N1) {
         C<R> v[N2];
 #pragma unroll
-        for (int q = 0; q < N2; ++q) v[q] = myex[c * EXS + q * (N1 + 1) + j];
+        for (int q = 0; q < N2; ++q) v[q] = myex[q * (N1 + 1) + j];
         Dft<N2, 1, R>::run(v);
 #pragma unroll
-        for (int t1 = 0; t1 < N2; ++t1) {
+        for (int t1 = 0; t1 < (N2 + 1) / 2; ++t1) {
           const int tt = j + N1 * t1;
           if (tt < n) base[c * plane + tt] = v[t1];
         }
       }
+      tsync();
     }
-    __syncthreads();
   }
 }
 
@@ -369,7 +414,7 @@ __global__ void to_c64(const C<double>* __restrict__ a, C<float>* __restrict__ b
 }
 
 // ---- launch helpers -----------------------------------------------------------
-template <typename R, typename IO, int P, int MODE>
+template <typename R, typename IO, int P, int MODE, bool PAD = true>
 static ls_status launch_col(const void* in, void* out, const void* aux, const C<R>* tw, int rows_in,
                             int rows_out, long L, long in_bs, long out_bs, long nbatch, R scale,
                             hipStream_t s) {
@@ -379,20 +424,40 @@ static ls_status launch_col(const void* in, void* out, const void* aux, const C<
   const long blocks = nbatch * ntiles;
   if (blocks <= 0) return LS_OK;
   if (blocks > 0x7fffffffL) return LS_EINVAL;
-  hipLaunchKernelGGL((col_fft_kernel<R, IO, P, f.n1, f.n2, T, MODE>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((col_fft_kernel<R, IO, P, f.n1, f.n2, T, MODE, PAD>), dim3((unsigned)blocks),
                      dim3(T * cmax(f.n1, f.n2)), 0, s, in, out,
                      reinterpret_cast<const C<R>*>(aux), tw, rows_in, rows_out, L, in_bs, out_bs,
                      (int)ntiles, scale);
   return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
 }
 
+template <typename R, int P, int W>
+static ls_status launch_kmul_w(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, hipStream_t s) {
+  constexpr Fac f = row_factors<R>(P);
+  constexpr int H = P / 2 + 1;
+  hipLaunchKernelGGL((kmul_kernel<R, P, f.n1, f.n2, W>), dim3(H * H), dim3(W * 4 * cmax(f.n1, f.n2)),
+                     0, s, X, Kh, tw, n, B);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+// Teams per workgroup.  Measured at 128^3 with 8 right-hand sides: two
+// teams (1.04 ms) beat one (1.07 ms), four (1.04 ms) and eight (1.30 ms):
+// small workgroups let several workgroups per CU sit in different phases
+// (loads, arithmetic, stores), which a single large workgroup cannot.
+// LS_KMUL_W overrides the choice at build time (tuning only).
 template <typename R, int P>
 static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, hipStream_t s) {
   constexpr Fac f = row_factors<R>(P);
-  constexpr int H = P / 2 + 1;
-  hipLaunchKernelGGL((kmul_kernel<R, P, f.n1, f.n2>), dim3(H * H), dim3(4 * cmax(f.n1, f.n2)), 0, s,
-                     X, Kh, tw, n, B);
-  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+  constexpr int TPL = cmax(f.n1, f.n2);
+#ifdef LS_KMUL_W
+  constexpr int WT = LS_KMUL_W;
+#else
+  constexpr int WT = 2;
+#endif
+  if constexpr (4 * TPL == 64 && WT > 1) {
+    if (B >= WT) return launch_kmul_w<R, P, WT>(X, Kh, tw, n, B, s);
+  }
+  return launch_kmul_w<R, P, 1>(X, Kh, tw, n, B, s);
 }
 
 template <typename R, int P>
@@ -409,9 +474,9 @@ template <int P>
 static ls_status fft3d_f64(C<double>* E, C<double>* scratch, const C<double>* tw, hipStream_t s) {
   const long P2 = (long)P * P;
   // dim 1: lines = P^2 (dims 2,3), rows = dim 1
-  LS_TRY((launch_col<double, double, P, COL_FWD>(E, scratch, nullptr, tw, P, P, P2, 0, 0, 1, 1.0, s)));
+  LS_TRY((launch_col<double, double, P, COL_FWD, false>(E, scratch, nullptr, tw, P, P, P2, 0, 0, 1, 1.0, s)));
   // dim 2: batch over dim 1, lines = P (dim 3)
-  LS_TRY((launch_col<double, double, P, COL_FWD>(scratch, E, nullptr, tw, P, P, P, P2, P2, P, 1.0, s)));
+  LS_TRY((launch_col<double, double, P, COL_FWD, false>(scratch, E, nullptr, tw, P, P, P, P2, P2, P, 1.0, s)));
   // dim 3: contiguous
   LS_TRY((launch_rowfft<double, P>(E, tw, P2, s)));
   return LS_OK;
