@@ -95,6 +95,78 @@ ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs
 ls_status ls_rhs_from_incident(ls_plan* plan, const void* Ei_dev, void* g_dev, int nrhs,
                                void* hip_stream);
 
+/* ---- sparsifying preconditioner (Section 3) ------------------------------- */
+
+typedef enum {
+  LS_FIT_CLASS = 0      /* the paper's fit: one stencil per position class     */
+} ls_fit_mode;
+
+typedef struct {
+  int iters;             /* FGMRES iterations (operator applications)          */
+  int restarts;          /* Arnoldi cycles                                      */
+  double rel_resid;      /* final ||g - A x|| / ||g|| with the FP64 apply      */
+  double t_gpu, t_host;  /* seconds: whole solve on the GPU side / host solves  */
+} ls_solve_info;
+
+/* Stencil fit and row assembly on the GPU (Section 3.1, Eqs. (10)-(12);
+ * Section 3.2).  LS_FIT_CLASS: for each of the 27 position classes (interior,
+ * 6 faces, 12 edges, 8 vertices) with neighbourhood tau and enlarged
+ * complement tau^c, alpha holds the three eigenvectors of the Gram matrix
+ * M M^H, M = [K(a - j)]_{a in tau, j in tau^c}, with the smallest eigenvalues
+ * (= the left singular vectors of M with the smallest singular values),
+ * beta = B^H alpha with B = [K(a - b)]_{a, b in tau}, and every point i gets
+ * the three rows alpha^H E_tau + beta^H diag(m)_tau E_tau of Eq. (11).
+ * The conjugate transpose is used for the paper's transpose.  Synchronises. */
+ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream);
+
+/* Copies of the fit to host memory (for inspection and tests).
+ * alpha_host, beta_host: [27][81][3] complex128, row 3 a + c for neighbour a
+ * (tau order: lexicographic offsets, last dimension fastest) and component c;
+ * a class with |tau| < 27 fills the first 3|tau| rows, the rest are zero.
+ * eig_host: [27][3] the three smallest Gram eigenvalues; gram_host:
+ * [27][81][81] complex128, the class Gram matrices M M^H (row-major, first
+ * 3|tau| rows and columns used).  Any pointer may be NULL.  LS_ESTATE before
+ * ls_stencil_fit. */
+ls_status ls_get_class_stencils(const ls_plan* plan, void* alpha_host, void* beta_host, double* eig_host,
+                                void* gram_host);
+
+/* The assembled rows S to host memory: [n^3][3 rows][27 slots][3 comps]
+ * complex128, slot 9 (s1+1) + 3 (s2+1) + (s3+1) for the neighbour at offset
+ * s; slots outside the grid are zero.  LS_ESTATE before ls_stencil_fit. */
+ls_status ls_get_rows(const ls_plan* plan, void* rows_host);
+
+/* Nested-dissection multifrontal LU of S on the host cores (the paper's
+ * sparse direct solve; Section 3.3).  Copies the rows from the GPU.
+ * LS_EHOST if the factor would exceed desc->host_mem_cap.  seconds_out may be
+ * NULL.  LS_ESTATE before ls_stencil_fit. */
+ls_status ls_factor(ls_plan* plan, double* seconds_out);
+
+/* Preconditioner z = S^-1 (Q v): Q v on the GPU, S^-1 on the host.
+ * v, z: device [nrhs][3][n][n][n] complex128 (may alias).  Synchronises.
+ * LS_ESTATE before ls_factor. */
+ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream);
+
+/* Right-preconditioned FGMRES (restart `restart`, at most `maxit` operator
+ * applications per rhs) for A x = g, x0 = 0, until ||g - A x|| <= tol ||g||
+ * with the FP64 apply.  apply_prec: LS_C128, or LS_MIXED (FP32 FFTs inside
+ * the FP64 Krylov loop, with FP64 true-residual restarts).  g, x: device
+ * [nrhs][3][n][n][n] complex128; info: host array of nrhs records.
+ * LS_ENOCONV when maxit is reached (x holds the last iterate).  LS_ESTATE
+ * before ls_factor.  Synchronises. */
+ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
+                         int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream);
+
+/* ---- the host sparse solver on its own (host memory, no GPU) -------------- */
+typedef struct ls_sparse ls_sparse;
+
+/* Factor rows given in the ls_get_rows layout on an n^3 grid. */
+ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_sparse** out);
+/* Solve S x = b in place, b host [nrhs][3][n][n][n] complex128. */
+ls_status ls_sparse_solve_host(ls_sparse* sp, void* b_host, int nrhs);
+/* Factor size in bytes and factorisation flop count. */
+ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops);
+void ls_sparse_destroy(ls_sparse* sp);
+
 /* Padded FFT length P used by the plan (P >= 2n - 1, even, 2^a 3^b). */
 int ls_plan_fft_size(const ls_plan* plan);
 

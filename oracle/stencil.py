@@ -141,8 +141,9 @@ def fit_class(kappa: int, n: int, k: float):
 
 def fit_all_classes(n: int, k: float):
     """The 27 class stencils: lists alpha[kappa], beta[kappa], sigma[kappa]."""
-    if n < 3:
-        raise ValueError("class fit needs n >= 3")
+    if n < 4:
+        # n = 3: the interior class has an empty complement (any alpha is optimal)
+        raise ValueError("class fit needs n >= 4")
     out = [fit_class(kappa, n, k) for kappa in range(27)]
     return [o[0] for o in out], [o[1] for o in out], [o[2] for o in out]
 

@@ -40,9 +40,67 @@ SIGNATURES = [
     ("ls_apply", _I, [_VP, _VP, _VP, _I, _I, _VP]),
     ("ls_apply_timed", _I, [_VP, _VP, _VP, _I, _I, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls_rhs_from_incident", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls_stencil_fit", _I, [_VP, _I, _VP]),
+    ("ls_get_class_stencils", _I, [_VP, _VP, _VP, _VP, _VP]),
+    ("ls_get_rows", _I, [_VP, _VP]),
+    ("ls_factor", _I, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("ls_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
+    ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
+    ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
+    ("ls_sparse_destroy", None, [_VP]),
     ("ls_plan_fft_size", _I, [_VP]),
     ("ls_plan_destroy", None, [_VP]),
 ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("rel_resid", ctypes.c_double),
+                ("t_gpu", ctypes.c_double), ("t_host", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SparseHost:
+    """The host multifrontal solver on its own (host memory only, no GPU needed)."""
+
+    def __init__(self, n: int, rows, host_mem_cap: int = 0):
+        import numpy as np
+        lib = load()
+        rows = np.ascontiguousarray(rows, dtype=np.complex128)
+        if rows.shape != (n ** 3, 3, 27, 3):
+            raise ValueError("rows must have shape (n^3, 3, 27, 3)")
+        self.n = n
+        h = ctypes.c_void_p()
+        _check(lib.ls_sparse_factor_host(n, rows.ctypes.data_as(ctypes.c_void_p), host_mem_cap,
+                                         ctypes.byref(h)), "ls_sparse_factor_host")
+        self._h = h
+
+    def solve(self, b):
+        """x = S^-1 b for b of shape (nrhs, 3, n, n, n) complex128 (host)."""
+        import numpy as np
+        x = np.array(b, dtype=np.complex128, order="C", copy=True)
+        _check(_lib.ls_sparse_solve_host(self._h, x.ctypes.data_as(ctypes.c_void_p), x.shape[0]),
+               "ls_sparse_solve_host")
+        return x
+
+    def info(self):
+        nb, fl = ctypes.c_size_t(), ctypes.c_double()
+        _check(_lib.ls_sparse_info(self._h, ctypes.byref(nb), ctypes.byref(fl)), "ls_sparse_info")
+        return {"bytes": nb.value, "flops": fl.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ls_sparse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def load(path: str = LIB_PATH):
@@ -136,6 +194,62 @@ class Plan:
         _check(_lib.ls_apply_timed(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream(), ms),
                "ls_apply_timed")
         return list(ms)
+
+    def stencil_fit(self, mode: int = 0):
+        """Class stencils, beta and the rows S on the GPU (Section 3.1, 3.2)."""
+        _check(_lib.ls_stencil_fit(self._h, mode, _stream()), "ls_stencil_fit")
+
+    def class_stencils(self, gram: bool = False):
+        """(alpha, beta, eig[, gram]): alpha, beta (27, 81, 3) complex128; eig (27, 3);
+        gram (27, 81, 81) complex128 when asked for."""
+        import numpy as np
+        al = np.zeros((27, 81, 3), np.complex128)
+        be = np.zeros((27, 81, 3), np.complex128)
+        ev = np.zeros((27, 3), np.float64)
+        gr = np.zeros((27, 81, 81), np.complex128) if gram else None
+        _check(_lib.ls_get_class_stencils(self._h, al.ctypes.data_as(ctypes.c_void_p),
+                                          be.ctypes.data_as(ctypes.c_void_p),
+                                          ev.ctypes.data_as(ctypes.c_void_p),
+                                          gr.ctypes.data_as(ctypes.c_void_p) if gram else None),
+               "ls_get_class_stencils")
+        return (al, be, ev, gr) if gram else (al, be, ev)
+
+    def rows(self):
+        """Assembled rows S, (n^3, 3, 27, 3) complex128."""
+        import numpy as np
+        r = np.zeros((self.n ** 3, 3, 27, 3), np.complex128)
+        _check(_lib.ls_get_rows(self._h, r.ctypes.data_as(ctypes.c_void_p)), "ls_get_rows")
+        return r
+
+    def factor(self):
+        """Host multifrontal LU of S; returns seconds."""
+        t = ctypes.c_double()
+        _check(_lib.ls_factor(self._h, ctypes.byref(t)), "ls_factor")
+        return t.value
+
+    def precond(self, v, z=None):
+        """z = S^-1 Q v (complex128 device fields)."""
+        import torch
+        _field(v, torch.complex128, self.n, "v")
+        if z is None:
+            z = torch.empty_like(v)
+        _check(_lib.ls_precond_apply(self._h, _ptr(v), _ptr(z), v.shape[0], _stream()), "ls_precond_apply")
+        return z
+
+    def solve(self, g, tol: float = 1e-8, restart: int = 30, maxit: int = 500, prec: str = "c128",
+              x=None, check: bool = True):
+        """FGMRES solve A x = g; returns (x, [info dict per rhs], status)."""
+        import torch
+        _field(g, torch.complex128, self.n, "g")
+        if x is None:
+            x = torch.empty_like(g)
+        nr = g.shape[0]
+        infos = (SolveInfo * nr)()
+        st = _lib.ls_gmres_solve(self._h, _ptr(g), _ptr(x), nr, float(tol), restart, maxit, PREC[prec],
+                                 ctypes.cast(infos, ctypes.c_void_p), _stream())
+        if check and st not in (0, -4):
+            _check(st, "ls_gmres_solve")
+        return x, [i.as_dict() for i in infos], st
 
     def rhs_from_incident(self, Ei, g=None):
         """g = -K * (m E^i) (right-hand side of Eq. (4)), complex128."""

@@ -17,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CLANGXX = os.environ.get("CLANGXX", "/opt/rocm/llvm/bin/clang++")   # host-only C++
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(os.path.dirname(HERE), "include")]
@@ -29,7 +30,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC] + COMMON + DEVICE + ["-c", src, "-o", obj]
     else:
-        cmd = [HIPCC] + COMMON + ["-fopenmp", "-march=x86-64-v3", "-c", src, "-o", obj]
+        cmd = [CLANGXX] + COMMON + ["-fopenmp", "-march=x86-64-v3", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

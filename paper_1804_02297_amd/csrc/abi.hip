@@ -1,12 +1,52 @@
 // C ABI entry points (include/ls.h).  Argument checking and dispatch only;
 // the arithmetic lives in the kernels of the other translation units.
+#include <chrono>
+#include <complex>
 #include <new>
 
-#include "common.h"
+#include "plan.h"
 
 using namespace ls;
 
 static inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+static inline double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// y = A x over nrhs fields, chunked by the plan's max_rhs
+static ls_status apply_chunked(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec,
+                               hipStream_t s, bool minus_conv = false) {
+  const size_t es = (prec == LS_C64) ? 8 : 16;
+  const size_t per = (size_t)3 * plan->ap.n * plan->ap.n * plan->ap.n * es;
+  for (int b0 = 0; b0 < nrhs; b0 += plan->ap.max_rhs) {
+    const int nb = (nrhs - b0 < plan->ap.max_rhs) ? nrhs - b0 : plan->ap.max_rhs;
+    LS_TRY(apply_run(plan->ap, static_cast<const char*>(x_dev) + (size_t)b0 * per,
+                     static_cast<char*>(y_dev) + (size_t)b0 * per, nb, prec, s, minus_conv));
+  }
+  return LS_OK;
+}
+
+// z <- S^-1 Q z for the listed right-hand sides (device vectors), host solve in one block
+static ls_status precond_list(ls_plan* plan, const std::vector<int>& lb,
+                              const std::function<C<double>*(int)>& ptr, hipStream_t s, double* t_host) {
+  const long len = 3L * plan->ap.n * plan->ap.n * plan->ap.n;
+  const size_t vb = (size_t)len * sizeof(C<double>);
+  const int nb = (int)lb.size();
+  if (plan->qtmp.bytes < vb) LS_TRY(plan->qtmp.alloc(vb));
+  plan->hbuf.resize((size_t)nb * len);
+  for (int q = 0; q < nb; ++q) {
+    LS_TRY(q_apply(plan->sd, plan->ap.n, ptr(lb[q]), plan->qtmp.as<C<double>>(), 1, s));
+    LS_HIP(hipMemcpyAsync(plan->hbuf.data() + (size_t)q * len, plan->qtmp.p, vb, hipMemcpyDeviceToHost, s));
+  }
+  LS_HIP(hipStreamSynchronize(s));
+  const double t0 = now_s();
+  LS_TRY(host_solve(plan->hs, plan->hbuf.data(), nb));
+  if (t_host) *t_host = now_s() - t0;
+  for (int q = 0; q < nb; ++q)
+    LS_HIP(hipMemcpyAsync(ptr(lb[q]), plan->hbuf.data() + (size_t)q * len, vb, hipMemcpyHostToDevice, s));
+  LS_HIP(hipStreamSynchronize(s));
+  return LS_OK;
+}
 
 extern "C" {
 
@@ -39,6 +79,7 @@ ls_status ls_plan_create(const ls_plan_desc* desc, const void* m_dev, void* hip_
     delete p;
     return st;
   }
+  p->gctx.len = 3L * desc->n * desc->n * desc->n;
   *out = p;
   return LS_OK;
 }
@@ -47,15 +88,7 @@ ls_status ls_apply(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_p
                    void* hip_stream) {
   if (!plan || !x_dev || !y_dev || nrhs < 1) return LS_EINVAL;
   if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
-  const size_t es = (prec == LS_C64) ? 8 : 16;
-  const size_t per = (size_t)3 * plan->ap.n * plan->ap.n * plan->ap.n * es;
-  for (int b0 = 0; b0 < nrhs; b0 += plan->ap.max_rhs) {
-    const int nb = (nrhs - b0 < plan->ap.max_rhs) ? nrhs - b0 : plan->ap.max_rhs;
-    const char* x = static_cast<const char*>(x_dev) + (size_t)b0 * per;
-    char* y = static_cast<char*>(y_dev) + (size_t)b0 * per;
-    LS_TRY(apply_run(plan->ap, x, y, nb, prec, as_stream(hip_stream)));
-  }
-  return LS_OK;
+  return apply_chunked(plan, x_dev, y_dev, nrhs, prec, as_stream(hip_stream));
 }
 
 ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec,
@@ -91,15 +124,114 @@ ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs
 ls_status ls_rhs_from_incident(ls_plan* plan, const void* Ei_dev, void* g_dev, int nrhs,
                                void* hip_stream) {
   if (!plan || !Ei_dev || !g_dev || nrhs < 1) return LS_EINVAL;
-  const size_t per = (size_t)3 * plan->ap.n * plan->ap.n * plan->ap.n * 16;
-  for (int b0 = 0; b0 < nrhs; b0 += plan->ap.max_rhs) {
-    const int nb = (nrhs - b0 < plan->ap.max_rhs) ? nrhs - b0 : plan->ap.max_rhs;
-    LS_TRY(apply_run(plan->ap, static_cast<const char*>(Ei_dev) + (size_t)b0 * per,
-                     static_cast<char*>(g_dev) + (size_t)b0 * per, nb, LS_C128,
-                     as_stream(hip_stream), /*minus_conv=*/true));
-  }
+  return apply_chunked(plan, Ei_dev, g_dev, nrhs, LS_C128, as_stream(hip_stream), /*minus_conv=*/true);
+}
+
+ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
+  if (!plan || mode != LS_FIT_CLASS) return LS_EINVAL;
+  hipStream_t s = as_stream(hip_stream);
+  host_free(plan->hs);
+  plan->hs = nullptr;
+  plan->sd.have_point = false;
+  LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
+  LS_TRY(assemble_rows(plan->sd, plan->ap.n, plan->ap.m64.as<C<double>>(), s));
+  LS_HIP(hipStreamSynchronize(s));
+  plan->sd.have_rows = true;
   return LS_OK;
 }
+
+ls_status ls_get_class_stencils(const ls_plan* plan, void* alpha_host, void* beta_host, double* eig_host,
+                                void* gram_host) {
+  if (!plan) return LS_EINVAL;
+  if (!plan->sd.have_class) return LS_ESTATE;
+  if (alpha_host) LS_HIP(hipMemcpy(alpha_host, plan->sd.alpha.p, plan->sd.alpha.bytes, hipMemcpyDeviceToHost));
+  if (beta_host) LS_HIP(hipMemcpy(beta_host, plan->sd.beta.p, plan->sd.beta.bytes, hipMemcpyDeviceToHost));
+  if (eig_host) LS_HIP(hipMemcpy(eig_host, plan->sd.evals.p, plan->sd.evals.bytes, hipMemcpyDeviceToHost));
+  if (gram_host) LS_HIP(hipMemcpy(gram_host, plan->sd.gram.p, plan->sd.gram.bytes, hipMemcpyDeviceToHost));
+  return LS_OK;
+}
+
+ls_status ls_get_rows(const ls_plan* plan, void* rows_host) {
+  if (!plan || !rows_host) return LS_EINVAL;
+  if (!plan->sd.have_rows) return LS_ESTATE;
+  LS_HIP(hipMemcpy(rows_host, plan->sd.rows.p, plan->sd.rows.bytes, hipMemcpyDeviceToHost));
+  return LS_OK;
+}
+
+ls_status ls_factor(ls_plan* plan, double* seconds_out) {
+  if (!plan) return LS_EINVAL;
+  if (!plan->sd.have_rows) return LS_ESTATE;
+  const double t0 = now_s();
+  std::vector<std::complex<double>> rows(plan->sd.rows.bytes / sizeof(std::complex<double>));
+  LS_HIP(hipMemcpy(rows.data(), plan->sd.rows.p, plan->sd.rows.bytes, hipMemcpyDeviceToHost));
+  host_free(plan->hs);
+  plan->hs = nullptr;
+  LS_TRY(host_factor(plan->ap.n, rows.data(), plan->host_mem_cap, &plan->hs));
+  if (seconds_out) *seconds_out = now_s() - t0;
+  return LS_OK;
+}
+
+ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream) {
+  if (!plan || !v_dev || !z_dev || nrhs < 1) return LS_EINVAL;
+  if (!plan->hs) return LS_ESTATE;
+  hipStream_t s = as_stream(hip_stream);
+  const long len = plan->gctx.len;
+  if (v_dev != z_dev)
+    LS_HIP(hipMemcpyAsync(z_dev, v_dev, (size_t)nrhs * len * sizeof(C<double>), hipMemcpyDeviceToDevice, s));
+  std::vector<int> lb(nrhs);
+  for (int b = 0; b < nrhs; ++b) lb[b] = b;
+  C<double>* z = static_cast<C<double>*>(z_dev);
+  return precond_list(plan, lb, [&](int b) { return z + (long)b * len; }, s, nullptr);
+}
+
+ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
+                         int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream) {
+  if (!plan || !g_dev || !x_dev || nrhs < 1 || !info || restart < 1 || maxit < 1 || !(tol > 0.0))
+    return LS_EINVAL;
+  if (apply_prec != LS_C128 && apply_prec != LS_MIXED) return LS_EINVAL;
+  if (!plan->hs) return LS_ESTATE;
+  hipStream_t s = as_stream(hip_stream);
+  GmresOps ops;
+  ops.apply = [plan](const C<double>* x, C<double>* y, int nb, ls_prec pr, hipStream_t st) {
+    return apply_chunked(plan, x, y, nb, pr, st);
+  };
+  ops.precond_batch = [plan](const std::vector<int>& lb, const std::function<C<double>*(int)>& ptr, hipStream_t st,
+                             double* th) { return precond_list(plan, lb, ptr, st, th); };
+  const double t0 = now_s();
+  ls_status st = gmres_solve(plan->gctx, ops, static_cast<const C<double>*>(g_dev), static_cast<C<double>*>(x_dev),
+                             nrhs, tol, restart, maxit, apply_prec, info, s);
+  const double tt = now_s() - t0;
+  for (int b = 0; b < nrhs; ++b) info[b].t_gpu = tt / nrhs - info[b].t_host;
+  return st;
+}
+
+ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_sparse** out) {
+  if (n < 1 || !rows_host || !out) return LS_EINVAL;
+  *out = nullptr;
+  ls_sparse* sp = new (std::nothrow) ls_sparse();
+  if (!sp) return LS_ENOMEM;
+  ls_status st = host_factor(n, static_cast<const std::complex<double>*>(rows_host), host_mem_cap, &sp->hs);
+  if (st != LS_OK) {
+    delete sp;
+    return st;
+  }
+  *out = sp;
+  return LS_OK;
+}
+
+ls_status ls_sparse_solve_host(ls_sparse* sp, void* b_host, int nrhs) {
+  if (!sp || !b_host || nrhs < 1) return LS_EINVAL;
+  return host_solve(sp->hs, static_cast<std::complex<double>*>(b_host), nrhs);
+}
+
+ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops) {
+  if (!sp) return LS_EINVAL;
+  if (bytes) *bytes = host_factor_bytes(sp->hs);
+  if (flops) *flops = host_factor_flops(sp->hs);
+  return LS_OK;
+}
+
+void ls_sparse_destroy(ls_sparse* sp) { delete sp; }
 
 int ls_plan_fft_size(const ls_plan* plan) { return plan ? plan->ap.P : 0; }
 

@@ -77,9 +77,3 @@ ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec pre
                     bool minus_conv = false, hipEvent_t* ev = nullptr);
 
 }  // namespace ls
-
-struct ls_plan {
-  ls::ApplyPlan ap;
-  std::string tune_cache;
-  size_t host_mem_cap = 0;
-};

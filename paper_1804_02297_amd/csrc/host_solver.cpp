@@ -1,0 +1,547 @@
+// Host multifrontal sparse LU of the sparsified system S.
+//
+// Paper: the assembled local rows form a sparse system that is factored by
+// nested dissection and used as the preconditioner (end of Section 3.1;
+// costs in Section 3.3).  Here: geometric nested dissection of the n^3 grid
+// (planar separators of thickness one, which separate a 27-point stencil),
+// a multifrontal LU with partial pivoting inside each front's pivot block,
+// and multifrontal forward / backward solves for many right-hand sides.
+//
+// Front of a node = its pivot points (the separator; all points of the box
+// for a leaf) followed by its boundary points (the one-point shell of its
+// box, which lies on ancestor separators).  Entry (i, j) of S is assembled
+// at the node that eliminates i or j first.  Fronts are dense, row-major,
+// with real and imaginary parts stored apart (vectorises on AVX2/AVX-512);
+// the subtree recursion and the Schur-complement updates of large fronts
+// run as OpenMP tasks.
+#include "host_solver.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+namespace ls {
+
+namespace {
+
+constexpr int kLeafPoints = 64;
+constexpr int kNB = 32;         // panel width of the blocked partial LU
+
+struct Node {
+  int lo[3], hi[3];
+  int child[2] = {-1, -1};
+  std::vector<int> piv, bnd;    // sorted global point indices
+  int np = 0, nb = 0;
+  std::vector<double> l11r, l11i;   // np x np: L (unit, below) and U (on and above)
+  std::vector<double> u12r, u12i;   // np x nb
+  std::vector<double> l21r, l21i;   // nb x np
+  std::vector<int> ipiv;            // np
+  std::vector<double> updr, updi;   // nb x nb update matrix, freed once the parent took it
+};
+
+inline int pos_in(const std::vector<int>& v, int p) {
+  auto it = std::lower_bound(v.begin(), v.end(), p);
+  return (it != v.end() && *it == p) ? int(it - v.begin()) : -1;
+}
+
+// C[i][j] -= sum_k A[i][k] B[k][j] over rows [r0, r1), cols [c0, c1), k in [k0, k1)
+// of one row-major planar matrix (lda = nf).  Four rows at a time share B loads.
+#if defined(__x86_64__)
+__attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+void gemm_rows(double* __restrict__ Fr, double* __restrict__ Fi, long nf, long r0, long r1, long c0, long c1,
+               long k0, long k1) {
+  constexpr long JB = 256;
+  for (long jb = c0; jb < c1; jb += JB) {
+    const long je = std::min(c1, jb + JB);
+    long i = r0;
+    for (; i + 4 <= r1; i += 4) {
+      double* c0r = Fr + i * nf;
+      double* c0i = Fi + i * nf;
+      double* c1r = c0r + nf;
+      double* c1i = c0i + nf;
+      double* c2r = c1r + nf;
+      double* c2i = c1i + nf;
+      double* c3r = c2r + nf;
+      double* c3i = c2i + nf;
+      for (long k = k0; k < k1; ++k) {
+        const double a0r = c0r[k], a0i = c0i[k], a1r = c1r[k], a1i = c1i[k];
+        const double a2r = c2r[k], a2i = c2i[k], a3r = c3r[k], a3i = c3i[k];
+        const double* br = Fr + k * nf;
+        const double* bi = Fi + k * nf;
+#pragma omp simd
+        for (long j = jb; j < je; ++j) {
+          const double xr = br[j], xi = bi[j];
+          c0r[j] -= a0r * xr - a0i * xi;
+          c0i[j] -= a0r * xi + a0i * xr;
+          c1r[j] -= a1r * xr - a1i * xi;
+          c1i[j] -= a1r * xi + a1i * xr;
+          c2r[j] -= a2r * xr - a2i * xi;
+          c2i[j] -= a2r * xi + a2i * xr;
+          c3r[j] -= a3r * xr - a3i * xi;
+          c3i[j] -= a3r * xi + a3i * xr;
+        }
+      }
+    }
+    for (; i < r1; ++i) {
+      double* cr = Fr + i * nf;
+      double* ci = Fi + i * nf;
+      for (long k = k0; k < k1; ++k) {
+        const double ar = cr[k], ai = ci[k];
+        const double* br = Fr + k * nf;
+        const double* bi = Fi + k * nf;
+#pragma omp simd
+        for (long j = jb; j < je; ++j) {
+          cr[j] -= ar * br[j] - ai * bi[j];
+          ci[j] -= ar * bi[j] + ai * br[j];
+        }
+      }
+    }
+  }
+}
+
+// Partial LU of the nf x nf front: eliminate the first np pivots, choosing
+// each pivot by magnitude among the remaining pivot rows; the trailing
+// (nf-np) x (nf-np) block becomes the Schur complement.
+void partial_lu(double* Fr, double* Fi, long nf, long np, int* ipiv, double* flops) {
+  for (long kb = 0; kb < np; kb += kNB) {
+    const long ke = std::min(np, kb + kNB);
+    for (long k = kb; k < ke; ++k) {
+      long p = k;
+      double best = -1.0;
+      for (long i = k; i < np; ++i) {
+        const double v = Fr[i * nf + k] * Fr[i * nf + k] + Fi[i * nf + k] * Fi[i * nf + k];
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      ipiv[k] = (int)p;
+      if (p != k) {
+        std::swap_ranges(Fr + k * nf, Fr + (k + 1) * nf, Fr + p * nf);
+        std::swap_ranges(Fi + k * nf, Fi + (k + 1) * nf, Fi + p * nf);
+      }
+      double pr = Fr[k * nf + k], pi = Fi[k * nf + k];
+      double den = pr * pr + pi * pi;
+      if (den == 0.0) {   // exactly singular pivot block: perturb (FGMRES absorbs it)
+        pr = 1e-300;
+        pi = 0.0;
+        Fr[k * nf + k] = pr;
+        den = pr * pr;
+      }
+      const double ir = pr / den, ii = -pi / den;
+      for (long i = k + 1; i < nf; ++i) {
+        const double xr = Fr[i * nf + k], xi = Fi[i * nf + k];
+        const double lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+        Fr[i * nf + k] = lr;
+        Fi[i * nf + k] = li;
+        double* rr = Fr + i * nf;
+        double* ri = Fi + i * nf;
+        const double* kr = Fr + k * nf;
+        const double* ki = Fi + k * nf;
+        for (long j = k + 1; j < ke; ++j) {
+          rr[j] -= lr * kr[j] - li * ki[j];
+          ri[j] -= lr * ki[j] + li * kr[j];
+        }
+      }
+    }
+    // block row: unit-lower solve for columns [ke, nf) of rows [kb, ke)
+    for (long k = kb; k < ke; ++k)
+      for (long i = k + 1; i < ke; ++i) {
+        const double lr = Fr[i * nf + k], li = Fi[i * nf + k];
+        double* rr = Fr + i * nf;
+        double* ri = Fi + i * nf;
+        const double* kr = Fr + k * nf;
+        const double* ki = Fi + k * nf;
+        for (long j = ke; j < nf; ++j) {
+          rr[j] -= lr * kr[j] - li * ki[j];
+          ri[j] -= lr * ki[j] + li * kr[j];
+        }
+      }
+    // trailing update, rows split into tasks when the front is large
+    const long rows = nf - ke;
+    const double work = (double)rows * (double)rows * (double)(ke - kb);
+    *flops += 8.0 * work;
+    if (work > 2e6) {
+      const long grain = std::max(8L, rows / (4 * omp_get_num_threads() + 1));
+#pragma omp taskloop grainsize(grain)
+      for (long i0 = ke; i0 < nf; i0 += 8) gemm_rows(Fr, Fi, nf, i0, std::min(nf, i0 + 8), ke, nf, kb, ke);
+    } else {
+      gemm_rows(Fr, Fi, nf, ke, nf, ke, nf, kb, ke);
+    }
+  }
+}
+
+}  // namespace
+
+struct HostSolver {
+  int n = 0;
+  std::vector<Node> nodes;
+  int root = -1;
+  std::vector<int> post;           // post-order of the elimination tree
+  std::vector<const std::complex<double>*> dummy;
+  size_t bytes = 0;
+  double flops = 0.0;
+};
+
+namespace {
+
+int build_tree(HostSolver& hs, const int lo[3], const int hi[3]) {
+  const int n = hs.n;
+  Node nd;
+  for (int d = 0; d < 3; ++d) {
+    nd.lo[d] = lo[d];
+    nd.hi[d] = hi[d];
+  }
+  long len[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+  const long vol = len[0] * len[1] * len[2];
+  int dsplit = 0;
+  for (int d = 1; d < 3; ++d)
+    if (len[d] > len[dsplit]) dsplit = d;
+  const bool leaf = vol <= kLeafPoints || len[dsplit] <= 2;
+  int mid = lo[dsplit] + (int)(len[dsplit] / 2);
+  for (int a = lo[0]; a < hi[0]; ++a)
+    for (int b = lo[1]; b < hi[1]; ++b)
+      for (int c = lo[2]; c < hi[2]; ++c) {
+        const int q[3] = {a, b, c};
+        if (leaf || q[dsplit] == mid) nd.piv.push_back((a * n + b) * n + c);
+      }
+  for (int a = std::max(0, lo[0] - 1); a < std::min(n, hi[0] + 1); ++a)
+    for (int b = std::max(0, lo[1] - 1); b < std::min(n, hi[1] + 1); ++b)
+      for (int c = std::max(0, lo[2] - 1); c < std::min(n, hi[2] + 1); ++c) {
+        const bool inside = a >= lo[0] && a < hi[0] && b >= lo[1] && b < hi[1] && c >= lo[2] && c < hi[2];
+        if (!inside) nd.bnd.push_back((a * n + b) * n + c);
+      }
+  nd.np = 3 * (int)nd.piv.size();
+  nd.nb = 3 * (int)nd.bnd.size();
+  const int id = (int)hs.nodes.size();
+  hs.nodes.push_back(std::move(nd));
+  if (!leaf) {
+    int l_hi[3] = {hi[0], hi[1], hi[2]};
+    int r_lo[3] = {lo[0], lo[1], lo[2]};
+    l_hi[dsplit] = mid;
+    r_lo[dsplit] = mid + 1;
+    int c0 = -1, c1 = -1;
+    if (mid > lo[dsplit]) c0 = build_tree(hs, lo, l_hi);
+    if (mid + 1 < hi[dsplit]) c1 = build_tree(hs, r_lo, hi);
+    hs.nodes[id].child[0] = c0;
+    hs.nodes[id].child[1] = c1;
+  }
+  return id;
+}
+
+void post_order(const HostSolver& hs, int id, std::vector<int>& out) {
+  const Node& nd = hs.nodes[id];
+  for (int c : nd.child)
+    if (c >= 0) post_order(hs, c, out);
+  out.push_back(id);
+}
+
+size_t node_factor_bytes(const Node& nd) {
+  return 16ull * ((size_t)nd.np * nd.np + 2ull * nd.np * nd.nb);
+}
+
+// local front index of global point p (pivot first, then boundary), or -1
+inline int front_pos(const Node& nd, int p) {
+  int k = pos_in(nd.piv, p);
+  if (k >= 0) return k;
+  k = pos_in(nd.bnd, p);
+  return k >= 0 ? (int)nd.piv.size() + k : -1;
+}
+
+void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::atomic<double>* flops) {
+  Node& nd = hs.nodes[id];
+  const int n = hs.n;
+  const long np = nd.np, nb = nd.nb, nf = np + nb;
+  std::vector<double> Fr((size_t)nf * nf, 0.0), Fi((size_t)nf * nf, 0.0);
+  auto add_point_rows = [&](int pi, int li, bool pivot_row) {
+    const int i3 = pi % n, i2 = (pi / n) % n, i1 = pi / (n * n);
+    for (int s1 = -1; s1 <= 1; ++s1)
+      for (int s2 = -1; s2 <= 1; ++s2)
+        for (int s3 = -1; s3 <= 1; ++s3) {
+          const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
+          if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n || j3 < 0 || j3 >= n) continue;
+          const int pj = (j1 * n + j2) * n + j3;
+          int lj;
+          if (pivot_row) {
+            lj = front_pos(nd, pj);
+          } else {
+            lj = pos_in(nd.piv, pj);
+          }
+          if (lj < 0) continue;
+          const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+              const std::complex<double> v = rows[(size_t)pi * 243 + (r * 27 + slot) * 3 + c];
+              const size_t o = (size_t)(3 * li + r) * nf + (3 * lj + c);
+              Fr[o] += v.real();
+              Fi[o] += v.imag();
+            }
+        }
+  };
+  for (size_t a = 0; a < nd.piv.size(); ++a) add_point_rows(nd.piv[a], (int)a, true);
+  for (size_t a = 0; a < nd.bnd.size(); ++a) add_point_rows(nd.bnd[a], (int)(nd.piv.size() + a), false);
+  // extend-add of the children's update matrices
+  for (int c : nd.child) {
+    if (c < 0) continue;
+    Node& ch = hs.nodes[c];
+    std::vector<int> map(ch.nb);
+    for (size_t a = 0; a < ch.bnd.size(); ++a) {
+      const int fp = front_pos(nd, ch.bnd[a]);
+      for (int q = 0; q < 3; ++q) map[3 * a + q] = 3 * fp + q;
+    }
+    for (int r = 0; r < ch.nb; ++r)
+      for (int s = 0; s < ch.nb; ++s) {
+        const size_t o = (size_t)map[r] * nf + map[s];
+        Fr[o] += ch.updr[(size_t)r * ch.nb + s];
+        Fi[o] += ch.updi[(size_t)r * ch.nb + s];
+      }
+    std::vector<double>().swap(ch.updr);
+    std::vector<double>().swap(ch.updi);
+  }
+  nd.ipiv.resize(np);
+  double fl = 0.0;
+  partial_lu(Fr.data(), Fi.data(), nf, np, nd.ipiv.data(), &fl);
+  double prev = flops->load();
+  while (!flops->compare_exchange_weak(prev, prev + fl)) {
+  }
+  nd.l11r.resize(np * np);
+  nd.l11i.resize(np * np);
+  nd.u12r.resize(np * nb);
+  nd.u12i.resize(np * nb);
+  nd.l21r.resize(nb * np);
+  nd.l21i.resize(nb * np);
+  nd.updr.resize(nb * nb);
+  nd.updi.resize(nb * nb);
+  for (long i = 0; i < np; ++i) {
+    std::memcpy(&nd.l11r[i * np], &Fr[i * nf], np * sizeof(double));
+    std::memcpy(&nd.l11i[i * np], &Fi[i * nf], np * sizeof(double));
+    std::memcpy(&nd.u12r[i * nb], &Fr[i * nf + np], nb * sizeof(double));
+    std::memcpy(&nd.u12i[i * nb], &Fi[i * nf + np], nb * sizeof(double));
+  }
+  for (long i = 0; i < nb; ++i) {
+    std::memcpy(&nd.l21r[i * np], &Fr[(np + i) * nf], np * sizeof(double));
+    std::memcpy(&nd.l21i[i * np], &Fi[(np + i) * nf], np * sizeof(double));
+    std::memcpy(&nd.updr[i * nb], &Fr[(np + i) * nf + np], nb * sizeof(double));
+    std::memcpy(&nd.updi[i * nb], &Fi[(np + i) * nf + np], nb * sizeof(double));
+  }
+}
+
+void factor_rec(HostSolver& hs, int id, const std::complex<double>* rows, std::atomic<double>* flops) {
+  Node& nd = hs.nodes[id];
+  for (int c : nd.child) {
+    if (c < 0) continue;
+#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 16)
+    factor_rec(hs, c, rows, flops);
+  }
+#pragma omp taskwait
+  factor_node(hs, id, rows, flops);
+}
+
+// ---- solves ---------------------------------------------------------------------
+// Per node and right-hand side: w (nf) = [b at pivots; 0] + children's update
+// vectors; z1 = L11^-1 P w1 is kept, u = w2 - L21 z1 goes to the parent.
+struct SolveWork {
+  std::vector<std::vector<double>> ur, ui;   // per node: nb x nrhs update vectors
+};
+
+void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
+              SolveWork& W, long ldb) {
+  Node& nd = hs.nodes[id];
+  const long np = nd.np, nb = nd.nb, nf = np + nb;
+  std::vector<double> wr((size_t)nf * nrhs, 0.0), wi((size_t)nf * nrhs, 0.0);   // [dof][rhs]
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      for (int r = 0; r < nrhs; ++r) {
+        wr[(3 * a + q) * nrhs + r] = Br[r * ldb + g];
+        wi[(3 * a + q) * nrhs + r] = Bi[r * ldb + g];
+      }
+    }
+  for (int c : nd.child) {
+    if (c < 0) continue;
+    Node& ch = hs.nodes[c];
+    for (size_t a = 0; a < ch.bnd.size(); ++a) {
+      const int fp = front_pos(nd, ch.bnd[a]);
+      for (int q = 0; q < 3; ++q)
+        for (int r = 0; r < nrhs; ++r) {
+          wr[(3 * fp + q) * nrhs + r] += W.ur[c][(3 * a + q) * nrhs + r];
+          wi[(3 * fp + q) * nrhs + r] += W.ui[c][(3 * a + q) * nrhs + r];
+        }
+    }
+    std::vector<double>().swap(W.ur[c]);
+    std::vector<double>().swap(W.ui[c]);
+  }
+  // row interchanges, then unit-lower solve on the pivot part
+  for (long k = 0; k < np; ++k) {
+    const long p = nd.ipiv[k];
+    if (p != k)
+      for (int r = 0; r < nrhs; ++r) {
+        std::swap(wr[k * nrhs + r], wr[p * nrhs + r]);
+        std::swap(wi[k * nrhs + r], wi[p * nrhs + r]);
+      }
+  }
+  for (long i = 0; i < np; ++i)
+    for (long k = 0; k < i; ++k) {
+      const double lr = nd.l11r[i * np + k], li = nd.l11i[i * np + k];
+      for (int r = 0; r < nrhs; ++r) {
+        const double xr = wr[k * nrhs + r], xi = wi[k * nrhs + r];
+        wr[i * nrhs + r] -= lr * xr - li * xi;
+        wi[i * nrhs + r] -= lr * xi + li * xr;
+      }
+    }
+  for (long i = 0; i < nb; ++i)
+    for (long k = 0; k < np; ++k) {
+      const double lr = nd.l21r[i * np + k], li = nd.l21i[i * np + k];
+      for (int r = 0; r < nrhs; ++r) {
+        const double xr = wr[k * nrhs + r], xi = wi[k * nrhs + r];
+        wr[(np + i) * nrhs + r] -= lr * xr - li * xi;
+        wi[(np + i) * nrhs + r] -= lr * xi + li * xr;
+      }
+    }
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      for (int r = 0; r < nrhs; ++r) {
+        Zr[r * ldb + g] = wr[(3 * a + q) * nrhs + r];
+        Zi[r * ldb + g] = wi[(3 * a + q) * nrhs + r];
+      }
+    }
+  W.ur[id].assign(wr.begin() + np * nrhs, wr.end());
+  W.ui[id].assign(wi.begin() + np * nrhs, wi.end());
+}
+
+void fwd_rec(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
+             SolveWork& W, long ldb) {
+  for (int c : hs.nodes[id].child) {
+    if (c < 0) continue;
+#pragma omp task firstprivate(c) shared(hs, W) if (hs.nodes[c].piv.size() > 64)
+    fwd_rec(hs, c, nrhs, Br, Bi, Zr, Zi, W, ldb);
+  }
+#pragma omp taskwait
+  fwd_node(hs, id, nrhs, Br, Bi, Zr, Zi, W, ldb);
+}
+
+// x_P = U11^-1 (z1 - U12 x_B); X holds z on entry at pivots, x on exit
+void bwd_node(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
+  Node& nd = hs.nodes[id];
+  const long np = nd.np, nb = nd.nb;
+  std::vector<double> xr((size_t)np * nrhs), xi((size_t)np * nrhs);
+  std::vector<double> yr((size_t)nb * nrhs), yi((size_t)nb * nrhs);
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q)
+      for (int r = 0; r < nrhs; ++r) {
+        xr[(3 * a + q) * nrhs + r] = Xr[r * ldb + 3L * nd.piv[a] + q];
+        xi[(3 * a + q) * nrhs + r] = Xi[r * ldb + 3L * nd.piv[a] + q];
+      }
+  for (size_t a = 0; a < nd.bnd.size(); ++a)
+    for (int q = 0; q < 3; ++q)
+      for (int r = 0; r < nrhs; ++r) {
+        yr[(3 * a + q) * nrhs + r] = Xr[r * ldb + 3L * nd.bnd[a] + q];
+        yi[(3 * a + q) * nrhs + r] = Xi[r * ldb + 3L * nd.bnd[a] + q];
+      }
+  for (long i = 0; i < np; ++i)
+    for (long k = 0; k < nb; ++k) {
+      const double ur = nd.u12r[i * nb + k], ui = nd.u12i[i * nb + k];
+      for (int r = 0; r < nrhs; ++r) {
+        const double vr = yr[k * nrhs + r], vi = yi[k * nrhs + r];
+        xr[i * nrhs + r] -= ur * vr - ui * vi;
+        xi[i * nrhs + r] -= ur * vi + ui * vr;
+      }
+    }
+  for (long i = np - 1; i >= 0; --i) {
+    for (long k = i + 1; k < np; ++k) {
+      const double ur = nd.l11r[i * np + k], ui = nd.l11i[i * np + k];
+      for (int r = 0; r < nrhs; ++r) {
+        const double vr = xr[k * nrhs + r], vi = xi[k * nrhs + r];
+        xr[i * nrhs + r] -= ur * vr - ui * vi;
+        xi[i * nrhs + r] -= ur * vi + ui * vr;
+      }
+    }
+    const double dr = nd.l11r[i * np + i], di = nd.l11i[i * np + i];
+    const double den = dr * dr + di * di;
+    for (int r = 0; r < nrhs; ++r) {
+      const double vr = xr[i * nrhs + r], vi = xi[i * nrhs + r];
+      xr[i * nrhs + r] = (vr * dr + vi * di) / den;
+      xi[i * nrhs + r] = (vi * dr - vr * di) / den;
+    }
+  }
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q)
+      for (int r = 0; r < nrhs; ++r) {
+        Xr[r * ldb + 3L * nd.piv[a] + q] = xr[(3 * a + q) * nrhs + r];
+        Xi[r * ldb + 3L * nd.piv[a] + q] = xi[(3 * a + q) * nrhs + r];
+      }
+}
+
+void bwd_rec(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
+  bwd_node(hs, id, nrhs, Xr, Xi, ldb);
+  for (int c : hs.nodes[id].child) {
+    if (c < 0) continue;
+#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 64)
+    bwd_rec(hs, c, nrhs, Xr, Xi, ldb);
+  }
+#pragma omp taskwait
+}
+
+}  // namespace
+
+ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, HostSolver** out) {
+  if (n < 1 || !rows || !out) return LS_EINVAL;
+  std::unique_ptr<HostSolver> hs(new HostSolver());
+  hs->n = n;
+  const int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
+  hs->root = build_tree(*hs, lo, hi);
+  post_order(*hs, hs->root, hs->post);
+  size_t need = 0;
+  for (const Node& nd : hs->nodes) need += node_factor_bytes(nd);
+  hs->bytes = need;
+  if (mem_cap && need > mem_cap) return LS_EHOST;
+  std::atomic<double> flops(0.0);
+#pragma omp parallel
+#pragma omp single
+  factor_rec(*hs, hs->root, rows, &flops);
+  hs->flops = flops.load();
+  *out = hs.release();
+  return LS_OK;
+}
+
+ls_status host_solve(HostSolver* hs, std::complex<double>* b, int nrhs) {
+  if (!hs || !b || nrhs < 1) return LS_EINVAL;
+  const long n3 = (long)hs->n * hs->n * hs->n;
+  const long ldb = 3 * n3;
+  std::vector<double> Br((size_t)nrhs * ldb), Bi((size_t)nrhs * ldb);
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < 3; ++c)
+      for (long p = 0; p < n3; ++p) {
+        const std::complex<double> v = b[(size_t)r * ldb + c * n3 + p];
+        Br[r * ldb + 3 * p + c] = v.real();
+        Bi[r * ldb + 3 * p + c] = v.imag();
+      }
+  std::vector<double> Zr((size_t)nrhs * ldb, 0.0), Zi((size_t)nrhs * ldb, 0.0);
+  SolveWork W;
+  W.ur.resize(hs->nodes.size());
+  W.ui.resize(hs->nodes.size());
+#pragma omp parallel
+#pragma omp single
+  fwd_rec(*hs, hs->root, nrhs, Br.data(), Bi.data(), Zr.data(), Zi.data(), W, ldb);
+#pragma omp parallel
+#pragma omp single
+  bwd_rec(*hs, hs->root, nrhs, Zr.data(), Zi.data(), ldb);
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < 3; ++c)
+      for (long p = 0; p < n3; ++p)
+        b[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[r * ldb + 3 * p + c], Zi[r * ldb + 3 * p + c]);
+  return LS_OK;
+}
+
+size_t host_factor_bytes(const HostSolver* hs) { return hs ? hs->bytes : 0; }
+double host_factor_flops(const HostSolver* hs) { return hs ? hs->flops : 0.0; }
+void host_free(HostSolver* hs) { delete hs; }
+
+}  // namespace ls

@@ -1,0 +1,24 @@
+// The plan behind the opaque ls_plan handle.
+#pragma once
+
+#include "common.h"
+#include "gmres.h"
+#include "host_solver.h"
+#include "stencil.h"
+
+struct ls_plan {
+  ls::ApplyPlan ap;
+  ls::StencilData sd;
+  ls::HostSolver* hs = nullptr;
+  ls::GmresContext gctx;
+  ls::DevBuf qtmp;              // Q v scratch for the preconditioner
+  std::vector<std::complex<double>> hbuf;   // host staging of preconditioner vectors
+  std::string tune_cache;
+  size_t host_mem_cap = 0;
+  ~ls_plan() { ls::host_free(hs); }
+};
+
+struct ls_sparse {
+  ls::HostSolver* hs = nullptr;
+  ~ls_sparse() { ls::host_free(hs); }
+};
