@@ -98,7 +98,11 @@ ls_status ls_rhs_from_incident(ls_plan* plan, const void* Ei_dev, void* g_dev, i
 /* ---- sparsifying preconditioner (Section 3) ------------------------------- */
 
 typedef enum {
-  LS_FIT_CLASS = 0      /* the paper's fit: one stencil per position class     */
+  LS_FIT_CLASS = 0,     /* the paper's fit: one stencil per position class     */
+  LS_FIT_POINT = 1      /* medium-dependent per-point fit (project extension):
+                           interior points minimise sum_j w_j^2 |alpha^H K_{tau,j}|^2
+                           with w_j = 1 + |m_{i+j}| / 0.1 on the 5^3 shell around i
+                           and w_j = 1 beyond; boundary points keep the class fit */
 } ls_fit_mode;
 
 typedef struct {
@@ -129,6 +133,13 @@ ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream);
  * ls_stencil_fit. */
 ls_status ls_get_class_stencils(const ls_plan* plan, void* alpha_host, void* beta_host, double* eig_host,
                                 void* gram_host);
+
+/* Per-point stencils after LS_FIT_POINT: alpha_host [n^3][81][3] complex128
+ * (interior points: the medium-weighted fit; others: their class stencil in
+ * the first 3|tau| rows); eig_host [n^3][3] (the three smallest eigenvalues
+ * of each interior point's weighted Gram, zero elsewhere).  Either may be
+ * NULL.  LS_ESTATE unless the last fit was LS_FIT_POINT. */
+ls_status ls_get_point_stencils(const ls_plan* plan, void* alpha_host, double* eig_host);
 
 /* The assembled rows S to host memory: [n^3][3 rows][27 slots][3 comps]
  * complex128, slot 9 (s1+1) + 3 (s2+1) + (s3+1) for the neighbour at offset

@@ -42,6 +42,7 @@ SIGNATURES = [
     ("ls_rhs_from_incident", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls_stencil_fit", _I, [_VP, _I, _VP]),
     ("ls_get_class_stencils", _I, [_VP, _VP, _VP, _VP, _VP]),
+    ("ls_get_point_stencils", _I, [_VP, _VP, _VP]),
     ("ls_get_rows", _I, [_VP, _VP]),
     ("ls_factor", _I, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
@@ -213,6 +214,15 @@ class Plan:
                                           gr.ctypes.data_as(ctypes.c_void_p) if gram else None),
                "ls_get_class_stencils")
         return (al, be, ev, gr) if gram else (al, be, ev)
+
+    def point_stencils(self):
+        """(alpha (n^3, 81, 3) complex128, eig (n^3, 3)) after a per-point fit."""
+        import numpy as np
+        al = np.zeros((self.n ** 3, 81, 3), np.complex128)
+        ev = np.zeros((self.n ** 3, 3), np.float64)
+        _check(_lib.ls_get_point_stencils(self._h, al.ctypes.data_as(ctypes.c_void_p),
+                                          ev.ctypes.data_as(ctypes.c_void_p)), "ls_get_point_stencils")
+        return al, ev
 
     def rows(self):
         """Assembled rows S, (n^3, 3, 27, 3) complex128."""

@@ -128,15 +128,27 @@ ls_status ls_rhs_from_incident(ls_plan* plan, const void* Ei_dev, void* g_dev, i
 }
 
 ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
-  if (!plan || mode != LS_FIT_CLASS) return LS_EINVAL;
+  if (!plan || (mode != LS_FIT_CLASS && mode != LS_FIT_POINT)) return LS_EINVAL;
+  if (plan->ap.n < 4) return LS_EINVAL;     // n = 3: the interior complement is empty
   hipStream_t s = as_stream(hip_stream);
   host_free(plan->hs);
   plan->hs = nullptr;
   plan->sd.have_point = false;
+  plan->sd.have_rows = false;
   LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
+  if (mode == LS_FIT_POINT)
+    LS_TRY(point_fit(plan->sd, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0, 16384, 12, s));
   LS_TRY(assemble_rows(plan->sd, plan->ap.n, plan->ap.m64.as<C<double>>(), s));
   LS_HIP(hipStreamSynchronize(s));
   plan->sd.have_rows = true;
+  return LS_OK;
+}
+
+ls_status ls_get_point_stencils(const ls_plan* plan, void* alpha_host, double* eig_host) {
+  if (!plan) return LS_EINVAL;
+  if (!plan->sd.have_point) return LS_ESTATE;
+  if (alpha_host) LS_HIP(hipMemcpy(alpha_host, plan->sd.palpha.p, plan->sd.palpha.bytes, hipMemcpyDeviceToHost));
+  if (eig_host) LS_HIP(hipMemcpy(eig_host, plan->sd.peval.p, plan->sd.peval.bytes, hipMemcpyDeviceToHost));
   return LS_OK;
 }
 

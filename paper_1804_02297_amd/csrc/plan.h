@@ -4,7 +4,12 @@
 #include "common.h"
 #include "gmres.h"
 #include "host_solver.h"
+#include "pointfit.h"
 #include "stencil.h"
+
+namespace ls {
+constexpr double kPointFitM0 = 0.1;   // medium scale of the per-point weights w = 1 + |m| / m0
+}
 
 struct ls_plan {
   ls::ApplyPlan ap;

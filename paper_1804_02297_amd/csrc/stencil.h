@@ -26,7 +26,9 @@ struct StencilData {
   DevBuf gram;                   // 27 x 81 x 81 complex128 (class Gram M M^H)
   DevBuf alpha, beta;            // 27 x 81 x 3 complex128 (rows (a, c), column v)
   DevBuf evals;                  // 27 x 3: three smallest eigenvalues of each Gram
+  DevBuf ritz8;                  // 27 x 81 x 8: the eight lowest Ritz vectors of each Gram
   DevBuf palpha, pbeta;          // per-point stencils n^3 x 81 x 3 (medium-dependent modes)
+  DevBuf peval;                  // n^3 x 3: per-point smallest eigenvalues (0 where unset)
   DevBuf rows;                   // S rows: n^3 x [3 rows][27 slots][3 comps] complex128
   bool have_class = false;
   bool have_point = false;

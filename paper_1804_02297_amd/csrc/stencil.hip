@@ -241,7 +241,8 @@ __device__ inline void jacobi8(C<double> (*T)[EB], C<double> (*V)[EB]) {
 // three smallest Ritz values.
 __global__ __launch_bounds__(256) void heev_low3_kernel(const C<double>* __restrict__ Gall, const int* __restrict__ Rs,
                                                         long gstride, C<double>* __restrict__ alpha_all,
-                                                        long astride, double* __restrict__ evals) {
+                                                        long astride, double* __restrict__ evals,
+                                                        C<double>* __restrict__ ritz8) {
   constexpr int RMAX = 81;
   __shared__ C<double> L[RMAX * (RMAX + 1) / 2];
   __shared__ C<double> Xb[RMAX][EB];
@@ -380,10 +381,8 @@ __global__ __launch_bounds__(256) void heev_low3_kernel(const C<double>* __restr
           idx[p] = idx[q];
           idx[q] = t;
         }
-    for (int v = 0; v < 3; ++v) {
-      Yk[v] = cmk((double)idx[v], 0.0);
-      evals[mat * 3 + v] = T[idx[v]][idx[v]].re;
-    }
+    for (int v = 0; v < EB; ++v) Yk[v] = cmk((double)idx[v], 0.0);
+    for (int v = 0; v < 3; ++v) evals[mat * 3 + v] = T[idx[v]][idx[v]].re;
   }
   __syncthreads();
   C<double>* alpha = alpha_all + mat * astride;
@@ -393,6 +392,15 @@ __global__ __launch_bounds__(256) void heev_low3_kernel(const C<double>* __restr
     C<double> s = cmk(0.0, 0.0);
     for (int q = 0; q < EB; ++q) s = s + Xb[i][q] * V[q][col];
     alpha[i * 3 + v] = s;
+  }
+  // all eight Ritz vectors in ascending order (warm start of the per-point fit)
+  C<double>* r8 = ritz8 + (long)mat * 81 * EB;
+  for (int e = tid; e < R * EB; e += 256) {
+    const int i = e / EB, v = e % EB;
+    const int col = (int)Yk[v].re;
+    C<double> s = cmk(0.0, 0.0);
+    for (int q = 0; q < EB; ++q) s = s + Xb[i][q] * V[q][col];
+    r8[i * EB + v] = s;
   }
 }
 
@@ -494,6 +502,8 @@ ls_status class_fit(StencilData& sd, int n, double k, hipStream_t s) {
   LS_TRY(sd.alpha.alloc(27L * 81 * 3 * sizeof(C<double>)));
   LS_TRY(sd.beta.alloc(27L * 81 * 3 * sizeof(C<double>)));
   LS_TRY(sd.evals.alloc(27L * 3 * sizeof(double)));
+  LS_TRY(sd.ritz8.alloc(27L * 81 * 8 * sizeof(C<double>)));
+  LS_HIP(hipMemsetAsync(sd.ritz8.p, 0, sd.ritz8.bytes, s));
   DevBuf dR;
   LS_TRY(dR.alloc(27 * sizeof(int)));
   LS_HIP(hipMemcpyAsync(dR.p, Rs.data(), 27 * sizeof(int), hipMemcpyHostToDevice, s));
@@ -525,7 +535,7 @@ ls_status class_fit(StencilData& sd, int n, double k, hipStream_t s) {
     LS_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(heev_low3_kernel, dim3(27), dim3(256), 0, s, sd.gram.as<C<double>>(), dR.as<int>(),
-                     81L * 81, sd.alpha.as<C<double>>(), 81L * 3, sd.evals.as<double>());
+                     81L * 81, sd.alpha.as<C<double>>(), 81L * 3, sd.evals.as<double>(), sd.ritz8.as<C<double>>());
   LS_HIP(hipGetLastError());
   hipLaunchKernelGGL(beta_kernel, dim3(27), dim3(256), 0, s, sd.geoms.as<ClassGeom>(), k, h,
                      sd.alpha.as<C<double>>(), sd.beta.as<C<double>>(), 81L * 3);
