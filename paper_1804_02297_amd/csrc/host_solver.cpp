@@ -343,77 +343,144 @@ void factor_rec(HostSolver& hs, int id, const std::complex<double>* rows, std::a
   factor_node(hs, id, rows, flops);
 }
 
+
 // ---- solves ---------------------------------------------------------------------
-// Per node and right-hand side: w (nf) = [b at pivots; 0] + children's update
-// vectors; z1 = L11^-1 P w1 is kept, u = w2 - L21 z1 goes to the parent.
+// Vectors are kept right-hand-side major ([rhs][dof], real and imaginary
+// parts apart) so that every inner product with a factor row is a contiguous
+// SIMD dot product.  Per node and rhs: w (nf) = [b at pivots; 0] + children's
+// update vectors; z1 = L11^-1 P w1 is kept, u = w2 - L21 z1 goes to the parent.
+// Backward: x1 = U11^-1 (z1 - U12 x_B).
 struct SolveWork {
-  std::vector<std::vector<double>> ur, ui;   // per node: nb x nrhs update vectors
+  std::vector<std::vector<double>> ur, ui;   // per node: [rhs][nb] update vectors
 };
+
+// sum_k (ar + i ai)[k] (xr + i xi)[k]
+#if defined(__x86_64__)
+__attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+void cdot(const double* __restrict__ ar, const double* __restrict__ ai, const double* __restrict__ xr,
+          const double* __restrict__ xi, long len, double* outr, double* outi) {
+  double sr = 0.0, si = 0.0;
+#pragma omp simd reduction(+ : sr, si)
+  for (long k = 0; k < len; ++k) {
+    sr += ar[k] * xr[k] - ai[k] * xi[k];
+    si += ar[k] * xi[k] + ai[k] * xr[k];
+  }
+  *outr = sr;
+  *outi = si;
+}
+
+constexpr long kRowTask = 64;          // rows per task in the large matrix-vector products
+constexpr double kParWork = 4e5;       // complex MACs above which a product is split into tasks
+
+// y[i] -= sum_k A[i][k] x[k] for rows [0, m) of a row-major m x len block (lda), one rhs
+void gemv_sub(const double* Ar, const double* Ai, long lda, long m, long len, const double* xr, const double* xi,
+              double* yr, double* yi) {
+  auto rows = [&](long i0, long i1) {
+    for (long i = i0; i < i1; ++i) {
+      double dr, di;
+      cdot(Ar + i * lda, Ai + i * lda, xr, xi, len, &dr, &di);
+      yr[i] -= dr;
+      yi[i] -= di;
+    }
+  };
+  if ((double)m * (double)len > kParWork) {
+#pragma omp taskloop grainsize(1)
+    for (long i0 = 0; i0 < m; i0 += kRowTask) rows(i0, std::min(m, i0 + kRowTask));
+  } else {
+    rows(0, m);
+  }
+}
+
+// unit-lower solve L x = b in place (rows of L row-major, lda = np), blocked so
+// the off-diagonal block products run as tasks
+void lower_unit_solve(const double* Lr, const double* Li, long np, double* xr, double* xi) {
+  constexpr long BS = 256;
+  for (long b0 = 0; b0 < np; b0 += BS) {
+    const long b1 = std::min(np, b0 + BS);
+    // rows [b0, b1): subtract the contribution of x[0, b0)
+    if (b0 > 0) gemv_sub(Lr + b0 * np, Li + b0 * np, np, b1 - b0, b0, xr, xi, xr + b0, xi + b0);
+    for (long i = b0; i < b1; ++i) {
+      double dr, di;
+      cdot(Lr + i * np + b0, Li + i * np + b0, xr + b0, xi + b0, i - b0, &dr, &di);
+      xr[i] -= dr;
+      xi[i] -= di;
+    }
+  }
+}
+
+// upper solve U x = b in place (diagonal included)
+void upper_solve(const double* Ur, const double* Ui, long np, double* xr, double* xi) {
+  constexpr long BS = 256;
+  for (long b1 = np; b1 > 0; b1 -= BS) {
+    const long b0 = std::max(0L, b1 - BS);
+    if (b1 < np) gemv_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, xr + b1, xi + b1, xr + b0, xi + b0);
+    for (long i = b1 - 1; i >= b0; --i) {
+      double dr, di;
+      cdot(Ur + i * np + i + 1, Ui + i * np + i + 1, xr + i + 1, xi + i + 1, b1 - i - 1, &dr, &di);
+      const double vr = xr[i] - dr, vi = xi[i] - di;
+      const double ur = Ur[i * np + i], ui = Ui[i * np + i];
+      const double den = ur * ur + ui * ui;
+      xr[i] = (vr * ur + vi * ui) / den;
+      xi[i] = (vi * ur - vr * ui) / den;
+    }
+  }
+}
 
 void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
               SolveWork& W, long ldb) {
   Node& nd = hs.nodes[id];
   const long np = nd.np, nb = nd.nb, nf = np + nb;
-  std::vector<double> wr((size_t)nf * nrhs, 0.0), wi((size_t)nf * nrhs, 0.0);   // [dof][rhs]
-  for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      for (int r = 0; r < nrhs; ++r) {
-        wr[(3 * a + q) * nrhs + r] = Br[r * ldb + g];
-        wi[(3 * a + q) * nrhs + r] = Bi[r * ldb + g];
+  std::vector<double> wr((size_t)nf * nrhs, 0.0), wi((size_t)nf * nrhs, 0.0);   // [rhs][dof]
+  for (int r = 0; r < nrhs; ++r)
+    for (size_t a = 0; a < nd.piv.size(); ++a)
+      for (int q = 0; q < 3; ++q) {
+        const long g = 3L * nd.piv[a] + q;
+        wr[r * nf + 3 * a + q] = Br[r * ldb + g];
+        wi[r * nf + 3 * a + q] = Bi[r * ldb + g];
       }
-    }
   for (int c : nd.child) {
     if (c < 0) continue;
     Node& ch = hs.nodes[c];
+    std::vector<int> map(ch.nb);
     for (size_t a = 0; a < ch.bnd.size(); ++a) {
       const int fp = front_pos(nd, ch.bnd[a]);
-      for (int q = 0; q < 3; ++q)
-        for (int r = 0; r < nrhs; ++r) {
-          wr[(3 * fp + q) * nrhs + r] += W.ur[c][(3 * a + q) * nrhs + r];
-          wi[(3 * fp + q) * nrhs + r] += W.ui[c][(3 * a + q) * nrhs + r];
-        }
+      for (int q = 0; q < 3; ++q) map[3 * a + q] = 3 * fp + q;
     }
+    for (int r = 0; r < nrhs; ++r)
+      for (int e = 0; e < ch.nb; ++e) {
+        wr[r * nf + map[e]] += W.ur[c][(size_t)r * ch.nb + e];
+        wi[r * nf + map[e]] += W.ui[c][(size_t)r * ch.nb + e];
+      }
     std::vector<double>().swap(W.ur[c]);
     std::vector<double>().swap(W.ui[c]);
   }
-  // row interchanges, then unit-lower solve on the pivot part
-  for (long k = 0; k < np; ++k) {
-    const long p = nd.ipiv[k];
-    if (p != k)
-      for (int r = 0; r < nrhs; ++r) {
-        std::swap(wr[k * nrhs + r], wr[p * nrhs + r]);
-        std::swap(wi[k * nrhs + r], wi[p * nrhs + r]);
-      }
-  }
-  for (long i = 0; i < np; ++i)
-    for (long k = 0; k < i; ++k) {
-      const double lr = nd.l11r[i * np + k], li = nd.l11i[i * np + k];
-      for (int r = 0; r < nrhs; ++r) {
-        const double xr = wr[k * nrhs + r], xi = wi[k * nrhs + r];
-        wr[i * nrhs + r] -= lr * xr - li * xi;
-        wi[i * nrhs + r] -= lr * xi + li * xr;
-      }
-    }
-  for (long i = 0; i < nb; ++i)
+  for (int r = 0; r < nrhs; ++r) {
+    double* xr = &wr[(size_t)r * nf];
+    double* xi = &wi[(size_t)r * nf];
     for (long k = 0; k < np; ++k) {
-      const double lr = nd.l21r[i * np + k], li = nd.l21i[i * np + k];
-      for (int r = 0; r < nrhs; ++r) {
-        const double xr = wr[k * nrhs + r], xi = wi[k * nrhs + r];
-        wr[(np + i) * nrhs + r] -= lr * xr - li * xi;
-        wi[(np + i) * nrhs + r] -= lr * xi + li * xr;
+      const long p = nd.ipiv[k];
+      if (p != k) {
+        std::swap(xr[k], xr[p]);
+        std::swap(xi[k], xi[p]);
       }
     }
-  for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      for (int r = 0; r < nrhs; ++r) {
-        Zr[r * ldb + g] = wr[(3 * a + q) * nrhs + r];
-        Zi[r * ldb + g] = wi[(3 * a + q) * nrhs + r];
+    lower_unit_solve(nd.l11r.data(), nd.l11i.data(), np, xr, xi);
+    if (nb) gemv_sub(nd.l21r.data(), nd.l21i.data(), np, nb, np, xr, xi, xr + np, xi + np);
+  }
+  for (int r = 0; r < nrhs; ++r)
+    for (size_t a = 0; a < nd.piv.size(); ++a)
+      for (int q = 0; q < 3; ++q) {
+        const long g = 3L * nd.piv[a] + q;
+        Zr[r * ldb + g] = wr[r * nf + 3 * a + q];
+        Zi[r * ldb + g] = wi[r * nf + 3 * a + q];
       }
-    }
-  W.ur[id].assign(wr.begin() + np * nrhs, wr.end());
-  W.ui[id].assign(wi.begin() + np * nrhs, wi.end());
+  W.ur[id].resize((size_t)nrhs * nb);
+  W.ui[id].resize((size_t)nrhs * nb);
+  for (int r = 0; r < nrhs; ++r) {
+    std::memcpy(&W.ur[id][(size_t)r * nb], &wr[(size_t)r * nf + np], nb * sizeof(double));
+    std::memcpy(&W.ui[id][(size_t)r * nb], &wi[(size_t)r * nf + np], nb * sizeof(double));
+  }
 }
 
 void fwd_rec(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
@@ -427,56 +494,31 @@ void fwd_rec(HostSolver& hs, int id, int nrhs, const double* Br, const double* B
   fwd_node(hs, id, nrhs, Br, Bi, Zr, Zi, W, ldb);
 }
 
-// x_P = U11^-1 (z1 - U12 x_B); X holds z on entry at pivots, x on exit
 void bwd_node(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
   Node& nd = hs.nodes[id];
   const long np = nd.np, nb = nd.nb;
-  std::vector<double> xr((size_t)np * nrhs), xi((size_t)np * nrhs);
-  std::vector<double> yr((size_t)nb * nrhs), yi((size_t)nb * nrhs);
-  for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q)
-      for (int r = 0; r < nrhs; ++r) {
-        xr[(3 * a + q) * nrhs + r] = Xr[r * ldb + 3L * nd.piv[a] + q];
-        xi[(3 * a + q) * nrhs + r] = Xi[r * ldb + 3L * nd.piv[a] + q];
+  std::vector<double> xr((size_t)np), xi((size_t)np), yr((size_t)nb), yi((size_t)nb);
+  for (int r = 0; r < nrhs; ++r) {
+    double* Rr = Xr + r * ldb;
+    double* Ri = Xi + r * ldb;
+    for (size_t a = 0; a < nd.piv.size(); ++a)
+      for (int q = 0; q < 3; ++q) {
+        xr[3 * a + q] = Rr[3L * nd.piv[a] + q];
+        xi[3 * a + q] = Ri[3L * nd.piv[a] + q];
       }
-  for (size_t a = 0; a < nd.bnd.size(); ++a)
-    for (int q = 0; q < 3; ++q)
-      for (int r = 0; r < nrhs; ++r) {
-        yr[(3 * a + q) * nrhs + r] = Xr[r * ldb + 3L * nd.bnd[a] + q];
-        yi[(3 * a + q) * nrhs + r] = Xi[r * ldb + 3L * nd.bnd[a] + q];
+    for (size_t a = 0; a < nd.bnd.size(); ++a)
+      for (int q = 0; q < 3; ++q) {
+        yr[3 * a + q] = Rr[3L * nd.bnd[a] + q];
+        yi[3 * a + q] = Ri[3L * nd.bnd[a] + q];
       }
-  for (long i = 0; i < np; ++i)
-    for (long k = 0; k < nb; ++k) {
-      const double ur = nd.u12r[i * nb + k], ui = nd.u12i[i * nb + k];
-      for (int r = 0; r < nrhs; ++r) {
-        const double vr = yr[k * nrhs + r], vi = yi[k * nrhs + r];
-        xr[i * nrhs + r] -= ur * vr - ui * vi;
-        xi[i * nrhs + r] -= ur * vi + ui * vr;
+    if (nb) gemv_sub(nd.u12r.data(), nd.u12i.data(), nb, np, nb, yr.data(), yi.data(), xr.data(), xi.data());
+    upper_solve(nd.l11r.data(), nd.l11i.data(), np, xr.data(), xi.data());
+    for (size_t a = 0; a < nd.piv.size(); ++a)
+      for (int q = 0; q < 3; ++q) {
+        Rr[3L * nd.piv[a] + q] = xr[3 * a + q];
+        Ri[3L * nd.piv[a] + q] = xi[3 * a + q];
       }
-    }
-  for (long i = np - 1; i >= 0; --i) {
-    for (long k = i + 1; k < np; ++k) {
-      const double ur = nd.l11r[i * np + k], ui = nd.l11i[i * np + k];
-      for (int r = 0; r < nrhs; ++r) {
-        const double vr = xr[k * nrhs + r], vi = xi[k * nrhs + r];
-        xr[i * nrhs + r] -= ur * vr - ui * vi;
-        xi[i * nrhs + r] -= ur * vi + ui * vr;
-      }
-    }
-    const double dr = nd.l11r[i * np + i], di = nd.l11i[i * np + i];
-    const double den = dr * dr + di * di;
-    for (int r = 0; r < nrhs; ++r) {
-      const double vr = xr[i * nrhs + r], vi = xi[i * nrhs + r];
-      xr[i * nrhs + r] = (vr * dr + vi * di) / den;
-      xi[i * nrhs + r] = (vi * dr - vr * di) / den;
-    }
   }
-  for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q)
-      for (int r = 0; r < nrhs; ++r) {
-        Xr[r * ldb + 3L * nd.piv[a] + q] = xr[(3 * a + q) * nrhs + r];
-        Xi[r * ldb + 3L * nd.piv[a] + q] = xi[(3 * a + q) * nrhs + r];
-      }
 }
 
 void bwd_rec(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
