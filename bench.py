@@ -30,6 +30,30 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
                 "col_fft_kernel (mode 2)", "col_fft_kernel (mode 3)"]
 
 
+# HBM traffic of the dominant kernel (kmul_kernel, pass 3) per launch at n=128,
+# 8 rhs, complex64, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the 1 GiB
+# copy calibration (read = 2.0 x FETCH_SIZE, write = 1.0 x WRITE_SIZE), valid
+# only while the apply sources are the ones that were profiled.
+MEASURED_TRAFFIC = {
+    "sources": ["fft_apply.hip", "common.h", "cplx.h"],
+    "sha256": "d3c81545c8204ac98fff02b41a63af089979689c65db7b11e945675806b03de1",
+    "workload": (128, 8, "c64"),
+    "bytes": 3.3268e9,
+    "profile": "profiles/ls_apply_n128_b8_c64.md",
+}
+
+
+def measured_traffic(n: int, B: int, prec: str):
+    import hashlib
+    h = hashlib.sha256()
+    for f in MEASURED_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_1804_02297_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != MEASURED_TRAFFIC["sha256"] or (n, B, prec) != MEASURED_TRAFFIC["workload"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"]
+
+
 def pass_bytes(n: int, P: int, B: int, s: int, s_io: int) -> list[float]:
     """Algorithmic HBM bytes of each pass for B right-hand sides.
 
@@ -73,6 +97,60 @@ def cpu_baseline(n: int, seconds: float = 15.0):
                       f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
 
 
+def solve_section(n: int, ndirs: int, binding, I, torch):
+    """Per-rhs time to a 1e-8 relative residual: plain FP64 against the batched mixed form.
+
+    Both use the same class stencils and host factorisation (set-up timed
+    apart).  Plain: one rhs at a time, FP64 apply.  Batched: ndirs Fibonacci
+    directions x 2 polarisations solved together, FP32 apply inside the FP64
+    outer FGMRES.
+    """
+    import numpy as np
+    dev = torch.device("cuda:0")
+    k = I.wavenumber_for(n)
+    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
+    nb = 2 * ndirs
+    plan = binding.Plan(n, k, m, max_rhs=nb)
+    t0 = time.perf_counter()
+    plan.stencil_fit(0)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan.factor()
+    t_factor = time.perf_counter() - t0
+    dirs, pols = I.fibonacci_incident_set(ndirs)
+    Ei = torch.from_numpy(I.plane_waves(n, k, dirs, pols)).to(dev)
+    g = plan.rhs_from_incident(Ei)
+    torch.cuda.synchronize()
+
+    def run(gg, prec):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, infos, st = plan.solve(gg, tol=1e-8, prec=prec)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, x, infos, st
+
+    run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
+    t_plain, x1, inf1, st1 = run(g[:1], "c128")
+    t_mixed, xb, infb, stb = run(g, "mixed")
+    # residuals re-measured with the FP64 apply: r = g - A x
+    r = torch.empty_like(g)
+    plan.apply(xb, r, prec="c128")
+    rel = (torch.linalg.vector_norm((g - r).reshape(nb, -1), dim=1) /
+           torch.linalg.vector_norm(g.reshape(nb, -1), dim=1)).max().item()
+    plan.close()
+    return {
+        "n": n, "unknowns_per_rhs": 3 * n ** 3, "nrhs_batched": nb,
+        "stencil_fit_s": round(t_fit, 3), "factor_s": round(t_factor, 3),
+        "plain_fp64_s_per_rhs": round(t_plain, 4), "plain_iters": inf1[0]["iters"],
+        "batched_mixed_s_per_rhs": round(t_mixed / nb, 4),
+        "batched_iters_max": max(i["iters"] for i in infb),
+        "batched_max_rel_resid_fp64": float(f"{rel:.3e}"),
+        "status": [st1, stb],
+        "speedup_per_rhs": round(t_plain / (t_mixed / nb), 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +160,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--solve-n", type=int, default=32, help="grid of the per-rhs solve section (0: skip)")
+    ap.add_argument("--solve-dirs", type=int, default=8, help="incident directions (2 polarisations each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -155,7 +235,9 @@ def main():
                    "n": n, "fft_size": P, "nrhs": B, "unknowns_per_rhs": 3 * n ** 3},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "pass": PASS_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(n, B, "c64") if dom == 2 else None,
+                     "algorithmic_bytes": round(pb[dom])},
         "apply_whole_GBps": round(whole, 1),
         "apply_whole_frac": round(whole / HBM_PEAK_GBS, 4),
         "pass_ms": [round(v, 4) for v in pms],
@@ -164,6 +246,8 @@ def main():
         "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
         "wall_s_timed": round(wall32, 3),
     }
+    if args.solve_n:
+        out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)

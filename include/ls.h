@@ -167,6 +167,55 @@ ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nr
 ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
                          int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream);
 
+/* ---- learned stencils (project extension) ----------------------------------
+ * A network predicts each interior point's medium-dependent stencil from the
+ * 5^3 patch of m around it (x = Re, Im of m / 0.3, 250 inputs, last dimension
+ * fastest, zero off the grid): 250 -> 256 GELU -> 256 GELU -> 468, GELU(x) =
+ * x Phi(x).  The 468 outputs are the 26 off-centre 3x3 blocks [block][c][r]
+ * (re, im interleaved) of alpha~_i - alpha~_class, alpha~ = alpha (alpha_centre)^-1.
+ * Parameters: flat float32 W1[250][256] b1[256] W2[256][256] b2[256]
+ * W3[256][468] b3[468] (250324 values, y = x W + b).  Products use BF16
+ * operands with FP32 accumulation on MFMA; Adam (0.9, 0.999, 1e-8) updates
+ * FP32 masters.  The network lives on the device current at creation. */
+typedef struct ls_mlp ls_mlp;
+
+#define LS_MLP_NPARAM 250324
+
+ls_status ls_mlp_create(const float* params_host, ls_mlp** out);
+ls_status ls_mlp_get_params(const ls_mlp* mlp, float* params_host);
+/* One forward + backward pass on host data: x_host [B][250], t_host [B][468]
+ * (float32); y_host [B][468] outputs, grad_host [LS_MLP_NPARAM] the gradient of
+ * mean((y - t)^2), loss_out the loss.  Outputs may be NULL.  Synchronises. */
+ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float* t_host, int B, float* y_host,
+                                  float* grad_host, double* loss_out, void* hip_stream);
+/* One Adam step (learning rate lr) with the gradient of the last backward pass. */
+ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream);
+/* Exact per-point fits (LS_FIT_POINT definition) at the listed interior points
+ * (linear indices (i1 n + i2) n + i3) of the plan's medium become training
+ * samples.  LS_EINVAL for a boundary point.  Synchronises. */
+ls_status ls_mlp_add_samples(ls_mlp* mlp, ls_plan* plan, const int* points_host, int npts, void* hip_stream);
+long ls_mlp_num_samples(const ls_mlp* mlp);
+/* Copies of the samples: x_host [N][256] float32 (the BF16 features, zero
+ * padded), t_host [N][468] float32 targets.  Either may be NULL. */
+ls_status ls_mlp_get_samples(const ls_mlp* mlp, float* x_host, float* t_host);
+/* `steps` Adam steps on minibatches of `batch` samples (a seeded permutation
+ * per epoch); loss_out (may be NULL) receives the loss of every step. */
+ls_status ls_mlp_train(ls_mlp* mlp, int steps, int batch, double lr, unsigned seed, double* loss_out,
+                       void* hip_stream);
+/* Checkpoint: a JSON header line, then float32 parameters, Adam m and v. */
+ls_status ls_mlp_save(const ls_mlp* mlp, const char* path);
+ls_status ls_mlp_load(const char* path, ls_mlp** out);
+void ls_mlp_destroy(ls_mlp* mlp);
+
+/* Learned fit: every interior point gets the network's stencil when its
+ * locality tr(Q^H Gram_i Q) (Q an orthonormal basis of it, Gram_i the
+ * medium-weighted Gram of LS_FIT_POINT) is below the class stencil's by more
+ * than a relative 1e-9;
+ * otherwise the exact per-point fit.  Boundary points keep the class fit.
+ * n_fallback_out (may be NULL): the number of points that fell back.  Then
+ * assembles the rows, like ls_stencil_fit.  Synchronises. */
+ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out, void* hip_stream);
+
 /* ---- the host sparse solver on its own (host memory, no GPU) -------------- */
 typedef struct ls_sparse ls_sparse;
 

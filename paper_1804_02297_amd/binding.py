@@ -47,6 +47,18 @@ SIGNATURES = [
     ("ls_factor", _I, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
+    ("ls_mlp_create", _I, [_VP, ctypes.POINTER(_VP)]),
+    ("ls_mlp_get_params", _I, [_VP, _VP]),
+    ("ls_mlp_forward_backward", _I, [_VP, _VP, _VP, _I, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    ("ls_mlp_adam_step", _I, [_VP, _D, _VP]),
+    ("ls_mlp_add_samples", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls_mlp_num_samples", ctypes.c_long, [_VP]),
+    ("ls_mlp_get_samples", _I, [_VP, _VP, _VP]),
+    ("ls_mlp_train", _I, [_VP, _I, _I, _D, ctypes.c_uint, _VP, _VP]),
+    ("ls_mlp_save", _I, [_VP, ctypes.c_char_p]),
+    ("ls_mlp_load", _I, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
+    ("ls_mlp_destroy", None, [_VP]),
+    ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
     ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
     ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
@@ -95,6 +107,107 @@ class SparseHost:
     def close(self):
         if getattr(self, "_h", None):
             _lib.ls_sparse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MLP_NPARAM = 250324
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Mlp:
+    """The stencil-prediction network on the GPU (see include/ls.h)."""
+
+    def __init__(self, params=None, path: str | None = None):
+        import numpy as np
+        lib = load()
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(lib.ls_mlp_load(path.encode(), ctypes.byref(h)), "ls_mlp_load")
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != MLP_NPARAM:
+                raise ValueError(f"need {MLP_NPARAM} parameters")
+            _check(lib.ls_mlp_create(_fp(p), ctypes.byref(h)), "ls_mlp_create")
+        self._h = h
+
+    @staticmethod
+    def flat(params) -> "np.ndarray":
+        """Flat float32 layout from a dict W1, b1, W2, b2, W3, b3 (arrays shaped (in, out))."""
+        import numpy as np
+        return np.concatenate([np.asarray(params[k], dtype=np.float64).reshape(-1)
+                               for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
+
+    @staticmethod
+    def unflat(v) -> dict:
+        import numpy as np
+        v = np.asarray(v, dtype=np.float64)
+        out, o = {}, 0
+        for k, shp in (("W1", (250, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+                       ("W3", (256, 468)), ("b3", (468,))):
+            cnt = int(np.prod(shp))
+            out[k] = v[o:o + cnt].reshape(shp)
+            o += cnt
+        return out
+
+    def params(self):
+        import numpy as np
+        p = np.zeros(MLP_NPARAM, np.float32)
+        _check(_lib.ls_mlp_get_params(self._h, _fp(p)), "ls_mlp_get_params")
+        return p
+
+    def forward_backward(self, x, t):
+        """(y (B, 468), flat grad, loss) for host x (B, 250), t (B, 468)."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = np.ascontiguousarray(t, dtype=np.float32)
+        B = x.shape[0]
+        y = np.zeros((B, 468), np.float32)
+        g = np.zeros(MLP_NPARAM, np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.ls_mlp_forward_backward(self._h, _fp(x), _fp(t), B, _fp(y), _fp(g), ctypes.byref(loss),
+                                            _stream()), "ls_mlp_forward_backward")
+        return y, g, loss.value
+
+    def adam_step(self, lr: float):
+        _check(_lib.ls_mlp_adam_step(self._h, float(lr), _stream()), "ls_mlp_adam_step")
+
+    def add_samples(self, plan: "Plan", points):
+        import numpy as np
+        pts = np.ascontiguousarray(points, dtype=np.int32)
+        _check(_lib.ls_mlp_add_samples(self._h, plan._h, _fp(pts), len(pts), _stream()), "ls_mlp_add_samples")
+
+    def num_samples(self) -> int:
+        return int(_lib.ls_mlp_num_samples(self._h))
+
+    def samples(self):
+        import numpy as np
+        N = self.num_samples()
+        x = np.zeros((N, 256), np.float32)
+        t = np.zeros((N, 468), np.float32)
+        _check(_lib.ls_mlp_get_samples(self._h, _fp(x), _fp(t)), "ls_mlp_get_samples")
+        return x, t
+
+    def train(self, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+        import numpy as np
+        loss = np.zeros(steps, np.float64)
+        _check(_lib.ls_mlp_train(self._h, steps, batch, float(lr), seed, _fp(loss), _stream()), "ls_mlp_train")
+        return loss
+
+    def save(self, path: str):
+        _check(_lib.ls_mlp_save(self._h, path.encode()), "ls_mlp_save")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ls_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -197,8 +310,14 @@ class Plan:
         return list(ms)
 
     def stencil_fit(self, mode: int = 0):
-        """Class stencils, beta and the rows S on the GPU (Section 3.1, 3.2)."""
+        """Class stencils, beta and the rows S on the GPU (Section 3.1, 3.2); mode 1: per point."""
         _check(_lib.ls_stencil_fit(self._h, mode, _stream()), "ls_stencil_fit")
+
+    def stencil_fit_learned(self, mlp: Mlp) -> int:
+        """Learned fit with exact fallback; returns the number of fallback points."""
+        nf = ctypes.c_int()
+        _check(_lib.ls_stencil_fit_learned(self._h, mlp._h, ctypes.byref(nf), _stream()), "ls_stencil_fit_learned")
+        return nf.value
 
     def class_stencils(self, gram: bool = False):
         """(alpha, beta, eig[, gram]): alpha, beta (27, 81, 3) complex128; eig (27, 3);

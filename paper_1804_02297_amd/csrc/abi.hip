@@ -2,6 +2,8 @@
 // the arithmetic lives in the kernels of the other translation units.
 #include <chrono>
 #include <complex>
+#include <cstdio>
+#include <cstring>
 #include <new>
 
 #include "plan.h"
@@ -215,6 +217,175 @@ ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs
   const double tt = now_s() - t0;
   for (int b = 0; b < nrhs; ++b) info[b].t_gpu = tt / nrhs - info[b].t_host;
   return st;
+}
+
+// ---- learned stencils -------------------------------------------------------------
+
+ls_status ls_mlp_create(const float* params_host, ls_mlp** out) {
+  if (!params_host || !out) return LS_EINVAL;
+  *out = nullptr;
+  ls_mlp* p = new (std::nothrow) ls_mlp();
+  if (!p) return LS_ENOMEM;
+  ls_status st = mlp_init(p->st, params_host, nullptr);
+  if (st == LS_OK && hipStreamSynchronize(nullptr) != hipSuccess) st = LS_EHIP;
+  if (st != LS_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return LS_OK;
+}
+
+ls_status ls_mlp_get_params(const ls_mlp* mlp, float* params_host) {
+  if (!mlp || !params_host) return LS_EINVAL;
+  LS_HIP(hipMemcpy(params_host, mlp->st.w.p, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost));
+  return LS_OK;
+}
+
+ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float* t_host, int B, float* y_host,
+                                  float* grad_host, double* loss_out, void* hip_stream) {
+  if (!mlp || !x_host || !t_host || B < 1) return LS_EINVAL;
+  hipStream_t s = as_stream(hip_stream);
+  std::vector<float> xpad((size_t)B * MLP_IP, 0.f);
+  for (int b = 0; b < B; ++b)
+    for (int f = 0; f < MLP_I; ++f) xpad[(size_t)b * MLP_IP + f] = x_host[(size_t)b * MLP_I + f];
+  // host rounding of the inputs to bf16 (nearest, ties to even), as the features kernel does
+  std::vector<unsigned short> xb(xpad.size());
+  for (size_t i = 0; i < xpad.size(); ++i) {
+    unsigned u;
+    std::memcpy(&u, &xpad[i], 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    xb[i] = (unsigned short)(u >> 16);
+  }
+  DevBuf dx, dt;
+  LS_TRY(dx.alloc(xb.size() * 2));
+  LS_TRY(dt.alloc((size_t)B * MLP_O * 4));
+  LS_HIP(hipMemcpyAsync(dx.p, xb.data(), xb.size() * 2, hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(dt.p, t_host, (size_t)B * MLP_O * 4, hipMemcpyHostToDevice, s));
+  LS_TRY(mlp_forward(mlp->st, dx.as<unsigned short>(), B, s));
+  double loss = 0.0;
+  LS_TRY(mlp_backward(mlp->st, dx.as<unsigned short>(), dt.as<float>(), B, &loss, s));
+  if (y_host) {
+    std::vector<float> y((size_t)B * MLP_OP);
+    LS_HIP(hipMemcpyAsync(y.data(), mlp->st.y.p, y.size() * 4, hipMemcpyDeviceToHost, s));
+    LS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b)
+      std::memcpy(y_host + (size_t)b * MLP_O, y.data() + (size_t)b * MLP_OP, MLP_O * 4);
+  }
+  if (grad_host) LS_HIP(hipMemcpyAsync(grad_host, mlp->st.grad.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost, s));
+  LS_HIP(hipStreamSynchronize(s));
+  if (loss_out) *loss_out = loss;
+  return LS_OK;
+}
+
+ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream) {
+  if (!mlp) return LS_EINVAL;
+  LS_TRY(mlp_adam(mlp->st, lr, as_stream(hip_stream)));
+  LS_HIP(hipStreamSynchronize(as_stream(hip_stream)));
+  return LS_OK;
+}
+
+ls_status ls_mlp_add_samples(ls_mlp* mlp, ls_plan* plan, const int* points_host, int npts, void* hip_stream) {
+  if (!mlp || !plan || !points_host || npts < 1 || plan->ap.n < 4) return LS_EINVAL;
+  return mlp_add_samples(mlp->st, plan->sd, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0,
+                         points_host, npts, as_stream(hip_stream));
+}
+
+long ls_mlp_num_samples(const ls_mlp* mlp) { return mlp ? mlp->st.nsamples : 0; }
+
+ls_status ls_mlp_get_samples(const ls_mlp* mlp, float* x_host, float* t_host) {
+  if (!mlp) return LS_EINVAL;
+  const long N = mlp->st.nsamples;
+  if (N == 0) return LS_OK;
+  if (x_host) {
+    std::vector<unsigned short> xb((size_t)N * MLP_IP);
+    LS_HIP(hipMemcpy(xb.data(), mlp->st.xs.p, xb.size() * 2, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < xb.size(); ++i) {
+      const unsigned u = ((unsigned)xb[i]) << 16;
+      std::memcpy(&x_host[i], &u, 4);
+    }
+  }
+  if (t_host) LS_HIP(hipMemcpy(t_host, mlp->st.ts.p, (size_t)N * MLP_O * 4, hipMemcpyDeviceToHost));
+  return LS_OK;
+}
+
+ls_status ls_mlp_train(ls_mlp* mlp, int steps, int batch, double lr, unsigned seed, double* loss_out,
+                       void* hip_stream) {
+  if (!mlp) return LS_EINVAL;
+  return mlp_train(mlp->st, steps, batch, lr, seed, loss_out, as_stream(hip_stream));
+}
+
+ls_status ls_mlp_save(const ls_mlp* mlp, const char* path) {
+  if (!mlp || !path) return LS_EINVAL;
+  std::vector<float> buf(3 * (size_t)MLP_NPARAM);
+  LS_HIP(hipMemcpy(buf.data(), mlp->st.w.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+  LS_HIP(hipMemcpy(buf.data() + MLP_NPARAM, mlp->st.m.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+  LS_HIP(hipMemcpy(buf.data() + 2 * MLP_NPARAM, mlp->st.v.p, MLP_NPARAM * 4, hipMemcpyDeviceToHost));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return LS_EIO;
+  std::fprintf(f,
+               "{\"format\": \"ls_mlp\", \"version\": 1, \"nparam\": %ld, \"adam_t\": %d, \"layout\": "
+               "\"W1[250][256] b1[256] W2[256][256] b2[256] W3[256][468] b3[468]; then Adam m, v\"}\n",
+               (long)MLP_NPARAM, mlp->st.t);
+  const size_t wr = std::fwrite(buf.data(), 4, buf.size(), f);
+  std::fclose(f);
+  return wr == buf.size() ? LS_OK : LS_EIO;
+}
+
+ls_status ls_mlp_load(const char* path, ls_mlp** out) {
+  if (!path || !out) return LS_EINVAL;
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return LS_EIO;
+  char line[512];
+  if (!std::fgets(line, sizeof(line), f)) {
+    std::fclose(f);
+    return LS_EIO;
+  }
+  long np = 0;
+  int t = 0;
+  const char* pn = std::strstr(line, "\"nparam\":");
+  const char* pt = std::strstr(line, "\"adam_t\":");
+  if (!std::strstr(line, "\"ls_mlp\"") || !pn || !pt || std::sscanf(pn + 9, "%ld", &np) != 1 ||
+      std::sscanf(pt + 9, "%d", &t) != 1 || np != MLP_NPARAM) {
+    std::fclose(f);
+    return LS_EIO;
+  }
+  std::vector<float> buf(3 * (size_t)MLP_NPARAM);
+  const size_t rd = std::fread(buf.data(), 4, buf.size(), f);
+  std::fclose(f);
+  if (rd != buf.size()) return LS_EIO;
+  ls_mlp* p = nullptr;
+  LS_TRY(ls_mlp_create(buf.data(), &p));
+  if (hipMemcpy(p->st.m.p, buf.data() + MLP_NPARAM, MLP_NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->st.v.p, buf.data() + 2 * MLP_NPARAM, MLP_NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    delete p;
+    return LS_EHIP;
+  }
+  p->st.t = t;
+  *out = p;
+  return LS_OK;
+}
+
+void ls_mlp_destroy(ls_mlp* mlp) {
+  if (!mlp) return;
+  (void)hipDeviceSynchronize();
+  delete mlp;
+}
+
+ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out, void* hip_stream) {
+  if (!plan || !mlp || plan->ap.n < 4) return LS_EINVAL;
+  hipStream_t s = as_stream(hip_stream);
+  host_free(plan->hs);
+  plan->hs = nullptr;
+  plan->sd.have_point = false;
+  plan->sd.have_rows = false;
+  LS_TRY(learned_fit(plan->sd, mlp->st, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0,
+                     n_fallback_out, s));
+  LS_TRY(assemble_rows(plan->sd, plan->ap.n, plan->ap.m64.as<C<double>>(), s));
+  LS_HIP(hipStreamSynchronize(s));
+  plan->sd.have_rows = true;
+  return LS_OK;
 }
 
 ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_sparse** out) {

@@ -531,6 +531,291 @@ void bwd_rec(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb)
 #pragma omp taskwait
 }
 
+// ---- many right-hand sides: block vectors [dof][R], R a multiple of 4 ----------
+// The solves above read every factor entry once per right-hand side.  With the
+// right-hand sides interleaved (entry (k, r) at k R + r), a factor entry is
+// broadcast against a short vector of right-hand sides, so each factor row is
+// streamed once per 8 right-hand sides and the arithmetic vectorises over r.
+
+// Y[a][r] -= sum_k A[a][k] X[k][r] for MR rows a, RB right-hand sides r.
+template <int MR, int RB>
+__attribute__((always_inline)) inline void mk_sub(const double* __restrict__ Ar, const double* __restrict__ Ai,
+                                                  long lda, long K, const double* __restrict__ Xr,
+                                                  const double* __restrict__ Xi, long R,
+                                                  double* __restrict__ Yr, double* __restrict__ Yi) {
+  double cr[MR][RB], ci[MR][RB];
+  for (int a = 0; a < MR; ++a)
+    for (int r = 0; r < RB; ++r) cr[a][r] = ci[a][r] = 0.0;
+  for (long k = 0; k < K; ++k) {
+    const double* xr = Xr + k * R;
+    const double* xi = Xi + k * R;
+    for (int a = 0; a < MR; ++a) {
+      const double ar = Ar[a * lda + k], ai = Ai[a * lda + k];
+#pragma omp simd
+      for (int r = 0; r < RB; ++r) {
+        cr[a][r] += ar * xr[r] - ai * xi[r];
+        ci[a][r] += ar * xi[r] + ai * xr[r];
+      }
+    }
+  }
+  for (int a = 0; a < MR; ++a)
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      Yr[a * R + r] -= cr[a][r];
+      Yi[a * R + r] -= ci[a][r];
+    }
+}
+
+// rows [i0, i1) of Y -= A X; A row-major (lda), K columns; X, Y block vectors
+#if defined(__x86_64__)
+__attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+void gemm_sub_rows(const double* Ar, const double* Ai, long lda, long i0, long i1, long K, const double* Xr,
+                   const double* Xi, long R, double* Yr, double* Yi) {
+  long i = i0;
+  for (; i + 4 <= i1; i += 4)
+    for (long r0 = 0; r0 < R;) {
+      if (R - r0 >= 16) {
+        mk_sub<4, 16>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
+        r0 += 16;
+      } else if (R - r0 >= 8) {
+        mk_sub<4, 8>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
+        r0 += 8;
+      } else {
+        mk_sub<4, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
+        r0 += 4;
+      }
+    }
+  for (; i < i1; ++i)
+    for (long r0 = 0; r0 < R; r0 += 4)
+      mk_sub<1, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
+}
+
+// Y (m rows) -= A X, split into row tasks when large
+void gemm_sub(const double* Ar, const double* Ai, long lda, long m, long K, const double* Xr, const double* Xi,
+              long R, double* Yr, double* Yi) {
+  if (m <= 0 || K <= 0) return;
+  if ((double)m * (double)K * (double)R > 4.0 * kParWork) {
+    constexpr long RT = 32;
+#pragma omp taskloop grainsize(1)
+    for (long i0 = 0; i0 < m; i0 += RT) gemm_sub_rows(Ar, Ai, lda, i0, std::min(m, i0 + RT), K, Xr, Xi, R, Yr, Yi);
+  } else {
+    gemm_sub_rows(Ar, Ai, lda, 0, m, K, Xr, Xi, R, Yr, Yi);
+  }
+}
+
+// W[i][r] -= L[i][k] W[k][r] for k in [b0, i), i in [b0, b1)  (within a diagonal block)
+#if defined(__x86_64__)
+__attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+void lower_block_multi(const double* __restrict__ Lr, const double* __restrict__ Li, long np, long b0, long b1,
+                       double* __restrict__ Wr, double* __restrict__ Wi, long R) {
+  for (long i = b0; i < b1; ++i) {
+    double* yr = Wr + i * R;
+    double* yi = Wi + i * R;
+    for (long k = b0; k < i; ++k) {
+      const double ar = Lr[i * np + k], ai = Li[i * np + k];
+      const double* xr = Wr + k * R;
+      const double* xi = Wi + k * R;
+#pragma omp simd
+      for (long r = 0; r < R; ++r) {
+        yr[r] -= ar * xr[r] - ai * xi[r];
+        yi[r] -= ar * xi[r] + ai * xr[r];
+      }
+    }
+  }
+}
+
+// W[i][r] = (W[i][r] - sum_{k in (i, b1)} U[i][k] W[k][r]) / U[i][i], i from b1-1 down to b0
+#if defined(__x86_64__)
+__attribute__((target_clones("avx512f", "avx2", "default")))
+#endif
+void upper_block_multi(const double* __restrict__ Ur, const double* __restrict__ Ui, long np, long b0, long b1,
+                       double* __restrict__ Wr, double* __restrict__ Wi, long R) {
+  for (long i = b1 - 1; i >= b0; --i) {
+    double* yr = Wr + i * R;
+    double* yi = Wi + i * R;
+    for (long k = i + 1; k < b1; ++k) {
+      const double ar = Ur[i * np + k], ai = Ui[i * np + k];
+      const double* xr = Wr + k * R;
+      const double* xi = Wi + k * R;
+#pragma omp simd
+      for (long r = 0; r < R; ++r) {
+        yr[r] -= ar * xr[r] - ai * xi[r];
+        yi[r] -= ar * xi[r] + ai * xr[r];
+      }
+    }
+    const double ur = Ur[i * np + i], ui = Ui[i * np + i];
+    const double den = ur * ur + ui * ui;
+    const double qr = ur / den, qi = -ui / den;      // 1 / u
+#pragma omp simd
+    for (long r = 0; r < R; ++r) {
+      const double vr = yr[r], vi = yi[r];
+      yr[r] = vr * qr - vi * qi;
+      yi[r] = vr * qi + vi * qr;
+    }
+  }
+}
+
+void lower_unit_solve_multi(const double* Lr, const double* Li, long np, double* Wr, double* Wi, long R) {
+  constexpr long BS = 128;
+  for (long b0 = 0; b0 < np; b0 += BS) {
+    const long b1 = std::min(np, b0 + BS);
+    if (b0 > 0) gemm_sub(Lr + b0 * np, Li + b0 * np, np, b1 - b0, b0, Wr, Wi, R, Wr + b0 * R, Wi + b0 * R);
+    lower_block_multi(Lr, Li, np, b0, b1, Wr, Wi, R);
+  }
+}
+
+void upper_solve_multi(const double* Ur, const double* Ui, long np, double* Wr, double* Wi, long R) {
+  constexpr long BS = 128;
+  for (long b1 = np; b1 > 0; b1 -= BS) {
+    const long b0 = std::max(0L, b1 - BS);
+    if (b1 < np)
+      gemm_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, Wr + b1 * R, Wi + b1 * R, R,
+               Wr + b0 * R, Wi + b0 * R);
+    upper_block_multi(Ur, Ui, np, b0, b1, Wr, Wi, R);
+  }
+}
+
+// B, Z, X: block vectors over all 3 n^3 unknowns, [3 p + c][R]
+void fwd_node_multi(HostSolver& hs, int id, long R, const double* Br, const double* Bi, double* Zr, double* Zi,
+                    SolveWork& W) {
+  Node& nd = hs.nodes[id];
+  const long np = nd.np, nb = nd.nb, nf = np + nb;
+  std::vector<double> wr((size_t)nf * R, 0.0), wi((size_t)nf * R, 0.0);
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      std::memcpy(&wr[(3 * a + q) * R], Br + g * R, R * sizeof(double));
+      std::memcpy(&wi[(3 * a + q) * R], Bi + g * R, R * sizeof(double));
+    }
+  for (int c : nd.child) {
+    if (c < 0) continue;
+    Node& ch = hs.nodes[c];
+    for (size_t a = 0; a < ch.bnd.size(); ++a) {
+      const long fp = front_pos(nd, ch.bnd[a]);
+      for (int q = 0; q < 3; ++q) {
+        const double* ur = &W.ur[c][(3 * a + q) * R];
+        const double* ui = &W.ui[c][(3 * a + q) * R];
+        double* xr = &wr[(3 * fp + q) * R];
+        double* xi = &wi[(3 * fp + q) * R];
+        for (long r = 0; r < R; ++r) {
+          xr[r] += ur[r];
+          xi[r] += ui[r];
+        }
+      }
+    }
+    std::vector<double>().swap(W.ur[c]);
+    std::vector<double>().swap(W.ui[c]);
+  }
+  for (long k = 0; k < np; ++k) {
+    const long p = nd.ipiv[k];
+    if (p != k)
+      for (long r = 0; r < R; ++r) {
+        std::swap(wr[k * R + r], wr[p * R + r]);
+        std::swap(wi[k * R + r], wi[p * R + r]);
+      }
+  }
+  lower_unit_solve_multi(nd.l11r.data(), nd.l11i.data(), np, wr.data(), wi.data(), R);
+  if (nb) gemm_sub(nd.l21r.data(), nd.l21i.data(), np, nb, np, wr.data(), wi.data(), R, wr.data() + np * R,
+                   wi.data() + np * R);
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      std::memcpy(Zr + g * R, &wr[(3 * a + q) * R], R * sizeof(double));
+      std::memcpy(Zi + g * R, &wi[(3 * a + q) * R], R * sizeof(double));
+    }
+  W.ur[id].assign(wr.begin() + np * R, wr.end());
+  W.ui[id].assign(wi.begin() + np * R, wi.end());
+}
+
+void fwd_rec_multi(HostSolver& hs, int id, long R, const double* Br, const double* Bi, double* Zr, double* Zi,
+                   SolveWork& W) {
+  for (int c : hs.nodes[id].child) {
+    if (c < 0) continue;
+#pragma omp task firstprivate(c) shared(hs, W) if (hs.nodes[c].piv.size() > 64)
+    fwd_rec_multi(hs, c, R, Br, Bi, Zr, Zi, W);
+  }
+#pragma omp taskwait
+  fwd_node_multi(hs, id, R, Br, Bi, Zr, Zi, W);
+}
+
+void bwd_node_multi(HostSolver& hs, int id, long R, double* Xr, double* Xi) {
+  Node& nd = hs.nodes[id];
+  const long np = nd.np, nb = nd.nb;
+  std::vector<double> xr((size_t)np * R), xi((size_t)np * R), yr((size_t)nb * R), yi((size_t)nb * R);
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      std::memcpy(&xr[(3 * a + q) * R], Xr + g * R, R * sizeof(double));
+      std::memcpy(&xi[(3 * a + q) * R], Xi + g * R, R * sizeof(double));
+    }
+  for (size_t a = 0; a < nd.bnd.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.bnd[a] + q;
+      std::memcpy(&yr[(3 * a + q) * R], Xr + g * R, R * sizeof(double));
+      std::memcpy(&yi[(3 * a + q) * R], Xi + g * R, R * sizeof(double));
+    }
+  if (nb) gemm_sub(nd.u12r.data(), nd.u12i.data(), nb, np, nb, yr.data(), yi.data(), R, xr.data(), xi.data());
+  upper_solve_multi(nd.l11r.data(), nd.l11i.data(), np, xr.data(), xi.data(), R);
+  for (size_t a = 0; a < nd.piv.size(); ++a)
+    for (int q = 0; q < 3; ++q) {
+      const long g = 3L * nd.piv[a] + q;
+      std::memcpy(Xr + g * R, &xr[(3 * a + q) * R], R * sizeof(double));
+      std::memcpy(Xi + g * R, &xi[(3 * a + q) * R], R * sizeof(double));
+    }
+}
+
+void bwd_rec_multi(HostSolver& hs, int id, long R, double* Xr, double* Xi) {
+  bwd_node_multi(hs, id, R, Xr, Xi);
+  for (int c : hs.nodes[id].child) {
+    if (c < 0) continue;
+#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 64)
+    bwd_rec_multi(hs, c, R, Xr, Xi);
+  }
+#pragma omp taskwait
+}
+
+// Right-hand sides per block solve: a multiple of 4 (the micro-kernel width);
+// larger batches are solved in blocks of this many.
+constexpr int kMultiBlock = 32;
+constexpr int kMultiMin = 3;         // from this many right-hand sides on, the block solve
+
+ls_status host_solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
+  const long n3 = (long)hs->n * hs->n * hs->n;
+  const long ldb = 3 * n3;
+  for (int r0 = 0; r0 < nrhs; r0 += kMultiBlock) {
+    const int nr = std::min(kMultiBlock, nrhs - r0);
+    const long R = (nr + 3) / 4 * 4;
+    std::vector<double> Br((size_t)ldb * R, 0.0), Bi((size_t)ldb * R, 0.0);
+    std::vector<double> Zr((size_t)ldb * R, 0.0), Zi((size_t)ldb * R, 0.0);
+    std::complex<double>* bb = b + (size_t)r0 * ldb;
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < n3; ++p)
+      for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < nr; ++r) {
+          const std::complex<double> v = bb[(size_t)r * ldb + c * n3 + p];
+          Br[(3 * p + c) * R + r] = v.real();
+          Bi[(3 * p + c) * R + r] = v.imag();
+        }
+    SolveWork W;
+    W.ur.resize(hs->nodes.size());
+    W.ui.resize(hs->nodes.size());
+#pragma omp parallel
+#pragma omp single
+    fwd_rec_multi(*hs, hs->root, R, Br.data(), Bi.data(), Zr.data(), Zi.data(), W);
+#pragma omp parallel
+#pragma omp single
+    bwd_rec_multi(*hs, hs->root, R, Zr.data(), Zi.data());
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < n3; ++p)
+      for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < nr; ++r)
+          bb[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[(3 * p + c) * R + r], Zi[(3 * p + c) * R + r]);
+  }
+  return LS_OK;
+}
+
 }  // namespace
 
 ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, HostSolver** out) {
@@ -555,6 +840,7 @@ ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, H
 
 ls_status host_solve(HostSolver* hs, std::complex<double>* b, int nrhs) {
   if (!hs || !b || nrhs < 1) return LS_EINVAL;
+  if (nrhs >= kMultiMin) return host_solve_multi(hs, b, nrhs);
   const long n3 = (long)hs->n * hs->n * hs->n;
   const long ldb = 3 * n3;
   std::vector<double> Br((size_t)nrhs * ldb), Bi((size_t)nrhs * ldb);

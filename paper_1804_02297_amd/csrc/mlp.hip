@@ -1,0 +1,346 @@
+// Stencil-prediction network on gfx950 (a project extension of Section 3).
+//
+// The per-point fit (pointfit.hip) makes an interior point's stencil depend on
+// the medium in its 5^3 patch.  This network predicts that dependence:
+//
+//   x (250)  = Re, Im of m on the 5^3 patch / 0.3 (last dimension fastest, 0 off the grid)
+//   h1 = GELU(x W1 + b1) (256), h2 = GELU(h1 W2 + b2) (256), y = h2 W3 + b3 (468)
+//   y encodes the 26 off-centre 3x3 blocks of alpha~_i - alpha~_class, where
+//   alpha~ = alpha (alpha_centre)^-1 is the gauge with the identity as centre block
+//   (S^-1 Q is invariant under alpha -> alpha X, so the gauge costs nothing).
+//
+// Weights are FP32 masters with BF16 copies; every product runs on
+// v_mfma_f32_16x16x16_bf16 with BF16 operands and FP32 accumulation.  GELU is
+// the exact x Phi(x) (device erf).  Loss: mean squared error; optimiser: Adam.
+//
+// The learned fit predicts alpha for every interior point, orthonormalises it,
+// and accepts it when its locality tr(Q^H Gram_i Q) is no larger than the
+// class stencil's tr(alpha_c^H Gram_i alpha_c) on the same medium-weighted
+// Gram; other points fall back to the exact per-point fit.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "mlp.h"
+
+namespace ls {
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);      // round to nearest, ties to even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+enum Epi { EPI_STORE = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_DACT = 3 };
+
+struct EpiArgs {
+  const float* bias;       // EPI_HIDDEN, EPI_OUT
+  float* zf;               // EPI_HIDDEN: pre-activation out; EPI_DACT: dZ (f32) out
+  const float* zin;        // EPI_DACT: the forward pre-activation
+  unsigned short* hb;      // EPI_HIDDEN: GELU(z) as bf16; EPI_DACT: dZ as bf16
+  float* cf;               // EPI_STORE / EPI_OUT
+  int ld;                  // leading dimension of every output (row-major, M x ld)
+  int nvalid;              // columns >= nvalid are written as zero (padding)
+};
+
+// C (M x N) = A (M x K) B (K x N), BF16 operands, FP32 accumulation.
+// A(m, k) = TA ? A[k lda + m] : A[m lda + k];  B(k, n) = TB ? B[n ldb + k] : B[k ldb + n].
+// Workgroup: 4 waves, 64 x 64 output tile, K in steps of 32 through LDS.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(const unsigned short* __restrict__ A, int lda,
+                                                        const unsigned short* __restrict__ B, int ldb, int M, int N,
+                                                        int K, EpiArgs ep) {
+  __shared__ unsigned short As[64][32 + 4];   // [m][k]
+  __shared__ unsigned short Bs[64][32 + 4];   // [n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int r = e / 32, c = e % 32;        // r: m or n within the tile, c: k
+      const int m = m0 + r, n = n0 + r, k = k0 + c;
+      unsigned short av = 0, bv = 0;
+      if (m < M && k < K) av = TA ? A[(long)k * lda + m] : A[(long)m * lda + k];
+      if (n < N && k < K) bv = TB ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
+      As[r][c] = av;
+      Bs[r][c] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 32; ks += 16) {
+      v4s af[2], bfr[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int kk = ks + 4 * (lane >> 4);
+        const int ra = wm + 16 * t + (lane & 15);
+        const int rb = wn + 16 * t + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          af[t][q] = (short)As[ra][kk + q];
+          bfr[t][q] = (short)Bs[rb][kk + q];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D[4 (l / 16) + r][l % 16] in register r of lane l
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + 16 * b + (lane & 15);
+        if (m >= M || n >= N) continue;
+        const long o = (long)m * ep.ld + n;
+        const bool pad = n >= ep.nvalid;
+        float v = acc[a][b][r];
+        if (EPI == EPI_STORE) {
+          ep.cf[o] = pad ? 0.f : v;
+        } else if (EPI == EPI_OUT) {
+          ep.cf[o] = pad ? 0.f : v + ep.bias[n];
+        } else if (EPI == EPI_HIDDEN) {
+          const float z = pad ? 0.f : v + ep.bias[n];
+          ep.zf[o] = z;
+          ep.hb[o] = pad ? 0 : f2bf(gelu(z));
+        } else {   // EPI_DACT
+          const float d = pad ? 0.f : v * gelu_grad(ep.zin[o]);
+          ep.zf[o] = d;
+          ep.hb[o] = f2bf(d);
+        }
+      }
+}
+
+template <bool TA, bool TB, int EPI>
+ls_status gemm(const unsigned short* A, int lda, const unsigned short* B, int ldb, int M, int N, int K,
+               const EpiArgs& ep, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ a, unsigned short* __restrict__ b, long cnt) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = f2bf(a[i]);
+}
+
+// copy an r x c FP32 block into a zero-padded R x Cp BF16 block (row-major)
+__global__ void pad_bf16_kernel(const float* __restrict__ a, int r, int c, unsigned short* __restrict__ b, int R,
+                                int Cp) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)R * Cp) return;
+  const int row = (int)(i / Cp), col = (int)(i % Cp);
+  b[i] = (row < r && col < c) ? f2bf(a[(long)row * c + col]) : (unsigned short)0;
+}
+
+// dY = 2 (Y - T) / (B * 468), padded columns zero; per-row squared error partials
+__global__ void loss_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T, int Bm, float inv,
+                                 unsigned short* __restrict__ dYb, float* __restrict__ sq) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)Bm * MLP_OP) return;
+  const int n = (int)(i % MLP_OP);
+  const long m = i / MLP_OP;
+  float d = 0.f;
+  if (n < MLP_O) {
+    d = Y[i] - T[m * MLP_O + n];
+    atomicAdd(&sq[m % 256], d * d);
+  }
+  dYb[i] = f2bf(2.0f * d * inv);
+}
+
+// db[n] = sum_m dZ[m][n]
+__global__ void bias_grad_kernel(const float* __restrict__ dZ, int Bm, int ld, int nvalid, float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nvalid) return;
+  float s = 0.f;
+  for (int m = 0; m < Bm; ++m) s += dZ[(long)m * ld + n];
+  db[n] = s;
+}
+
+// gather a row-major block of FP32 dW (rows x cols, ld) into the flat gradient
+__global__ void gather_grad_kernel(const float* __restrict__ src, int rows, int cols, int ld, float* __restrict__ dst) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)rows * cols) return;
+  dst[i] = src[(i / cols) * ld + i % cols];
+}
+
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, long cnt, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+inline unsigned nbk(long len, int t) { return (unsigned)((len + t - 1) / t); }
+
+}  // namespace
+
+// ---- host side ----------------------------------------------------------------
+
+ls_status mlp_init(MlpState& st, const float* params_host, hipStream_t s) {
+  LS_TRY(st.w.alloc(MLP_NPARAM * sizeof(float)));
+  LS_TRY(st.m.alloc(MLP_NPARAM * sizeof(float)));
+  LS_TRY(st.v.alloc(MLP_NPARAM * sizeof(float)));
+  LS_TRY(st.grad.alloc(MLP_NPARAM * sizeof(float)));
+  LS_TRY(st.w1b.alloc((size_t)MLP_IP * MLP_H * 2));
+  LS_TRY(st.w2b.alloc((size_t)MLP_H * MLP_H * 2));
+  LS_TRY(st.w3b.alloc((size_t)MLP_H * MLP_OP * 2));
+  LS_HIP(hipMemcpyAsync(st.w.p, params_host, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemsetAsync(st.m.p, 0, st.m.bytes, s));
+  LS_HIP(hipMemsetAsync(st.v.p, 0, st.v.bytes, s));
+  st.t = 0;
+  return mlp_refresh_bf16(st, s);
+}
+
+ls_status mlp_refresh_bf16(MlpState& st, hipStream_t s) {
+  const float* w = st.w.as<float>();
+  hipLaunchKernelGGL(pad_bf16_kernel, dim3(nbk((long)MLP_IP * MLP_H, 256)), dim3(256), 0, s, w + MLP_OFF_W1, MLP_I,
+                     MLP_H, st.w1b.as<unsigned short>(), MLP_IP, MLP_H);
+  hipLaunchKernelGGL(pad_bf16_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s, w + MLP_OFF_W2, MLP_H,
+                     MLP_H, st.w2b.as<unsigned short>(), MLP_H, MLP_H);
+  hipLaunchKernelGGL(pad_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s, w + MLP_OFF_W3, MLP_H,
+                     MLP_O, st.w3b.as<unsigned short>(), MLP_H, MLP_OP);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+ls_status mlp_workspace(MlpState& st, int Bm) {
+  if (st.ws_rows >= Bm) return LS_OK;
+  LS_TRY(st.z1.alloc((size_t)Bm * MLP_H * 4));
+  LS_TRY(st.z2.alloc((size_t)Bm * MLP_H * 4));
+  LS_TRY(st.h1b.alloc((size_t)Bm * MLP_H * 2));
+  LS_TRY(st.h2b.alloc((size_t)Bm * MLP_H * 2));
+  LS_TRY(st.y.alloc((size_t)Bm * MLP_OP * 4));
+  LS_TRY(st.dyb.alloc((size_t)Bm * MLP_OP * 2));
+  LS_TRY(st.dz2.alloc((size_t)Bm * MLP_H * 4));
+  LS_TRY(st.dz2b.alloc((size_t)Bm * MLP_H * 2));
+  LS_TRY(st.dz1.alloc((size_t)Bm * MLP_H * 4));
+  LS_TRY(st.dz1b.alloc((size_t)Bm * MLP_H * 2));
+  LS_TRY(st.dw.alloc((size_t)MLP_H * MLP_OP * 4));
+  LS_TRY(st.sq.alloc(256 * 4));
+  st.ws_rows = Bm;
+  return LS_OK;
+}
+
+// y (Bm x 480, FP32) for inputs xb (Bm x 256, BF16)
+ls_status mlp_forward(MlpState& st, const unsigned short* xb, int Bm, hipStream_t s) {
+  LS_TRY(mlp_workspace(st, Bm));
+  const float* w = st.w.as<float>();
+  EpiArgs e1{w + MLP_OFF_B1, st.z1.as<float>(), nullptr, st.h1b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
+  LS_TRY((gemm<false, false, EPI_HIDDEN>(xb, MLP_IP, st.w1b.as<unsigned short>(), MLP_H, Bm, MLP_H, MLP_IP, e1, s)));
+  EpiArgs e2{w + MLP_OFF_B2, st.z2.as<float>(), nullptr, st.h2b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
+  LS_TRY((gemm<false, false, EPI_HIDDEN>(st.h1b.as<unsigned short>(), MLP_H, st.w2b.as<unsigned short>(), MLP_H, Bm,
+                                         MLP_H, MLP_H, e2, s)));
+  EpiArgs e3{w + MLP_OFF_B3, nullptr, nullptr, nullptr, st.y.as<float>(), MLP_OP, MLP_O};
+  LS_TRY((gemm<false, false, EPI_OUT>(st.h2b.as<unsigned short>(), MLP_H, st.w3b.as<unsigned short>(), MLP_OP, Bm,
+                                      MLP_OP, MLP_H, e3, s)));
+  return LS_OK;
+}
+
+// gradients of the mean squared error into st.grad (flat, like the parameters)
+ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, int Bm, double* loss, hipStream_t s) {
+  const float* w = st.w.as<float>();
+  float* g = st.grad.as<float>();
+  LS_HIP(hipMemsetAsync(st.sq.p, 0, 256 * 4, s));
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(nbk((long)Bm * MLP_OP, 256)), dim3(256), 0, s, st.y.as<float>(), T, Bm,
+                     1.0f / ((float)Bm * MLP_O), st.dyb.as<unsigned short>(), st.sq.as<float>());
+  LS_HIP(hipGetLastError());
+  // layer 3: dW3 = h2^T dY (256 x 468), db3, dh2 = dY W3^T -> dZ2
+  EpiArgs es{nullptr, nullptr, nullptr, nullptr, st.dw.as<float>(), MLP_OP, MLP_O};
+  LS_TRY((gemm<true, false, EPI_STORE>(st.h2b.as<unsigned short>(), MLP_H, st.dyb.as<unsigned short>(), MLP_OP, MLP_H,
+                                       MLP_OP, Bm, es, s)));
+  hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_H * MLP_O, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_H,
+                     MLP_O, MLP_OP, g + MLP_OFF_W3);
+  // db3 from dY: reuse dz2 (f32) as scratch is not possible (bf16 dY); recompute from Y - T
+  EpiArgs ed2{nullptr, st.dz2.as<float>(), st.z2.as<float>(), st.dz2b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
+  LS_TRY((gemm<false, true, EPI_DACT>(st.dyb.as<unsigned short>(), MLP_OP, st.w3b.as<unsigned short>(), MLP_OP, Bm,
+                                      MLP_H, MLP_OP, ed2, s)));
+  // layer 2
+  es.cf = st.dw.as<float>();
+  es.ld = MLP_H;
+  es.nvalid = MLP_H;
+  LS_TRY((gemm<true, false, EPI_STORE>(st.h1b.as<unsigned short>(), MLP_H, st.dz2b.as<unsigned short>(), MLP_H, MLP_H,
+                                       MLP_H, Bm, es, s)));
+  hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_H,
+                     MLP_H, MLP_H, g + MLP_OFF_W2);
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(256), 0, s, st.dz2.as<float>(), Bm, MLP_H, MLP_H, g + MLP_OFF_B2);
+  EpiArgs ed1{nullptr, st.dz1.as<float>(), st.z1.as<float>(), st.dz1b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
+  LS_TRY((gemm<false, true, EPI_DACT>(st.dz2b.as<unsigned short>(), MLP_H, st.w2b.as<unsigned short>(), MLP_H, Bm,
+                                      MLP_H, MLP_H, ed1, s)));
+  // layer 1
+  es.cf = st.dw.as<float>();
+  LS_TRY((gemm<true, false, EPI_STORE>(xb, MLP_IP, st.dz1b.as<unsigned short>(), MLP_H, MLP_IP, MLP_H, Bm, es, s)));
+  hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_I * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_I,
+                     MLP_H, MLP_H, g + MLP_OFF_W1);
+  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(256), 0, s, st.dz1.as<float>(), Bm, MLP_H, MLP_H, g + MLP_OFF_B1);
+  LS_HIP(hipGetLastError());
+  // db3 = column sums of dY in FP32: dY = 2 (Y - T) / (B 468)
+  LS_TRY(mlp_bias3_grad(st, T, Bm, g + MLP_OFF_B3, s));
+  if (loss) {
+    float sq[256];
+    LS_HIP(hipMemcpyAsync(sq, st.sq.p, sizeof(sq), hipMemcpyDeviceToHost, s));
+    LS_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (int i = 0; i < 256; ++i) t += sq[i];
+    *loss = t / ((double)Bm * MLP_O);
+  }
+  return LS_OK;
+}
+
+namespace {
+__global__ void bias3_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T, int Bm, float inv,
+                                  float* __restrict__ db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= MLP_O) return;
+  float s = 0.f;
+  for (int m = 0; m < Bm; ++m) s += Y[(long)m * MLP_OP + n] - T[(long)m * MLP_O + n];
+  db[n] = 2.0f * s * inv;
+}
+}  // namespace
+
+ls_status mlp_bias3_grad(MlpState& st, const float* T, int Bm, float* db, hipStream_t s) {
+  hipLaunchKernelGGL(bias3_grad_kernel, dim3(nbk(MLP_O, 256)), dim3(256), 0, s, st.y.as<float>(), T, Bm,
+                     1.0f / ((float)Bm * MLP_O), db);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+}
+
+ls_status mlp_adam(MlpState& st, double lr, hipStream_t s) {
+  st.t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)st.t), c2 = 1.0f - powf(b2, (float)st.t);
+  hipLaunchKernelGGL(adam_kernel, dim3(nbk(MLP_NPARAM, 256)), dim3(256), 0, s, st.w.as<float>(), st.grad.as<float>(),
+                     st.m.as<float>(), st.v.as<float>(), (long)MLP_NPARAM, (float)lr, b1, b2, 1e-8f, c1, c2);
+  LS_HIP(hipGetLastError());
+  return mlp_refresh_bf16(st, s);
+}
+
+}  // namespace ls

@@ -4,6 +4,8 @@
 #include "common.h"
 #include "gmres.h"
 #include "host_solver.h"
+#include "learned.h"
+#include "mlp.h"
 #include "pointfit.h"
 #include "stencil.h"
 
@@ -26,4 +28,8 @@ struct ls_plan {
 struct ls_sparse {
   ls::HostSolver* hs = nullptr;
   ~ls_sparse() { ls::host_free(hs); }
+};
+
+struct ls_mlp {
+  ls::MlpState st;
 };

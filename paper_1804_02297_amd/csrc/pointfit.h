@@ -13,4 +13,18 @@ namespace ls {
 ls_status point_fit(StencilData& sd, int n, double k, const C<double>* m, double m0, int batch, int iters,
                     hipStream_t s);
 
+// The same fit in pieces, for point lists (training samples, learned-fit fallback).
+struct PointFitCtx {
+  int n = 0, batch = 0;
+  DevBuf Hr, Gcls, Bint, coef, Gb;
+};
+// allocates per-point stencils (initialised to the class stencils) and the shell data
+ls_status pointfit_prepare(PointFitCtx& ctx, StencilData& sd, int n, double k, int batch, hipStream_t s);
+// weighted Grams of cnt <= batch interior points (device list) into ctx.Gb
+ls_status pointfit_grams(PointFitCtx& ctx, const C<double>* m, double m0, const int* dpts, int cnt, hipStream_t s);
+// exact stencils of those points into sd.palpha
+ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s);
+// beta = B^H alpha of those points into sd.pbeta
+ls_status pointfit_beta(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, hipStream_t s);
+
 }  // namespace ls

@@ -462,4 +462,64 @@ ls_status point_fit(StencilData& sd, int n, double k, const C<double>* m, double
   return LS_OK;
 }
 
+// ---- pieces of the per-point fit for callers that work on point lists ----------
+
+ls_status pointfit_prepare(PointFitCtx& ctx, StencilData& sd, int n, double k, int batch, hipStream_t s) {
+  if (!sd.have_class || n < 4) return LS_ESTATE;
+  const double h = 1.0 / (n + 1);
+  const long n3 = (long)n * n * n;
+  ctx.n = n;
+  ctx.batch = batch;
+  LS_TRY(sd.palpha.alloc((size_t)n3 * 243 * sizeof(C<double>)));
+  LS_TRY(sd.pbeta.alloc((size_t)n3 * 243 * sizeof(C<double>)));
+  LS_TRY(sd.peval.alloc((size_t)n3 * 3 * sizeof(double)));
+  LS_HIP(hipMemsetAsync(sd.peval.p, 0, sd.peval.bytes, s));
+  hipLaunchKernelGGL(broadcast_class_kernel, dim3(nb(n3 * 243, 256)), dim3(256), 0, s, n, sd.alpha.as<C<double>>(),
+                     sd.beta.as<C<double>>(), sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
+  LS_HIP(hipGetLastError());
+  LS_TRY(ctx.Hr.alloc((size_t)KPAD * NCOL * sizeof(double)));
+  LS_HIP(hipMemsetAsync(ctx.Hr.p, 0, ctx.Hr.bytes, s));
+  hipLaunchKernelGGL(shell_h_kernel, dim3(KSH), dim3(256), 0, s, k, h, ctx.Hr.as<double>());
+  LS_HIP(hipGetLastError());
+  LS_TRY(ctx.Gcls.alloc((size_t)NCOL * sizeof(double)));
+  LS_HIP(hipMemsetAsync(ctx.Gcls.p, 0, ctx.Gcls.bytes, s));
+  hipLaunchKernelGGL(pack_lower_kernel, dim3(nb(NPK, 256)), dim3(256), 0, s,
+                     sd.gram.as<C<double>>() + 13L * R81 * R81, ctx.Gcls.as<double>());
+  LS_HIP(hipGetLastError());
+  LS_TRY(ctx.Bint.alloc((size_t)R81 * R81 * sizeof(C<double>)));
+  hipLaunchKernelGGL(interior_block_kernel, dim3(nb(R81 * R81, 256)), dim3(256), 0, s, k, h, ctx.Bint.as<C<double>>());
+  LS_HIP(hipGetLastError());
+  LS_TRY(ctx.coef.alloc((size_t)batch * KPAD * sizeof(double)));
+  LS_TRY(ctx.Gb.alloc((size_t)batch * NPKR * sizeof(double)));
+  return LS_OK;
+}
+
+// weighted Grams of cnt <= batch points (device list) into ctx.Gb (packed lower triangles)
+ls_status pointfit_grams(PointFitCtx& ctx, const C<double>* m, double m0, const int* dpts, int cnt, hipStream_t s) {
+  if (cnt > ctx.batch) return LS_EINVAL;
+  hipLaunchKernelGGL(shell_coef_kernel, dim3(nb((long)cnt * KPAD, 256)), dim3(256), 0, s, ctx.n, m, dpts, cnt,
+                     1.0 / m0, ctx.coef.as<double>());
+  LS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram_batch_kernel, dim3(NCOL / 256, (cnt + 15) / 16), dim3(256), 0, s, ctx.coef.as<double>(),
+                     ctx.Hr.as<double>(), ctx.Gcls.as<double>(), cnt, ctx.Gb.as<double>());
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+// exact per-point stencils for cnt points whose Grams are in ctx.Gb
+ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s) {
+  const C<double>* X0 = sd.ritz8.as<C<double>>() + 13L * R81 * EBW;
+  hipLaunchKernelGGL(heev_wave_kernel, dim3(cnt), dim3(64), 0, s, ctx.Gb.as<C<double>>(), cnt, X0, iters, dpts,
+                     sd.palpha.as<C<double>>(), sd.peval.as<double>());
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+ls_status pointfit_beta(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, hipStream_t s) {
+  hipLaunchKernelGGL(point_beta_kernel, dim3(nb((long)cnt * 243, 256)), dim3(256), 0, s, ctx.Bint.as<C<double>>(),
+                     dpts, cnt, sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
 }  // namespace ls

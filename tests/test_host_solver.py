@@ -54,6 +54,24 @@ def test_host_multifrontal_matches_spsolve(n, seed):
     assert info["bytes"] > 0 and info["flops"] > 0
 
 
+@pytest.mark.parametrize("nrhs", [3, 5, 9, 13, 34])
+def test_host_block_solve_matches_single(nrhs):
+    """The block (many right-hand side) solve equals one-at-a-time solves."""
+    n = 7
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 4)
+    al, be, _ = ost.fit_all_classes(n, k)
+    S, _ = osp.assemble(n, m, al, be)
+    sp = binding.SparseHost(n, csr_to_rows(S, n))
+    b = I.random_field(nrhs, n, 70 + nrhs)
+    x = sp.solve(b)
+    for r in sorted({0, nrhs // 2, nrhs - 1}):
+        one = sp.solve(b[r:r + 1])[0]
+        assert np.abs(x[r] - one).max() <= 1e-12 * np.abs(one).max(), r
+    res = np.stack([(S @ xx.reshape(-1) - bb.reshape(-1)) for xx, bb in zip(x, b)])
+    assert np.abs(res).max() <= 1e-10 * np.abs(b).max()
+
+
 def test_host_solver_random_matrix_same_pattern():
     """A random matrix on the 27-point pattern with a strong diagonal."""
     n = 6
