@@ -132,6 +132,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch):
 
     run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
     t_plain, x1, inf1, st1 = run(g[:1], "c128")
+    tune = plan.tune(nb, "mixed")                         # launch choice of the batched apply
     t_mixed, xb, infb, stb = run(g, "mixed")
     # residuals re-measured with the FP64 apply: r = g - A x
     r = torch.empty_like(g)
@@ -148,6 +149,9 @@ def solve_section(n: int, ndirs: int, binding, I, torch):
         "batched_max_rel_resid_fp64": float(f"{rel:.3e}"),
         "status": [st1, stb],
         "speedup_per_rhs": round(t_plain / (t_mixed / nb), 2),
+        "gpu_s_batched": round(max(i["t_gpu"] for i in infb), 4),
+        "host_s_batched": round(max(i["t_host"] for i in infb), 4),
+        "tuned_apply": {k: tune[k] for k in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
     }
 
 

@@ -89,6 +89,31 @@ ls_status ls_apply(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_p
 ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec,
                          void* hip_stream, double* pass_ms);
 
+/* Launch choices of the batched apply (block right-hand sides; the FFT of
+ * Section 2 applied to many incident fields at once).  Results never depend
+ * on them: every choice computes the same operations in the same order. */
+typedef struct {
+  int chunk;                  /* right-hand sides per launch set, 1..max_rhs            */
+  int kmul_w;                 /* pass-3 teams per workgroup (1, 2 or 4)                 */
+  double ms_per_rhs;          /* measured GPU ms per rhs of the chosen choice           */
+  double ms_default_per_rhs;  /* the same for the built-in default (0 on a cache hit)   */
+  int from_cache;             /* 1: read from desc.tune_cache, nothing was timed        */
+  int n_tried;                /* choices timed                                          */
+} ls_tune_info;
+
+/* Autotune the apply of prec for batches of nrhs: look the key (GPU, n, P,
+ * prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time every
+ * choice on the plan's operator (scratch fields of nrhs, allocated and freed
+ * here), keep the fastest and append it to the cache file (a JSON array, one
+ * object per line; rewritten through a temporary file).  The choice then holds
+ * for every later apply and solve of that precision.  A cache that cannot be
+ * written is not an error.  Synchronises hip_stream.  info may be NULL. */
+ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, ls_tune_info* info);
+
+/* Set the launch choice of prec by hand (chunk 0 / kmul_w 0 = default).
+ * LS_EINVAL for chunk > max_rhs or kmul_w not in {0, 1, 2, 4}. */
+ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w);
+
 /* Right-hand side of the scattered-field equation (Eq. (4)):
  * g = -K * (m E^i) = E^i - A E^i, complex128, computed with the FP64 apply.
  * Ei, g: device [nrhs][3][n][n][n] complex128. */
@@ -192,7 +217,11 @@ ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float*
 ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream);
 /* Exact per-point fits (LS_FIT_POINT definition) at the listed interior points
  * (linear indices (i1 n + i2) n + i3) of the plan's medium become training
- * samples.  LS_EINVAL for a boundary point.  Synchronises. */
+ * samples: input = the 5^3 patch of m, target = the gauge-fixed stencil
+ * alpha (alpha_centre)^-1 minus the interior class's, over a fixed scale.  A
+ * point whose centre block has Frobenius condition number above 1e6 (gauge
+ * undefined) is skipped; ls_mlp_num_samples tells how many were kept.
+ * LS_EINVAL for a boundary point.  Synchronises. */
 ls_status ls_mlp_add_samples(ls_mlp* mlp, ls_plan* plan, const int* points_host, int npts, void* hip_stream);
 long ls_mlp_num_samples(const ls_mlp* mlp);
 /* Copies of the samples: x_host [N][256] float32 (the BF16 features, zero

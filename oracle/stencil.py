@@ -250,6 +250,13 @@ def gauge_fix(alpha: np.ndarray, kappa: int = 13) -> np.ndarray:
     return alpha @ np.linalg.inv(A0)
 
 
+def gauge_condition(alpha: np.ndarray, kappa: int = 13) -> float:
+    """|A0|_F |A0^-1|_F of the centre block; the gauge is used only when <= 1e6."""
+    c = centre_index(kappa)
+    A0 = alpha[3 * c:3 * c + 3, :]
+    return float(np.linalg.norm(A0) * np.linalg.norm(np.linalg.inv(A0)))
+
+
 def locality(alpha: np.ndarray, gram: np.ndarray) -> float:
     """tr(q^H Gram q) with q an orthonormal basis of span(alpha)."""
     q, _ = np.linalg.qr(alpha)

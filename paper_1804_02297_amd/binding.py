@@ -64,8 +64,17 @@ SIGNATURES = [
     ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
     ("ls_sparse_destroy", None, [_VP]),
     ("ls_plan_fft_size", _I, [_VP]),
+    ("ls_plan_tune", _I, [_VP, _I, _I, _VP, _VP]), ("ls_plan_set_tune", _I, [_VP, _I, _I, _I]),
     ("ls_plan_destroy", None, [_VP]),
 ]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int), ("kmul_w", ctypes.c_int), ("ms_per_rhs", ctypes.c_double),
+                ("ms_default_per_rhs", ctypes.c_double), ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SolveInfo(ctypes.Structure):
@@ -379,6 +388,15 @@ class Plan:
         if check and st not in (0, -4):
             _check(st, "ls_gmres_solve")
         return x, [i.as_dict() for i in infos], st
+
+    def tune(self, nrhs: int, prec: str = "c64") -> dict:
+        """Autotune the batched apply (cache: the plan's tune_cache file)."""
+        info = TuneInfo()
+        _check(_lib.ls_plan_tune(self._h, nrhs, PREC[prec], _stream(), ctypes.byref(info)), "ls_plan_tune")
+        return info.as_dict()
+
+    def set_tune(self, prec: str, chunk: int = 0, kmul_w: int = 0):
+        _check(_lib.ls_plan_set_tune(self._h, PREC[prec], chunk, kmul_w), "ls_plan_set_tune")
 
     def rhs_from_incident(self, Ei, g=None):
         """g = -K * (m E^i) (right-hand side of Eq. (4)), complex128."""

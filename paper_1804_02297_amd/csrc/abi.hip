@@ -7,6 +7,7 @@
 #include <new>
 
 #include "plan.h"
+#include "tune.h"
 
 using namespace ls;
 
@@ -18,14 +19,7 @@ static inline double now_s() {
 // y = A x over nrhs fields, chunked by the plan's max_rhs
 static ls_status apply_chunked(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec,
                                hipStream_t s, bool minus_conv = false) {
-  const size_t es = (prec == LS_C64) ? 8 : 16;
-  const size_t per = (size_t)3 * plan->ap.n * plan->ap.n * plan->ap.n * es;
-  for (int b0 = 0; b0 < nrhs; b0 += plan->ap.max_rhs) {
-    const int nb = (nrhs - b0 < plan->ap.max_rhs) ? nrhs - b0 : plan->ap.max_rhs;
-    LS_TRY(apply_run(plan->ap, static_cast<const char*>(x_dev) + (size_t)b0 * per,
-                     static_cast<char*>(y_dev) + (size_t)b0 * per, nb, prec, s, minus_conv));
-  }
-  return LS_OK;
+  return apply_batched(plan->ap, x_dev, y_dev, nrhs, prec, s, minus_conv);
 }
 
 // z <- S^-1 Q z for the listed right-hand sides (device vectors), host solve in one block
@@ -108,8 +102,10 @@ ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs
   const size_t es = (prec == LS_C64) ? 8 : 16;
   const size_t per = (size_t)3 * plan->ap.n * plan->ap.n * plan->ap.n * es;
   ls_status st = LS_OK;
-  for (int b0 = 0; b0 < nrhs && st == LS_OK; b0 += plan->ap.max_rhs) {
-    const int nb = (nrhs - b0 < plan->ap.max_rhs) ? nrhs - b0 : plan->ap.max_rhs;
+  int chunk = plan->ap.tune[prec].chunk;
+  if (chunk <= 0 || chunk > plan->ap.max_rhs) chunk = plan->ap.max_rhs;
+  for (int b0 = 0; b0 < nrhs && st == LS_OK; b0 += chunk) {
+    const int nb = (nrhs - b0 < chunk) ? nrhs - b0 : chunk;
     st = apply_run(plan->ap, static_cast<const char*>(x_dev) + (size_t)b0 * per,
                    static_cast<char*>(y_dev) + (size_t)b0 * per, nb, prec, s, false, ev);
     if (st == LS_OK && hipEventSynchronize(ev[5]) != hipSuccess) st = LS_EHIP;
@@ -121,6 +117,32 @@ ls_status ls_apply_timed(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs
   }
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   return st;
+}
+
+ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, ls_tune_info* info) {
+  if (!plan || nrhs < 1) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
+  TuneOutcome r;
+  LS_TRY(apply_tune(plan->ap, plan->tune_cache, nrhs, prec, as_stream(hip_stream), &r));
+  if (info) {
+    info->chunk = r.chunk;
+    info->kmul_w = r.kmul_w;
+    info->ms_per_rhs = r.ms_per_rhs;
+    info->ms_default_per_rhs = r.ms_default_per_rhs;
+    info->from_cache = r.from_cache;
+    info->n_tried = r.n_tried;
+  }
+  return LS_OK;
+}
+
+ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w) {
+  if (!plan) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
+  if (chunk < 0 || chunk > plan->ap.max_rhs) return LS_EINVAL;
+  if (kmul_w != 0 && kmul_w != 1 && kmul_w != 2 && kmul_w != 4) return LS_EINVAL;
+  plan->ap.tune[prec].chunk = chunk;
+  plan->ap.tune[prec].kmul_w = kmul_w;
+  return LS_OK;
 }
 
 ls_status ls_rhs_from_incident(ls_plan* plan, const void* Ei_dev, void* g_dev, int nrhs,

@@ -58,6 +58,13 @@ struct DevBuf {
 
 // Operator data owned by a plan: contrast, Khat in both precisions, twiddles
 // and the pass workspace of the FFT apply.
+// Launch choices of the apply for one precision, picked by the autotuner.
+// 0 = the built-in default.
+struct ApplyTune {
+  int chunk = 0;                 // right-hand sides per apply launch set (<= max_rhs)
+  int kmul_w = 0;                // pass-3 teams per workgroup (1, 2, 4)
+};
+
 struct ApplyPlan {
   int n = 0, P = 0, H = 0;       // H = P/2 + 1 (octant extent)
   double k = 0.0, h = 0.0;
@@ -67,6 +74,7 @@ struct ApplyPlan {
   DevBuf tw64, tw32;             // exp(-2 pi i t / P), t in [0, P)
   DevBuf work;                   // pass intermediates
   size_t work_per_rhs64 = 0;     // bytes per rhs in FP64
+  ApplyTune tune[3];             // per ls_prec
 };
 
 ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const void* m_dev,
@@ -75,5 +83,12 @@ ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const voi
 // nrhs <= max_rhs.  ev, when given, holds 6 events recorded around the 5 passes.
 ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
                     bool minus_conv = false, hipEvent_t* ev = nullptr);
+// apply_run over any number of right-hand sides, ap.tune[prec].chunk (default
+// max_rhs) at a time.
+ls_status apply_batched(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
+                        bool minus_conv = false);
+// Pass-3 team counts the plan's FFT size supports (1 always; 2 and 4 when a
+// team is one wavefront).
+std::vector<int> kmul_team_choices(const ApplyPlan& ap);
 
 }  // namespace ls

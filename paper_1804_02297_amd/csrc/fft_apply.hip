@@ -24,6 +24,7 @@
 // Pass 3 transforms along the contiguous dimension; a workgroup owns one
 // octant line (f1, f2) of Khat and the up-to-four grid lines
 // (+-f1, +-f2) that share it, so Khat is read from HBM once per apply.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -440,22 +441,19 @@ static ls_status launch_kmul_w(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, i
   return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
 }
 
-// Teams per workgroup.  Measured at 128^3 with 8 right-hand sides: two
-// teams (1.04 ms) beat one (1.07 ms), four (1.04 ms) and eight (1.30 ms):
-// small workgroups let several workgroups per CU sit in different phases
-// (loads, arithmetic, stores), which a single large workgroup cannot.
-// LS_KMUL_W overrides the choice at build time (tuning only).
+// Teams per workgroup (wt; 0 = default 2).  Measured at 128^3 with 8
+// right-hand sides: two teams (1.04 ms) beat one (1.07 ms), four (1.04 ms)
+// and eight (1.30 ms): small workgroups let several workgroups per CU sit in
+// different phases (loads, arithmetic, stores), which one large workgroup
+// cannot.  The autotuner may pick another count per plan.
 template <typename R, int P>
-static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, hipStream_t s) {
+static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, int wt, hipStream_t s) {
   constexpr Fac f = row_factors<R>(P);
   constexpr int TPL = cmax(f.n1, f.n2);
-#ifdef LS_KMUL_W
-  constexpr int WT = LS_KMUL_W;
-#else
-  constexpr int WT = 2;
-#endif
-  if constexpr (4 * TPL == 64 && WT > 1) {
-    if (B >= WT) return launch_kmul_w<R, P, WT>(X, Kh, tw, n, B, s);
+  if (wt <= 0) wt = 2;
+  if constexpr (4 * TPL == 64) {
+    if (wt >= 4 && B >= 4) return launch_kmul_w<R, P, 4>(X, Kh, tw, n, B, s);
+    if (wt >= 2 && B >= 2) return launch_kmul_w<R, P, 2>(X, Kh, tw, n, B, s);
   }
   return launch_kmul_w<R, P, 1>(X, Kh, tw, n, B, s);
 }
@@ -506,7 +504,7 @@ static ls_status build_symbol(ApplyPlan& ap, hipStream_t s) {
 
 template <typename R, typename IO, int P>
 static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, const C<R>* m,
-                            const C<R>* kh, const C<R>* tw, bool minus_conv, hipStream_t s,
+                            const C<R>* kh, const C<R>* tw, bool minus_conv, int wt, hipStream_t s,
                             hipEvent_t* ev) {
   const int n = ap.n;
   const long n2 = (long)n * n, n3 = n2 * n;
@@ -523,7 +521,7 @@ static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, con
   LS_TRY((launch_col<R, R, P, COL_FWD>(X1, X2, nullptr, tw, n, P, n, n2, (long)P * n, nb * P, (R)1, s)));
   LS_MARK(2);
   // pass 3: along dim 3 with the 3x3 multiply
-  LS_TRY((launch_kmul<R, P>(X2, kh, tw, n, nrhs, s)));
+  LS_TRY((launch_kmul<R, P>(X2, kh, tw, n, nrhs, wt, s)));
   LS_MARK(3);
   // pass 4: inverse along dim 2
   LS_TRY((launch_col<R, R, P, COL_INV>(X2, X1, nullptr, tw, P, n, n, (long)P * n, n2, nb * P, (R)1, s)));
@@ -541,16 +539,17 @@ static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, con
 template <int P>
 static ls_status apply_dispatch(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec,
                                 bool minus_conv, hipStream_t s, hipEvent_t* ev) {
+  const int wt = ap.tune[prec].kmul_w;
   switch (prec) {
     case LS_C128:
-      return run_passes<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(),
-                                           ap.kh64.as<C<double>>(), ap.tw64.as<C<double>>(), minus_conv, s, ev);
+      return run_passes<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(), ap.kh64.as<C<double>>(),
+                                           ap.tw64.as<C<double>>(), minus_conv, wt, s, ev);
     case LS_C64:
-      return run_passes<float, float, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(),
-                                         ap.kh32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+      return run_passes<float, float, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.kh32.as<C<float>>(),
+                                         ap.tw32.as<C<float>>(), minus_conv, wt, s, ev);
     case LS_MIXED:
-      return run_passes<float, double, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(),
-                                          ap.kh32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+      return run_passes<float, double, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.kh32.as<C<float>>(),
+                                          ap.tw32.as<C<float>>(), minus_conv, wt, s, ev);
   }
   return LS_EINVAL;
 }
@@ -600,9 +599,16 @@ ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const voi
   return LS_EINVAL;
 }
 
+std::vector<int> kmul_team_choices(const ApplyPlan& ap) {
+  const Fac f = col_factors(ap.P);
+  if (4 * cmax(f.n1, f.n2) == 64) return {1, 2, 4};
+  return {1};
+}
+
 ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
                     bool minus_conv, hipEvent_t* ev) {
   if (nrhs < 1 || nrhs > ap.max_rhs) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
   switch (ap.P) {
 #define X(SZ) \
   case SZ: return apply_dispatch<SZ>(ap, x, y, nrhs, prec, minus_conv, s, ev);
@@ -610,6 +616,22 @@ ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec pre
 #undef X
   }
   return LS_EINVAL;
+}
+
+ls_status apply_batched(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
+                        bool minus_conv) {
+  if (nrhs < 1) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
+  const size_t es = (prec == LS_C64) ? 8 : 16;
+  const size_t per = (size_t)3 * ap.n * ap.n * ap.n * es;
+  int chunk = ap.tune[prec].chunk;
+  if (chunk <= 0 || chunk > ap.max_rhs) chunk = ap.max_rhs;
+  for (int b0 = 0; b0 < nrhs; b0 += chunk) {
+    const int nb = std::min(chunk, nrhs - b0);
+    LS_TRY(apply_run(ap, static_cast<const char*>(x) + (size_t)b0 * per, static_cast<char*>(y) + (size_t)b0 * per,
+                     nb, prec, s, minus_conv));
+  }
+  return LS_OK;
 }
 
 }  // namespace ls

@@ -21,6 +21,7 @@ namespace {
 
 constexpr int R81 = 81;
 constexpr int CENTRE = 13;          // index of offset (0,0,0) in the interior tau
+constexpr double kGaugeCondMax = 1e6;   // training samples need a well-conditioned centre block
 
 __device__ __forceinline__ unsigned short f2bf_l(float x) {
   unsigned u = __float_as_uint(x);
@@ -28,8 +29,9 @@ __device__ __forceinline__ unsigned short f2bf_l(float x) {
   return (unsigned short)(u >> 16);
 }
 
-__global__ void features_kernel(int n, const C<double>* __restrict__ m, const int* __restrict__ pts, int np,
-                                unsigned short* __restrict__ xb) {
+// xb[q] = features of point pts[sel[q]] (sel == nullptr: q itself), q < np
+__global__ void features_kernel(int n, const C<double>* __restrict__ m, const int* __restrict__ pts,
+                                const int* __restrict__ sel, int np, unsigned short* __restrict__ xb) {
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long)np * MLP_IP) return;
   const int p = (int)(id / MLP_IP), f = (int)(id % MLP_IP);
@@ -37,7 +39,7 @@ __global__ void features_kernel(int n, const C<double>* __restrict__ m, const in
   if (f < MLP_I) {
     const int t = f / 2, part = f % 2;
     const int o1 = t / 25 - 2, o2 = (t / 5) % 5 - 2, o3 = t % 5 - 2;
-    const int i = pts[p];
+    const int i = pts[sel ? sel[p] : p];
     const int i3 = i % n, i2 = (i / n) % n, i1 = i / (n * n);
     const int j1 = i1 + o1, j2 = i2 + o2, j3 = i3 + o3;
     if (j1 >= 0 && j1 < n && j2 >= 0 && j2 < n && j3 >= 0 && j3 < n) {
@@ -63,9 +65,11 @@ __device__ inline void inv3(const C<double> a[3][3], C<double> r[3][3]) {
     for (int j = 0; j < 3; ++j) r[i][j] = cof[j][i] * idet;
 }
 
-// out[p] = alpha[p] (alpha[p]_centre)^-1 for cnt stencils given by row pointers
+// out[p] = alpha[p] (alpha[p]_centre)^-1 for cnt stencils given by row pointers;
+// ok[p] (when given) = 1 if the centre block's Frobenius condition number
+// |A0|_F |A0^-1|_F is at most kGaugeCondMax (the gauge is then well defined)
 __global__ void gauge_kernel(const C<double>* __restrict__ alpha, const int* __restrict__ pts, int cnt,
-                             C<double>* __restrict__ out) {
+                             C<double>* __restrict__ out, int* __restrict__ ok) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= cnt) return;
   const C<double>* a = alpha + (long)(pts ? pts[p] : p) * 243;
@@ -73,6 +77,16 @@ __global__ void gauge_kernel(const C<double>* __restrict__ alpha, const int* __r
   for (int c = 0; c < 3; ++c)
     for (int r = 0; r < 3; ++r) A0[c][r] = a[(3 * CENTRE + c) * 3 + r];
   inv3(A0, Ai);
+  if (ok) {
+    double f0 = 0.0, f1 = 0.0;
+    for (int c = 0; c < 3; ++c)
+      for (int r = 0; r < 3; ++r) {
+        f0 += A0[c][r].re * A0[c][r].re + A0[c][r].im * A0[c][r].im;
+        f1 += Ai[c][r].re * Ai[c][r].re + Ai[c][r].im * Ai[c][r].im;
+      }
+    const double cf = sqrt(f0 * f1);
+    ok[p] = (cf == cf && cf <= kGaugeCondMax) ? 1 : 0;     // NaN (singular block) fails too
+  }
   C<double>* o = out + (long)p * 243;
   for (int row = 0; row < R81; ++row)
     for (int r = 0; r < 3; ++r) {
@@ -83,15 +97,17 @@ __global__ void gauge_kernel(const C<double>* __restrict__ alpha, const int* __r
 }
 
 // targets[p][2 (9 t + 3 c + r) + {0,1}] = Re, Im of (gt[p] - gclass)[(a, c), r], a != centre
-__global__ void encode_kernel(const C<double>* __restrict__ gt, const C<double>* __restrict__ gclass, int cnt,
-                              float* __restrict__ targets) {
+// targets[q] from gt[sel[q]], q < cnt
+__global__ void encode_kernel(const C<double>* __restrict__ gt, const C<double>* __restrict__ gclass,
+                              const int* __restrict__ sel, int cnt, float* __restrict__ targets) {
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (long)cnt * 234) return;
   const long p = id / 234;
+  const long src = sel[p];
   const int e = (int)(id % 234);
   const int t = e / 9, c = (e % 9) / 3, r = e % 3;
   const int a = t < CENTRE ? t : t + 1;
-  const C<double> d = gt[p * 243 + (3 * a + c) * 3 + r] - gclass[(3 * a + c) * 3 + r];
+  const C<double> d = gt[src * 243 + (3 * a + c) * 3 + r] - gclass[(3 * a + c) * 3 + r];
   targets[p * MLP_O + 2 * e] = (float)(d.re / MLP_T_SCALE);
   targets[p * MLP_O + 2 * e + 1] = (float)(d.im / MLP_T_SCALE);
 }
@@ -207,7 +223,7 @@ std::vector<int> interior_points(int n) {
 static ls_status class_gauge(StencilData& sd, DevBuf& out, hipStream_t s) {
   LS_TRY(out.alloc(243 * sizeof(C<double>)));
   hipLaunchKernelGGL(gauge_kernel, dim3(1), dim3(64), 0, s, sd.alpha.as<C<double>>() + 13L * 243, nullptr, 1,
-                     out.as<C<double>>());
+                     out.as<C<double>>(), nullptr);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -242,26 +258,40 @@ ls_status mlp_add_samples(MlpState& st, StencilData& sd, int n, double k, const 
   PointFitCtx ctx;
   const int B = std::min(npts, 8192);
   LS_TRY(pointfit_prepare(ctx, sd, n, k, B, s));
-  DevBuf dpts, gclass, gt;
+  DevBuf dpts, gclass, gt, dok, dsel;
   LS_TRY(dpts.alloc((size_t)npts * sizeof(int)));
   LS_HIP(hipMemcpyAsync(dpts.p, pts_host, (size_t)npts * sizeof(int), hipMemcpyHostToDevice, s));
   LS_TRY(class_gauge(sd, gclass, s));
   LS_TRY(gt.alloc((size_t)B * 243 * sizeof(C<double>)));
+  LS_TRY(dok.alloc((size_t)B * sizeof(int)));
+  LS_TRY(dsel.alloc((size_t)B * sizeof(int)));
+  std::vector<int> ok(B), sel;
+  long added = 0;
   for (int p0 = 0; p0 < npts; p0 += B) {
     const int cnt = std::min(B, npts - p0);
     const int* dp = dpts.as<int>() + p0;
     LS_TRY(pointfit_grams(ctx, m, m0, dp, cnt, s));
     LS_TRY(pointfit_solve(ctx, sd, dp, cnt, 12, s));
     hipLaunchKernelGGL(gauge_kernel, dim3(nbl(cnt, 64)), dim3(64), 0, s, sd.palpha.as<C<double>>(), dp, cnt,
-                       gt.as<C<double>>());
-    hipLaunchKernelGGL(encode_kernel, dim3(nbl((long)cnt * 234, 256)), dim3(256), 0, s, gt.as<C<double>>(),
-                       gclass.as<C<double>>(), cnt, st.ts.as<float>() + (st.nsamples + p0) * MLP_O);
-    hipLaunchKernelGGL(features_kernel, dim3(nbl((long)cnt * MLP_IP, 256)), dim3(256), 0, s, n, m, dp, cnt,
-                       st.xs.as<unsigned short>() + (st.nsamples + p0) * MLP_IP);
+                       gt.as<C<double>>(), dok.as<int>());
     LS_HIP(hipGetLastError());
+    LS_HIP(hipMemcpyAsync(ok.data(), dok.p, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+    LS_HIP(hipStreamSynchronize(s));
+    sel.clear();
+    for (int q = 0; q < cnt; ++q)
+      if (ok[q]) sel.push_back(q);
+    const int cg = (int)sel.size();
+    if (cg == 0) continue;
+    LS_HIP(hipMemcpyAsync(dsel.p, sel.data(), cg * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(encode_kernel, dim3(nbl((long)cg * 234, 256)), dim3(256), 0, s, gt.as<C<double>>(),
+                       gclass.as<C<double>>(), dsel.as<int>(), cg, st.ts.as<float>() + (st.nsamples + added) * MLP_O);
+    hipLaunchKernelGGL(features_kernel, dim3(nbl((long)cg * MLP_IP, 256)), dim3(256), 0, s, n, m, dp,
+                       dsel.as<int>(), cg, st.xs.as<unsigned short>() + (st.nsamples + added) * MLP_IP);
+    LS_HIP(hipGetLastError());
+    added += cg;
   }
   LS_HIP(hipStreamSynchronize(s));
-  st.nsamples += npts;
+  st.nsamples += added;
   sd.have_point = false;      // palpha now holds a partial fit: not a usable per-point stencil set
   return LS_OK;
 }
@@ -333,8 +363,8 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
   for (int p0 = 0; p0 < npts; p0 += B) {
     const int cnt = std::min(B, npts - p0);
     const int* dp = dpts.as<int>() + p0;
-    hipLaunchKernelGGL(features_kernel, dim3(nbl((long)cnt * MLP_IP, 256)), dim3(256), 0, s, n, m, dp, cnt,
-                       xb.as<unsigned short>());
+    hipLaunchKernelGGL(features_kernel, dim3(nbl((long)cnt * MLP_IP, 256)), dim3(256), 0, s, n, m, dp, nullptr,
+                       cnt, xb.as<unsigned short>());
     LS_HIP(hipGetLastError());
     LS_TRY(mlp_forward(st, xb.as<unsigned short>(), cnt, s));
     hipLaunchKernelGGL(decode_kernel, dim3(nbl((long)cnt * 243, 256)), dim3(256), 0, s, st.y.as<float>(),

@@ -1,0 +1,193 @@
+// Autotuner of the batched apply: for one (n, precision, batch) it times every
+// launch choice on the plan's own operator and keeps the fastest.
+//
+// Choices: the right-hand sides per launch set (chunk: 1, 2, 4, ... up to the
+// batch) and the pass-3 teams per workgroup (1, 2, 4 where a team is one
+// wavefront).  A smaller chunk trades launch count for a working set that can
+// stay in the last-level cache between passes; the team count trades
+// workgroup size against phase overlap on a CU.  Each candidate runs once to
+// warm up, then 3 times between HIP events.
+//
+// Cache: a JSON array, one object per line,
+//   {"key": "<arch>|cu=<CUs>|n=<n>|P=<P>|prec=<p>|nrhs=<b>|max_rhs=<m>", "chunk": c, "kmul_w": w, "ms_per_rhs": t}
+// read before timing (a hit skips it) and rewritten with the new entry after.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "tune.h"
+
+namespace ls {
+
+namespace {
+
+std::string tune_key(const ApplyPlan& ap, int nrhs, ls_prec prec) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|cu=%d|n=%d|P=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus, ap.n, ap.P,
+                (int)prec, nrhs, ap.max_rhs);
+  return buf;
+}
+
+struct Entry {
+  std::string key;
+  int chunk = 0, kmul_w = 0;
+  double ms = 0.0;
+};
+
+bool parse_int_field(const std::string& line, const char* name, int* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return false;
+  return std::sscanf(line.c_str() + p + pat.size(), " %d", v) == 1;
+}
+
+std::vector<Entry> read_cache(const std::string& path) {
+  std::vector<Entry> out;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t k = line.find("\"key\": \"");
+    if (k == std::string::npos) continue;
+    const size_t k0 = k + 8, k1 = line.find('"', k0);
+    if (k1 == std::string::npos) continue;
+    Entry e;
+    e.key = line.substr(k0, k1 - k0);
+    if (!parse_int_field(line, "chunk", &e.chunk) || !parse_int_field(line, "kmul_w", &e.kmul_w)) continue;
+    const size_t t = line.find("\"ms_per_rhs\":");
+    if (t != std::string::npos) std::sscanf(line.c_str() + t + 13, " %lf", &e.ms);
+    out.push_back(e);
+  }
+  return out;
+}
+
+bool write_cache(const std::string& path, const std::vector<Entry>& es) {
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "[\n";
+    for (size_t i = 0; i < es.size(); ++i) {
+      char buf[512];
+      std::snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"chunk\": %d, \"kmul_w\": %d, \"ms_per_rhs\": %.6g}%s\n",
+                    es[i].key.c_str(), es[i].chunk, es[i].kmul_w, es[i].ms, i + 1 < es.size() ? "," : "");
+      f << buf;
+    }
+    f << "]\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+// average ms of one batched apply under the plan's current choice
+ls_status time_apply(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
+                     hipEvent_t e0, hipEvent_t e1, double* ms) {
+  constexpr int kReps = 3;
+  LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
+  LS_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < kReps; ++r) LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
+  LS_HIP(hipEventRecord(e1, s));
+  LS_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  LS_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = (double)t / kReps;
+  return LS_OK;
+}
+
+}  // namespace
+
+ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec prec, hipStream_t s,
+                     TuneOutcome* out) {
+  if (nrhs < 1) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
+  TuneOutcome res;
+  const std::string key = tune_key(ap, nrhs, prec);
+  std::vector<Entry> entries;
+  if (!cache.empty()) {
+    entries = read_cache(cache);
+    for (const Entry& e : entries)
+      if (e.key == key && e.chunk >= 1 && e.chunk <= ap.max_rhs && e.kmul_w >= 1) {
+        ap.tune[prec].chunk = e.chunk;
+        ap.tune[prec].kmul_w = e.kmul_w;
+        res.chunk = e.chunk;
+        res.kmul_w = e.kmul_w;
+        res.ms_per_rhs = e.ms;
+        res.from_cache = 1;
+        if (out) *out = res;
+        return LS_OK;
+      }
+  }
+  const size_t es = (prec == LS_C64) ? 8 : 16;
+  const size_t bytes = (size_t)nrhs * 3 * ap.n * ap.n * ap.n * es;
+  DevBuf x, y;
+  LS_TRY(x.alloc(bytes));
+  LS_TRY(y.alloc(bytes));
+  LS_HIP(hipMemsetAsync(x.p, 0x3c, bytes, s));     // small finite values in either precision
+  hipEvent_t e0, e1;
+  LS_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LS_EHIP;
+  }
+  const ApplyTune saved = ap.tune[prec];
+  std::vector<int> chunks;
+  const int cmax = std::min(nrhs, ap.max_rhs);
+  for (int c = 1; c < cmax; c *= 2) chunks.push_back(c);
+  chunks.push_back(cmax);
+  const std::vector<int> teams = kmul_team_choices(ap);
+  ls_status st = LS_OK;
+  double best = 1e300;
+  ApplyTune pick = saved;
+  // the default choice first, for reference
+  ap.tune[prec] = ApplyTune{};
+  st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &res.ms_default_per_rhs);
+  res.ms_default_per_rhs /= nrhs;
+  for (size_t ci = 0; ci < chunks.size() && st == LS_OK; ++ci)
+    for (size_t wi = 0; wi < teams.size() && st == LS_OK; ++wi) {
+      if (teams[wi] > chunks[ci]) continue;       // a team needs its own right-hand side
+      ap.tune[prec].chunk = chunks[ci];
+      ap.tune[prec].kmul_w = teams[wi];
+      double ms = 0.0;
+      st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &ms);
+      ++res.n_tried;
+      if (st == LS_OK && ms < best) {
+        best = ms;
+        pick = ap.tune[prec];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LS_OK) {
+    ap.tune[prec] = saved;
+    return st;
+  }
+  ap.tune[prec] = pick;
+  res.chunk = pick.chunk;
+  res.kmul_w = pick.kmul_w;
+  res.ms_per_rhs = best / nrhs;
+  if (!cache.empty()) {
+    Entry e;
+    e.key = key;
+    e.chunk = pick.chunk;
+    e.kmul_w = pick.kmul_w;
+    e.ms = res.ms_per_rhs;
+    entries.push_back(e);
+    if (!write_cache(cache, entries)) res.cache_write_failed = 1;
+  }
+  if (out) *out = res;
+  return LS_OK;
+}
+
+}  // namespace ls

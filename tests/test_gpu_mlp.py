@@ -97,6 +97,7 @@ def test_samples_match_oracle(lib):
     assert not xs[:, 250:].any()
     for q, i0 in enumerate(pts0):
         al, _, _ = ost.fit_point_weighted(m, i0, k, m0=0.1)
+        assert ost.gauge_condition(al) <= 1e6        # all four are kept
         ref = omlp.encode_target(ost.gauge_fix(al), cal)
         assert np.abs(ts[q] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max()), i0
 

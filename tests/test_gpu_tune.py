@@ -1,0 +1,81 @@
+"""Block right-hand sides and the apply autotuner on the GPU.
+
+Every launch choice (right-hand sides per launch set, pass-3 teams per
+workgroup) runs the same arithmetic in the same order, so results must be
+bitwise identical across choices; the tuned batch apply must also match the
+oracle within the FP32 bar.  The tuner's cache file must round-trip.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import operator as oop
+from paper_1804_02297_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _plan(n, max_rhs, cache=None, seed=3):
+    from paper_1804_02297_amd.binding import Plan
+    m = torch.from_numpy(I.medium_bumps(n, seed)).to("cuda:0")
+    return Plan(n, I.wavenumber_for(n), m, max_rhs=max_rhs, tune_cache=cache)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128", "mixed"])
+def test_launch_choices_bitwise_identical(lib, prec):
+    n, B = 50, 4                         # P = 128: teams of one wavefront, 1/2/4 teams allowed
+    plan = _plan(n, B)
+    assert plan.P == 128
+    dt = torch.complex64 if prec == "c64" else torch.complex128
+    x = torch.from_numpy(I.random_field(B, n, 11)).to("cuda:0").to(dt)
+    ref = plan.apply(x, prec=prec)
+    for chunk, w in [(1, 1), (2, 2), (4, 4), (4, 1), (3, 2), (1, 4)]:
+        plan.set_tune(prec, chunk, w)
+        y = plan.apply(x, prec=prec)
+        assert torch.equal(y, ref), (chunk, w)
+    plan.set_tune(prec, 0, 0)
+    plan.close()
+
+
+def test_set_tune_rejects_bad_choices(lib):
+    from paper_1804_02297_amd.binding import LSError
+    plan = _plan(8, 2)
+    for chunk, w in [(3, 0), (-1, 0), (0, 3), (0, 8)]:
+        with pytest.raises(LSError):
+            plan.set_tune("c64", chunk, w)
+    plan.close()
+
+
+def test_tune_picks_valid_choice_and_caches(lib, tmp_path):
+    cache = str(tmp_path / "tune.json")
+    n, B = 50, 8
+    plan = _plan(n, B, cache)
+    info = plan.tune(B, "c64")
+    print("tune", info, flush=True)
+    assert info["from_cache"] == 0 and info["n_tried"] >= 4
+    assert 1 <= info["chunk"] <= B and info["kmul_w"] in (1, 2, 4)
+    assert 0 < info["ms_per_rhs"] <= info["ms_default_per_rhs"] * 1.05
+    with open(cache) as f:
+        entries = json.load(f)
+    assert len(entries) == 1 and f"n={n}|P=128|prec=1|nrhs={B}" in entries[0]["key"]
+    # the tuned apply still matches the oracle (FP32 bar) on every rhs
+    x = I.random_field(B, n, 12)
+    y = plan.apply(torch.from_numpy(x).to("cuda:0").to(torch.complex64), prec="c64").cpu().numpy()
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 3)
+    for r in (0, B - 1):
+        ref = oop.apply_fft(n, k, m, x[r:r + 1])[0]
+        assert np.abs(y[r] - ref).max() <= 1e-5 * np.abs(ref).max()
+    plan.close()
+    # a second plan with the same key reads the cache and times nothing
+    plan2 = _plan(n, B, cache)
+    info2 = plan2.tune(B, "c64")
+    assert info2["from_cache"] == 1 and info2["n_tried"] == 0
+    assert (info2["chunk"], info2["kmul_w"]) == (info["chunk"], info["kmul_w"])
+    # another precision adds a second entry
+    plan2.tune(B, "mixed")
+    with open(cache) as f:
+        assert len(json.load(f)) == 2
+    plan2.close()

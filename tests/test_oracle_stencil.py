@@ -159,3 +159,15 @@ def test_weighted_fit_ky_fan_and_gauge():
     c0 = st.centre_index(13)
     assert np.abs(at[3 * c0:3 * c0 + 3] - np.eye(3)).max() <= 1e-13
     assert np.abs(st.projector(at) - st.projector(al)).max() <= 1e-10
+
+
+def test_gauge_condition_closed_forms():
+    """|A0|_F |A0^-1|_F: 3 for a unitary centre block, ~1/eps for diag(1, 1, eps)."""
+    c = st.centre_index(13)
+    a = np.zeros((81, 3), complex)
+    q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((3, 3)) + 1j)
+    a[3 * c:3 * c + 3] = q
+    assert abs(st.gauge_condition(a) - 3.0) <= 1e-12
+    a[3 * c:3 * c + 3] = np.diag([1.0, 1.0, 1e-7])
+    assert abs(st.gauge_condition(a) - np.sqrt(2 + 1e-14) * np.sqrt(2 + 1e14)) <= 1e-6 * 1e7
+    assert st.gauge_condition(a) > 1e6
