@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "d3c81545c8204ac98fff02b41a63af089979689c65db7b11e945675806b03de1",
+    "sha256": "6840f5357aec613ed90f303d8105b7c33a771d95576eb1a63ee2a505d077b894",
     "workload": (128, 8, "c64"),
     "bytes": 3.3268e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
@@ -97,62 +97,121 @@ def cpu_baseline(n: int, seconds: float = 15.0):
                       f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
 
 
-def solve_section(n: int, ndirs: int, binding, I, torch):
-    """Per-rhs time to a 1e-8 relative residual: plain FP64 against the batched mixed form.
+def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500):
+    """Per-rhs time to a 1e-8 relative residual: plain FP64 against the chosen form.
 
-    Both use the same class stencils and host factorisation (set-up timed
-    apart).  Plain: one rhs at a time, FP64 apply.  Batched: ndirs Fibonacci
-    directions x 2 polarisations solved together, FP32 apply inside the FP64
-    outer FGMRES.
+    Plain: class stencils (the paper's 27 fits), FP64 apply, one rhs at a time.
+    Chosen: learned per-point stencils (network trained here on exact
+    per-point fits of other seeded media, exact fit where it is not accepted),
+    FP32 apply inside the FP64 outer FGMRES, ndirs Fibonacci directions x 2
+    polarisations solved as one block with the autotuned apply.  Set-up
+    (training, fits, host factorisations) is timed apart.
     """
     import numpy as np
     dev = torch.device("cuda:0")
     k = I.wavenumber_for(n)
-    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
     nb = 2 * ndirs
-    plan = binding.Plan(n, k, m, max_rhs=nb)
+    interior = [(a * n + b) * n + c for a in range(1, n - 1) for b in range(1, n - 1) for c in range(1, n - 1)]
+
+    # --- set-up: train the stencil network on other media
     t0 = time.perf_counter()
-    plan.stencil_fit(0)
+    net = binding.Mlp(binding.Mlp.flat(_init_params(7)))
+    for seed in range(1000, 1000 + train_media):
+        pt = binding.Plan(n, k, torch.from_numpy(I.medium_bumps(n, seed)).to(dev))
+        net.add_samples(pt, interior)
+        pt.close()
     torch.cuda.synchronize()
-    t_fit = time.perf_counter() - t0
+    t_samples = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan.factor()
-    t_factor = time.perf_counter() - t0
+    loss = net.train(train_steps, batch=1024, lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t0
+
+    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
+    plan = binding.Plan(n, k, m, max_rhs=nb)
     dirs, pols = I.fibonacci_incident_set(ndirs)
     Ei = torch.from_numpy(I.plane_waves(n, k, dirs, pols)).to(dev)
     g = plan.rhs_from_incident(Ei)
     torch.cuda.synchronize()
 
-    def run(gg, prec):
+    def timed(fn):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, infos, st = plan.solve(gg, tol=1e-8, prec=prec)
+        r = fn()
         torch.cuda.synchronize()
-        return time.perf_counter() - t, x, infos, st
+        return time.perf_counter() - t, r
 
+    def run(gg, prec):
+        return timed(lambda: plan.solve(gg, tol=1e-8, prec=prec))
+
+    # --- plain FP64 path: class stencils, one rhs
+    t_fit_cls, _ = timed(lambda: plan.stencil_fit(0))
+    t_fac_cls, _ = timed(plan.factor)
     run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
-    t_plain, x1, inf1, st1 = run(g[:1], "c128")
+    t_plain, (x1, inf1, st1) = run(g[:1], "c128")
+    # --- chosen path: exact per-point fit (for its time), then the learned fit
+    t_fit_pt, _ = timed(lambda: plan.stencil_fit(1))
+    t_fit_lrn, nfb = timed(lambda: plan.stencil_fit_learned(net))
+    t_fac_lrn, _ = timed(plan.factor)
     tune = plan.tune(nb, "mixed")                         # launch choice of the batched apply
-    t_mixed, xb, infb, stb = run(g, "mixed")
+    t_mixed, (xb, infb, stb) = run(g, "mixed")
     # residuals re-measured with the FP64 apply: r = g - A x
     r = torch.empty_like(g)
     plan.apply(xb, r, prec="c128")
     rel = (torch.linalg.vector_norm((g - r).reshape(nb, -1), dim=1) /
            torch.linalg.vector_norm(g.reshape(nb, -1), dim=1)).max().item()
     plan.close()
+    net.close()
     return {
         "n": n, "unknowns_per_rhs": 3 * n ** 3, "nrhs_batched": nb,
-        "stencil_fit_s": round(t_fit, 3), "factor_s": round(t_factor, 3),
         "plain_fp64_s_per_rhs": round(t_plain, 4), "plain_iters": inf1[0]["iters"],
-        "batched_mixed_s_per_rhs": round(t_mixed / nb, 4),
-        "batched_iters_max": max(i["iters"] for i in infb),
-        "batched_max_rel_resid_fp64": float(f"{rel:.3e}"),
+        "chosen_s_per_rhs": round(t_mixed / nb, 4),
+        "chosen_iters_max": max(i["iters"] for i in infb),
+        "chosen_max_rel_resid_fp64": float(f"{rel:.3e}"),
         "status": [st1, stb],
         "speedup_per_rhs": round(t_plain / (t_mixed / nb), 2),
-        "gpu_s_batched": round(max(i["t_gpu"] for i in infb), 4),
-        "host_s_batched": round(max(i["t_host"] for i in infb), 4),
-        "tuned_apply": {k: tune[k] for k in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
+        "chosen_gpu_s": round(max(i["t_gpu"] for i in infb), 4),
+        "chosen_host_s": round(max(i["t_host"] for i in infb), 4),
+        "learned_fallback_points": int(nfb), "interior_points": len(interior),
+        "setup_s": {"samples": round(t_samples, 3), "train": round(t_train, 3),
+                    "train_loss_first_last": [round(float(loss[0]), 4), round(float(np.mean(loss[-20:])), 4)],
+                    "class_fit": round(t_fit_cls, 3), "point_fit_exact": round(t_fit_pt, 3),
+                    "learned_fit": round(t_fit_lrn, 3),
+                    "factor_class": round(t_fac_cls, 3), "factor_learned": round(t_fac_lrn, 3)},
+        "tuned_apply": {k2: tune[k2] for k2 in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
     }
+
+
+def _init_params(seed: int):
+    """He-normal weights, zero biases, in the network's flat layout (250-256-256-468)."""
+    import numpy as np
+    g = np.random.default_rng(seed)
+    dims = [(250, 256), (256, 256), (256, 468)]
+    p = {}
+    for i, (a, b) in enumerate(dims, 1):
+        p[f"W{i}"] = g.standard_normal((a, b)) * np.sqrt(2.0 / a)
+        p[f"b{i}"] = np.zeros(b)
+    return p
+
+
+def hbm_copy_gbps(torch, gib: float = 2.0) -> float:
+    """Device-to-device copy bandwidth (read + write bytes / time) of a torch copy."""
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
 
 
 def main():
@@ -250,6 +309,7 @@ def main():
         "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
         "wall_s_timed": round(wall32, 3),
     }
+    out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
     if args.solve_n:
         out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch)
     if not args.no_cpu:
