@@ -197,7 +197,8 @@ ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs
  * 5^3 patch of m around it (x = Re, Im of m / 0.3, 250 inputs, last dimension
  * fastest, zero off the grid): 250 -> 256 GELU -> 256 GELU -> 468, GELU(x) =
  * x Phi(x).  The 468 outputs are the 26 off-centre 3x3 blocks [block][c][r]
- * (re, im interleaved) of alpha~_i - alpha~_class, alpha~ = alpha (alpha_centre)^-1.
+ * (re, im interleaved) of (alpha~_i - alpha~_class) / 3e-3, alpha~ = alpha
+ * (alpha_centre)^-1 (the scale brings the corrections to unit size).
  * Parameters: flat float32 W1[250][256] b1[256] W2[256][256] b2[256]
  * W3[256][468] b3[468] (250324 values, y = x W + b).  Products use BF16
  * operands with FP32 accumulation on MFMA; Adam (0.9, 0.999, 1e-8) updates

@@ -171,3 +171,29 @@ def test_gauge_condition_closed_forms():
     a[3 * c:3 * c + 3] = np.diag([1.0, 1.0, 1e-7])
     assert abs(st.gauge_condition(a) - np.sqrt(2 + 1e-14) * np.sqrt(2 + 1e14)) <= 1e-6 * 1e7
     assert st.gauge_condition(a) > 1e6
+
+
+def test_locality_ratio_bounds_of_the_learned_acceptance():
+    """rho(alpha^) = tr(Q^H G Q) / tr(alpha_c^H G alpha_c) over spans: Ky Fan gives
+    rho >= sum of the 3 smallest eigenvalues / tr(alpha_c^H G alpha_c), with equality
+    for the exact fit; the class stencil has rho = 1; a decoded encode of the exact
+    fit reproduces it; the acceptance rho < 1 therefore takes exactly the predictions
+    that beat the class stencil on the point's own objective."""
+    from oracle import mlp as om
+    n = 8
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 5)
+    i0 = (4, 3, 4)
+    al, _, s = st.fit_point_weighted(m, i0, k)
+    G = st.weighted_gram(m, i0, k)
+    ac = st.fit_class(13, n, k)[0]
+    ta = st.locality(ac, G)
+    bound = np.sum(np.sort(np.linalg.eigvalsh(G))[:3]) / ta
+    assert abs(np.sum(s[:3] ** 2) / ta - bound) <= 1e-10
+    assert abs(st.locality(al, G) / ta - bound) <= 1e-10
+    cal = st.gauge_fix(ac)
+    assert abs(st.locality(om.decode_output(np.zeros(om.D_OUT), cal), G) / ta - 1.0) <= 1e-12
+    rec = om.decode_output(om.encode_target(st.gauge_fix(al), cal), cal)
+    assert abs(st.locality(rec, G) / ta - bound) <= 1e-10
+    rnd = np.random.default_rng(1).standard_normal(om.D_OUT)
+    assert st.locality(om.decode_output(rnd, cal), G) / ta >= bound - 1e-12
