@@ -159,7 +159,8 @@ ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
   plan->hs = nullptr;
   plan->sd.have_point = false;
   plan->sd.have_rows = false;
-  LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
+  // the class stencils depend on (n, k) only: computed once per plan
+  if (!plan->sd.have_class) LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
   if (mode == LS_FIT_POINT)
     LS_TRY(point_fit(plan->sd, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0, 16384, 12, s));
   LS_TRY(assemble_rows(plan->sd, plan->ap.n, plan->ap.m64.as<C<double>>(), s));

@@ -344,7 +344,7 @@ ls_status mlp_train(MlpState& st, int steps, int batch, double lr, unsigned seed
 
 ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<double>* m, double m0,
                       int* n_fallback, hipStream_t s) {
-  LS_TRY(class_fit(sd, n, k, s));
+  if (!sd.have_class) LS_TRY(class_fit(sd, n, k, s));
   std::vector<int> pts = interior_points(n);
   const int npts = (int)pts.size();
   const int B = std::min(npts, 8192);

@@ -27,7 +27,7 @@ struct MlpState {
   int t = 0;                         // Adam step count
   // activations / gradients workspace
   int ws_rows = 0;
-  DevBuf z1, z2, h1b, h2b, y, dyb, dz2, dz2b, dz1, dz1b, dw, sq;
+  DevBuf z1, z2, h1b, h2b, y, dyb, dz2, dz2b, dz1, dz1b, dw, sq, part;
   // training set: features (BF16, N x 256) and targets (FP32, N x 468)
   DevBuf xs, ts;
   long nsamples = 0, cap = 0;

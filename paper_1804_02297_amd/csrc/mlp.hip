@@ -156,28 +156,61 @@ __global__ void pad_bf16_kernel(const float* __restrict__ a, int r, int c, unsig
   b[i] = (row < r && col < c) ? f2bf(a[(long)row * c + col]) : (unsigned short)0;
 }
 
-// dY = 2 (Y - T) / (B * 468), padded columns zero; per-row squared error partials
-__global__ void loss_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T, int Bm, float inv,
-                                 unsigned short* __restrict__ dYb, float* __restrict__ sq) {
+// dY = 2 (Y - T) / (B * 468), padded columns zero; the block's sum of squared
+// errors goes to sq[block % 256] (one atomic per block)
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                        int Bm, float inv, unsigned short* __restrict__ dYb,
+                                                        float* __restrict__ sq) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)Bm * MLP_OP) return;
-  const int n = (int)(i % MLP_OP);
-  const long m = i / MLP_OP;
   float d = 0.f;
-  if (n < MLP_O) {
-    d = Y[i] - T[m * MLP_O + n];
-    atomicAdd(&sq[m % 256], d * d);
+  if (i < (long)Bm * MLP_OP) {
+    const int n = (int)(i % MLP_OP);
+    const long m = i / MLP_OP;
+    if (n < MLP_O) d = Y[i] - T[m * MLP_O + n];
+    dYb[i] = f2bf(2.0f * d * inv);
   }
-  dYb[i] = f2bf(2.0f * d * inv);
+  float e = d * d;
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&sq[blockIdx.x % 256], red[0] + red[1] + red[2] + red[3]);
 }
 
-// db[n] = sum_m dZ[m][n]
-__global__ void bias_grad_kernel(const float* __restrict__ dZ, int Bm, int ld, int nvalid, float* __restrict__ db) {
+// Column sums in two deterministic stages.  Stage 1: part[c][n] = sum over
+// the rows m of chunk c of (A[m][n] - B[m][n]) (B may be null); a block is 64
+// columns x 4 row phases, blockIdx.y the chunk.  Stage 2: out[n] = scale sum_c.
+constexpr int kColChunks = 32;
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ A, int lda,
+                                                             const float* __restrict__ B, int ldb, int rows,
+                                                             int cols, float* __restrict__ part) {
+  const int cx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + cx;
+  const int per = (rows + kColChunks - 1) / kColChunks;
+  const int m0 = blockIdx.y * per, m1 = min(rows, m0 + per);
+  float acc = 0.f;
+  if (n < cols)
+    for (int m = m0 + ry; m < m1; m += 4) acc += A[(long)m * lda + n] - (B ? B[(long)m * ldb + n] : 0.f);
+  __shared__ float red[4][64];
+  red[ry][cx] = acc;
+  __syncthreads();
+  if (ry == 0 && n < cols) part[(long)blockIdx.y * cols + n] = red[0][cx] + red[1][cx] + red[2][cx] + red[3][cx];
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part, int cols, float scale, float* __restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nvalid) return;
-  float s = 0.f;
-  for (int m = 0; m < Bm; ++m) s += dZ[(long)m * ld + n];
-  db[n] = s;
+  if (n >= cols) return;
+  float acc = 0.f;
+  for (int c = 0; c < kColChunks; ++c) acc += part[(long)c * cols + n];
+  out[n] = scale * acc;
+}
+
+static ls_status colsum(const float* A, int lda, const float* B, int ldb, int rows, int cols, float scale,
+                        float* part, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((cols + 63) / 64, kColChunks), dim3(256), 0, s, A, lda, B, ldb, rows,
+                     cols, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, part, cols, scale, out);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
 }
 
 // gather a row-major block of FP32 dW (rows x cols, ld) into the flat gradient
@@ -247,6 +280,7 @@ ls_status mlp_workspace(MlpState& st, int Bm) {
   LS_TRY(st.dz1b.alloc((size_t)Bm * MLP_H * 2));
   LS_TRY(st.dw.alloc((size_t)MLP_H * MLP_OP * 4));
   LS_TRY(st.sq.alloc(256 * 4));
+  LS_TRY(st.part.alloc((size_t)kColChunks * MLP_OP * 4));
   st.ws_rows = Bm;
   return LS_OK;
 }
@@ -292,7 +326,7 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
                                        MLP_H, Bm, es, s)));
   hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_H,
                      MLP_H, MLP_H, g + MLP_OFF_W2);
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(256), 0, s, st.dz2.as<float>(), Bm, MLP_H, MLP_H, g + MLP_OFF_B2);
+  LS_TRY(colsum(st.dz2.as<float>(), MLP_H, nullptr, 0, Bm, MLP_H, 1.0f, st.part.as<float>(), g + MLP_OFF_B2, s));
   EpiArgs ed1{nullptr, st.dz1.as<float>(), st.z1.as<float>(), st.dz1b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
   LS_TRY((gemm<false, true, EPI_DACT>(st.dz2b.as<unsigned short>(), MLP_H, st.w2b.as<unsigned short>(), MLP_H, Bm,
                                       MLP_H, MLP_H, ed1, s)));
@@ -301,7 +335,7 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
   LS_TRY((gemm<true, false, EPI_STORE>(xb, MLP_IP, st.dz1b.as<unsigned short>(), MLP_H, MLP_IP, MLP_H, Bm, es, s)));
   hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_I * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_I,
                      MLP_H, MLP_H, g + MLP_OFF_W1);
-  hipLaunchKernelGGL(bias_grad_kernel, dim3(1), dim3(256), 0, s, st.dz1.as<float>(), Bm, MLP_H, MLP_H, g + MLP_OFF_B1);
+  LS_TRY(colsum(st.dz1.as<float>(), MLP_H, nullptr, 0, Bm, MLP_H, 1.0f, st.part.as<float>(), g + MLP_OFF_B1, s));
   LS_HIP(hipGetLastError());
   // db3 = column sums of dY in FP32: dY = 2 (Y - T) / (B 468)
   LS_TRY(mlp_bias3_grad(st, T, Bm, g + MLP_OFF_B3, s));
@@ -316,21 +350,8 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
   return LS_OK;
 }
 
-namespace {
-__global__ void bias3_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T, int Bm, float inv,
-                                  float* __restrict__ db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= MLP_O) return;
-  float s = 0.f;
-  for (int m = 0; m < Bm; ++m) s += Y[(long)m * MLP_OP + n] - T[(long)m * MLP_O + n];
-  db[n] = 2.0f * s * inv;
-}
-}  // namespace
-
 ls_status mlp_bias3_grad(MlpState& st, const float* T, int Bm, float* db, hipStream_t s) {
-  hipLaunchKernelGGL(bias3_grad_kernel, dim3(nbk(MLP_O, 256)), dim3(256), 0, s, st.y.as<float>(), T, Bm,
-                     1.0f / ((float)Bm * MLP_O), db);
-  return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+  return colsum(st.y.as<float>(), MLP_OP, T, MLP_O, Bm, MLP_O, 2.0f / ((float)Bm * MLP_O), st.part.as<float>(), db, s);
 }
 
 ls_status mlp_adam(MlpState& st, double lr, hipStream_t s) {

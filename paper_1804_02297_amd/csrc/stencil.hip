@@ -11,7 +11,8 @@
 //                         non-local block X = [Re M; Im M], on FP64 MFMA
 //                         (v_mfma_f64_16x16x4); M's columns K(a - j) are
 //                         evaluated on the fly from the closed form.
-//   gram_reduce_kernel  : sums the partial tiles, forms the complex Gram M M^H.
+//   gram_sum_kernel     : sums the partial tiles in 16 chunks (coalesced).
+//   gram_reduce_kernel  : sums the chunks, forms the complex Gram M M^H.
 //   heev_low3_kernel    : three smallest eigenvectors of the Hermitian Gram by
 //                         Cholesky + block inverse iteration (8 vectors) +
 //                         Rayleigh-Ritz with a cyclic Jacobi on the 8x8 block.
@@ -175,6 +176,20 @@ __device__ inline double gram_real_entry(const double* __restrict__ partial, int
   double s = 0.0;
   for (int w = 0; w < nwg; ++w) s += partial[(long)w * NTILE * 256 + off];
   return s;
+}
+
+// First stage of the tile reduction: part2[c][e] = sum over the workgroups w
+// of chunk c of partial[w][e], e < len (len = tiles x 256), kGramChunks
+// chunks; the result has the partial layout with kGramChunks "workgroups".
+constexpr int kGramChunks = 16;
+__global__ void gram_sum_kernel(const double* __restrict__ partial, int nwg, long len, double* __restrict__ part2) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const int per = (nwg + kGramChunks - 1) / kGramChunks;
+  const int w0 = blockIdx.y * per, w1 = min(nwg, w0 + per);
+  double acc = 0.0;
+  for (int w = w0; w < w1; ++w) acc += partial[(long)w * len + e];
+  part2[(long)blockIdx.y * len + e] = acc;
 }
 
 __global__ void gram_reduce_kernel(const double* __restrict__ partial, int nwg, int NT, int R,
@@ -511,8 +526,9 @@ ls_status class_fit(StencilData& sd, int n, double k, hipStream_t s) {
   LS_HIP(hipMemsetAsync(sd.beta.p, 0, sd.beta.bytes, s));
   LS_HIP(hipMemsetAsync(sd.gram.p, 0, sd.gram.bytes, s));
   const int nwg_max = 512;
-  DevBuf partial;
+  DevBuf partial, part2;
   LS_TRY(partial.alloc((size_t)nwg_max * 66 * 256 * sizeof(double)));
+  LS_TRY(part2.alloc((size_t)kGramChunks * 66 * 256 * sizeof(double)));
   for (int kap = 0; kap < 27; ++kap) {
     const ClassGeom& g = geoms[kap];
     const long nchunks = (g.nbox + GJC - 1) / GJC;
@@ -530,8 +546,11 @@ ls_status class_fit(StencilData& sd, int n, double k, hipStream_t s) {
     // the per-workgroup count in the launch equals ceil(nchunks / nwg); every
     // workgroup index < nwg wrote its tiles
     const int R = Rs[kap];
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((R * R + 255) / 256), dim3(256), 0, s, partial.as<double>(), nwg,
-                       NT, R, sd.gram.as<C<double>>() + (long)kap * 81 * 81);
+    const long len = (long)NT * (NT + 1) / 2 * 256;
+    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)((len + 255) / 256), kGramChunks), dim3(256), 0, s,
+                       partial.as<double>(), nwg, len, part2.as<double>());
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((R * R + 255) / 256), dim3(256), 0, s, part2.as<double>(),
+                       kGramChunks, NT, R, sd.gram.as<C<double>>() + (long)kap * 81 * 81);
     LS_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(heev_low3_kernel, dim3(27), dim3(256), 0, s, sd.gram.as<C<double>>(), dR.as<int>(),

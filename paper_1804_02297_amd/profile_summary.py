@@ -14,8 +14,8 @@ import sys
 
 
 def short(name: str) -> str:
-    name = re.sub(r"\(.*$", "", name)
-    return name.replace("void ", "").replace("ls::", "").replace("(anonymous namespace)::", "")
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("ls::", "")
+    return re.sub(r"\(.*$", "", name)
 
 
 def trace(db: str) -> str:
