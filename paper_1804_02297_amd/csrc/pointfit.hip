@@ -17,8 +17,9 @@
 //   shell_h_kernel     : H_s for the 98 shell offsets, packed lower triangles
 //   shell_coef_kernel  : c[p][s] = w_s^2 - 1 for a batch of interior points
 //   gram_batch_kernel  : Gram_p = Gram_class + C H on FP64 MFMA (batch x 98 x 6642)
-//   heev_wave_kernel   : one wavefront per point: Cholesky in LDS, block inverse
-//                        iteration warm-started from the class Ritz vectors,
+//   heev_block_kernel  : one workgroup per point: Cholesky and triangular inverse
+//                        in LDS, block inverse iteration warm-started from the
+//                        class Ritz vectors as dense triangular products,
 //                        Rayleigh-Ritz with a lane-parallel 8x8 Jacobi
 //   point_beta_kernel  : beta_p = B^H alpha_p
 #include "common.h"
@@ -147,120 +148,184 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// One wavefront per point.  G: packed lower triangles [np][3321] complex.
-// X0: [81][8] warm start (class Ritz vectors).  Writes alpha [pts[p]][81][3].
-__global__ __launch_bounds__(64) void heev_wave_kernel(const C<double>* __restrict__ Gall, int np,
-                                                       const C<double>* __restrict__ X0, int iters,
-                                                       const int* __restrict__ pts, C<double>* __restrict__ alpha_out,
-                                                       double* __restrict__ eval_out) {
+// One workgroup of four wavefronts per point.  G: packed lower triangles
+// [np][3321] complex; X0: [81][8] warm start (class Ritz vectors).  Writes
+// alpha [pts[p]][81][3] and the three smallest Ritz values:
+//   1. Cholesky G + shift I = L L^H, right-looking, packed in LDS;
+//   2. W = L^-1 in place, eight rows per step;
+//   3. `iters` block inverse iterations X <- W^H (W X), each followed by
+//      modified Gram-Schmidt twice (wavefront 0);
+//   4. Rayleigh-Ritz with the unshifted G and an 8x8 cyclic Jacobi (wavefront 0).
+// The products of step 3 have no sequential dependency, so all four SIMDs of
+// the CU share them; only the factorisation and the 8x8 work are sequential.
+constexpr int HB = 256;           // threads per point
+constexpr int RBW = 8;            // rows per step of the triangular inverse
+__global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restrict__ Gall, int np,
+                                                        const C<double>* __restrict__ X0, int iters,
+                                                        const int* __restrict__ pts,
+                                                        C<double>* __restrict__ alpha_out,
+                                                        double* __restrict__ eval_out) {
+  // rows of X and Y padded to 9 entries: lanes that walk rows then hit
+  // distinct LDS banks (a 128-byte row stride puts them all on two)
   __shared__ C<double> L[NPK];
-  __shared__ C<double> X[R81][EBW];
-  __shared__ C<double> Yk[EBW];
+  __shared__ C<double> X[R81][EBW + 1];
+  __shared__ C<double> Y[R81][EBW + 1];
   __shared__ C<double> T[EBW][EBW];
   __shared__ C<double> V[EBW][EBW];
-  __shared__ double red[64];
+  __shared__ double red[R81];
   const int p = blockIdx.x;
-  if (p >= np) return;
-  const int l = threadIdx.x;
+  if (p >= np) return;                 // uniform over the workgroup
+  const int t = threadIdx.x;
   const C<double>* G = Gall + (long)p * NPK;
 
-  // load, shift, Cholesky
-  double tr = 0.0;
-  for (int i = l; i < R81; i += 64) tr += G[LI(i, i)].re;
-  red[l] = tr;
-  wsync();
+  if (t < R81) red[t] = G[LI(t, t)].re;
+  for (int e = t; e < NPK; e += HB) L[e] = G[e];
+  __syncthreads();
   double trace = 0.0;
-  for (int q = 0; q < 64; ++q) trace += red[q];
-  const double shift = 1e-15 * trace;
-  for (int e = l; e < NPK; e += 64) L[e] = G[e];
-  wsync();
-  if (l == 0)
-    for (int i = 0; i < R81; ++i) L[LI(i, i)].re += shift;
-  wsync();
+  for (int q = 0; q < R81; ++q) trace += red[q];
+  if (t < R81) L[LI(t, t)].re += 1e-15 * trace;
+  __syncthreads();
+
+  // 1. Cholesky.  Step kk updates the trailing triangle from the unscaled
+  // column kk (scaled by 1/d^2 on use), then scales the column; the next
+  // step reads neither column kk nor entries this step's scaling writes.
   for (int kk = 0; kk < R81; ++kk) {
-    if (l == 0) L[LI(kk, kk)] = cmk(sqrt(fmax(L[LI(kk, kk)].re, 1e-300)), 0.0);
-    wsync();
-    const double dinv = 1.0 / L[LI(kk, kk)].re;
-    for (int i = kk + 1 + l; i < R81; i += 64) L[LI(i, kk)] = cscale(L[LI(i, kk)], dinv);
-    wsync();
+    const double dkk = sqrt(fmax(L[LI(kk, kk)].re, 1e-300));
+    const double dinv = 1.0 / dkk;
+    const double d2 = dinv * dinv;
     const int m = R81 - kk - 1;
     const int tot = m * (m + 1) / 2;
-    for (int e = l; e < tot; e += 64) {
-      int ii = (int)((sqrt(8.0 * e + 1.0) - 1.0) / 2.0);
+    for (int e = t; e < tot; e += HB) {
+      int ii = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
       while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
       while (ii * (ii + 1) / 2 > e) --ii;
-      const int jj = e - ii * (ii + 1) / 2;
-      const int i = kk + 1 + ii, j = kk + 1 + jj;
-      L[LI(i, j)] = L[LI(i, j)] - L[LI(i, kk)] * cconj(L[LI(j, kk)]);
+      const int i = kk + 1 + ii, j = kk + 1 + (e - ii * (ii + 1) / 2);
+      L[LI(i, j)] = L[LI(i, j)] - cscale(L[LI(i, kk)] * cconj(L[LI(j, kk)]), d2);
     }
-    wsync();
+    __syncthreads();
+    for (int i = kk + 1 + t; i < R81; i += HB) L[LI(i, kk)] = cscale(L[LI(i, kk)], dinv);
+    if (t == 0) L[LI(kk, kk)] = cmk(dkk, 0.0);
   }
-  for (int e = l; e < R81 * EBW; e += 64) X[e / EBW][e % EBW] = X0[e];
-  wsync();
-  for (int it = 0; it < iters; ++it) {
-    for (int kk = 0; kk < R81; ++kk) {               // L Y = X
-      if (l < EBW) Yk[l] = cscale(X[kk][l], 1.0 / L[LI(kk, kk)].re);
-      wsync();
-      if (l < EBW) X[kk][l] = Yk[l];
-      for (int e = l; e < (R81 - kk - 1) * EBW; e += 64) {
-        const int i = kk + 1 + e / EBW, c = e % EBW;
-        X[i][c] = X[i][c] - L[LI(i, kk)] * Yk[c];
-      }
-      wsync();
+  __syncthreads();
+
+  // 2. W = L^-1 in place, rows [i0, i1) per step: (a) every thread forms
+  // partial sums acc[r][j] = sum_{j <= k < i0} L[i0+r][k] W[k][j] over the
+  // finished rows of W; (b) thread j runs the block rows in order; (c) the
+  // block rows of W replace those of L.  X holds acc, Y the new rows.
+  C<double>* accb = &X[0][0];                       // RBW x 81
+  C<double>* tmp = &Y[0][0];                        // RBW x 81
+  for (int i0 = 0; i0 < R81; i0 += RBW) {
+    const int i1 = min(R81, i0 + RBW);
+    for (int e = t; e < (i1 - i0) * R81; e += HB) {
+      const int r = e / R81, j = e % R81;
+      C<double> acc = cmk(0.0, 0.0);
+      for (int k = j; k < i0; ++k) acc = acc + L[LI(i0 + r, k)] * L[LI(k, j)];
+      accb[e] = acc;
     }
-    for (int kk = R81 - 1; kk >= 0; --kk) {          // L^H Z = Y
-      if (l < EBW) Yk[l] = cscale(X[kk][l], 1.0 / L[LI(kk, kk)].re);
-      wsync();
-      if (l < EBW) X[kk][l] = Yk[l];
-      for (int e = l; e < kk * EBW; e += 64) {
-        const int i = e / EBW, c = e % EBW;
-        X[i][c] = X[i][c] - cconj(L[LI(kk, i)]) * Yk[c];
-      }
-      wsync();
-    }
-    for (int pass = 0; pass < 2; ++pass)              // modified Gram-Schmidt, twice
-      for (int c = 0; c < EBW; ++c) {
-        double nr = 0.0;
-        for (int i = l; i < R81; i += 64) nr += X[i][c].re * X[i][c].re + X[i][c].im * X[i][c].im;
-        for (int o = 32; o > 0; o >>= 1) nr += __shfl_xor(nr, o);
-        const double sc = 1.0 / sqrt(nr);
-        for (int i = l; i < R81; i += 64) X[i][c] = cscale(X[i][c], sc);
-        wsync();
-        for (int d = c + 1; d < EBW; ++d) {
-          double pr = 0.0, pi = 0.0;
-          for (int i = l; i < R81; i += 64) {
-            const C<double> a = X[i][c], b = X[i][d];
-            pr += a.re * b.re + a.im * b.im;
-            pi += a.re * b.im - a.im * b.re;
+    __syncthreads();
+    if (t < i1) {
+      const int j = t;
+      C<double> wb[RBW];
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        const int i = i0 + r;
+        C<double> v = cmk(0.0, 0.0);
+        if (i < i1 && i >= j) {
+          const double lii = L[LI(i, i)].re;
+          if (i == j) {
+            v = cmk(1.0 / lii, 0.0);
+          } else {
+            C<double> sacc = (j < i0) ? accb[r * R81 + j] : cmk(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < r; ++q)
+              if (i0 + q >= j) sacc = sacc + L[LI(i, i0 + q)] * wb[q];
+            v = cscale(sacc, -1.0 / lii);
           }
-          for (int o = 32; o > 0; o >>= 1) {
-            pr += __shfl_xor(pr, o);
-            pi += __shfl_xor(pi, o);
-          }
-          const C<double> pc = cmk(pr, pi);
-          for (int i = l; i < R81; i += 64) X[i][d] = X[i][d] - X[i][c] * pc;
-          wsync();
         }
+        wb[r] = v;
+        if (i < i1) tmp[r * R81 + j] = v;
       }
-  }
-  // Rayleigh-Ritz with the unshifted G: GX (81 x 8) into the space of L, then
-  // T = X^H (G X), lane (pp, qq) of the 8x8
-  C<double>* GX = L;
-  for (int i = l; i < R81; i += 64) {
-    C<double> acc[EBW];
-    for (int q = 0; q < EBW; ++q) acc[q] = cmk(0.0, 0.0);
-    for (int j = 0; j < R81; ++j) {
-      const C<double> gij = (j <= i) ? G[LI(i, j)] : cconj(G[LI(j, i)]);
-      for (int q = 0; q < EBW; ++q) acc[q] = acc[q] + gij * X[j][q];
     }
-    for (int q = 0; q < EBW; ++q) GX[i * EBW + q] = acc[q];
+    __syncthreads();
+    for (int e = t; e < (i1 - i0) * R81; e += HB) {
+      const int i = i0 + e / R81, j = e % R81;
+      if (j <= i) L[LI(i, j)] = tmp[e];
+    }
+    __syncthreads();
   }
-  wsync();
+
+  // 3. block inverse iteration with (G + shift)^-1 = W^H W
+  for (int e = t; e < R81 * EBW; e += HB) X[e / EBW][e % EBW] = X0[e];
+  __syncthreads();
+  const int c = t & (EBW - 1), rg = t / EBW;      // column, row group (32 groups)
+  const int l = t;                                 // lane index inside wavefront 0
+  for (int it = 0; it < iters; ++it) {
+    for (int i = rg; i < R81; i += HB / EBW) {
+      C<double> acc = cmk(0.0, 0.0);
+      for (int k = 0; k <= i; ++k) acc = acc + L[LI(i, k)] * X[k][c];
+      Y[i][c] = acc;
+    }
+    __syncthreads();
+    for (int i = rg; i < R81; i += HB / EBW) {
+      C<double> acc = cmk(0.0, 0.0);
+      for (int k = i; k < R81; ++k) acc = acc + cconj(L[LI(k, i)]) * Y[k][c];
+      X[i][c] = acc;
+    }
+    __syncthreads();
+    // classical Gram-Schmidt with one reorthogonalisation, column by column,
+    // on all four wavefronts: thread (part, d) sums conj(X[i][d]) X[i][cc]
+    // over the rows i = part (mod 32), the partial sums meet in LDS
+    for (int cc = 0; cc < EBW; ++cc) {
+      for (int pass = 0; pass < 2 && cc > 0; ++pass) {
+        {
+          const int d = t % EBW, part = t / EBW;
+          C<double> h = cmk(0.0, 0.0);
+          if (d < cc)
+            for (int i = part; i < R81; i += HB / EBW) h = h + cconj(X[i][d]) * X[i][cc];
+          Y[part][d] = h;                                   // Y: 32 x 8 partial sums
+        }
+        __syncthreads();
+        if (t < cc) {
+          C<double> h = cmk(0.0, 0.0);
+          for (int part = 0; part < HB / EBW; ++part) h = h + Y[part][t];
+          T[0][t] = h;
+        }
+        __syncthreads();
+        if (t < R81) {
+          C<double> v = X[t][cc];
+          for (int d = 0; d < cc; ++d) v = v - X[t][d] * T[0][d];
+          X[t][cc] = v;
+        }
+        __syncthreads();
+      }
+      if (t < R81) red[t] = X[t][cc].re * X[t][cc].re + X[t][cc].im * X[t][cc].im;
+      __syncthreads();
+      double nr = 0.0;
+      for (int q = 0; q < R81; ++q) nr += red[q];
+      const double sc = 1.0 / sqrt(nr);
+      __syncthreads();                                      // red is reused next column
+      if (t < R81) X[t][cc] = cscale(X[t][cc], sc);
+      __syncthreads();
+    }
+  }
+
+  // 4. Rayleigh-Ritz with the unshifted G (reloaded into L): GX (81 x 8)
+  // into Y, T = X^H (G X)
+  for (int e = t; e < NPK; e += HB) L[e] = G[e];
+  __syncthreads();
+  for (int i = rg; i < R81; i += HB / EBW) {
+    C<double> acc = cmk(0.0, 0.0);
+    for (int j = 0; j <= i; ++j) acc = acc + L[LI(i, j)] * X[j][c];
+    for (int j = i + 1; j < R81; ++j) acc = acc + cconj(L[LI(j, i)]) * X[j][c];
+    Y[i][c] = acc;
+  }
+  __syncthreads();
+  if (t >= 64) return;                              // the 8x8 work is one wavefront's
   {
     const int pp = l / EBW, qq = l % EBW;
-    C<double> s = cmk(0.0, 0.0);
-    for (int i = 0; i < R81; ++i) s = s + cconj(X[i][pp]) * GX[i * EBW + qq];
-    T[pp][qq] = s;
+    C<double> sacc = cmk(0.0, 0.0);
+    for (int i = 0; i < R81; ++i) sacc = sacc + cconj(X[i][pp]) * Y[i][qq];
+    T[pp][qq] = sacc;
     V[pp][qq] = cmk(pp == qq ? 1.0 : 0.0, 0.0);
   }
   wsync();
@@ -273,6 +338,20 @@ __global__ __launch_bounds__(64) void heev_wave_kernel(const C<double>* __restri
   }
   // cyclic Jacobi, one rotation at a time, every lane owns one entry (i, j)
   for (int sweep = 0; sweep < 12; ++sweep) {
+    {
+      // converged: off-diagonal mass below 1e-30 of the diagonal's (uniform)
+      const int i = l / EBW, j = l % EBW;
+      double off = (i < j) ? T[i][j].re * T[i][j].re + T[i][j].im * T[i][j].im : 0.0;
+      double dia = (i == j) ? T[i][i].re * T[i][i].re : 0.0;
+      for (int o = 32; o > 0; o >>= 1) {
+        off += __shfl_xor(off, o);
+        dia += __shfl_xor(dia, o);
+      }
+      // lanes may round the butterfly sums differently: decide on lane 0's
+      off = __shfl(off, 0);
+      dia = __shfl(dia, 0);
+      if (off <= 1e-30 * dia) break;
+    }
     for (int p1 = 0; p1 < EBW; ++p1)
       for (int q1 = p1 + 1; q1 < EBW; ++q1) {
         const C<double> apq = T[p1][q1];
@@ -450,7 +529,7 @@ ls_status point_fit(StencilData& sd, int n, double k, const C<double>* m, double
     hipLaunchKernelGGL(gram_batch_kernel, dim3(NCOL / 256, (cnt + 15) / 16), dim3(256), 0, s, coef.as<double>(),
                        Hr.as<double>(), Gcls.as<double>(), cnt, Gb.as<double>());
     LS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(heev_wave_kernel, dim3(cnt), dim3(64), 0, s, Gb.as<C<double>>(), cnt, X0, iters, dp,
+    hipLaunchKernelGGL(heev_block_kernel, dim3(cnt), dim3(HB), 0, s, Gb.as<C<double>>(), cnt, X0, iters, dp,
                        sd.palpha.as<C<double>>(), sd.peval.as<double>());
     LS_HIP(hipGetLastError());
     hipLaunchKernelGGL(point_beta_kernel, dim3(nb((long)cnt * 243, 256)), dim3(256), 0, s, Bint.as<C<double>>(), dp,
@@ -509,7 +588,7 @@ ls_status pointfit_grams(PointFitCtx& ctx, const C<double>* m, double m0, const 
 // exact per-point stencils for cnt points whose Grams are in ctx.Gb
 ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s) {
   const C<double>* X0 = sd.ritz8.as<C<double>>() + 13L * R81 * EBW;
-  hipLaunchKernelGGL(heev_wave_kernel, dim3(cnt), dim3(64), 0, s, ctx.Gb.as<C<double>>(), cnt, X0, iters, dpts,
+  hipLaunchKernelGGL(heev_block_kernel, dim3(cnt), dim3(HB), 0, s, ctx.Gb.as<C<double>>(), cnt, X0, iters, dpts,
                      sd.palpha.as<C<double>>(), sd.peval.as<double>());
   LS_HIP(hipGetLastError());
   return LS_OK;
