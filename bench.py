@@ -100,11 +100,12 @@ def cpu_baseline(n: int, seconds: float = 15.0):
 def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500):
     """Per-rhs time to a 1e-8 relative residual: plain FP64 against the chosen form.
 
-    Plain: class stencils (the paper's 27 fits), FP64 apply, one rhs at a time.
-    Chosen: learned per-point stencils (network trained here on exact
-    per-point fits of other seeded media, exact fit where it is not accepted),
-    FP32 apply inside the FP64 outer FGMRES, ndirs Fibonacci directions x 2
-    polarisations solved as one block with the autotuned apply.  Set-up
+    Plain: class stencils (the paper's 27 fits), complex128 factor, FP64
+    apply, one rhs at a time.  Chosen: learned per-point stencils (network
+    trained here on exact per-point fits of other seeded media, exact fit
+    where it is not accepted), complex64 factor, FP32 apply inside the FP64
+    outer FGMRES, ndirs Fibonacci directions x 2 polarisations solved as one
+    block with the autotuned apply.  Set-up
     (training, fits, host factorisations) is timed apart.
     """
     import numpy as np
@@ -122,6 +123,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
         pt.close()
     torch.cuda.synchronize()
     t_samples = time.perf_counter() - t0
+    _progress(f"training samples: {t_samples:.1f} s")
     t0 = time.perf_counter()
     loss = net.train(train_steps, batch=1024, lr=1e-3, seed=0)
     t_train = time.perf_counter() - t0
@@ -146,14 +148,19 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
     # --- plain FP64 path: class stencils, one rhs
     t_fit_cls, _ = timed(lambda: plan.stencil_fit(0))
     t_fac_cls, _ = timed(plan.factor)
+    _progress(f"complex128 factor: {t_fac_cls:.1f} s")
     run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
     t_plain, (x1, inf1, st1) = run(g[:1], "c128")
+    _progress(f"plain FP64 solve: {t_plain:.3f} s")
     # --- chosen path: exact per-point fit (for its time), then the learned fit
     t_fit_pt, _ = timed(lambda: plan.stencil_fit(1))
     t_fit_lrn, nfb = timed(lambda: plan.stencil_fit_learned(net))
-    t_fac_lrn, _ = timed(plan.factor)
+    _progress(f"learned fit: {nfb} of {len(interior)} points fell back")
+    t_fac_lrn, _ = timed(lambda: plan.factor("c64"))              # complex64 preconditioner factor
+    _progress(f"complex64 factor: {t_fac_lrn:.1f} s")
     tune = plan.tune(nb, "mixed")                         # launch choice of the batched apply
     t_mixed, (xb, infb, stb) = run(g, "mixed")
+    _progress(f"block mixed solve of {nb}: {t_mixed:.3f} s")
     # residuals re-measured with the FP64 apply: r = g - A x
     r = torch.empty_like(g)
     plan.apply(xb, r, prec="c128")
@@ -176,9 +183,13 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
                     "train_loss_first_last": [round(float(loss[0]), 4), round(float(np.mean(loss[-20:])), 4)],
                     "class_fit": round(t_fit_cls, 3), "point_fit_exact": round(t_fit_pt, 3),
                     "learned_fit": round(t_fit_lrn, 3),
-                    "factor_class": round(t_fac_cls, 3), "factor_learned": round(t_fac_lrn, 3)},
+                    "factor_class_c128": round(t_fac_cls, 3), "factor_learned_c64": round(t_fac_lrn, 3)},
         "tuned_apply": {k2: tune[k2] for k2 in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
     }
+
+
+def _progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _init_params(seed: int):

@@ -177,6 +177,13 @@ ls_status ls_get_rows(const ls_plan* plan, void* rows_host);
  * NULL.  LS_ESTATE before ls_stencil_fit. */
 ls_status ls_factor(ls_plan* plan, double* seconds_out);
 
+/* ls_factor with the factor's precision: LS_C128 keeps it in complex128
+ * (what ls_factor does); LS_C64 (or LS_MIXED, the same) in complex64, half the
+ * host memory and about twice as fast to factor and to solve.  A complex64
+ * factor is an inexact S^-1; the flexible GMRES still reaches its tolerance
+ * on the FP64 residual, possibly with more iterations.  Errors as ls_factor. */
+ls_status ls_factor_prec(ls_plan* plan, ls_prec factor_prec, double* seconds_out);
+
 /* Preconditioner z = S^-1 (Q v): Q v on the GPU, S^-1 on the host.
  * v, z: device [nrhs][3][n][n][n] complex128 (may alias).  Synchronises.
  * LS_ESTATE before ls_factor. */
@@ -249,8 +256,10 @@ ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out
 /* ---- the host sparse solver on its own (host memory, no GPU) -------------- */
 typedef struct ls_sparse ls_sparse;
 
-/* Factor rows given in the ls_get_rows layout on an n^3 grid. */
-ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_sparse** out);
+/* Factor rows given in the ls_get_rows layout on an n^3 grid; factor_prec as
+ * in ls_factor_prec (solves take and return complex128 either way). */
+ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_prec factor_prec,
+                                ls_sparse** out);
 /* Solve S x = b in place, b host [nrhs][3][n][n][n] complex128. */
 ls_status ls_sparse_solve_host(ls_sparse* sp, void* b_host, int nrhs);
 /* Factor size in bytes and factorisation flop count. */

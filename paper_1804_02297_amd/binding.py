@@ -45,6 +45,7 @@ SIGNATURES = [
     ("ls_get_point_stencils", _I, [_VP, _VP, _VP]),
     ("ls_get_rows", _I, [_VP, _VP]),
     ("ls_factor", _I, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("ls_factor_prec", _I, [_VP, _I, ctypes.POINTER(ctypes.c_double)]),
     ("ls_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
     ("ls_mlp_create", _I, [_VP, ctypes.POINTER(_VP)]),
@@ -59,7 +60,7 @@ SIGNATURES = [
     ("ls_mlp_load", _I, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
     ("ls_mlp_destroy", None, [_VP]),
     ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
-    ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
     ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
     ("ls_sparse_destroy", None, [_VP]),
@@ -88,7 +89,7 @@ class SolveInfo(ctypes.Structure):
 class SparseHost:
     """The host multifrontal solver on its own (host memory only, no GPU needed)."""
 
-    def __init__(self, n: int, rows, host_mem_cap: int = 0):
+    def __init__(self, n: int, rows, host_mem_cap: int = 0, prec: str = "c128"):
         import numpy as np
         lib = load()
         rows = np.ascontiguousarray(rows, dtype=np.complex128)
@@ -96,7 +97,7 @@ class SparseHost:
             raise ValueError("rows must have shape (n^3, 3, 27, 3)")
         self.n = n
         h = ctypes.c_void_p()
-        _check(lib.ls_sparse_factor_host(n, rows.ctypes.data_as(ctypes.c_void_p), host_mem_cap,
+        _check(lib.ls_sparse_factor_host(n, rows.ctypes.data_as(ctypes.c_void_p), host_mem_cap, PREC[prec],
                                          ctypes.byref(h)), "ls_sparse_factor_host")
         self._h = h
 
@@ -359,10 +360,10 @@ class Plan:
         _check(_lib.ls_get_rows(self._h, r.ctypes.data_as(ctypes.c_void_p)), "ls_get_rows")
         return r
 
-    def factor(self):
-        """Host multifrontal LU of S; returns seconds."""
+    def factor(self, prec: str = "c128"):
+        """Host multifrontal LU of S (complex128 or complex64 factor); returns seconds."""
         t = ctypes.c_double()
-        _check(_lib.ls_factor(self._h, ctypes.byref(t)), "ls_factor")
+        _check(_lib.ls_factor_prec(self._h, PREC[prec], ctypes.byref(t)), "ls_factor_prec")
         return t.value
 
     def precond(self, v, z=None):

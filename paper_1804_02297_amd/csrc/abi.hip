@@ -195,15 +195,18 @@ ls_status ls_get_rows(const ls_plan* plan, void* rows_host) {
   return LS_OK;
 }
 
-ls_status ls_factor(ls_plan* plan, double* seconds_out) {
+ls_status ls_factor(ls_plan* plan, double* seconds_out) { return ls_factor_prec(plan, LS_C128, seconds_out); }
+
+ls_status ls_factor_prec(ls_plan* plan, ls_prec factor_prec, double* seconds_out) {
   if (!plan) return LS_EINVAL;
+  if (factor_prec != LS_C128 && factor_prec != LS_C64 && factor_prec != LS_MIXED) return LS_EINVAL;
   if (!plan->sd.have_rows) return LS_ESTATE;
   const double t0 = now_s();
   std::vector<std::complex<double>> rows(plan->sd.rows.bytes / sizeof(std::complex<double>));
   LS_HIP(hipMemcpy(rows.data(), plan->sd.rows.p, plan->sd.rows.bytes, hipMemcpyDeviceToHost));
   host_free(plan->hs);
   plan->hs = nullptr;
-  LS_TRY(host_factor(plan->ap.n, rows.data(), plan->host_mem_cap, &plan->hs));
+  LS_TRY(host_factor(plan->ap.n, rows.data(), plan->host_mem_cap, factor_prec != LS_C128, &plan->hs));
   if (seconds_out) *seconds_out = now_s() - t0;
   return LS_OK;
 }
@@ -411,12 +414,15 @@ ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out
   return LS_OK;
 }
 
-ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_sparse** out) {
+ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_cap, ls_prec factor_prec,
+                                ls_sparse** out) {
   if (n < 1 || !rows_host || !out) return LS_EINVAL;
+  if (factor_prec != LS_C128 && factor_prec != LS_C64 && factor_prec != LS_MIXED) return LS_EINVAL;
   *out = nullptr;
   ls_sparse* sp = new (std::nothrow) ls_sparse();
   if (!sp) return LS_ENOMEM;
-  ls_status st = host_factor(n, static_cast<const std::complex<double>*>(rows_host), host_mem_cap, &sp->hs);
+  ls_status st = host_factor(n, static_cast<const std::complex<double>*>(rows_host), host_mem_cap,
+                             factor_prec != LS_C128, &sp->hs);
   if (st != LS_OK) {
     delete sp;
     return st;

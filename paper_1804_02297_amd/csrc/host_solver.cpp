@@ -14,6 +14,10 @@
 // with real and imaginary parts stored apart (vectorises on AVX2/AVX-512);
 // the subtree recursion and the Schur-complement updates of large fronts
 // run as OpenMP tasks.
+//
+// The factor is kept in FP64 or FP32 (R = double / float).  An FP32 factor
+// is a preconditioner for the FP64 flexible GMRES: half the memory and twice
+// the SIMD width for the factorisation and every solve.
 #include "host_solver.h"
 
 #include <omp.h>
@@ -22,8 +26,20 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <vector>
+
+#if defined(__x86_64__)
+#include <xmmintrin.h>
+#endif
+
+#if defined(__x86_64__)
+#define LS_CLONES __attribute__((target_clones("avx512f", "avx2", "default")))
+#else
+#define LS_CLONES
+#endif
+#define LS_INLINE __attribute__((always_inline)) inline
 
 namespace ls {
 
@@ -32,16 +48,33 @@ namespace {
 constexpr int kLeafPoints = 64;
 constexpr int kNB = 32;         // panel width of the blocked partial LU
 
-struct Node {
+// geometry of one node of the dissection tree (shared by both precisions)
+struct Geom {
   int lo[3], hi[3];
   int child[2] = {-1, -1};
   std::vector<int> piv, bnd;    // sorted global point indices
   int np = 0, nb = 0;
-  std::vector<double> l11r, l11i;   // np x np: L (unit, below) and U (on and above)
-  std::vector<double> u12r, u12i;   // np x nb
-  std::vector<double> l21r, l21i;   // nb x np
-  std::vector<int> ipiv;            // np
-  std::vector<double> updr, updi;   // nb x nb update matrix, freed once the parent took it
+};
+
+// numeric data of one node
+template <typename R>
+struct Vals {
+  std::vector<R> l11r, l11i;    // np x np: L (unit, below) and U (on and above)
+  std::vector<R> u12r, u12i;    // np x nb
+  std::vector<R> l21r, l21i;    // nb x np
+  std::vector<int> ipiv;        // np
+  std::vector<R> updr, updi;    // nb x nb update matrix, freed once the parent took it
+};
+
+// Subnormal inputs and results (fill-in decays below FP32's normal range)
+// take a slow path on x86; every thread of the factor and solve regions runs
+// with flush-to-zero and denormals-are-zero and restores its own mode after.
+struct FlushDenormals {
+#if defined(__x86_64__)
+  unsigned saved;
+  FlushDenormals() : saved(_mm_getcsr()) { _mm_setcsr(saved | 0x8040u); }
+  ~FlushDenormals() { _mm_setcsr(saved); }
+#endif
 };
 
 inline int pos_in(const std::vector<int>& v, int p) {
@@ -49,34 +82,42 @@ inline int pos_in(const std::vector<int>& v, int p) {
   return (it != v.end() && *it == p) ? int(it - v.begin()) : -1;
 }
 
+// local front index of global point p (pivot first, then boundary), or -1
+inline int front_pos(const Geom& nd, int p) {
+  int k = pos_in(nd.piv, p);
+  if (k >= 0) return k;
+  k = pos_in(nd.bnd, p);
+  return k >= 0 ? (int)nd.piv.size() + k : -1;
+}
+
+// ---- kernels: one template body, multiversioned per real type -------------------
+
 // C[i][j] -= sum_k A[i][k] B[k][j] over rows [r0, r1), cols [c0, c1), k in [k0, k1)
 // of one row-major planar matrix (lda = nf).  Four rows at a time share B loads.
-#if defined(__x86_64__)
-__attribute__((target_clones("avx512f", "avx2", "default")))
-#endif
-void gemm_rows(double* __restrict__ Fr, double* __restrict__ Fi, long nf, long r0, long r1, long c0, long c1,
-               long k0, long k1) {
+template <typename R>
+LS_INLINE void gemm_rows_t(R* __restrict__ Fr, R* __restrict__ Fi, long nf, long r0, long r1, long c0, long c1,
+                           long k0, long k1) {
   constexpr long JB = 256;
   for (long jb = c0; jb < c1; jb += JB) {
     const long je = std::min(c1, jb + JB);
     long i = r0;
     for (; i + 4 <= r1; i += 4) {
-      double* c0r = Fr + i * nf;
-      double* c0i = Fi + i * nf;
-      double* c1r = c0r + nf;
-      double* c1i = c0i + nf;
-      double* c2r = c1r + nf;
-      double* c2i = c1i + nf;
-      double* c3r = c2r + nf;
-      double* c3i = c2i + nf;
+      R* c0r = Fr + i * nf;
+      R* c0i = Fi + i * nf;
+      R* c1r = c0r + nf;
+      R* c1i = c0i + nf;
+      R* c2r = c1r + nf;
+      R* c2i = c1i + nf;
+      R* c3r = c2r + nf;
+      R* c3i = c2i + nf;
       for (long k = k0; k < k1; ++k) {
-        const double a0r = c0r[k], a0i = c0i[k], a1r = c1r[k], a1i = c1i[k];
-        const double a2r = c2r[k], a2i = c2i[k], a3r = c3r[k], a3i = c3i[k];
-        const double* br = Fr + k * nf;
-        const double* bi = Fi + k * nf;
+        const R a0r = c0r[k], a0i = c0i[k], a1r = c1r[k], a1i = c1i[k];
+        const R a2r = c2r[k], a2i = c2i[k], a3r = c3r[k], a3i = c3i[k];
+        const R* br = Fr + k * nf;
+        const R* bi = Fi + k * nf;
 #pragma omp simd
         for (long j = jb; j < je; ++j) {
-          const double xr = br[j], xi = bi[j];
+          const R xr = br[j], xi = bi[j];
           c0r[j] -= a0r * xr - a0i * xi;
           c0i[j] -= a0r * xi + a0i * xr;
           c1r[j] -= a1r * xr - a1i * xi;
@@ -89,12 +130,12 @@ void gemm_rows(double* __restrict__ Fr, double* __restrict__ Fi, long nf, long r
       }
     }
     for (; i < r1; ++i) {
-      double* cr = Fr + i * nf;
-      double* ci = Fi + i * nf;
+      R* cr = Fr + i * nf;
+      R* ci = Fi + i * nf;
       for (long k = k0; k < k1; ++k) {
-        const double ar = cr[k], ai = ci[k];
-        const double* br = Fr + k * nf;
-        const double* bi = Fi + k * nf;
+        const R ar = cr[k], ai = ci[k];
+        const R* br = Fr + k * nf;
+        const R* bi = Fi + k * nf;
 #pragma omp simd
         for (long j = jb; j < je; ++j) {
           cr[j] -= ar * br[j] - ai * bi[j];
@@ -104,18 +145,221 @@ void gemm_rows(double* __restrict__ Fr, double* __restrict__ Fi, long nf, long r
     }
   }
 }
+LS_CLONES void gemm_rows_d(double* Fr, double* Fi, long nf, long r0, long r1, long c0, long c1, long k0, long k1) {
+  gemm_rows_t<double>(Fr, Fi, nf, r0, r1, c0, c1, k0, k1);
+}
+LS_CLONES void gemm_rows_f(float* Fr, float* Fi, long nf, long r0, long r1, long c0, long c1, long k0, long k1) {
+  gemm_rows_t<float>(Fr, Fi, nf, r0, r1, c0, c1, k0, k1);
+}
+inline void gemm_rows(double* Fr, double* Fi, long nf, long r0, long r1, long c0, long c1, long k0, long k1) {
+  gemm_rows_d(Fr, Fi, nf, r0, r1, c0, c1, k0, k1);
+}
+inline void gemm_rows(float* Fr, float* Fi, long nf, long r0, long r1, long c0, long c1, long k0, long k1) {
+  gemm_rows_f(Fr, Fi, nf, r0, r1, c0, c1, k0, k1);
+}
+
+// sum_k (ar + i ai)[k] (xr + i xi)[k]
+template <typename R>
+LS_INLINE void cdot_t(const R* __restrict__ ar, const R* __restrict__ ai, const R* __restrict__ xr,
+                      const R* __restrict__ xi, long len, R* outr, R* outi) {
+  R sr = 0, si = 0;
+#pragma omp simd reduction(+ : sr, si)
+  for (long k = 0; k < len; ++k) {
+    sr += ar[k] * xr[k] - ai[k] * xi[k];
+    si += ar[k] * xi[k] + ai[k] * xr[k];
+  }
+  *outr = sr;
+  *outi = si;
+}
+LS_CLONES void cdot_d(const double* ar, const double* ai, const double* xr, const double* xi, long len,
+                      double* outr, double* outi) {
+  cdot_t<double>(ar, ai, xr, xi, len, outr, outi);
+}
+LS_CLONES void cdot_f(const float* ar, const float* ai, const float* xr, const float* xi, long len, float* outr,
+                      float* outi) {
+  cdot_t<float>(ar, ai, xr, xi, len, outr, outi);
+}
+inline void cdot(const double* ar, const double* ai, const double* xr, const double* xi, long len, double* outr,
+                 double* outi) {
+  cdot_d(ar, ai, xr, xi, len, outr, outi);
+}
+inline void cdot(const float* ar, const float* ai, const float* xr, const float* xi, long len, float* outr,
+                 float* outi) {
+  cdot_f(ar, ai, xr, xi, len, outr, outi);
+}
+
+// ---- many right-hand sides: block vectors [dof][ldx], ldx a multiple of 4 -------
+// With the right-hand sides interleaved (entry (k, r) at k ldx + r), a factor
+// entry is broadcast against a short vector of right-hand sides, so each
+// factor row is streamed once per 16 right-hand sides and the arithmetic
+// vectorises over r.
+
+// Y[a][r] -= sum_k A[a][k] X[k][r] for MR rows a, RB right-hand sides r.
+template <typename R, int MR, int RB>
+LS_INLINE void mk_sub(const R* __restrict__ Ar, const R* __restrict__ Ai, long lda, long K,
+                      const R* __restrict__ Xr, const R* __restrict__ Xi, long ldx, R* __restrict__ Yr,
+                      R* __restrict__ Yi) {
+  R cr[MR][RB], ci[MR][RB];
+  for (int a = 0; a < MR; ++a)
+    for (int r = 0; r < RB; ++r) cr[a][r] = ci[a][r] = 0;
+  for (long k = 0; k < K; ++k) {
+    const R* xr = Xr + k * ldx;
+    const R* xi = Xi + k * ldx;
+    for (int a = 0; a < MR; ++a) {
+      const R ar = Ar[a * lda + k], ai = Ai[a * lda + k];
+#pragma omp simd
+      for (int r = 0; r < RB; ++r) {
+        cr[a][r] += ar * xr[r] - ai * xi[r];
+        ci[a][r] += ar * xi[r] + ai * xr[r];
+      }
+    }
+  }
+  for (int a = 0; a < MR; ++a)
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      Yr[a * ldx + r] -= cr[a][r];
+      Yi[a * ldx + r] -= ci[a][r];
+    }
+}
+
+// rows [i0, i1) of Y -= A X; A row-major (lda), K columns; X, Y block vectors
+template <typename R>
+LS_INLINE void gemm_sub_rows_t(const R* Ar, const R* Ai, long lda, long i0, long i1, long K, const R* Xr,
+                               const R* Xi, long ldx, R* Yr, R* Yi) {
+  long i = i0;
+  for (; i + 4 <= i1; i += 4)
+    for (long r0 = 0; r0 < ldx;) {
+      if (ldx - r0 >= 16) {
+        mk_sub<R, 4, 16>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
+                         Yi + i * ldx + r0);
+        r0 += 16;
+      } else if (ldx - r0 >= 8) {
+        mk_sub<R, 4, 8>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
+                        Yi + i * ldx + r0);
+        r0 += 8;
+      } else {
+        mk_sub<R, 4, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
+                        Yi + i * ldx + r0);
+        r0 += 4;
+      }
+    }
+  for (; i < i1; ++i)
+    for (long r0 = 0; r0 < ldx; r0 += 4)
+      mk_sub<R, 1, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
+                      Yi + i * ldx + r0);
+}
+LS_CLONES void gemm_sub_rows_d(const double* Ar, const double* Ai, long lda, long i0, long i1, long K,
+                               const double* Xr, const double* Xi, long ldx, double* Yr, double* Yi) {
+  gemm_sub_rows_t<double>(Ar, Ai, lda, i0, i1, K, Xr, Xi, ldx, Yr, Yi);
+}
+LS_CLONES void gemm_sub_rows_f(const float* Ar, const float* Ai, long lda, long i0, long i1, long K, const float* Xr,
+                               const float* Xi, long ldx, float* Yr, float* Yi) {
+  gemm_sub_rows_t<float>(Ar, Ai, lda, i0, i1, K, Xr, Xi, ldx, Yr, Yi);
+}
+inline void gemm_sub_rows(const double* Ar, const double* Ai, long lda, long i0, long i1, long K, const double* Xr,
+                          const double* Xi, long ldx, double* Yr, double* Yi) {
+  gemm_sub_rows_d(Ar, Ai, lda, i0, i1, K, Xr, Xi, ldx, Yr, Yi);
+}
+inline void gemm_sub_rows(const float* Ar, const float* Ai, long lda, long i0, long i1, long K, const float* Xr,
+                          const float* Xi, long ldx, float* Yr, float* Yi) {
+  gemm_sub_rows_f(Ar, Ai, lda, i0, i1, K, Xr, Xi, ldx, Yr, Yi);
+}
+
+// W[i][r] -= L[i][k] W[k][r] for k in [b0, i), i in [b0, b1)  (within a diagonal block)
+template <typename R>
+LS_INLINE void lower_block_multi_t(const R* __restrict__ Lr, const R* __restrict__ Li, long np, long b0, long b1,
+                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+  for (long i = b0; i < b1; ++i) {
+    R* yr = Wr + i * ldx;
+    R* yi = Wi + i * ldx;
+    for (long k = b0; k < i; ++k) {
+      const R ar = Lr[i * np + k], ai = Li[i * np + k];
+      const R* xr = Wr + k * ldx;
+      const R* xi = Wi + k * ldx;
+#pragma omp simd
+      for (long r = 0; r < ldx; ++r) {
+        yr[r] -= ar * xr[r] - ai * xi[r];
+        yi[r] -= ar * xi[r] + ai * xr[r];
+      }
+    }
+  }
+}
+LS_CLONES void lower_block_multi_d(const double* Lr, const double* Li, long np, long b0, long b1, double* Wr,
+                                   double* Wi, long ldx) {
+  lower_block_multi_t<double>(Lr, Li, np, b0, b1, Wr, Wi, ldx);
+}
+LS_CLONES void lower_block_multi_f(const float* Lr, const float* Li, long np, long b0, long b1, float* Wr, float* Wi,
+                                   long ldx) {
+  lower_block_multi_t<float>(Lr, Li, np, b0, b1, Wr, Wi, ldx);
+}
+inline void lower_block_multi(const double* Lr, const double* Li, long np, long b0, long b1, double* Wr, double* Wi,
+                              long ldx) {
+  lower_block_multi_d(Lr, Li, np, b0, b1, Wr, Wi, ldx);
+}
+inline void lower_block_multi(const float* Lr, const float* Li, long np, long b0, long b1, float* Wr, float* Wi,
+                              long ldx) {
+  lower_block_multi_f(Lr, Li, np, b0, b1, Wr, Wi, ldx);
+}
+
+// W[i][r] = (W[i][r] - sum_{k in (i, b1)} U[i][k] W[k][r]) / U[i][i], i from b1-1 down to b0
+template <typename R>
+LS_INLINE void upper_block_multi_t(const R* __restrict__ Ur, const R* __restrict__ Ui, long np, long b0, long b1,
+                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+  for (long i = b1 - 1; i >= b0; --i) {
+    R* yr = Wr + i * ldx;
+    R* yi = Wi + i * ldx;
+    for (long k = i + 1; k < b1; ++k) {
+      const R ar = Ur[i * np + k], ai = Ui[i * np + k];
+      const R* xr = Wr + k * ldx;
+      const R* xi = Wi + k * ldx;
+#pragma omp simd
+      for (long r = 0; r < ldx; ++r) {
+        yr[r] -= ar * xr[r] - ai * xi[r];
+        yi[r] -= ar * xi[r] + ai * xr[r];
+      }
+    }
+    const R ur = Ur[i * np + i], ui = Ui[i * np + i];
+    const R den = ur * ur + ui * ui;
+    const R qr = ur / den, qi = -ui / den;      // 1 / u
+#pragma omp simd
+    for (long r = 0; r < ldx; ++r) {
+      const R vr = yr[r], vi = yi[r];
+      yr[r] = vr * qr - vi * qi;
+      yi[r] = vr * qi + vi * qr;
+    }
+  }
+}
+LS_CLONES void upper_block_multi_d(const double* Ur, const double* Ui, long np, long b0, long b1, double* Wr,
+                                   double* Wi, long ldx) {
+  upper_block_multi_t<double>(Ur, Ui, np, b0, b1, Wr, Wi, ldx);
+}
+LS_CLONES void upper_block_multi_f(const float* Ur, const float* Ui, long np, long b0, long b1, float* Wr, float* Wi,
+                                   long ldx) {
+  upper_block_multi_t<float>(Ur, Ui, np, b0, b1, Wr, Wi, ldx);
+}
+inline void upper_block_multi(const double* Ur, const double* Ui, long np, long b0, long b1, double* Wr, double* Wi,
+                              long ldx) {
+  upper_block_multi_d(Ur, Ui, np, b0, b1, Wr, Wi, ldx);
+}
+inline void upper_block_multi(const float* Ur, const float* Ui, long np, long b0, long b1, float* Wr, float* Wi,
+                              long ldx) {
+  upper_block_multi_f(Ur, Ui, np, b0, b1, Wr, Wi, ldx);
+}
+
+// ---- factorisation -----------------------------------------------------------------
 
 // Partial LU of the nf x nf front: eliminate the first np pivots, choosing
 // each pivot by magnitude among the remaining pivot rows; the trailing
 // (nf-np) x (nf-np) block becomes the Schur complement.
-void partial_lu(double* Fr, double* Fi, long nf, long np, int* ipiv, double* flops) {
+template <typename R>
+void partial_lu(R* Fr, R* Fi, long nf, long np, int* ipiv, double* flops) {
   for (long kb = 0; kb < np; kb += kNB) {
     const long ke = std::min(np, kb + kNB);
     for (long k = kb; k < ke; ++k) {
       long p = k;
-      double best = -1.0;
+      R best = -1;
       for (long i = k; i < np; ++i) {
-        const double v = Fr[i * nf + k] * Fr[i * nf + k] + Fi[i * nf + k] * Fi[i * nf + k];
+        const R v = Fr[i * nf + k] * Fr[i * nf + k] + Fi[i * nf + k] * Fi[i * nf + k];
         if (v > best) {
           best = v;
           p = i;
@@ -126,24 +370,24 @@ void partial_lu(double* Fr, double* Fi, long nf, long np, int* ipiv, double* flo
         std::swap_ranges(Fr + k * nf, Fr + (k + 1) * nf, Fr + p * nf);
         std::swap_ranges(Fi + k * nf, Fi + (k + 1) * nf, Fi + p * nf);
       }
-      double pr = Fr[k * nf + k], pi = Fi[k * nf + k];
-      double den = pr * pr + pi * pi;
-      if (den == 0.0) {   // exactly singular pivot block: perturb (FGMRES absorbs it)
-        pr = 1e-300;
-        pi = 0.0;
+      R pr = Fr[k * nf + k], pi = Fi[k * nf + k];
+      R den = pr * pr + pi * pi;
+      if (den == 0) {   // exactly singular pivot block: perturb (FGMRES absorbs it)
+        pr = std::sqrt(std::numeric_limits<R>::min());
+        pi = 0;
         Fr[k * nf + k] = pr;
         den = pr * pr;
       }
-      const double ir = pr / den, ii = -pi / den;
+      const R ir = pr / den, ii = -pi / den;
       for (long i = k + 1; i < nf; ++i) {
-        const double xr = Fr[i * nf + k], xi = Fi[i * nf + k];
-        const double lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+        const R xr = Fr[i * nf + k], xi = Fi[i * nf + k];
+        const R lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
         Fr[i * nf + k] = lr;
         Fi[i * nf + k] = li;
-        double* rr = Fr + i * nf;
-        double* ri = Fi + i * nf;
-        const double* kr = Fr + k * nf;
-        const double* ki = Fi + k * nf;
+        R* rr = Fr + i * nf;
+        R* ri = Fi + i * nf;
+        const R* kr = Fr + k * nf;
+        const R* ki = Fi + k * nf;
         for (long j = k + 1; j < ke; ++j) {
           rr[j] -= lr * kr[j] - li * ki[j];
           ri[j] -= lr * ki[j] + li * kr[j];
@@ -153,11 +397,11 @@ void partial_lu(double* Fr, double* Fi, long nf, long np, int* ipiv, double* flo
     // block row: unit-lower solve for columns [ke, nf) of rows [kb, ke)
     for (long k = kb; k < ke; ++k)
       for (long i = k + 1; i < ke; ++i) {
-        const double lr = Fr[i * nf + k], li = Fi[i * nf + k];
-        double* rr = Fr + i * nf;
-        double* ri = Fi + i * nf;
-        const double* kr = Fr + k * nf;
-        const double* ki = Fi + k * nf;
+        const R lr = Fr[i * nf + k], li = Fi[i * nf + k];
+        R* rr = Fr + i * nf;
+        R* ri = Fi + i * nf;
+        const R* kr = Fr + k * nf;
+        const R* ki = Fi + k * nf;
         for (long j = ke; j < nf; ++j) {
           rr[j] -= lr * kr[j] - li * ki[j];
           ri[j] -= lr * ki[j] + li * kr[j];
@@ -181,19 +425,31 @@ void partial_lu(double* Fr, double* Fi, long nf, long np, int* ipiv, double* flo
 
 struct HostSolver {
   int n = 0;
-  std::vector<Node> nodes;
+  bool fp32 = false;
+  std::vector<Geom> geo;
   int root = -1;
-  std::vector<int> post;           // post-order of the elimination tree
-  std::vector<const std::complex<double>*> dummy;
+  std::vector<Vals<double>> v64;
+  std::vector<Vals<float>> v32;
   size_t bytes = 0;
   double flops = 0.0;
 };
 
 namespace {
 
+template <typename R>
+std::vector<Vals<R>>& vals_of(HostSolver& hs);
+template <>
+std::vector<Vals<double>>& vals_of<double>(HostSolver& hs) {
+  return hs.v64;
+}
+template <>
+std::vector<Vals<float>>& vals_of<float>(HostSolver& hs) {
+  return hs.v32;
+}
+
 int build_tree(HostSolver& hs, const int lo[3], const int hi[3]) {
   const int n = hs.n;
-  Node nd;
+  Geom nd;
   for (int d = 0; d < 3; ++d) {
     nd.lo[d] = lo[d];
     nd.hi[d] = hi[d];
@@ -219,8 +475,8 @@ int build_tree(HostSolver& hs, const int lo[3], const int hi[3]) {
       }
   nd.np = 3 * (int)nd.piv.size();
   nd.nb = 3 * (int)nd.bnd.size();
-  const int id = (int)hs.nodes.size();
-  hs.nodes.push_back(std::move(nd));
+  const int id = (int)hs.geo.size();
+  hs.geo.push_back(std::move(nd));
   if (!leaf) {
     int l_hi[3] = {hi[0], hi[1], hi[2]};
     int r_lo[3] = {lo[0], lo[1], lo[2]};
@@ -229,36 +485,20 @@ int build_tree(HostSolver& hs, const int lo[3], const int hi[3]) {
     int c0 = -1, c1 = -1;
     if (mid > lo[dsplit]) c0 = build_tree(hs, lo, l_hi);
     if (mid + 1 < hi[dsplit]) c1 = build_tree(hs, r_lo, hi);
-    hs.nodes[id].child[0] = c0;
-    hs.nodes[id].child[1] = c1;
+    hs.geo[id].child[0] = c0;
+    hs.geo[id].child[1] = c1;
   }
   return id;
 }
 
-void post_order(const HostSolver& hs, int id, std::vector<int>& out) {
-  const Node& nd = hs.nodes[id];
-  for (int c : nd.child)
-    if (c >= 0) post_order(hs, c, out);
-  out.push_back(id);
-}
-
-size_t node_factor_bytes(const Node& nd) {
-  return 16ull * ((size_t)nd.np * nd.np + 2ull * nd.np * nd.nb);
-}
-
-// local front index of global point p (pivot first, then boundary), or -1
-inline int front_pos(const Node& nd, int p) {
-  int k = pos_in(nd.piv, p);
-  if (k >= 0) return k;
-  k = pos_in(nd.bnd, p);
-  return k >= 0 ? (int)nd.piv.size() + k : -1;
-}
-
+template <typename R>
 void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::atomic<double>* flops) {
-  Node& nd = hs.nodes[id];
+  const Geom& nd = hs.geo[id];
+  std::vector<Vals<R>>& V = vals_of<R>(hs);
+  Vals<R>& v = V[id];
   const int n = hs.n;
   const long np = nd.np, nb = nd.nb, nf = np + nb;
-  std::vector<double> Fr((size_t)nf * nf, 0.0), Fi((size_t)nf * nf, 0.0);
+  std::vector<R> Fr((size_t)nf * nf, R(0)), Fi((size_t)nf * nf, R(0));
   auto add_point_rows = [&](int pi, int li, bool pivot_row) {
     const int i3 = pi % n, i2 = (pi / n) % n, i1 = pi / (n * n);
     for (int s1 = -1; s1 <= 1; ++s1)
@@ -267,20 +507,15 @@ void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::
           const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
           if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n || j3 < 0 || j3 >= n) continue;
           const int pj = (j1 * n + j2) * n + j3;
-          int lj;
-          if (pivot_row) {
-            lj = front_pos(nd, pj);
-          } else {
-            lj = pos_in(nd.piv, pj);
-          }
+          const int lj = pivot_row ? front_pos(nd, pj) : pos_in(nd.piv, pj);
           if (lj < 0) continue;
           const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
           for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
-              const std::complex<double> v = rows[(size_t)pi * 243 + (r * 27 + slot) * 3 + c];
+              const std::complex<double> val = rows[(size_t)pi * 243 + (r * 27 + slot) * 3 + c];
               const size_t o = (size_t)(3 * li + r) * nf + (3 * lj + c);
-              Fr[o] += v.real();
-              Fi[o] += v.imag();
+              Fr[o] += (R)val.real();
+              Fi[o] += (R)val.imag();
             }
         }
   };
@@ -289,96 +524,81 @@ void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::
   // extend-add of the children's update matrices
   for (int c : nd.child) {
     if (c < 0) continue;
-    Node& ch = hs.nodes[c];
-    std::vector<int> map(ch.nb);
-    for (size_t a = 0; a < ch.bnd.size(); ++a) {
-      const int fp = front_pos(nd, ch.bnd[a]);
+    const Geom& cg = hs.geo[c];
+    Vals<R>& cv = V[c];
+    std::vector<int> map(cg.nb);
+    for (size_t a = 0; a < cg.bnd.size(); ++a) {
+      const int fp = front_pos(nd, cg.bnd[a]);
       for (int q = 0; q < 3; ++q) map[3 * a + q] = 3 * fp + q;
     }
-    for (int r = 0; r < ch.nb; ++r)
-      for (int s = 0; s < ch.nb; ++s) {
+    for (int r = 0; r < cg.nb; ++r)
+      for (int s = 0; s < cg.nb; ++s) {
         const size_t o = (size_t)map[r] * nf + map[s];
-        Fr[o] += ch.updr[(size_t)r * ch.nb + s];
-        Fi[o] += ch.updi[(size_t)r * ch.nb + s];
+        Fr[o] += cv.updr[(size_t)r * cg.nb + s];
+        Fi[o] += cv.updi[(size_t)r * cg.nb + s];
       }
-    std::vector<double>().swap(ch.updr);
-    std::vector<double>().swap(ch.updi);
+    std::vector<R>().swap(cv.updr);
+    std::vector<R>().swap(cv.updi);
   }
-  nd.ipiv.resize(np);
+  v.ipiv.resize(np);
   double fl = 0.0;
-  partial_lu(Fr.data(), Fi.data(), nf, np, nd.ipiv.data(), &fl);
+  partial_lu(Fr.data(), Fi.data(), nf, np, v.ipiv.data(), &fl);
   double prev = flops->load();
   while (!flops->compare_exchange_weak(prev, prev + fl)) {
   }
-  nd.l11r.resize(np * np);
-  nd.l11i.resize(np * np);
-  nd.u12r.resize(np * nb);
-  nd.u12i.resize(np * nb);
-  nd.l21r.resize(nb * np);
-  nd.l21i.resize(nb * np);
-  nd.updr.resize(nb * nb);
-  nd.updi.resize(nb * nb);
+  v.l11r.resize(np * np);
+  v.l11i.resize(np * np);
+  v.u12r.resize(np * nb);
+  v.u12i.resize(np * nb);
+  v.l21r.resize(nb * np);
+  v.l21i.resize(nb * np);
+  v.updr.resize(nb * nb);
+  v.updi.resize(nb * nb);
   for (long i = 0; i < np; ++i) {
-    std::memcpy(&nd.l11r[i * np], &Fr[i * nf], np * sizeof(double));
-    std::memcpy(&nd.l11i[i * np], &Fi[i * nf], np * sizeof(double));
-    std::memcpy(&nd.u12r[i * nb], &Fr[i * nf + np], nb * sizeof(double));
-    std::memcpy(&nd.u12i[i * nb], &Fi[i * nf + np], nb * sizeof(double));
+    std::memcpy(&v.l11r[i * np], &Fr[i * nf], np * sizeof(R));
+    std::memcpy(&v.l11i[i * np], &Fi[i * nf], np * sizeof(R));
+    std::memcpy(&v.u12r[i * nb], &Fr[i * nf + np], nb * sizeof(R));
+    std::memcpy(&v.u12i[i * nb], &Fi[i * nf + np], nb * sizeof(R));
   }
   for (long i = 0; i < nb; ++i) {
-    std::memcpy(&nd.l21r[i * np], &Fr[(np + i) * nf], np * sizeof(double));
-    std::memcpy(&nd.l21i[i * np], &Fi[(np + i) * nf], np * sizeof(double));
-    std::memcpy(&nd.updr[i * nb], &Fr[(np + i) * nf + np], nb * sizeof(double));
-    std::memcpy(&nd.updi[i * nb], &Fi[(np + i) * nf + np], nb * sizeof(double));
+    std::memcpy(&v.l21r[i * np], &Fr[(np + i) * nf], np * sizeof(R));
+    std::memcpy(&v.l21i[i * np], &Fi[(np + i) * nf], np * sizeof(R));
+    std::memcpy(&v.updr[i * nb], &Fr[(np + i) * nf + np], nb * sizeof(R));
+    std::memcpy(&v.updi[i * nb], &Fi[(np + i) * nf + np], nb * sizeof(R));
   }
 }
 
+template <typename R>
 void factor_rec(HostSolver& hs, int id, const std::complex<double>* rows, std::atomic<double>* flops) {
-  Node& nd = hs.nodes[id];
-  for (int c : nd.child) {
+  for (int c : hs.geo[id].child) {
     if (c < 0) continue;
-#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 16)
-    factor_rec(hs, c, rows, flops);
+#pragma omp task firstprivate(c) shared(hs) if (hs.geo[c].piv.size() > 16)
+    factor_rec<R>(hs, c, rows, flops);
   }
 #pragma omp taskwait
-  factor_node(hs, id, rows, flops);
+  factor_node<R>(hs, id, rows, flops);
 }
 
-
-// ---- solves ---------------------------------------------------------------------
+// ---- solves, one right-hand side at a time ------------------------------------------
 // Vectors are kept right-hand-side major ([rhs][dof], real and imaginary
 // parts apart) so that every inner product with a factor row is a contiguous
 // SIMD dot product.  Per node and rhs: w (nf) = [b at pivots; 0] + children's
 // update vectors; z1 = L11^-1 P w1 is kept, u = w2 - L21 z1 goes to the parent.
 // Backward: x1 = U11^-1 (z1 - U12 x_B).
+template <typename R>
 struct SolveWork {
-  std::vector<std::vector<double>> ur, ui;   // per node: [rhs][nb] update vectors
+  std::vector<std::vector<R>> ur, ui;   // per node: update vectors
 };
-
-// sum_k (ar + i ai)[k] (xr + i xi)[k]
-#if defined(__x86_64__)
-__attribute__((target_clones("avx512f", "avx2", "default")))
-#endif
-void cdot(const double* __restrict__ ar, const double* __restrict__ ai, const double* __restrict__ xr,
-          const double* __restrict__ xi, long len, double* outr, double* outi) {
-  double sr = 0.0, si = 0.0;
-#pragma omp simd reduction(+ : sr, si)
-  for (long k = 0; k < len; ++k) {
-    sr += ar[k] * xr[k] - ai[k] * xi[k];
-    si += ar[k] * xi[k] + ai[k] * xr[k];
-  }
-  *outr = sr;
-  *outi = si;
-}
 
 constexpr long kRowTask = 64;          // rows per task in the large matrix-vector products
 constexpr double kParWork = 4e5;       // complex MACs above which a product is split into tasks
 
 // y[i] -= sum_k A[i][k] x[k] for rows [0, m) of a row-major m x len block (lda), one rhs
-void gemv_sub(const double* Ar, const double* Ai, long lda, long m, long len, const double* xr, const double* xi,
-              double* yr, double* yi) {
+template <typename R>
+void gemv_sub(const R* Ar, const R* Ai, long lda, long m, long len, const R* xr, const R* xi, R* yr, R* yi) {
   auto rows = [&](long i0, long i1) {
     for (long i = i0; i < i1; ++i) {
-      double dr, di;
+      R dr, di;
       cdot(Ar + i * lda, Ai + i * lda, xr, xi, len, &dr, &di);
       yr[i] -= dr;
       yi[i] -= di;
@@ -394,14 +614,14 @@ void gemv_sub(const double* Ar, const double* Ai, long lda, long m, long len, co
 
 // unit-lower solve L x = b in place (rows of L row-major, lda = np), blocked so
 // the off-diagonal block products run as tasks
-void lower_unit_solve(const double* Lr, const double* Li, long np, double* xr, double* xi) {
+template <typename R>
+void lower_unit_solve(const R* Lr, const R* Li, long np, R* xr, R* xi) {
   constexpr long BS = 256;
   for (long b0 = 0; b0 < np; b0 += BS) {
     const long b1 = std::min(np, b0 + BS);
-    // rows [b0, b1): subtract the contribution of x[0, b0)
     if (b0 > 0) gemv_sub(Lr + b0 * np, Li + b0 * np, np, b1 - b0, b0, xr, xi, xr + b0, xi + b0);
     for (long i = b0; i < b1; ++i) {
-      double dr, di;
+      R dr, di;
       cdot(Lr + i * np + b0, Li + i * np + b0, xr + b0, xi + b0, i - b0, &dr, &di);
       xr[i] -= dr;
       xi[i] -= di;
@@ -410,28 +630,31 @@ void lower_unit_solve(const double* Lr, const double* Li, long np, double* xr, d
 }
 
 // upper solve U x = b in place (diagonal included)
-void upper_solve(const double* Ur, const double* Ui, long np, double* xr, double* xi) {
+template <typename R>
+void upper_solve(const R* Ur, const R* Ui, long np, R* xr, R* xi) {
   constexpr long BS = 256;
   for (long b1 = np; b1 > 0; b1 -= BS) {
     const long b0 = std::max(0L, b1 - BS);
-    if (b1 < np) gemv_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, xr + b1, xi + b1, xr + b0, xi + b0);
+    if (b1 < np)
+      gemv_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, xr + b1, xi + b1, xr + b0, xi + b0);
     for (long i = b1 - 1; i >= b0; --i) {
-      double dr, di;
+      R dr, di;
       cdot(Ur + i * np + i + 1, Ui + i * np + i + 1, xr + i + 1, xi + i + 1, b1 - i - 1, &dr, &di);
-      const double vr = xr[i] - dr, vi = xi[i] - di;
-      const double ur = Ur[i * np + i], ui = Ui[i * np + i];
-      const double den = ur * ur + ui * ui;
+      const R vr = xr[i] - dr, vi = xi[i] - di;
+      const R ur = Ur[i * np + i], ui = Ui[i * np + i];
+      const R den = ur * ur + ui * ui;
       xr[i] = (vr * ur + vi * ui) / den;
       xi[i] = (vi * ur - vr * ui) / den;
     }
   }
 }
 
-void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
-              SolveWork& W, long ldb) {
-  Node& nd = hs.nodes[id];
+template <typename R>
+void fwd_node(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr, R* Zi, SolveWork<R>& W, long ldb) {
+  const Geom& nd = hs.geo[id];
+  const Vals<R>& v = vals_of<R>(hs)[id];
   const long np = nd.np, nb = nd.nb, nf = np + nb;
-  std::vector<double> wr((size_t)nf * nrhs, 0.0), wi((size_t)nf * nrhs, 0.0);   // [rhs][dof]
+  std::vector<R> wr((size_t)nf * nrhs, R(0)), wi((size_t)nf * nrhs, R(0));   // [rhs][dof]
   for (int r = 0; r < nrhs; ++r)
     for (size_t a = 0; a < nd.piv.size(); ++a)
       for (int q = 0; q < 3; ++q) {
@@ -441,7 +664,7 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* 
       }
   for (int c : nd.child) {
     if (c < 0) continue;
-    Node& ch = hs.nodes[c];
+    const Geom& ch = hs.geo[c];
     std::vector<int> map(ch.nb);
     for (size_t a = 0; a < ch.bnd.size(); ++a) {
       const int fp = front_pos(nd, ch.bnd[a]);
@@ -452,21 +675,21 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* 
         wr[r * nf + map[e]] += W.ur[c][(size_t)r * ch.nb + e];
         wi[r * nf + map[e]] += W.ui[c][(size_t)r * ch.nb + e];
       }
-    std::vector<double>().swap(W.ur[c]);
-    std::vector<double>().swap(W.ui[c]);
+    std::vector<R>().swap(W.ur[c]);
+    std::vector<R>().swap(W.ui[c]);
   }
   for (int r = 0; r < nrhs; ++r) {
-    double* xr = &wr[(size_t)r * nf];
-    double* xi = &wi[(size_t)r * nf];
+    R* xr = &wr[(size_t)r * nf];
+    R* xi = &wi[(size_t)r * nf];
     for (long k = 0; k < np; ++k) {
-      const long p = nd.ipiv[k];
+      const long p = v.ipiv[k];
       if (p != k) {
         std::swap(xr[k], xr[p]);
         std::swap(xi[k], xi[p]);
       }
     }
-    lower_unit_solve(nd.l11r.data(), nd.l11i.data(), np, xr, xi);
-    if (nb) gemv_sub(nd.l21r.data(), nd.l21i.data(), np, nb, np, xr, xi, xr + np, xi + np);
+    lower_unit_solve(v.l11r.data(), v.l11i.data(), np, xr, xi);
+    if (nb) gemv_sub(v.l21r.data(), v.l21i.data(), np, nb, np, xr, xi, xr + np, xi + np);
   }
   for (int r = 0; r < nrhs; ++r)
     for (size_t a = 0; a < nd.piv.size(); ++a)
@@ -478,29 +701,31 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const double* Br, const double* 
   W.ur[id].resize((size_t)nrhs * nb);
   W.ui[id].resize((size_t)nrhs * nb);
   for (int r = 0; r < nrhs; ++r) {
-    std::memcpy(&W.ur[id][(size_t)r * nb], &wr[(size_t)r * nf + np], nb * sizeof(double));
-    std::memcpy(&W.ui[id][(size_t)r * nb], &wi[(size_t)r * nf + np], nb * sizeof(double));
+    std::memcpy(&W.ur[id][(size_t)r * nb], &wr[(size_t)r * nf + np], nb * sizeof(R));
+    std::memcpy(&W.ui[id][(size_t)r * nb], &wi[(size_t)r * nf + np], nb * sizeof(R));
   }
 }
 
-void fwd_rec(HostSolver& hs, int id, int nrhs, const double* Br, const double* Bi, double* Zr, double* Zi,
-             SolveWork& W, long ldb) {
-  for (int c : hs.nodes[id].child) {
+template <typename R>
+void fwd_rec(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr, R* Zi, SolveWork<R>& W, long ldb) {
+  for (int c : hs.geo[id].child) {
     if (c < 0) continue;
-#pragma omp task firstprivate(c) shared(hs, W) if (hs.nodes[c].piv.size() > 64)
-    fwd_rec(hs, c, nrhs, Br, Bi, Zr, Zi, W, ldb);
+#pragma omp task firstprivate(c) shared(hs, W) if (hs.geo[c].piv.size() > 64)
+    fwd_rec<R>(hs, c, nrhs, Br, Bi, Zr, Zi, W, ldb);
   }
 #pragma omp taskwait
-  fwd_node(hs, id, nrhs, Br, Bi, Zr, Zi, W, ldb);
+  fwd_node<R>(hs, id, nrhs, Br, Bi, Zr, Zi, W, ldb);
 }
 
-void bwd_node(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
-  Node& nd = hs.nodes[id];
+template <typename R>
+void bwd_node(HostSolver& hs, int id, int nrhs, R* Xr, R* Xi, long ldb) {
+  const Geom& nd = hs.geo[id];
+  const Vals<R>& v = vals_of<R>(hs)[id];
   const long np = nd.np, nb = nd.nb;
-  std::vector<double> xr((size_t)np), xi((size_t)np), yr((size_t)nb), yi((size_t)nb);
+  std::vector<R> xr((size_t)np), xi((size_t)np), yr((size_t)nb), yi((size_t)nb);
   for (int r = 0; r < nrhs; ++r) {
-    double* Rr = Xr + r * ldb;
-    double* Ri = Xi + r * ldb;
+    R* Rr = Xr + r * ldb;
+    R* Ri = Xi + r * ldb;
     for (size_t a = 0; a < nd.piv.size(); ++a)
       for (int q = 0; q < 3; ++q) {
         xr[3 * a + q] = Rr[3L * nd.piv[a] + q];
@@ -511,8 +736,8 @@ void bwd_node(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb
         yr[3 * a + q] = Rr[3L * nd.bnd[a] + q];
         yi[3 * a + q] = Ri[3L * nd.bnd[a] + q];
       }
-    if (nb) gemv_sub(nd.u12r.data(), nd.u12i.data(), nb, np, nb, yr.data(), yi.data(), xr.data(), xi.data());
-    upper_solve(nd.l11r.data(), nd.l11i.data(), np, xr.data(), xi.data());
+    if (nb) gemv_sub(v.u12r.data(), v.u12i.data(), nb, np, nb, yr.data(), yi.data(), xr.data(), xi.data());
+    upper_solve(v.l11r.data(), v.l11i.data(), np, xr.data(), xi.data());
     for (size_t a = 0; a < nd.piv.size(); ++a)
       for (int q = 0; q < 3; ++q) {
         Rr[3L * nd.piv[a] + q] = xr[3 * a + q];
@@ -521,257 +746,154 @@ void bwd_node(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb
   }
 }
 
-void bwd_rec(HostSolver& hs, int id, int nrhs, double* Xr, double* Xi, long ldb) {
-  bwd_node(hs, id, nrhs, Xr, Xi, ldb);
-  for (int c : hs.nodes[id].child) {
+template <typename R>
+void bwd_rec(HostSolver& hs, int id, int nrhs, R* Xr, R* Xi, long ldb) {
+  bwd_node<R>(hs, id, nrhs, Xr, Xi, ldb);
+  for (int c : hs.geo[id].child) {
     if (c < 0) continue;
-#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 64)
-    bwd_rec(hs, c, nrhs, Xr, Xi, ldb);
+#pragma omp task firstprivate(c) shared(hs) if (hs.geo[c].piv.size() > 64)
+    bwd_rec<R>(hs, c, nrhs, Xr, Xi, ldb);
   }
 #pragma omp taskwait
 }
 
-// ---- many right-hand sides: block vectors [dof][R], R a multiple of 4 ----------
-// The solves above read every factor entry once per right-hand side.  With the
-// right-hand sides interleaved (entry (k, r) at k R + r), a factor entry is
-// broadcast against a short vector of right-hand sides, so each factor row is
-// streamed once per 8 right-hand sides and the arithmetic vectorises over r.
-
-// Y[a][r] -= sum_k A[a][k] X[k][r] for MR rows a, RB right-hand sides r.
-template <int MR, int RB>
-__attribute__((always_inline)) inline void mk_sub(const double* __restrict__ Ar, const double* __restrict__ Ai,
-                                                  long lda, long K, const double* __restrict__ Xr,
-                                                  const double* __restrict__ Xi, long R,
-                                                  double* __restrict__ Yr, double* __restrict__ Yi) {
-  double cr[MR][RB], ci[MR][RB];
-  for (int a = 0; a < MR; ++a)
-    for (int r = 0; r < RB; ++r) cr[a][r] = ci[a][r] = 0.0;
-  for (long k = 0; k < K; ++k) {
-    const double* xr = Xr + k * R;
-    const double* xi = Xi + k * R;
-    for (int a = 0; a < MR; ++a) {
-      const double ar = Ar[a * lda + k], ai = Ai[a * lda + k];
-#pragma omp simd
-      for (int r = 0; r < RB; ++r) {
-        cr[a][r] += ar * xr[r] - ai * xi[r];
-        ci[a][r] += ar * xi[r] + ai * xr[r];
-      }
-    }
-  }
-  for (int a = 0; a < MR; ++a)
-#pragma omp simd
-    for (int r = 0; r < RB; ++r) {
-      Yr[a * R + r] -= cr[a][r];
-      Yi[a * R + r] -= ci[a][r];
-    }
-}
-
-// rows [i0, i1) of Y -= A X; A row-major (lda), K columns; X, Y block vectors
-#if defined(__x86_64__)
-__attribute__((target_clones("avx512f", "avx2", "default")))
-#endif
-void gemm_sub_rows(const double* Ar, const double* Ai, long lda, long i0, long i1, long K, const double* Xr,
-                   const double* Xi, long R, double* Yr, double* Yi) {
-  long i = i0;
-  for (; i + 4 <= i1; i += 4)
-    for (long r0 = 0; r0 < R;) {
-      if (R - r0 >= 16) {
-        mk_sub<4, 16>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
-        r0 += 16;
-      } else if (R - r0 >= 8) {
-        mk_sub<4, 8>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
-        r0 += 8;
-      } else {
-        mk_sub<4, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
-        r0 += 4;
-      }
-    }
-  for (; i < i1; ++i)
-    for (long r0 = 0; r0 < R; r0 += 4)
-      mk_sub<1, 4>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, R, Yr + i * R + r0, Yi + i * R + r0);
-}
+// ---- solves, block vectors ----------------------------------------------------------
 
 // Y (m rows) -= A X, split into row tasks when large
-void gemm_sub(const double* Ar, const double* Ai, long lda, long m, long K, const double* Xr, const double* Xi,
-              long R, double* Yr, double* Yi) {
+template <typename R>
+void gemm_sub(const R* Ar, const R* Ai, long lda, long m, long K, const R* Xr, const R* Xi, long ldx, R* Yr, R* Yi) {
   if (m <= 0 || K <= 0) return;
-  if ((double)m * (double)K * (double)R > 4.0 * kParWork) {
+  if ((double)m * (double)K * (double)ldx > 4.0 * kParWork) {
     constexpr long RT = 32;
 #pragma omp taskloop grainsize(1)
-    for (long i0 = 0; i0 < m; i0 += RT) gemm_sub_rows(Ar, Ai, lda, i0, std::min(m, i0 + RT), K, Xr, Xi, R, Yr, Yi);
+    for (long i0 = 0; i0 < m; i0 += RT) gemm_sub_rows(Ar, Ai, lda, i0, std::min(m, i0 + RT), K, Xr, Xi, ldx, Yr, Yi);
   } else {
-    gemm_sub_rows(Ar, Ai, lda, 0, m, K, Xr, Xi, R, Yr, Yi);
+    gemm_sub_rows(Ar, Ai, lda, 0, m, K, Xr, Xi, ldx, Yr, Yi);
   }
 }
 
-// W[i][r] -= L[i][k] W[k][r] for k in [b0, i), i in [b0, b1)  (within a diagonal block)
-#if defined(__x86_64__)
-__attribute__((target_clones("avx512f", "avx2", "default")))
-#endif
-void lower_block_multi(const double* __restrict__ Lr, const double* __restrict__ Li, long np, long b0, long b1,
-                       double* __restrict__ Wr, double* __restrict__ Wi, long R) {
-  for (long i = b0; i < b1; ++i) {
-    double* yr = Wr + i * R;
-    double* yi = Wi + i * R;
-    for (long k = b0; k < i; ++k) {
-      const double ar = Lr[i * np + k], ai = Li[i * np + k];
-      const double* xr = Wr + k * R;
-      const double* xi = Wi + k * R;
-#pragma omp simd
-      for (long r = 0; r < R; ++r) {
-        yr[r] -= ar * xr[r] - ai * xi[r];
-        yi[r] -= ar * xi[r] + ai * xr[r];
-      }
-    }
-  }
-}
-
-// W[i][r] = (W[i][r] - sum_{k in (i, b1)} U[i][k] W[k][r]) / U[i][i], i from b1-1 down to b0
-#if defined(__x86_64__)
-__attribute__((target_clones("avx512f", "avx2", "default")))
-#endif
-void upper_block_multi(const double* __restrict__ Ur, const double* __restrict__ Ui, long np, long b0, long b1,
-                       double* __restrict__ Wr, double* __restrict__ Wi, long R) {
-  for (long i = b1 - 1; i >= b0; --i) {
-    double* yr = Wr + i * R;
-    double* yi = Wi + i * R;
-    for (long k = i + 1; k < b1; ++k) {
-      const double ar = Ur[i * np + k], ai = Ui[i * np + k];
-      const double* xr = Wr + k * R;
-      const double* xi = Wi + k * R;
-#pragma omp simd
-      for (long r = 0; r < R; ++r) {
-        yr[r] -= ar * xr[r] - ai * xi[r];
-        yi[r] -= ar * xi[r] + ai * xr[r];
-      }
-    }
-    const double ur = Ur[i * np + i], ui = Ui[i * np + i];
-    const double den = ur * ur + ui * ui;
-    const double qr = ur / den, qi = -ui / den;      // 1 / u
-#pragma omp simd
-    for (long r = 0; r < R; ++r) {
-      const double vr = yr[r], vi = yi[r];
-      yr[r] = vr * qr - vi * qi;
-      yi[r] = vr * qi + vi * qr;
-    }
-  }
-}
-
-void lower_unit_solve_multi(const double* Lr, const double* Li, long np, double* Wr, double* Wi, long R) {
+template <typename R>
+void lower_unit_solve_multi(const R* Lr, const R* Li, long np, R* Wr, R* Wi, long ldx) {
   constexpr long BS = 128;
   for (long b0 = 0; b0 < np; b0 += BS) {
     const long b1 = std::min(np, b0 + BS);
-    if (b0 > 0) gemm_sub(Lr + b0 * np, Li + b0 * np, np, b1 - b0, b0, Wr, Wi, R, Wr + b0 * R, Wi + b0 * R);
-    lower_block_multi(Lr, Li, np, b0, b1, Wr, Wi, R);
+    if (b0 > 0) gemm_sub(Lr + b0 * np, Li + b0 * np, np, b1 - b0, b0, Wr, Wi, ldx, Wr + b0 * ldx, Wi + b0 * ldx);
+    lower_block_multi(Lr, Li, np, b0, b1, Wr, Wi, ldx);
   }
 }
 
-void upper_solve_multi(const double* Ur, const double* Ui, long np, double* Wr, double* Wi, long R) {
+template <typename R>
+void upper_solve_multi(const R* Ur, const R* Ui, long np, R* Wr, R* Wi, long ldx) {
   constexpr long BS = 128;
   for (long b1 = np; b1 > 0; b1 -= BS) {
     const long b0 = std::max(0L, b1 - BS);
     if (b1 < np)
-      gemm_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, Wr + b1 * R, Wi + b1 * R, R,
-               Wr + b0 * R, Wi + b0 * R);
-    upper_block_multi(Ur, Ui, np, b0, b1, Wr, Wi, R);
+      gemm_sub(Ur + b0 * np + b1, Ui + b0 * np + b1, np, b1 - b0, np - b1, Wr + b1 * ldx, Wi + b1 * ldx, ldx,
+               Wr + b0 * ldx, Wi + b0 * ldx);
+    upper_block_multi(Ur, Ui, np, b0, b1, Wr, Wi, ldx);
   }
 }
 
-// B, Z, X: block vectors over all 3 n^3 unknowns, [3 p + c][R]
-void fwd_node_multi(HostSolver& hs, int id, long R, const double* Br, const double* Bi, double* Zr, double* Zi,
-                    SolveWork& W) {
-  Node& nd = hs.nodes[id];
+// B, Z, X: block vectors over all 3 n^3 unknowns, [3 p + c][ldx]
+template <typename R>
+void fwd_node_multi(HostSolver& hs, int id, long ldx, const R* Br, const R* Bi, R* Zr, R* Zi, SolveWork<R>& W) {
+  const Geom& nd = hs.geo[id];
+  const Vals<R>& v = vals_of<R>(hs)[id];
   const long np = nd.np, nb = nd.nb, nf = np + nb;
-  std::vector<double> wr((size_t)nf * R, 0.0), wi((size_t)nf * R, 0.0);
+  std::vector<R> wr((size_t)nf * ldx, R(0)), wi((size_t)nf * ldx, R(0));
   for (size_t a = 0; a < nd.piv.size(); ++a)
     for (int q = 0; q < 3; ++q) {
       const long g = 3L * nd.piv[a] + q;
-      std::memcpy(&wr[(3 * a + q) * R], Br + g * R, R * sizeof(double));
-      std::memcpy(&wi[(3 * a + q) * R], Bi + g * R, R * sizeof(double));
+      std::memcpy(&wr[(3 * a + q) * ldx], Br + g * ldx, ldx * sizeof(R));
+      std::memcpy(&wi[(3 * a + q) * ldx], Bi + g * ldx, ldx * sizeof(R));
     }
   for (int c : nd.child) {
     if (c < 0) continue;
-    Node& ch = hs.nodes[c];
+    const Geom& ch = hs.geo[c];
     for (size_t a = 0; a < ch.bnd.size(); ++a) {
       const long fp = front_pos(nd, ch.bnd[a]);
       for (int q = 0; q < 3; ++q) {
-        const double* ur = &W.ur[c][(3 * a + q) * R];
-        const double* ui = &W.ui[c][(3 * a + q) * R];
-        double* xr = &wr[(3 * fp + q) * R];
-        double* xi = &wi[(3 * fp + q) * R];
-        for (long r = 0; r < R; ++r) {
+        const R* ur = &W.ur[c][(3 * a + q) * ldx];
+        const R* ui = &W.ui[c][(3 * a + q) * ldx];
+        R* xr = &wr[(3 * fp + q) * ldx];
+        R* xi = &wi[(3 * fp + q) * ldx];
+        for (long r = 0; r < ldx; ++r) {
           xr[r] += ur[r];
           xi[r] += ui[r];
         }
       }
     }
-    std::vector<double>().swap(W.ur[c]);
-    std::vector<double>().swap(W.ui[c]);
+    std::vector<R>().swap(W.ur[c]);
+    std::vector<R>().swap(W.ui[c]);
   }
   for (long k = 0; k < np; ++k) {
-    const long p = nd.ipiv[k];
+    const long p = v.ipiv[k];
     if (p != k)
-      for (long r = 0; r < R; ++r) {
-        std::swap(wr[k * R + r], wr[p * R + r]);
-        std::swap(wi[k * R + r], wi[p * R + r]);
+      for (long r = 0; r < ldx; ++r) {
+        std::swap(wr[k * ldx + r], wr[p * ldx + r]);
+        std::swap(wi[k * ldx + r], wi[p * ldx + r]);
       }
   }
-  lower_unit_solve_multi(nd.l11r.data(), nd.l11i.data(), np, wr.data(), wi.data(), R);
-  if (nb) gemm_sub(nd.l21r.data(), nd.l21i.data(), np, nb, np, wr.data(), wi.data(), R, wr.data() + np * R,
-                   wi.data() + np * R);
+  lower_unit_solve_multi(v.l11r.data(), v.l11i.data(), np, wr.data(), wi.data(), ldx);
+  if (nb)
+    gemm_sub(v.l21r.data(), v.l21i.data(), np, nb, np, wr.data(), wi.data(), ldx, wr.data() + np * ldx,
+             wi.data() + np * ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
     for (int q = 0; q < 3; ++q) {
       const long g = 3L * nd.piv[a] + q;
-      std::memcpy(Zr + g * R, &wr[(3 * a + q) * R], R * sizeof(double));
-      std::memcpy(Zi + g * R, &wi[(3 * a + q) * R], R * sizeof(double));
+      std::memcpy(Zr + g * ldx, &wr[(3 * a + q) * ldx], ldx * sizeof(R));
+      std::memcpy(Zi + g * ldx, &wi[(3 * a + q) * ldx], ldx * sizeof(R));
     }
-  W.ur[id].assign(wr.begin() + np * R, wr.end());
-  W.ui[id].assign(wi.begin() + np * R, wi.end());
+  W.ur[id].assign(wr.begin() + np * ldx, wr.end());
+  W.ui[id].assign(wi.begin() + np * ldx, wi.end());
 }
 
-void fwd_rec_multi(HostSolver& hs, int id, long R, const double* Br, const double* Bi, double* Zr, double* Zi,
-                   SolveWork& W) {
-  for (int c : hs.nodes[id].child) {
+template <typename R>
+void fwd_rec_multi(HostSolver& hs, int id, long ldx, const R* Br, const R* Bi, R* Zr, R* Zi, SolveWork<R>& W) {
+  for (int c : hs.geo[id].child) {
     if (c < 0) continue;
-#pragma omp task firstprivate(c) shared(hs, W) if (hs.nodes[c].piv.size() > 64)
-    fwd_rec_multi(hs, c, R, Br, Bi, Zr, Zi, W);
+#pragma omp task firstprivate(c) shared(hs, W) if (hs.geo[c].piv.size() > 64)
+    fwd_rec_multi<R>(hs, c, ldx, Br, Bi, Zr, Zi, W);
   }
 #pragma omp taskwait
-  fwd_node_multi(hs, id, R, Br, Bi, Zr, Zi, W);
+  fwd_node_multi<R>(hs, id, ldx, Br, Bi, Zr, Zi, W);
 }
 
-void bwd_node_multi(HostSolver& hs, int id, long R, double* Xr, double* Xi) {
-  Node& nd = hs.nodes[id];
+template <typename R>
+void bwd_node_multi(HostSolver& hs, int id, long ldx, R* Xr, R* Xi) {
+  const Geom& nd = hs.geo[id];
+  const Vals<R>& v = vals_of<R>(hs)[id];
   const long np = nd.np, nb = nd.nb;
-  std::vector<double> xr((size_t)np * R), xi((size_t)np * R), yr((size_t)nb * R), yi((size_t)nb * R);
+  std::vector<R> xr((size_t)np * ldx), xi((size_t)np * ldx), yr((size_t)nb * ldx), yi((size_t)nb * ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
     for (int q = 0; q < 3; ++q) {
       const long g = 3L * nd.piv[a] + q;
-      std::memcpy(&xr[(3 * a + q) * R], Xr + g * R, R * sizeof(double));
-      std::memcpy(&xi[(3 * a + q) * R], Xi + g * R, R * sizeof(double));
+      std::memcpy(&xr[(3 * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
+      std::memcpy(&xi[(3 * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
     }
   for (size_t a = 0; a < nd.bnd.size(); ++a)
     for (int q = 0; q < 3; ++q) {
       const long g = 3L * nd.bnd[a] + q;
-      std::memcpy(&yr[(3 * a + q) * R], Xr + g * R, R * sizeof(double));
-      std::memcpy(&yi[(3 * a + q) * R], Xi + g * R, R * sizeof(double));
+      std::memcpy(&yr[(3 * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
+      std::memcpy(&yi[(3 * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
     }
-  if (nb) gemm_sub(nd.u12r.data(), nd.u12i.data(), nb, np, nb, yr.data(), yi.data(), R, xr.data(), xi.data());
-  upper_solve_multi(nd.l11r.data(), nd.l11i.data(), np, xr.data(), xi.data(), R);
+  if (nb) gemm_sub(v.u12r.data(), v.u12i.data(), nb, np, nb, yr.data(), yi.data(), ldx, xr.data(), xi.data());
+  upper_solve_multi(v.l11r.data(), v.l11i.data(), np, xr.data(), xi.data(), ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
     for (int q = 0; q < 3; ++q) {
       const long g = 3L * nd.piv[a] + q;
-      std::memcpy(Xr + g * R, &xr[(3 * a + q) * R], R * sizeof(double));
-      std::memcpy(Xi + g * R, &xi[(3 * a + q) * R], R * sizeof(double));
+      std::memcpy(Xr + g * ldx, &xr[(3 * a + q) * ldx], ldx * sizeof(R));
+      std::memcpy(Xi + g * ldx, &xi[(3 * a + q) * ldx], ldx * sizeof(R));
     }
 }
 
-void bwd_rec_multi(HostSolver& hs, int id, long R, double* Xr, double* Xi) {
-  bwd_node_multi(hs, id, R, Xr, Xi);
-  for (int c : hs.nodes[id].child) {
+template <typename R>
+void bwd_rec_multi(HostSolver& hs, int id, long ldx, R* Xr, R* Xi) {
+  bwd_node_multi<R>(hs, id, ldx, Xr, Xi);
+  for (int c : hs.geo[id].child) {
     if (c < 0) continue;
-#pragma omp task firstprivate(c) shared(hs) if (hs.nodes[c].piv.size() > 64)
-    bwd_rec_multi(hs, c, R, Xr, Xi);
+#pragma omp task firstprivate(c) shared(hs) if (hs.geo[c].piv.size() > 64)
+    bwd_rec_multi<R>(hs, c, ldx, Xr, Xi);
   }
 #pragma omp taskwait
 }
@@ -781,58 +903,114 @@ void bwd_rec_multi(HostSolver& hs, int id, long R, double* Xr, double* Xi) {
 constexpr int kMultiBlock = 32;
 constexpr int kMultiMin = 3;         // from this many right-hand sides on, the block solve
 
-ls_status host_solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
+template <typename R>
+void solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
   const long n3 = (long)hs->n * hs->n * hs->n;
   const long ldb = 3 * n3;
   for (int r0 = 0; r0 < nrhs; r0 += kMultiBlock) {
     const int nr = std::min(kMultiBlock, nrhs - r0);
-    const long R = (nr + 3) / 4 * 4;
-    std::vector<double> Br((size_t)ldb * R, 0.0), Bi((size_t)ldb * R, 0.0);
-    std::vector<double> Zr((size_t)ldb * R, 0.0), Zi((size_t)ldb * R, 0.0);
+    const long ldx = (nr + 3) / 4 * 4;
+    std::vector<R> Br((size_t)ldb * ldx, R(0)), Bi((size_t)ldb * ldx, R(0));
+    std::vector<R> Zr((size_t)ldb * ldx, R(0)), Zi((size_t)ldb * ldx, R(0));
     std::complex<double>* bb = b + (size_t)r0 * ldb;
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < n3; ++p)
       for (int c = 0; c < 3; ++c)
         for (int r = 0; r < nr; ++r) {
           const std::complex<double> v = bb[(size_t)r * ldb + c * n3 + p];
-          Br[(3 * p + c) * R + r] = v.real();
-          Bi[(3 * p + c) * R + r] = v.imag();
+          Br[(3 * p + c) * ldx + r] = (R)v.real();
+          Bi[(3 * p + c) * ldx + r] = (R)v.imag();
         }
-    SolveWork W;
-    W.ur.resize(hs->nodes.size());
-    W.ui.resize(hs->nodes.size());
+    SolveWork<R> W;
+    W.ur.resize(hs->geo.size());
+    W.ui.resize(hs->geo.size());
 #pragma omp parallel
+{
+  FlushDenormals fd;
 #pragma omp single
-    fwd_rec_multi(*hs, hs->root, R, Br.data(), Bi.data(), Zr.data(), Zi.data(), W);
+  fwd_rec_multi<R>(*hs, hs->root, ldx, Br.data(), Bi.data(), Zr.data(), Zi.data(), W);
+}
 #pragma omp parallel
+{
+  FlushDenormals fd;
 #pragma omp single
-    bwd_rec_multi(*hs, hs->root, R, Zr.data(), Zi.data());
+  bwd_rec_multi<R>(*hs, hs->root, ldx, Zr.data(), Zi.data());
+}
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < n3; ++p)
       for (int c = 0; c < 3; ++c)
         for (int r = 0; r < nr; ++r)
-          bb[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[(3 * p + c) * R + r], Zi[(3 * p + c) * R + r]);
+          bb[(size_t)r * ldb + c * n3 + p] =
+              std::complex<double>(Zr[(3 * p + c) * ldx + r], Zi[(3 * p + c) * ldx + r]);
   }
-  return LS_OK;
+}
+
+template <typename R>
+void solve_single(HostSolver* hs, std::complex<double>* b, int nrhs) {
+  const long n3 = (long)hs->n * hs->n * hs->n;
+  const long ldb = 3 * n3;
+  std::vector<R> Br((size_t)nrhs * ldb), Bi((size_t)nrhs * ldb);
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < 3; ++c)
+      for (long p = 0; p < n3; ++p) {
+        const std::complex<double> v = b[(size_t)r * ldb + c * n3 + p];
+        Br[r * ldb + 3 * p + c] = (R)v.real();
+        Bi[r * ldb + 3 * p + c] = (R)v.imag();
+      }
+  std::vector<R> Zr((size_t)nrhs * ldb, R(0)), Zi((size_t)nrhs * ldb, R(0));
+  SolveWork<R> W;
+  W.ur.resize(hs->geo.size());
+  W.ui.resize(hs->geo.size());
+#pragma omp parallel
+{
+  FlushDenormals fd;
+#pragma omp single
+  fwd_rec<R>(*hs, hs->root, nrhs, Br.data(), Bi.data(), Zr.data(), Zi.data(), W, ldb);
+}
+#pragma omp parallel
+{
+  FlushDenormals fd;
+#pragma omp single
+  bwd_rec<R>(*hs, hs->root, nrhs, Zr.data(), Zi.data(), ldb);
+}
+  for (int r = 0; r < nrhs; ++r)
+    for (int c = 0; c < 3; ++c)
+      for (long p = 0; p < n3; ++p)
+        b[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[r * ldb + 3 * p + c], Zi[r * ldb + 3 * p + c]);
 }
 
 }  // namespace
 
-ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, HostSolver** out) {
+ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, bool fp32, HostSolver** out) {
   if (n < 1 || !rows || !out) return LS_EINVAL;
   std::unique_ptr<HostSolver> hs(new HostSolver());
   hs->n = n;
+  hs->fp32 = fp32;
   const int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
   hs->root = build_tree(*hs, lo, hi);
-  post_order(*hs, hs->root, hs->post);
+  const size_t cbytes = fp32 ? 8 : 16;
   size_t need = 0;
-  for (const Node& nd : hs->nodes) need += node_factor_bytes(nd);
+  for (const Geom& nd : hs->geo) need += cbytes * ((size_t)nd.np * nd.np + 2ull * nd.np * nd.nb);
   hs->bytes = need;
   if (mem_cap && need > mem_cap) return LS_EHOST;
   std::atomic<double> flops(0.0);
+  if (fp32) {
+    hs->v32.resize(hs->geo.size());
 #pragma omp parallel
+{
+  FlushDenormals fd;
 #pragma omp single
-  factor_rec(*hs, hs->root, rows, &flops);
+  factor_rec<float>(*hs, hs->root, rows, &flops);
+}
+  } else {
+    hs->v64.resize(hs->geo.size());
+#pragma omp parallel
+{
+  FlushDenormals fd;
+#pragma omp single
+  factor_rec<double>(*hs, hs->root, rows, &flops);
+}
+  }
   hs->flops = flops.load();
   *out = hs.release();
   return LS_OK;
@@ -840,36 +1018,23 @@ ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, H
 
 ls_status host_solve(HostSolver* hs, std::complex<double>* b, int nrhs) {
   if (!hs || !b || nrhs < 1) return LS_EINVAL;
-  if (nrhs >= kMultiMin) return host_solve_multi(hs, b, nrhs);
-  const long n3 = (long)hs->n * hs->n * hs->n;
-  const long ldb = 3 * n3;
-  std::vector<double> Br((size_t)nrhs * ldb), Bi((size_t)nrhs * ldb);
-  for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < 3; ++c)
-      for (long p = 0; p < n3; ++p) {
-        const std::complex<double> v = b[(size_t)r * ldb + c * n3 + p];
-        Br[r * ldb + 3 * p + c] = v.real();
-        Bi[r * ldb + 3 * p + c] = v.imag();
-      }
-  std::vector<double> Zr((size_t)nrhs * ldb, 0.0), Zi((size_t)nrhs * ldb, 0.0);
-  SolveWork W;
-  W.ur.resize(hs->nodes.size());
-  W.ui.resize(hs->nodes.size());
-#pragma omp parallel
-#pragma omp single
-  fwd_rec(*hs, hs->root, nrhs, Br.data(), Bi.data(), Zr.data(), Zi.data(), W, ldb);
-#pragma omp parallel
-#pragma omp single
-  bwd_rec(*hs, hs->root, nrhs, Zr.data(), Zi.data(), ldb);
-  for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < 3; ++c)
-      for (long p = 0; p < n3; ++p)
-        b[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[r * ldb + 3 * p + c], Zi[r * ldb + 3 * p + c]);
+  if (hs->fp32) {
+    if (nrhs >= kMultiMin)
+      solve_multi<float>(hs, b, nrhs);
+    else
+      solve_single<float>(hs, b, nrhs);
+  } else {
+    if (nrhs >= kMultiMin)
+      solve_multi<double>(hs, b, nrhs);
+    else
+      solve_single<double>(hs, b, nrhs);
+  }
   return LS_OK;
 }
 
 size_t host_factor_bytes(const HostSolver* hs) { return hs ? hs->bytes : 0; }
 double host_factor_flops(const HostSolver* hs) { return hs ? hs->flops : 0.0; }
+bool host_factor_is_fp32(const HostSolver* hs) { return hs && hs->fp32; }
 void host_free(HostSolver* hs) { delete hs; }
 
 }  // namespace ls

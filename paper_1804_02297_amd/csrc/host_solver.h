@@ -13,11 +13,13 @@ struct HostSolver;
 // rows: host array [n^3][3 rows][27 slots][3 comps] of complex128; slot
 // 9 (s1+1) + 3 (s2+1) + (s3+1) holds the 3x3 block coupling point i to i + s.
 // mem_cap: bytes the factor may use (0 = unlimited); LS_EHOST if exceeded.
-ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, HostSolver** out);
+// fp32: keep the factor in single precision (a preconditioner for FP64 FGMRES).
+ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, bool fp32, HostSolver** out);
 // Solve S x = b in place; b is [nrhs][3][n^3] (component-major, like the fields).
 ls_status host_solve(HostSolver* hs, std::complex<double>* b, int nrhs);
 size_t host_factor_bytes(const HostSolver* hs);
 double host_factor_flops(const HostSolver* hs);
+bool host_factor_is_fp32(const HostSolver* hs);
 void host_free(HostSolver* hs);
 
 }  // namespace ls

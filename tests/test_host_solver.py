@@ -112,3 +112,28 @@ def test_memory_cap_is_enforced():
     with pytest.raises(binding.LSError) as e:
         binding.SparseHost(n, rows, host_mem_cap=1000)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("nrhs", [1, 6])
+def test_host_fp32_factor_is_single_precision_solve(nrhs):
+    """complex64 factor: the solve equals the complex128 one to single-precision
+    accuracy (times the conditioning of S), and its block solve equals its
+    one-at-a-time solves."""
+    n = 7
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 6)
+    al, be, _ = ost.fit_all_classes(n, k)
+    S, _ = osp.assemble(n, m, al, be)
+    rows = csr_to_rows(S, n)
+    sp64 = binding.SparseHost(n, rows)
+    sp32 = binding.SparseHost(n, rows, prec="c64")
+    assert sp32.info()["bytes"] * 2 == sp64.info()["bytes"]
+    b = I.random_field(nrhs, n, 90 + nrhs)
+    x64 = sp64.solve(b)
+    x32 = sp32.solve(b)
+    assert x32.dtype == np.complex128
+    rel = np.abs(x32 - x64).max() / np.abs(x64).max()
+    assert 1e-9 < rel <= 1e-4, rel                 # single, not double, precision
+    if nrhs > 1:
+        one = sp32.solve(b[1:2])[0]
+        assert np.abs(x32[1] - one).max() <= 1e-5 * np.abs(one).max()
