@@ -47,6 +47,7 @@ namespace {
 
 constexpr int kLeafPoints = 64;
 constexpr int kNB = 32;         // panel width of the blocked partial LU
+constexpr long kPanelTask = 65536;   // panel updates above this many entries run as row tasks
 
 // geometry of one node of the dissection tree (shared by both precisions)
 struct Geom {
@@ -92,56 +93,77 @@ inline int front_pos(const Geom& nd, int p) {
 
 // ---- kernels: one template body, multiversioned per real type -------------------
 
+// Y[a][r] -= sum_k A[a][k] X[k][r] for MR rows a, RB right-hand sides r.
+template <typename R, int MR, int RB>
+LS_INLINE void mk_sub(const R* __restrict__ Ar, const R* __restrict__ Ai, long lda, long K,
+                      const R* __restrict__ Xr, const R* __restrict__ Xi, long ldx, R* __restrict__ Yr,
+                      R* __restrict__ Yi) {
+  R cr[MR][RB], ci[MR][RB];
+  for (int a = 0; a < MR; ++a)
+    for (int r = 0; r < RB; ++r) cr[a][r] = ci[a][r] = 0;
+  for (long k = 0; k < K; ++k) {
+    const R* xr = Xr + k * ldx;
+    const R* xi = Xi + k * ldx;
+    for (int a = 0; a < MR; ++a) {
+      const R ar = Ar[a * lda + k], ai = Ai[a * lda + k];
+#pragma omp simd
+      for (int r = 0; r < RB; ++r) {
+        cr[a][r] += ar * xr[r] - ai * xi[r];
+        ci[a][r] += ar * xi[r] + ai * xr[r];
+      }
+    }
+  }
+  for (int a = 0; a < MR; ++a)
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      Yr[a * ldx + r] -= cr[a][r];
+      Yi[a * ldx + r] -= ci[a][r];
+    }
+}
+
 // C[i][j] -= sum_k A[i][k] B[k][j] over rows [r0, r1), cols [c0, c1), k in [k0, k1)
-// of one row-major planar matrix (lda = nf).  Four rows at a time share B loads.
+// of one row-major planar matrix F (A = F[.][k], B = F[k][.], C = F, lda = nf):
+// 4 x 16 blocks of C stay in registers across the panel (mk_sub), column
+// blocks of 256 outside so the panel rows they read stay in L2.
 template <typename R>
 LS_INLINE void gemm_rows_t(R* __restrict__ Fr, R* __restrict__ Fi, long nf, long r0, long r1, long c0, long c1,
                            long k0, long k1) {
+  const long K = k1 - k0;
+  const R* Ar = Fr + k0;
+  const R* Ai = Fi + k0;
+  const R* Br = Fr + k0 * nf;
+  const R* Bi = Fi + k0 * nf;
   constexpr long JB = 256;
   for (long jb = c0; jb < c1; jb += JB) {
     const long je = std::min(c1, jb + JB);
-    long i = r0;
-    for (; i + 4 <= r1; i += 4) {
-      R* c0r = Fr + i * nf;
-      R* c0i = Fi + i * nf;
-      R* c1r = c0r + nf;
-      R* c1i = c0i + nf;
-      R* c2r = c1r + nf;
-      R* c2i = c1i + nf;
-      R* c3r = c2r + nf;
-      R* c3i = c2i + nf;
-      for (long k = k0; k < k1; ++k) {
-        const R a0r = c0r[k], a0i = c0i[k], a1r = c1r[k], a1i = c1i[k];
-        const R a2r = c2r[k], a2i = c2i[k], a3r = c3r[k], a3i = c3i[k];
-        const R* br = Fr + k * nf;
-        const R* bi = Fi + k * nf;
-#pragma omp simd
-        for (long j = jb; j < je; ++j) {
-          const R xr = br[j], xi = bi[j];
-          c0r[j] -= a0r * xr - a0i * xi;
-          c0i[j] -= a0r * xi + a0i * xr;
-          c1r[j] -= a1r * xr - a1i * xi;
-          c1i[j] -= a1r * xi + a1i * xr;
-          c2r[j] -= a2r * xr - a2i * xi;
-          c2i[j] -= a2r * xi + a2i * xr;
-          c3r[j] -= a3r * xr - a3i * xi;
-          c3i[j] -= a3r * xi + a3i * xr;
-        }
+    for (long i = r0; i < r1;) {
+      const bool quad = i + 4 <= r1;
+      long j = jb;
+      if (quad) {
+        for (; j + 16 <= je; j += 16)
+          mk_sub<R, 4, 16>(Ar + i * nf, Ai + i * nf, nf, K, Br + j, Bi + j, nf, Fr + i * nf + j, Fi + i * nf + j);
+        for (; j + 4 <= je; j += 4)
+          mk_sub<R, 4, 4>(Ar + i * nf, Ai + i * nf, nf, K, Br + j, Bi + j, nf, Fr + i * nf + j, Fi + i * nf + j);
+      } else {
+        for (; j + 16 <= je; j += 16)
+          mk_sub<R, 1, 16>(Ar + i * nf, Ai + i * nf, nf, K, Br + j, Bi + j, nf, Fr + i * nf + j, Fi + i * nf + j);
+        for (; j + 4 <= je; j += 4)
+          mk_sub<R, 1, 4>(Ar + i * nf, Ai + i * nf, nf, K, Br + j, Bi + j, nf, Fr + i * nf + j, Fi + i * nf + j);
       }
-    }
-    for (; i < r1; ++i) {
-      R* cr = Fr + i * nf;
-      R* ci = Fi + i * nf;
-      for (long k = k0; k < k1; ++k) {
-        const R ar = cr[k], ai = ci[k];
-        const R* br = Fr + k * nf;
-        const R* bi = Fi + k * nf;
-#pragma omp simd
-        for (long j = jb; j < je; ++j) {
-          cr[j] -= ar * br[j] - ai * bi[j];
-          ci[j] -= ar * bi[j] + ai * br[j];
+      const long rows = quad ? 4 : 1;
+      for (; j < je; ++j)                  // fewer than four columns left
+        for (long a = i; a < i + rows; ++a) {
+          R sr = 0, si = 0;
+          for (long k = 0; k < K; ++k) {
+            const R ar = Ar[a * nf + k], ai = Ai[a * nf + k];
+            const R br = Br[k * nf + j], bi = Bi[k * nf + j];
+            sr += ar * br - ai * bi;
+            si += ar * bi + ai * br;
+          }
+          Fr[a * nf + j] -= sr;
+          Fi[a * nf + j] -= si;
         }
-      }
+      i += rows;
     }
   }
 }
@@ -193,34 +215,6 @@ inline void cdot(const float* ar, const float* ai, const float* xr, const float*
 // entry is broadcast against a short vector of right-hand sides, so each
 // factor row is streamed once per 16 right-hand sides and the arithmetic
 // vectorises over r.
-
-// Y[a][r] -= sum_k A[a][k] X[k][r] for MR rows a, RB right-hand sides r.
-template <typename R, int MR, int RB>
-LS_INLINE void mk_sub(const R* __restrict__ Ar, const R* __restrict__ Ai, long lda, long K,
-                      const R* __restrict__ Xr, const R* __restrict__ Xi, long ldx, R* __restrict__ Yr,
-                      R* __restrict__ Yi) {
-  R cr[MR][RB], ci[MR][RB];
-  for (int a = 0; a < MR; ++a)
-    for (int r = 0; r < RB; ++r) cr[a][r] = ci[a][r] = 0;
-  for (long k = 0; k < K; ++k) {
-    const R* xr = Xr + k * ldx;
-    const R* xi = Xi + k * ldx;
-    for (int a = 0; a < MR; ++a) {
-      const R ar = Ar[a * lda + k], ai = Ai[a * lda + k];
-#pragma omp simd
-      for (int r = 0; r < RB; ++r) {
-        cr[a][r] += ar * xr[r] - ai * xi[r];
-        ci[a][r] += ar * xi[r] + ai * xr[r];
-      }
-    }
-  }
-  for (int a = 0; a < MR; ++a)
-#pragma omp simd
-    for (int r = 0; r < RB; ++r) {
-      Yr[a * ldx + r] -= cr[a][r];
-      Yi[a * ldx + r] -= ci[a][r];
-    }
-}
 
 // rows [i0, i1) of Y -= A X; A row-major (lda), K columns; X, Y block vectors
 template <typename R>
@@ -379,19 +373,31 @@ void partial_lu(R* Fr, R* Fi, long nf, long np, int* ipiv, double* flops) {
         den = pr * pr;
       }
       const R ir = pr / den, ii = -pi / den;
-      for (long i = k + 1; i < nf; ++i) {
-        const R xr = Fr[i * nf + k], xi = Fi[i * nf + k];
-        const R lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
-        Fr[i * nf + k] = lr;
-        Fi[i * nf + k] = li;
-        R* rr = Fr + i * nf;
-        R* ri = Fi + i * nf;
+      // column k of L and the rank-1 update of the panel columns (k, ke);
+      // rows are independent, so a tall front splits them into tasks
+      auto panel_rows = [&](long i0, long i1) {
         const R* kr = Fr + k * nf;
         const R* ki = Fi + k * nf;
-        for (long j = k + 1; j < ke; ++j) {
-          rr[j] -= lr * kr[j] - li * ki[j];
-          ri[j] -= lr * ki[j] + li * kr[j];
+        for (long i = i0; i < i1; ++i) {
+          const R xr = Fr[i * nf + k], xi = Fi[i * nf + k];
+          const R lr = xr * ir - xi * ii, li = xr * ii + xi * ir;
+          Fr[i * nf + k] = lr;
+          Fi[i * nf + k] = li;
+          R* rr = Fr + i * nf;
+          R* ri = Fi + i * nf;
+          for (long j = k + 1; j < ke; ++j) {
+            rr[j] -= lr * kr[j] - li * ki[j];
+            ri[j] -= lr * ki[j] + li * kr[j];
+          }
         }
+      };
+      const long tall = nf - k - 1;
+      if (tall * (ke - k) > kPanelTask) {
+        constexpr long PR = 256;
+#pragma omp taskloop grainsize(1)
+        for (long i0 = k + 1; i0 < nf; i0 += PR) panel_rows(i0, std::min(nf, i0 + PR));
+      } else {
+        panel_rows(k + 1, nf);
       }
     }
     // block row: unit-lower solve for columns [ke, nf) of rows [kb, ke)
@@ -412,9 +418,11 @@ void partial_lu(R* Fr, R* Fi, long nf, long np, int* ipiv, double* flops) {
     const double work = (double)rows * (double)rows * (double)(ke - kb);
     *flops += 8.0 * work;
     if (work > 2e6) {
-      const long grain = std::max(8L, rows / (4 * omp_get_num_threads() + 1));
-#pragma omp taskloop grainsize(grain)
-      for (long i0 = ke; i0 < nf; i0 += 8) gemm_rows(Fr, Fi, nf, i0, std::min(nf, i0 + 8), ke, nf, kb, ke);
+      // 64-row tasks: each 256-column block of the panel rows stays in L2
+      // while 16 row quads use it
+      constexpr long TR = 64;
+#pragma omp taskloop grainsize(1)
+      for (long i0 = ke; i0 < nf; i0 += TR) gemm_rows(Fr, Fi, nf, i0, std::min(nf, i0 + TR), ke, nf, kb, ke);
     } else {
       gemm_rows(Fr, Fi, nf, ke, nf, ke, nf, kb, ke);
     }
