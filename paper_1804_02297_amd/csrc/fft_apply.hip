@@ -233,9 +233,12 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
   constexpr int KIN = (N2 + 1) / 2;     // t = j + N1 k < n <= P/2
   for (int b = team; b < B; b += W) {
     C<R>* base = X + (long)b * 3 * plane + lineoff;
-    // FP32: all loads of the three components are issued before any
-    // arithmetic (FP64 has no registers to spare for it)
-    constexpr bool PREFETCH = sizeof(R) == 4;
+    // FP32 at P >= 256: all loads of the three components are issued before
+    // any arithmetic.  Below that the kernel fits three waves per SIMD
+    // without the prefetch registers, which wins (P = 128, 16 rhs: 0.33 ms
+    // against 0.41 ms); at P = 256 it cannot, and the prefetch wins (1.05 ms
+    // against 1.12 ms).  FP64 has no registers to spare for it.
+    constexpr bool PREFETCH = sizeof(R) == 4 && P >= 256;
     C<R> pre[3][KIN];
     if (PREFETCH && active && j < N1) {
 #pragma unroll
