@@ -204,6 +204,44 @@ def _init_params(seed: int):
     return p
 
 
+def apply_192(binding, I, torch, steps: int, B: int = 8):
+    """The apply at n = 192 (padded 384^3 FFTs), FP32, 8 rhs: throughput and pass rates."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    n = 192
+    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
+    plan = binding.Plan(n, I.wavenumber_for(n), m, max_rhs=B)
+    P = plan.P
+    g = torch.Generator(device=dev).manual_seed(99)
+    x = torch.randn((B, 3, n, n, n), dtype=torch.complex64, device=dev, generator=g)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        plan.apply(x, y, prec="c64")
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(5, steps // 5)
+    e0.record()
+    for _ in range(reps):
+        plan.apply(x, y, prec="c64")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pms = np.zeros(5)
+    for _ in range(5):
+        pms += np.array(plan.apply_timed(x, y, prec="c64"))
+    pms /= 5
+    pb = pass_bytes(n, P, B, 8, 8)
+    plan.close()
+    del x, y
+    torch.cuda.empty_cache()
+    return {"n": n, "fft_size": P, "nrhs": B, "ms_per_apply": round(ms, 3),
+            "Munknowns_per_s": round(B * 3 * n ** 3 / (ms * 1e-3) / 1e6, 1),
+            "whole_GBps": round(sum(pb) / (ms * 1e-3) / 1e9, 1),
+            "pass_ms": [round(v, 4) for v in pms],
+            "pass_GBps": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(pb, pms)]}
+
+
 def hbm_copy_gbps(torch, gib: float = 2.0) -> float:
     """Device-to-device copy bandwidth (read + write bytes / time) of a torch copy."""
     n = int(gib * (1 << 30)) // 4
@@ -234,6 +272,7 @@ def main():
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
     ap.add_argument("--solve-n", type=int, default=32, help="grid of the per-rhs solve section (0: skip)")
     ap.add_argument("--solve-dirs", type=int, default=8, help="incident directions (2 polarisations each)")
     args = ap.parse_args()
@@ -320,6 +359,8 @@ def main():
         "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
         "wall_s_timed": round(wall32, 3),
     }
+    if args.n192:
+        out["apply_192"] = apply_192(binding, I, torch, args.steps)
     out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
     if args.solve_n:
         out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch)

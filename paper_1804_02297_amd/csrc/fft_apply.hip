@@ -71,12 +71,16 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // The dim-2 inverse (mode COL_INV) reads twice what it writes; it runs with
 // half-length runs, whose smaller LDS tile fits more workgroups per CU to
 // cover its read latency (measured at 128^3 and 64^3: 8 % faster, while the
-// other passes are fastest with full runs).
+// other passes are fastest with full runs).  The tile is capped at 64 KB of
+// LDS, except in the dim-1 passes (modes 0 and 3, whose rows lie n^2 apart)
+// which may use 96 KB so that P = 384 keeps full runs (192^3: 0.29 ms faster
+// over the two passes; the dim-2 forward is slower with 96 KB).
 template <typename R>
 constexpr int col_tile(int P, int mode) {
   int t = LS_COL_RUN_BYTES / (2 * (int)sizeof(R));
   if (mode == 2 && t > 8) t /= 2;
-  while (t > 8 && (long)P * t * 2 * (long)sizeof(R) > 65536) t /= 2;
+  const long cap = (mode == 0 || mode == 3) ? 98304 : 65536;
+  while (t > 8 && (long)P * t * 2 * (long)sizeof(R) > cap) t /= 2;
   return t;
 }
 
@@ -233,12 +237,13 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
   constexpr int KIN = (N2 + 1) / 2;     // t = j + N1 k < n <= P/2
   for (int b = team; b < B; b += W) {
     C<R>* base = X + (long)b * 3 * plane + lineoff;
-    // FP32 at P >= 256: all loads of the three components are issued before
-    // any arithmetic.  Below that the kernel fits three waves per SIMD
-    // without the prefetch registers, which wins (P = 128, 16 rhs: 0.33 ms
-    // against 0.41 ms); at P = 256 it cannot, and the prefetch wins (1.05 ms
+    // FP32 at P = 256: all loads of the three components are issued before
+    // any arithmetic.  Without the prefetch registers the kernel fits more
+    // waves per SIMD, which wins elsewhere (P = 128, 16 rhs: 0.33 against
+    // 0.41 ms, three waves; P = 384: 5.6 against 10.4 ms, two waves instead
+    // of one); at P = 256 it still fits only two, and the prefetch wins (1.05
     // against 1.12 ms).  FP64 has no registers to spare for it.
-    constexpr bool PREFETCH = sizeof(R) == 4 && P >= 256;
+    constexpr bool PREFETCH = sizeof(R) == 4 && P == 256;
     C<R> pre[3][KIN];
     if (PREFETCH && active && j < N1) {
 #pragma unroll

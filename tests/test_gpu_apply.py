@@ -132,17 +132,18 @@ def _direct_sample(n, k, m, x, pts):
     return np.array(out)
 
 
+@pytest.mark.parametrize("n", [128, 192])
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-12), ("mixed", 1e-5), ("c64", 1e-5)])
-def test_full_size_sampled(lib, prec, tol):
-    """n = 128 (the benchmark workload): sampled outputs against the direct sum."""
+def test_full_size_sampled(lib, prec, tol, n):
+    """n = 128 (the benchmark workload) and n = 192 (P = 384, the largest FFT
+    length): sampled outputs against the direct sum."""
     from paper_1804_02297_amd.binding import Plan
-    n = 128
     k = I.wavenumber_for(n)
     m = I.medium_bumps(n, 3)
     x = I.random_field(1, n, 11)
     rng = np.random.default_rng(0)
     pts = [tuple(rng.integers(0, n, 3)) for _ in range(4)] + [(0, 0, 0), (n - 1, n - 1, n - 1)]
-    print(f"full-size apply {prec}", flush=True)
+    print(f"full-size apply {prec} n={n}", flush=True)
     plan = Plan(n, k, _dev(m), max_rhs=1)
     xin = x.astype(np.complex64) if prec == "c64" else x
     y = plan.apply(_dev(xin), prec=prec).cpu().numpy()[0]
