@@ -324,6 +324,167 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
   }
 }
 
+// ---- pass 3 with two lanes per transform column (FP64, P = 256 = 16 x 16) ----
+// The same transform as kmul_kernel, with each length-16 DFT of the four-step
+// split between two adjacent lanes by one radix-2 step, so a lane holds 8
+// values per component instead of 16 (96 instead of 192 VGPRs in FP64) and
+// the kernel fits two waves per SIMD instead of one:
+//   forward step 1 (column j, 8 nonzero inputs k < 8 since n <= P/2):
+//     V[j][2q'+h] = DFT8_k(x_k W16^{kh})[q']               (no lane exchange)
+//   forward step 3 (row q):
+//     X[q + 16(2s'+h)] = DFT8_j'((V[j'] + (-1)^h V[j'+8]) W16^{j'h})[s']
+//   inverse step 1' (row q, lane h holds s = 2s'+h):
+//     E / O = IDFT8 of the even / odd s, y[t'+8m] = E[t'] + (-1)^m W16^{-t'} O[t'];
+//     the pair swaps its 8 values once (DPP) and lane h keeps t2 = t' + 8h
+//   inverse step 3' (column t2, outputs t1 = 2t1'+h < 8):
+//     DFT8^-1_q'((Y[q'] + (-1)^h Y[q'+8]) W16^{-q'h})[t1']
+// A job (one line) is 32 lanes, a team (the four mirrored lines) two
+// wavefronts; exchanges stay inside a job's half wavefront.  In FP32 the
+// extra radix-2 work outweighs the occupancy (both fit two waves), so the
+// FP32 path keeps kmul_kernel.
+__device__ __forceinline__ int dpp_pair(int x) {
+  // quad_perm [1, 0, 3, 2]: the adjacent lane's value
+  return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float pair_swap(float x) { return __int_as_float(dpp_pair(__float_as_int(x))); }
+__device__ __forceinline__ double pair_swap(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_pair((int)(b & 0xffffffffLL)), hi = dpp_pair((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename R, int W>
+__global__ __launch_bounds__(W * 128) void kmul2_kernel(C<R>* __restrict__ X, const C<R>* __restrict__ Kh,
+                                                         const C<R>* __restrict__ tw, int n, int B) {
+  constexpr int P = 256, N = 16, H = P / 2 + 1;
+  constexpr int EXS = N * (N + 1);            // padded exchange of one job
+  __shared__ C<R> kl[6 * H];
+  __shared__ C<R> twl[P];
+  __shared__ C<R> ex[W * 4 * EXS];
+  const int f1 = blockIdx.x / H;
+  const int f2 = blockIdx.x % H;
+  const int tid = threadIdx.x;
+  const int team = tid / 128;
+  const int lt = tid % 128;
+  const int job = lt / 32;
+  const int col = (lt % 32) >> 1;             // column / row index of the current step
+  const int h = lt & 1;                       // which half of the radix-2 split
+  const int s1 = job & 1, s2 = job >> 1;
+  const bool edge1 = (f1 == 0) || (2 * f1 == P);
+  const bool edge2 = (f2 == 0) || (2 * f2 == P);
+  const bool active = !((s1 && edge1) || (s2 && edge2));
+  const int q1 = s1 ? P - f1 : f1;
+  const int q2 = s2 ? P - f2 : f2;
+  const long plane = (long)P * P * n;
+  const long lineoff = ((long)q1 * P + q2) * n;
+
+  const C<R>* kg = Kh + ((long)f1 * H + f2) * 6 * H;
+  for (int e = tid; e < 6 * H; e += W * 128) kl[e] = kg[e];
+  for (int e = tid; e < P; e += W * 128) twl[e] = tw[e];
+  const R sxy = (s1 != s2) ? (R)-1 : (R)1;
+  const R sx = s1 ? (R)-1 : (R)1;
+  const R sy = s2 ? (R)-1 : (R)1;
+  const R sg = h ? (R)-1 : (R)1;              // (-1)^h
+  __syncthreads();
+
+  C<R>* myex = ex + (team * 4 + job) * EXS;
+  // z W16^{k h} (forward) and z W16^{-k h} (inverse): multiply by the
+  // compile-time constant, then select, so no per-lane twiddle registers
+  auto hf = [&](C<R> z, int k) { const C<R> w = z * ctw<R, 16, -1>(k); return h ? w : z; };
+  auto hi = [&](C<R> z, int k) { const C<R> w = z * ctw<R, 16, 1>(k); return h ? w : z; };
+
+  for (int b = team; b < B; b += W) {
+    C<R>* base = X + (long)b * 3 * plane + lineoff;
+    C<R> u[3][8];                             // frequencies col + 16 h + 32 s'
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (active) {
+        C<R> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int tt = col + N * k;
+          const C<R> x = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+          v[k] = (k == 0) ? x : hf(x, k);
+        }
+        Dft<8, -1, R>::run(v);
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          const int q = 2 * qq + h;
+          myex[q * (N + 1) + col] = (col * q == 0) ? v[qq] : v[qq] * twl[col * q];
+        }
+      }
+      wave_lds_sync();
+      if (active) {
+        C<R> y[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const C<R> a = myex[col * (N + 1) + j], bb = myex[col * (N + 1) + j + 8];
+          const C<R> d = cmk(a.re + sg * bb.re, a.im + sg * bb.im);
+          y[j] = (j == 0) ? d : hf(d, j);
+        }
+        Dft<8, -1, R>::run(y);
+#pragma unroll
+        for (int ss = 0; ss < 8; ++ss) u[c][ss] = y[ss];
+      }
+      wave_lds_sync();
+    }
+    if (active) {
+#pragma unroll
+      for (int ss = 0; ss < 8; ++ss) {
+        const int q3 = col + N * h + 2 * N * ss;
+        const bool fl3 = 2 * q3 > P;
+        const int f3 = fl3 ? P - q3 : q3;
+        const R s3 = fl3 ? (R)-1 : (R)1;
+        const C<R> kxx = kl[0 * H + f3], kyy = kl[1 * H + f3], kzz = kl[2 * H + f3];
+        const C<R> kxy = cscale(kl[3 * H + f3], sxy);
+        const C<R> kxz = cscale(kl[4 * H + f3], sx * s3);
+        const C<R> kyz = cscale(kl[5 * H + f3], sy * s3);
+        const C<R> ux = u[0][ss], uy = u[1][ss], uz = u[2][ss];
+        u[0][ss] = kxx * ux + kxy * uy + kxz * uz;
+        u[1][ss] = kxy * ux + kyy * uy + kyz * uz;
+        u[2][ss] = kxz * ux + kyz * uy + kzz * uz;
+        if ((ss & 3) == 3) asm volatile("" ::: "memory");   // bound the LDS prefetch depth
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (active) {
+        C<R> z[8];
+#pragma unroll
+        for (int ss = 0; ss < 8; ++ss) z[ss] = u[c][ss];
+        Dft<8, 1, R>::run(z);
+#pragma unroll
+        for (int t = 1; t < 8; ++t) z[t] = hi(z[t], t);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const C<R> pz = cmk(pair_swap(z[t].re), pair_swap(z[t].im));
+          const C<R> e = h ? pz : z[t], o = h ? z[t] : pz;
+          const C<R> y = cmk(e.re + sg * o.re, e.im + sg * o.im);
+          const int t2 = t + 8 * h;
+          myex[col * (N + 1) + t2] = (col * t2 == 0) ? y : y * cconj(twl[col * t2]);
+        }
+      }
+      wave_lds_sync();
+      if (active) {
+        C<R> v[8];
+#pragma unroll
+        for (int qq = 0; qq < 8; ++qq) {
+          const C<R> a = myex[qq * (N + 1) + col], bb = myex[(qq + 8) * (N + 1) + col];
+          const C<R> d = cmk(a.re + sg * bb.re, a.im + sg * bb.im);
+          v[qq] = (qq == 0) ? d : hi(d, qq);
+        }
+        Dft<8, 1, R>::run(v);
+#pragma unroll
+        for (int t1 = 0; t1 < 4; ++t1) {
+          const int tt = col + N * (2 * t1 + h);
+          if (tt < n) base[c * plane + tt] = v[t1];
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
 // ---- plain row FFT along the contiguous dimension (plan set-up only) --------
 // X: nlines lines of length P, transformed in place (forward).
 template <typename R, int P, int N1, int N2>
@@ -463,6 +624,15 @@ template <typename R, int P>
 static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, int wt, hipStream_t s) {
   constexpr Fac f = row_factors<R>(P);
   constexpr int TPL = cmax(f.n1, f.n2);
+  if constexpr (P == 256 && sizeof(R) == 8) {
+    // FP64: paired lanes; teams are two wavefronts, one or two per workgroup
+    constexpr int H = P / 2 + 1;
+    if (wt >= 2 && B >= 2)
+      hipLaunchKernelGGL((kmul2_kernel<R, 2>), dim3(H * H), dim3(256), 0, s, X, Kh, tw, n, B);
+    else
+      hipLaunchKernelGGL((kmul2_kernel<R, 1>), dim3(H * H), dim3(128), 0, s, X, Kh, tw, n, B);
+    return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
+  }
   if (wt <= 0) wt = 2;
   if constexpr (4 * TPL == 64) {
     if (wt >= 4 && B >= 4) return launch_kmul_w<R, P, 4>(X, Kh, tw, n, B, s);

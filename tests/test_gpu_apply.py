@@ -61,10 +61,11 @@ def test_apply_fp32_and_mixed_match_oracle(lib, n):
 
 
 @pytest.mark.parametrize("n", [100, 128])
-def test_apply_fp32_full_field_at_p256(lib, n):
-    """P = 256 (the benchmark's FFT length, its own pass-3 kernel): every output
-    of 2 rhs against the oracle, with one and two teams per workgroup (which
-    must agree bitwise); n = 100 leaves a ragged tail in every dimension."""
+def test_apply_full_field_at_p256(lib, n):
+    """P = 256 (the benchmark's FFT length; FP64 has its own paired-lane pass-3
+    kernel there): every output of 2 rhs against the oracle in all three
+    precisions, with one and two teams per workgroup (which must agree
+    bitwise); n = 100 leaves a ragged tail in every dimension."""
     from paper_1804_02297_amd.binding import Plan
     k = I.wavenumber_for(n)
     m = I.medium_bumps(n, 2)
@@ -75,12 +76,15 @@ def test_apply_fp32_full_field_at_p256(lib, n):
     assert plan.P == 256
     outs = {}
     for w in (1, 2):
-        plan.set_tune("c64", 0, w)
-        plan.set_tune("mixed", 0, w)
-        outs[w] = (plan.apply(_dev(x.astype(np.complex64)), prec="c64"), plan.apply(_dev(x), prec="mixed"))
+        for pr in ("c64", "mixed", "c128"):
+            plan.set_tune(pr, 0, w)
+        outs[w] = (plan.apply(_dev(x.astype(np.complex64)), prec="c64"), plan.apply(_dev(x), prec="mixed"),
+                   plan.apply(_dev(x), prec="c128"))
         assert _rel(outs[w][0].cpu().numpy(), ref) <= 1e-5, w
         assert _rel(outs[w][1].cpu().numpy(), ref) <= 1e-5, w
-    assert torch.equal(outs[1][0], outs[2][0]) and torch.equal(outs[1][1], outs[2][1])
+        assert _rel(outs[w][2].cpu().numpy(), ref) <= 1e-12, w
+    for i in range(3):
+        assert torch.equal(outs[1][i], outs[2][i]), i
 
 
 def test_zero_contrast_is_exact_identity(lib):
