@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "f917a759ea9d85c6cab594f1b5b87599239ae1529e44d227d2c64ce7fdec521c",
+    "sha256": "8331e11e823553478f7603359e103dcd0e71c5b02e0db88e7ae4966375670c85",
     "workload": (128, 8, "c64"),
     "bytes": 3.3268e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
