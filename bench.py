@@ -97,7 +97,8 @@ def cpu_baseline(n: int, seconds: float = 15.0):
                       f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
 
 
-def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500):
+def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500,
+                  exact_iters: bool = True):
     """Per-rhs time to a 1e-8 relative residual: plain FP64 against the chosen form.
 
     Plain: class stencils (the paper's 27 fits), complex128 factor, FP64
@@ -152,8 +153,18 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
     run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
     t_plain, (x1, inf1, st1) = run(g[:1], "c128")
     _progress(f"plain FP64 solve: {t_plain:.3f} s")
-    # --- chosen path: exact per-point fit (for its time), then the learned fit
+    # the FP32 apply alone: class stencils, complex128 factor, one rhs
+    t_f32one, (_, inf32, st32) = run(g[:1], "mixed")
+    _progress(f"FP32-apply single-rhs solve: {t_f32one:.3f} s")
+    # --- chosen path: exact per-point fit (for its time and, optionally, its
+    # iterations), then the learned fit
     t_fit_pt, _ = timed(lambda: plan.stencil_fit(1))
+    exact = None
+    if exact_iters:
+        plan.factor("c64")
+        _, (_, infx, stx) = run(g[:1], "mixed")
+        exact = {"iters": infx[0]["iters"], "status": stx}
+        _progress(f"exact per-point stencils: {infx[0]['iters']} iterations")
     t_fit_lrn, nfb = timed(lambda: plan.stencil_fit_learned(net))
     _progress(f"learned fit: {nfb} of {len(interior)} points fell back")
     t_fac_lrn, _ = timed(lambda: plan.factor("c64"))              # complex64 preconditioner factor
@@ -174,8 +185,10 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
         "chosen_s_per_rhs": round(t_mixed / nb, 4),
         "chosen_iters_max": max(i["iters"] for i in infb),
         "chosen_max_rel_resid_fp64": float(f"{rel:.3e}"),
-        "status": [st1, stb],
+        "status": [st1, st32, stb],
         "speedup_per_rhs": round(t_plain / (t_mixed / nb), 2),
+        "fp32_apply_single_rhs_s": round(t_f32one, 4), "fp32_apply_single_rhs_iters": inf32[0]["iters"],
+        "exact_point_stencils_iters": exact["iters"] if exact else None,
         "chosen_gpu_s": round(max(i["t_gpu"] for i in infb), 4),
         "chosen_host_s": round(max(i["t_host"] for i in infb), 4),
         "learned_fallback_points": int(nfb), "interior_points": len(interior),
@@ -275,6 +288,8 @@ def main():
     ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
     ap.add_argument("--solve-n", type=int, default=32, help="grid of the per-rhs solve section (0: skip)")
     ap.add_argument("--solve-dirs", type=int, default=8, help="incident directions (2 polarisations each)")
+    ap.add_argument("--solve-exact", type=int, default=-1,
+                    help="also solve with the exact per-point stencils (1/0; default: when n <= 48)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -363,7 +378,8 @@ def main():
         out["apply_192"] = apply_192(binding, I, torch, args.steps)
     out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
     if args.solve_n:
-        out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch)
+        ex = (args.solve_n <= 48) if args.solve_exact < 0 else bool(args.solve_exact)
+        out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch, exact_iters=ex)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)
