@@ -108,3 +108,29 @@ def test_forced_failure_paths(lib):
     x, info, st = plan.solve(g, tol=1e-30, maxit=2)
     assert st == -4
     assert info[0]["iters"] == 2 and info[0]["rel_resid"] < 1.0
+
+
+def test_reciprocity_of_gpu_solutions(lib):
+    """Total fields E = E^i + x from two incident waves satisfy
+    (E^i_a)^T diag(m) E_b = (E^i_b)^T diag(m) E_a (unconjugated): M (I + K M)^-1
+    is symmetric because K(r) is a symmetric tensor, even in r.  A property of
+    the exact solution, checked on the GPU solves at a size the dense matrix
+    cannot reach; the solve tolerance bounds the defect."""
+    from paper_1804_02297_amd.binding import Plan
+    n = 24
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 8)
+    dirs = np.array([[1.0, 0, 0], [0, 0.6, 0.8]])
+    pols = np.array([[0, 0, 1.0], [1.0, 0, 0]])
+    Ei = I.plane_waves(n, k, dirs, pols)
+    plan = Plan(n, k, _dev(m), max_rhs=2)
+    g = plan.rhs_from_incident(_dev(Ei))
+    plan.stencil_fit()
+    plan.factor()
+    x, info, st = plan.solve(g, tol=1e-11, restart=30, maxit=300)
+    assert st == 0, info
+    E = Ei + x.cpu().numpy()
+    ab = np.sum(Ei[0] * m[None] * E[1])
+    ba = np.sum(Ei[1] * m[None] * E[0])
+    print("reciprocity", ab, ba, flush=True)
+    assert abs(ab - ba) <= 1e-8 * max(abs(ab), abs(ba))
