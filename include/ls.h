@@ -58,7 +58,7 @@ typedef enum {
 } ls_prec;
 
 typedef struct {
-  int n;                 /* grid points per dimension, 3 <= n <= 384                   */
+  int n;                 /* grid points per dimension, 3 <= n <= 192 (FFT length <= 384) */
   double k;              /* background wavenumber k > 0                                */
   int max_rhs;           /* largest nrhs any later call will pass (>= 1)              */
   size_t host_mem_cap;   /* bytes the host factorisation may use; 0 = no cap           */
@@ -221,7 +221,9 @@ ls_status ls_mlp_get_params(const ls_mlp* mlp, float* params_host);
  * mean((y - t)^2), loss_out the loss.  Outputs may be NULL.  Synchronises. */
 ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float* t_host, int B, float* y_host,
                                   float* grad_host, double* loss_out, void* hip_stream);
-/* One Adam step (learning rate lr) with the gradient of the last backward pass. */
+/* One Adam step (learning rate lr > 0) with the gradient of the last backward
+ * pass; LS_ESTATE before any backward pass (ls_mlp_forward_backward or
+ * ls_mlp_train). */
 ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream);
 /* Exact per-point fits (LS_FIT_POINT definition) at the listed interior points
  * (linear indices (i1 n + i2) n + i3) of the plan's medium become training

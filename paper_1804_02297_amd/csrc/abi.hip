@@ -1,6 +1,7 @@
 // C ABI entry points (include/ls.h).  Argument checking and dispatch only;
 // the arithmetic lives in the kernels of the other translation units.
 #include <chrono>
+#include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -305,7 +306,8 @@ ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float*
 }
 
 ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream) {
-  if (!mlp) return LS_EINVAL;
+  if (!mlp || !(lr > 0.0) || !std::isfinite(lr)) return LS_EINVAL;
+  if (!mlp->st.have_grad) return LS_ESTATE;
   LS_TRY(mlp_adam(mlp->st, lr, as_stream(hip_stream)));
   LS_HIP(hipStreamSynchronize(as_stream(hip_stream)));
   return LS_OK;
@@ -337,7 +339,7 @@ ls_status ls_mlp_get_samples(const ls_mlp* mlp, float* x_host, float* t_host) {
 
 ls_status ls_mlp_train(ls_mlp* mlp, int steps, int batch, double lr, unsigned seed, double* loss_out,
                        void* hip_stream) {
-  if (!mlp) return LS_EINVAL;
+  if (!mlp || !(lr > 0.0) || !std::isfinite(lr)) return LS_EINVAL;
   return mlp_train(mlp->st, steps, batch, lr, seed, loss_out, as_stream(hip_stream));
 }
 

@@ -213,8 +213,8 @@ inline void cdot(const float* ar, const float* ai, const float* xr, const float*
 // ---- many right-hand sides: block vectors [dof][ldx], ldx a multiple of 4 -------
 // With the right-hand sides interleaved (entry (k, r) at k ldx + r), a factor
 // entry is broadcast against a short vector of right-hand sides, so each
-// factor row is streamed once per 16 right-hand sides and the arithmetic
-// vectorises over r.
+// factor row is streamed once per 16 (FP64) or 32 (FP32) right-hand sides and
+// the arithmetic vectorises over r.
 
 // rows [i0, i1) of Y -= A X; A row-major (lda), K columns; X, Y block vectors
 template <typename R>
@@ -223,7 +223,11 @@ LS_INLINE void gemm_sub_rows_t(const R* Ar, const R* Ai, long lda, long i0, long
   long i = i0;
   for (; i + 4 <= i1; i += 4)
     for (long r0 = 0; r0 < ldx;) {
-      if (ldx - r0 >= 16) {
+      if (sizeof(R) == 4 && ldx - r0 >= 32) {     // FP32: a 4 x 32 tile still fits the registers
+        mk_sub<R, 4, 32>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
+                         Yi + i * ldx + r0);
+        r0 += 32;
+      } else if (ldx - r0 >= 16) {
         mk_sub<R, 4, 16>(Ar + i * lda, Ai + i * lda, lda, K, Xr + r0, Xi + r0, ldx, Yr + i * ldx + r0,
                          Yi + i * ldx + r0);
         r0 += 16;
@@ -259,22 +263,50 @@ inline void gemm_sub_rows(const float* Ar, const float* Ai, long lda, long i0, l
   gemm_sub_rows_f(Ar, Ai, lda, i0, i1, K, Xr, Xi, ldx, Yr, Yi);
 }
 
-// W[i][r] -= L[i][k] W[k][r] for k in [b0, i), i in [b0, b1)  (within a diagonal block)
-template <typename R>
-LS_INLINE void lower_block_multi_t(const R* __restrict__ Lr, const R* __restrict__ Li, long np, long b0, long b1,
-                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+// W[i][r] -= L[i][k] W[k][r] for k in [b0, i), i in [b0, b1)  (within a diagonal block).
+// Row i of W is held in local accumulators for RB right-hand sides at a time
+// (rows i and k of W share one array, so the compiler cannot keep it in
+// registers on its own).
+template <typename R, int RB>
+LS_INLINE void lower_block_chunk(const R* __restrict__ Lr, const R* __restrict__ Li, long np, long b0, long b1,
+                                 R* __restrict__ Wr, R* __restrict__ Wi, long ldx, long r0) {
   for (long i = b0; i < b1; ++i) {
-    R* yr = Wr + i * ldx;
-    R* yi = Wi + i * ldx;
+    R yr[RB], yi[RB];
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      yr[r] = Wr[i * ldx + r0 + r];
+      yi[r] = Wi[i * ldx + r0 + r];
+    }
     for (long k = b0; k < i; ++k) {
       const R ar = Lr[i * np + k], ai = Li[i * np + k];
-      const R* xr = Wr + k * ldx;
-      const R* xi = Wi + k * ldx;
+      const R* xr = Wr + k * ldx + r0;
+      const R* xi = Wi + k * ldx + r0;
 #pragma omp simd
-      for (long r = 0; r < ldx; ++r) {
+      for (int r = 0; r < RB; ++r) {
         yr[r] -= ar * xr[r] - ai * xi[r];
         yi[r] -= ar * xi[r] + ai * xr[r];
       }
+    }
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      Wr[i * ldx + r0 + r] = yr[r];
+      Wi[i * ldx + r0 + r] = yi[r];
+    }
+  }
+}
+template <typename R>
+LS_INLINE void lower_block_multi_t(const R* __restrict__ Lr, const R* __restrict__ Li, long np, long b0, long b1,
+                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+  for (long r0 = 0; r0 < ldx;) {
+    if (ldx - r0 >= 16) {
+      lower_block_chunk<R, 16>(Lr, Li, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 16;
+    } else if (ldx - r0 >= 8) {
+      lower_block_chunk<R, 8>(Lr, Li, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 8;
+    } else {
+      lower_block_chunk<R, 4>(Lr, Li, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 4;
     }
   }
 }
@@ -295,19 +327,24 @@ inline void lower_block_multi(const float* Lr, const float* Li, long np, long b0
   lower_block_multi_f(Lr, Li, np, b0, b1, Wr, Wi, ldx);
 }
 
-// W[i][r] = (W[i][r] - sum_{k in (i, b1)} U[i][k] W[k][r]) / U[i][i], i from b1-1 down to b0
-template <typename R>
-LS_INLINE void upper_block_multi_t(const R* __restrict__ Ur, const R* __restrict__ Ui, long np, long b0, long b1,
-                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+// W[i][r] = (W[i][r] - sum_{k in (i, b1)} U[i][k] W[k][r]) / U[i][i], i from b1-1 down to b0,
+// row i held in local accumulators as above
+template <typename R, int RB>
+LS_INLINE void upper_block_chunk(const R* __restrict__ Ur, const R* __restrict__ Ui, long np, long b0, long b1,
+                                 R* __restrict__ Wr, R* __restrict__ Wi, long ldx, long r0) {
   for (long i = b1 - 1; i >= b0; --i) {
-    R* yr = Wr + i * ldx;
-    R* yi = Wi + i * ldx;
+    R yr[RB], yi[RB];
+#pragma omp simd
+    for (int r = 0; r < RB; ++r) {
+      yr[r] = Wr[i * ldx + r0 + r];
+      yi[r] = Wi[i * ldx + r0 + r];
+    }
     for (long k = i + 1; k < b1; ++k) {
       const R ar = Ur[i * np + k], ai = Ui[i * np + k];
-      const R* xr = Wr + k * ldx;
-      const R* xi = Wi + k * ldx;
+      const R* xr = Wr + k * ldx + r0;
+      const R* xi = Wi + k * ldx + r0;
 #pragma omp simd
-      for (long r = 0; r < ldx; ++r) {
+      for (int r = 0; r < RB; ++r) {
         yr[r] -= ar * xr[r] - ai * xi[r];
         yi[r] -= ar * xi[r] + ai * xr[r];
       }
@@ -316,10 +353,25 @@ LS_INLINE void upper_block_multi_t(const R* __restrict__ Ur, const R* __restrict
     const R den = ur * ur + ui * ui;
     const R qr = ur / den, qi = -ui / den;      // 1 / u
 #pragma omp simd
-    for (long r = 0; r < ldx; ++r) {
-      const R vr = yr[r], vi = yi[r];
-      yr[r] = vr * qr - vi * qi;
-      yi[r] = vr * qi + vi * qr;
+    for (int r = 0; r < RB; ++r) {
+      Wr[i * ldx + r0 + r] = yr[r] * qr - yi[r] * qi;
+      Wi[i * ldx + r0 + r] = yr[r] * qi + yi[r] * qr;
+    }
+  }
+}
+template <typename R>
+LS_INLINE void upper_block_multi_t(const R* __restrict__ Ur, const R* __restrict__ Ui, long np, long b0, long b1,
+                                   R* __restrict__ Wr, R* __restrict__ Wi, long ldx) {
+  for (long r0 = 0; r0 < ldx;) {
+    if (ldx - r0 >= 16) {
+      upper_block_chunk<R, 16>(Ur, Ui, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 16;
+    } else if (ldx - r0 >= 8) {
+      upper_block_chunk<R, 8>(Ur, Ui, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 8;
+    } else {
+      upper_block_chunk<R, 4>(Ur, Ui, np, b0, b1, Wr, Wi, ldx, r0);
+      r0 += 4;
     }
   }
 }
@@ -772,7 +824,7 @@ template <typename R>
 void gemm_sub(const R* Ar, const R* Ai, long lda, long m, long K, const R* Xr, const R* Xi, long ldx, R* Yr, R* Yi) {
   if (m <= 0 || K <= 0) return;
   if ((double)m * (double)K * (double)ldx > 4.0 * kParWork) {
-    constexpr long RT = 32;
+    constexpr long RT = 8;
 #pragma omp taskloop grainsize(1)
     for (long i0 = 0; i0 < m; i0 += RT) gemm_sub_rows(Ar, Ai, lda, i0, std::min(m, i0 + RT), K, Xr, Xi, ldx, Yr, Yi);
   } else {

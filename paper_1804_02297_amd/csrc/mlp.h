@@ -25,6 +25,7 @@ struct MlpState {
   DevBuf w, m, v, grad;              // FP32 masters, Adam moments, gradient
   DevBuf w1b, w2b, w3b;              // BF16 copies, zero-padded
   int t = 0;                         // Adam step count
+  bool have_grad = false;            // a backward pass has filled grad
   // activations / gradients workspace
   int ws_rows = 0;
   DevBuf z1, z2, h1b, h2b, y, dyb, dz2, dz2b, dz1, dz1b, dw, sq, part;

@@ -250,7 +250,9 @@ ls_status mlp_init(MlpState& st, const float* params_host, hipStream_t s) {
   LS_HIP(hipMemcpyAsync(st.w.p, params_host, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
   LS_HIP(hipMemsetAsync(st.m.p, 0, st.m.bytes, s));
   LS_HIP(hipMemsetAsync(st.v.p, 0, st.v.bytes, s));
+  LS_HIP(hipMemsetAsync(st.grad.p, 0, st.grad.bytes, s));
   st.t = 0;
+  st.have_grad = false;
   return mlp_refresh_bf16(st, s);
 }
 
@@ -347,6 +349,7 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
     for (int i = 0; i < 256; ++i) t += sq[i];
     *loss = t / ((double)Bm * MLP_O);
   }
+  st.have_grad = true;
   return LS_OK;
 }
 
