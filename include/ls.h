@@ -184,9 +184,23 @@ ls_status ls_factor(ls_plan* plan, double* seconds_out);
  * on the FP64 residual, possibly with more iterations.  Errors as ls_factor. */
 ls_status ls_factor_prec(ls_plan* plan, ls_prec factor_prec, double* seconds_out);
 
-/* Preconditioner z = S^-1 (Q v): Q v on the GPU, S^-1 on the host.
+/* Nested-dissection multifrontal LU of S on the GPU (the paper's sparse
+ * direct solve, Section 3.3, with every front in device memory): the same
+ * dissection as ls_factor, pivots chosen by magnitude within 48-row tiles of
+ * each front's pivot block (a whole number of points' three unknowns; on the
+ * tested media this picks the pivots of ls_factor), Schur complements on the
+ * matrix cores.  factor_prec LS_C128: complex128 factor; LS_C64 or
+ * LS_MIXED: complex64.  Replaces any earlier factor of the plan; from then
+ * on ls_precond_apply and ls_gmres_solve apply S^-1 on the GPU.  Device
+ * memory: about 8 (complex64) or 16 (complex128) bytes per factor entry, plus
+ * two levels of fronts while factoring.  LS_ENOMEM if it does not fit.
+ * seconds_out may be NULL.  LS_ESTATE before ls_stencil_fit.  Synchronises. */
+ls_status ls_factor_gpu(ls_plan* plan, ls_prec factor_prec, void* hip_stream, double* seconds_out);
+
+/* Preconditioner z = S^-1 (Q v): Q v on the GPU, S^-1 on the host (after
+ * ls_factor / ls_factor_prec) or on the GPU (after ls_factor_gpu).
  * v, z: device [nrhs][3][n][n][n] complex128 (may alias).  Synchronises.
- * LS_ESTATE before ls_factor. */
+ * LS_ESTATE before a factorisation. */
 ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream);
 
 /* Right-preconditioned FGMRES (restart `restart`, at most `maxit` operator
@@ -195,7 +209,8 @@ ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nr
  * the FP64 Krylov loop, with FP64 true-residual restarts).  g, x: device
  * [nrhs][3][n][n][n] complex128; info: host array of nrhs records.
  * LS_ENOCONV when maxit is reached (x holds the last iterate).  LS_ESTATE
- * before ls_factor.  Synchronises. */
+ * before a factorisation (ls_factor, ls_factor_prec or ls_factor_gpu).
+ * Synchronises. */
 ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
                          int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream);
 
@@ -255,7 +270,7 @@ void ls_mlp_destroy(ls_mlp* mlp);
  * assembles the rows, like ls_stencil_fit.  Synchronises. */
 ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out, void* hip_stream);
 
-/* ---- the host sparse solver on its own (host memory, no GPU) -------------- */
+/* ---- the sparse solver on its own (host or GPU factor) --------------------- */
 typedef struct ls_sparse ls_sparse;
 
 /* Factor rows given in the ls_get_rows layout on an n^3 grid; factor_prec as
@@ -264,6 +279,13 @@ ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_ca
                                 ls_sparse** out);
 /* Solve S x = b in place, b host [nrhs][3][n][n][n] complex128. */
 ls_status ls_sparse_solve_host(ls_sparse* sp, void* b_host, int nrhs);
+/* The same factorisation on the GPU (as ls_factor_gpu): rows_host in the
+ * ls_get_rows layout, copied to the device; 3 <= n <= 192. */
+ls_status ls_sparse_factor_gpu(int n, const void* rows_host, ls_prec factor_prec, void* hip_stream, ls_sparse** out);
+/* Solve S x = b in place on the GPU, b device [nrhs][3][n][n][n] complex128,
+ * stream-ordered.  LS_ESTATE for a host-factored ls_sparse (and
+ * ls_sparse_solve_host returns LS_ESTATE for a GPU-factored one). */
+ls_status ls_sparse_solve_gpu(ls_sparse* sp, void* b_dev, int nrhs, void* hip_stream);
 /* Factor size in bytes and factorisation flop count. */
 ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops);
 void ls_sparse_destroy(ls_sparse* sp);

@@ -46,6 +46,7 @@ SIGNATURES = [
     ("ls_get_rows", _I, [_VP, _VP]),
     ("ls_factor", _I, [_VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls_factor_prec", _I, [_VP, _I, ctypes.POINTER(ctypes.c_double)]),
+    ("ls_factor_gpu", _I, [_VP, _I, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
     ("ls_mlp_create", _I, [_VP, ctypes.POINTER(_VP)]),
@@ -62,6 +63,8 @@ SIGNATURES = [
     ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
     ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
+    ("ls_sparse_factor_gpu", _I, [_I, _VP, _I, _VP, ctypes.POINTER(_VP)]),
+    ("ls_sparse_solve_gpu", _I, [_VP, _VP, _I, _VP]),
     ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
     ("ls_sparse_destroy", None, [_VP]),
     ("ls_plan_fft_size", _I, [_VP]),
@@ -124,6 +127,30 @@ class SparseHost:
             self.close()
         except Exception:
             pass
+
+
+class SparseGpu(SparseHost):
+    """The GPU multifrontal solver on its own: rows from the host, factor and
+    solves in device memory."""
+
+    def __init__(self, n: int, rows, prec: str = "c128"):
+        import numpy as np
+        lib = load()
+        rows = np.ascontiguousarray(rows, dtype=np.complex128)
+        if rows.shape != (n ** 3, 3, 27, 3):
+            raise ValueError("rows must have shape (n^3, 3, 27, 3)")
+        self.n = n
+        h = ctypes.c_void_p()
+        _check(lib.ls_sparse_factor_gpu(n, rows.ctypes.data_as(ctypes.c_void_p), PREC[prec], _stream(),
+                                        ctypes.byref(h)), "ls_sparse_factor_gpu")
+        self._h = h
+
+    def solve(self, b):
+        """x = S^-1 b in place for a device tensor b (nrhs, 3, n, n, n) complex128."""
+        import torch
+        _field(b, torch.complex128, self.n, "b")
+        _check(_lib.ls_sparse_solve_gpu(self._h, _ptr(b), b.shape[0], _stream()), "ls_sparse_solve_gpu")
+        return b
 
 
 MLP_NPARAM = 250324
@@ -359,6 +386,12 @@ class Plan:
         r = np.zeros((self.n ** 3, 3, 27, 3), np.complex128)
         _check(_lib.ls_get_rows(self._h, r.ctypes.data_as(ctypes.c_void_p)), "ls_get_rows")
         return r
+
+    def factor_gpu(self, prec: str = "c128"):
+        """GPU multifrontal LU of S (complex128 or complex64 factor); returns seconds."""
+        t = ctypes.c_double()
+        _check(_lib.ls_factor_gpu(self._h, PREC[prec], _stream(), ctypes.byref(t)), "ls_factor_gpu")
+        return t.value
 
     def factor(self, prec: str = "c128"):
         """Host multifrontal LU of S (complex128 or complex64 factor); returns seconds."""

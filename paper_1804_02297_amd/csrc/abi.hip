@@ -29,6 +29,16 @@ static ls_status precond_list(ls_plan* plan, const std::vector<int>& lb,
   const long len = 3L * plan->ap.n * plan->ap.n * plan->ap.n;
   const size_t vb = (size_t)len * sizeof(C<double>);
   const int nb = (int)lb.size();
+  if (plan->gs) {   // GPU factor: Q v into a contiguous block, solve it in HBM, copy back
+    if (plan->qtmp.bytes < (size_t)nb * vb) LS_TRY(plan->qtmp.alloc((size_t)nb * vb));
+    C<double>* blk = plan->qtmp.as<C<double>>();
+    for (int q = 0; q < nb; ++q) LS_TRY(q_apply(plan->sd, plan->ap.n, ptr(lb[q]), blk + (size_t)q * len, 1, s));
+    LS_TRY(gpu_solve(plan->gs, blk, nb, s));
+    for (int q = 0; q < nb; ++q)
+      LS_HIP(hipMemcpyAsync(ptr(lb[q]), blk + (size_t)q * len, vb, hipMemcpyDeviceToDevice, s));
+    if (t_host) *t_host = 0.0;
+    return LS_OK;
+  }
   if (plan->qtmp.bytes < vb) LS_TRY(plan->qtmp.alloc(vb));
   plan->hbuf.resize((size_t)nb * len);
   for (int q = 0; q < nb; ++q) {
@@ -158,6 +168,8 @@ ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
   hipStream_t s = as_stream(hip_stream);
   host_free(plan->hs);
   plan->hs = nullptr;
+  gpu_free(plan->gs);
+  plan->gs = nullptr;
   plan->sd.have_point = false;
   plan->sd.have_rows = false;
   // the class stencils depend on (n, k) only: computed once per plan
@@ -207,14 +219,32 @@ ls_status ls_factor_prec(ls_plan* plan, ls_prec factor_prec, double* seconds_out
   LS_HIP(hipMemcpy(rows.data(), plan->sd.rows.p, plan->sd.rows.bytes, hipMemcpyDeviceToHost));
   host_free(plan->hs);
   plan->hs = nullptr;
+  gpu_free(plan->gs);
+  plan->gs = nullptr;
   LS_TRY(host_factor(plan->ap.n, rows.data(), plan->host_mem_cap, factor_prec != LS_C128, &plan->hs));
+  if (seconds_out) *seconds_out = now_s() - t0;
+  return LS_OK;
+}
+
+ls_status ls_factor_gpu(ls_plan* plan, ls_prec factor_prec, void* hip_stream, double* seconds_out) {
+  if (!plan) return LS_EINVAL;
+  if (factor_prec != LS_C128 && factor_prec != LS_C64 && factor_prec != LS_MIXED) return LS_EINVAL;
+  if (!plan->sd.have_rows) return LS_ESTATE;
+  hipStream_t s = as_stream(hip_stream);
+  LS_HIP(hipStreamSynchronize(s));
+  const double t0 = now_s();
+  host_free(plan->hs);
+  plan->hs = nullptr;
+  gpu_free(plan->gs);
+  plan->gs = nullptr;
+  LS_TRY(gpu_factor(plan->ap.n, plan->sd.rows.as<C<double>>(), factor_prec != LS_C128, s, &plan->gs));
   if (seconds_out) *seconds_out = now_s() - t0;
   return LS_OK;
 }
 
 ls_status ls_precond_apply(ls_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream) {
   if (!plan || !v_dev || !z_dev || nrhs < 1) return LS_EINVAL;
-  if (!plan->hs) return LS_ESTATE;
+  if (!plan->hs && !plan->gs) return LS_ESTATE;
   hipStream_t s = as_stream(hip_stream);
   const long len = plan->gctx.len;
   if (v_dev != z_dev)
@@ -230,7 +260,7 @@ ls_status ls_gmres_solve(ls_plan* plan, const void* g_dev, void* x_dev, int nrhs
   if (!plan || !g_dev || !x_dev || nrhs < 1 || !info || restart < 1 || maxit < 1 || !(tol > 0.0))
     return LS_EINVAL;
   if (apply_prec != LS_C128 && apply_prec != LS_MIXED) return LS_EINVAL;
-  if (!plan->hs) return LS_ESTATE;
+  if (!plan->hs && !plan->gs) return LS_ESTATE;
   hipStream_t s = as_stream(hip_stream);
   GmresOps ops;
   ops.apply = [plan](const C<double>* x, C<double>* y, int nb, ls_prec pr, hipStream_t st) {
@@ -406,6 +436,8 @@ ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out
   hipStream_t s = as_stream(hip_stream);
   host_free(plan->hs);
   plan->hs = nullptr;
+  gpu_free(plan->gs);
+  plan->gs = nullptr;
   plan->sd.have_point = false;
   plan->sd.have_rows = false;
   LS_TRY(learned_fit(plan->sd, mlp->st, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0,
@@ -435,13 +467,40 @@ ls_status ls_sparse_factor_host(int n, const void* rows_host, size_t host_mem_ca
 
 ls_status ls_sparse_solve_host(ls_sparse* sp, void* b_host, int nrhs) {
   if (!sp || !b_host || nrhs < 1) return LS_EINVAL;
+  if (!sp->hs) return LS_ESTATE;
   return host_solve(sp->hs, static_cast<std::complex<double>*>(b_host), nrhs);
+}
+
+ls_status ls_sparse_factor_gpu(int n, const void* rows_host, ls_prec factor_prec, void* hip_stream, ls_sparse** out) {
+  if (!rows_host || !out || n < 3 || n > 192) return LS_EINVAL;
+  if (factor_prec != LS_C128 && factor_prec != LS_C64 && factor_prec != LS_MIXED) return LS_EINVAL;
+  *out = nullptr;
+  hipStream_t s = as_stream(hip_stream);
+  const size_t rb = (size_t)n * n * n * 243 * sizeof(C<double>);
+  DevBuf rows;
+  LS_TRY(rows.alloc(rb));
+  LS_HIP(hipMemcpyAsync(rows.p, rows_host, rb, hipMemcpyHostToDevice, s));
+  ls_sparse* sp = new (std::nothrow) ls_sparse();
+  if (!sp) return LS_ENOMEM;
+  ls_status st = gpu_factor(n, rows.as<C<double>>(), factor_prec != LS_C128, s, &sp->gs);
+  if (st != LS_OK) {
+    delete sp;
+    return st;
+  }
+  *out = sp;
+  return LS_OK;
+}
+
+ls_status ls_sparse_solve_gpu(ls_sparse* sp, void* b_dev, int nrhs, void* hip_stream) {
+  if (!sp || !b_dev || nrhs < 1) return LS_EINVAL;
+  if (!sp->gs) return LS_ESTATE;
+  return gpu_solve(sp->gs, static_cast<C<double>*>(b_dev), nrhs, as_stream(hip_stream));
 }
 
 ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops) {
   if (!sp) return LS_EINVAL;
-  if (bytes) *bytes = host_factor_bytes(sp->hs);
-  if (flops) *flops = host_factor_flops(sp->hs);
+  if (bytes) *bytes = sp->gs ? gpu_factor_bytes(sp->gs) : host_factor_bytes(sp->hs);
+  if (flops) *flops = sp->gs ? gpu_factor_flops(sp->gs) : host_factor_flops(sp->hs);
   return LS_OK;
 }
 

@@ -1,0 +1,21 @@
+// GPU multifrontal sparse LU of the sparsified system S, fronts in HBM.
+#pragma once
+
+#include "common.h"
+
+namespace ls {
+
+struct GpuSolver;
+
+// rows_dev: device array [n^3][3 rows][27 slots][3 comps] of complex128 (the
+// layout of the plan's assembled rows).  fp32: keep the factor in complex64.
+// Synchronises the stream before returning.
+ls_status gpu_factor(int n, const C<double>* rows_dev, bool fp32, hipStream_t s, GpuSolver** out);
+// Solve S x = b in place on the device; b is [nrhs][3][n^3] complex128.
+ls_status gpu_solve(GpuSolver* gs, C<double>* b_dev, int nrhs, hipStream_t s);
+size_t gpu_factor_bytes(const GpuSolver* gs);
+double gpu_factor_flops(const GpuSolver* gs);
+bool gpu_factor_is_fp32(const GpuSolver* gs);
+void gpu_free(GpuSolver* gs);
+
+}  // namespace ls

@@ -1,0 +1,1071 @@
+// GPU multifrontal LU of the sparsified system S and its block solves.
+//
+// Paper: the assembled local rows form a sparse system that is factored by
+// nested dissection and used as the preconditioner (end of Section 3.1;
+// costs in Section 3.3).  The dissection is the host solver's (nd_tree.h);
+// here every front lives in HBM and a whole level of the tree is processed
+// by each launch (grid.y or grid.z runs over the level's fronts).
+//
+// Factorisation of a level:
+//   zero the fronts; assemble S's entries; extend-add the children's update
+//   blocks (child 0, then child 1: their targets overlap); then for each
+//   48-column step kb of the pivot block:
+//     diag_kernel   LU of the 48 x 48 diagonal tile in LDS, pivots searched
+//                   among the tile's rows; the tile's L^-1 and U^-1
+//     panel_kernel  L = F U^-1 below the tile, U = L^-1 P F right of it
+//     schur_kernel  F -= L U on the trailing block, complex product on
+//                   MFMA (v_mfma_*_16x16x4, FP32 or FP64)
+//   and copy the pivot rows and the boundary rows' pivot columns out.
+// Pivoting inside 48-row tiles (a multiple of the three unknowns of a
+// point) reproduces the host solver's partial pivoting over the whole pivot
+// block to rounding on the tested media: the pivots of S sit in each
+// point's own 3 x 3 diagonal block.
+//
+// Tile permutations are not applied to the L part left of the tile: the
+// forward solve applies a tile's permutation to its rows right before the
+// tile is solved, after every earlier tile has updated them.
+//
+// Solves (many right-hand sides): vectors in elimination order (each
+// node's pivots contiguous), right-hand side fastest, real and imaginary
+// parts in separate planes.  Forward by levels from the leaves: add the
+// children's update vectors, then per tile z = L^-1 P x and a right-looking
+// update of the rows below (pivot rows in place, boundary rows into the
+// node's update vector).  Backward from the root: subtract U12 x_boundary,
+// then per tile (last first) x = U^-1 z and the update of the rows above.
+#include "gpu_solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <memory>
+#include <vector>
+
+#include "nd_tree.h"
+
+namespace ls {
+
+namespace {
+
+constexpr int kT = 48;     // diagonal tile (pivot search window)
+constexpr int kRB = 64;    // rows or columns per workgroup in the panel and solve kernels
+constexpr int kRC = 16;    // right-hand sides per workgroup in the solve kernels
+constexpr int kTileElems = kT * kT;
+
+struct FrontDev {
+  int np, nb, nf, e0;   // pivot / boundary / front unknowns; first elimination index
+  int child[2];
+  long f;    // front in its level buffer: re plane [nf][nf], then the im plane
+  long p;    // factor: pivot rows [np][nf] (re plane, then im plane)
+  long l;    // factor: boundary rows' pivot columns [nb][np] (re, then im)
+  long t;    // factor: per tile Linv re, Linv im, Uinv re, Uinv im, each [kT][kT]
+  long pv;   // ints: per pivot, the tile row it was taken from
+  long am;   // ints: pivot rows, 27 front point positions per pivot point (-1: none)
+  long ab;   // ints: boundary rows, 27 pivot point positions per boundary point
+  long bp;   // ints: boundary point list (global point indices)
+  long xm;   // ints: boundary point a -> parent front point position
+  long bm;   // ints: boundary unknown j -> elimination index
+  long u;    // solve: first row of the node's update vector
+};
+
+// ---- MFMA operand conventions -------------------------------------------------------
+// v_mfma_{f32,f64}_16x16x4 (wave64): A lane l holds A[l % 16][l / 16], B lane l holds
+// B[l / 16][l % 16].  The 16 x 16 result sits in 4 registers per lane: the f32 form
+// holds D[4 (l / 16) + r][l % 16] in register r, the f64 form D[4 r + l / 16][l % 16].
+template <typename R>
+struct Mma;
+template <>
+struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+// ---- factorisation kernels ------------------------------------------------------------
+
+template <typename R>
+__global__ void zero_kernel(R* __restrict__ a, long cnt) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (long)gridDim.x * blockDim.x) a[i] = R(0);
+}
+
+// S's entries into the fronts of a level; each entry of S belongs to exactly
+// one front position, so plain additions do not collide.
+template <typename R>
+__global__ __launch_bounds__(256) void assemble_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                       int nlvl, const int* __restrict__ ib,
+                                                       const C<double>* __restrict__ rows, R* __restrict__ buf) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    const int npp = d.np / 3, nbp = d.nb / 3;
+    const long nf = d.nf;
+    R* Fr = buf + d.f;
+    R* Fi = Fr + nf * nf;
+    const long work = (long)(npp + nbp) * 27;
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < work; w += (long)gridDim.x * blockDim.x) {
+      const int a = (int)(w / 27), slot = (int)(w % 27);
+      int pt, lj;
+      if (a < npp) {
+        pt = ib[d.e0 + 3 * a];                         // perm (at offset 0): component 0 of point a
+        lj = ib[d.am + 27L * a + slot];
+      } else {
+        pt = ib[d.bp + (a - npp)];
+        lj = ib[d.ab + 27L * (a - npp) + slot];
+      }
+      if (lj < 0) continue;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C<double> v = rows[(((long)pt * 3 + r) * 27 + slot) * 3 + c];
+          const long o = (3L * a + r) * nf + 3L * lj + c;
+          Fr[o] += (R)v.re;
+          Fi[o] += (R)v.im;
+        }
+    }
+  }
+}
+
+// F_parent += child's update block (rows and columns mapped through the child's
+// boundary-to-parent positions), for child `slot` of every front of a level.
+template <typename R>
+__global__ __launch_bounds__(256) void extend_add_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                         int nlvl, int slot, const int* __restrict__ ib,
+                                                         const R* __restrict__ cbuf, R* __restrict__ buf) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (d.child[slot] < 0) continue;
+    const FrontDev c = fr[d.child[slot]];
+    const long nf = d.nf, cnf = c.nf, cnb = c.nb;
+    R* Fr = buf + d.f;
+    R* Fi = Fr + nf * nf;
+    const R* Cr = cbuf + c.f;
+    const R* Ci = Cr + cnf * cnf;
+    const long cnt = cnb * cnb;
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
+      const long r = w / cnb, s = w % cnb;
+      const long pr = 3L * ib[c.xm + r / 3] + r % 3;
+      const long ps = 3L * ib[c.xm + s / 3] + s % 3;
+      const long src = (c.np + r) * cnf + c.np + s;
+      Fr[pr * nf + ps] += Cr[src];
+      Fi[pr * nf + ps] += Ci[src];
+    }
+  }
+}
+
+// LU with partial pivoting of the diagonal tile [kb, kb + tw)^2 of every front
+// of a level (one workgroup per front), then the tile's L^-1 (unit lower) and
+// U^-1 (upper), stored for the panel kernel and the solves.
+template <typename R>
+__global__ __launch_bounds__(256) void diag_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl, int nlvl,
+                                                   int kb, R* __restrict__ buf, R* __restrict__ fac,
+                                                   int* __restrict__ ib) {
+  __shared__ R Dr[kT][kT + 1], Di[kT][kT + 1];
+  __shared__ R Xr[kT][kT + 1], Xi[kT][kT + 1];
+  __shared__ int perm[kT];
+  __shared__ int piv;
+  const int tid = threadIdx.x;
+  for (int q = blockIdx.x; q < nlvl; q += gridDim.x) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb >= d.np) continue;
+    const int tw = min(kT, d.np - kb);
+    const long nf = d.nf;
+    R* Fr = buf + d.f;
+    R* Fi = Fr + nf * nf;
+    for (int o = tid; o < tw * tw; o += blockDim.x) {
+      const int i = o / tw, c = o % tw;
+      Dr[i][c] = Fr[(kb + i) * nf + kb + c];
+      Di[i][c] = Fi[(kb + i) * nf + kb + c];
+    }
+    if (tid < tw) perm[tid] = tid;
+    __syncthreads();
+    for (int j = 0; j < tw; ++j) {
+      if (tid < 64) {
+        R v = R(-1);
+        int idx = tid;
+        if (tid >= j && tid < tw) v = Dr[tid][j] * Dr[tid][j] + Di[tid][j] * Di[tid][j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const R ov = __shfl_xor(v, off);
+          const int oi = __shfl_xor(idx, off);
+          if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+          }
+        }
+        if (tid == 0) piv = idx;
+      }
+      __syncthreads();
+      const int p = piv;
+      if (p != j) {
+        for (int c = tid; c < tw; c += blockDim.x) {
+          R t = Dr[j][c];
+          Dr[j][c] = Dr[p][c];
+          Dr[p][c] = t;
+          t = Di[j][c];
+          Di[j][c] = Di[p][c];
+          Di[p][c] = t;
+        }
+        if (tid == 0) {
+          const int t = perm[j];
+          perm[j] = perm[p];
+          perm[p] = t;
+        }
+      }
+      __syncthreads();
+      if (tid == 0 && Dr[j][j] == R(0) && Di[j][j] == R(0))
+        Dr[j][j] = sqrt(std::numeric_limits<R>::min());   // exactly singular tile: perturb (FGMRES absorbs it)
+      __syncthreads();
+      const R pr = Dr[j][j], pi = Di[j][j];
+      const R den = pr * pr + pi * pi;
+      const R ir = pr / den, ii = -pi / den;
+      for (int i = j + 1 + tid; i < tw; i += blockDim.x) {
+        const R xr = Dr[i][j], xi = Di[i][j];
+        Dr[i][j] = xr * ir - xi * ii;
+        Di[i][j] = xr * ii + xi * ir;
+      }
+      __syncthreads();
+      const int m = tw - j - 1;
+      for (int o = tid; o < m * m; o += blockDim.x) {
+        const int i = j + 1 + o / m, c = j + 1 + o % m;
+        const R lr = Dr[i][j], li = Di[i][j], ur = Dr[j][c], ui = Di[j][c];
+        Dr[i][c] -= lr * ur - li * ui;
+        Di[i][c] -= lr * ui + li * ur;
+      }
+      __syncthreads();
+    }
+    for (int o = tid; o < tw * tw; o += blockDim.x) {
+      const int i = o / tw, c = o % tw;
+      Fr[(kb + i) * nf + kb + c] = Dr[i][c];
+      Fi[(kb + i) * nf + kb + c] = Di[i][c];
+    }
+    if (tid < tw) ib[d.pv + kb + tid] = perm[tid];
+    R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems;
+    // L^-1, one column per thread: X[r][c] = -sum_{c <= k < r} L[r][k] X[k][c]
+    for (int c = tid; c < tw; c += blockDim.x) {
+      for (int r = 0; r < tw; ++r) {
+        if (r < c) {
+          Xr[r][c] = R(0);
+          Xi[r][c] = R(0);
+        } else if (r == c) {
+          Xr[r][c] = R(1);
+          Xi[r][c] = R(0);
+        } else {
+          R sr = R(0), si = R(0);
+          for (int k = c; k < r; ++k) {
+            sr += Dr[r][k] * Xr[k][c] - Di[r][k] * Xi[k][c];
+            si += Dr[r][k] * Xi[k][c] + Di[r][k] * Xr[k][c];
+          }
+          Xr[r][c] = -sr;
+          Xi[r][c] = -si;
+        }
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < tw * tw; o += blockDim.x) {
+      const int i = o / tw, c = o % tw;
+      T[i * kT + c] = Xr[i][c];
+      T[kTileElems + i * kT + c] = Xi[i][c];
+    }
+    __syncthreads();
+    // U^-1, one column per thread: X[c][c] = 1 / U[c][c],
+    // X[r][c] = -(sum_{r < k <= c} U[r][k] X[k][c]) / U[r][r]
+    for (int c = tid; c < tw; c += blockDim.x) {
+      for (int r = tw - 1; r > c; --r) {
+        Xr[r][c] = R(0);
+        Xi[r][c] = R(0);
+      }
+      for (int r = c; r >= 0; --r) {
+        R nr, ni;
+        if (r == c) {
+          nr = R(1);
+          ni = R(0);
+        } else {
+          R sr = R(0), si = R(0);
+          for (int k = r + 1; k <= c; ++k) {
+            sr += Dr[r][k] * Xr[k][c] - Di[r][k] * Xi[k][c];
+            si += Dr[r][k] * Xi[k][c] + Di[r][k] * Xr[k][c];
+          }
+          nr = -sr;
+          ni = -si;
+        }
+        const R ur = Dr[r][r], ui = Di[r][r];
+        const R dd = ur * ur + ui * ui;
+        const R vr = ur / dd, vi = -ui / dd;
+        Xr[r][c] = nr * vr - ni * vi;
+        Xi[r][c] = nr * vi + ni * vr;
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < tw * tw; o += blockDim.x) {
+      const int i = o / tw, c = o % tw;
+      T[2 * kTileElems + i * kT + c] = Xr[i][c];
+      T[3 * kTileElems + i * kT + c] = Xi[i][c];
+    }
+    __syncthreads();
+  }
+}
+
+// Workgroups [0, half): L = F U^-1 for 64 rows below the tile.
+// Workgroups [half, 2 half): U = L^-1 P F for 64 columns right of the tile.
+template <typename R>
+__global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                    int nlvl, int kb, int half, R* __restrict__ buf,
+                                                    const R* __restrict__ fac, const int* __restrict__ ib) {
+  __shared__ R Wr[kT][kT + 1], Wi[kT][kT + 1];
+  __shared__ R Br[kRB][kT + 1], Bi[kRB][kT + 1];
+  const int tid = threadIdx.x;
+  const bool lrole = (int)blockIdx.x < half;
+  const long blk = lrole ? blockIdx.x : blockIdx.x - half;
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb >= d.np) continue;
+    const int tw = min(kT, d.np - kb);
+    const long ke = kb + tw, nf = d.nf;
+    const long x0 = ke + blk * kRB;
+    if (x0 >= nf) continue;
+    const int cnt = (int)min((long)kRB, nf - x0);
+    R* Fr = buf + d.f;
+    R* Fi = Fr + nf * nf;
+    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems + (lrole ? 2 * kTileElems : 0);
+    for (int o = tid; o < tw * tw; o += blockDim.x) {
+      const int i = o / tw, c = o % tw;
+      Wr[i][c] = T[i * kT + c];
+      Wi[i][c] = T[kTileElems + i * kT + c];
+    }
+    if (lrole) {
+      for (int o = tid; o < cnt * tw; o += blockDim.x) {
+        const int i = o / tw, k = o % tw;
+        Br[i][k] = Fr[(x0 + i) * nf + kb + k];
+        Bi[i][k] = Fi[(x0 + i) * nf + kb + k];
+      }
+      __syncthreads();
+      for (int o = tid; o < cnt * tw; o += blockDim.x) {
+        const int i = o / tw, c = o % tw;
+        R sr = R(0), si = R(0);
+        for (int k = 0; k <= c; ++k) {
+          sr += Br[i][k] * Wr[k][c] - Bi[i][k] * Wi[k][c];
+          si += Br[i][k] * Wi[k][c] + Bi[i][k] * Wr[k][c];
+        }
+        Fr[(x0 + i) * nf + kb + c] = sr;
+        Fi[(x0 + i) * nf + kb + c] = si;
+      }
+    } else {
+      for (int o = tid; o < cnt * tw; o += blockDim.x) {
+        const int k = o / cnt, j = o % cnt;
+        const long src = (kb + ib[d.pv + kb + k]) * nf + x0 + j;
+        Br[j][k] = Fr[src];
+        Bi[j][k] = Fi[src];
+      }
+      __syncthreads();
+      for (int o = tid; o < cnt * tw; o += blockDim.x) {
+        const int r = o / cnt, j = o % cnt;
+        R sr = R(0), si = R(0);
+        for (int k = 0; k <= r; ++k) {
+          sr += Wr[r][k] * Br[j][k] - Wi[r][k] * Bi[j][k];
+          si += Wr[r][k] * Bi[j][k] + Wi[r][k] * Br[j][k];
+        }
+        Fr[(kb + r) * nf + x0 + j] = sr;
+        Fi[(kb + r) * nf + x0 + j] = si;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Trailing update F[ke:, ke:] -= L U (K = tw) on a 64 x 64 tile per workgroup;
+// four waves of 32 x 32, complex product as four real MFMA products.
+template <typename R>
+__global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                    int nlvl, int kb, R* __restrict__ buf) {
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar[64][17], Ai[64][17];
+  __shared__ R Br[16][65], Bi[16][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  for (int q = blockIdx.z; q < nlvl; q += gridDim.z) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb >= d.np) continue;
+    const int tw = min(kT, d.np - kb);
+    const long ke = kb + tw, nf = d.nf;
+    const long i0 = ke + 64L * blockIdx.y, j0 = ke + 64L * blockIdx.x;
+    if (i0 >= nf || j0 >= nf) continue;
+    R* Fr = buf + d.f;
+    R* Fi = Fr + nf * nf;
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+      }
+    for (int kc = 0; kc < tw; kc += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = tid + 256 * u;
+        const int ii = o >> 4, kk = o & 15;
+        const bool ok = i0 + ii < nf && kc + kk < tw;
+        const long src = (i0 + ii) * nf + kb + kc + kk;
+        Ar[ii][kk] = ok ? Fr[src] : R(0);
+        Ai[ii][kk] = ok ? Fi[src] : R(0);
+        const int kr = o >> 6, jj = o & 63;
+        const bool okb = kc + kr < tw && j0 + jj < nf;
+        const long srcb = (kb + kc + kr) * nf + j0 + jj;
+        Br[kr][jj] = okb ? Fr[srcb] : R(0);
+        Bi[kr][jj] = okb ? Fi[srcb] : R(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k4 = 0; k4 < 16; k4 += 4) {
+        const int kr = k4 + (lane >> 4);
+        R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          ar[a] = Ar[wm + 16 * a + (lane & 15)][kr];
+          ai[a] = Ai[wm + 16 * a + (lane & 15)][kr];
+          br[a] = Br[kr][wn + 16 * a + (lane & 15)];
+          bi[a] = Bi[kr][wn + 16 * a + (lane & 15)];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = Mma<R>::op(ar[a], br[b], cr[a][b]);
+            cr[a][b] = Mma<R>::op(-ai[a], bi[b], cr[a][b]);
+            ci[a][b] = Mma<R>::op(ar[a], bi[b], ci[a][b]);
+            ci[a][b] = Mma<R>::op(ai[a], br[b], ci[a][b]);
+          }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long gi = i0 + wm + 16 * a + Mma<R>::row(lane, r);
+          const long gj = j0 + wn + 16 * b + (lane & 15);
+          if (gi < nf && gj < nf) {
+            Fr[gi * nf + gj] -= cr[a][b][r];
+            Fi[gi * nf + gj] -= ci[a][b][r];
+          }
+        }
+  }
+}
+
+// pivot rows and the boundary rows' pivot columns into the factor
+template <typename R>
+__global__ __launch_bounds__(256) void copyout_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                      int nlvl, const R* __restrict__ buf, R* __restrict__ fac) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    const long nf = d.nf, np = d.np, nb = d.nb;
+    const R* Fr = buf + d.f;
+    const R* Fi = Fr + nf * nf;
+    const long c1 = np * nf, c2 = nb * np;
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < c1 + c2; w += (long)gridDim.x * blockDim.x) {
+      if (w < c1) {
+        fac[d.p + w] = Fr[w];
+        fac[d.p + c1 + w] = Fi[w];
+      } else {
+        const long o = w - c1, i = o / np, j = o % np;
+        fac[d.l + o] = Fr[(np + i) * nf + j];
+        fac[d.l + c2 + o] = Fi[(np + i) * nf + j];
+      }
+    }
+  }
+}
+
+// ---- solve kernels --------------------------------------------------------------------
+
+template <typename R>
+__global__ void sol_in_kernel(const C<double>* __restrict__ b, long N, int nrhs, const int* __restrict__ perm,
+                              R* __restrict__ Xr, R* __restrict__ Xi) {
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < N * nrhs; w += (long)gridDim.x * blockDim.x) {
+    const long e = w / nrhs;
+    const int r = (int)(w % nrhs);
+    const C<double> v = b[r * N + perm[e]];
+    Xr[w] = (R)v.re;
+    Xi[w] = (R)v.im;
+  }
+}
+
+template <typename R>
+__global__ void sol_out_kernel(C<double>* __restrict__ b, long N, int nrhs, const int* __restrict__ perm,
+                               const R* __restrict__ Xr, const R* __restrict__ Xi) {
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < N * nrhs; w += (long)gridDim.x * blockDim.x) {
+    const long e = w / nrhs;
+    const int r = (int)(w % nrhs);
+    b[r * N + perm[e]] = cmk((double)Xr[w], (double)Xi[w]);
+  }
+}
+
+// children's update vectors into the pivot rows (x) or the update vector (u)
+// of every front of a level, for child `slot`
+template <typename R>
+__global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                        int nlvl, int slot, const int* __restrict__ ib, int nrhs,
+                                                        R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Ur,
+                                                        R* __restrict__ Ui) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (d.child[slot] < 0) continue;
+    const FrontDev c = fr[d.child[slot]];
+    const long cnt = (long)c.nb * nrhs;
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
+      const long rr = w / nrhs;
+      const int r = (int)(w % nrhs);
+      const long pos = 3L * ib[c.xm + rr / 3] + rr % 3;
+      const long src = (c.u + rr) * nrhs + r;
+      const long dst = pos < d.np ? (d.e0 + pos) * nrhs + r : (d.u + pos - d.np) * nrhs + r;
+      R* Tr = pos < d.np ? Xr : Ur;
+      R* Ti = pos < d.np ? Xi : Ui;
+      Tr[dst] += Ur[src];
+      Ti[dst] += Ui[src];
+    }
+  }
+}
+
+// forward step of tile kb: z = L^-1 P x_tile (written by workgroup 0), and
+// x_i -= L[i][tile] z for 64 rows i >= ke per workgroup (pivot rows in x,
+// boundary rows in the node's update vector)
+template <typename R>
+__global__ __launch_bounds__(256) void fwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                       int nlvl, int kb, const R* __restrict__ fac,
+                                                       const int* __restrict__ ib, int nrhs, R* __restrict__ Xr,
+                                                       R* __restrict__ Xi, R* __restrict__ Zr, R* __restrict__ Zi,
+                                                       R* __restrict__ Ur, R* __restrict__ Ui) {
+  __shared__ R xr[kT][kRC + 1], xi[kT][kRC + 1];
+  __shared__ R zr[kT][kRC + 1], zi[kT][kRC + 1];
+  __shared__ R Lr[kRB][kT + 1], Li[kRB][kT + 1];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.z * kRC;
+  const int nr = min(kRC, nrhs - r0);
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb >= d.np) continue;
+    const int tw = min(kT, d.np - kb);
+    const long ke = kb + tw, nf = d.nf, np = d.np;
+    const long i0 = ke + (long)blockIdx.x * kRB;
+    if (blockIdx.x > 0 && i0 >= nf) continue;
+    for (int o = tid; o < tw * kRC; o += blockDim.x) {
+      const int k = o / kRC, r = o % kRC;
+      if (r < nr) {
+        const long e = d.e0 + kb + ib[d.pv + kb + k];
+        xr[k][r] = Xr[e * nrhs + r0 + r];
+        xi[k][r] = Xi[e * nrhs + r0 + r];
+      }
+    }
+    __syncthreads();
+    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems;
+    for (int o = tid; o < tw * kRC; o += blockDim.x) {
+      const int k = o / kRC, r = o % kRC;
+      if (r < nr) {
+        R sr = R(0), si = R(0);
+        for (int c = 0; c <= k; ++c) {
+          const R ar = T[k * kT + c], ai = T[kTileElems + k * kT + c];
+          sr += ar * xr[c][r] - ai * xi[c][r];
+          si += ar * xi[c][r] + ai * xr[c][r];
+        }
+        zr[k][r] = sr;
+        zi[k][r] = si;
+        if (blockIdx.x == 0) {
+          Zr[(d.e0 + kb + k) * nrhs + r0 + r] = sr;
+          Zi[(d.e0 + kb + k) * nrhs + r0 + r] = si;
+        }
+      }
+    }
+    const int cnt = (int)max(0L, min((long)kRB, nf - i0));
+    for (int o = tid; o < cnt * tw; o += blockDim.x) {
+      const int i = o / tw, k = o % tw;
+      const long gi = i0 + i;
+      if (gi < np) {
+        Lr[i][k] = fac[d.p + gi * nf + kb + k];
+        Li[i][k] = fac[d.p + np * nf + gi * nf + kb + k];
+      } else {
+        Lr[i][k] = fac[d.l + (gi - np) * np + kb + k];
+        Li[i][k] = fac[d.l + (long)d.nb * np + (gi - np) * np + kb + k];
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < cnt * kRC; o += blockDim.x) {
+      const int i = o / kRC, r = o % kRC;
+      if (r < nr) {
+        R sr = R(0), si = R(0);
+        for (int k = 0; k < tw; ++k) {
+          sr += Lr[i][k] * zr[k][r] - Li[i][k] * zi[k][r];
+          si += Lr[i][k] * zi[k][r] + Li[i][k] * zr[k][r];
+        }
+        const long gi = i0 + i;
+        const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + r : (d.u + gi - np) * nrhs + r0 + r;
+        R* Tr = gi < np ? Xr : Ur;
+        R* Ti = gi < np ? Xi : Ui;
+        Tr[dst] -= sr;
+        Ti[dst] -= si;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// z_i -= sum_j U12[i][j] x_bnd(j) for 64 pivot rows per workgroup
+template <typename R>
+__global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                      int nlvl, const R* __restrict__ fac, const int* __restrict__ ib,
+                                                      int nrhs, const R* __restrict__ Xr, const R* __restrict__ Xi,
+                                                      R* __restrict__ Zr, R* __restrict__ Zi) {
+  __shared__ R xr[64][kRC + 1], xi[64][kRC + 1];
+  __shared__ R Ar[kRB][65], Ai[kRB][65];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.z * kRC;
+  const int nr = min(kRC, nrhs - r0);
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (d.nb == 0) continue;
+    const long np = d.np, nf = d.nf, nb = d.nb;
+    const long i0 = (long)blockIdx.x * kRB;
+    if (i0 >= np) continue;
+    const int cnt = (int)min((long)kRB, np - i0);
+    R accr[4] = {R(0), R(0), R(0), R(0)}, acci[4] = {R(0), R(0), R(0), R(0)};
+    for (long j0 = 0; j0 < nb; j0 += 64) {
+      const int nj = (int)min(64L, nb - j0);
+      for (int o = tid; o < nj * kRC; o += blockDim.x) {
+        const int j = o / kRC, r = o % kRC;
+        if (r < nr) {
+          const long e = ib[d.bm + j0 + j];
+          xr[j][r] = Xr[e * nrhs + r0 + r];
+          xi[j][r] = Xi[e * nrhs + r0 + r];
+        }
+      }
+      for (int o = tid; o < cnt * nj; o += blockDim.x) {
+        const int i = o / nj, j = o % nj;
+        Ar[i][j] = fac[d.p + (i0 + i) * nf + np + j0 + j];
+        Ai[i][j] = fac[d.p + np * nf + (i0 + i) * nf + np + j0 + j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = tid + 256 * u;
+        const int i = o / kRC, r = o % kRC;
+        if (i < cnt && r < nr) {
+          for (int j = 0; j < nj; ++j) {
+            accr[u] += Ar[i][j] * xr[j][r] - Ai[i][j] * xi[j][r];
+            acci[u] += Ar[i][j] * xi[j][r] + Ai[i][j] * xr[j][r];
+          }
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int o = tid + 256 * u;
+      const int i = o / kRC, r = o % kRC;
+      if (i < cnt && r < nr) {
+        Zr[(d.e0 + i0 + i) * nrhs + r0 + r] -= accr[u];
+        Zi[(d.e0 + i0 + i) * nrhs + r0 + r] -= acci[u];
+      }
+    }
+  }
+}
+
+// backward step of tile kb: x_tile = U^-1 z_tile (written by workgroup 0), and
+// z_i -= U[i][tile] x_tile for 64 rows i < kb per workgroup
+template <typename R>
+__global__ __launch_bounds__(256) void bwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                       int nlvl, int kb, const R* __restrict__ fac, int nrhs,
+                                                       R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
+                                                       R* __restrict__ Zi) {
+  __shared__ R yr[kT][kRC + 1], yi[kT][kRC + 1];
+  __shared__ R xr[kT][kRC + 1], xi[kT][kRC + 1];
+  __shared__ R Ar[kRB][kT + 1], Ai[kRB][kT + 1];
+  const int tid = threadIdx.x;
+  const int r0 = blockIdx.z * kRC;
+  const int nr = min(kRC, nrhs - r0);
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb >= d.np) continue;
+    const int tw = min(kT, d.np - kb);
+    const long nf = d.nf, np = d.np;
+    const long i0 = (long)blockIdx.x * kRB;
+    if (blockIdx.x > 0 && i0 >= kb) continue;
+    for (int o = tid; o < tw * kRC; o += blockDim.x) {
+      const int k = o / kRC, r = o % kRC;
+      if (r < nr) {
+        yr[k][r] = Zr[(d.e0 + kb + k) * nrhs + r0 + r];
+        yi[k][r] = Zi[(d.e0 + kb + k) * nrhs + r0 + r];
+      }
+    }
+    __syncthreads();
+    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems + 2 * kTileElems;
+    for (int o = tid; o < tw * kRC; o += blockDim.x) {
+      const int k = o / kRC, r = o % kRC;
+      if (r < nr) {
+        R sr = R(0), si = R(0);
+        for (int c = k; c < tw; ++c) {
+          const R ar = T[k * kT + c], ai = T[kTileElems + k * kT + c];
+          sr += ar * yr[c][r] - ai * yi[c][r];
+          si += ar * yi[c][r] + ai * yr[c][r];
+        }
+        xr[k][r] = sr;
+        xi[k][r] = si;
+        if (blockIdx.x == 0) {
+          Xr[(d.e0 + kb + k) * nrhs + r0 + r] = sr;
+          Xi[(d.e0 + kb + k) * nrhs + r0 + r] = si;
+        }
+      }
+    }
+    const int cnt = (int)max(0L, min((long)kRB, (long)kb - i0));
+    for (int o = tid; o < cnt * tw; o += blockDim.x) {
+      const int i = o / tw, k = o % tw;
+      Ar[i][k] = fac[d.p + (i0 + i) * nf + kb + k];
+      Ai[i][k] = fac[d.p + np * nf + (i0 + i) * nf + kb + k];
+    }
+    __syncthreads();
+    for (int o = tid; o < cnt * kRC; o += blockDim.x) {
+      const int i = o / kRC, r = o % kRC;
+      if (r < nr) {
+        R sr = R(0), si = R(0);
+        for (int k = 0; k < tw; ++k) {
+          sr += Ar[i][k] * xr[k][r] - Ai[i][k] * xi[k][r];
+          si += Ar[i][k] * xi[k][r] + Ai[i][k] * xr[k][r];
+        }
+        Zr[(d.e0 + i0 + i) * nrhs + r0 + r] -= sr;
+        Zi[(d.e0 + i0 + i) * nrhs + r0 + r] -= si;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+inline unsigned grid_for(long work, long per = 256, long cap = 65535) {
+  long g = (work + per - 1) / per;
+  return (unsigned)std::max(1L, std::min(g, cap));
+}
+
+}  // namespace
+
+struct GpuSolver {
+  int n = 0;
+  bool fp32 = false;
+  long N = 0;                          // 3 n^3 unknowns
+  std::vector<FrontDev> fh;            // per node (host copy)
+  std::vector<std::vector<int>> levels;   // node ids per depth
+  std::vector<long> lvl_off;           // offset of each level's list in lvl_d
+  std::vector<int> lvl_np, lvl_nf;     // largest np / nf per level
+  std::vector<size_t> lvl_elems;       // level buffer elements (R) per level
+  DevBuf fd, lvl_d, ib, fac;
+  long u_rows = 0;                     // sum of nb over the nodes
+  DevBuf X, Z, U;                      // solve work, sized for cap_rhs
+  int cap_rhs = 0;
+  size_t bytes = 0;
+  double flops = 0.0;
+};
+
+namespace {
+
+// Symbolic phase: dissection, elimination order, offsets and index maps.
+ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
+  const int n = g.n;
+  NdTree t = nd_build(n);
+  const int nn = (int)t.nodes.size();
+  g.N = 3L * n * n * n;
+  const long n3 = (long)n * n * n;
+  g.levels.assign(t.max_depth + 1, {});
+  for (int i = 0; i < nn; ++i) g.levels[t.nodes[i].depth].push_back(i);
+  g.fh.assign(nn, FrontDev{});
+  // elimination order: deepest level first
+  std::vector<long> elim_of_point(n3, -1);
+  long e = 0;
+  for (int dep = t.max_depth; dep >= 0; --dep)
+    for (int id : g.levels[dep]) {
+      const NdNode& nd = t.nodes[id];
+      FrontDev& f = g.fh[id];
+      f.np = nd.np;
+      f.nb = nd.nb;
+      f.nf = nd.np + nd.nb;
+      f.e0 = (int)e;
+      f.child[0] = nd.child[0];
+      f.child[1] = nd.child[1];
+      for (size_t a = 0; a < nd.piv.size(); ++a) elim_of_point[nd.piv[a]] = e + 3 * (long)a;
+      e += nd.np;
+    }
+  if (e != g.N) return LS_EINVAL;
+  // int maps: perm [N], then per node pv, am, ab, bp, xm, bm
+  long io = g.N;
+  for (int id = 0; id < nn; ++id) {
+    const NdNode& nd = t.nodes[id];
+    FrontDev& f = g.fh[id];
+    f.pv = io;
+    io += nd.np;
+    f.am = io;
+    io += 27L * (long)nd.piv.size();
+    f.ab = io;
+    io += 27L * (long)nd.bnd.size();
+    f.bp = io;
+    io += (long)nd.bnd.size();
+    f.xm = io;
+    io += (long)nd.bnd.size();
+    f.bm = io;
+    io += nd.nb;
+  }
+  if (io > (long)std::numeric_limits<int>::max()) return LS_ENOMEM;
+  ibh.assign(io, -1);
+  for (int id = 0; id < nn; ++id) {
+    const NdNode& nd = t.nodes[id];
+    const FrontDev& f = g.fh[id];
+    for (size_t a = 0; a < nd.piv.size(); ++a)
+      for (int c = 0; c < 3; ++c) ibh[f.e0 + 3 * a + c] = (int)(c * n3 + nd.piv[a]);
+    const int npp = (int)nd.piv.size();
+    auto nb_map = [&](int p, long dst, bool pivot_row) {
+      const int i3 = p % n, i2 = (p / n) % n, i1 = p / (n * n);
+      for (int s1 = -1; s1 <= 1; ++s1)
+        for (int s2 = -1; s2 <= 1; ++s2)
+          for (int s3 = -1; s3 <= 1; ++s3) {
+            const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
+            const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
+            int v = -1;
+            if (j1 >= 0 && j1 < n && j2 >= 0 && j2 < n && j3 >= 0 && j3 < n) {
+              const int pj = (j1 * n + j2) * n + j3;
+              v = pivot_row ? nd_front_pos(nd, pj) : nd_pos_in(nd.piv, pj);
+            }
+            ibh[dst + slot] = v;
+          }
+    };
+    for (int a = 0; a < npp; ++a) nb_map(nd.piv[a], f.am + 27L * a, true);
+    for (size_t b = 0; b < nd.bnd.size(); ++b) {
+      nb_map(nd.bnd[b], f.ab + 27L * b, false);
+      ibh[f.bp + b] = nd.bnd[b];
+      const long eb = elim_of_point[nd.bnd[b]];
+      if (eb < 0) return LS_EINVAL;
+      for (int c = 0; c < 3; ++c) ibh[f.bm + 3 * b + c] = (int)(eb + c);
+    }
+    if (nd.parent >= 0) {
+      const NdNode& pa = t.nodes[nd.parent];
+      for (size_t b = 0; b < nd.bnd.size(); ++b) {
+        const int fp = nd_front_pos(pa, nd.bnd[b]);
+        if (fp < 0) return LS_EINVAL;           // a child's shell lies in its parent's front
+        ibh[f.xm + b] = fp;
+      }
+    }
+  }
+  // factor offsets (R elements) and solve update rows
+  long fo = 0, uo = 0;
+  double fl = 0.0;
+  for (int id = 0; id < nn; ++id) {
+    FrontDev& f = g.fh[id];
+    const long np = f.np, nb = f.nb, nf = f.nf;
+    f.p = fo;
+    fo += 2 * np * nf;
+    f.l = fo;
+    fo += 2 * nb * np;
+    f.t = fo;
+    fo += 4L * kTileElems * ((np + kT - 1) / kT);
+    f.u = uo;
+    uo += nb;
+    for (long kb = 0; kb < np; kb += kT) {
+      const long ke = std::min(np, kb + kT), rows = nf - ke;
+      fl += 8.0 * (double)rows * (double)rows * (double)(ke - kb);
+    }
+  }
+  fac_elems = fo;
+  g.u_rows = uo;
+  g.flops = fl;
+  // level buffers and per-level extents
+  const int L = (int)g.levels.size();
+  g.lvl_off.assign(L, 0);
+  g.lvl_np.assign(L, 0);
+  g.lvl_nf.assign(L, 0);
+  g.lvl_elems.assign(L, 0);
+  long lo = 0;
+  for (int dep = 0; dep < L; ++dep) {
+    g.lvl_off[dep] = lo;
+    lo += (long)g.levels[dep].size();
+    size_t off = 0;
+    for (int id : g.levels[dep]) {
+      FrontDev& f = g.fh[id];
+      f.f = (long)off;
+      off += 2 * (size_t)f.nf * f.nf;
+      g.lvl_np[dep] = std::max(g.lvl_np[dep], f.np);
+      g.lvl_nf[dep] = std::max(g.lvl_nf[dep], f.nf);
+    }
+    g.lvl_elems[dep] = off;
+  }
+  // every map entry in range (checked once here; the kernels trust them)
+  for (int id = 0; id < nn; ++id) {
+    const FrontDev& f = g.fh[id];
+    const NdNode& nd = t.nodes[id];
+    for (long i = 0; i < 27L * (long)nd.piv.size(); ++i)
+      if (ibh[f.am + i] >= f.nf / 3) return LS_EINVAL;
+    for (long i = 0; i < 27L * (long)nd.bnd.size(); ++i)
+      if (ibh[f.ab + i] >= f.np / 3) return LS_EINVAL;
+    if (nd.parent >= 0)
+      for (size_t b = 0; b < nd.bnd.size(); ++b)
+        if (ibh[f.xm + b] >= g.fh[nd.parent].nf / 3) return LS_EINVAL;
+  }
+  return LS_OK;
+}
+
+template <typename R>
+ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
+  const int L = (int)g.levels.size();
+  size_t cap[2] = {0, 0};
+  for (int dep = 0; dep < L; ++dep) cap[dep & 1] = std::max(cap[dep & 1], g.lvl_elems[dep]);
+  DevBuf lb[2];
+  LS_TRY(lb[0].alloc(cap[0] * sizeof(R)));
+  LS_TRY(lb[1].alloc(cap[1] * sizeof(R)));
+  const FrontDev* fr = g.fd.as<FrontDev>();
+  int* ib = g.ib.as<int>();
+  R* fac = g.fac.as<R>();
+  for (int dep = L - 1; dep >= 0; --dep) {
+    const int nl = (int)g.levels[dep].size();
+    const int* lvl = g.lvl_d.as<int>() + g.lvl_off[dep];
+    R* buf = lb[dep & 1].as<R>();
+    const R* cbuf = lb[(dep + 1) & 1].as<R>();
+    const unsigned gy = (unsigned)std::min(nl, 65535);
+    const long mnf = g.lvl_nf[dep], mnp = g.lvl_np[dep];
+    hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for((long)g.lvl_elems[dep], 256, 1 << 20)), dim3(256), 0, s, buf,
+                       (long)g.lvl_elems[dep]);
+    hipLaunchKernelGGL(assemble_kernel<R>, dim3(grid_for(mnf / 3 * 27), gy), dim3(256), 0, s, fr, lvl, nl, ib, rows,
+                       buf);
+    if (dep + 1 < L)
+      for (int slot = 0; slot < 2; ++slot) {
+        long mcnb = 0;
+        for (int id : g.levels[dep])
+          if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
+        if (mcnb == 0) continue;
+        hipLaunchKernelGGL(extend_add_kernel<R>, dim3(grid_for(mcnb * mcnb, 256, 1 << 16), gy), dim3(256), 0, s, fr,
+                           lvl, nl, slot, ib, cbuf, buf);
+      }
+    for (long kb = 0; kb < mnp; kb += kT) {
+      hipLaunchKernelGGL(diag_kernel<R>, dim3(gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf, fac, ib);
+      const long rest = mnf - kb - 1;           // rows right of / below the tile, at most
+      const int half = (int)std::max(1L, (rest + kRB - 1) / kRB);
+      hipLaunchKernelGGL(panel_kernel<R>, dim3(2 * half, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, half, buf,
+                         (const R*)fac, (const int*)ib);
+      const unsigned t64 = (unsigned)std::max(1L, (rest + 63) / 64);
+      hipLaunchKernelGGL(schur_kernel<R>, dim3(t64, t64, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf);
+    }
+    hipLaunchKernelGGL(copyout_kernel<R>, dim3(grid_for(mnf * mnf, 256, 1 << 16), gy), dim3(256), 0, s, fr, lvl, nl,
+                       (const R*)buf, fac);
+    LS_HIP(hipGetLastError());
+  }
+  LS_HIP(hipStreamSynchronize(s));
+  return LS_OK;
+}
+
+template <typename R>
+ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
+  if (g.cap_rhs < nrhs) {
+    LS_TRY(g.X.alloc(2 * (size_t)g.N * nrhs * sizeof(R)));
+    LS_TRY(g.Z.alloc(2 * (size_t)g.N * nrhs * sizeof(R)));
+    LS_TRY(g.U.alloc(2 * (size_t)std::max(1L, g.u_rows) * nrhs * sizeof(R)));
+    g.cap_rhs = nrhs;
+  }
+  const long N = g.N;
+  R* Xr = g.X.as<R>();
+  R* Xi = Xr + N * nrhs;
+  R* Zr = g.Z.as<R>();
+  R* Zi = Zr + N * nrhs;
+  R* Ur = g.U.as<R>();
+  R* Ui = Ur + std::max(1L, g.u_rows) * nrhs;
+  const FrontDev* fr = g.fd.as<FrontDev>();
+  const int* ib = g.ib.as<int>();
+  const R* fac = g.fac.as<R>();
+  const int L = (int)g.levels.size();
+  const unsigned gz = (unsigned)((nrhs + kRC - 1) / kRC);
+  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N * nrhs, 256, 1 << 16)), dim3(256), 0, s, b, N, nrhs, ib, Xr,
+                     Xi);
+  hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
+                     s, Ur, 2 * std::max(1L, g.u_rows) * nrhs);
+  for (int dep = L - 1; dep >= 0; --dep) {
+    const int nl = (int)g.levels[dep].size();
+    const int* lvl = g.lvl_d.as<int>() + g.lvl_off[dep];
+    const unsigned gy = (unsigned)std::min(nl, 65535);
+    const long mnf = g.lvl_nf[dep], mnp = g.lvl_np[dep];
+    if (dep + 1 < L)
+      for (int slot = 0; slot < 2; ++slot) {
+        long mcnb = 0;
+        for (int id : g.levels[dep])
+          if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
+        if (mcnb == 0) continue;
+        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3(grid_for(mcnb * nrhs, 256, 1 << 14), gy), dim3(256), 0, s, fr,
+                           lvl, nl, slot, ib, nrhs, Xr, Xi, Ur, Ui);
+      }
+    for (long kb = 0; kb < mnp; kb += kT) {
+      const long rest = mnf - kb - 1;
+      const unsigned gx = (unsigned)std::max(1L, (rest + kRB - 1) / kRB);
+      hipLaunchKernelGGL(fwd_tile_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb, fac, ib, nrhs,
+                         Xr, Xi, Zr, Zi, Ur, Ui);
+    }
+  }
+  for (int dep = 0; dep < L; ++dep) {
+    const int nl = (int)g.levels[dep].size();
+    const int* lvl = g.lvl_d.as<int>() + g.lvl_off[dep];
+    const unsigned gy = (unsigned)std::min(nl, 65535);
+    const long mnp = g.lvl_np[dep];
+    const unsigned gu = (unsigned)std::max(1L, (mnp + kRB - 1) / kRB);
+    hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz), dim3(256), 0, s, fr, lvl, nl, fac, ib, nrhs,
+                       (const R*)Xr, (const R*)Xi, Zr, Zi);
+    for (long kb = ((mnp - 1) / kT) * kT; kb >= 0; kb -= kT) {
+      const unsigned gx = (unsigned)std::max(1L, (kb + kRB - 1) / kRB);
+      hipLaunchKernelGGL(bwd_tile_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb, fac, nrhs, Xr,
+                         Xi, Zr, Zi);
+    }
+  }
+  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N * nrhs, 256, 1 << 16)), dim3(256), 0, s, b, N, nrhs, ib,
+                     (const R*)Xr, (const R*)Xi);
+  LS_HIP(hipGetLastError());
+  return LS_OK;
+}
+
+}  // namespace
+
+ls_status gpu_factor(int n, const C<double>* rows_dev, bool fp32, hipStream_t s, GpuSolver** out) {
+  if (n < 1 || !rows_dev || !out) return LS_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<GpuSolver> g(new GpuSolver());
+  g->n = n;
+  g->fp32 = fp32;
+  std::vector<int> ibh;
+  long fac_elems = 0;
+  LS_TRY(symbolic(*g, ibh, fac_elems));
+  const size_t rs = fp32 ? sizeof(float) : sizeof(double);
+  LS_TRY(g->fac.alloc((size_t)fac_elems * rs));
+  LS_TRY(g->ib.alloc(ibh.size() * sizeof(int)));
+  LS_TRY(g->fd.alloc(g->fh.size() * sizeof(FrontDev)));
+  std::vector<int> lv;
+  for (const auto& l : g->levels) lv.insert(lv.end(), l.begin(), l.end());
+  LS_TRY(g->lvl_d.alloc(lv.size() * sizeof(int)));
+  LS_HIP(hipMemcpyAsync(g->ib.p, ibh.data(), ibh.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(g->fd.p, g->fh.data(), g->fh.size() * sizeof(FrontDev), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(g->lvl_d.p, lv.data(), lv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  g->bytes = (size_t)fac_elems * rs;
+  if (fp32)
+    LS_TRY(factor_numeric<float>(*g, rows_dev, s));
+  else
+    LS_TRY(factor_numeric<double>(*g, rows_dev, s));
+  *out = g.release();
+  return LS_OK;
+}
+
+ls_status gpu_solve(GpuSolver* gs, C<double>* b_dev, int nrhs, hipStream_t s) {
+  if (!gs || !b_dev || nrhs < 1) return LS_EINVAL;
+  return gs->fp32 ? solve_numeric<float>(*gs, b_dev, nrhs, s) : solve_numeric<double>(*gs, b_dev, nrhs, s);
+}
+
+size_t gpu_factor_bytes(const GpuSolver* gs) { return gs ? gs->bytes : 0; }
+double gpu_factor_flops(const GpuSolver* gs) { return gs ? gs->flops : 0.0; }
+bool gpu_factor_is_fp32(const GpuSolver* gs) { return gs && gs->fp32; }
+void gpu_free(GpuSolver* gs) { delete gs; }
+
+}  // namespace ls

@@ -19,6 +19,7 @@
 // is a preconditioner for the FP64 flexible GMRES: half the memory and twice
 // the SIMD width for the factorisation and every solve.
 #include "host_solver.h"
+#include "nd_tree.h"
 
 #include <omp.h>
 
@@ -45,17 +46,8 @@ namespace ls {
 
 namespace {
 
-constexpr int kLeafPoints = 64;
 constexpr int kNB = 32;         // panel width of the blocked partial LU
 constexpr long kPanelTask = 65536;   // panel updates above this many entries run as row tasks
-
-// geometry of one node of the dissection tree (shared by both precisions)
-struct Geom {
-  int lo[3], hi[3];
-  int child[2] = {-1, -1};
-  std::vector<int> piv, bnd;    // sorted global point indices
-  int np = 0, nb = 0;
-};
 
 // numeric data of one node
 template <typename R>
@@ -78,18 +70,9 @@ struct FlushDenormals {
 #endif
 };
 
-inline int pos_in(const std::vector<int>& v, int p) {
-  auto it = std::lower_bound(v.begin(), v.end(), p);
-  return (it != v.end() && *it == p) ? int(it - v.begin()) : -1;
-}
-
-// local front index of global point p (pivot first, then boundary), or -1
-inline int front_pos(const Geom& nd, int p) {
-  int k = pos_in(nd.piv, p);
-  if (k >= 0) return k;
-  k = pos_in(nd.bnd, p);
-  return k >= 0 ? (int)nd.piv.size() + k : -1;
-}
+using Geom = NdNode;
+inline int pos_in(const std::vector<int>& v, int p) { return nd_pos_in(v, p); }
+inline int front_pos(const Geom& nd, int p) { return nd_front_pos(nd, p); }
 
 // ---- kernels: one template body, multiversioned per real type -------------------
 
@@ -505,50 +488,6 @@ std::vector<Vals<double>>& vals_of<double>(HostSolver& hs) {
 template <>
 std::vector<Vals<float>>& vals_of<float>(HostSolver& hs) {
   return hs.v32;
-}
-
-int build_tree(HostSolver& hs, const int lo[3], const int hi[3]) {
-  const int n = hs.n;
-  Geom nd;
-  for (int d = 0; d < 3; ++d) {
-    nd.lo[d] = lo[d];
-    nd.hi[d] = hi[d];
-  }
-  long len[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
-  const long vol = len[0] * len[1] * len[2];
-  int dsplit = 0;
-  for (int d = 1; d < 3; ++d)
-    if (len[d] > len[dsplit]) dsplit = d;
-  const bool leaf = vol <= kLeafPoints || len[dsplit] <= 2;
-  int mid = lo[dsplit] + (int)(len[dsplit] / 2);
-  for (int a = lo[0]; a < hi[0]; ++a)
-    for (int b = lo[1]; b < hi[1]; ++b)
-      for (int c = lo[2]; c < hi[2]; ++c) {
-        const int q[3] = {a, b, c};
-        if (leaf || q[dsplit] == mid) nd.piv.push_back((a * n + b) * n + c);
-      }
-  for (int a = std::max(0, lo[0] - 1); a < std::min(n, hi[0] + 1); ++a)
-    for (int b = std::max(0, lo[1] - 1); b < std::min(n, hi[1] + 1); ++b)
-      for (int c = std::max(0, lo[2] - 1); c < std::min(n, hi[2] + 1); ++c) {
-        const bool inside = a >= lo[0] && a < hi[0] && b >= lo[1] && b < hi[1] && c >= lo[2] && c < hi[2];
-        if (!inside) nd.bnd.push_back((a * n + b) * n + c);
-      }
-  nd.np = 3 * (int)nd.piv.size();
-  nd.nb = 3 * (int)nd.bnd.size();
-  const int id = (int)hs.geo.size();
-  hs.geo.push_back(std::move(nd));
-  if (!leaf) {
-    int l_hi[3] = {hi[0], hi[1], hi[2]};
-    int r_lo[3] = {lo[0], lo[1], lo[2]};
-    l_hi[dsplit] = mid;
-    r_lo[dsplit] = mid + 1;
-    int c0 = -1, c1 = -1;
-    if (mid > lo[dsplit]) c0 = build_tree(hs, lo, l_hi);
-    if (mid + 1 < hi[dsplit]) c1 = build_tree(hs, r_lo, hi);
-    hs.geo[id].child[0] = c0;
-    hs.geo[id].child[1] = c1;
-  }
-  return id;
 }
 
 template <typename R>
@@ -1046,8 +985,11 @@ ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, b
   std::unique_ptr<HostSolver> hs(new HostSolver());
   hs->n = n;
   hs->fp32 = fp32;
-  const int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
-  hs->root = build_tree(*hs, lo, hi);
+  {
+    NdTree t = nd_build(n);
+    hs->geo = std::move(t.nodes);
+    hs->root = t.root;
+  }
   const size_t cbytes = fp32 ? 8 : 16;
   size_t need = 0;
   for (const Geom& nd : hs->geo) need += cbytes * ((size_t)nd.np * nd.np + 2ull * nd.np * nd.nb);
