@@ -48,8 +48,11 @@ namespace {
 
 constexpr int kT = 48;     // diagonal tile (pivot search window)
 constexpr int kRB = 64;    // rows or columns per workgroup in the panel and solve kernels
-constexpr int kRC = 16;    // right-hand sides per workgroup in the solve kernels
+constexpr int kSR = 64;    // right-hand sides per workgroup in the solve kernels
+constexpr int kKC = 32;    // boundary columns per LDS chunk of the U12 product
+constexpr int kKS = 512;   // boundary columns per workgroup of the U12 product (split over workgroups)
 constexpr int kTileElems = kT * kT;
+constexpr int kOB = 4 * kT;   // outer block: the trailing matrix is updated once per kOB pivot columns
 
 struct FrontDev {
   int np, nb, nf, e0;   // pivot / boundary / front unknowns; first elimination index
@@ -381,11 +384,19 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__
   }
 }
 
-// Trailing update F[ke:, ke:] -= L U (K = tw) on a 64 x 64 tile per workgroup;
-// four waves of 32 x 32, complex product as four real MFMA products.
+// Schur updates F[rows][cols] -= F[rows][K] F[K][cols] on a 64 x 64 tile per
+// workgroup (four waves of 32 x 32, the complex product as four real MFMA
+// products).  With the 48-column step kb inside the outer block starting at
+// kb0 (obe = min(kb0 + kOB, np)):
+//   mode 0: rows [ke, nf), cols [ke, obe), K = the step's columns
+//   mode 1: rows [ke, obe), cols [obe, nf), K = the step's columns
+//   mode 2: rows [obe, nf), cols [obe, nf), K = [kb0, obe)   (once per block)
+// Modes 0 and 1 keep the block's own columns and rows current for the next
+// step; the rest of the trailing matrix is read by nothing inside the block,
+// so its update waits and is applied once with K up to kOB.
 template <typename R>
 __global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                    int nlvl, int kb, R* __restrict__ buf) {
+                                                    int nlvl, int kb, int kb0, int mode, R* __restrict__ buf) {
   typedef typename Mma<R>::v4 v4;
   __shared__ R Ar[64][17], Ai[64][17];
   __shared__ R Br[16][65], Bi[16][65];
@@ -393,11 +404,27 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   for (int q = blockIdx.z; q < nlvl; q += gridDim.z) {
     const FrontDev d = fr[lvl[q]];
-    if (kb >= d.np) continue;
-    const int tw = min(kT, d.np - kb);
-    const long ke = kb + tw, nf = d.nf;
-    const long i0 = ke + 64L * blockIdx.y, j0 = ke + 64L * blockIdx.x;
-    if (i0 >= nf || j0 >= nf) continue;
+    const long nf = d.nf, obe = min((long)kb0 + kOB, (long)d.np);
+    long r0, r1, c0, c1, k0, k1;
+    if (mode == 2) {
+      if (kb0 >= d.np) continue;
+      r0 = c0 = obe;
+      r1 = c1 = nf;
+      k0 = kb0;
+      k1 = obe;
+    } else {
+      if (kb >= d.np) continue;
+      k0 = kb;
+      k1 = min((long)kb + kT, (long)d.np);
+      r0 = c0 = k1;
+      r1 = mode == 0 ? nf : obe;
+      if (mode == 1) c0 = obe;
+      c1 = mode == 0 ? obe : nf;
+    }
+    const long i0 = r0 + 64L * blockIdx.y, j0 = c0 + 64L * blockIdx.x;
+    if (i0 >= r1 || j0 >= c1) continue;
+    const int tw = (int)(k1 - k0);
+    const long kb_ = k0;
     R* Fr = buf + d.f;
     R* Fi = Fr + nf * nf;
     v4 cr[2][2], ci[2][2];
@@ -413,13 +440,13 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__
       for (int u = 0; u < 4; ++u) {
         const int o = tid + 256 * u;
         const int ii = o >> 4, kk = o & 15;
-        const bool ok = i0 + ii < nf && kc + kk < tw;
-        const long src = (i0 + ii) * nf + kb + kc + kk;
+        const bool ok = i0 + ii < r1 && kc + kk < tw;
+        const long src = (i0 + ii) * nf + kb_ + kc + kk;
         Ar[ii][kk] = ok ? Fr[src] : R(0);
         Ai[ii][kk] = ok ? Fi[src] : R(0);
         const int kr = o >> 6, jj = o & 63;
-        const bool okb = kc + kr < tw && j0 + jj < nf;
-        const long srcb = (kb + kc + kr) * nf + j0 + jj;
+        const bool okb = kc + kr < tw && j0 + jj < c1;
+        const long srcb = (kb_ + kc + kr) * nf + j0 + jj;
         Br[kr][jj] = okb ? Fr[srcb] : R(0);
         Bi[kr][jj] = okb ? Fi[srcb] : R(0);
       }
@@ -455,7 +482,7 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__
         for (int r = 0; r < 4; ++r) {
           const long gi = i0 + wm + 16 * a + Mma<R>::row(lane, r);
           const long gj = j0 + wn + 16 * b + (lane & 15);
-          if (gi < nf && gj < nf) {
+          if (gi < r1 && gj < c1) {
             Fr[gi * nf + gj] -= cr[a][b][r];
             Fi[gi * nf + gj] -= ci[a][b][r];
           }
@@ -536,21 +563,86 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
   }
 }
 
-// forward step of tile kb: z = L^-1 P x_tile (written by workgroup 0), and
-// x_i -= L[i][tile] z for 64 rows i >= ke per workgroup (pivot rows in x,
-// boundary rows in the node's update vector)
+// 64 x 64 complex tile product acc += A B on MFMA: A [64][lda] (rows x K) and
+// B [K][ldb] in LDS, K a multiple of 4; wave (wm, wn) owns a 32 x 32 quarter.
+template <typename R>
+__device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
+                                       int wm, int wn, int lane, typename Mma<R>::v4 (&cr)[2][2],
+                                       typename Mma<R>::v4 (&ci)[2][2]) {
+  for (int k4 = 0; k4 < K; k4 += 4) {
+    const int kr = k4 + (lane >> 4);
+    R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
+      ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
+      br[a] = Br[kr * ldb + wn + 16 * a + (lane & 15)];
+      bi[a] = Bi[kr * ldb + wn + 16 * a + (lane & 15)];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = Mma<R>::op(ar[a], br[b], cr[a][b]);
+        cr[a][b] = Mma<R>::op(-ai[a], bi[b], cr[a][b]);
+        ci[a][b] = Mma<R>::op(ar[a], bi[b], ci[a][b]);
+        ci[a][b] = Mma<R>::op(ai[a], br[b], ci[a][b]);
+      }
+  }
+}
+
+// Y (kT x kSR) = T X for a tile's triangular inverse T (global [kT][kT], re
+// plane then im plane; rows or columns >= tw read as zero) and X (kT x kSR)
+// in LDS; wave w computes the columns [16 w, 16 w + 16).
+template <typename R>
+__device__ __forceinline__ void tile_inv_apply(const R* __restrict__ T, int tw, const R* Xr, const R* Xi, int ldx,
+                                               R* Yr, R* Yi, int ldy, int wave, int lane) {
+  typedef typename Mma<R>::v4 v4;
+  const int c0 = 16 * wave + (lane & 15);
+#pragma unroll
+  for (int rt = 0; rt < kT / 16; ++rt) {
+    v4 yr = v4{R(0), R(0), R(0), R(0)}, yi = v4{R(0), R(0), R(0), R(0)};
+    const int row = 16 * rt + (lane & 15);
+#pragma unroll 4
+    for (int k4 = 0; k4 < kT; k4 += 4) {
+      const int k = k4 + (lane >> 4);
+      const bool ok = row < tw && k < tw;
+      const R ar = ok ? T[row * kT + k] : R(0);
+      const R ai = ok ? T[kTileElems + row * kT + k] : R(0);
+      const R br = Xr[k * ldx + c0], bi = Xi[k * ldx + c0];
+      yr = Mma<R>::op(ar, br, yr);
+      yr = Mma<R>::op(-ai, bi, yr);
+      yi = Mma<R>::op(ar, bi, yi);
+      yi = Mma<R>::op(ai, br, yi);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      Yr[(16 * rt + Mma<R>::row(lane, r)) * ldy + c0] = yr[r];
+      Yi[(16 * rt + Mma<R>::row(lane, r)) * ldy + c0] = yi[r];
+    }
+  }
+}
+
+constexpr int kLX = kSR + 1;                 // row stride of tile vectors in LDS
+constexpr int kLL = kT + 1;                  // row stride of a 64 x 48 factor block in LDS
+constexpr int kBuf = (kT * kLX > kRB * kLL) ? kT * kLX : kRB * kLL;
+
+// forward step of tile kb: z = L^-1 P x_tile (written to Z by workgroup 0),
+// and x_i -= L[i][tile] z for 64 rows i >= ke per workgroup (pivot rows in
+// x, boundary rows in the node's update vector); 64 rhs per workgroup.
 template <typename R>
 __global__ __launch_bounds__(256) void fwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                        int nlvl, int kb, const R* __restrict__ fac,
                                                        const int* __restrict__ ib, int nrhs, R* __restrict__ Xr,
                                                        R* __restrict__ Xi, R* __restrict__ Zr, R* __restrict__ Zi,
                                                        R* __restrict__ Ur, R* __restrict__ Ui) {
-  __shared__ R xr[kT][kRC + 1], xi[kT][kRC + 1];
-  __shared__ R zr[kT][kRC + 1], zi[kT][kRC + 1];
-  __shared__ R Lr[kRB][kT + 1], Li[kRB][kT + 1];
-  const int tid = threadIdx.x;
-  const int r0 = blockIdx.z * kRC;
-  const int nr = min(kRC, nrhs - r0);
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar_[kBuf], Ai_[kBuf];          // P x_tile [kT][kLX], then the L block [kRB][kLL]
+  __shared__ R Yr_[kT * kLX], Yi_[kT * kLX];  // z
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r0 = blockIdx.z * kSR;
+  const int nr = min(kSR, nrhs - r0);
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
     if (kb >= d.np) continue;
@@ -558,139 +650,201 @@ __global__ __launch_bounds__(256) void fwd_tile_kernel(const FrontDev* __restric
     const long ke = kb + tw, nf = d.nf, np = d.np;
     const long i0 = ke + (long)blockIdx.x * kRB;
     if (blockIdx.x > 0 && i0 >= nf) continue;
-    for (int o = tid; o < tw * kRC; o += blockDim.x) {
-      const int k = o / kRC, r = o % kRC;
-      if (r < nr) {
+    for (int o = tid; o < kT * kSR; o += blockDim.x) {
+      const int k = o / kSR, r = o % kSR;
+      R vr = R(0), vi = R(0);
+      if (k < tw && r < nr) {
         const long e = d.e0 + kb + ib[d.pv + kb + k];
-        xr[k][r] = Xr[e * nrhs + r0 + r];
-        xi[k][r] = Xi[e * nrhs + r0 + r];
+        vr = Xr[e * nrhs + r0 + r];
+        vi = Xi[e * nrhs + r0 + r];
       }
+      Ar_[k * kLX + r] = vr;
+      Ai_[k * kLX + r] = vi;
     }
     __syncthreads();
-    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems;
-    for (int o = tid; o < tw * kRC; o += blockDim.x) {
-      const int k = o / kRC, r = o % kRC;
-      if (r < nr) {
-        R sr = R(0), si = R(0);
-        for (int c = 0; c <= k; ++c) {
-          const R ar = T[k * kT + c], ai = T[kTileElems + k * kT + c];
-          sr += ar * xr[c][r] - ai * xi[c][r];
-          si += ar * xi[c][r] + ai * xr[c][r];
-        }
-        zr[k][r] = sr;
-        zi[k][r] = si;
-        if (blockIdx.x == 0) {
-          Zr[(d.e0 + kb + k) * nrhs + r0 + r] = sr;
-          Zi[(d.e0 + kb + k) * nrhs + r0 + r] = si;
+    tile_inv_apply<R>(fac + d.t + (long)(kb / kT) * 4 * kTileElems, tw, Ar_, Ai_, kLX, Yr_, Yi_, kLX, wave, lane);
+    __syncthreads();
+    if (blockIdx.x == 0)
+      for (int o = tid; o < tw * kSR; o += blockDim.x) {
+        const int k = o / kSR, r = o % kSR;
+        if (r < nr) {
+          Zr[(d.e0 + kb + k) * nrhs + r0 + r] = Yr_[k * kLX + r];
+          Zi[(d.e0 + kb + k) * nrhs + r0 + r] = Yi_[k * kLX + r];
         }
       }
-    }
     const int cnt = (int)max(0L, min((long)kRB, nf - i0));
-    for (int o = tid; o < cnt * tw; o += blockDim.x) {
-      const int i = o / tw, k = o % tw;
-      const long gi = i0 + i;
-      if (gi < np) {
-        Lr[i][k] = fac[d.p + gi * nf + kb + k];
-        Li[i][k] = fac[d.p + np * nf + gi * nf + kb + k];
-      } else {
-        Lr[i][k] = fac[d.l + (gi - np) * np + kb + k];
-        Li[i][k] = fac[d.l + (long)d.nb * np + (gi - np) * np + kb + k];
-      }
-    }
-    __syncthreads();
-    for (int o = tid; o < cnt * kRC; o += blockDim.x) {
-      const int i = o / kRC, r = o % kRC;
-      if (r < nr) {
-        R sr = R(0), si = R(0);
-        for (int k = 0; k < tw; ++k) {
-          sr += Lr[i][k] * zr[k][r] - Li[i][k] * zi[k][r];
-          si += Lr[i][k] * zi[k][r] + Li[i][k] * zr[k][r];
+    if (cnt > 0) {
+      for (int o = tid; o < kRB * kT; o += blockDim.x) {
+        const int i = o / kT, k = o % kT;
+        R vr = R(0), vi = R(0);
+        if (i < cnt && k < tw) {
+          const long gi = i0 + i;
+          if (gi < np) {
+            vr = fac[d.p + gi * nf + kb + k];
+            vi = fac[d.p + np * nf + gi * nf + kb + k];
+          } else {
+            vr = fac[d.l + (gi - np) * np + kb + k];
+            vi = fac[d.l + (long)d.nb * np + (gi - np) * np + kb + k];
+          }
         }
-        const long gi = i0 + i;
-        const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + r : (d.u + gi - np) * nrhs + r0 + r;
-        R* Tr = gi < np ? Xr : Ur;
-        R* Ti = gi < np ? Xi : Ui;
-        Tr[dst] -= sr;
-        Ti[dst] -= si;
+        Ar_[i * kLL + k] = vr;
+        Ai_[i * kLL + k] = vi;
       }
+      __syncthreads();
+      v4 cr[2][2], ci[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+          ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+        }
+      cmma64<R>(Ar_, Ai_, kLL, Yr_, Yi_, kLX, kT, wm, wn, lane, cr, ci);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+            if (row < cnt && col < nr) {
+              const long gi = i0 + row;
+              const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + col : (d.u + gi - np) * nrhs + r0 + col;
+              R* Tr = gi < np ? Xr : Ur;
+              R* Ti = gi < np ? Xi : Ui;
+              Tr[dst] -= cr[a][b][r];
+              Ti[dst] -= ci[a][b][r];
+            }
+          }
     }
     __syncthreads();
   }
 }
 
-// z_i -= sum_j U12[i][j] x_bnd(j) for 64 pivot rows per workgroup
+// z_i -= sum_j U12[i][j] x_bnd(j) for 64 pivot rows and kKS boundary columns
+// per workgroup (grid.z = column split + splits * rhs chunk).  A node with
+// one split subtracts in place; with more, each split writes its partial sum
+// and u12_reduce_kernel adds them in split order.
 template <typename R>
 __global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                      int nlvl, const R* __restrict__ fac, const int* __restrict__ ib,
-                                                      int nrhs, const R* __restrict__ Xr, const R* __restrict__ Xi,
-                                                      R* __restrict__ Zr, R* __restrict__ Zi) {
-  __shared__ R xr[64][kRC + 1], xi[64][kRC + 1];
-  __shared__ R Ar[kRB][65], Ai[kRB][65];
-  const int tid = threadIdx.x;
-  const int r0 = blockIdx.z * kRC;
-  const int nr = min(kRC, nrhs - r0);
+                                                      int nlvl, int nks_max, long np_max,
+                                                      const R* __restrict__ fac, const int* __restrict__ ib, int nrhs,
+                                                      const R* __restrict__ Xr, const R* __restrict__ Xi,
+                                                      R* __restrict__ Zr, R* __restrict__ Zi, R* __restrict__ Pr,
+                                                      R* __restrict__ Pi) {
+  typedef typename Mma<R>::v4 v4;
+  constexpr int LA = kKC + 1;
+  __shared__ R Ar_[kRB * LA], Ai_[kRB * LA];   // U12 block [64][kKC]
+  __shared__ R Br_[kKC * kLX], Bi_[kKC * kLX]; // gathered x_bnd [kKC][kSR]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int ks = blockIdx.z % nks_max;
+  const int r0 = (blockIdx.z / nks_max) * kSR;
+  const int nr = min(kSR, nrhs - r0);
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
-    if (d.nb == 0) continue;
     const long np = d.np, nf = d.nf, nb = d.nb;
+    const int nks = (int)((nb + kKS - 1) / kKS);
+    if (ks >= nks) continue;
     const long i0 = (long)blockIdx.x * kRB;
     if (i0 >= np) continue;
     const int cnt = (int)min((long)kRB, np - i0);
-    R accr[4] = {R(0), R(0), R(0), R(0)}, acci[4] = {R(0), R(0), R(0), R(0)};
-    for (long j0 = 0; j0 < nb; j0 += 64) {
-      const int nj = (int)min(64L, nb - j0);
-      for (int o = tid; o < nj * kRC; o += blockDim.x) {
-        const int j = o / kRC, r = o % kRC;
-        if (r < nr) {
-          const long e = ib[d.bm + j0 + j];
-          xr[j][r] = Xr[e * nrhs + r0 + r];
-          xi[j][r] = Xi[e * nrhs + r0 + r];
-        }
+    const long j0 = (long)ks * kKS, j1 = min(nb, j0 + kKS);
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
       }
-      for (int o = tid; o < cnt * nj; o += blockDim.x) {
-        const int i = o / nj, j = o % nj;
-        Ar[i][j] = fac[d.p + (i0 + i) * nf + np + j0 + j];
-        Ai[i][j] = fac[d.p + np * nf + (i0 + i) * nf + np + j0 + j];
+    for (long jc = j0; jc < j1; jc += kKC) {
+      const int nj = (int)min((long)kKC, j1 - jc);
+      for (int o = tid; o < kRB * kKC; o += blockDim.x) {
+        const int i = o / kKC, j = o % kKC;
+        R vr = R(0), vi = R(0);
+        if (i < cnt && j < nj) {
+          vr = fac[d.p + (i0 + i) * nf + np + jc + j];
+          vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
+        }
+        Ar_[i * LA + j] = vr;
+        Ai_[i * LA + j] = vi;
+      }
+      for (int o = tid; o < kKC * kSR; o += blockDim.x) {
+        const int j = o / kSR, r = o % kSR;
+        R vr = R(0), vi = R(0);
+        if (j < nj && r < nr) {
+          const long e = ib[d.bm + jc + j];
+          vr = Xr[e * nrhs + r0 + r];
+          vi = Xi[e * nrhs + r0 + r];
+        }
+        Br_[j * kLX + r] = vr;
+        Bi_[j * kLX + r] = vi;
       }
       __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int o = tid + 256 * u;
-        const int i = o / kRC, r = o % kRC;
-        if (i < cnt && r < nr) {
-          for (int j = 0; j < nj; ++j) {
-            accr[u] += Ar[i][j] * xr[j][r] - Ai[i][j] * xi[j][r];
-            acci[u] += Ar[i][j] * xi[j][r] + Ai[i][j] * xr[j][r];
-          }
-        }
-      }
+      cmma64<R>(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane, cr, ci);
       __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int o = tid + 256 * u;
-      const int i = o / kRC, r = o % kRC;
-      if (i < cnt && r < nr) {
-        Zr[(d.e0 + i0 + i) * nrhs + r0 + r] -= accr[u];
-        Zi[(d.e0 + i0 + i) * nrhs + r0 + r] -= acci[u];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+          if (row < cnt && col < nr) {
+            if (nks == 1) {
+              Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
+              Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+            } else {
+              const long o = (((long)q * nks_max + ks) * np_max + i0 + row) * nrhs + r0 + col;
+              Pr[o] = cr[a][b][r];
+              Pi[o] = ci[a][b][r];
+            }
+          }
+        }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                         int nlvl, int nks_max, long np_max, int nrhs,
+                                                         const R* __restrict__ Pr, const R* __restrict__ Pi,
+                                                         R* __restrict__ Zr, R* __restrict__ Zi) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    const int nks = (int)((d.nb + kKS - 1) / kKS);
+    if (nks < 2) continue;
+    const long cnt = (long)d.np * nrhs;
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
+      const long i = w / nrhs;
+      const int r = (int)(w % nrhs);
+      R sr = R(0), si = R(0);
+      for (int ks = 0; ks < nks; ++ks) {
+        const long o = (((long)q * nks_max + ks) * np_max + i) * nrhs + r;
+        sr += Pr[o];
+        si += Pi[o];
       }
+      Zr[(d.e0 + i) * nrhs + r] -= sr;
+      Zi[(d.e0 + i) * nrhs + r] -= si;
     }
   }
 }
 
-// backward step of tile kb: x_tile = U^-1 z_tile (written by workgroup 0), and
-// z_i -= U[i][tile] x_tile for 64 rows i < kb per workgroup
+// backward step of tile kb: x_tile = U^-1 z_tile (written to X by workgroup
+// 0), and z_i -= U[i][tile] x_tile for 64 rows i < kb per workgroup.
 template <typename R>
 __global__ __launch_bounds__(256) void bwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                        int nlvl, int kb, const R* __restrict__ fac, int nrhs,
                                                        R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                        R* __restrict__ Zi) {
-  __shared__ R yr[kT][kRC + 1], yi[kT][kRC + 1];
-  __shared__ R xr[kT][kRC + 1], xi[kT][kRC + 1];
-  __shared__ R Ar[kRB][kT + 1], Ai[kRB][kT + 1];
-  const int tid = threadIdx.x;
-  const int r0 = blockIdx.z * kRC;
-  const int nr = min(kRC, nrhs - r0);
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar_[kBuf], Ai_[kBuf];          // z_tile [kT][kLX], then the U block [kRB][kLL]
+  __shared__ R Yr_[kT * kLX], Yi_[kT * kLX];  // x_tile
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r0 = blockIdx.z * kSR;
+  const int nr = min(kSR, nrhs - r0);
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
     if (kb >= d.np) continue;
@@ -698,50 +852,62 @@ __global__ __launch_bounds__(256) void bwd_tile_kernel(const FrontDev* __restric
     const long nf = d.nf, np = d.np;
     const long i0 = (long)blockIdx.x * kRB;
     if (blockIdx.x > 0 && i0 >= kb) continue;
-    for (int o = tid; o < tw * kRC; o += blockDim.x) {
-      const int k = o / kRC, r = o % kRC;
-      if (r < nr) {
-        yr[k][r] = Zr[(d.e0 + kb + k) * nrhs + r0 + r];
-        yi[k][r] = Zi[(d.e0 + kb + k) * nrhs + r0 + r];
+    for (int o = tid; o < kT * kSR; o += blockDim.x) {
+      const int k = o / kSR, r = o % kSR;
+      R vr = R(0), vi = R(0);
+      if (k < tw && r < nr) {
+        vr = Zr[(d.e0 + kb + k) * nrhs + r0 + r];
+        vi = Zi[(d.e0 + kb + k) * nrhs + r0 + r];
       }
+      Ar_[k * kLX + r] = vr;
+      Ai_[k * kLX + r] = vi;
     }
     __syncthreads();
-    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems + 2 * kTileElems;
-    for (int o = tid; o < tw * kRC; o += blockDim.x) {
-      const int k = o / kRC, r = o % kRC;
-      if (r < nr) {
-        R sr = R(0), si = R(0);
-        for (int c = k; c < tw; ++c) {
-          const R ar = T[k * kT + c], ai = T[kTileElems + k * kT + c];
-          sr += ar * yr[c][r] - ai * yi[c][r];
-          si += ar * yi[c][r] + ai * yr[c][r];
-        }
-        xr[k][r] = sr;
-        xi[k][r] = si;
-        if (blockIdx.x == 0) {
-          Xr[(d.e0 + kb + k) * nrhs + r0 + r] = sr;
-          Xi[(d.e0 + kb + k) * nrhs + r0 + r] = si;
+    tile_inv_apply<R>(fac + d.t + (long)(kb / kT) * 4 * kTileElems + 2 * kTileElems, tw, Ar_, Ai_, kLX, Yr_, Yi_,
+                      kLX, wave, lane);
+    __syncthreads();
+    if (blockIdx.x == 0)
+      for (int o = tid; o < tw * kSR; o += blockDim.x) {
+        const int k = o / kSR, r = o % kSR;
+        if (r < nr) {
+          Xr[(d.e0 + kb + k) * nrhs + r0 + r] = Yr_[k * kLX + r];
+          Xi[(d.e0 + kb + k) * nrhs + r0 + r] = Yi_[k * kLX + r];
         }
       }
-    }
     const int cnt = (int)max(0L, min((long)kRB, (long)kb - i0));
-    for (int o = tid; o < cnt * tw; o += blockDim.x) {
-      const int i = o / tw, k = o % tw;
-      Ar[i][k] = fac[d.p + (i0 + i) * nf + kb + k];
-      Ai[i][k] = fac[d.p + np * nf + (i0 + i) * nf + kb + k];
-    }
-    __syncthreads();
-    for (int o = tid; o < cnt * kRC; o += blockDim.x) {
-      const int i = o / kRC, r = o % kRC;
-      if (r < nr) {
-        R sr = R(0), si = R(0);
-        for (int k = 0; k < tw; ++k) {
-          sr += Ar[i][k] * xr[k][r] - Ai[i][k] * xi[k][r];
-          si += Ar[i][k] * xi[k][r] + Ai[i][k] * xr[k][r];
+    if (cnt > 0) {
+      for (int o = tid; o < kRB * kT; o += blockDim.x) {
+        const int i = o / kT, k = o % kT;
+        R vr = R(0), vi = R(0);
+        if (i < cnt && k < tw) {
+          vr = fac[d.p + (i0 + i) * nf + kb + k];
+          vi = fac[d.p + np * nf + (i0 + i) * nf + kb + k];
         }
-        Zr[(d.e0 + i0 + i) * nrhs + r0 + r] -= sr;
-        Zi[(d.e0 + i0 + i) * nrhs + r0 + r] -= si;
+        Ar_[i * kLL + k] = vr;
+        Ai_[i * kLL + k] = vi;
       }
+      __syncthreads();
+      v4 cr[2][2], ci[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+          ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+        }
+      cmma64<R>(Ar_, Ai_, kLL, Yr_, Yi_, kLX, kT, wm, wn, lane, cr, ci);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+            if (row < cnt && col < nr) {
+              Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
+              Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+            }
+          }
     }
     __syncthreads();
   }
@@ -766,6 +932,7 @@ struct GpuSolver {
   DevBuf fd, lvl_d, ib, fac;
   long u_rows = 0;                     // sum of nb over the nodes
   DevBuf X, Z, U;                      // solve work, sized for cap_rhs
+  DevBuf P;                            // split-K partial sums of the U12 products
   int cap_rhs = 0;
   size_t bytes = 0;
   double flops = 0.0;
@@ -946,14 +1113,26 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
         hipLaunchKernelGGL(extend_add_kernel<R>, dim3(grid_for(mcnb * mcnb, 256, 1 << 16), gy), dim3(256), 0, s, fr,
                            lvl, nl, slot, ib, cbuf, buf);
       }
-    for (long kb = 0; kb < mnp; kb += kT) {
-      hipLaunchKernelGGL(diag_kernel<R>, dim3(gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf, fac, ib);
-      const long rest = mnf - kb - 1;           // rows right of / below the tile, at most
-      const int half = (int)std::max(1L, (rest + kRB - 1) / kRB);
-      hipLaunchKernelGGL(panel_kernel<R>, dim3(2 * half, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, half, buf,
-                         (const R*)fac, (const int*)ib);
-      const unsigned t64 = (unsigned)std::max(1L, (rest + 63) / 64);
-      hipLaunchKernelGGL(schur_kernel<R>, dim3(t64, t64, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf);
+    for (long kb0 = 0; kb0 < mnp; kb0 += kOB) {
+      const long kbe = std::min(mnp, kb0 + kOB);
+      for (long kb = kb0; kb < kbe; kb += kT) {
+        hipLaunchKernelGGL(diag_kernel<R>, dim3(gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf, fac, ib);
+        const long rest = mnf - kb - 1;           // rows right of / below the tile, at most
+        const int half = (int)std::max(1L, (rest + kRB - 1) / kRB);
+        hipLaunchKernelGGL(panel_kernel<R>, dim3(2 * half, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, half, buf,
+                           (const R*)fac, (const int*)ib);
+        const unsigned tall = (unsigned)std::max(1L, (rest + 63) / 64);
+        const unsigned blk = (unsigned)std::max(1L, (kbe - kb - 1 + 63) / 64);   // block columns left
+        if (kb + kT < kbe) {
+          hipLaunchKernelGGL(schur_kernel<R>, dim3(blk, tall, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb,
+                             (int)kb0, 0, buf);
+          hipLaunchKernelGGL(schur_kernel<R>, dim3(tall, blk, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb,
+                             (int)kb0, 1, buf);
+        }
+      }
+      const unsigned t64 = (unsigned)std::max(1L, (mnf - kb0 - 1 + 63) / 64);
+      hipLaunchKernelGGL(schur_kernel<R>, dim3(t64, t64, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, (int)kb0, 2,
+                         buf);
     }
     hipLaunchKernelGGL(copyout_kernel<R>, dim3(grid_for(mnf * mnf, 256, 1 << 16), gy), dim3(256), 0, s, fr, lvl, nl,
                        (const R*)buf, fac);
@@ -965,12 +1144,25 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
 
 template <typename R>
 ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
+  const int L = (int)g.levels.size();
+  // split-K partial sums of the U12 products: levels whose widest boundary
+  // needs more than one split
+  std::vector<int> nks(L, 1);
+  size_t pelems = 1;
+  for (int dep = 0; dep < L; ++dep) {
+    for (int id : g.levels[dep]) nks[dep] = std::max(nks[dep], (int)((g.fh[id].nb + kKS - 1) / kKS));
+    if (nks[dep] > 1)
+      pelems = std::max(pelems, (size_t)g.levels[dep].size() * nks[dep] * (size_t)g.lvl_np[dep] * nrhs);
+  }
   if (g.cap_rhs < nrhs) {
     LS_TRY(g.X.alloc(2 * (size_t)g.N * nrhs * sizeof(R)));
     LS_TRY(g.Z.alloc(2 * (size_t)g.N * nrhs * sizeof(R)));
     LS_TRY(g.U.alloc(2 * (size_t)std::max(1L, g.u_rows) * nrhs * sizeof(R)));
     g.cap_rhs = nrhs;
   }
+  if (g.P.bytes < 2 * pelems * sizeof(R)) LS_TRY(g.P.alloc(2 * pelems * sizeof(R)));
+  R* Pr = g.P.as<R>();
+  R* Pi = Pr + pelems;
   const long N = g.N;
   R* Xr = g.X.as<R>();
   R* Xi = Xr + N * nrhs;
@@ -981,8 +1173,7 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
   const FrontDev* fr = g.fd.as<FrontDev>();
   const int* ib = g.ib.as<int>();
   const R* fac = g.fac.as<R>();
-  const int L = (int)g.levels.size();
-  const unsigned gz = (unsigned)((nrhs + kRC - 1) / kRC);
+  const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
   hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N * nrhs, 256, 1 << 16)), dim3(256), 0, s, b, N, nrhs, ib, Xr,
                      Xi);
   hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
@@ -1014,8 +1205,11 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
     const unsigned gy = (unsigned)std::min(nl, 65535);
     const long mnp = g.lvl_np[dep];
     const unsigned gu = (unsigned)std::max(1L, (mnp + kRB - 1) / kRB);
-    hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz), dim3(256), 0, s, fr, lvl, nl, fac, ib, nrhs,
-                       (const R*)Xr, (const R*)Xi, Zr, Zi);
+    hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
+                       fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
+    if (nks[dep] > 1)
+      hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp * nrhs, 256, 1 << 14), gy), dim3(256), 0, s, fr,
+                         lvl, nl, nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
     for (long kb = ((mnp - 1) / kT) * kT; kb >= 0; kb -= kT) {
       const unsigned gx = (unsigned)std::max(1L, (kb + kRB - 1) / kRB);
       hipLaunchKernelGGL(bwd_tile_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb, fac, nrhs, Xr,
