@@ -147,19 +147,23 @@ __global__ __launch_bounds__(256) void extend_add_kernel(const FrontDev* __restr
     const FrontDev d = fr[lvl[q]];
     if (d.child[slot] < 0) continue;
     const FrontDev c = fr[d.child[slot]];
-    const long nf = d.nf, cnf = c.nf, cnb = c.nb;
+    const long nf = d.nf, cnf = c.nf;
+    const int cnb = c.nb;
     R* Fr = buf + d.f;
     R* Fi = Fr + nf * nf;
     const R* Cr = cbuf + c.f;
     const R* Ci = Cr + cnf * cnf;
-    const long cnt = cnb * cnb;
-    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
-      const long r = w / cnb, s = w % cnb;
+    for (int r = blockIdx.x; r < cnb; r += gridDim.x) {
       const long pr = 3L * ib[c.xm + r / 3] + r % 3;
-      const long ps = 3L * ib[c.xm + s / 3] + s % 3;
-      const long src = (c.np + r) * cnf + c.np + s;
-      Fr[pr * nf + ps] += Cr[src];
-      Fi[pr * nf + ps] += Ci[src];
+      const R* sr = Cr + (c.np + r) * cnf + c.np;
+      const R* si = Ci + (c.np + r) * cnf + c.np;
+      R* dr = Fr + pr * nf;
+      R* di = Fi + pr * nf;
+      for (int s = threadIdx.x; s < cnb; s += blockDim.x) {
+        const int ps = 3 * ib[c.xm + s / 3] + s % 3;
+        dr[ps] += sr[s];
+        di[ps] += si[s];
+      }
     }
   }
 }
@@ -500,45 +504,49 @@ __global__ __launch_bounds__(256) void copyout_kernel(const FrontDev* __restrict
     const R* Fr = buf + d.f;
     const R* Fi = Fr + nf * nf;
     const long c1 = np * nf, c2 = nb * np;
-    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < c1 + c2; w += (long)gridDim.x * blockDim.x) {
-      if (w < c1) {
-        fac[d.p + w] = Fr[w];
-        fac[d.p + c1 + w] = Fi[w];
-      } else {
-        const long o = w - c1, i = o / np, j = o % np;
-        fac[d.l + o] = Fr[(np + i) * nf + j];
-        fac[d.l + c2 + o] = Fi[(np + i) * nf + j];
-      }
+    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < c1; w += (long)gridDim.x * blockDim.x) {
+      fac[d.p + w] = Fr[w];
+      fac[d.p + c1 + w] = Fi[w];
     }
+    for (long i = blockIdx.x; i < nb; i += gridDim.x)
+      for (long j = threadIdx.x; j < np; j += blockDim.x) {
+        fac[d.l + i * np + j] = Fr[(np + i) * nf + j];
+        fac[d.l + c2 + i * np + j] = Fi[(np + i) * nf + j];
+      }
   }
 }
 
 // ---- solve kernels --------------------------------------------------------------------
 
+// b (complex128 [nrhs][N]) -> X ([N][nrhs] in elimination order, split planes);
+// four unknowns per workgroup pass, the right-hand sides across 64 lanes
 template <typename R>
-__global__ void sol_in_kernel(const C<double>* __restrict__ b, long N, int nrhs, const int* __restrict__ perm,
-                              R* __restrict__ Xr, R* __restrict__ Xi) {
-  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < N * nrhs; w += (long)gridDim.x * blockDim.x) {
-    const long e = w / nrhs;
-    const int r = (int)(w % nrhs);
-    const C<double> v = b[r * N + perm[e]];
-    Xr[w] = (R)v.re;
-    Xi[w] = (R)v.im;
+__global__ __launch_bounds__(256) void sol_in_kernel(const C<double>* __restrict__ b, long N, int nrhs,
+                                                     const int* __restrict__ perm, R* __restrict__ Xr,
+                                                     R* __restrict__ Xi) {
+  for (long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6); e < N; e += (long)gridDim.x * 4) {
+    const long pe = perm[e];
+    for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+      const C<double> v = b[r * N + pe];
+      Xr[e * nrhs + r] = (R)v.re;
+      Xi[e * nrhs + r] = (R)v.im;
+    }
   }
 }
 
 template <typename R>
-__global__ void sol_out_kernel(C<double>* __restrict__ b, long N, int nrhs, const int* __restrict__ perm,
-                               const R* __restrict__ Xr, const R* __restrict__ Xi) {
-  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < N * nrhs; w += (long)gridDim.x * blockDim.x) {
-    const long e = w / nrhs;
-    const int r = (int)(w % nrhs);
-    b[r * N + perm[e]] = cmk((double)Xr[w], (double)Xi[w]);
+__global__ __launch_bounds__(256) void sol_out_kernel(C<double>* __restrict__ b, long N, int nrhs,
+                                                      const int* __restrict__ perm, const R* __restrict__ Xr,
+                                                      const R* __restrict__ Xi) {
+  for (long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6); e < N; e += (long)gridDim.x * 4) {
+    const long pe = perm[e];
+    for (int r = threadIdx.x & 63; r < nrhs; r += 64)
+      b[r * N + pe] = cmk((double)Xr[e * nrhs + r], (double)Xi[e * nrhs + r]);
   }
 }
 
 // children's update vectors into the pivot rows (x) or the update vector (u)
-// of every front of a level, for child `slot`
+// of every front of a level, for child `slot`; four rows per workgroup pass
 template <typename R>
 __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                         int nlvl, int slot, const int* __restrict__ ib, int nrhs,
@@ -548,17 +556,17 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
     const FrontDev d = fr[lvl[q]];
     if (d.child[slot] < 0) continue;
     const FrontDev c = fr[d.child[slot]];
-    const long cnt = (long)c.nb * nrhs;
-    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
-      const long rr = w / nrhs;
-      const int r = (int)(w % nrhs);
-      const long pos = 3L * ib[c.xm + rr / 3] + rr % 3;
-      const long src = (c.u + rr) * nrhs + r;
-      const long dst = pos < d.np ? (d.e0 + pos) * nrhs + r : (d.u + pos - d.np) * nrhs + r;
-      R* Tr = pos < d.np ? Xr : Ur;
-      R* Ti = pos < d.np ? Xi : Ui;
-      Tr[dst] += Ur[src];
-      Ti[dst] += Ui[src];
+    for (int rr = blockIdx.x * 4 + (threadIdx.x >> 6); rr < c.nb; rr += gridDim.x * 4) {
+      const int pos = 3 * ib[c.xm + rr / 3] + rr % 3;
+      const bool piv = pos < d.np;
+      const long src = (c.u + rr) * nrhs;
+      const long dst = piv ? (long)(d.e0 + pos) * nrhs : (d.u + pos - d.np) * nrhs;
+      R* Tr = piv ? Xr : Ur;
+      R* Ti = piv ? Xi : Ui;
+      for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+        Tr[dst + r] += Ur[src + r];
+        Ti[dst + r] += Ui[src + r];
+      }
     }
   }
 }
@@ -591,133 +599,218 @@ __device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const 
   }
 }
 
-// Y (kT x kSR) = T X for a tile's triangular inverse T (global [kT][kT], re
-// plane then im plane; rows or columns >= tw read as zero) and X (kT x kSR)
-// in LDS; wave w computes the columns [16 w, 16 w + 16).
+// acc[rt] (rows 16 rt.., rt < 3; the 16 columns col0..col0+15) = A B for a
+// 48 x 48 block A read from global memory (A(i, k) = Ag[i * lda + k] for
+// i < arows and k < acols, zero elsewhere) and B rows of an LDS array
+// (B(k, c) = Bs[bidx(k) * ldb + c] for k < acols, zero elsewhere).
 template <typename R>
-__device__ __forceinline__ void tile_inv_apply(const R* __restrict__ T, int tw, const R* Xr, const R* Xi, int ldx,
-                                               R* Yr, R* Yi, int ldy, int wave, int lane) {
+__device__ __forceinline__ void mma48_gl(const R* __restrict__ Agr, const R* __restrict__ Agi, long lda, int arows,
+                                         int acols, const R* Bsr, const R* Bsi, int ldb, const int* bperm, int brow0,
+                                         int col0, int lane, typename Mma<R>::v4 (&yr)[3],
+                                         typename Mma<R>::v4 (&yi)[3]) {
   typedef typename Mma<R>::v4 v4;
-  const int c0 = 16 * wave + (lane & 15);
 #pragma unroll
-  for (int rt = 0; rt < kT / 16; ++rt) {
-    v4 yr = v4{R(0), R(0), R(0), R(0)}, yi = v4{R(0), R(0), R(0), R(0)};
-    const int row = 16 * rt + (lane & 15);
+  for (int rt = 0; rt < 3; ++rt) {
+    yr[rt] = v4{R(0), R(0), R(0), R(0)};
+    yi[rt] = v4{R(0), R(0), R(0), R(0)};
+  }
+  const int c = col0 + (lane & 15);
 #pragma unroll 4
-    for (int k4 = 0; k4 < kT; k4 += 4) {
-      const int k = k4 + (lane >> 4);
-      const bool ok = row < tw && k < tw;
-      const R ar = ok ? T[row * kT + k] : R(0);
-      const R ai = ok ? T[kTileElems + row * kT + k] : R(0);
-      const R br = Xr[k * ldx + c0], bi = Xi[k * ldx + c0];
-      yr = Mma<R>::op(ar, br, yr);
-      yr = Mma<R>::op(-ai, bi, yr);
-      yi = Mma<R>::op(ar, bi, yi);
-      yi = Mma<R>::op(ai, br, yi);
+  for (int k4 = 0; k4 < kT; k4 += 4) {
+    const int k = k4 + (lane >> 4);
+    R br = R(0), bi = R(0);
+    if (k < acols) {
+      const int row = brow0 + (bperm ? bperm[k] : k);
+      br = Bsr[row * ldb + c];
+      bi = Bsi[row * ldb + c];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      Yr[(16 * rt + Mma<R>::row(lane, r)) * ldy + c0] = yr[r];
-      Yi[(16 * rt + Mma<R>::row(lane, r)) * ldy + c0] = yi[r];
+    for (int rt = 0; rt < 3; ++rt) {
+      const int i = 16 * rt + (lane & 15);
+      const bool ok = i < arows && k < acols;
+      const R ar = ok ? Agr[i * lda + k] : R(0);
+      const R ai = ok ? Agi[i * lda + k] : R(0);
+      yr[rt] = Mma<R>::op(ar, br, yr[rt]);
+      yr[rt] = Mma<R>::op(-ai, bi, yr[rt]);
+      yi[rt] = Mma<R>::op(ar, bi, yi[rt]);
+      yi[rt] = Mma<R>::op(ai, br, yi[rt]);
     }
   }
 }
 
-constexpr int kLX = kSR + 1;                 // row stride of tile vectors in LDS
+constexpr int kLX = kSR + 1;                 // row stride of right-hand-side blocks in LDS
 constexpr int kLL = kT + 1;                  // row stride of a 64 x 48 factor block in LDS
-constexpr int kBuf = (kT * kLX > kRB * kLL) ? kT * kLX : kRB * kLL;
-
-// forward step of tile kb: z = L^-1 P x_tile (written to Z by workgroup 0),
-// and x_i -= L[i][tile] z for 64 rows i >= ke per workgroup (pivot rows in
-// x, boundary rows in the node's update vector); 64 rhs per workgroup.
+constexpr int kSB = kOB;                     // solve super-tile: four factor tiles
 template <typename R>
-__global__ __launch_bounds__(256) void fwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                       int nlvl, int kb, const R* __restrict__ fac,
-                                                       const int* __restrict__ ib, int nrhs, R* __restrict__ Xr,
-                                                       R* __restrict__ Xi, R* __restrict__ Zr, R* __restrict__ Zi,
-                                                       R* __restrict__ Ur, R* __restrict__ Ui) {
+struct SolveCfg {
+  static constexpr int RZ = sizeof(R) == 4 ? 64 : 32;   // rhs per super-tile workgroup (LDS: 192 x RZ)
+};
+
+// Forward super-tile [kb0, kb0 + sw) of every front of a level (one workgroup
+// per front and RZ right-hand sides): for each 48-row tile t, z_t = L^-1 P_t
+// x_t, then x_t' -= L[t'][t] z_t for the later tiles t' of the super-tile;
+// all in LDS, products on MFMA.  The super-tile's z goes to Z.
+template <typename R>
+__global__ __launch_bounds__(256) void fwd_super_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                        int nlvl, int kb0, const R* __restrict__ fac,
+                                                        const int* __restrict__ ib, int nrhs,
+                                                        const R* __restrict__ Xr, const R* __restrict__ Xi,
+                                                        R* __restrict__ Zr, R* __restrict__ Zi) {
   typedef typename Mma<R>::v4 v4;
-  __shared__ R Ar_[kBuf], Ai_[kBuf];          // P x_tile [kT][kLX], then the L block [kRB][kLL]
-  __shared__ R Yr_[kT * kLX], Yi_[kT * kLX];  // z
+  constexpr int RZ = SolveCfg<R>::RZ, LD = RZ + 1;
+  __shared__ R Sr[kSB * LD], Si[kSB * LD];
+  __shared__ int perm[kT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.z * RZ;
+  const int nr = min(RZ, nrhs - r0);
+  const bool active = wave < RZ / 16;
+  for (int q = blockIdx.x; q < nlvl; q += gridDim.x) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
+    const long nf = d.nf, np = d.np;
+    for (int o = tid; o < sw * RZ; o += blockDim.x) {
+      const int k = o / RZ, r = o % RZ;
+      R vr = R(0), vi = R(0);
+      if (r < nr) {
+        vr = Xr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
+        vi = Xi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
+      }
+      Sr[k * LD + r] = vr;
+      Si[k * LD + r] = vi;
+    }
+    for (int t0 = 0; t0 < sw; t0 += kT) {
+      const int tw = min(kT, sw - t0);
+      const long kb = kb0 + t0;
+      if (tid < tw) perm[tid] = ib[d.pv + kb + tid];
+      __syncthreads();
+      if (active) {   // z_t = L^-1 (P x_t), in place (each wave owns 16 columns)
+        v4 yr[3], yi[3];
+        const R* T = fac + d.t + (kb / kT) * 4 * kTileElems;
+        mma48_gl<R>(T, T + kTileElems, kT, tw, tw, Sr, Si, LD, perm, t0, 16 * wave, lane, yr, yi);
+#pragma unroll
+        for (int rt = 0; rt < 3; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * rt + Mma<R>::row(lane, r);
+            if (i < tw) {
+              Sr[(t0 + i) * LD + 16 * wave + (lane & 15)] = yr[rt][r];
+              Si[(t0 + i) * LD + 16 * wave + (lane & 15)] = yi[rt][r];
+            }
+          }
+      }
+      __syncthreads();
+      if (active)     // later tiles of the super-tile: x_t' -= L[t'][t] z_t
+        for (int u0 = t0 + kT; u0 < sw; u0 += kT) {
+          const int uw = min(kT, sw - u0);
+          v4 yr[3], yi[3];
+          const long a0 = (kb0 + u0) * nf + kb;
+          mma48_gl<R>(fac + d.p + a0, fac + d.p + np * nf + a0, nf, uw, tw, Sr, Si, LD, nullptr, t0, 16 * wave,
+                      lane, yr, yi);
+#pragma unroll
+          for (int rt = 0; rt < 3; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = 16 * rt + Mma<R>::row(lane, r);
+              if (i < uw) {
+                Sr[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yr[rt][r];
+                Si[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yi[rt][r];
+              }
+            }
+        }
+      __syncthreads();
+    }
+    for (int o = tid; o < sw * RZ; o += blockDim.x) {
+      const int k = o / RZ, r = o % RZ;
+      if (r < nr) {
+        Zr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Sr[k * LD + r];
+        Zi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Si[k * LD + r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Rows below the forward super-tile: x_i -= L[i][super-tile] z_super for 64
+// rows per workgroup (pivot rows in X, boundary rows in the update vector),
+// 64 rhs per workgroup, K in chunks of 48 through LDS.
+template <typename R>
+__global__ __launch_bounds__(256) void fwd_update_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                         int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                         R* __restrict__ Xr, R* __restrict__ Xi,
+                                                         const R* __restrict__ Zr, const R* __restrict__ Zi,
+                                                         R* __restrict__ Ur, R* __restrict__ Ui) {
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
+  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int r0 = blockIdx.z * kSR;
   const int nr = min(kSR, nrhs - r0);
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
-    if (kb >= d.np) continue;
-    const int tw = min(kT, d.np - kb);
-    const long ke = kb + tw, nf = d.nf, np = d.np;
-    const long i0 = ke + (long)blockIdx.x * kRB;
-    if (blockIdx.x > 0 && i0 >= nf) continue;
-    for (int o = tid; o < kT * kSR; o += blockDim.x) {
-      const int k = o / kSR, r = o % kSR;
-      R vr = R(0), vi = R(0);
-      if (k < tw && r < nr) {
-        const long e = d.e0 + kb + ib[d.pv + kb + k];
-        vr = Xr[e * nrhs + r0 + r];
-        vi = Xi[e * nrhs + r0 + r];
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
+    const long nf = d.nf, np = d.np, obe = kb0 + sw;
+    const long i0 = obe + (long)blockIdx.x * kRB;
+    if (i0 >= nf) continue;
+    const int cnt = (int)min((long)kRB, nf - i0);
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
       }
-      Ar_[k * kLX + r] = vr;
-      Ai_[k * kLX + r] = vi;
-    }
-    __syncthreads();
-    tile_inv_apply<R>(fac + d.t + (long)(kb / kT) * 4 * kTileElems, tw, Ar_, Ai_, kLX, Yr_, Yi_, kLX, wave, lane);
-    __syncthreads();
-    if (blockIdx.x == 0)
-      for (int o = tid; o < tw * kSR; o += blockDim.x) {
-        const int k = o / kSR, r = o % kSR;
-        if (r < nr) {
-          Zr[(d.e0 + kb + k) * nrhs + r0 + r] = Yr_[k * kLX + r];
-          Zi[(d.e0 + kb + k) * nrhs + r0 + r] = Yi_[k * kLX + r];
-        }
-      }
-    const int cnt = (int)max(0L, min((long)kRB, nf - i0));
-    if (cnt > 0) {
+    for (int kc = 0; kc < sw; kc += kT) {
+      const int kw = min(kT, sw - kc);
       for (int o = tid; o < kRB * kT; o += blockDim.x) {
         const int i = o / kT, k = o % kT;
         R vr = R(0), vi = R(0);
-        if (i < cnt && k < tw) {
-          const long gi = i0 + i;
+        if (i < cnt && k < kw) {
+          const long gi = i0 + i, col = kb0 + kc + k;
           if (gi < np) {
-            vr = fac[d.p + gi * nf + kb + k];
-            vi = fac[d.p + np * nf + gi * nf + kb + k];
+            vr = fac[d.p + gi * nf + col];
+            vi = fac[d.p + np * nf + gi * nf + col];
           } else {
-            vr = fac[d.l + (gi - np) * np + kb + k];
-            vi = fac[d.l + (long)d.nb * np + (gi - np) * np + kb + k];
+            vr = fac[d.l + (gi - np) * np + col];
+            vi = fac[d.l + (long)d.nb * np + (gi - np) * np + col];
           }
         }
         Ar_[i * kLL + k] = vr;
         Ai_[i * kLL + k] = vi;
       }
-      __syncthreads();
-      v4 cr[2][2], ci[2][2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-          ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+      for (int o = tid; o < kT * kSR; o += blockDim.x) {
+        const int k = o / kSR, r = o % kSR;
+        R vr = R(0), vi = R(0);
+        if (k < kw && r < nr) {
+          vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vi = Zi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
         }
-      cmma64<R>(Ar_, Ai_, kLL, Yr_, Yi_, kLX, kT, wm, wn, lane, cr, ci);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
-            if (row < cnt && col < nr) {
-              const long gi = i0 + row;
-              const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + col : (d.u + gi - np) * nrhs + r0 + col;
-              R* Tr = gi < np ? Xr : Ur;
-              R* Ti = gi < np ? Xi : Ui;
-              Tr[dst] -= cr[a][b][r];
-              Ti[dst] -= ci[a][b][r];
-            }
-          }
+        Br_[k * kLX + r] = vr;
+        Bi_[k * kLX + r] = vi;
+      }
+      __syncthreads();
+      cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
+      __syncthreads();
     }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+          if (row < cnt && col < nr) {
+            const long gi = i0 + row;
+            const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + col : (d.u + gi - np) * nrhs + r0 + col;
+            R* Tr = gi < np ? Xr : Ur;
+            R* Ti = gi < np ? Xi : Ui;
+            Tr[dst] -= cr[a][b][r];
+            Ti[dst] -= ci[a][b][r];
+          }
+        }
   }
 }
 
@@ -815,101 +908,166 @@ __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restr
     const FrontDev d = fr[lvl[q]];
     const int nks = (int)((d.nb + kKS - 1) / kKS);
     if (nks < 2) continue;
-    const long cnt = (long)d.np * nrhs;
-    for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < cnt; w += (long)gridDim.x * blockDim.x) {
-      const long i = w / nrhs;
-      const int r = (int)(w % nrhs);
-      R sr = R(0), si = R(0);
-      for (int ks = 0; ks < nks; ++ks) {
-        const long o = (((long)q * nks_max + ks) * np_max + i) * nrhs + r;
-        sr += Pr[o];
-        si += Pi[o];
+    for (long i = (long)blockIdx.x * 4 + (threadIdx.x >> 6); i < d.np; i += (long)gridDim.x * 4)
+      for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+        R sr = R(0), si = R(0);
+        for (int ks = 0; ks < nks; ++ks) {
+          const long o = (((long)q * nks_max + ks) * np_max + i) * nrhs + r;
+          sr += Pr[o];
+          si += Pi[o];
+        }
+        Zr[(d.e0 + i) * nrhs + r] -= sr;
+        Zi[(d.e0 + i) * nrhs + r] -= si;
       }
-      Zr[(d.e0 + i) * nrhs + r] -= sr;
-      Zi[(d.e0 + i) * nrhs + r] -= si;
-    }
   }
 }
 
-// backward step of tile kb: x_tile = U^-1 z_tile (written to X by workgroup
-// 0), and z_i -= U[i][tile] x_tile for 64 rows i < kb per workgroup.
+// Backward super-tile [kb0, kb0 + sw) (one workgroup per front and RZ rhs):
+// for the tiles from last to first, x_t = U^-1 y_t, then y_t' -= U[t'][t] x_t
+// for the earlier tiles t'; the super-tile's x goes to X.
 template <typename R>
-__global__ __launch_bounds__(256) void bwd_tile_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                       int nlvl, int kb, const R* __restrict__ fac, int nrhs,
-                                                       R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
-                                                       R* __restrict__ Zi) {
+__global__ __launch_bounds__(256) void bwd_super_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                        int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                        R* __restrict__ Xr, R* __restrict__ Xi,
+                                                        const R* __restrict__ Zr, const R* __restrict__ Zi) {
   typedef typename Mma<R>::v4 v4;
-  __shared__ R Ar_[kBuf], Ai_[kBuf];          // z_tile [kT][kLX], then the U block [kRB][kLL]
-  __shared__ R Yr_[kT * kLX], Yi_[kT * kLX];  // x_tile
+  constexpr int RZ = SolveCfg<R>::RZ, LD = RZ + 1;
+  __shared__ R Sr[kSB * LD], Si[kSB * LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.z * RZ;
+  const int nr = min(RZ, nrhs - r0);
+  const bool active = wave < RZ / 16;
+  for (int q = blockIdx.x; q < nlvl; q += gridDim.x) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
+    const long nf = d.nf, np = d.np;
+    for (int o = tid; o < sw * RZ; o += blockDim.x) {
+      const int k = o / RZ, r = o % RZ;
+      R vr = R(0), vi = R(0);
+      if (r < nr) {
+        vr = Zr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
+        vi = Zi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
+      }
+      Sr[k * LD + r] = vr;
+      Si[k * LD + r] = vi;
+    }
+    __syncthreads();
+    for (int t0 = ((sw - 1) / kT) * kT; t0 >= 0; t0 -= kT) {
+      const int tw = min(kT, sw - t0);
+      const long kb = kb0 + t0;
+      if (active) {   // x_t = U^-1 y_t, in place
+        v4 yr[3], yi[3];
+        const R* T = fac + d.t + (kb / kT) * 4 * kTileElems + 2 * kTileElems;
+        mma48_gl<R>(T, T + kTileElems, kT, tw, tw, Sr, Si, LD, nullptr, t0, 16 * wave, lane, yr, yi);
+#pragma unroll
+        for (int rt = 0; rt < 3; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * rt + Mma<R>::row(lane, r);
+            if (i < tw) {
+              Sr[(t0 + i) * LD + 16 * wave + (lane & 15)] = yr[rt][r];
+              Si[(t0 + i) * LD + 16 * wave + (lane & 15)] = yi[rt][r];
+            }
+          }
+      }
+      __syncthreads();
+      if (active)     // earlier tiles: y_t' -= U[t'][t] x_t
+        for (int u0 = 0; u0 < t0; u0 += kT) {
+          v4 yr[3], yi[3];
+          const long a0 = (kb0 + u0) * nf + kb;
+          mma48_gl<R>(fac + d.p + a0, fac + d.p + np * nf + a0, nf, kT, tw, Sr, Si, LD, nullptr, t0, 16 * wave,
+                      lane, yr, yi);
+#pragma unroll
+          for (int rt = 0; rt < 3; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = 16 * rt + Mma<R>::row(lane, r);
+              Sr[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yr[rt][r];
+              Si[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yi[rt][r];
+            }
+        }
+      __syncthreads();
+    }
+    for (int o = tid; o < sw * RZ; o += blockDim.x) {
+      const int k = o / RZ, r = o % RZ;
+      if (r < nr) {
+        Xr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Sr[k * LD + r];
+        Xi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Si[k * LD + r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Rows above the backward super-tile: z_i -= U[i][super-tile] x_super for 64
+// rows i < kb0 per workgroup, 64 rhs per workgroup.
+template <typename R>
+__global__ __launch_bounds__(256) void bwd_update_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                         int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                         const R* __restrict__ Xr, const R* __restrict__ Xi,
+                                                         R* __restrict__ Zr, R* __restrict__ Zi) {
+  typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
+  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int r0 = blockIdx.z * kSR;
   const int nr = min(kSR, nrhs - r0);
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
-    if (kb >= d.np) continue;
-    const int tw = min(kT, d.np - kb);
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
     const long nf = d.nf, np = d.np;
     const long i0 = (long)blockIdx.x * kRB;
-    if (blockIdx.x > 0 && i0 >= kb) continue;
-    for (int o = tid; o < kT * kSR; o += blockDim.x) {
-      const int k = o / kSR, r = o % kSR;
-      R vr = R(0), vi = R(0);
-      if (k < tw && r < nr) {
-        vr = Zr[(d.e0 + kb + k) * nrhs + r0 + r];
-        vi = Zi[(d.e0 + kb + k) * nrhs + r0 + r];
+    if (i0 >= kb0) continue;
+    const int cnt = (int)min((long)kRB, kb0 - i0);
+    v4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
       }
-      Ar_[k * kLX + r] = vr;
-      Ai_[k * kLX + r] = vi;
-    }
-    __syncthreads();
-    tile_inv_apply<R>(fac + d.t + (long)(kb / kT) * 4 * kTileElems + 2 * kTileElems, tw, Ar_, Ai_, kLX, Yr_, Yi_,
-                      kLX, wave, lane);
-    __syncthreads();
-    if (blockIdx.x == 0)
-      for (int o = tid; o < tw * kSR; o += blockDim.x) {
-        const int k = o / kSR, r = o % kSR;
-        if (r < nr) {
-          Xr[(d.e0 + kb + k) * nrhs + r0 + r] = Yr_[k * kLX + r];
-          Xi[(d.e0 + kb + k) * nrhs + r0 + r] = Yi_[k * kLX + r];
-        }
-      }
-    const int cnt = (int)max(0L, min((long)kRB, (long)kb - i0));
-    if (cnt > 0) {
+    for (int kc = 0; kc < sw; kc += kT) {
+      const int kw = min(kT, sw - kc);
       for (int o = tid; o < kRB * kT; o += blockDim.x) {
         const int i = o / kT, k = o % kT;
         R vr = R(0), vi = R(0);
-        if (i < cnt && k < tw) {
-          vr = fac[d.p + (i0 + i) * nf + kb + k];
-          vi = fac[d.p + np * nf + (i0 + i) * nf + kb + k];
+        if (i < cnt && k < kw) {
+          vr = fac[d.p + (i0 + i) * nf + kb0 + kc + k];
+          vi = fac[d.p + np * nf + (i0 + i) * nf + kb0 + kc + k];
         }
         Ar_[i * kLL + k] = vr;
         Ai_[i * kLL + k] = vi;
       }
-      __syncthreads();
-      v4 cr[2][2], ci[2][2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-          ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+      for (int o = tid; o < kT * kSR; o += blockDim.x) {
+        const int k = o / kSR, r = o % kSR;
+        R vr = R(0), vi = R(0);
+        if (k < kw && r < nr) {
+          vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vi = Xi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
         }
-      cmma64<R>(Ar_, Ai_, kLL, Yr_, Yi_, kLX, kT, wm, wn, lane, cr, ci);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
-            if (row < cnt && col < nr) {
-              Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
-              Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
-            }
-          }
+        Br_[k * kLX + r] = vr;
+        Bi_[k * kLX + r] = vi;
+      }
+      __syncthreads();
+      cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
+      __syncthreads();
     }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+          if (row < cnt && col < nr) {
+            Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
+            Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+          }
+        }
   }
 }
 
@@ -1110,8 +1268,8 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
         for (int id : g.levels[dep])
           if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
         if (mcnb == 0) continue;
-        hipLaunchKernelGGL(extend_add_kernel<R>, dim3(grid_for(mcnb * mcnb, 256, 1 << 16), gy), dim3(256), 0, s, fr,
-                           lvl, nl, slot, ib, cbuf, buf);
+        hipLaunchKernelGGL(extend_add_kernel<R>, dim3((unsigned)std::min(mcnb, 8192L), std::min(gy, 64u)),
+                           dim3(256), 0, s, fr, lvl, nl, slot, ib, cbuf, buf);
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kOB) {
       const long kbe = std::min(mnp, kb0 + kOB);
@@ -1134,8 +1292,8 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
       hipLaunchKernelGGL(schur_kernel<R>, dim3(t64, t64, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, (int)kb0, 2,
                          buf);
     }
-    hipLaunchKernelGGL(copyout_kernel<R>, dim3(grid_for(mnf * mnf, 256, 1 << 16), gy), dim3(256), 0, s, fr, lvl, nl,
-                       (const R*)buf, fac);
+    hipLaunchKernelGGL(copyout_kernel<R>, dim3(grid_for(mnf * mnf, 256, 8192), std::min(gy, 64u)), dim3(256), 0, s,
+                       fr, lvl, nl, (const R*)buf, fac);
     LS_HIP(hipGetLastError());
   }
   LS_HIP(hipStreamSynchronize(s));
@@ -1174,8 +1332,8 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
   const int* ib = g.ib.as<int>();
   const R* fac = g.fac.as<R>();
   const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
-  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N * nrhs, 256, 1 << 16)), dim3(256), 0, s, b, N, nrhs, ib, Xr,
-                     Xi);
+  const unsigned gzz = (unsigned)((nrhs + SolveCfg<R>::RZ - 1) / SolveCfg<R>::RZ);
+  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
   hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
                      s, Ur, 2 * std::max(1L, g.u_rows) * nrhs);
   for (int dep = L - 1; dep >= 0; --dep) {
@@ -1189,14 +1347,15 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
         for (int id : g.levels[dep])
           if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
         if (mcnb == 0) continue;
-        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3(grid_for(mcnb * nrhs, 256, 1 << 14), gy), dim3(256), 0, s, fr,
-                           lvl, nl, slot, ib, nrhs, Xr, Xi, Ur, Ui);
+        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3(grid_for(mcnb, 4, 1024), std::min(gy, 64u)), dim3(256), 0, s,
+                           fr, lvl, nl, slot, ib, nrhs, Xr, Xi, Ur, Ui);
       }
-    for (long kb = 0; kb < mnp; kb += kT) {
-      const long rest = mnf - kb - 1;
-      const unsigned gx = (unsigned)std::max(1L, (rest + kRB - 1) / kRB);
-      hipLaunchKernelGGL(fwd_tile_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb, fac, ib, nrhs,
-                         Xr, Xi, Zr, Zi, Ur, Ui);
+    for (long kb0 = 0; kb0 < mnp; kb0 += kSB) {
+      hipLaunchKernelGGL(fwd_super_kernel<R>, dim3(gy, 1, gzz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, ib,
+                         nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi);
+      const unsigned gx = (unsigned)std::max(1L, (mnf - kb0 - 1 + kRB - 1) / kRB);
+      hipLaunchKernelGGL(fwd_update_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
+                         Xr, Xi, (const R*)Zr, (const R*)Zi, Ur, Ui);
     }
   }
   for (int dep = 0; dep < L; ++dep) {
@@ -1208,16 +1367,20 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
                        fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
     if (nks[dep] > 1)
-      hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp * nrhs, 256, 1 << 14), gy), dim3(256), 0, s, fr,
+      hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp, 4, 4096), std::min(gy, 64u)), dim3(256), 0, s, fr,
                          lvl, nl, nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
-    for (long kb = ((mnp - 1) / kT) * kT; kb >= 0; kb -= kT) {
-      const unsigned gx = (unsigned)std::max(1L, (kb + kRB - 1) / kRB);
-      hipLaunchKernelGGL(bwd_tile_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb, fac, nrhs, Xr,
-                         Xi, Zr, Zi);
+    for (long kb0 = ((mnp - 1) / kSB) * kSB; kb0 >= 0; kb0 -= kSB) {
+      hipLaunchKernelGGL(bwd_super_kernel<R>, dim3(gy, 1, gzz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
+                         Xr, Xi, (const R*)Zr, (const R*)Zi);
+      if (kb0 > 0) {
+        const unsigned gx = (unsigned)((kb0 + kRB - 1) / kRB);
+        hipLaunchKernelGGL(bwd_update_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
+                           nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi);
+      }
     }
   }
-  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N * nrhs, 256, 1 << 16)), dim3(256), 0, s, b, N, nrhs, ib,
-                     (const R*)Xr, (const R*)Xi);
+  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, (const R*)Xr,
+                     (const R*)Xi);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
