@@ -68,6 +68,8 @@ struct FrontDev {
   long xm;   // ints: boundary point a -> parent front point position
   long bm;   // ints: boundary unknown j -> elimination index
   long u;    // solve: first row of the node's update vector
+  long m;    // factor: per super-block forward map M (z = M x on the block), [kSB][kSB] re, then im
+  long h;    // factor: per super-block backward map H = U_block^-1, same layout
 };
 
 // ---- MFMA operand conventions -------------------------------------------------------
@@ -646,115 +648,217 @@ struct SolveCfg {
   static constexpr int RZ = sizeof(R) == 4 ? 64 : 32;   // rhs per super-tile workgroup (LDS: 192 x RZ)
 };
 
-// Forward super-tile [kb0, kb0 + sw) of every front of a level (one workgroup
-// per front and RZ right-hand sides): for each 48-row tile t, z_t = L^-1 P_t
-// x_t, then x_t' -= L[t'][t] z_t for the later tiles t' of the super-tile;
-// all in LDS, products on MFMA.  The super-tile's z goes to Z.
-template <typename R>
-__global__ __launch_bounds__(256) void fwd_super_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                        int nlvl, int kb0, const R* __restrict__ fac,
-                                                        const int* __restrict__ ib, int nrhs,
-                                                        const R* __restrict__ Xr, const R* __restrict__ Xi,
-                                                        R* __restrict__ Zr, R* __restrict__ Zi) {
+// Selective inversion of each super-block [kb0, kb0 + sw) of a front's pivot
+// block, at factor time (the front still in its level buffer F):
+//   FWD: M with z_block = M x_block for the forward tile procedure (for each
+//        48-row tile t: x_t <- L_t^-1 P_t x_t, then x_t' -= L[t'][t] x_t for
+//        the later tiles t' of the block);
+//   BWD: H = U_block^-1 (tiles from last to first: x_t <- U_t^-1 x_t, then
+//        x_t' -= U[t'][t] x_t for the earlier tiles).
+// Each workgroup runs the procedure on RZ columns of the identity in LDS
+// (grid.y: super-blocks, grid.z: column chunks), products on MFMA.
+template <typename R, bool FWD>
+__global__ __launch_bounds__(256) void sb_inverse_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                         int nlvl, const R* __restrict__ buf, R* __restrict__ fac,
+                                                         const int* __restrict__ ib) {
   typedef typename Mma<R>::v4 v4;
   constexpr int RZ = SolveCfg<R>::RZ, LD = RZ + 1;
   __shared__ R Sr[kSB * LD], Si[kSB * LD];
   __shared__ int perm[kT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = blockIdx.z * RZ;
-  const int nr = min(RZ, nrhs - r0);
   const bool active = wave < RZ / 16;
   for (int q = blockIdx.x; q < nlvl; q += gridDim.x) {
     const FrontDev d = fr[lvl[q]];
-    if (kb0 >= d.np) continue;
-    const int sw = min(kSB, d.np - kb0);
-    const long nf = d.nf, np = d.np;
-    for (int o = tid; o < sw * RZ; o += blockDim.x) {
-      const int k = o / RZ, r = o % RZ;
-      R vr = R(0), vi = R(0);
-      if (r < nr) {
-        vr = Xr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
-        vi = Xi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
-      }
-      Sr[k * LD + r] = vr;
-      Si[k * LD + r] = vi;
-    }
-    for (int t0 = 0; t0 < sw; t0 += kT) {
-      const int tw = min(kT, sw - t0);
-      const long kb = kb0 + t0;
-      if (tid < tw) perm[tid] = ib[d.pv + kb + tid];
-      __syncthreads();
-      if (active) {   // z_t = L^-1 (P x_t), in place (each wave owns 16 columns)
-        v4 yr[3], yi[3];
-        const R* T = fac + d.t + (kb / kT) * 4 * kTileElems;
-        mma48_gl<R>(T, T + kTileElems, kT, tw, tw, Sr, Si, LD, perm, t0, 16 * wave, lane, yr, yi);
-#pragma unroll
-        for (int rt = 0; rt < 3; ++rt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * rt + Mma<R>::row(lane, r);
-            if (i < tw) {
-              Sr[(t0 + i) * LD + 16 * wave + (lane & 15)] = yr[rt][r];
-              Si[(t0 + i) * LD + 16 * wave + (lane & 15)] = yi[rt][r];
-            }
-          }
+    const long nf = d.nf;
+    const R* Fr = buf + d.f;
+    const R* Fi = Fr + nf * nf;
+    for (int sb = blockIdx.y; (long)sb * kSB < d.np; sb += gridDim.y) {
+      const int kb0 = sb * kSB;
+      const int sw = min(kSB, d.np - kb0);
+      const int c0 = blockIdx.z * RZ;
+      if (c0 >= sw) continue;
+      for (int o = tid; o < kSB * RZ; o += blockDim.x) {
+        const int k = o / RZ, r = o % RZ;
+        Sr[k * LD + r] = (k == c0 + r && k < sw) ? R(1) : R(0);
+        Si[k * LD + r] = R(0);
       }
       __syncthreads();
-      if (active)     // later tiles of the super-tile: x_t' -= L[t'][t] z_t
-        for (int u0 = t0 + kT; u0 < sw; u0 += kT) {
-          const int uw = min(kT, sw - u0);
+      const int nt = (sw + kT - 1) / kT;
+      for (int s = 0; s < nt; ++s) {
+        const int t0 = FWD ? s * kT : (nt - 1 - s) * kT;
+        const int tw = min(kT, sw - t0);
+        const long kb = kb0 + t0;
+        if (FWD && tid < tw) perm[tid] = ib[d.pv + kb + tid];
+        __syncthreads();
+        if (active) {   // x_t <- L_t^-1 P_t x_t  or  U_t^-1 x_t, in place
           v4 yr[3], yi[3];
-          const long a0 = (kb0 + u0) * nf + kb;
-          mma48_gl<R>(fac + d.p + a0, fac + d.p + np * nf + a0, nf, uw, tw, Sr, Si, LD, nullptr, t0, 16 * wave,
-                      lane, yr, yi);
+          const R* T = fac + d.t + (kb / kT) * 4 * kTileElems + (FWD ? 0 : 2 * kTileElems);
+          mma48_gl<R>(T, T + kTileElems, kT, tw, tw, Sr, Si, LD, FWD ? perm : nullptr, t0, 16 * wave, lane, yr, yi);
 #pragma unroll
           for (int rt = 0; rt < 3; ++rt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = 16 * rt + Mma<R>::row(lane, r);
-              if (i < uw) {
-                Sr[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yr[rt][r];
-                Si[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yi[rt][r];
+              if (i < tw) {
+                Sr[(t0 + i) * LD + 16 * wave + (lane & 15)] = yr[rt][r];
+                Si[(t0 + i) * LD + 16 * wave + (lane & 15)] = yi[rt][r];
               }
             }
         }
+        __syncthreads();
+        if (active) {   // the other tiles of the block: x_t' -= F[t'][t] x_t
+          const int ua = FWD ? t0 + kT : 0, ue = FWD ? sw : t0;
+          for (int u0 = ua; u0 < ue; u0 += kT) {
+            const int uw = min(kT, sw - u0);
+            v4 yr[3], yi[3];
+            const long a0 = (kb0 + u0) * nf + kb;
+            mma48_gl<R>(Fr + a0, Fi + a0, nf, uw, tw, Sr, Si, LD, nullptr, t0, 16 * wave, lane, yr, yi);
+#pragma unroll
+            for (int rt = 0; rt < 3; ++rt)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = 16 * rt + Mma<R>::row(lane, r);
+                if (i < uw) {
+                  Sr[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yr[rt][r];
+                  Si[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yi[rt][r];
+                }
+              }
+          }
+        }
+        __syncthreads();
+      }
+      R* Mr = fac + (FWD ? d.m : d.h) + (long)sb * 2 * kSB * kSB;
+      R* Mi = Mr + kSB * kSB;
+      for (int o = tid; o < sw * RZ; o += blockDim.x) {
+        const int k = o / RZ, r = o % RZ;
+        if (c0 + r < sw) {
+          Mr[k * kSB + c0 + r] = Sr[k * LD + r];
+          Mi[k * kSB + c0 + r] = Si[k * LD + r];
+        }
+      }
       __syncthreads();
     }
-    for (int o = tid; o < sw * RZ; o += blockDim.x) {
-      const int k = o / RZ, r = o % RZ;
-      if (r < nr) {
-        Zr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Sr[k * LD + r];
-        Zi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Si[k * LD + r];
-      }
-    }
-    __syncthreads();
   }
 }
 
-// Rows below the forward super-tile: x_i -= L[i][super-tile] z_super for 64
-// rows per workgroup (pivot rows in X, boundary rows in the update vector),
-// 64 rhs per workgroup, K in chunks of 48 through LDS.
-template <typename R>
-__global__ __launch_bounds__(256) void fwd_update_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                         int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
-                                                         R* __restrict__ Xr, R* __restrict__ Xi,
-                                                         const R* __restrict__ Zr, const R* __restrict__ Zi,
-                                                         R* __restrict__ Ur, R* __restrict__ Ui) {
+// The factor entries outside a super-block that multiply its unknowns, folded
+// with the block's map: LU = 0: Lhat[i][block] = L[i][block] M for the rows
+// below the block (pivot rows after it and boundary rows); LU = 1:
+// Uhat[i][block] = U[i][block] H for the pivot rows above it.  Read from the
+// front F, written into the factor; 64 x 64 output tile per workgroup (grid.y:
+// super-block x three column tiles), K = the block width in chunks of 48.
+template <typename R, int LU>
+__global__ __launch_bounds__(256) void hat_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                  int nlvl, const R* __restrict__ buf, R* __restrict__ fac) {
   typedef typename Mma<R>::v4 v4;
+  __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
+  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  constexpr int NCT = kSB / 64;
+  for (int q = blockIdx.z; q < nlvl; q += gridDim.z) {
+    const FrontDev d = fr[lvl[q]];
+    const long nf = d.nf, np = d.np;
+    const R* Fr = buf + d.f;
+    const R* Fi = Fr + nf * nf;
+    for (int y = blockIdx.y; (long)(y / NCT) * kSB < np; y += gridDim.y) {
+      const int sb = y / NCT, ct = y % NCT;
+      const long kb0 = (long)sb * kSB;
+      const int sw = (int)min((long)kSB, np - kb0);
+      const int j0 = ct * 64;
+      if (j0 >= sw) continue;
+      const long r0 = LU == 0 ? kb0 + sw : 0, r1 = LU == 0 ? nf : kb0;
+      const long i0 = r0 + (long)blockIdx.x * kRB;
+      if (i0 >= r1) continue;
+      const int cnt = (int)min((long)kRB, r1 - i0);
+      const R* Br = fac + (LU == 0 ? d.m : d.h) + (long)sb * 2 * kSB * kSB;
+      const R* Bi = Br + kSB * kSB;
+      v4 cr[2][2], ci[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+          ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+        }
+      for (int kc = 0; kc < sw; kc += kT) {
+        const int kw = min(kT, sw - kc);
+        for (int o = tid; o < kRB * kT; o += blockDim.x) {
+          const int i = o / kT, k = o % kT;
+          const bool ok = i < cnt && k < kw;
+          const long src = (i0 + i) * nf + kb0 + kc + k;
+          Ar_[i * kLL + k] = ok ? Fr[src] : R(0);
+          Ai_[i * kLL + k] = ok ? Fi[src] : R(0);
+        }
+        for (int o = tid; o < kT * 64; o += blockDim.x) {
+          const int k = o / 64, c = o % 64;
+          const bool ok = k < kw && j0 + c < sw;
+          Br_[k * kLX + c] = ok ? Br[(kc + k) * kSB + j0 + c] : R(0);
+          Bi_[k * kLX + c] = ok ? Bi[(kc + k) * kSB + j0 + c] : R(0);
+        }
+        __syncthreads();
+        cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+            if (row < cnt && j0 + col < sw) {
+              const long gi = i0 + row, gc = kb0 + j0 + col;
+              if (gi < np) {
+                fac[d.p + gi * nf + gc] = cr[a][b][r];
+                fac[d.p + np * nf + gi * nf + gc] = ci[a][b][r];
+              } else {
+                fac[d.l + (gi - np) * np + gc] = cr[a][b][r];
+                fac[d.l + (long)d.nb * np + (gi - np) * np + gc] = ci[a][b][r];
+              }
+            }
+          }
+    }
+  }
+}
+
+// Forward solve step of super-block [kb0, kb0 + sw) of every front of a
+// level.  Workgroups [0, 3): z_block (64 rows each) = M x_block, written to Z.
+// The others: 64 rows i below the block: x_i -= Lhat[i][block] x_block (pivot
+// rows in X, boundary rows in the node's update vector).  Both read only the
+// block's x rows, which no workgroup writes.  64 rhs per workgroup.
+template <typename R>
+__global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                     int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                     R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
+                                                     R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
+  typedef typename Mma<R>::v4 v4;
+  constexpr int NZB = kSB / kRB;
   __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
   __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int r0 = blockIdx.z * kSR;
   const int nr = min(kSR, nrhs - r0);
+  const bool zrole = (int)blockIdx.x < NZB;
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
     if (kb0 >= d.np) continue;
     const int sw = min(kSB, d.np - kb0);
-    const long nf = d.nf, np = d.np, obe = kb0 + sw;
-    const long i0 = obe + (long)blockIdx.x * kRB;
-    if (i0 >= nf) continue;
-    const int cnt = (int)min((long)kRB, nf - i0);
+    const long nf = d.nf, np = d.np;
+    long i0;
+    int cnt;
+    if (zrole) {
+      i0 = (long)blockIdx.x * kRB;                       // rows of the block
+      if (i0 >= sw) continue;
+      cnt = (int)min((long)kRB, sw - i0);
+    } else {
+      i0 = kb0 + sw + (long)(blockIdx.x - NZB) * kRB;    // rows below it
+      if (i0 >= nf) continue;
+      cnt = (int)min((long)kRB, nf - i0);
+    }
+    const R* Mr = fac + d.m + (long)(kb0 / kSB) * 2 * kSB * kSB;
+    const R* Mi = Mr + kSB * kSB;
     v4 cr[2][2], ci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -769,13 +873,18 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const FrontDev* __restr
         const int i = o / kT, k = o % kT;
         R vr = R(0), vi = R(0);
         if (i < cnt && k < kw) {
-          const long gi = i0 + i, col = kb0 + kc + k;
-          if (gi < np) {
-            vr = fac[d.p + gi * nf + col];
-            vi = fac[d.p + np * nf + gi * nf + col];
+          if (zrole) {
+            vr = Mr[(i0 + i) * kSB + kc + k];
+            vi = Mi[(i0 + i) * kSB + kc + k];
           } else {
-            vr = fac[d.l + (gi - np) * np + col];
-            vi = fac[d.l + (long)d.nb * np + (gi - np) * np + col];
+            const long gi = i0 + i, col = kb0 + kc + k;
+            if (gi < np) {
+              vr = fac[d.p + gi * nf + col];
+              vi = fac[d.p + np * nf + gi * nf + col];
+            } else {
+              vr = fac[d.l + (gi - np) * np + col];
+              vi = fac[d.l + (long)d.nb * np + (gi - np) * np + col];
+            }
           }
         }
         Ar_[i * kLL + k] = vr;
@@ -785,8 +894,8 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const FrontDev* __restr
         const int k = o / kSR, r = o % kSR;
         R vr = R(0), vi = R(0);
         if (k < kw && r < nr) {
-          vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
-          vi = Zi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vi = Xi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
         }
         Br_[k * kLX + r] = vr;
         Bi_[k * kLX + r] = vi;
@@ -803,12 +912,17 @@ __global__ __launch_bounds__(256) void fwd_update_kernel(const FrontDev* __restr
         for (int r = 0; r < 4; ++r) {
           const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
           if (row < cnt && col < nr) {
-            const long gi = i0 + row;
-            const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + col : (d.u + gi - np) * nrhs + r0 + col;
-            R* Tr = gi < np ? Xr : Ur;
-            R* Ti = gi < np ? Xi : Ui;
-            Tr[dst] -= cr[a][b][r];
-            Ti[dst] -= ci[a][b][r];
+            if (zrole) {
+              Zr[(d.e0 + kb0 + i0 + row) * nrhs + r0 + col] = cr[a][b][r];
+              Zi[(d.e0 + kb0 + i0 + row) * nrhs + r0 + col] = ci[a][b][r];
+            } else {
+              const long gi = i0 + row;
+              const long dst = gi < np ? (d.e0 + gi) * nrhs + r0 + col : (d.u + gi - np) * nrhs + r0 + col;
+              R* Tr = gi < np ? Xr : Ur;
+              R* Ti = gi < np ? Xi : Ui;
+              Tr[dst] -= cr[a][b][r];
+              Ti[dst] -= ci[a][b][r];
+            }
           }
         }
   }
@@ -922,106 +1036,41 @@ __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restr
   }
 }
 
-// Backward super-tile [kb0, kb0 + sw) (one workgroup per front and RZ rhs):
-// for the tiles from last to first, x_t = U^-1 y_t, then y_t' -= U[t'][t] x_t
-// for the earlier tiles t'; the super-tile's x goes to X.
+// Backward solve step of super-block [kb0, kb0 + sw).  Workgroups [0, 3):
+// x_block (64 rows each) = H y_block, written to X.  The others: 64 rows
+// i < kb0: y_i -= Uhat[i][block] y_block.  Both read only the block's y rows.
 template <typename R>
-__global__ __launch_bounds__(256) void bwd_super_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                        int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
-                                                        R* __restrict__ Xr, R* __restrict__ Xi,
-                                                        const R* __restrict__ Zr, const R* __restrict__ Zi) {
+__global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                     int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                     R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
+                                                     R* __restrict__ Zi) {
   typedef typename Mma<R>::v4 v4;
-  constexpr int RZ = SolveCfg<R>::RZ, LD = RZ + 1;
-  __shared__ R Sr[kSB * LD], Si[kSB * LD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = blockIdx.z * RZ;
-  const int nr = min(RZ, nrhs - r0);
-  const bool active = wave < RZ / 16;
-  for (int q = blockIdx.x; q < nlvl; q += gridDim.x) {
-    const FrontDev d = fr[lvl[q]];
-    if (kb0 >= d.np) continue;
-    const int sw = min(kSB, d.np - kb0);
-    const long nf = d.nf, np = d.np;
-    for (int o = tid; o < sw * RZ; o += blockDim.x) {
-      const int k = o / RZ, r = o % RZ;
-      R vr = R(0), vi = R(0);
-      if (r < nr) {
-        vr = Zr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
-        vi = Zi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r];
-      }
-      Sr[k * LD + r] = vr;
-      Si[k * LD + r] = vi;
-    }
-    __syncthreads();
-    for (int t0 = ((sw - 1) / kT) * kT; t0 >= 0; t0 -= kT) {
-      const int tw = min(kT, sw - t0);
-      const long kb = kb0 + t0;
-      if (active) {   // x_t = U^-1 y_t, in place
-        v4 yr[3], yi[3];
-        const R* T = fac + d.t + (kb / kT) * 4 * kTileElems + 2 * kTileElems;
-        mma48_gl<R>(T, T + kTileElems, kT, tw, tw, Sr, Si, LD, nullptr, t0, 16 * wave, lane, yr, yi);
-#pragma unroll
-        for (int rt = 0; rt < 3; ++rt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = 16 * rt + Mma<R>::row(lane, r);
-            if (i < tw) {
-              Sr[(t0 + i) * LD + 16 * wave + (lane & 15)] = yr[rt][r];
-              Si[(t0 + i) * LD + 16 * wave + (lane & 15)] = yi[rt][r];
-            }
-          }
-      }
-      __syncthreads();
-      if (active)     // earlier tiles: y_t' -= U[t'][t] x_t
-        for (int u0 = 0; u0 < t0; u0 += kT) {
-          v4 yr[3], yi[3];
-          const long a0 = (kb0 + u0) * nf + kb;
-          mma48_gl<R>(fac + d.p + a0, fac + d.p + np * nf + a0, nf, kT, tw, Sr, Si, LD, nullptr, t0, 16 * wave,
-                      lane, yr, yi);
-#pragma unroll
-          for (int rt = 0; rt < 3; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = 16 * rt + Mma<R>::row(lane, r);
-              Sr[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yr[rt][r];
-              Si[(u0 + i) * LD + 16 * wave + (lane & 15)] -= yi[rt][r];
-            }
-        }
-      __syncthreads();
-    }
-    for (int o = tid; o < sw * RZ; o += blockDim.x) {
-      const int k = o / RZ, r = o % RZ;
-      if (r < nr) {
-        Xr[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Sr[k * LD + r];
-        Xi[(d.e0 + kb0 + k) * (long)nrhs + r0 + r] = Si[k * LD + r];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Rows above the backward super-tile: z_i -= U[i][super-tile] x_super for 64
-// rows i < kb0 per workgroup, 64 rhs per workgroup.
-template <typename R>
-__global__ __launch_bounds__(256) void bwd_update_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                         int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
-                                                         const R* __restrict__ Xr, const R* __restrict__ Xi,
-                                                         R* __restrict__ Zr, R* __restrict__ Zi) {
-  typedef typename Mma<R>::v4 v4;
+  constexpr int NZB = kSB / kRB;
   __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
   __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int r0 = blockIdx.z * kSR;
   const int nr = min(kSR, nrhs - r0);
+  const bool xrole = (int)blockIdx.x < NZB;
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
     if (kb0 >= d.np) continue;
     const int sw = min(kSB, d.np - kb0);
     const long nf = d.nf, np = d.np;
-    const long i0 = (long)blockIdx.x * kRB;
-    if (i0 >= kb0) continue;
-    const int cnt = (int)min((long)kRB, kb0 - i0);
+    long i0;
+    int cnt;
+    if (xrole) {
+      i0 = (long)blockIdx.x * kRB;
+      if (i0 >= sw) continue;
+      cnt = (int)min((long)kRB, sw - i0);
+    } else {
+      i0 = (long)(blockIdx.x - NZB) * kRB;
+      if (i0 >= kb0) continue;
+      cnt = (int)min((long)kRB, kb0 - i0);
+    }
+    const R* Hr = fac + d.h + (long)(kb0 / kSB) * 2 * kSB * kSB;
+    const R* Hi = Hr + kSB * kSB;
     v4 cr[2][2], ci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -1036,8 +1085,13 @@ __global__ __launch_bounds__(256) void bwd_update_kernel(const FrontDev* __restr
         const int i = o / kT, k = o % kT;
         R vr = R(0), vi = R(0);
         if (i < cnt && k < kw) {
-          vr = fac[d.p + (i0 + i) * nf + kb0 + kc + k];
-          vi = fac[d.p + np * nf + (i0 + i) * nf + kb0 + kc + k];
+          if (xrole) {
+            vr = Hr[(i0 + i) * kSB + kc + k];
+            vi = Hi[(i0 + i) * kSB + kc + k];
+          } else {
+            vr = fac[d.p + (i0 + i) * nf + kb0 + kc + k];
+            vi = fac[d.p + np * nf + (i0 + i) * nf + kb0 + kc + k];
+          }
         }
         Ar_[i * kLL + k] = vr;
         Ai_[i * kLL + k] = vi;
@@ -1046,8 +1100,8 @@ __global__ __launch_bounds__(256) void bwd_update_kernel(const FrontDev* __restr
         const int k = o / kSR, r = o % kSR;
         R vr = R(0), vi = R(0);
         if (k < kw && r < nr) {
-          vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
-          vi = Xi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          vi = Zi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
         }
         Br_[k * kLX + r] = vr;
         Bi_[k * kLX + r] = vi;
@@ -1064,8 +1118,13 @@ __global__ __launch_bounds__(256) void bwd_update_kernel(const FrontDev* __restr
         for (int r = 0; r < 4; ++r) {
           const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
           if (row < cnt && col < nr) {
-            Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
-            Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+            if (xrole) {
+              Xr[(d.e0 + kb0 + i0 + row) * nrhs + r0 + col] = cr[a][b][r];
+              Xi[(d.e0 + kb0 + i0 + row) * nrhs + r0 + col] = ci[a][b][r];
+            } else {
+              Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
+              Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+            }
           }
         }
   }
@@ -1195,6 +1254,10 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
     fo += 2 * nb * np;
     f.t = fo;
     fo += 4L * kTileElems * ((np + kT - 1) / kT);
+    f.m = fo;
+    fo += 2L * kSB * kSB * ((np + kSB - 1) / kSB);
+    f.h = fo;
+    fo += 2L * kSB * kSB * ((np + kSB - 1) / kSB);
     f.u = uo;
     uo += nb;
     for (long kb = 0; kb < np; kb += kT) {
@@ -1294,6 +1357,17 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
     }
     hipLaunchKernelGGL(copyout_kernel<R>, dim3(grid_for(mnf * mnf, 256, 8192), std::min(gy, 64u)), dim3(256), 0, s,
                        fr, lvl, nl, (const R*)buf, fac);
+    // selective inversion of the super-blocks, then the folded L and U entries
+    const unsigned nsb = (unsigned)((mnp + kSB - 1) / kSB);
+    const unsigned ncc = (unsigned)(kSB / SolveCfg<R>::RZ);
+    hipLaunchKernelGGL((sb_inverse_kernel<R, true>), dim3(gy, nsb, ncc), dim3(256), 0, s, fr, lvl, nl,
+                       (const R*)buf, fac, (const int*)ib);
+    hipLaunchKernelGGL((sb_inverse_kernel<R, false>), dim3(gy, nsb, ncc), dim3(256), 0, s, fr, lvl, nl,
+                       (const R*)buf, fac, (const int*)ib);
+    const unsigned hy = std::min(65535u, nsb * (unsigned)(kSB / 64));
+    const unsigned hx = (unsigned)std::max(1L, (mnf + kRB - 1) / kRB);
+    hipLaunchKernelGGL((hat_kernel<R, 0>), dim3(hx, hy, gy), dim3(256), 0, s, fr, lvl, nl, (const R*)buf, fac);
+    hipLaunchKernelGGL((hat_kernel<R, 1>), dim3(hx, hy, gy), dim3(256), 0, s, fr, lvl, nl, (const R*)buf, fac);
     LS_HIP(hipGetLastError());
   }
   LS_HIP(hipStreamSynchronize(s));
@@ -1332,7 +1406,6 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
   const int* ib = g.ib.as<int>();
   const R* fac = g.fac.as<R>();
   const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
-  const unsigned gzz = (unsigned)((nrhs + SolveCfg<R>::RZ - 1) / SolveCfg<R>::RZ);
   hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
   hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
                      s, Ur, 2 * std::max(1L, g.u_rows) * nrhs);
@@ -1347,15 +1420,15 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
         for (int id : g.levels[dep])
           if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
         if (mcnb == 0) continue;
-        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3(grid_for(mcnb, 4, 1024), std::min(gy, 64u)), dim3(256), 0, s,
-                           fr, lvl, nl, slot, ib, nrhs, Xr, Xi, Ur, Ui);
+        // one front per workgroup row (a front loop would chain descriptor loads)
+        const long gxc = std::max(1L, std::min((mcnb + 3) / 4, std::max(1L, 65536L / nl)));
+        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3((unsigned)gxc, gy), dim3(256), 0, s, fr, lvl, nl, slot, ib,
+                           nrhs, Xr, Xi, Ur, Ui);
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kSB) {
-      hipLaunchKernelGGL(fwd_super_kernel<R>, dim3(gy, 1, gzz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, ib,
-                         nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi);
-      const unsigned gx = (unsigned)std::max(1L, (mnf - kb0 - 1 + kRB - 1) / kRB);
-      hipLaunchKernelGGL(fwd_update_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
-                         Xr, Xi, (const R*)Zr, (const R*)Zi, Ur, Ui);
+      const unsigned gx = (unsigned)(kSB / kRB + std::max(0L, (mnf - kb0 - 1 + kRB - 1) / kRB));
+      hipLaunchKernelGGL(fwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs, Xr,
+                         Xi, Zr, Zi, Ur, Ui);
     }
   }
   for (int dep = 0; dep < L; ++dep) {
@@ -1367,16 +1440,12 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
                        fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
     if (nks[dep] > 1)
-      hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp, 4, 4096), std::min(gy, 64u)), dim3(256), 0, s, fr,
-                         lvl, nl, nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
+      hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp, 4, 4096), gy), dim3(256), 0, s, fr, lvl, nl,
+                         nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
     for (long kb0 = ((mnp - 1) / kSB) * kSB; kb0 >= 0; kb0 -= kSB) {
-      hipLaunchKernelGGL(bwd_super_kernel<R>, dim3(gy, 1, gzz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
-                         Xr, Xi, (const R*)Zr, (const R*)Zi);
-      if (kb0 > 0) {
-        const unsigned gx = (unsigned)((kb0 + kRB - 1) / kRB);
-        hipLaunchKernelGGL(bwd_update_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
-                           nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi);
-      }
+      const unsigned gx = (unsigned)(kSB / kRB + (kb0 + kRB - 1) / kRB);
+      hipLaunchKernelGGL(bwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs, Xr,
+                         Xi, Zr, Zi);
     }
   }
   hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, (const R*)Xr,
