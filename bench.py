@@ -98,17 +98,17 @@ def cpu_baseline(n: int, seconds: float = 15.0):
 
 
 def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500,
-                  exact_iters: bool = True, host_factor_chosen: bool = True):
+                  exact_iters: bool = True, host_factor_chosen: bool = False, host_factor_plain: bool = False):
     """Per-rhs time to a 1e-8 relative residual: plain FP64 against the chosen form.
 
-    Plain: class stencils (the paper's 27 fits), complex128 host factor,
-    FP64 apply, one rhs at a time.  Chosen: learned per-point stencils
-    (network trained here on exact per-point fits of other seeded media,
-    exact fit where it is not accepted), complex64 factor in HBM with the
-    solves on the GPU, FP32 apply inside the FP64 outer FGMRES, ndirs
-    Fibonacci directions x 2 polarisations solved as one block with the
-    autotuned apply; optionally the same block with the complex64 host
-    factor.  Set-up (training, fits, factorisations) is timed apart.
+    Plain: class stencils (the paper's 27 fits), complex128 factor, FP64
+    apply, one rhs at a time.  Chosen: learned per-point stencils (network
+    trained here on exact per-point fits of other seeded media, exact fit
+    where it is not accepted), complex64 factor, FP32 apply inside the FP64
+    outer FGMRES, ndirs Fibonacci directions x 2 polarisations solved as one
+    block with the autotuned apply.  Both factor and solve S in HBM on the
+    GPU; optionally the plain path and the chosen block are also timed with
+    the host factor.  Set-up (training, fits, factorisations) is timed apart.
     """
     import numpy as np
     dev = torch.device("cuda:0")
@@ -147,10 +147,19 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
     def run(gg, prec):
         return timed(lambda: plan.solve(gg, tol=1e-8, prec=prec))
 
-    # --- plain FP64 path: class stencils, one rhs
+    # --- plain FP64 path: class stencils, complex128 factor, FP64 apply, one rhs
     t_fit_cls, _ = timed(lambda: plan.stencil_fit(0))
-    t_fac_cls, _ = timed(plan.factor)
-    _progress(f"complex128 factor: {t_fac_cls:.1f} s")
+    plain_host = None
+    if host_factor_plain:                                 # the factor on host cores
+        t_fac_h, _ = timed(plan.factor)
+        _progress(f"complex128 host factor: {t_fac_h:.1f} s")
+        run(g[:1], "c128")                               # warm-up (kernels, workspaces)
+        t_ph, (_, infph, stph) = run(g[:1], "c128")
+        _progress(f"plain FP64 solve, host factor: {t_ph:.3f} s")
+        plain_host = {"s_per_rhs": round(t_ph, 4), "iters": infph[0]["iters"], "status": stph,
+                      "factor_s": round(t_fac_h, 3)}
+    t_fac_cls, _ = timed(lambda: plan.factor_gpu("c128"))
+    _progress(f"complex128 GPU factor: {t_fac_cls:.2f} s")
     run(g[:1], "c128")                                   # warm-up (kernels, workspaces)
     t_plain, (x1, inf1, st1) = run(g[:1], "c128")
     _progress(f"plain FP64 solve: {t_plain:.3f} s")
@@ -162,7 +171,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
     t_fit_pt, _ = timed(lambda: plan.stencil_fit(1))
     exact = None
     if exact_iters:
-        plan.factor("c64")
+        plan.factor_gpu("c64")
         _, (_, infx, stx) = run(g[:1], "mixed")
         exact = {"iters": infx[0]["iters"], "status": stx}
         _progress(f"exact per-point stencils: {infx[0]['iters']} iterations")
@@ -197,6 +206,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
         "chosen_iters_max": max(i["iters"] for i in infb),
         "chosen_max_rel_resid_fp64": float(f"{rel:.3e}"),
         "status": [st1, st32, stb],
+        "plain_with_host_factor": plain_host,
         "speedup_per_rhs": round(t_plain / (t_mixed / nb), 2),
         "fp32_apply_single_rhs_s": round(t_f32one, 4), "fp32_apply_single_rhs_iters": inf32[0]["iters"],
         "exact_point_stencils_iters": exact["iters"] if exact else None,
@@ -206,7 +216,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
                     "train_loss_first_last": [round(float(loss[0]), 4), round(float(np.mean(loss[-20:])), 4)],
                     "class_fit": round(t_fit_cls, 3), "point_fit_exact": round(t_fit_pt, 3),
                     "learned_fit": round(t_fit_lrn, 3),
-                    "factor_class_c128_host": round(t_fac_cls, 3), "factor_learned_c64_gpu": round(t_fac_lrn, 3)},
+                    "factor_class_c128_gpu": round(t_fac_cls, 3), "factor_learned_c64_gpu": round(t_fac_lrn, 3)},
         "tuned_apply": {k2: tune[k2] for k2 in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
     }
 
@@ -296,12 +306,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
-    ap.add_argument("--solve-n", type=int, default=32, help="grid of the per-rhs solve section (0: skip)")
-    ap.add_argument("--solve-dirs", type=int, default=8, help="incident directions (2 polarisations each)")
+    ap.add_argument("--solve-n", type=int, default=64, help="grid of the per-rhs solve section (0: skip)")
+    ap.add_argument("--solve-dirs", type=int, default=32, help="incident directions (2 polarisations each)")
     ap.add_argument("--solve-exact", type=int, default=-1,
                     help="also solve with the exact per-point stencils (1/0; default: when n <= 48)")
     ap.add_argument("--solve-host-factor", type=int, default=-1,
-                    help="also solve the block with the host complex64 factor (1/0; default: when n <= 48)")
+                    help="also time the plain path and the chosen block with host factors (1/0; default: n <= 32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by "
@@ -391,9 +401,9 @@ def main():
     out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
     if args.solve_n:
         ex = (args.solve_n <= 48) if args.solve_exact < 0 else bool(args.solve_exact)
-        hf = (args.solve_n <= 48) if args.solve_host_factor < 0 else bool(args.solve_host_factor)
+        hf = (args.solve_n <= 32) if args.solve_host_factor < 0 else bool(args.solve_host_factor)
         out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch, exact_iters=ex,
-                                     host_factor_chosen=hf)
+                                     host_factor_chosen=hf, host_factor_plain=hf)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)
