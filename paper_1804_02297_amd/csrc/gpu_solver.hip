@@ -783,18 +783,44 @@ __global__ __launch_bounds__(256) void hat_kernel(const FrontDev* __restrict__ f
         }
       for (int kc = 0; kc < sw; kc += kT) {
         const int kw = min(kT, sw - kc);
-        for (int o = tid; o < kRB * kT; o += blockDim.x) {
-          const int i = o / kT, k = o % kT;
-          const bool ok = i < cnt && k < kw;
-          const long src = (i0 + i) * nf + kb0 + kc + k;
-          Ar_[i * kLL + k] = ok ? Fr[src] : R(0);
-          Ai_[i * kLL + k] = ok ? Fi[src] : R(0);
+        {  // all loads issued before the LDS stores
+          constexpr int NU = (kRB * kT) / 256;
+          R ld0_[NU], ld1_[NU];
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int o = tid + 256 * u;
+            const int i = o / kT, k = o % kT;
+            const bool ok = i < cnt && k < kw;
+            const long src = (i0 + i) * nf + kb0 + kc + k;
+            ld0_[u] = ok ? Fr[src] : R(0);
+            ld1_[u] = ok ? Fi[src] : R(0);
+          }
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int o = tid + 256 * u;
+            const int i = o / kT, k = o % kT;
+            Ar_[i * kLL + k] = ld0_[u];
+            Ai_[i * kLL + k] = ld1_[u];
+          }
         }
-        for (int o = tid; o < kT * 64; o += blockDim.x) {
-          const int k = o / 64, c = o % 64;
-          const bool ok = k < kw && j0 + c < sw;
-          Br_[k * kLX + c] = ok ? Br[(kc + k) * kSB + j0 + c] : R(0);
-          Bi_[k * kLX + c] = ok ? Bi[(kc + k) * kSB + j0 + c] : R(0);
+        {  // all loads issued before the LDS stores
+          constexpr int NU = (kT * 64) / 256;
+          R ld0_[NU], ld1_[NU];
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int o = tid + 256 * u;
+            const int k = o / 64, c = o % 64;
+            const bool ok = k < kw && j0 + c < sw;
+            ld0_[u] = ok ? Br[(kc + k) * kSB + j0 + c] : R(0);
+            ld1_[u] = ok ? Bi[(kc + k) * kSB + j0 + c] : R(0);
+          }
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int o = tid + 256 * u;
+            const int k = o / 64, c = o % 64;
+            Br_[k * kLX + c] = ld0_[u];
+            Bi_[k * kLX + c] = ld1_[u];
+          }
         }
         __syncthreads();
         cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
@@ -869,36 +895,62 @@ __global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict_
       }
     for (int kc = 0; kc < sw; kc += kT) {
       const int kw = min(kT, sw - kc);
-      for (int o = tid; o < kRB * kT; o += blockDim.x) {
-        const int i = o / kT, k = o % kT;
-        R vr = R(0), vi = R(0);
-        if (i < cnt && k < kw) {
-          if (zrole) {
-            vr = Mr[(i0 + i) * kSB + kc + k];
-            vi = Mi[(i0 + i) * kSB + kc + k];
-          } else {
-            const long gi = i0 + i, col = kb0 + kc + k;
-            if (gi < np) {
-              vr = fac[d.p + gi * nf + col];
-              vi = fac[d.p + np * nf + gi * nf + col];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kRB * kT) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kT, k = o % kT;
+          R vr = R(0), vi = R(0);
+          if (i < cnt && k < kw) {
+            if (zrole) {
+              vr = Mr[(i0 + i) * kSB + kc + k];
+              vi = Mi[(i0 + i) * kSB + kc + k];
             } else {
-              vr = fac[d.l + (gi - np) * np + col];
-              vi = fac[d.l + (long)d.nb * np + (gi - np) * np + col];
+              const long gi = i0 + i, col = kb0 + kc + k;
+              if (gi < np) {
+                vr = fac[d.p + gi * nf + col];
+                vi = fac[d.p + np * nf + gi * nf + col];
+              } else {
+                vr = fac[d.l + (gi - np) * np + col];
+                vi = fac[d.l + (long)d.nb * np + (gi - np) * np + col];
+              }
             }
           }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Ar_[i * kLL + k] = vr;
-        Ai_[i * kLL + k] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kT, k = o % kT;
+          Ar_[i * kLL + k] = ld0_[u];
+          Ai_[i * kLL + k] = ld1_[u];
+        }
       }
-      for (int o = tid; o < kT * kSR; o += blockDim.x) {
-        const int k = o / kSR, r = o % kSR;
-        R vr = R(0), vi = R(0);
-        if (k < kw && r < nr) {
-          vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
-          vi = Xi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kT * kSR) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int k = o / kSR, r = o % kSR;
+          R vr = R(0), vi = R(0);
+          if (k < kw && r < nr) {
+            vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+            vi = Xi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Br_[k * kLX + r] = vr;
-        Bi_[k * kLX + r] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int k = o / kSR, r = o % kSR;
+          Br_[k * kLX + r] = ld0_[u];
+          Bi_[k * kLX + r] = ld1_[u];
+        }
       }
       __syncthreads();
       cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
@@ -967,26 +1019,52 @@ __global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict
       }
     for (long jc = j0; jc < j1; jc += kKC) {
       const int nj = (int)min((long)kKC, j1 - jc);
-      for (int o = tid; o < kRB * kKC; o += blockDim.x) {
-        const int i = o / kKC, j = o % kKC;
-        R vr = R(0), vi = R(0);
-        if (i < cnt && j < nj) {
-          vr = fac[d.p + (i0 + i) * nf + np + jc + j];
-          vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kRB * kKC) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kKC, j = o % kKC;
+          R vr = R(0), vi = R(0);
+          if (i < cnt && j < nj) {
+            vr = fac[d.p + (i0 + i) * nf + np + jc + j];
+            vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Ar_[i * LA + j] = vr;
-        Ai_[i * LA + j] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kKC, j = o % kKC;
+          Ar_[i * LA + j] = ld0_[u];
+          Ai_[i * LA + j] = ld1_[u];
+        }
       }
-      for (int o = tid; o < kKC * kSR; o += blockDim.x) {
-        const int j = o / kSR, r = o % kSR;
-        R vr = R(0), vi = R(0);
-        if (j < nj && r < nr) {
-          const long e = ib[d.bm + jc + j];
-          vr = Xr[e * nrhs + r0 + r];
-          vi = Xi[e * nrhs + r0 + r];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kKC * kSR) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int j = o / kSR, r = o % kSR;
+          R vr = R(0), vi = R(0);
+          if (j < nj && r < nr) {
+            const long e = ib[d.bm + jc + j];
+            vr = Xr[e * nrhs + r0 + r];
+            vi = Xi[e * nrhs + r0 + r];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Br_[j * kLX + r] = vr;
-        Bi_[j * kLX + r] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int j = o / kSR, r = o % kSR;
+          Br_[j * kLX + r] = ld0_[u];
+          Bi_[j * kLX + r] = ld1_[u];
+        }
       }
       __syncthreads();
       cmma64<R>(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane, cr, ci);
@@ -1081,30 +1159,56 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
       }
     for (int kc = 0; kc < sw; kc += kT) {
       const int kw = min(kT, sw - kc);
-      for (int o = tid; o < kRB * kT; o += blockDim.x) {
-        const int i = o / kT, k = o % kT;
-        R vr = R(0), vi = R(0);
-        if (i < cnt && k < kw) {
-          if (xrole) {
-            vr = Hr[(i0 + i) * kSB + kc + k];
-            vi = Hi[(i0 + i) * kSB + kc + k];
-          } else {
-            vr = fac[d.p + (i0 + i) * nf + kb0 + kc + k];
-            vi = fac[d.p + np * nf + (i0 + i) * nf + kb0 + kc + k];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kRB * kT) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kT, k = o % kT;
+          R vr = R(0), vi = R(0);
+          if (i < cnt && k < kw) {
+            if (xrole) {
+              vr = Hr[(i0 + i) * kSB + kc + k];
+              vi = Hi[(i0 + i) * kSB + kc + k];
+            } else {
+              vr = fac[d.p + (i0 + i) * nf + kb0 + kc + k];
+              vi = fac[d.p + np * nf + (i0 + i) * nf + kb0 + kc + k];
+            }
           }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Ar_[i * kLL + k] = vr;
-        Ai_[i * kLL + k] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kT, k = o % kT;
+          Ar_[i * kLL + k] = ld0_[u];
+          Ai_[i * kLL + k] = ld1_[u];
+        }
       }
-      for (int o = tid; o < kT * kSR; o += blockDim.x) {
-        const int k = o / kSR, r = o % kSR;
-        R vr = R(0), vi = R(0);
-        if (k < kw && r < nr) {
-          vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
-          vi = Zi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kT * kSR) / 256;
+        R ld0_[NU], ld1_[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int k = o / kSR, r = o % kSR;
+          R vr = R(0), vi = R(0);
+          if (k < kw && r < nr) {
+            vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+            vi = Zi[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        Br_[k * kLX + r] = vr;
-        Bi_[k * kLX + r] = vi;
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int k = o / kSR, r = o % kSR;
+          Br_[k * kLX + r] = ld0_[u];
+          Bi_[k * kLX + r] = ld1_[u];
+        }
       }
       __syncthreads();
       cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
