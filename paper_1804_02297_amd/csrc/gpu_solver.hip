@@ -12,7 +12,8 @@
 //   48-column step kb of the pivot block:
 //     diag_kernel   LU of the 48 x 48 diagonal tile in LDS, pivots searched
 //                   among the tile's rows; the tile's L^-1 and U^-1
-//     panel_kernel  L = F U^-1 below the tile, U = L^-1 P F right of it
+//     panel_kernel  L below the tile (l U = f) and U right of it (L u = P f),
+//                   by substitution
 //     schur_kernel  F -= L U on the trailing block, complex product on
 //                   MFMA (v_mfma_*_16x16x4, FP32 or FP64)
 //   and copy the pivot rows and the boundary rows' pivot columns out.
@@ -323,14 +324,25 @@ __global__ __launch_bounds__(256) void diag_kernel(const FrontDev* __restrict__ 
   }
 }
 
-// Workgroups [0, half): L = F U^-1 for 64 rows below the tile.
-// Workgroups [half, 2 half): U = L^-1 P F for 64 columns right of the tile.
+// Rows (columns) per workgroup of the panel kernel: one per thread, each held
+// in a row of LDS.
+template <typename R>
+struct PanelCfg {
+  static constexpr int PR = sizeof(R) == 4 ? 256 : 128;
+};
+
+// Workgroups [0, half): the L part below the tile by substitution, l U = f
+// for PR rows (U the tile's upper factor).  Workgroups [half, 2 half): the U
+// part right of it, L u = P f for PR columns (L the tile's unit lower factor,
+// P its row permutation).  Substitution rather than the tile's explicit
+// inverse keeps the panel backward stable.
 template <typename R>
 __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                     int nlvl, int kb, int half, R* __restrict__ buf,
-                                                    const R* __restrict__ fac, const int* __restrict__ ib) {
-  __shared__ R Wr[kT][kT + 1], Wi[kT][kT + 1];
-  __shared__ R Br[kRB][kT + 1], Bi[kRB][kT + 1];
+                                                    const int* __restrict__ ib) {
+  constexpr int PR = PanelCfg<R>::PR;
+  __shared__ R Tr[kT][kT + 1], Ti[kT][kT + 1];   // the factored diagonal tile
+  __shared__ R Br[PR][kT + 1], Bi[PR][kT + 1];   // one row (or column) per thread
   const int tid = threadIdx.x;
   const bool lrole = (int)blockIdx.x < half;
   const long blk = lrole ? blockIdx.x : blockIdx.x - half;
@@ -339,33 +351,21 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__
     if (kb >= d.np) continue;
     const int tw = min(kT, d.np - kb);
     const long ke = kb + tw, nf = d.nf;
-    const long x0 = ke + blk * kRB;
+    const long x0 = ke + blk * PR;
     if (x0 >= nf) continue;
-    const int cnt = (int)min((long)kRB, nf - x0);
+    const int cnt = (int)min((long)PR, nf - x0);
     R* Fr = buf + d.f;
     R* Fi = Fr + nf * nf;
-    const R* T = fac + d.t + (long)(kb / kT) * 4 * kTileElems + (lrole ? 2 * kTileElems : 0);
     for (int o = tid; o < tw * tw; o += blockDim.x) {
       const int i = o / tw, c = o % tw;
-      Wr[i][c] = T[i * kT + c];
-      Wi[i][c] = T[kTileElems + i * kT + c];
+      Tr[i][c] = Fr[(kb + i) * nf + kb + c];
+      Ti[i][c] = Fi[(kb + i) * nf + kb + c];
     }
     if (lrole) {
       for (int o = tid; o < cnt * tw; o += blockDim.x) {
         const int i = o / tw, k = o % tw;
         Br[i][k] = Fr[(x0 + i) * nf + kb + k];
         Bi[i][k] = Fi[(x0 + i) * nf + kb + k];
-      }
-      __syncthreads();
-      for (int o = tid; o < cnt * tw; o += blockDim.x) {
-        const int i = o / tw, c = o % tw;
-        R sr = R(0), si = R(0);
-        for (int k = 0; k <= c; ++k) {
-          sr += Br[i][k] * Wr[k][c] - Bi[i][k] * Wi[k][c];
-          si += Br[i][k] * Wi[k][c] + Bi[i][k] * Wr[k][c];
-        }
-        Fr[(x0 + i) * nf + kb + c] = sr;
-        Fi[(x0 + i) * nf + kb + c] = si;
       }
     } else {
       for (int o = tid; o < cnt * tw; o += blockDim.x) {
@@ -374,16 +374,40 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__
         Br[j][k] = Fr[src];
         Bi[j][k] = Fi[src];
       }
-      __syncthreads();
-      for (int o = tid; o < cnt * tw; o += blockDim.x) {
-        const int r = o / cnt, j = o % cnt;
-        R sr = R(0), si = R(0);
-        for (int k = 0; k <= r; ++k) {
-          sr += Wr[r][k] * Br[j][k] - Wi[r][k] * Bi[j][k];
-          si += Wr[r][k] * Bi[j][k] + Wi[r][k] * Br[j][k];
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      R* br = Br[tid];
+      R* bi = Bi[tid];
+      if (lrole) {
+        for (int j = 0; j < tw; ++j) {   // l_j = f_j / U_jj; f_c -= l_j U_jc for c > j
+          const R ur = Tr[j][j], ui = Ti[j][j];
+          const R den = ur * ur + ui * ui;
+          const R xr = br[j], xi = bi[j];
+          const R lr = (xr * ur + xi * ui) / den, li = (xi * ur - xr * ui) / den;
+          br[j] = lr;
+          bi[j] = li;
+          for (int c = j + 1; c < tw; ++c) {
+            br[c] -= lr * Tr[j][c] - li * Ti[j][c];
+            bi[c] -= lr * Ti[j][c] + li * Tr[j][c];
+          }
         }
-        Fr[(kb + r) * nf + x0 + j] = sr;
-        Fi[(kb + r) * nf + x0 + j] = si;
+        for (int c = 0; c < tw; ++c) {
+          Fr[(x0 + tid) * nf + kb + c] = br[c];
+          Fi[(x0 + tid) * nf + kb + c] = bi[c];
+        }
+      } else {
+        for (int k = 0; k < tw; ++k) {   // u_r -= L_rk u_k for r > k (unit diagonal)
+          const R ukr = br[k], uki = bi[k];
+          for (int r = k + 1; r < tw; ++r) {
+            br[r] -= Tr[r][k] * ukr - Ti[r][k] * uki;
+            bi[r] -= Tr[r][k] * uki + Ti[r][k] * ukr;
+          }
+        }
+        for (int r = 0; r < tw; ++r) {
+          Fr[(kb + r) * nf + x0 + tid] = br[r];
+          Fi[(kb + r) * nf + x0 + tid] = bi[r];
+        }
       }
     }
     __syncthreads();
@@ -1443,9 +1467,9 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
       for (long kb = kb0; kb < kbe; kb += kT) {
         hipLaunchKernelGGL(diag_kernel<R>, dim3(gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, buf, fac, ib);
         const long rest = mnf - kb - 1;           // rows right of / below the tile, at most
-        const int half = (int)std::max(1L, (rest + kRB - 1) / kRB);
+        const int half = (int)std::max(1L, (rest + PanelCfg<R>::PR - 1) / PanelCfg<R>::PR);
         hipLaunchKernelGGL(panel_kernel<R>, dim3(2 * half, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb, half, buf,
-                           (const R*)fac, (const int*)ib);
+                           (const int*)ib);
         const unsigned tall = (unsigned)std::max(1L, (rest + 63) / 64);
         const unsigned blk = (unsigned)std::max(1L, (kbe - kb - 1 + 63) / 64);   // block columns left
         if (kb + kT < kbe) {
