@@ -465,22 +465,37 @@ __global__ __launch_bounds__(256) void schur_kernel(const FrontDev* __restrict__
         cr[a][b] = v4{R(0), R(0), R(0), R(0)};
         ci[a][b] = v4{R(0), R(0), R(0), R(0)};
       }
-    for (int kc = 0; kc < tw; kc += 16) {
+    // the next 16-deep K chunk is loaded into registers while the MFMAs
+    // consume the current one from LDS
+    R par[4], pai[4], pbr[4], pbi[4];
+    auto fetch = [&](int kc) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int o = tid + 256 * u;
         const int ii = o >> 4, kk = o & 15;
         const bool ok = i0 + ii < r1 && kc + kk < tw;
         const long src = (i0 + ii) * nf + kb_ + kc + kk;
-        Ar[ii][kk] = ok ? Fr[src] : R(0);
-        Ai[ii][kk] = ok ? Fi[src] : R(0);
+        par[u] = ok ? Fr[src] : R(0);
+        pai[u] = ok ? Fi[src] : R(0);
         const int kr = o >> 6, jj = o & 63;
         const bool okb = kc + kr < tw && j0 + jj < c1;
         const long srcb = (kb_ + kc + kr) * nf + j0 + jj;
-        Br[kr][jj] = okb ? Fr[srcb] : R(0);
-        Bi[kr][jj] = okb ? Fi[srcb] : R(0);
+        pbr[u] = okb ? Fr[srcb] : R(0);
+        pbi[u] = okb ? Fi[srcb] : R(0);
+      }
+    };
+    fetch(0);
+    for (int kc = 0; kc < tw; kc += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = tid + 256 * u;
+        Ar[o >> 4][o & 15] = par[u];
+        Ai[o >> 4][o & 15] = pai[u];
+        Br[o >> 6][o & 63] = pbr[u];
+        Bi[o >> 6][o & 63] = pbi[u];
       }
       __syncthreads();
+      if (kc + 16 < tw) fetch(kc + 16);
 #pragma unroll
       for (int k4 = 0; k4 < 16; k4 += 4) {
         const int kr = k4 + (lane >> 4);

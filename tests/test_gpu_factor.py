@@ -107,14 +107,15 @@ def test_gpu_factor_equals_host_factor(lib):
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_block_solve_equals_single_solves(lib, prec):
-    """nrhs across the 16-rhs workgroup chunks, ragged last chunk: bitwise."""
+    """nrhs across the 64-rhs workgroup chunks of the solve kernels, ragged
+    last chunk: bitwise."""
     from paper_1804_02297_amd.binding import SparseGpu
     n = 9
     _, rows = _oracle_system(n, 6)
     sp = SparseGpu(n, rows, prec=prec)
-    b = I.random_field(33, n, 80)
+    b = I.random_field(70, n, 80)
     single = np.stack([sp.solve(_dev(b[i:i + 1])).cpu().numpy()[0] for i in range(len(b))])
-    for nr in (2, 16, 17, 33):
+    for nr in (2, 17, 33, 64, 65, 70):
         xb = sp.solve(_dev(b[:nr])).cpu().numpy()
         assert np.array_equal(xb, single[:nr]), nr
 
