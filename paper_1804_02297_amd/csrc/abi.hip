@@ -29,14 +29,21 @@ static ls_status precond_list(ls_plan* plan, const std::vector<int>& lb,
   const long len = 3L * plan->ap.n * plan->ap.n * plan->ap.n;
   const size_t vb = (size_t)len * sizeof(C<double>);
   const int nb = (int)lb.size();
-  if (plan->gs) {   // GPU factor: Q v into a contiguous block, solve it in HBM, copy back
+  if (plan->gs) {   // GPU factor: Q v into a contiguous block, solve it in HBM
     if (plan->qtmp.bytes < (size_t)nb * vb) LS_TRY(plan->qtmp.alloc((size_t)nb * vb));
     C<double>* blk = plan->qtmp.as<C<double>>();
+    C<double>* v0 = ptr(lb[0]);
+    bool contiguous = true;   // the vectors one after another (every rhs of a lockstep block)
+    for (int q = 1; q < nb && contiguous; ++q) contiguous = ptr(lb[q]) == v0 + (size_t)q * len;
+    if (t_host) *t_host = 0.0;
+    if (contiguous) {
+      LS_TRY(q_apply(plan->sd, plan->ap.n, v0, blk, nb, s));
+      return gpu_solve(plan->gs, blk, v0, nb, s);
+    }
     for (int q = 0; q < nb; ++q) LS_TRY(q_apply(plan->sd, plan->ap.n, ptr(lb[q]), blk + (size_t)q * len, 1, s));
-    LS_TRY(gpu_solve(plan->gs, blk, nb, s));
+    LS_TRY(gpu_solve(plan->gs, blk, blk, nb, s));
     for (int q = 0; q < nb; ++q)
       LS_HIP(hipMemcpyAsync(ptr(lb[q]), blk + (size_t)q * len, vb, hipMemcpyDeviceToDevice, s));
-    if (t_host) *t_host = 0.0;
     return LS_OK;
   }
   if (plan->qtmp.bytes < vb) LS_TRY(plan->qtmp.alloc(vb));
@@ -494,7 +501,8 @@ ls_status ls_sparse_factor_gpu(int n, const void* rows_host, ls_prec factor_prec
 ls_status ls_sparse_solve_gpu(ls_sparse* sp, void* b_dev, int nrhs, void* hip_stream) {
   if (!sp || !b_dev || nrhs < 1) return LS_EINVAL;
   if (!sp->gs) return LS_ESTATE;
-  return gpu_solve(sp->gs, static_cast<C<double>*>(b_dev), nrhs, as_stream(hip_stream));
+  return gpu_solve(sp->gs, static_cast<C<double>*>(b_dev), static_cast<C<double>*>(b_dev), nrhs,
+                   as_stream(hip_stream));
 }
 
 ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops) {

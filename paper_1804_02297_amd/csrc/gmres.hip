@@ -125,7 +125,10 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
   LS_TRY(ctx.Z.alloc(vbytes * (size_t)m * nrhs));
   LS_TRY(ctx.W.alloc(vbytes * (size_t)nrhs));
   LS_TRY(ctx.partial.alloc(sizeof(C<double>) * 64 * (m + 1)));
-  LS_TRY(ctx.hdev.alloc(sizeof(C<double>) * (m + 1)));
+  // per rhs: h1, h2 (the two Gram-Schmidt passes) and the norm, m + 1 each
+  const size_t hslot = (size_t)3 * (m + 1);
+  if (ctx.hdev.bytes < sizeof(C<double>) * hslot * nrhs) LS_TRY(ctx.hdev.alloc(sizeof(C<double>) * hslot * nrhs));
+  std::vector<C<double>> hhost(hslot * nrhs);
   C<double>* V = ctx.V.as<C<double>>();
   C<double>* Z = ctx.Z.as<C<double>>();
   C<double>* W = ctx.W.as<C<double>>();
@@ -136,29 +139,21 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
   auto Zp = [&](int b, int q) { return Z + q * qstride + (long)b * len; };
   auto Wp = [&](int b) { return W + (long)b * len; };
 
-  auto dots = [&](int b, int nv, const C<double>* w, std::vector<C<double>>& h) -> ls_status {
-    LS_TRY(multidot(Vp(b, 0), qstride, nv, w, len, ctx.partial.as<C<double>>(), ctx.hdev.as<C<double>>(), s));
-    h.resize(nv);
-    LS_HIP(hipMemcpyAsync(h.data(), ctx.hdev.p, nv * sizeof(C<double>), hipMemcpyDeviceToHost, s));
+  // squared norms of nrhs vectors (w(b)) into hslot b, one copy and one wait
+  C<double>* hd = ctx.hdev.as<C<double>>();
+  auto norms = [&](const std::function<const C<double>*(int)>& w, std::vector<double>& out) -> ls_status {
+    for (int b = 0; b < nrhs; ++b)
+      LS_TRY(multidot(w(b), len, 1, w(b), len, ctx.partial.as<C<double>>(), hd + (size_t)b * hslot, s));
+    LS_HIP(hipMemcpyAsync(hhost.data(), hd, sizeof(C<double>) * hslot * nrhs, hipMemcpyDeviceToHost, s));
     LS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nrhs; ++b) out[b] = sqrt(fmax(hhost[(size_t)b * hslot].re, 0.0));
     return LS_OK;
   };
-  auto norm = [&](const C<double>* w, double* out) -> ls_status {
-    LS_TRY(multidot(w, len, 1, w, len, ctx.partial.as<C<double>>(), ctx.hdev.as<C<double>>(), s));
-    C<double> h;
-    LS_HIP(hipMemcpyAsync(&h, ctx.hdev.p, sizeof(C<double>), hipMemcpyDeviceToHost, s));
-    LS_HIP(hipStreamSynchronize(s));
-    *out = sqrt(fmax(h.re, 0.0));
-    return LS_OK;
-  };
-
   std::vector<double> gnorm(nrhs), rel(nrhs);
   std::vector<int> iters(nrhs, 0), restarts(nrhs, 0);
   std::vector<char> done(nrhs, 0);
-  for (int b = 0; b < nrhs; ++b) {
-    LS_TRY(norm(g + (long)b * len, &gnorm[b]));
-    info[b] = ls_solve_info{0, 0, 0.0, 0.0, 0.0};
-  }
+  LS_TRY(norms([&](int b) { return g + (long)b * len; }, gnorm));
+  for (int b = 0; b < nrhs; ++b) info[b] = ls_solve_info{0, 0, 0.0, 0.0, 0.0};
   LS_HIP(hipMemsetAsync(x, 0, (size_t)nrhs * vbytes, s));
   double t_host = 0.0;
   const double mixed_drop = 1e-4;
@@ -171,7 +166,9 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
     for (int b = 0; b < nrhs; ++b) {
       hipLaunchKernelGGL(residual_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, g + (long)b * len, Wp(b), len);
       LS_HIP(hipGetLastError());
-      LS_TRY(norm(Wp(b), &beta[b]));
+    }
+    LS_TRY(norms([&](int b) { return (const C<double>*)Wp(b); }, beta));
+    for (int b = 0; b < nrhs; ++b) {
       rel[b] = gnorm[b] > 0 ? beta[b] / gnorm[b] : 0.0;
       if (rel[b] <= tol || gnorm[b] == 0.0) done[b] = 1;
       if (!done[b]) ++active;
@@ -198,7 +195,11 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
       for (int b = 0; b < nrhs; ++b)
         if (live[b]) lb.push_back(b);
       if (lb.empty()) break;
-      for (int b : lb) LS_HIP(hipMemcpyAsync(Zp(b, j), Vp(b, j), vbytes, hipMemcpyDeviceToDevice, s));
+      const bool run = lb.back() - lb.front() + 1 == (int)lb.size();   // consecutive rhs: one copy
+      if (run)
+        LS_HIP(hipMemcpyAsync(Zp(lb.front(), j), Vp(lb.front(), j), vbytes * lb.size(), hipMemcpyDeviceToDevice, s));
+      else
+        for (int b : lb) LS_HIP(hipMemcpyAsync(Zp(b, j), Vp(b, j), vbytes, hipMemcpyDeviceToDevice, s));
       // preconditioner, in place on Z_j of every live rhs
       {
         double th = 0.0;
@@ -207,21 +208,29 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
       }
       LS_TRY(ops.apply(Zp(0, j), W, nrhs, mixed ? LS_MIXED : LS_C128, s));
       ++total;
+      // classical Gram-Schmidt, two passes, for every live rhs: the
+      // coefficients stay on the device for the subtractions; one copy and
+      // one wait bring all of them (and the norms) to the host
       for (int b : lb) {
-        // classical Gram-Schmidt, two passes
-        std::vector<C<double>> h1, h2;
-        LS_TRY(dots(b, j + 1, Wp(b), h1));
-        LS_HIP(hipMemcpyAsync(ctx.hdev.p, h1.data(), (j + 1) * sizeof(C<double>), hipMemcpyHostToDevice, s));
+        C<double>* h1d = hd + (size_t)b * hslot;
+        C<double>* h2d = h1d + (m + 1);
+        C<double>* hnd = h2d + (m + 1);
+        LS_TRY(multidot(Vp(b, 0), qstride, j + 1, Wp(b), len, ctx.partial.as<C<double>>(), h1d, s));
         hipLaunchKernelGGL(subtract_combo_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, Vp(b, 0), qstride,
-                           j + 1, ctx.hdev.as<C<double>>(), Wp(b), len);
+                           j + 1, (const C<double>*)h1d, Wp(b), len);
         LS_HIP(hipGetLastError());
-        LS_TRY(dots(b, j + 1, Wp(b), h2));
-        LS_HIP(hipMemcpyAsync(ctx.hdev.p, h2.data(), (j + 1) * sizeof(C<double>), hipMemcpyHostToDevice, s));
+        LS_TRY(multidot(Vp(b, 0), qstride, j + 1, Wp(b), len, ctx.partial.as<C<double>>(), h2d, s));
         hipLaunchKernelGGL(subtract_combo_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, Vp(b, 0), qstride,
-                           j + 1, ctx.hdev.as<C<double>>(), Wp(b), len);
+                           j + 1, (const C<double>*)h2d, Wp(b), len);
         LS_HIP(hipGetLastError());
-        double hn;
-        LS_TRY(norm(Wp(b), &hn));
+        LS_TRY(multidot(Wp(b), len, 1, Wp(b), len, ctx.partial.as<C<double>>(), hnd, s));
+      }
+      LS_HIP(hipMemcpyAsync(hhost.data(), hd, sizeof(C<double>) * hslot * nrhs, hipMemcpyDeviceToHost, s));
+      LS_HIP(hipStreamSynchronize(s));
+      for (int b : lb) {
+        const C<double>* h1 = hhost.data() + (size_t)b * hslot;
+        const C<double>* h2 = h1 + (m + 1);
+        const double hn = sqrt(fmax(h2[m + 1].re, 0.0));
         auto& Hb = H[b];
         for (int i = 0; i <= j; ++i) Hb[(size_t)i * m + j] = h1[i] + h2[i];
         Hb[(size_t)(j + 1) * m + j] = cmk(hn, 0.0);
@@ -274,9 +283,10 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
         const double dd = d.re * d.re + d.im * d.im;
         y[i] = dd > 0 ? cscale(acc * cconj(d), 1.0 / dd) : cmk(0.0, 0.0);
       }
-      LS_HIP(hipMemcpyAsync(ctx.hdev.p, y.data(), ju * sizeof(C<double>), hipMemcpyHostToDevice, s));
+      C<double>* yd = hd + (size_t)b * hslot;   // this rhs's own slot: no reuse before the copy lands
+      LS_HIP(hipMemcpyAsync(yd, y.data(), ju * sizeof(C<double>), hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(add_combo_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, Zp(b, 0), qstride, ju,
-                         ctx.hdev.as<C<double>>(), x + (long)b * len, len);
+                         (const C<double>*)yd, x + (long)b * len, len);
       LS_HIP(hipGetLastError());
       restarts[b] += 1;
     }

@@ -11,8 +11,9 @@ struct GpuSolver;
 // layout of the plan's assembled rows).  fp32: keep the factor in complex64.
 // Synchronises the stream before returning.
 ls_status gpu_factor(int n, const C<double>* rows_dev, bool fp32, hipStream_t s, GpuSolver** out);
-// Solve S x = b in place on the device; b is [nrhs][3][n^3] complex128.
-ls_status gpu_solve(GpuSolver* gs, C<double>* b_dev, int nrhs, hipStream_t s);
+// Solve S x = b on the device; b, x are [nrhs][3][n^3] complex128 and may be
+// the same array (stream-ordered: b is read completely before x is written).
+ls_status gpu_solve(GpuSolver* gs, const C<double>* b_dev, C<double>* x_dev, int nrhs, hipStream_t s);
 size_t gpu_factor_bytes(const GpuSolver* gs);
 double gpu_factor_flops(const GpuSolver* gs);
 bool gpu_factor_is_fp32(const GpuSolver* gs);

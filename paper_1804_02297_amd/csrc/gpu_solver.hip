@@ -1518,7 +1518,7 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
 }
 
 template <typename R>
-ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
+ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrhs, hipStream_t s) {
   const int L = (int)g.levels.size();
   // split-K partial sums of the U12 products: levels whose widest boundary
   // needs more than one split
@@ -1591,7 +1591,7 @@ ls_status solve_numeric(GpuSolver& g, C<double>* b, int nrhs, hipStream_t s) {
                          Xi, Zr, Zi);
     }
   }
-  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, (const R*)Xr,
+  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, xo, N, nrhs, ib, (const R*)Xr,
                      (const R*)Xi);
   LS_HIP(hipGetLastError());
   return LS_OK;
@@ -1627,9 +1627,10 @@ ls_status gpu_factor(int n, const C<double>* rows_dev, bool fp32, hipStream_t s,
   return LS_OK;
 }
 
-ls_status gpu_solve(GpuSolver* gs, C<double>* b_dev, int nrhs, hipStream_t s) {
-  if (!gs || !b_dev || nrhs < 1) return LS_EINVAL;
-  return gs->fp32 ? solve_numeric<float>(*gs, b_dev, nrhs, s) : solve_numeric<double>(*gs, b_dev, nrhs, s);
+ls_status gpu_solve(GpuSolver* gs, const C<double>* b_dev, C<double>* x_dev, int nrhs, hipStream_t s) {
+  if (!gs || !b_dev || !x_dev || nrhs < 1) return LS_EINVAL;
+  return gs->fp32 ? solve_numeric<float>(*gs, b_dev, x_dev, nrhs, s)
+                  : solve_numeric<double>(*gs, b_dev, x_dev, nrhs, s);
 }
 
 size_t gpu_factor_bytes(const GpuSolver* gs) { return gs ? gs->bytes : 0; }
