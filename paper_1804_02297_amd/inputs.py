@@ -10,9 +10,12 @@ dimension on the unit cube, spacing h = 1/(n+1), node i at x = h*i with
 i in {1..n}^3.  Arrays are C-ordered ``[i1, i2, i3]`` (i3 fastest); fields
 are ``[rhs, component, i1, i2, i3]``.
 
-The paper's own test media (a Gaussian lens, a smoothed cube obstacle and a
+The paper's own test media (a Gaussian lens, a cube obstacle and a
 perturbed cube, Section 4) are described by name only; smooth seeded
-Gaussian media of the same kind stand in for them.
+Gaussian media of the same kind stand in for them, and ``medium_lens``,
+``medium_cube`` and ``medium_perturbed_cube`` are stated analogues of the
+three named media (the shapes and contrasts are this module's choice), with
+the paper's incident field E^i = (0, 0, e^{i k x_1}) (``paper_incident``).
 """
 from __future__ import annotations
 
@@ -49,6 +52,45 @@ def medium_single_bump(n: int, seed: int = 0, amplitude: float = -0.2,
     x1, x2, x3 = _grid_mesh(n)
     r2 = (x1 - c[0]) ** 2 + (x2 - c[1]) ** 2 + (x3 - c[2]) ** 2
     return (amplitude * np.exp(-r2 / (2.0 * width * width))).astype(np.complex128)
+
+
+def medium_lens(n: int, amplitude: float = -0.5, width: float = 0.15) -> np.ndarray:
+    """Analogue of the paper's Gaussian lens: one centred Gaussian,
+    m(x) = amplitude * exp(-|x - (1/2, 1/2, 1/2)|^2 / (2 width^2))
+    (relative permittivity 1 - m = 1.5 at the centre)."""
+    x1, x2, x3 = _grid_mesh(n)
+    r2 = (x1 - 0.5) ** 2 + (x2 - 0.5) ** 2 + (x3 - 0.5) ** 2
+    return (amplitude * np.exp(-r2 / (2.0 * width * width))).astype(np.complex128)
+
+
+def medium_cube(n: int, amplitude: float = -0.5, side: float = 0.3, edge: float = 0.02) -> np.ndarray:
+    """Analogue of the paper's cube obstacle with a smooth boundary:
+    m(x) = amplitude * prod_d s(x_d), s(t) = (1 - tanh((|t - 1/2| - side/2) / edge)) / 2,
+    a centred cube of the given side whose faces blur over about `edge`."""
+    x1, x2, x3 = _grid_mesh(n)
+
+    def step(t):
+        return 0.5 * (1.0 - np.tanh((np.abs(t - 0.5) - side / 2) / edge))
+
+    return (amplitude * step(x1) * step(x2) * step(x3)).astype(np.complex128)
+
+
+def medium_perturbed_cube(n: int, seed: int = 0, amplitude: float = -0.5, side: float = 0.3,
+                          perturbation: float = 0.2) -> np.ndarray:
+    """Analogue of the paper's randomly perturbed cube obstacle: ``medium_cube``
+    multiplied pointwise by 1 + perturbation * u, u ~ U[-1, 1] per grid point
+    (seeded)."""
+    g = _rng(seed)
+    u = g.uniform(-1.0, 1.0, size=(n, n, n))
+    return (medium_cube(n, amplitude, side) * (1.0 + perturbation * u)).astype(np.complex128)
+
+
+PAPER_MEDIA = {"lens": medium_lens, "cube": medium_cube, "perturbed cube": medium_perturbed_cube}
+
+
+def paper_wavenumber(n: int) -> float:
+    """Six points per wavelength, as in the paper's tables: k = 2 pi (n + 1) / 6."""
+    return 2.0 * math.pi * (n + 1) / 6.0
 
 
 def medium_bumps(n: int, seed: int = 1, nbumps: int = 6, amp: float = 0.3,
@@ -143,3 +185,9 @@ def plane_waves(n: int, k: float, dirs, pols) -> np.ndarray:
         for c in range(3):
             out[r, c] = p[c] * phase
     return out
+
+
+def paper_incident(n: int, k: float) -> np.ndarray:
+    """The incident field of the paper's 3-D examples, E^i = (0, 0, e^{i k x_1});
+    shape (1, 3, n, n, n)."""
+    return plane_waves(n, k, [[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]])
