@@ -290,6 +290,24 @@ ls_status ls_sparse_solve_gpu(ls_sparse* sp, void* b_dev, int nrhs, void* hip_st
 ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops);
 void ls_sparse_destroy(ls_sparse* sp);
 
+/* Operator form of the plan's apply (ls_apply, ls_apply_timed,
+ * ls_rhs_from_incident and the FGMRES solves). */
+typedef enum {
+  LS_FORM_DYADIC = 0,  /* y = x + K*(m x), K = (k^2 I + grad grad) G (the default) */
+  LS_FORM_PAPER = 1    /* the paper's own form (Section 2, the discrete equations):
+                          y_d = x_d + k^2 G*(m x_d) + G^d*(p.x), p^d = (dm/dx_d)/(1 - m),
+                          G^d = dG/dx_d; self weights: the integral of G over the ball of
+                          volume h^3, 0 for G^d; dm/dx_d by central differences with m = 0
+                          outside the grid */
+} ls_form;
+
+/* Select the operator form.  The first selection of LS_FORM_PAPER builds its
+ * symbol (four FP64 FFTs of P^3), p and a workspace of about 4/3 the dyadic
+ * one; LS_ENOMEM if that does not fit.  The stencils, S and its factor stay
+ * those of the dyadic fit (a preconditioner for either form).  LS_EINVAL for
+ * an unknown form.  Stream-ordered. */
+ls_status ls_plan_set_form(ls_plan* plan, ls_form form, void* hip_stream);
+
 /* Padded FFT length P used by the plan (P >= 2n - 1, even, 2^a 3^b). */
 int ls_plan_fft_size(const ls_plan* plan);
 

@@ -68,6 +68,7 @@ SIGNATURES = [
     ("ls_sparse_info", _I, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_double)]),
     ("ls_sparse_destroy", None, [_VP]),
     ("ls_plan_fft_size", _I, [_VP]),
+    ("ls_plan_set_form", _I, [_VP, _I, _VP]),
     ("ls_plan_tune", _I, [_VP, _I, _I, _VP, _VP]), ("ls_plan_set_tune", _I, [_VP, _I, _I, _I]),
     ("ls_plan_destroy", None, [_VP]),
 ]
@@ -386,6 +387,10 @@ class Plan:
         r = np.zeros((self.n ** 3, 3, 27, 3), np.complex128)
         _check(_lib.ls_get_rows(self._h, r.ctypes.data_as(ctypes.c_void_p)), "ls_get_rows")
         return r
+
+    def set_form(self, form: str):
+        """Operator form of the apply: "dyadic" (the default) or "paper" (Section 2's own form)."""
+        _check(_lib.ls_plan_set_form(self._h, {"dyadic": 0, "paper": 1}[form], _stream()), "ls_plan_set_form")
 
     def factor_gpu(self, prec: str = "c128"):
         """GPU multifrontal LU of S (complex128 or complex64 factor); returns seconds."""

@@ -514,6 +514,11 @@ ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops) {
 
 void ls_sparse_destroy(ls_sparse* sp) { delete sp; }
 
+ls_status ls_plan_set_form(ls_plan* plan, ls_form form, void* hip_stream) {
+  if (!plan || (form != LS_FORM_DYADIC && form != LS_FORM_PAPER)) return LS_EINVAL;
+  return apply_plan_set_form(plan->ap, (int)form, as_stream(hip_stream));
+}
+
 int ls_plan_fft_size(const ls_plan* plan) { return plan ? plan->ap.P : 0; }
 
 void ls_plan_destroy(ls_plan* plan) {

@@ -75,6 +75,11 @@ struct ApplyPlan {
   DevBuf work;                   // pass intermediates
   size_t work_per_rhs64 = 0;     // bytes per rhs in FP64
   ApplyTune tune[3];             // per ls_prec
+  // the paper's own 3x4 form (selected by form = 1), built on first use
+  int form = 0;
+  DevBuf kp64, kp32;             // octant symbol / P^3 of (k^2 G, G^1, G^2, G^3): [H][H][4][H]
+  DevBuf p64, p32;               // p^d = (dm/dx_d) / (1 - m), [3][n][n][n]
+  DevBuf work34;                 // four transformed fields per rhs, and p.x
 };
 
 ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const void* m_dev,
@@ -87,6 +92,10 @@ ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec pre
 // max_rhs) at a time.
 ls_status apply_batched(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
                         bool minus_conv = false);
+// Select the operator form: 0 the dyadic form y = x + K*(m x); 1 the paper's
+// form y_d = x_d + k^2 G*(m x_d) + G^d*(p.x) (its symbol, p and workspace are
+// built on the first selection).
+ls_status apply_plan_set_form(ApplyPlan& ap, int form, hipStream_t s);
 // Pass-3 team counts the plan's FFT size supports (1 always; 2 and 4 when a
 // team is one wavefront).
 std::vector<int> kmul_team_choices(const ApplyPlan& ap);

@@ -588,6 +588,201 @@ __global__ void to_c64(const C<double>* __restrict__ a, C<float>* __restrict__ b
   if (id < cnt) b[id] = ccast<float>(a[id]);
 }
 
+// ---- the paper's own form (Section 2): y_d = x_d + k^2 G*(m x_d) + G^d*(p.x) ----
+// Component cidx of (k^2 G, G^1, G^2, G^3) on the P^3 circulant embedding
+// (index r mod P for |r_d| <= n-1, zero elsewhere).  Off the origin:
+// k^2 h^3 G(hr) and h^3 dG/dx_d(hr) = h^3 G (ik - 1/R) x_d / R.  At the
+// origin: k^2 times the integral of G over the ball of volume h^3,
+// e^{ika}(1 - ika) - 1, and 0 for the odd G^d.
+__global__ void embed_paper_component(C<double>* __restrict__ E, int n, int P, double k, double h, int cidx) {
+  const long tot = (long)P * P * P;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= tot) return;
+  const int e3 = (int)(id % P);
+  const int e2 = (int)((id / P) % P);
+  const int e1 = (int)(id / ((long)P * P));
+  const int r1 = e1 <= P / 2 ? e1 : e1 - P;
+  const int r2 = e2 <= P / 2 ? e2 : e2 - P;
+  const int r3 = e3 <= P / 2 ? e3 : e3 - P;
+  C<double> val = cmk(0.0, 0.0);
+  if (abs(r1) <= n - 1 && abs(r2) <= n - 1 && abs(r3) <= n - 1) {
+    if (r1 == 0 && r2 == 0 && r3 == 0) {
+      if (cidx == 0) {
+        const double a = h * cbrt(3.0 / (4.0 * kPi));
+        double sn, cs;
+        sincos(k * a, &sn, &cs);
+        val = cmk(cs + k * a * sn - 1.0, sn - k * a * cs);   // (1 - ika) e^{ika} - 1
+      }
+    } else {
+      const double x[3] = {h * r1, h * r2, h * r3};
+      const double R = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      double sn, cs;
+      sincos(k * R, &sn, &cs);
+      const double g = h * h * h / (4.0 * kPi * R);
+      const C<double> G = cmk(cs * g, sn * g);                // h^3 G(hr)
+      if (cidx == 0)
+        val = cscale(G, k * k);
+      else
+        val = cscale(G * cmk(-1.0 / R, k), x[cidx - 1] / R);
+    }
+  }
+  E[id] = val;
+}
+
+// Kp[f1][f2][cidx][f3] = E[f1][f2][f3] * inv
+__global__ void gather_octant4(const C<double>* __restrict__ E, C<double>* __restrict__ kp64,
+                               C<float>* __restrict__ kp32, int P, int cidx, double inv) {
+  const int H = P / 2 + 1;
+  const long tot = (long)H * H * H;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= tot) return;
+  const int f3 = (int)(id % H);
+  const int f2 = (int)((id / H) % H);
+  const int f1 = (int)(id / ((long)H * H));
+  const C<double> v = cscale(E[((long)f1 * P + f2) * P + f3], inv);
+  const long o = (((long)f1 * H + f2) * 4 + cidx) * H + f3;
+  kp64[o] = v;
+  kp32[o] = ccast<float>(v);
+}
+
+// p^d = (m_{i+e_d} - m_{i-e_d}) / (2h) / (1 - m_i), m = 0 outside the grid
+__global__ void gradient_p_kernel(const C<double>* __restrict__ m, int n, double h, C<double>* __restrict__ p64,
+                                  C<float>* __restrict__ p32) {
+  const long n3 = (long)n * n * n;
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n3) return;
+  const int i3 = (int)(id % n), i2 = (int)((id / n) % n), i1 = (int)(id / ((long)n * n));
+  const int ii[3] = {i1, i2, i3};
+  const long st[3] = {(long)n * n, (long)n, 1};
+  const C<double> mi = m[id];
+  const double dr = 1.0 - mi.re, di = -mi.im, dd = dr * dr + di * di;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const C<double> mp = ii[d] + 1 < n ? m[id + st[d]] : cmk(0.0, 0.0);
+    const C<double> mm = ii[d] > 0 ? m[id - st[d]] : cmk(0.0, 0.0);
+    const C<double> g = cscale(mp - mm, 0.5 / h);
+    // g / (1 - m)
+    const C<double> q = cmk((g.re * dr + g.im * di) / dd, (g.im * dr - g.re * di) / dd);
+    p64[d * n3 + id] = q;
+    p32[d * n3 + id] = ccast<float>(q);
+  }
+}
+
+// w_b = sum_d p^d x_{b,d}  ([B][n^3], the fourth transformed field)
+template <typename R, typename IO>
+__global__ void pdot_kernel(const C<IO>* __restrict__ x, const C<R>* __restrict__ p, C<R>* __restrict__ w, long n3,
+                            int B) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n3 * B) return;
+  const long b = id / n3, e = id % n3;
+  const C<IO>* xb = x + b * 3 * n3;
+  w[id] = p[e] * ccast<R>(xb[e]) + p[n3 + e] * ccast<R>(xb[n3 + e]) + p[2 * n3 + e] * ccast<R>(xb[2 * n3 + e]);
+}
+
+// Pass 3 of the paper's form: along dim 3 for each (q1, q2) line, the forward
+// transform of the four fields (m x_1, m x_2, m x_3 at fields 3b + c, p.x at
+// field 3B + b), v_c = k^2 Ghat u_c + G^c hat w, and the inverse transform of
+// the three v_c into fields 3b + c.  k^2 G is even in every coordinate, G^d
+// odd in coordinate d: a mirrored line flips the sign of G^1 (q1), G^2 (q2),
+// and a frequency past P/2 that of G^3.  One team of four jobs per workgroup.
+template <typename R, int P, int N1, int N2>
+__global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul34_kernel(C<R>* __restrict__ X,
+                                                                  const C<R>* __restrict__ Kp,
+                                                                  const C<R>* __restrict__ tw, int n, int B) {
+  constexpr int H = P / 2 + 1;
+  constexpr int TPL = cmax(N1, N2);
+  constexpr int EXS = N1 * N2 + N2;
+  __shared__ C<R> kl[4 * H];
+  __shared__ C<R> twl[P];
+  __shared__ C<R> ex[4 * EXS];
+  const int f1 = blockIdx.x / H;
+  const int f2 = blockIdx.x % H;
+  const int tid = threadIdx.x;
+  const int job = tid / TPL;
+  const int j = tid % TPL;
+  const int s1 = job & 1, s2 = job >> 1;
+  const bool edge1 = (f1 == 0) || (2 * f1 == P);
+  const bool edge2 = (f2 == 0) || (2 * f2 == P);
+  const bool active = !((s1 && edge1) || (s2 && edge2));
+  const int q1 = s1 ? P - f1 : f1;
+  const int q2 = s2 ? P - f2 : f2;
+  const long plane = (long)P * P * n;
+  const long lineoff = ((long)q1 * P + q2) * n;
+  const C<R>* kg = Kp + ((long)f1 * H + f2) * 4 * H;
+  for (int e = tid; e < 4 * H; e += blockDim.x) kl[e] = kg[e];
+  for (int e = tid; e < P; e += blockDim.x) twl[e] = tw[e];
+  const R sx = s1 ? (R)-1 : (R)1;
+  const R sy = s2 ? (R)-1 : (R)1;
+  __syncthreads();
+  C<R>* myex = ex + job * EXS;
+  constexpr int KIN = (N2 + 1) / 2;
+  for (int b = 0; b < B; ++b) {
+    C<R>* base[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) base[c] = X + ((long)b * 3 + c) * plane + lineoff;
+    base[3] = X + ((long)B * 3 + b) * plane + lineoff;
+    C<R> u[4][N1];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (active && j < N1) {
+        C<R> v[N2];
+#pragma unroll
+        for (int k = 0; k < KIN; ++k) {
+          const int tt = j + N1 * k;
+          v[k] = (tt < n) ? base[c][tt] : cmk<R>(0, 0);
+        }
+        DftZ<N2, -1, R, KIN>::run(v);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) myex[q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * twl[j * q];
+      }
+      __syncthreads();
+      if (active && j < N2) {
+#pragma unroll
+        for (int a = 0; a < N1; ++a) u[c][a] = myex[j * (N1 + 1) + a];
+        Dft<N1, -1, R>::run(u[c]);
+      }
+      __syncthreads();
+    }
+    if (active && j < N2) {
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const int q3 = j + N2 * a;
+        const bool fl3 = 2 * q3 > P;
+        const int f3 = fl3 ? P - q3 : q3;
+        const R s3 = fl3 ? (R)-1 : (R)1;
+        const C<R> g0 = kl[f3];
+        const C<R> g1 = cscale(kl[H + f3], sx), g2 = cscale(kl[2 * H + f3], sy), g3 = cscale(kl[3 * H + f3], s3);
+        const C<R> w = u[3][a];
+        u[0][a] = g0 * u[0][a] + g1 * w;
+        u[1][a] = g0 * u[1][a] + g2 * w;
+        u[2][a] = g0 * u[2][a] + g3 * w;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (active && j < N2) {
+        Dft<N1, 1, R>::run(u[c]);
+#pragma unroll
+        for (int t2 = 0; t2 < N1; ++t2)
+          myex[j * (N1 + 1) + t2] = (j * t2 == 0) ? u[c][t2] : u[c][t2] * cconj(twl[j * t2]);
+      }
+      __syncthreads();
+      if (active && j < N1) {
+        C<R> v[N2];
+#pragma unroll
+        for (int q = 0; q < N2; ++q) v[q] = myex[q * (N1 + 1) + j];
+        Dft<N2, 1, R>::run(v);
+#pragma unroll
+        for (int t1 = 0; t1 < (N2 + 1) / 2; ++t1) {
+          const int tt = j + N1 * t1;
+          if (tt < n) base[c][tt] = v[t1];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // ---- launch helpers -----------------------------------------------------------
 template <typename R, typename IO, int P, int MODE, bool PAD = true>
 static ls_status launch_col(const void* in, void* out, const void* aux, const C<R>* tw, int rows_in,
@@ -685,6 +880,28 @@ static ls_status build_symbol(ApplyPlan& ap, hipStream_t s) {
   return LS_OK;
 }
 
+template <int P>
+static ls_status build_paper_symbol(ApplyPlan& ap, hipStream_t s) {
+  const long P3 = (long)P * P * P;
+  DevBuf E, scr;
+  LS_TRY(E.alloc(P3 * sizeof(C<double>)));
+  LS_TRY(scr.alloc(P3 * sizeof(C<double>)));
+  const int H = P / 2 + 1;
+  const long H3 = (long)H * H * H;
+  const double inv = 1.0 / (double)P3;
+  for (int c = 0; c < 4; ++c) {
+    hipLaunchKernelGGL(embed_paper_component, dim3((unsigned)((P3 + 255) / 256)), dim3(256), 0, s,
+                       E.as<C<double>>(), ap.n, P, ap.k, ap.h, c);
+    LS_HIP(hipGetLastError());
+    LS_TRY(fft3d_f64<P>(E.as<C<double>>(), scr.as<C<double>>(), ap.tw64.as<C<double>>(), s));
+    hipLaunchKernelGGL(gather_octant4, dim3((unsigned)((H3 + 255) / 256)), dim3(256), 0, s,
+                       E.as<C<double>>(), ap.kp64.as<C<double>>(), ap.kp32.as<C<float>>(), P, c, inv);
+    LS_HIP(hipGetLastError());
+  }
+  LS_HIP(hipStreamSynchronize(s));
+  return LS_OK;
+}
+
 template <typename R, typename IO, int P>
 static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, const C<R>* m,
                             const C<R>* kh, const C<R>* tw, bool minus_conv, int wt, hipStream_t s,
@@ -719,10 +936,67 @@ static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, con
   return LS_OK;
 }
 
+// The paper's form: passes 1 and 2 on the three fields m x_d and on p.x, the
+// 3x4 multiply in pass 3, passes 4 and 5 on the three results as in the
+// dyadic form.  work34: X1 [4B][P][n^2], X2 [4B][P][P][n], W [B][n^3].
+template <typename R, typename IO, int P>
+static ls_status run_passes34(ApplyPlan& ap, const void* x, void* y, int nrhs, const C<R>* m, const C<R>* p,
+                              const C<R>* kp, const C<R>* tw, bool minus_conv, hipStream_t s, hipEvent_t* ev) {
+  const int n = ap.n;
+  const long n2 = (long)n * n, n3 = n2 * n;
+  C<R>* X1 = ap.work34.as<C<R>>();
+  C<R>* X2 = X1 + (long)nrhs * 4 * P * n2;
+  C<R>* W = X2 + (long)nrhs * 4 * P * P * n;
+  const long nb = (long)nrhs * 3;
+#define LS_MARK(i) \
+  if (ev) LS_HIP(hipEventRecord(ev[i], s))
+  LS_MARK(0);
+  hipLaunchKernelGGL((pdot_kernel<R, IO>), dim3((unsigned)((n3 * nrhs + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const C<IO>*>(x), p, W, n3, nrhs);
+  LS_HIP(hipGetLastError());
+  LS_TRY((launch_col<R, IO, P, COL_P1>(x, X1, m, tw, n, P, n2, n3, (long)P * n2, nb, (R)1, s)));
+  LS_TRY((launch_col<R, R, P, COL_FWD>(W, X1 + nb * P * n2, nullptr, tw, n, P, n2, n3, (long)P * n2, nrhs, (R)1,
+                                       s)));
+  LS_MARK(1);
+  LS_TRY((launch_col<R, R, P, COL_FWD>(X1, X2, nullptr, tw, n, P, n, n2, (long)P * n, 4L * nrhs * P, (R)1, s)));
+  LS_MARK(2);
+  {
+    constexpr Fac f = row_factors<R>(P);
+    constexpr int H = P / 2 + 1;
+    hipLaunchKernelGGL((kmul34_kernel<R, P, f.n1, f.n2>), dim3(H * H), dim3(4 * cmax(f.n1, f.n2)), 0, s, X2, kp, tw,
+                       n, nrhs);
+    LS_HIP(hipGetLastError());
+  }
+  LS_MARK(3);
+  LS_TRY((launch_col<R, R, P, COL_INV>(X2, X1, nullptr, tw, P, n, n, (long)P * n, n2, nb * P, (R)1, s)));
+  LS_MARK(4);
+  if (minus_conv)
+    LS_TRY((launch_col<R, IO, P, COL_P5>(X1, y, nullptr, tw, P, n, n2, (long)P * n2, n3, nb, (R)-1, s)));
+  else
+    LS_TRY((launch_col<R, IO, P, COL_P5>(X1, y, x, tw, P, n, n2, (long)P * n2, n3, nb, (R)1, s)));
+  LS_MARK(5);
+#undef LS_MARK
+  return LS_OK;
+}
+
 template <int P>
 static ls_status apply_dispatch(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec,
                                 bool minus_conv, hipStream_t s, hipEvent_t* ev) {
   const int wt = ap.tune[prec].kmul_w;
+  if (ap.form == 1) {
+    switch (prec) {
+      case LS_C128:
+        return run_passes34<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(), ap.p64.as<C<double>>(),
+                                               ap.kp64.as<C<double>>(), ap.tw64.as<C<double>>(), minus_conv, s, ev);
+      case LS_C64:
+        return run_passes34<float, float, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.p32.as<C<float>>(),
+                                             ap.kp32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+      case LS_MIXED:
+        return run_passes34<float, double, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.p32.as<C<float>>(),
+                                              ap.kp32.as<C<float>>(), ap.tw32.as<C<float>>(), minus_conv, s, ev);
+    }
+    return LS_EINVAL;
+  }
   switch (prec) {
     case LS_C128:
       return run_passes<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(), ap.kh64.as<C<double>>(),
@@ -782,6 +1056,37 @@ ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const voi
   return LS_EINVAL;
 }
 
+ls_status apply_plan_set_form(ApplyPlan& ap, int form, hipStream_t s) {
+  if (form != 0 && form != 1) return LS_EINVAL;
+  if (form == 1 && !ap.kp64.p) {
+    const int n = ap.n, P = ap.P, H = ap.H;
+    const long n3 = (long)n * n * n, H3 = (long)H * H * H;
+    LS_TRY(ap.kp64.alloc(H3 * 4 * sizeof(C<double>)));
+    LS_TRY(ap.kp32.alloc(H3 * 4 * sizeof(C<float>)));
+    LS_TRY(ap.p64.alloc(3 * n3 * sizeof(C<double>)));
+    LS_TRY(ap.p32.alloc(3 * n3 * sizeof(C<float>)));
+    // FP64 sizes: X1 and X2 of four fields and W of one, per rhs
+    const size_t per = ((size_t)4 * P * n * n + (size_t)4 * P * P * n + (size_t)n3) * sizeof(C<double>);
+    LS_TRY(ap.work34.alloc(per * (size_t)ap.max_rhs));
+    hipLaunchKernelGGL(gradient_p_kernel, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s,
+                       ap.m64.as<C<double>>(), n, ap.h, ap.p64.as<C<double>>(), ap.p32.as<C<float>>());
+    LS_HIP(hipGetLastError());
+    ls_status st = LS_EINVAL;
+    switch (P) {
+#define X(SZ) \
+  case SZ: st = build_paper_symbol<SZ>(ap, s); break;
+      LS_FOR_SIZES(X)
+#undef X
+    }
+    if (st != LS_OK) {
+      ap.kp64.release();
+      return st;
+    }
+  }
+  ap.form = form;
+  return LS_OK;
+}
+
 std::vector<int> kmul_team_choices(const ApplyPlan& ap) {
   const Fac f = col_factors(ap.P);
   if (4 * cmax(f.n1, f.n2) == 64) return {1, 2, 4};
@@ -807,7 +1112,7 @@ ls_status apply_batched(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec
   if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
   const size_t es = (prec == LS_C64) ? 8 : 16;
   const size_t per = (size_t)3 * ap.n * ap.n * ap.n * es;
-  int chunk = ap.tune[prec].chunk;
+  int chunk = ap.form == 0 ? ap.tune[prec].chunk : 0;   // the tuned choices are the dyadic form's
   if (chunk <= 0 || chunk > ap.max_rhs) chunk = ap.max_rhs;
   for (int b0 = 0; b0 < nrhs; b0 += chunk) {
     const int nb = std::min(chunk, nrhs - b0);
