@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "8331e11e823553478f7603359e103dcd0e71c5b02e0db88e7ae4966375670c85",
+    "sha256": "4677f5972485c3a1652019bdd8e4fb98c78c1f97a3933c7b785595061258a863",
     "workload": (128, 8, "c64"),
     "bytes": 3.3268e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
@@ -360,6 +360,11 @@ def main():
     pms /= max(3, min(args.steps, 20))
     ms64, _ = timed("c128", x64, y64, max(5, args.steps // 2), 2)
     msmx, _ = timed("mixed", x64, y64, max(5, args.steps // 2), 2)
+    # the paper's own 3x4 form on the same plan (four forward transforms, three inverse)
+    plan.set_form("paper")
+    ms_pf, _ = timed("c64", x32, y32, max(5, args.steps // 2), 2)
+    ms_pf64, _ = timed("c128", x64, y64, max(5, args.steps // 4), 1)
+    plan.set_form("dyadic")
 
     unknowns = B * 3 * n ** 3
     value = unknowns / (ms32 * 1e-3) / 1e6
@@ -394,6 +399,8 @@ def main():
         "pass_GBps": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(pb, pms)],
         "c128_Munknowns_per_s": round(unknowns / (ms64 * 1e-3) / 1e6, 1),
         "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
+        "paper_form_Munknowns_per_s": round(unknowns / (ms_pf * 1e-3) / 1e6, 1),
+        "paper_form_c128_Munknowns_per_s": round(unknowns / (ms_pf64 * 1e-3) / 1e6, 1),
         "wall_s_timed": round(wall32, 3),
     }
     if args.n192:
