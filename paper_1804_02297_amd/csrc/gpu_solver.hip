@@ -1063,91 +1063,91 @@ __global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict
           const int o = tid + 256 * u;
           const int i = o / kKC, j = o % kKC;
           R vr = R(0), vi = R(0);
-        if (i < cnt && j < nj) {
-          vr = fac[d.p + (i0 + i) * nf + np + jc + j];
-          vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
+          if (i < cnt && j < nj) {
+            vr = fac[d.p + (i0 + i) * nf + np + jc + j];
+            vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
         }
-        ld0_[u] = vr;
-        ld1_[u] = vi;
-      }
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int o = tid + 256 * u;
-        const int i = o / kKC, j = o % kKC;
-        Ar_[i * LA + j] = ld0_[u];
-        Ai_[i * LA + j] = ld1_[u];
-      }
-    }
-    {  // all loads issued before the LDS stores
-      constexpr int NU = (kKC * kSR) / 256;
-      R ld0_[NU], ld1_[NU];
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int o = tid + 256 * u;
-        const int j = o / kSR, r = o % kSR;
-        R vr = R(0), vi = R(0);
-        if (j < nj && r < nr) {
-          const long e = ib[d.bm + jc + j];
-          vr = Xr[e * nrhs + r0 + r];
-          vi = Xi[e * nrhs + r0 + r];
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int i = o / kKC, j = o % kKC;
+          Ar_[i * LA + j] = ld0_[u];
+          Ai_[i * LA + j] = ld1_[u];
         }
-        ld0_[u] = vr;
-        ld1_[u] = vi;
       }
+      {  // all loads issued before the LDS stores
+        constexpr int NU = (kKC * kSR) / 256;
+        R ld0_[NU], ld1_[NU];
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int o = tid + 256 * u;
-        const int j = o / kSR, r = o % kSR;
-        Br_[j * kLX + r] = ld0_[u];
-        Bi_[j * kLX + r] = ld1_[u];
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int j = o / kSR, r = o % kSR;
+          R vr = R(0), vi = R(0);
+          if (j < nj && r < nr) {
+            const long e = ib[d.bm + jc + j];
+            vr = Xr[e * nrhs + r0 + r];
+            vi = Xi[e * nrhs + r0 + r];
+          }
+          ld0_[u] = vr;
+          ld1_[u] = vi;
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+          const int o = tid + 256 * u;
+          const int j = o / kSR, r = o % kSR;
+          Br_[j * kLX + r] = ld0_[u];
+          Bi_[j * kLX + r] = ld1_[u];
+        }
       }
+      __syncthreads();
+      cmma64<R>(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane, cr, ci);
+      __syncthreads();
     }
-    __syncthreads();
-    cmma64<R>(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane, cr, ci);
-    __syncthreads();
-  }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
-        if (row < cnt && col < nr) {
-          if (nks == 1) {
-            Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
-            Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
-          } else {
-            const long o = (((long)q * nks_max + ks) * np_max + i0 + row) * nrhs + r0 + col;
-            Pr[o] = cr[a][b][r];
-            Pi[o] = ci[a][b][r];
+        for (int r = 0; r < 4; ++r) {
+          const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
+          if (row < cnt && col < nr) {
+            if (nks == 1) {
+              Zr[(d.e0 + i0 + row) * nrhs + r0 + col] -= cr[a][b][r];
+              Zi[(d.e0 + i0 + row) * nrhs + r0 + col] -= ci[a][b][r];
+            } else {
+              const long o = (((long)q * nks_max + ks) * np_max + i0 + row) * nrhs + r0 + col;
+              Pr[o] = cr[a][b][r];
+              Pi[o] = ci[a][b][r];
+            }
           }
         }
-      }
-}
+  }
 }
 
 template <typename R>
 __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                       int nlvl, int nks_max, long np_max, int nrhs,
-                                                       const R* __restrict__ Pr, const R* __restrict__ Pi,
-                                                       R* __restrict__ Zr, R* __restrict__ Zi) {
-for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
-  const FrontDev d = fr[lvl[q]];
-  const int nks = (int)((d.nb + kKS - 1) / kKS);
-  if (nks < 2) continue;
-  for (long i = (long)blockIdx.x * 4 + (threadIdx.x >> 6); i < d.np; i += (long)gridDim.x * 4)
-    for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
-      R sr = R(0), si = R(0);
-      for (int ks = 0; ks < nks; ++ks) {
-        const long o = (((long)q * nks_max + ks) * np_max + i) * nrhs + r;
-        sr += Pr[o];
-        si += Pi[o];
+                                                         int nlvl, int nks_max, long np_max, int nrhs,
+                                                         const R* __restrict__ Pr, const R* __restrict__ Pi,
+                                                         R* __restrict__ Zr, R* __restrict__ Zi) {
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    const int nks = (int)((d.nb + kKS - 1) / kKS);
+    if (nks < 2) continue;
+    for (long i = (long)blockIdx.x * 4 + (threadIdx.x >> 6); i < d.np; i += (long)gridDim.x * 4)
+      for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+        R sr = R(0), si = R(0);
+        for (int ks = 0; ks < nks; ++ks) {
+          const long o = (((long)q * nks_max + ks) * np_max + i) * nrhs + r;
+          sr += Pr[o];
+          si += Pi[o];
+        }
+        Zr[(d.e0 + i) * nrhs + r] -= sr;
+        Zi[(d.e0 + i) * nrhs + r] -= si;
       }
-      Zr[(d.e0 + i) * nrhs + r] -= sr;
-      Zi[(d.e0 + i) * nrhs + r] -= si;
-    }
-}
+  }
 }
 
 // Backward solve step of super-block [kb0, kb0 + sw).  Workgroups [0, 3):
@@ -1155,54 +1155,54 @@ for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
 // i < kb0: y_i -= Uhat[i][block] y_block.  Both read only the block's y rows.
 template <typename R>
 __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
-                                                   int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
-                                                   R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
-                                                   R* __restrict__ Zi) {
-typedef typename Mma<R>::v4 v4;
-constexpr int NZB = kSB / kRB;
-__shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
-__shared__ R Br_[kT * kLX], Bi_[kT * kLX];
-const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-const int r0 = blockIdx.z * kSR;
-const int nr = min(kSR, nrhs - r0);
-const bool xrole = (int)blockIdx.x < NZB;
-for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
-  const FrontDev d = fr[lvl[q]];
-  if (kb0 >= d.np) continue;
-  const int sw = min(kSB, d.np - kb0);
-  const long nf = d.nf, np = d.np;
-  long i0;
-  int cnt;
-  if (xrole) {
-    i0 = (long)blockIdx.x * kRB;
-    if (i0 >= sw) continue;
-    cnt = (int)min((long)kRB, sw - i0);
-  } else {
-    i0 = (long)(blockIdx.x - NZB) * kRB;
-    if (i0 >= kb0) continue;
-    cnt = (int)min((long)kRB, kb0 - i0);
-  }
-  const R* Hr = fac + d.h + (long)(kb0 / kSB) * 2 * kSB * kSB;
-  const R* Hi = Hr + kSB * kSB;
-  v4 cr[2][2], ci[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-      ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+                                                     int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                     R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
+                                                     R* __restrict__ Zi) {
+  typedef typename Mma<R>::v4 v4;
+  constexpr int NZB = kSB / kRB;
+  __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
+  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r0 = blockIdx.z * kSR;
+  const int nr = min(kSR, nrhs - r0);
+  const bool xrole = (int)blockIdx.x < NZB;
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
+    const long nf = d.nf, np = d.np;
+    long i0;
+    int cnt;
+    if (xrole) {
+      i0 = (long)blockIdx.x * kRB;
+      if (i0 >= sw) continue;
+      cnt = (int)min((long)kRB, sw - i0);
+    } else {
+      i0 = (long)(blockIdx.x - NZB) * kRB;
+      if (i0 >= kb0) continue;
+      cnt = (int)min((long)kRB, kb0 - i0);
     }
-  // the next K chunk is loaded into registers while the MFMAs consume the current one
-  constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
-  R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
-  auto fetch = [&](int kc) {
-    const int kw = min(kT, sw - kc);
+    const R* Hr = fac + d.h + (long)(kb0 / kSB) * 2 * kSB * kSB;
+    const R* Hi = Hr + kSB * kSB;
+    v4 cr[2][2], ci[2][2];
 #pragma unroll
-    for (int u = 0; u < NUA; ++u) {
-      const int o = tid + 256 * u;
-      const int i = o / kT, k = o % kT;
-      R vr = R(0), vi = R(0);
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
+        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
+      }
+    // the next K chunk is loaded into registers while the MFMAs consume the current one
+    constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
+    R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
+    auto fetch = [&](int kc) {
+      const int kw = min(kT, sw - kc);
+#pragma unroll
+      for (int u = 0; u < NUA; ++u) {
+        const int o = tid + 256 * u;
+        const int i = o / kT, k = o % kT;
+        R vr = R(0), vi = R(0);
         if (i < cnt && k < kw) {
           if (xrole) {
             vr = Hr[(i0 + i) * kSB + kc + k];
