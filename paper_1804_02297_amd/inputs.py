@@ -16,6 +16,11 @@ Gaussian media of the same kind stand in for them, and ``medium_lens``,
 ``medium_cube`` and ``medium_perturbed_cube`` are stated analogues of the
 three named media (the shapes and contrasts are this module's choice), with
 the paper's incident field E^i = (0, 0, e^{i k x_1}) (``paper_incident``).
+
+The 2-D variant uses the n x n grid of the unit square, fields
+``[rhs, component(2), i1, i2]``, the analogues ``medium2_lens``,
+``medium2_square`` and ``medium2_perturbed_square`` of the paper's 2-D
+examples and its incident field E^i = (0, e^{i k x_1}) (``paper_incident2``).
 """
 from __future__ import annotations
 
@@ -191,3 +196,80 @@ def paper_incident(n: int, k: float) -> np.ndarray:
     """The incident field of the paper's 3-D examples, E^i = (0, 0, e^{i k x_1});
     shape (1, 3, n, n, n)."""
     return plane_waves(n, k, [[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]])
+
+
+# --- the 2-D variant: n x n grid of the unit square, fields [rhs, component(2), i1, i2] ---
+
+def _grid_mesh2(n: int):
+    x = grid_coords(n)
+    return np.meshgrid(x, x, indexing="ij")
+
+
+def medium2_lens(n: int, amplitude: float = -0.5, width: float = 0.15) -> np.ndarray:
+    """2-D analogue of the paper's converging Gaussian lens (Section 4, 2-D
+    examples): m(x) = amplitude * exp(-|x - (1/2, 1/2)|^2 / (2 width^2))."""
+    x1, x2 = _grid_mesh2(n)
+    r2 = (x1 - 0.5) ** 2 + (x2 - 0.5) ** 2
+    return (amplitude * np.exp(-r2 / (2.0 * width * width))).astype(np.complex128)
+
+
+def medium2_square(n: int, amplitude: float = -0.5, side: float = 0.3, edge: float = 0.02) -> np.ndarray:
+    """2-D analogue of the paper's square obstacle with a smooth boundary:
+    amplitude * s(x_1) s(x_2), s(t) = (1 - tanh((|t - 1/2| - side/2) / edge)) / 2."""
+    x1, x2 = _grid_mesh2(n)
+
+    def step(t):
+        return 0.5 * (1.0 - np.tanh((np.abs(t - 0.5) - side / 2) / edge))
+
+    return (amplitude * step(x1) * step(x2)).astype(np.complex128)
+
+
+def medium2_perturbed_square(n: int, seed: int = 0, amplitude: float = -0.5, side: float = 0.3,
+                             perturbation: float = 0.2) -> np.ndarray:
+    """2-D analogue of the paper's random perturbation of the square obstacle:
+    ``medium2_square`` times 1 + perturbation * u, u ~ U[-1, 1] per point (seeded)."""
+    u = _rng(seed).uniform(-1.0, 1.0, size=(n, n))
+    return (medium2_square(n, amplitude, side) * (1.0 + perturbation * u)).astype(np.complex128)
+
+
+PAPER_MEDIA_2D = {"lens": medium2_lens, "square": medium2_square, "perturbed square": medium2_perturbed_square}
+
+
+def medium2_random_complex(n: int, seed: int, scale: float = 0.3) -> np.ndarray:
+    """Unstructured complex 2-D contrast, for operator parity tests only."""
+    g = _rng(seed)
+    return scale * (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n)))
+
+
+def random_field2(nrhs: int, n: int, seed: int) -> np.ndarray:
+    """Complex standard-normal 2-D field, shape (nrhs, 2, n, n)."""
+    g = _rng(seed)
+    shp = (nrhs, 2, n, n)
+    return g.standard_normal(shp) + 1j * g.standard_normal(shp)
+
+
+def plane_waves2(n: int, k: float, dirs, pols) -> np.ndarray:
+    """E^i_c(x) = p_c exp(i k d.x) on the 2-D grid; shape (len(dirs), 2, n, n)."""
+    x1, x2 = _grid_mesh2(n)
+    dirs = np.atleast_2d(np.asarray(dirs, dtype=np.float64))
+    pols = np.atleast_2d(np.asarray(pols, dtype=np.float64))
+    out = np.empty((len(dirs), 2, n, n), dtype=np.complex128)
+    for r, (d, p) in enumerate(zip(dirs, pols)):
+        phase = np.exp(1j * k * (d[0] * x1 + d[1] * x2))
+        for c in range(2):
+            out[r, c] = p[c] * phase
+    return out
+
+
+def circle_incident_set2(count: int):
+    """``count`` directions evenly spaced on the circle, each with its in-plane
+    polarisation p = (-d_2, d_1): (directions, polarisations)."""
+    t = 2.0 * math.pi * np.arange(count) / count
+    d = np.stack([np.cos(t), np.sin(t)], axis=1)
+    return d, np.stack([-d[:, 1], d[:, 0]], axis=1)
+
+
+def paper_incident2(n: int, k: float) -> np.ndarray:
+    """The incident field of the paper's 2-D examples, E^i = (0, e^{i k x_1});
+    shape (1, 2, n, n)."""
+    return plane_waves2(n, k, [[1.0, 0.0]], [[0.0, 1.0]])

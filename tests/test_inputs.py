@@ -60,3 +60,18 @@ def test_paper_incident_field():
     x1 = I.grid_coords(n)[:, None, None]
     assert np.array_equal(e[0, 0], np.zeros((n, n, n))) and np.array_equal(e[0, 1], np.zeros((n, n, n)))
     assert np.allclose(e[0, 2], np.broadcast_to(np.exp(1j * k * x1), (n, n, n)))
+
+
+def test_two_d_generators():
+    n = 9
+    k = I.paper_wavenumber(n)
+    Ei = I.paper_incident2(n, k)
+    x = I.grid_coords(n)
+    assert Ei.shape == (1, 2, n, n)
+    assert np.array_equal(Ei[0, 0], np.zeros((n, n)))
+    assert np.allclose(Ei[0, 1], np.exp(1j * k * x)[:, None] * np.ones(n)[None])
+    d, p = I.circle_incident_set2(6)
+    assert np.allclose(np.sum(d * p, axis=1), 0) and np.allclose(np.linalg.norm(p, axis=1), 1)
+    assert np.array_equal(I.medium2_perturbed_square(n, 3), I.medium2_perturbed_square(n, 3))
+    assert abs(I.medium2_lens(n)[n // 2, n // 2] + 0.5) < 1e-12
+    assert I.random_field2(2, n, 1).shape == (2, 2, n, n)
