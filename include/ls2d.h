@@ -1,0 +1,66 @@
+/*
+ * ls2d.h - C ABI of the 2-D variant of the sparsifying-preconditioned solver
+ * (the paper notes in Section 2 that the scattered-field equation holds in
+ * 2-D with the 2-D Helmholtz kernel; Section 3.3 gives the 2-D costs and
+ * Section 4 the 2-D examples).
+ *
+ * Problem: on the unit square with n points per dimension, h = 1/(n+1),
+ * nodes x_i = i h, i in {1..n}^2, the field E has two complex components
+ * and the operator is the paper's own form in two dimensions:
+ *
+ *     (A E)^d_i = E^d_i + k^2 sum_j G_ij m_j E^d_j + sum_j G^d_ij (p . E)_j ,
+ *
+ * G(x) = (i/4) H_0^(1)(k|x|), G^d = dG/dx_d, G_ij = h^2 G(x_i - x_j) and
+ * G^d_ij = h^2 G^d(x_i - x_j) for i != j; the self weight of G is its
+ * integral over the disc of area h^2, that of G^d is 0; p^d = (dm/dx_d) /
+ * (1 - m) with dm/dx_d by central differences (m = 0 off the grid).
+ *
+ * Layout of every field: interleaved complex, [rhs][component(2)][i1][i2]
+ * with i2 fastest; the contrast m is complex128 [i1][i2].  Field and
+ * contrast pointers are DEVICE pointers owned by the caller; nothing is
+ * retained after a call except what the plan copies.  Calls are ordered on
+ * the HIP stream passed in (NULL = the default stream); calls that do host
+ * work synchronise it before they return.  Status codes and precisions are
+ * those of ls.h.
+ */
+#ifndef LS2D_H
+#define LS2D_H
+
+#include "ls.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ls2_plan ls2_plan;
+
+/* Create a plan for 3 <= n <= 1024 (padded FFT length P <= 2048, the
+ * smallest even 2^a 3^b >= 2n - 1), wavenumber k > 0 and at most max_rhs
+ * right-hand sides per internal launch set (any nrhs is accepted later).
+ * Copies m (complex128 [n][n], device), computes p, samples the weights in
+ * FP64 on the GPU and transforms their circulant embedding into the symbol
+ * (k^2 Ghat, Ghat^1, Ghat^2), kept in FP64 and rounded to FP32.  Workspace:
+ * max_rhs * 5 n P complex128.  LS_EINVAL on a bad argument, LS_ENOMEM when
+ * the device allocations fail.  Synchronises. */
+ls_status ls2_plan_create(int n, double k, int max_rhs, const void* m_dev, void* hip_stream, ls2_plan** out);
+
+/* y = A x for nrhs fields (the discrete equations above, by zero-padded 2-D
+ * FFTs: three forward, the 2x3 symbol multiply, two inverse).  x, y: device
+ * [nrhs][2][n][n], complex128 for LS_C128 and LS_MIXED, complex64 for LS_C64;
+ * x and y must not overlap.  Stream-ordered, no host sync. */
+ls_status ls2_apply(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream);
+
+/* g = E^i - A E^i (FP64): the right-hand side of the equation for the
+ * scattered field when the incident field E^i is given (complex128
+ * [nrhs][2][n][n], device).  Stream-ordered. */
+ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev, int nrhs, void* hip_stream);
+
+/* Padded FFT length of the plan. */
+int ls2_plan_fft_size(const ls2_plan* plan);
+
+void ls2_plan_destroy(ls2_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS2D_H */

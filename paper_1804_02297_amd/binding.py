@@ -71,6 +71,12 @@ SIGNATURES = [
     ("ls_plan_set_form", _I, [_VP, _I, _VP]),
     ("ls_plan_tune", _I, [_VP, _I, _I, _VP, _VP]), ("ls_plan_set_tune", _I, [_VP, _I, _I, _I]),
     ("ls_plan_destroy", None, [_VP]),
+    # the 2-D variant
+    ("ls2_plan_create", _I, [_I, _D, _I, _VP, _VP, ctypes.POINTER(_VP)]),
+    ("ls2_apply", _I, [_VP, _VP, _VP, _I, _I, _VP]),
+    ("ls2_rhs_from_incident", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls2_plan_fft_size", _I, [_VP]),
+    ("ls2_plan_destroy", None, [_VP]),
 ]
 
 
@@ -445,4 +451,59 @@ class Plan:
             g = torch.empty_like(Ei)
         _check(_lib.ls_rhs_from_incident(self._h, _ptr(Ei), _ptr(g), Ei.shape[0], _stream()),
                "ls_rhs_from_incident")
+        return g
+
+
+def _field2(t, dtype, n, name):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous CUDA tensor of {dtype}")
+    if t.dim() != 4 or tuple(t.shape[1:]) != (2, n, n):
+        raise ValueError(f"{name}: shape must be (nrhs, 2, {n}, {n}), got {tuple(t.shape)}")
+    return t
+
+
+class Plan2:
+    """A plan of the 2-D variant: contrast, p, symbol and workspaces on the GPU."""
+
+    def __init__(self, n: int, k: float, m, max_rhs: int = 1):
+        import torch
+        lib = load()
+        if m.dtype != torch.complex128 or not m.is_cuda or tuple(m.shape) != (n, n):
+            raise ValueError("m must be a (n, n) complex128 CUDA tensor")
+        m = m.contiguous()
+        self.n, self.k, self.max_rhs = n, float(k), max_rhs
+        h = ctypes.c_void_p()
+        _check(lib.ls2_plan_create(n, float(k), max_rhs, _ptr(m), _stream(), ctypes.byref(h)), "ls2_plan_create")
+        self._h = h
+        self.P = lib.ls2_plan_fft_size(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ls2_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, x, y=None, prec: str = "c128"):
+        """y = A x; x complex128 (c128, mixed) or complex64 (c64), shape (nrhs, 2, n, n)."""
+        import torch
+        dt = torch.complex64 if prec == "c64" else torch.complex128
+        _field2(x, dt, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        _field2(y, dt, self.n, "y")
+        _check(_lib.ls2_apply(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream()), "ls2_apply")
+        return y
+
+    def rhs_from_incident(self, Ei, g=None):
+        import torch
+        _field2(Ei, torch.complex128, self.n, "Ei")
+        if g is None:
+            g = torch.empty_like(Ei)
+        _check(_lib.ls2_rhs_from_incident(self._h, _ptr(Ei), _ptr(g), Ei.shape[0], _stream()),
+               "ls2_rhs_from_incident")
         return g

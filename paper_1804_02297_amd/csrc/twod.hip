@@ -1,0 +1,538 @@
+// The 2-D variant: the scattered-field equation on the n x n grid of the
+// unit square with the 2-D Helmholtz kernel (Section 2 notes that the
+// equation holds in 2-D with that kernel; Section 3.3 gives its costs and
+// Section 4 its examples).  Two field components, the paper's own form:
+//
+//   y_d = x_d + k^2 G * (m x_d) + G^d * (p . x),   d = 1, 2,
+//
+// G(x) = (i/4) H_0^(1)(k|x|), G^d = dG/dx_d, weights h^2 G(x_i - x_j); the
+// self weight of G is its integral over the disc of area h^2, that of G^d is
+// 0; p^d = (central difference of m, zero off the grid) / (1 - m).
+//
+// Apply: three kernels over HBM, every FFT of length P (the padded length,
+// P >= 2n - 1, even, 2^a 3^b) held in LDS.
+//   pass A  rows:    u_f = (m x_1, m x_2, p.x) per row, zero-padded, FFT
+//                    along i2; [rhs][3][n][P] in HBM;
+//   pass B  columns: per block of CW adjacent columns, for every rhs: FFT of
+//                    the three fields along i1, the 2x3 symbol multiply in
+//                    registers, two inverse FFTs, rows i1 < n kept;
+//                    [rhs][2][n][P];
+//   pass C  rows:    inverse FFT along i2, the first n kept, + x.
+// The symbol (k^2 Ghat, Ghat^1, Ghat^2) / P^2 is stored on the quadrant
+// [H][H][3], H = P/2 + 1: k^2 Ghat is even in both frequencies, Ghat^1 is
+// odd in q1 and even in q2, Ghat^2 the reverse.
+#include "twod.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace ls {
+
+namespace {
+
+constexpr int kT2 = 256;                 // threads per workgroup of every 2-D kernel
+constexpr size_t kLds2 = 65536;          // LDS bytes a 2-D FFT workgroup may use
+
+// ---- FFT of runtime length P = 2^a 3^b in LDS (Stockham, radices 4, 2, 3) ----
+// The radices are packed two bits per stage (0: 4, 1: 2, 2: 3), first stage lowest.
+Radices factor_radices(int P) {
+  Radices r;
+  int m = P, st = 0;
+  auto push = [&](unsigned c) { r.code |= (unsigned long long)c << (2 * st); ++st; };
+  while (m % 4 == 0) { push(0); m /= 4; }
+  while (m % 2 == 0) { push(1); m /= 2; }
+  while (m % 3 == 0) { push(2); m /= 3; }
+  r.nst = (m == 1) ? st : -1;
+  return r;
+}
+
+template <typename R, int DIR, int RR>
+__device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* __restrict__ dst, int j, int Ns,
+                                           int NR, int tstep, int es, const C<R>* __restrict__ tw) {
+  const int k = j % Ns;
+  C<R> v[RR];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) v[r] = src[(j + r * NR) * es];
+#pragma unroll
+  for (int r = 1; r < RR; ++r) {
+    C<R> w = tw[r * k * tstep];
+    if (DIR > 0) w = cconj(w);
+    v[r] = v[r] * w;
+  }
+  Dft<RR, DIR, R>::run(v);
+  const int d0 = (j - k) * RR + k;
+#pragma unroll
+  for (int r = 0; r < RR; ++r) dst[(d0 + r * Ns) * es] = v[r];
+}
+
+// nb transforms of length P held in LDS: element e of transform t at
+// a[t * bs + e * es].  b is scratch of the same extent.  BFAST: consecutive
+// threads take consecutive transforms (columns), else consecutive elements.
+// Returns the buffer that holds the result.  Ends with a barrier.
+template <typename R, int DIR, bool BFAST>
+__device__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs,
+                         const C<R>* __restrict__ tw) {
+  int Ns = 1;
+  for (int st = 0; st < rd.nst; ++st) {
+    const unsigned code = (unsigned)(rd.code >> (2 * st)) & 3u;
+    const int RR = code == 0 ? 4 : (code == 1 ? 2 : 3);
+    const int NR = P / RR;
+    const int tstep = P / (RR * Ns);
+    const int total = nb * NR;
+    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+      const int t = BFAST ? w % nb : w / NR;
+      const int j = BFAST ? w / nb : w % NR;
+      const C<R>* s = a + t * bs;
+      C<R>* d = b + t * bs;
+      if (code == 0)
+        stage_bfly<R, DIR, 4>(s, d, j, Ns, NR, tstep, es, tw);
+      else if (code == 1)
+        stage_bfly<R, DIR, 2>(s, d, j, Ns, NR, tstep, es, tw);
+      else
+        stage_bfly<R, DIR, 3>(s, d, j, Ns, NR, tstep, es, tw);
+    }
+    __syncthreads();
+    C<R>* t = a;
+    a = b;
+    b = t;
+    Ns *= RR;
+  }
+  return a;
+}
+
+// Work index of a block: consecutive indices stay on one XCD (blocks are
+// dispatched round-robin over the 8 XCDs), so blocks that share rows or
+// symbol lines share that XCD's L2.
+__device__ __forceinline__ int xcd_work_index(int bid, int nblk) {
+  const int xcd = bid & 7, slot = bid >> 3;
+  const int q = nblk >> 3, r = nblk & 7;
+  return xcd * q + min(xcd, r) + slot;
+}
+
+// ---- weights and symbol (FP64, once per plan) ----
+__device__ void weights_at(int r1, int r2, double k, double h, C<double>* w) {
+  if (r1 == 0 && r2 == 0) {
+    const double a = h * 0.56418958354775628694807945156;   // h / sqrt(pi)
+    const double c = 1.5707963267948966192313216916398 * a / k;
+    // k^2 [(i pi a / (2k)) H_1(k a) - 1/k^2]
+    w[0] = cmk<double>((-c * y1(k * a) - 1.0 / (k * k)) * k * k, c * j1(k * a) * k * k);
+    w[1] = cmk<double>(0.0, 0.0);
+    w[2] = cmk<double>(0.0, 0.0);
+    return;
+  }
+  const double x1 = h * r1, x2 = h * r2;
+  const double R = sqrt(x1 * x1 + x2 * x2);
+  const double z = k * R, h2 = h * h;
+  // k^2 h^2 (i/4)(J0 + i Y0);  h^2 dG/dR x_d / R with dG/dR = (k/4)(Y1 - i J1)
+  w[0] = cmk<double>(-0.25 * y0(z) * h2 * k * k, 0.25 * j0(z) * h2 * k * k);
+  const double g1r = 0.25 * k * y1(z) * h2 / R, g1i = -0.25 * k * j1(z) * h2 / R;
+  w[1] = cmk<double>(g1r * x1, g1i * x1);
+  w[2] = cmk<double>(g1r * x2, g1i * x2);
+}
+
+// emb[c][s1][s2]: circulant embedding of (k^2 G, G^1, G^2) weights, offset r = s mod P.
+__global__ void embed_kernel(C<double>* __restrict__ emb, int n, int P, double k, double h) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)P * P) return;
+  const int s1 = (int)(idx / P), s2 = (int)(idx % P);
+  const int r1 = s1 <= n - 1 ? s1 : (s1 >= P - (n - 1) ? s1 - P : P);
+  const int r2 = s2 <= n - 1 ? s2 : (s2 >= P - (n - 1) ? s2 - P : P);
+  C<double> w[3] = {cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0)};
+  if (r1 != P && r2 != P) weights_at(r1, r2, k, h, w);
+  const long PP = (long)P * P;
+  for (int c = 0; c < 3; ++c) emb[c * PP + idx] = w[c];
+}
+
+// In-place FFT of `rows` contiguous rows of length P, nb rows per block.
+template <typename R, int DIR>
+__global__ __launch_bounds__(kT2) void fft_rows_kernel(C<R>* __restrict__ data, int rows, int P, Radices rd, int nb,
+                                                       const C<R>* __restrict__ tw) {
+  extern __shared__ unsigned char lds_raw[];
+  C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
+  C<R>* b = a + (size_t)nb * P;
+  const long r0 = (long)blockIdx.x * nb;
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const long r = r0 + e / P;
+    a[e] = r < rows ? data[r * P + e % P] : cmk<R>(0, 0);
+  }
+  __syncthreads();
+  C<R>* x = lds_fft<R, DIR, false>(a, b, P, rd, nb, 1, P, tw);
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const long r = r0 + e / P;
+    if (r < rows) data[r * P + e % P] = x[e];
+  }
+}
+
+// In-place FFT along the first index of planes [planes][P][P], nb columns per block.
+template <typename R, int DIR>
+__global__ __launch_bounds__(kT2) void fft_cols_kernel(C<R>* __restrict__ data, int P, Radices rd, int nb,
+                                                       const C<R>* __restrict__ tw) {
+  extern __shared__ unsigned char lds_raw[];
+  C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
+  C<R>* b = a + (size_t)nb * P;
+  const int ncb = P / nb;
+  const int plane = blockIdx.x / ncb, q0 = (blockIdx.x % ncb) * nb;
+  C<R>* base = data + (size_t)plane * P * P + q0;
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) a[e] = base[(size_t)(e / nb) * P + e % nb];
+  __syncthreads();
+  C<R>* x = lds_fft<R, DIR, true>(a, b, P, rd, nb, nb, 1, tw);
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) base[(size_t)(e / nb) * P + e % nb] = x[e];
+}
+
+// Quadrant of the transformed embedding / P^2: sym[a1][a2][c].
+__global__ void quadrant_kernel(const C<double>* __restrict__ emb, C<double>* __restrict__ s64,
+                                C<float>* __restrict__ s32, int P, int H) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)H * H) return;
+  const int a1 = (int)(idx / H), a2 = (int)(idx % H);
+  const double sc = 1.0 / ((double)P * P);
+  for (int c = 0; c < 3; ++c) {
+    const C<double> v = cscale(emb[(size_t)c * P * P + (size_t)a1 * P + a2], sc);
+    s64[idx * 3 + c] = v;
+    s32[idx * 3 + c] = ccast<float>(v);
+  }
+}
+
+// p^d = (central difference of m over 2h, m = 0 off the grid) / (1 - m), [2][n][n].
+__global__ void gradient_kernel(const C<double>* __restrict__ m, C<double>* __restrict__ p64,
+                                C<float>* __restrict__ p32, C<float>* __restrict__ m32, int n, double h) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nn = (long)n * n;
+  if (idx >= nn) return;
+  const int i1 = (int)(idx / n), i2 = (int)(idx % n);
+  const C<double> z = cmk(0.0, 0.0);
+  const C<double> e1 = i1 + 1 < n ? m[idx + n] : z, w1 = i1 > 0 ? m[idx - n] : z;
+  const C<double> e2 = i2 + 1 < n ? m[idx + 1] : z, w2 = i2 > 0 ? m[idx - 1] : z;
+  const C<double> one_m = cmk(1.0 - m[idx].re, -m[idx].im);
+  // 1 / (1 - m)
+  const double den = one_m.re * one_m.re + one_m.im * one_m.im;
+  const C<double> inv = cmk(one_m.re / den, -one_m.im / den);
+  const double s = 0.5 / h;
+  const C<double> p1 = cscale(e1 - w1, s) * inv, p2 = cscale(e2 - w2, s) * inv;
+  p64[idx] = p1;
+  p64[nn + idx] = p2;
+  p32[idx] = ccast<float>(p1);
+  p32[nn + idx] = ccast<float>(p2);
+  m32[idx] = ccast<float>(m[idx]);
+}
+
+// ---- the apply ----
+template <typename T>
+__device__ __forceinline__ C<T> ld_c(const void* p, long i) { return reinterpret_cast<const C<T>*>(p)[i]; }
+
+// pass A: block w -> (rhs b, row block rb, field f), f fastest.
+template <typename R, typename IO>
+__global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x, const C<R>* __restrict__ m,
+                                                      const C<R>* __restrict__ p, C<R>* __restrict__ T, int n, int P,
+                                                      Radices rd, int nb, int nrb, int nwork,
+                                                      const C<R>* __restrict__ tw) {
+  extern __shared__ unsigned char lds_raw[];
+  C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
+  C<R>* bb = a + (size_t)nb * P;
+  const int w = xcd_work_index(blockIdx.x, nwork);
+  const int f = w % 3, rb = (w / 3) % nrb, b = w / (3 * nrb);
+  const long nn = (long)n * n;
+  const long xb = (long)b * 2 * nn;
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const int t = e / P, j = e % P;
+    const int i1 = rb * nb + t;
+    C<R> v = cmk<R>(0, 0);
+    if (i1 < n && j < n) {
+      const long o = (long)i1 * n + j;
+      if (f < 2) {
+        v = m[o] * ccast<R>(ld_c<IO>(x, xb + f * nn + o));
+      } else {
+        v = p[o] * ccast<R>(ld_c<IO>(x, xb + o)) + p[nn + o] * ccast<R>(ld_c<IO>(x, xb + nn + o));
+      }
+    }
+    a[e] = v;
+  }
+  __syncthreads();
+  C<R>* X = lds_fft<R, -1, false>(a, bb, P, rd, nb, 1, P, tw);
+  C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const int i1 = rb * nb + e / P;
+    if (i1 < n) out[(size_t)i1 * P + e % P] = X[e];
+  }
+}
+
+// pass B: block -> column block (CW = nb adjacent columns); loops over the rhs.
+template <typename R, int EMAX>
+__global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T, C<R>* __restrict__ T2,
+                                                      const C<R>* __restrict__ sym, int n, int P, int H, Radices rd,
+                                                      int nb, int nrhs, const C<R>* __restrict__ tw) {
+  extern __shared__ unsigned char lds_raw[];
+  C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
+  C<R>* bb = a + (size_t)nb * P;
+  const int ncb = P / nb;
+  const int q0 = xcd_work_index(blockIdx.x, ncb) * nb;
+  const int tot = nb * P;
+  // symbol of the elements this thread owns: e = threadIdx.x + kT2 * u, q1 = e / nb, q2 = q0 + e % nb
+  C<R> s0[EMAX], s1[EMAX], s2[EMAX];
+#pragma unroll
+  for (int u = 0; u < EMAX; ++u) {
+    const int e = threadIdx.x + kT2 * u;
+    if (e < tot) {
+      const int q1 = e / nb, q2 = q0 + e % nb;
+      const bool f1 = q1 > P / 2, f2 = q2 > P / 2;
+      const int a1 = f1 ? P - q1 : q1, a2 = f2 ? P - q2 : q2;
+      const C<R>* sp = sym + ((size_t)a1 * H + a2) * 3;
+      s0[u] = sp[0];
+      s1[u] = f1 ? cmk<R>(-sp[1].re, -sp[1].im) : sp[1];
+      s2[u] = f2 ? cmk<R>(-sp[2].re, -sp[2].im) : sp[2];
+    }
+  }
+  for (int b = 0; b < nrhs; ++b) {
+    C<R> o0[EMAX], o1[EMAX];
+    for (int f = 0; f < 3; ++f) {
+      const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
+      for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i1 = e / nb;
+        a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
+      }
+      __syncthreads();
+      const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tw);
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        const int e = threadIdx.x + kT2 * u;
+        if (e < tot) {
+          const C<R> v = X[e];
+          if (f == 0) o0[u] = s0[u] * v;
+          else if (f == 1) o1[u] = s0[u] * v;
+          else {
+            o0[u] = cfma(s1[u], v, o0[u]);
+            o1[u] = cfma(s2[u], v, o1[u]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int d = 0; d < 2; ++d) {
+#pragma unroll
+      for (int u = 0; u < EMAX; ++u) {
+        const int e = threadIdx.x + kT2 * u;
+        if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
+      }
+      __syncthreads();
+      const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tw);
+      C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
+      for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int i1 = e / nb;
+        if (i1 < n) out[(size_t)i1 * P + e % nb] = X[e];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// pass C: block w -> (rhs b, component d, row block rb); y = x + v (or -v).
+template <typename R, typename IO>
+__global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2, const void* __restrict__ x,
+                                                      void* __restrict__ y, int n, int P, Radices rd, int nb, int nrb,
+                                                      int nwork, int minus_conv, const C<R>* __restrict__ tw) {
+  extern __shared__ unsigned char lds_raw[];
+  C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
+  C<R>* bb = a + (size_t)nb * P;
+  const int w = xcd_work_index(blockIdx.x, nwork);
+  const int rb = w % nrb, d = (w / nrb) % 2, b = w / (2 * nrb);
+  const C<R>* in = T2 + ((size_t)(b * 2 + d) * n) * P;
+  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+    const int i1 = rb * nb + e / P;
+    a[e] = i1 < n ? in[(size_t)i1 * P + e % P] : cmk<R>(0, 0);
+  }
+  __syncthreads();
+  const C<R>* X = lds_fft<R, 1, false>(a, bb, P, rd, nb, 1, P, tw);
+  const long nn = (long)n * n;
+  const long base = ((long)b * 2 + d) * nn;
+  C<IO>* yo = reinterpret_cast<C<IO>*>(y);
+  for (int e = threadIdx.x; e < nb * n; e += blockDim.x) {
+    const int t = e / n, j = e % n;
+    const int i1 = rb * nb + t;
+    if (i1 < n) {
+      const long o = base + (long)i1 * n + j;
+      const C<R> v = X[t * P + j];
+      C<IO> r;
+      if (minus_conv) {
+        r = cmk<IO>(-(IO)v.re, -(IO)v.im);
+      } else {
+        const C<IO> xv = ld_c<IO>(x, o);
+        r = cmk<IO>(xv.re + (IO)v.re, xv.im + (IO)v.im);
+      }
+      yo[o] = r;
+    }
+  }
+}
+
+template <typename R>
+int batch_for(int P) {
+  const size_t per = 2 * (size_t)P * sizeof(C<R>);
+  int nb = (int)std::max<size_t>(1, kLds2 / per);
+  nb = std::min(nb, 16);
+  // a power of two that divides P (the column blocks tile P exactly)
+  int b = 1;
+  while (b * 2 <= nb && P % (b * 2) == 0) b *= 2;
+  return b;
+}
+
+template <typename R>
+size_t lds_bytes(int P, int nb) { return 2 * (size_t)nb * P * sizeof(C<R>); }
+
+template <typename R, typename IO>
+ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s) {
+  const int n = pl.n, P = pl.P;
+  const C<R>* m = (const C<R>*)(std::is_same<R, double>::value ? pl.m64.p : pl.m32.p);
+  const C<R>* p = (const C<R>*)(std::is_same<R, double>::value ? pl.p64.p : pl.p32.p);
+  const C<R>* sym = (const C<R>*)(std::is_same<R, double>::value ? pl.sym64.p : pl.sym32.p);
+  const C<R>* tw = (const C<R>*)(std::is_same<R, double>::value ? pl.tw64.p : pl.tw32.p);
+  C<R>* T = pl.work.as<C<R>>();
+  C<R>* T2 = T + (size_t)pl.max_rhs * 3 * n * P;
+  const int nb = batch_for<R>(P);
+  const size_t lds = lds_bytes<R>(P, nb);
+  const int nrb = (n + nb - 1) / nb;
+  for (int r0 = 0; r0 < nrhs; r0 += pl.max_rhs) {
+    const int nr = std::min(pl.max_rhs, nrhs - r0);
+    const size_t off = (size_t)r0 * 2 * n * n * sizeof(C<IO>);
+    const void* xr = (const unsigned char*)x + off;
+    void* yr = (unsigned char*)y + off;
+    const int wa = nr * nrb * 3;
+    hipLaunchKernelGGL((pass_a_kernel<R, IO>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
+                       tw);
+    LS_HIP(hipGetLastError());
+    constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kT2);
+    hipLaunchKernelGGL((pass_b_kernel<R, EMAX>), dim3(P / nb), dim3(kT2), lds, s, T, T2, sym, n, P, pl.H, pl.rd,
+                       nb, nr, tw);
+    LS_HIP(hipGetLastError());
+    const int wc = nr * 2 * nrb;
+    hipLaunchKernelGGL((pass_c_kernel<R, IO>), dim3(wc), dim3(kT2), lds, s, T2, xr, yr, n, P, pl.rd, nb, nrb, wc,
+                       minus_conv ? 1 : 0, tw);
+    LS_HIP(hipGetLastError());
+  }
+  return LS_OK;
+}
+
+}  // namespace
+
+int fft_size_2d(int n) {
+  for (int P = 2 * n - 1; P <= 4096; ++P) {
+    if (P % 2) continue;
+    int m = P;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    if (m == 1) return P;
+  }
+  return 0;
+}
+
+ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev, hipStream_t s) {
+  if (n < 3 || !(k > 0.0) || max_rhs < 1 || !m_dev) return LS_EINVAL;
+  const int P = fft_size_2d(n);
+  if (P == 0 || P > kMaxP2) return LS_EINVAL;
+  pl.n = n;
+  pl.P = P;
+  pl.H = P / 2 + 1;
+  pl.k = k;
+  pl.h = 1.0 / (n + 1);
+  pl.max_rhs = max_rhs;
+  Radices rd = factor_radices(P);
+  if (rd.nst < 0) return LS_EINVAL;
+  pl.rd = rd;
+  const long nn = (long)n * n;
+  LS_TRY(pl.m64.alloc(nn * sizeof(C<double>)));
+  LS_TRY(pl.m32.alloc(nn * sizeof(C<float>)));
+  LS_TRY(pl.p64.alloc(2 * nn * sizeof(C<double>)));
+  LS_TRY(pl.p32.alloc(2 * nn * sizeof(C<float>)));
+  LS_TRY(pl.sym64.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<double>)));
+  LS_TRY(pl.sym32.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<float>)));
+  LS_TRY(pl.tw64.alloc(P * sizeof(C<double>)));
+  LS_TRY(pl.tw32.alloc(P * sizeof(C<float>)));
+  // workspace: three transformed fields and two products per rhs, in FP64 (FP32 uses half)
+  LS_TRY(pl.work.alloc((size_t)max_rhs * 5 * n * P * sizeof(C<double>)));
+  std::vector<C<double>> t64(P);
+  std::vector<C<float>> t32(P);
+  for (int t = 0; t < P; ++t) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / P;
+    t64[t] = cmk((double)cosl(ang), (double)sinl(ang));
+    t32[t] = cmk((float)cosl(ang), (float)sinl(ang));
+  }
+  LS_HIP(hipMemcpyAsync(pl.tw64.p, t64.data(), P * sizeof(C<double>), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(pl.tw32.p, t32.data(), P * sizeof(C<float>), hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(pl.m64.p, m_dev, nn * sizeof(C<double>), hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(gradient_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, pl.m64.as<C<double>>(),
+                     pl.p64.as<C<double>>(), pl.p32.as<C<float>>(), pl.m32.as<C<float>>(), n, pl.h);
+  LS_HIP(hipGetLastError());
+  // symbol: embed, FFT rows then columns of the three planes in FP64, keep the quadrant / P^2
+  DevBuf emb;
+  const size_t PP = (size_t)P * P;
+  LS_TRY(emb.alloc(3 * PP * sizeof(C<double>)));
+  hipLaunchKernelGGL(embed_kernel, dim3((unsigned)((PP + 255) / 256)), dim3(256), 0, s, emb.as<C<double>>(), n, P,
+                     k, pl.h);
+  LS_HIP(hipGetLastError());
+  const int nb = batch_for<double>(P);
+  const size_t lds = lds_bytes<double>(P, nb);
+  hipLaunchKernelGGL((fft_rows_kernel<double, -1>), dim3((unsigned)((3 * P + nb - 1) / nb)), dim3(kT2), lds, s,
+                     emb.as<C<double>>(), 3 * P, P, rd, nb, pl.tw64.as<C<double>>());
+  LS_HIP(hipGetLastError());
+  hipLaunchKernelGGL((fft_cols_kernel<double, -1>), dim3((unsigned)(3 * (P / nb))), dim3(kT2), lds, s,
+                     emb.as<C<double>>(), P, rd, nb, pl.tw64.as<C<double>>());
+  LS_HIP(hipGetLastError());
+  const long HH = (long)pl.H * pl.H;
+  hipLaunchKernelGGL(quadrant_kernel, dim3((unsigned)((HH + 255) / 256)), dim3(256), 0, s, emb.as<C<double>>(),
+                     pl.sym64.as<C<double>>(), pl.sym32.as<C<float>>(), P, pl.H);
+  LS_HIP(hipGetLastError());
+  LS_HIP(hipStreamSynchronize(s));   // emb is released on return
+  return LS_OK;
+}
+
+ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv) {
+  if (nrhs < 1 || !x || !y) return LS_EINVAL;
+  switch (prec) {
+    case LS_C128: return run_apply<double, double>(pl, x, y, nrhs, minus_conv, s);
+    case LS_C64: return run_apply<float, float>(pl, x, y, nrhs, minus_conv, s);
+    case LS_MIXED: return run_apply<float, double>(pl, x, y, nrhs, minus_conv, s);
+  }
+  return LS_EINVAL;
+}
+
+}  // namespace ls
+
+// ---- C ABI ----
+struct ls2_plan {
+  ls::Plan2 pl;
+};
+
+namespace ls {
+Plan2::~Plan2() {}
+}  // namespace ls
+
+extern "C" {
+
+ls_status ls2_plan_create(int n, double k, int max_rhs, const void* m_dev, void* hip_stream, ls2_plan** out) {
+  if (!out) return LS_EINVAL;
+  *out = nullptr;
+  ls2_plan* p = new (std::nothrow) ls2_plan;
+  if (!p) return LS_ENOMEM;
+  const ls_status st = ls::plan2_init(p->pl, n, k, max_rhs, m_dev, (hipStream_t)hip_stream);
+  if (st != LS_OK) {
+    delete p;
+    return st;
+  }
+  *out = p;
+  return LS_OK;
+}
+
+ls_status ls2_apply(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream) {
+  if (!plan) return LS_EINVAL;
+  return ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, (hipStream_t)hip_stream, false);
+}
+
+ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev, int nrhs, void* hip_stream) {
+  if (!plan) return LS_EINVAL;
+  return ls::plan2_apply(plan->pl, Ei_dev, g_dev, nrhs, LS_C128, (hipStream_t)hip_stream, true);
+}
+
+int ls2_plan_fft_size(const ls2_plan* plan) { return plan ? plan->pl.P : 0; }
+
+void ls2_plan_destroy(ls2_plan* plan) { delete plan; }
+
+}  // extern "C"

@@ -1,27 +1,31 @@
-"""The C-ABI library loads and exports every entry point that include/ls.h declares.
+"""The C-ABI library loads and exports every entry point that include/*.h declare.
 
 No compute call is made here (no GPU is needed); argument checks that fail
 before any device work are exercised as well.
 """
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ls.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ls_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ls2?_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for required in ["ls_plan_create", "ls_apply", "ls_plan_destroy", "ls_status_string"]:
+    for required in ["ls_plan_create", "ls_apply", "ls_plan_destroy", "ls_status_string",
+                     "ls2_plan_create", "ls2_apply", "ls2_plan_destroy"]:
         assert required in names
 
 

@@ -1,0 +1,82 @@
+"""The 2-D variant on the GPU against the oracle (paper form with the 2-D
+Helmholtz kernel, two components).
+
+Bar: complex128 to 1e-12 of the output's size, FP32 (complex64 and mixed) to
+2e-5 (FFT rounding of length-P transforms, P <= 2048: a few 1e-7 per
+transform, with the symbol's spread of magnitudes), element by element, on
+grids spanning radix-4/2/3 lengths and ragged row and column blocks.
+"""
+import numpy as np
+import pytest
+
+from oracle import two_d as o2
+from paper_1804_02297_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 9, 12, 17, 25, 40, 61])
+def test_apply_matches_oracle(lib, n):
+    from paper_1804_02297_amd.binding import Plan2
+    k = I.paper_wavenumber(n)
+    m = I.medium2_random_complex(n, 30 + n, scale=0.2)
+    x = I.random_field2(3, n, 300 + n)
+    print(f"n={n}", flush=True)
+    plan = Plan2(n, k, _dev(m), max_rhs=2)
+    assert plan.P == 2 * n if n in (3, 4, 9, 12) else plan.P >= 2 * n - 1
+    ref = o2.apply_fft2(n, k, m, x)
+    scale = np.abs(ref).max()
+    y = plan.apply(_dev(x), prec="c128").cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-12 * scale
+    y = plan.apply(_dev(x), prec="mixed").cpu().numpy()
+    assert np.abs(y - ref).max() <= 2e-5 * scale
+    y = plan.apply(_dev(x.astype(np.complex64)), prec="c64").cpu().numpy()
+    assert np.abs(y - ref).max() <= 2e-5 * scale
+    plan.close()
+
+
+def test_rhs_and_dense_definition(lib):
+    """The right-hand side, and the apply against the literal double sum."""
+    from paper_1804_02297_amd.binding import Plan2
+    n = 7
+    k = I.paper_wavenumber(n)
+    m = I.medium2_lens(n)
+    Ei = I.paper_incident2(n, k)
+    plan = Plan2(n, k, _dev(m))
+    g = plan.rhs_from_incident(_dev(Ei)).cpu().numpy()
+    gref = o2.rhs2(n, k, m, Ei)
+    assert np.abs(g - gref).max() <= 1e-12 * np.abs(gref).max()
+    x = I.random_field2(1, n, 5)
+    y = plan.apply(_dev(x)).cpu().numpy()[0]
+    ref = o2.apply_dense2(n, k, m, x[0])
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_full_size_sampled(lib):
+    """The paper's largest 2-D grid (n = 959, P = 1944): sampled outputs of the
+    complex128 apply against the oracle's double sum, one output at a time."""
+    from paper_1804_02297_amd.binding import Plan2
+    n = 959
+    k = I.paper_wavenumber(n)
+    m = I.medium2_perturbed_square(n, 4)
+    x = I.random_field2(2, n, 77)
+    plan = Plan2(n, k, _dev(m), max_rhs=2)
+    assert plan.P == 1944
+    y = plan.apply(_dev(x)).cpu().numpy()
+    yf = plan.apply(_dev(x), prec="mixed").cpu().numpy()
+    p = o2.gradient_p2(n, m)
+    u = np.concatenate([m[None] * x[:, :1], m[None] * x[:, 1:2], (p[0] * x[:, 0] + p[1] * x[:, 1])[:, None]], axis=1)
+    s = np.arange(n)
+    rng = np.random.default_rng(3)
+    for _ in range(6):
+        b, d, i1, i2 = rng.integers(2), rng.integers(2), rng.integers(n), rng.integers(n)
+        r = np.stack(np.meshgrid(i1 - s, i2 - s, indexing="ij"), axis=-1)
+        W = o2.weights_at(r, n, k)
+        ref = x[b, d, i1, i2] + k * k * np.sum(W[0] * u[b, d]) + np.sum(W[1 + d] * u[b, 2])
+        assert abs(y[b, d, i1, i2] - ref) <= 1e-11 * abs(ref), (b, d, i1, i2)
+        assert abs(yf[b, d, i1, i2] - ref) <= 1e-4 * abs(ref), (b, d, i1, i2)
