@@ -55,6 +55,49 @@ ls_status ls2_apply(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls
  * [nrhs][2][n][n], device).  Stream-ordered. */
 ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev, int nrhs, void* hip_stream);
 
+/* Class stencils on the GPU (Section 3.1, the optimisation for alpha and the
+ * formula for beta; Section 3.2 in two dimensions).  Per dimension a point
+ * is lo (i_d = 1), in or hi (i_d = n): 9 classes 3 c1 + c2 (4 = interior)
+ * with neighbourhood tau (tau_d = {0,1}, {-1,0,1}, {-1,0}; listed with the
+ * second offset fastest) and enlarged complement tau^c (offsets in
+ * {0..n-1}, {-(n-2)..n-2}, {-(n-1)..0} per dimension, minus the 3 x 3
+ * block about 0).  alpha holds the two eigenvectors with the smallest
+ * eigenvalues of the Gram matrix M M^H (= the two left singular vectors of
+ * M with the smallest singular values), M = [[k^2 G, 0, G^1], [0, k^2 G,
+ * G^2]] over tau x tau^c, rows (t, c) -> 2 t + c; beta = B^H alpha with B
+ * the same block over tau x tau, rows (t, f) -> 3 t + f (f = 2: the p.E
+ * column).  Every point i gets the two rows alpha^H E_tau + beta^H u_tau,
+ * u = (m E^1, m E^2, p.E), and Q = alpha^H.  The conjugate transpose is used
+ * for the paper's transpose.  Needs n >= 4 (LS_EINVAL).  Synchronises. */
+ls_status ls2_stencil_fit(ls2_plan* plan, void* hip_stream);
+
+/* The class stencils of ls2_stencil_fit, host arrays: alpha complex128
+ * [9][18][2], beta complex128 [9][27][2] (rows beyond the class's tau are
+ * 0), eig [9][18] the Gram eigenvalues ascending (0 past 2 |tau|).
+ * LS_ESTATE before a fit. */
+ls_status ls2_get_stencils(const ls2_plan* plan, void* alpha_host, void* beta_host, double* eig_host);
+
+/* Factor the sparse system S (rows of the fit) on host cores by nested
+ * dissection (Section 3.1 ends with the sparse system solved by nested
+ * dissection; Section 3.3 gives its 2-D cost O(N^{3/2})): line separators,
+ * dense fronts, partial pivoting inside each front's pivot block.
+ * factor_prec LS_C128 or LS_C64 (the factor kept in complex64).  The time
+ * taken is written to *seconds_out when not NULL.  LS_ESTATE before a fit. */
+ls_status ls2_factor(ls2_plan* plan, ls_prec factor_prec, double* seconds_out);
+
+/* z = S^-1 (Q v) for nrhs fields (device, complex128 [nrhs][2][n][n]; z may
+ * equal v): Q v on the GPU, S^-1 on host cores over PCIe.  LS_ESTATE before
+ * ls2_factor.  Synchronises. */
+ls_status ls2_precond_apply(ls2_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream);
+
+/* Right-preconditioned FGMRES for A x = g, as ls_gmres_solve (restart,
+ * maxit, tol on ||g - A x|| / ||g|| with the FP64 apply, x0 = 0, a lockstep
+ * block of nrhs right-hand sides; apply_prec LS_C128 or LS_MIXED).  g, x:
+ * device complex128 [nrhs][2][n][n]; info: host array of nrhs records.
+ * LS_ESTATE before ls2_factor, LS_ENOCONV when maxit is reached. */
+ls_status ls2_gmres_solve(ls2_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
+                          int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream);
+
 /* Padded FFT length of the plan. */
 int ls2_plan_fft_size(const ls2_plan* plan);
 

@@ -75,6 +75,11 @@ SIGNATURES = [
     ("ls2_plan_create", _I, [_I, _D, _I, _VP, _VP, ctypes.POINTER(_VP)]),
     ("ls2_apply", _I, [_VP, _VP, _VP, _I, _I, _VP]),
     ("ls2_rhs_from_incident", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls2_stencil_fit", _I, [_VP, _VP]),
+    ("ls2_get_stencils", _I, [_VP, _VP, _VP, _VP]),
+    ("ls2_factor", _I, [_VP, _I, ctypes.POINTER(ctypes.c_double)]),
+    ("ls2_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
+    ("ls2_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
     ("ls2_plan_fft_size", _I, [_VP]),
     ("ls2_plan_destroy", None, [_VP]),
 ]
@@ -507,3 +512,44 @@ class Plan2:
         _check(_lib.ls2_rhs_from_incident(self._h, _ptr(Ei), _ptr(g), Ei.shape[0], _stream()),
                "ls2_rhs_from_incident")
         return g
+
+    def stencil_fit(self):
+        _check(_lib.ls2_stencil_fit(self._h, _stream()), "ls2_stencil_fit")
+
+    def stencils(self):
+        """(alpha [9][18][2], beta [9][27][2], eig [9][18]) as numpy arrays."""
+        import numpy as np
+        a = np.zeros((9, 18, 2), dtype=np.complex128)
+        b = np.zeros((9, 27, 2), dtype=np.complex128)
+        e = np.zeros((9, 18), dtype=np.float64)
+        _check(_lib.ls2_get_stencils(self._h, a.ctypes.data_as(_VP), b.ctypes.data_as(_VP), e.ctypes.data_as(_VP)),
+               "ls2_get_stencils")
+        return a, b, e
+
+    def factor(self, prec: str = "c128") -> float:
+        t = ctypes.c_double()
+        _check(_lib.ls2_factor(self._h, PREC[prec], ctypes.byref(t)), "ls2_factor")
+        return t.value
+
+    def precond(self, v, z=None):
+        import torch
+        _field2(v, torch.complex128, self.n, "v")
+        if z is None:
+            z = torch.empty_like(v)
+        _check(_lib.ls2_precond_apply(self._h, _ptr(v), _ptr(z), v.shape[0], _stream()), "ls2_precond_apply")
+        return z
+
+    def solve(self, g, tol: float = 1e-8, restart: int = 30, maxit: int = 500, prec: str = "c128"):
+        """FGMRES; returns (x, [info dicts], status)."""
+        import torch
+        _field2(g, torch.complex128, self.n, "g")
+        x = torch.zeros_like(g)
+        nr = g.shape[0]
+        infos = (SolveInfo * nr)()
+        st = _lib.ls2_gmres_solve(self._h, _ptr(g), _ptr(x), nr, float(tol), restart, maxit, PREC[prec],
+                                  ctypes.cast(infos, _VP), _stream())
+        if st not in (0, -4):
+            _check(st, "ls2_gmres_solve")
+        out = [dict(iters=i.iters, restarts=i.restarts, rel_resid=i.rel_resid, t_gpu=i.t_gpu, t_host=i.t_host)
+               for i in infos]
+        return x, out, st

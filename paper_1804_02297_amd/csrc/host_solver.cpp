@@ -468,6 +468,9 @@ void partial_lu(R* Fr, R* Fi, long nf, long np, int* ipiv, double* flops) {
 
 struct HostSolver {
   int n = 0;
+  int dims[3] = {0, 0, 0};
+  int nc = 3;                  // unknowns per point
+  long npts = 0;
   bool fp32 = false;
   std::vector<Geom> geo;
   int root = -1;
@@ -495,24 +498,25 @@ void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::
   const Geom& nd = hs.geo[id];
   std::vector<Vals<R>>& V = vals_of<R>(hs);
   Vals<R>& v = V[id];
-  const int n = hs.n;
+  const int* dm = hs.dims;
+  const int nc = hs.nc;
   const long np = nd.np, nb = nd.nb, nf = np + nb;
   std::vector<R> Fr((size_t)nf * nf, R(0)), Fi((size_t)nf * nf, R(0));
   auto add_point_rows = [&](int pi, int li, bool pivot_row) {
-    const int i3 = pi % n, i2 = (pi / n) % n, i1 = pi / (n * n);
+    const int i3 = pi % dm[2], i2 = (pi / dm[2]) % dm[1], i1 = pi / (dm[1] * dm[2]);
     for (int s1 = -1; s1 <= 1; ++s1)
       for (int s2 = -1; s2 <= 1; ++s2)
         for (int s3 = -1; s3 <= 1; ++s3) {
           const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
-          if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n || j3 < 0 || j3 >= n) continue;
-          const int pj = (j1 * n + j2) * n + j3;
+          if (j1 < 0 || j1 >= dm[0] || j2 < 0 || j2 >= dm[1] || j3 < 0 || j3 >= dm[2]) continue;
+          const int pj = (j1 * dm[1] + j2) * dm[2] + j3;
           const int lj = pivot_row ? front_pos(nd, pj) : pos_in(nd.piv, pj);
           if (lj < 0) continue;
           const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
-          for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) {
-              const std::complex<double> val = rows[(size_t)pi * 243 + (r * 27 + slot) * 3 + c];
-              const size_t o = (size_t)(3 * li + r) * nf + (3 * lj + c);
+          for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < nc; ++c) {
+              const std::complex<double> val = rows[(size_t)pi * (nc * 27 * nc) + (r * 27 + slot) * nc + c];
+              const size_t o = (size_t)(nc * li + r) * nf + (nc * lj + c);
               Fr[o] += (R)val.real();
               Fi[o] += (R)val.imag();
             }
@@ -528,7 +532,7 @@ void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::
     std::vector<int> map(cg.nb);
     for (size_t a = 0; a < cg.bnd.size(); ++a) {
       const int fp = front_pos(nd, cg.bnd[a]);
-      for (int q = 0; q < 3; ++q) map[3 * a + q] = 3 * fp + q;
+      for (int q = 0; q < hs.nc; ++q) map[hs.nc * a + q] = hs.nc * fp + q;
     }
     for (int r = 0; r < cg.nb; ++r)
       for (int s = 0; s < cg.nb; ++s) {
@@ -656,10 +660,10 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr,
   std::vector<R> wr((size_t)nf * nrhs, R(0)), wi((size_t)nf * nrhs, R(0));   // [rhs][dof]
   for (int r = 0; r < nrhs; ++r)
     for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int q = 0; q < 3; ++q) {
-        const long g = 3L * nd.piv[a] + q;
-        wr[r * nf + 3 * a + q] = Br[r * ldb + g];
-        wi[r * nf + 3 * a + q] = Bi[r * ldb + g];
+      for (int q = 0; q < hs.nc; ++q) {
+        const long g = (long)hs.nc * nd.piv[a] + q;
+        wr[r * nf + hs.nc * a + q] = Br[r * ldb + g];
+        wi[r * nf + hs.nc * a + q] = Bi[r * ldb + g];
       }
   for (int c : nd.child) {
     if (c < 0) continue;
@@ -667,7 +671,7 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr,
     std::vector<int> map(ch.nb);
     for (size_t a = 0; a < ch.bnd.size(); ++a) {
       const int fp = front_pos(nd, ch.bnd[a]);
-      for (int q = 0; q < 3; ++q) map[3 * a + q] = 3 * fp + q;
+      for (int q = 0; q < hs.nc; ++q) map[hs.nc * a + q] = hs.nc * fp + q;
     }
     for (int r = 0; r < nrhs; ++r)
       for (int e = 0; e < ch.nb; ++e) {
@@ -692,10 +696,10 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr,
   }
   for (int r = 0; r < nrhs; ++r)
     for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int q = 0; q < 3; ++q) {
-        const long g = 3L * nd.piv[a] + q;
-        Zr[r * ldb + g] = wr[r * nf + 3 * a + q];
-        Zi[r * ldb + g] = wi[r * nf + 3 * a + q];
+      for (int q = 0; q < hs.nc; ++q) {
+        const long g = (long)hs.nc * nd.piv[a] + q;
+        Zr[r * ldb + g] = wr[r * nf + hs.nc * a + q];
+        Zi[r * ldb + g] = wi[r * nf + hs.nc * a + q];
       }
   W.ur[id].resize((size_t)nrhs * nb);
   W.ui[id].resize((size_t)nrhs * nb);
@@ -726,21 +730,21 @@ void bwd_node(HostSolver& hs, int id, int nrhs, R* Xr, R* Xi, long ldb) {
     R* Rr = Xr + r * ldb;
     R* Ri = Xi + r * ldb;
     for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int q = 0; q < 3; ++q) {
-        xr[3 * a + q] = Rr[3L * nd.piv[a] + q];
-        xi[3 * a + q] = Ri[3L * nd.piv[a] + q];
+      for (int q = 0; q < hs.nc; ++q) {
+        xr[hs.nc * a + q] = Rr[(long)hs.nc * nd.piv[a] + q];
+        xi[hs.nc * a + q] = Ri[(long)hs.nc * nd.piv[a] + q];
       }
     for (size_t a = 0; a < nd.bnd.size(); ++a)
-      for (int q = 0; q < 3; ++q) {
-        yr[3 * a + q] = Rr[3L * nd.bnd[a] + q];
-        yi[3 * a + q] = Ri[3L * nd.bnd[a] + q];
+      for (int q = 0; q < hs.nc; ++q) {
+        yr[hs.nc * a + q] = Rr[(long)hs.nc * nd.bnd[a] + q];
+        yi[hs.nc * a + q] = Ri[(long)hs.nc * nd.bnd[a] + q];
       }
     if (nb) gemv_sub(v.u12r.data(), v.u12i.data(), nb, np, nb, yr.data(), yi.data(), xr.data(), xi.data());
     upper_solve(v.l11r.data(), v.l11i.data(), np, xr.data(), xi.data());
     for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int q = 0; q < 3; ++q) {
-        Rr[3L * nd.piv[a] + q] = xr[3 * a + q];
-        Ri[3L * nd.piv[a] + q] = xi[3 * a + q];
+      for (int q = 0; q < hs.nc; ++q) {
+        Rr[(long)hs.nc * nd.piv[a] + q] = xr[hs.nc * a + q];
+        Ri[(long)hs.nc * nd.piv[a] + q] = xi[hs.nc * a + q];
       }
   }
 }
@@ -801,21 +805,21 @@ void fwd_node_multi(HostSolver& hs, int id, long ldx, const R* Br, const R* Bi, 
   const long np = nd.np, nb = nd.nb, nf = np + nb;
   std::vector<R> wr((size_t)nf * ldx, R(0)), wi((size_t)nf * ldx, R(0));
   for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      std::memcpy(&wr[(3 * a + q) * ldx], Br + g * ldx, ldx * sizeof(R));
-      std::memcpy(&wi[(3 * a + q) * ldx], Bi + g * ldx, ldx * sizeof(R));
+    for (int q = 0; q < hs.nc; ++q) {
+      const long g = (long)hs.nc * nd.piv[a] + q;
+      std::memcpy(&wr[(hs.nc * a + q) * ldx], Br + g * ldx, ldx * sizeof(R));
+      std::memcpy(&wi[(hs.nc * a + q) * ldx], Bi + g * ldx, ldx * sizeof(R));
     }
   for (int c : nd.child) {
     if (c < 0) continue;
     const Geom& ch = hs.geo[c];
     for (size_t a = 0; a < ch.bnd.size(); ++a) {
       const long fp = front_pos(nd, ch.bnd[a]);
-      for (int q = 0; q < 3; ++q) {
-        const R* ur = &W.ur[c][(3 * a + q) * ldx];
-        const R* ui = &W.ui[c][(3 * a + q) * ldx];
-        R* xr = &wr[(3 * fp + q) * ldx];
-        R* xi = &wi[(3 * fp + q) * ldx];
+      for (int q = 0; q < hs.nc; ++q) {
+        const R* ur = &W.ur[c][(hs.nc * a + q) * ldx];
+        const R* ui = &W.ui[c][(hs.nc * a + q) * ldx];
+        R* xr = &wr[(hs.nc * fp + q) * ldx];
+        R* xi = &wi[(hs.nc * fp + q) * ldx];
         for (long r = 0; r < ldx; ++r) {
           xr[r] += ur[r];
           xi[r] += ui[r];
@@ -838,10 +842,10 @@ void fwd_node_multi(HostSolver& hs, int id, long ldx, const R* Br, const R* Bi, 
     gemm_sub(v.l21r.data(), v.l21i.data(), np, nb, np, wr.data(), wi.data(), ldx, wr.data() + np * ldx,
              wi.data() + np * ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      std::memcpy(Zr + g * ldx, &wr[(3 * a + q) * ldx], ldx * sizeof(R));
-      std::memcpy(Zi + g * ldx, &wi[(3 * a + q) * ldx], ldx * sizeof(R));
+    for (int q = 0; q < hs.nc; ++q) {
+      const long g = (long)hs.nc * nd.piv[a] + q;
+      std::memcpy(Zr + g * ldx, &wr[(hs.nc * a + q) * ldx], ldx * sizeof(R));
+      std::memcpy(Zi + g * ldx, &wi[(hs.nc * a + q) * ldx], ldx * sizeof(R));
     }
   W.ur[id].assign(wr.begin() + np * ldx, wr.end());
   W.ui[id].assign(wi.begin() + np * ldx, wi.end());
@@ -865,24 +869,24 @@ void bwd_node_multi(HostSolver& hs, int id, long ldx, R* Xr, R* Xi) {
   const long np = nd.np, nb = nd.nb;
   std::vector<R> xr((size_t)np * ldx), xi((size_t)np * ldx), yr((size_t)nb * ldx), yi((size_t)nb * ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      std::memcpy(&xr[(3 * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
-      std::memcpy(&xi[(3 * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
+    for (int q = 0; q < hs.nc; ++q) {
+      const long g = (long)hs.nc * nd.piv[a] + q;
+      std::memcpy(&xr[(hs.nc * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
+      std::memcpy(&xi[(hs.nc * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
     }
   for (size_t a = 0; a < nd.bnd.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.bnd[a] + q;
-      std::memcpy(&yr[(3 * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
-      std::memcpy(&yi[(3 * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
+    for (int q = 0; q < hs.nc; ++q) {
+      const long g = (long)hs.nc * nd.bnd[a] + q;
+      std::memcpy(&yr[(hs.nc * a + q) * ldx], Xr + g * ldx, ldx * sizeof(R));
+      std::memcpy(&yi[(hs.nc * a + q) * ldx], Xi + g * ldx, ldx * sizeof(R));
     }
   if (nb) gemm_sub(v.u12r.data(), v.u12i.data(), nb, np, nb, yr.data(), yi.data(), ldx, xr.data(), xi.data());
   upper_solve_multi(v.l11r.data(), v.l11i.data(), np, xr.data(), xi.data(), ldx);
   for (size_t a = 0; a < nd.piv.size(); ++a)
-    for (int q = 0; q < 3; ++q) {
-      const long g = 3L * nd.piv[a] + q;
-      std::memcpy(Xr + g * ldx, &xr[(3 * a + q) * ldx], ldx * sizeof(R));
-      std::memcpy(Xi + g * ldx, &xi[(3 * a + q) * ldx], ldx * sizeof(R));
+    for (int q = 0; q < hs.nc; ++q) {
+      const long g = (long)hs.nc * nd.piv[a] + q;
+      std::memcpy(Xr + g * ldx, &xr[(hs.nc * a + q) * ldx], ldx * sizeof(R));
+      std::memcpy(Xi + g * ldx, &xi[(hs.nc * a + q) * ldx], ldx * sizeof(R));
     }
 }
 
@@ -904,8 +908,9 @@ constexpr int kMultiMin = 3;         // from this many right-hand sides on, the 
 
 template <typename R>
 void solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
-  const long n3 = (long)hs->n * hs->n * hs->n;
-  const long ldb = 3 * n3;
+  const long n3 = hs->npts;
+  const int nc = hs->nc;
+  const long ldb = nc * n3;
   for (int r0 = 0; r0 < nrhs; r0 += kMultiBlock) {
     const int nr = std::min(kMultiBlock, nrhs - r0);
     const long ldx = (nr + 3) / 4 * 4;
@@ -914,11 +919,11 @@ void solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
     std::complex<double>* bb = b + (size_t)r0 * ldb;
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < n3; ++p)
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < nc; ++c)
         for (int r = 0; r < nr; ++r) {
           const std::complex<double> v = bb[(size_t)r * ldb + c * n3 + p];
-          Br[(3 * p + c) * ldx + r] = (R)v.real();
-          Bi[(3 * p + c) * ldx + r] = (R)v.imag();
+          Br[(nc * p + c) * ldx + r] = (R)v.real();
+          Bi[(nc * p + c) * ldx + r] = (R)v.imag();
         }
     SolveWork<R> W;
     W.ur.resize(hs->geo.size());
@@ -937,24 +942,25 @@ void solve_multi(HostSolver* hs, std::complex<double>* b, int nrhs) {
 }
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < n3; ++p)
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < nc; ++c)
         for (int r = 0; r < nr; ++r)
           bb[(size_t)r * ldb + c * n3 + p] =
-              std::complex<double>(Zr[(3 * p + c) * ldx + r], Zi[(3 * p + c) * ldx + r]);
+              std::complex<double>(Zr[(nc * p + c) * ldx + r], Zi[(nc * p + c) * ldx + r]);
   }
 }
 
 template <typename R>
 void solve_single(HostSolver* hs, std::complex<double>* b, int nrhs) {
-  const long n3 = (long)hs->n * hs->n * hs->n;
-  const long ldb = 3 * n3;
+  const long n3 = hs->npts;
+  const int nc = hs->nc;
+  const long ldb = nc * n3;
   std::vector<R> Br((size_t)nrhs * ldb), Bi((size_t)nrhs * ldb);
   for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < nc; ++c)
       for (long p = 0; p < n3; ++p) {
         const std::complex<double> v = b[(size_t)r * ldb + c * n3 + p];
-        Br[r * ldb + 3 * p + c] = (R)v.real();
-        Bi[r * ldb + 3 * p + c] = (R)v.imag();
+        Br[r * ldb + nc * p + c] = (R)v.real();
+        Bi[r * ldb + nc * p + c] = (R)v.imag();
       }
   std::vector<R> Zr((size_t)nrhs * ldb, R(0)), Zi((size_t)nrhs * ldb, R(0));
   SolveWork<R> W;
@@ -973,20 +979,29 @@ void solve_single(HostSolver* hs, std::complex<double>* b, int nrhs) {
   bwd_rec<R>(*hs, hs->root, nrhs, Zr.data(), Zi.data(), ldb);
 }
   for (int r = 0; r < nrhs; ++r)
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < nc; ++c)
       for (long p = 0; p < n3; ++p)
-        b[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[r * ldb + 3 * p + c], Zi[r * ldb + 3 * p + c]);
+        b[(size_t)r * ldb + c * n3 + p] = std::complex<double>(Zr[r * ldb + nc * p + c], Zi[r * ldb + nc * p + c]);
 }
 
 }  // namespace
 
 ls_status host_factor(int n, const std::complex<double>* rows, size_t mem_cap, bool fp32, HostSolver** out) {
-  if (n < 1 || !rows || !out) return LS_EINVAL;
+  const int dims[3] = {n, n, n};
+  return host_factor_grid(dims, 3, rows, mem_cap, fp32, out);
+}
+
+ls_status host_factor_grid(const int dims[3], int nc, const std::complex<double>* rows, size_t mem_cap, bool fp32,
+                           HostSolver** out) {
+  if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || nc < 1 || nc > 3 || !rows || !out) return LS_EINVAL;
   std::unique_ptr<HostSolver> hs(new HostSolver());
-  hs->n = n;
+  hs->n = dims[0];
+  for (int d = 0; d < 3; ++d) hs->dims[d] = dims[d];
+  hs->nc = nc;
+  hs->npts = (long)dims[0] * dims[1] * dims[2];
   hs->fp32 = fp32;
   {
-    NdTree t = nd_build(n);
+    NdTree t = nd_build_grid(dims, nc);
     hs->geo = std::move(t.nodes);
     hs->root = t.root;
   }

@@ -8,7 +8,7 @@ namespace ls {
 namespace {
 
 int build(NdTree& t, const int lo[3], const int hi[3], int parent, int depth) {
-  const int n = t.n;
+  const int* dm = t.dims;
   NdNode nd;
   for (int d = 0; d < 3; ++d) {
     nd.lo[d] = lo[d];
@@ -28,16 +28,16 @@ int build(NdTree& t, const int lo[3], const int hi[3], int parent, int depth) {
     for (int b = lo[1]; b < hi[1]; ++b)
       for (int c = lo[2]; c < hi[2]; ++c) {
         const int q[3] = {a, b, c};
-        if (leaf || q[dsplit] == mid) nd.piv.push_back((a * n + b) * n + c);
+        if (leaf || q[dsplit] == mid) nd.piv.push_back((a * dm[1] + b) * dm[2] + c);
       }
-  for (int a = std::max(0, lo[0] - 1); a < std::min(n, hi[0] + 1); ++a)
-    for (int b = std::max(0, lo[1] - 1); b < std::min(n, hi[1] + 1); ++b)
-      for (int c = std::max(0, lo[2] - 1); c < std::min(n, hi[2] + 1); ++c) {
+  for (int a = std::max(0, lo[0] - 1); a < std::min(dm[0], hi[0] + 1); ++a)
+    for (int b = std::max(0, lo[1] - 1); b < std::min(dm[1], hi[1] + 1); ++b)
+      for (int c = std::max(0, lo[2] - 1); c < std::min(dm[2], hi[2] + 1); ++c) {
         const bool inside = a >= lo[0] && a < hi[0] && b >= lo[1] && b < hi[1] && c >= lo[2] && c < hi[2];
-        if (!inside) nd.bnd.push_back((a * n + b) * n + c);
+        if (!inside) nd.bnd.push_back((a * dm[1] + b) * dm[2] + c);
       }
-  nd.np = 3 * (int)nd.piv.size();
-  nd.nb = 3 * (int)nd.bnd.size();
+  nd.np = t.nc * (int)nd.piv.size();
+  nd.nb = t.nc * (int)nd.bnd.size();
   const int id = (int)t.nodes.size();
   t.nodes.push_back(std::move(nd));
   if (!leaf) {
@@ -56,12 +56,19 @@ int build(NdTree& t, const int lo[3], const int hi[3], int parent, int depth) {
 
 }  // namespace
 
-NdTree nd_build(int n) {
+NdTree nd_build_grid(const int dims[3], int nc) {
   NdTree t;
-  t.n = n;
-  const int lo[3] = {0, 0, 0}, hi[3] = {n, n, n};
-  t.root = build(t, lo, hi, -1, 0);
+  t.n = dims[0];
+  for (int d = 0; d < 3; ++d) t.dims[d] = dims[d];
+  t.nc = nc;
+  const int lo[3] = {0, 0, 0};
+  t.root = build(t, lo, dims, -1, 0);
   return t;
+}
+
+NdTree nd_build(int n) {
+  const int dims[3] = {n, n, n};
+  return nd_build_grid(dims, 3);
 }
 
 int nd_pos_in(const std::vector<int>& v, int p) {

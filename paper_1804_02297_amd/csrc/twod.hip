@@ -24,8 +24,15 @@
 #include "twod.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <functional>
+#include <new>
 #include <vector>
+
+#include "host_solver.h"
+
+#include <cstring>
 
 namespace ls {
 
@@ -33,6 +40,10 @@ namespace {
 
 constexpr int kT2 = 256;                 // threads per workgroup of every 2-D kernel
 constexpr size_t kLds2 = 65536;          // LDS bytes a 2-D FFT workgroup may use
+
+double wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // ---- FFT of runtime length P = 2^a 3^b in LDS (Stockham, radices 4, 2, 3) ----
 // The radices are packed two bits per stage (0: 4, 1: 2, 2: 3), first stage lowest.
@@ -364,6 +375,206 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
   }
 }
 
+
+// ---- stencils (Sections 3.1 and 3.2 in two dimensions) ----
+// Per dimension a point is lo (i_d = 1), in, or hi (i_d = n); class 3 c1 + c2
+// (4 = interior).  tau_d = {0, 1}, {-1, 0, 1}, {-1, 0}; the enlarged
+// complement ranges are {0 .. n-1}, {-(n-2) .. n-2}, {-(n-1) .. 0} minus
+// the 3 x 3 block about 0.  tau is listed with the second offset fastest;
+// Gram rows are (t, c) -> 2 t + c.
+__host__ __device__ inline int tau_lo(int c) { return c == 0 ? 0 : -1; }
+__host__ __device__ inline int tau_len(int c) { return c == 1 ? 3 : 2; }
+__host__ __device__ inline int rng_lo(int c, int n) { return c == 0 ? 0 : (c == 1 ? -(n - 2) : -(n - 1)); }
+__host__ __device__ inline int rng_len(int c, int n) { return c == 1 ? 2 * n - 3 : n; }
+__host__ __device__ inline int dim_class(int i, int n) { return i == 0 ? 0 : (i == n - 1 ? 2 : 1); }
+
+// W[f][r1 + n - 1][r2 + n - 1] = (k^2 G, G^1, G^2) weights, r in [-(n-1), n-1]^2
+__global__ void wtable_kernel(C<double>* __restrict__ W, int n, double k, double h) {
+  const int L = 2 * n - 1;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)L * L) return;
+  C<double> w[3];
+  weights_at((int)(idx / L) - (n - 1), (int)(idx % L) - (n - 1), k, h, w);
+  for (int f = 0; f < 3; ++f) W[(long)f * L * L + idx] = w[f];
+}
+
+constexpr int kGramCols = 128;          // complement columns staged in LDS per step
+constexpr int kGramBlocks = 256;        // workgroups per class
+
+// partial[kappa][block][rho][sigma] = sum over this block's columns j of
+//   delta_{c c'} k^2G(a - j) conj(k^2G(b - j)) + G^c(a - j) conj(G^c'(b - j)),  rho = 2 t_a + c
+__global__ __launch_bounds__(256) void gram2_kernel(const C<double>* __restrict__ W, C<double>* __restrict__ partial,
+                                                    int n) {
+  __shared__ C<double> V[9][3][kGramCols];
+  const int kappa = blockIdx.y, c1 = kappa / 3, c2 = kappa % 3;
+  const int T1 = tau_len(c1), T2 = tau_len(c2), T = T1 * T2, D = 2 * T;
+  const int L = 2 * n - 1;
+  const long LL = (long)L * L;
+  const int R1 = rng_len(c1, n), R2 = rng_len(c2, n), o1 = rng_lo(c1, n), o2 = rng_lo(c2, n);
+  const long ncols = (long)R1 * R2;
+  C<double> acc[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
+  for (long j0 = (long)blockIdx.x * kGramCols; j0 < ncols; j0 += (long)gridDim.x * kGramCols) {
+    for (int e = threadIdx.x; e < T * kGramCols; e += blockDim.x) {
+      const int t = e / kGramCols, col = e % kGramCols;
+      const long j = j0 + col;
+      C<double> v0 = cmk(0.0, 0.0), v1 = v0, v2 = v0;
+      if (j < ncols) {
+        const int jj1 = o1 + (int)(j / R2), jj2 = o2 + (int)(j % R2);
+        if (abs(jj1) > 1 || abs(jj2) > 1) {
+          const int a1 = tau_lo(c1) + t / T2, a2 = tau_lo(c2) + t % T2;
+          const long o = (long)(a1 - jj1 + n - 1) * L + (a2 - jj2 + n - 1);
+          v0 = W[o];
+          v1 = W[LL + o];
+          v2 = W[2 * LL + o];
+        }
+      }
+      V[t][0][col] = v0;
+      V[t][1][col] = v1;
+      V[t][2][col] = v2;
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < D * D) {
+        const int rho = e / D, sig = e % D;
+        const int ta = rho / 2, ca = rho % 2, tb = sig / 2, cb = sig % 2;
+        C<double> sum = acc[q];
+        for (int col = 0; col < kGramCols; ++col) {
+          if (ca == cb) sum = cfma(V[ta][0][col], cconj(V[tb][0][col]), sum);
+          sum = cfma(V[ta][1 + ca][col], cconj(V[tb][1 + cb][col]), sum);
+        }
+        acc[q] = sum;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < 324) partial[((size_t)kappa * gridDim.x + blockIdx.x) * 324 + e] = e < D * D ? acc[q] : cmk(0.0, 0.0);
+  }
+}
+
+// gram[kappa][e] = sum over blocks in order (a fixed order: the same result every run)
+__global__ void gram2_reduce_kernel(const C<double>* __restrict__ partial, C<double>* __restrict__ gram, int nblk) {
+  const int kappa = blockIdx.x, e = threadIdx.x;
+  if (e >= 324) return;
+  C<double> s = cmk(0.0, 0.0);
+  for (int b = 0; b < nblk; ++b) s = s + partial[((size_t)kappa * nblk + b) * 324 + e];
+  gram[kappa * 324 + e] = s;
+}
+
+// Rows of Q ([point][2 rows][9 slots][2 comps]) and of S in the 27-slot form of
+// the host factor ([point][2][27][2], slot 9 (s1+1) + 3 (s2+1) + 1):
+//   Q = conj(alpha[2t+c][r]),  S = Q + conj(beta[3t+c][r]) m_j + conj(beta[3t+2][r]) p^c_j,  j = i + tau[t]
+__global__ void rows2_kernel(const C<double>* __restrict__ alpha, const C<double>* __restrict__ beta,
+                             const C<double>* __restrict__ m, const C<double>* __restrict__ p,
+                             C<double>* __restrict__ Q, C<double>* __restrict__ S, int n) {
+  const long nn = (long)n * n;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const int i1 = (int)(idx / n), i2 = (int)(idx % n);
+  const int c1 = dim_class(i1, n), c2 = dim_class(i2, n), kappa = 3 * c1 + c2, T2 = tau_len(c2);
+  const C<double>* al = alpha + (size_t)kappa * 36;
+  const C<double>* be = beta + (size_t)kappa * 54;
+  C<double>* q = Q + idx * 36;
+  C<double>* sr = S + idx * 108;
+  for (int e = 0; e < 36; ++e) q[e] = cmk(0.0, 0.0);
+  for (int e = 0; e < 108; ++e) sr[e] = cmk(0.0, 0.0);
+  for (int s1 = -1; s1 <= 1; ++s1)
+    for (int s2 = -1; s2 <= 1; ++s2) {
+      const int t1 = s1 - tau_lo(c1), t2 = s2 - tau_lo(c2);
+      if (t1 < 0 || t1 >= tau_len(c1) || t2 < 0 || t2 >= T2) continue;
+      const int t = t1 * T2 + t2;
+      const long j = idx + (long)s1 * n + s2;
+      const int slot9 = 3 * (s1 + 1) + (s2 + 1), slot27 = 9 * (s1 + 1) + 3 * (s2 + 1) + 1;
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+          const C<double> qa = cconj(al[(2 * t + c) * 2 + r]);
+          const C<double> sv = qa + cconj(be[(3 * t + c) * 2 + r]) * m[j] + cconj(be[(3 * t + 2) * 2 + r]) * p[c * nn + j];
+          q[(r * 9 + slot9) * 2 + c] = qa;
+          sr[(r * 27 + slot27) * 2 + c] = sv;
+        }
+    }
+}
+
+// w = Q v for nrhs fields [rhs][2][n][n]
+__global__ void qapply2_kernel(const C<double>* __restrict__ Q, const C<double>* __restrict__ v,
+                               C<double>* __restrict__ w, int n, int nrhs) {
+  const long nn = (long)n * n;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn * nrhs) return;
+  const long b = idx / nn, i = idx % nn;
+  const int i1 = (int)(i / n), i2 = (int)(i % n);
+  const C<double>* q = Q + i * 36;
+  const C<double>* vb = v + b * 2 * nn;
+  C<double> acc[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
+  for (int s1 = -1; s1 <= 1; ++s1)
+    for (int s2 = -1; s2 <= 1; ++s2) {
+      const int j1 = i1 + s1, j2 = i2 + s2;
+      if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n) continue;
+      const long j = (long)j1 * n + j2;
+      const int slot = 3 * (s1 + 1) + (s2 + 1);
+      for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) acc[r] = cfma(q[(r * 9 + slot) * 2 + c], vb[c * nn + j], acc[r]);
+    }
+  w[b * 2 * nn + i] = acc[0];
+  w[b * 2 * nn + nn + i] = acc[1];
+}
+
+// Eigenvectors of a Hermitian matrix (row-major, dim D) by cyclic Jacobi rotations, ascending.
+void herm_eig(int D, std::vector<std::complex<double>> A, std::vector<double>& ev,
+              std::vector<std::complex<double>>& V) {
+  using cd = std::complex<double>;
+  V.assign((size_t)D * D, cd(0.0));
+  for (int i = 0; i < D; ++i) V[i * D + i] = 1.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        tot += std::norm(A[i * D + j]);
+        if (i != j) off += std::norm(A[i * D + j]);
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < D - 1; ++p)
+      for (int q = p + 1; q < D; ++q) {
+        const cd apq = A[p * D + q];
+        const double ab = std::abs(apq);
+        if (ab == 0.0) continue;
+        const double app = A[p * D + p].real(), aqq = A[q * D + q].real();
+        // rotate to zero A[p][q]: with e = apq / |apq|, a real Jacobi rotation on (p, q)
+        const cd e = apq / ab;
+        const double theta = 0.5 * std::atan2(2.0 * ab, aqq - app);
+        const double c = std::cos(theta), sn = std::sin(theta);
+        // columns: new_p = c col_p - s conj(e) col_q ; new_q = s e col_p + c col_q
+        for (int i = 0; i < D; ++i) {
+          const cd aip = A[i * D + p], aiq = A[i * D + q];
+          A[i * D + p] = c * aip - sn * std::conj(e) * aiq;
+          A[i * D + q] = sn * e * aip + c * aiq;
+        }
+        for (int j = 0; j < D; ++j) {
+          const cd apj = A[p * D + j], aqj = A[q * D + j];
+          A[p * D + j] = c * apj - sn * e * aqj;
+          A[q * D + j] = sn * std::conj(e) * apj + c * aqj;
+        }
+        for (int i = 0; i < D; ++i) {
+          const cd vip = V[i * D + p], viq = V[i * D + q];
+          V[i * D + p] = c * vip - sn * std::conj(e) * viq;
+          V[i * D + q] = sn * e * vip + c * viq;
+        }
+      }
+  }
+  std::vector<int> ord(D);
+  for (int i = 0; i < D; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return A[a * D + a].real() < A[b * D + b].real(); });
+  std::vector<cd> Vs((size_t)D * D);
+  ev.resize(D);
+  for (int k = 0; k < D; ++k) {
+    ev[k] = A[ord[k] * D + ord[k]].real();
+    for (int i = 0; i < D; ++i) Vs[i * D + k] = V[i * D + ord[k]];
+  }
+  V.swap(Vs);
+}
+
 template <typename R>
 int batch_for(int P) {
   const size_t per = 2 * (size_t)P * sizeof(C<R>);
@@ -484,6 +695,148 @@ ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev,
   return LS_OK;
 }
 
+
+ls_status plan2_fit(Plan2& pl, hipStream_t s) {
+  const int n = pl.n;
+  if (n < 4) return LS_EINVAL;   // the interior class needs a non-empty complement
+  const int L = 2 * n - 1;
+  const long LL = (long)L * L;
+  DevBuf W, partial, gram;
+  LS_TRY(W.alloc(3 * LL * sizeof(C<double>)));
+  LS_TRY(partial.alloc((size_t)9 * kGramBlocks * 324 * sizeof(C<double>)));
+  LS_TRY(gram.alloc((size_t)9 * 324 * sizeof(C<double>)));
+  hipLaunchKernelGGL(wtable_kernel, dim3((unsigned)((LL + 255) / 256)), dim3(256), 0, s, W.as<C<double>>(), n, pl.k,
+                     pl.h);
+  LS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram2_kernel, dim3(kGramBlocks, 9), dim3(256), 0, s, W.as<C<double>>(),
+                     partial.as<C<double>>(), n);
+  LS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gram2_reduce_kernel, dim3(9), dim3(324), 0, s, partial.as<C<double>>(), gram.as<C<double>>(),
+                     kGramBlocks);
+  LS_HIP(hipGetLastError());
+  using cd = std::complex<double>;
+  std::vector<cd> G(9 * 324), Wc(3 * 25);
+  LS_HIP(hipMemcpyAsync(G.data(), gram.p, G.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+  // the weights at offsets in [-2, 2]^2 (the local block B)
+  for (int f = 0; f < 3; ++f)
+    for (int d1 = -2; d1 <= 2; ++d1)
+      LS_HIP(hipMemcpyAsync(&Wc[(f * 5 + d1 + 2) * 5], W.as<C<double>>() + f * LL + (long)(d1 + n - 1) * L + (n - 3),
+                            5 * sizeof(cd), hipMemcpyDeviceToHost, s));
+  LS_HIP(hipStreamSynchronize(s));
+  auto wloc = [&](int f, int d1, int d2) { return Wc[(f * 5 + d1 + 2) * 5 + d2 + 2]; };
+  pl.alpha.assign(9 * 36, cd(0.0));
+  pl.beta.assign(9 * 54, cd(0.0));
+  pl.eig.assign(9 * 18, 0.0);
+  for (int kappa = 0; kappa < 9; ++kappa) {
+    const int c1 = kappa / 3, c2 = kappa % 3, T2 = tau_len(c2), T = tau_len(c1) * T2, D = 2 * T;
+    std::vector<cd> A((size_t)D * D);
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) A[i * D + j] = 0.5 * (G[kappa * 324 + i * D + j] + std::conj(G[kappa * 324 + j * D + i]));
+    std::vector<double> ev;
+    std::vector<cd> V;
+    herm_eig(D, A, ev, V);
+    for (int i = 0; i < D; ++i) pl.eig[kappa * 18 + i] = ev[i];
+    for (int i = 0; i < D; ++i)
+      for (int r = 0; r < 2; ++r) pl.alpha[kappa * 36 + i * 2 + r] = V[i * D + r];
+    // beta[(b, f)][r] = sum_{(a, c)} conj(B[(a, c)][(b, f)]) alpha[(a, c)][r],
+    // B[(a, c)][(b, f)] = delta_{f c} k^2 G(a - b) + delta_{f 2} G^c(a - b)
+    for (int tb = 0; tb < T; ++tb)
+      for (int f = 0; f < 3; ++f)
+        for (int r = 0; r < 2; ++r) {
+          cd acc = 0.0;
+          for (int ta = 0; ta < T; ++ta) {
+            const int d1 = ta / T2 - tb / T2, d2 = ta % T2 - tb % T2;
+            for (int c = 0; c < 2; ++c) {
+              cd B = 0.0;
+              if (f == c) B = wloc(0, d1, d2);
+              else if (f == 2) B = wloc(1 + c, d1, d2);
+              acc += std::conj(B) * pl.alpha[kappa * 36 + (2 * ta + c) * 2 + r];
+            }
+          }
+          pl.beta[kappa * 54 + (3 * tb + f) * 2 + r] = acc;
+        }
+  }
+  // rows
+  const long nn = (long)n * n;
+  DevBuf dal, dbe, Sdev;
+  LS_TRY(dal.alloc(pl.alpha.size() * sizeof(cd)));
+  LS_TRY(dbe.alloc(pl.beta.size() * sizeof(cd)));
+  LS_TRY(pl.qrows.alloc((size_t)nn * 36 * sizeof(cd)));
+  LS_TRY(Sdev.alloc((size_t)nn * 108 * sizeof(cd)));
+  LS_HIP(hipMemcpyAsync(dal.p, pl.alpha.data(), dal.bytes, hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(dbe.p, pl.beta.data(), dbe.bytes, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(rows2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, dal.as<C<double>>(),
+                     dbe.as<C<double>>(), pl.m64.as<C<double>>(), pl.p64.as<C<double>>(), pl.qrows.as<C<double>>(),
+                     Sdev.as<C<double>>(), n);
+  LS_HIP(hipGetLastError());
+  pl.srows.resize((size_t)nn * 108);
+  LS_HIP(hipMemcpyAsync(pl.srows.data(), Sdev.p, Sdev.bytes, hipMemcpyDeviceToHost, s));
+  LS_HIP(hipStreamSynchronize(s));
+  pl.fitted = true;
+  if (pl.hs) {
+    host_free(pl.hs);
+    pl.hs = nullptr;
+  }
+  return LS_OK;
+}
+
+ls_status plan2_factor(Plan2& pl, bool fp32) {
+  if (!pl.fitted) return LS_ESTATE;
+  if (pl.hs) {
+    host_free(pl.hs);
+    pl.hs = nullptr;
+  }
+  const int dims[3] = {pl.n, pl.n, 1};
+  return host_factor_grid(dims, 2, pl.srows.data(), 0, fp32, &pl.hs);
+}
+
+// z = S^-1 Q v for the listed fields (in place), S^-1 on host cores.
+ls_status plan2_precond(Plan2& pl, const std::vector<int>& lb, const std::function<C<double>*(int)>& ptr,
+                        hipStream_t s, double* t_host) {
+  if (!pl.hs) return LS_ESTATE;
+  const long len = 2L * pl.n * pl.n;
+  const size_t vb = (size_t)len * sizeof(C<double>);
+  const int nb = (int)lb.size();
+  if (pl.pbuf.bytes < vb) LS_TRY(pl.pbuf.alloc(vb));
+  std::vector<std::complex<double>> hb((size_t)nb * len);
+  const long nn = (long)pl.n * pl.n;
+  for (int q = 0; q < nb; ++q) {
+    hipLaunchKernelGGL(qapply2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                       pl.qrows.as<C<double>>(), ptr(lb[q]), pl.pbuf.as<C<double>>(), pl.n, 1);
+    LS_HIP(hipGetLastError());
+    LS_HIP(hipMemcpyAsync(hb.data() + (size_t)q * len, pl.pbuf.p, vb, hipMemcpyDeviceToHost, s));
+  }
+  LS_HIP(hipStreamSynchronize(s));
+  const double t0 = wall_seconds();
+  LS_TRY(host_solve(pl.hs, hb.data(), nb));
+  if (t_host) *t_host = wall_seconds() - t0;
+  for (int q = 0; q < nb; ++q)
+    LS_HIP(hipMemcpyAsync(ptr(lb[q]), hb.data() + (size_t)q * len, vb, hipMemcpyHostToDevice, s));
+  LS_HIP(hipStreamSynchronize(s));
+  return LS_OK;
+}
+
+ls_status plan2_solve(Plan2& pl, const void* g, void* x, int nrhs, double tol, int restart, int maxit, ls_prec prec,
+                      ls_solve_info* info, hipStream_t s) {
+  if (!g || !x || nrhs < 1 || !info || restart < 1 || maxit < 1 || !(tol > 0.0)) return LS_EINVAL;
+  if (prec != LS_C128 && prec != LS_MIXED) return LS_EINVAL;
+  if (!pl.hs) return LS_ESTATE;
+  pl.gctx.len = 2L * pl.n * pl.n;
+  GmresOps ops;
+  Plan2* P = &pl;
+  ops.apply = [P](const C<double>* xx, C<double>* yy, int nb, ls_prec pr, hipStream_t st) {
+    return plan2_apply(*P, xx, yy, nb, pr, st, false);
+  };
+  ops.precond_batch = [P](const std::vector<int>& lb, const std::function<C<double>*(int)>& ptr, hipStream_t st,
+                          double* th) { return plan2_precond(*P, lb, ptr, st, th); };
+  const double t0 = wall_seconds();
+  const ls_status st = gmres_solve(pl.gctx, ops, static_cast<const C<double>*>(g), static_cast<C<double>*>(x), nrhs,
+                                   tol, restart, maxit, prec, info, s);
+  const double tt = wall_seconds() - t0;
+  for (int b = 0; b < nrhs; ++b) info[b].t_gpu = tt / nrhs - info[b].t_host;
+  return st;
+}
+
 ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv) {
   if (nrhs < 1 || !x || !y) return LS_EINVAL;
   switch (prec) {
@@ -502,7 +855,9 @@ struct ls2_plan {
 };
 
 namespace ls {
-Plan2::~Plan2() {}
+Plan2::~Plan2() {
+  if (hs) host_free(hs);
+}
 }  // namespace ls
 
 extern "C" {
@@ -532,6 +887,47 @@ ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev,
 }
 
 int ls2_plan_fft_size(const ls2_plan* plan) { return plan ? plan->pl.P : 0; }
+
+ls_status ls2_stencil_fit(ls2_plan* plan, void* hip_stream) {
+  if (!plan) return LS_EINVAL;
+  return ls::plan2_fit(plan->pl, (hipStream_t)hip_stream);
+}
+
+ls_status ls2_get_stencils(const ls2_plan* plan, void* alpha_host, void* beta_host, double* eig_host) {
+  if (!plan || !alpha_host || !beta_host || !eig_host) return LS_EINVAL;
+  if (!plan->pl.fitted) return LS_ESTATE;
+  std::memcpy(alpha_host, plan->pl.alpha.data(), plan->pl.alpha.size() * sizeof(std::complex<double>));
+  std::memcpy(beta_host, plan->pl.beta.data(), plan->pl.beta.size() * sizeof(std::complex<double>));
+  std::memcpy(eig_host, plan->pl.eig.data(), plan->pl.eig.size() * sizeof(double));
+  return LS_OK;
+}
+
+ls_status ls2_factor(ls2_plan* plan, ls_prec factor_prec, double* seconds_out) {
+  if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
+  const double t0 = ls::wall_seconds();
+  const ls_status st = ls::plan2_factor(plan->pl, factor_prec == LS_C64);
+  if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
+  return st;
+}
+
+ls_status ls2_precond_apply(ls2_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream) {
+  if (!plan || !v_dev || !z_dev || nrhs < 1) return LS_EINVAL;
+  const long len = 2L * plan->pl.n * plan->pl.n;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (v_dev != z_dev)
+    LS_HIP(hipMemcpyAsync(z_dev, v_dev, (size_t)nrhs * len * sizeof(ls::C<double>), hipMemcpyDeviceToDevice, s));
+  std::vector<int> lb(nrhs);
+  for (int b = 0; b < nrhs; ++b) lb[b] = b;
+  ls::C<double>* z = static_cast<ls::C<double>*>(z_dev);
+  return ls::plan2_precond(plan->pl, lb, [&](int b) { return z + (long)b * len; }, s, nullptr);
+}
+
+ls_status ls2_gmres_solve(ls2_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
+                          int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream) {
+  if (!plan) return LS_EINVAL;
+  return ls::plan2_solve(plan->pl, g_dev, x_dev, nrhs, tol, restart, maxit, apply_prec, info,
+                         (hipStream_t)hip_stream);
+}
 
 void ls2_plan_destroy(ls2_plan* plan) { delete plan; }
 

@@ -80,3 +80,96 @@ def test_full_size_sampled(lib):
         ref = x[b, d, i1, i2] + k * k * np.sum(W[0] * u[b, d]) + np.sum(W[1 + d] * u[b, 2])
         assert abs(y[b, d, i1, i2] - ref) <= 1e-11 * abs(ref), (b, d, i1, i2)
         assert abs(yf[b, d, i1, i2] - ref) <= 1e-4 * abs(ref), (b, d, i1, i2)
+
+
+def _projector(a):
+    return a @ a.conj().T
+
+
+@pytest.mark.parametrize("n", [6, 13, 32])
+def test_class_stencils_match_oracle(lib, n):
+    """The two-dimensional subspace of alpha (alpha is fixed up to a 2 x 2
+    unitary factor, the two smallest eigenvalues being a near-degenerate
+    pair) and the Ky Fan value: projectors to 1e-9, eigenvalues to 1e-9 of
+    the largest."""
+    from paper_1804_02297_amd.binding import Plan2
+    k = I.paper_wavenumber(n)
+    m = I.medium2_lens(n)
+    plan = Plan2(n, k, _dev(m))
+    plan.stencil_fit()
+    a, b, e = plan.stencils()
+    print(f"n={n}", flush=True)
+    for kappa in range(9):
+        ao, bo, so = o2.fit_class2(kappa, n, k)
+        D = ao.shape[0]
+        assert np.abs(_projector(a[kappa, :D]) - _projector(ao)).max() <= 1e-9
+        assert np.abs(e[kappa, :2] - np.sort(so ** 2)[:2]).max() <= 1e-9 * so.max() ** 2
+        # beta = B^H alpha for the returned alpha
+        tau = o2.tau_offsets2(kappa)
+        B = o2.coupling_block2(tau, tau, n, k)
+        assert np.abs(b[kappa, :3 * len(tau)] - B.conj().T @ a[kappa, :D]).max() <= 1e-10 * np.abs(B).max()
+
+
+@pytest.mark.parametrize("n,prec,tol", [(12, "c128", 1e-10), (27, "c128", 1e-10), (27, "c64", 2e-4)])
+def test_preconditioner_matches_oracle(lib, n, prec, tol):
+    """z = S^-1 Q v is unique (independent of the unitary freedom in alpha):
+    element by element against the oracle's rows factored by SuperLU."""
+    import oracle.sparse as osp
+    from paper_1804_02297_amd.binding import Plan2
+    k = I.paper_wavenumber(n)
+    m = I.medium2_perturbed_square(n, 2)
+    plan = Plan2(n, k, _dev(m), max_rhs=2)
+    plan.stencil_fit()
+    plan.factor(prec)
+    v = I.random_field2(2, n, 11)
+    z = plan.precond(_dev(v)).cpu().numpy()
+    al, be, _ = o2.fit_all_classes2(n, k)
+    S, Q = o2.assemble2(n, m, al, be)
+    P = osp.Preconditioner(S, Q)
+    for r in range(2):
+        ref = P(v[r])
+        assert np.abs(z[r] - ref).max() <= tol * np.abs(ref).max(), r
+
+
+def test_solve_paper_square(lib):
+    """FGMRES with the sparsifying preconditioner on the analogue of the
+    paper's 2-D square obstacle at six points per wavelength; the residual
+    recomputed with the oracle's apply; the iteration count of the oracle's
+    own preconditioned GMRES (4 at this size)."""
+    from paper_1804_02297_amd.binding import Plan2
+    n = 39
+    k = I.paper_wavenumber(n)
+    m = I.medium2_square(n)
+    Ei = I.paper_incident2(n, k)
+    plan = Plan2(n, k, _dev(m))
+    plan.stencil_fit()
+    plan.factor("c128")
+    g = plan.rhs_from_incident(_dev(Ei))
+    x, info, st = plan.solve(g, tol=1e-6, restart=20)
+    assert st == 0, info
+    gh = o2.rhs2(n, k, m, Ei[0])
+    r = gh - o2.apply_fft2(n, k, m, x.cpu().numpy()[0])
+    rr = np.linalg.norm(r) / np.linalg.norm(gh)
+    print("2-D square: iterations", info[0]["iters"], "oracle residual", rr, flush=True)
+    assert rr <= 1e-6 and info[0]["iters"] <= 5
+    x2, info2, st2 = plan.solve(g, tol=1e-10, restart=20, prec="mixed")
+    assert st2 == 0
+    r = gh - o2.apply_fft2(n, k, m, x2.cpu().numpy()[0])
+    assert np.linalg.norm(r) / np.linalg.norm(gh) <= 1e-10
+
+
+def test_errors(lib):
+    from paper_1804_02297_amd.binding import LSError, Plan2
+    n = 3
+    plan = Plan2(n, 5.0, _dev(I.medium2_lens(n)))
+    with pytest.raises(LSError):
+        plan.stencil_fit()                        # n = 3: the interior complement is empty
+    n = 8
+    plan = Plan2(n, 5.0, _dev(I.medium2_lens(n)))
+    g = _dev(I.random_field2(1, n, 1))
+    with pytest.raises(LSError):
+        plan.factor()                             # before the fit
+    with pytest.raises(LSError):
+        plan.solve(g)                             # before the factor
+    with pytest.raises(ValueError):
+        plan.apply(_dev(I.random_field2(1, n + 1, 1)))
