@@ -275,6 +275,108 @@ def apply_192(binding, I, torch, steps: int, B: int = 8):
             "pass_GBps": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(pb, pms)]}
 
 
+def pass_bytes_2d(n: int, P: int, H: int, B: int, s: int, s_io: int) -> list[float]:
+    """Algorithmic HBM bytes of the three passes of the 2-D apply for B rhs:
+    intermediates of s bytes per complex, fields of s_io bytes per complex.
+    A: x, m, p read, the three row-transformed fields written ([B][3][n][P]);
+    B: those read, the symbol quadrant read once, two products written;
+    C: the products read, x read, y written."""
+    nn = n * n
+    a = B * 2 * nn * s_io + 3 * nn * s + B * 3 * n * P * s
+    b = B * 3 * n * P * s + 3 * H * H * s + B * 2 * n * P * s
+    c = B * 2 * n * P * s + 2 * B * 2 * nn * s_io
+    return [a, b, c]
+
+
+def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve_n: int = 479):
+    """The 2-D variant at the paper's largest 2-D grid (n = 959, P = 1944,
+    six points per wavelength): apply throughput, pass times and the
+    roofline of the dominant pass; and the paper's 2-D lens example solved
+    with its settings (class stencils, complex128 factor, GMRES(20) to 1e-6)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    k = I.paper_wavenumber(n)
+    m = torch.from_numpy(I.medium2_perturbed_square(n, 3)).to(dev)
+    plan = binding.Plan2(n, k, m, max_rhs=B)
+    P, H = plan.P, plan.P // 2 + 1
+    g = torch.Generator(device=dev).manual_seed(7)
+    x64 = torch.randn((B, 2, n, n), dtype=torch.complex128, device=dev, generator=g)
+    x32 = x64.to(torch.complex64)
+    y32, y64 = torch.empty_like(x32), torch.empty_like(x64)
+
+    def timed(prec, x, y, reps):
+        for _ in range(3):
+            plan.apply(x, y, prec=prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.apply(x, y, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(5, steps)
+    ms32 = timed("c64", x32, y32, reps)
+    ms64 = timed("c128", x64, y64, max(5, reps // 2))
+    msmx = timed("mixed", x64, y64, max(5, reps // 2))
+    pms = np.zeros(3)
+    for _ in range(10):
+        pms += np.array(plan.apply_timed(x32, y32, prec="c64"))
+    pms /= 10
+    pb = pass_bytes_2d(n, P, H, B, 8, 8)
+    dom = int(np.argmax(pms))
+    achieved = pb[dom] / (pms[dom] * 1e-3) / 1e9
+    unknowns = B * 2 * n * n
+    plan.close()
+    del x64, x32, y32, y64
+    torch.cuda.empty_cache()
+    out = {"workload": f"2-D apply, n={n} (P={P}), {B} rhs, FP32 FFTs", "n": n, "fft_size": P, "nrhs": B,
+           "Munknowns_per_s": round(unknowns / (ms32 * 1e-3) / 1e6, 1), "ms_per_apply": round(ms32, 4),
+           "c128_Munknowns_per_s": round(unknowns / (ms64 * 1e-3) / 1e6, 1),
+           "mixed_Munknowns_per_s": round(unknowns / (msmx * 1e-3) / 1e6, 1),
+           "pass_ms": [round(v, 4) for v in pms],
+           "pass_GBps": [round(b / (t * 1e-3) / 1e9, 1) for b, t in zip(pb, pms)],
+           "whole_GBps": round(sum(pb) / (ms32 * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "hbm", "kernel": ["pass_a_kernel", "pass_b_kernel", "pass_c_kernel"][dom],
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "algorithmic_bytes": round(pb[dom])}}
+    if solve_n:
+        import time
+        ks = I.paper_wavenumber(solve_n)
+        ms_ = torch.from_numpy(I.medium2_lens(solve_n)).to(dev)
+        plan = binding.Plan2(solve_n, ks, ms_, max_rhs=1)
+        gg = plan.rhs_from_incident(torch.from_numpy(I.paper_incident2(solve_n, ks)).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.stencil_fit()
+        t_fac = plan.factor("c128")
+        t_setup = time.perf_counter() - t0
+        v = torch.randn_like(gg)
+        z = torch.empty_like(gg)
+        plan.precond(v, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.precond(v, z)
+        torch.cuda.synchronize()
+        t_app = (time.perf_counter() - t0) / 3
+        plan.solve(gg, tol=1e-6, restart=20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, st = plan.solve(gg, tol=1e-6, restart=20)
+        torch.cuda.synchronize()
+        t_sol = time.perf_counter() - t0
+        plan.close()
+        out["paper_lens_solve"] = {"n": solve_n, "k_over_2pi": round(ks / (2 * math.pi), 3), "N": 2 * solve_n ** 2,
+                                   "T_setup": round(t_setup, 3), "T_factor": round(t_fac, 3),
+                                   "T_apply": round(t_app, 4), "N_iter": info[0]["iters"],
+                                   "T_solve": round(t_sol, 3), "rel_resid": info[0]["rel_resid"], "status": st}
+    return out
+
+
 def hbm_copy_gbps(torch, gib: float = 2.0) -> float:
     """Device-to-device copy bandwidth (read + write bytes / time) of a torch copy."""
     n = int(gib * (1 << 30)) // 4
@@ -306,6 +408,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
+    ap.add_argument("--two-d-n", type=int, default=959, help="grid of the 2-D variant's apply line (0: skip)")
+    ap.add_argument("--two-d-solve-n", type=int, default=479, help="grid of the 2-D lens solve (0: skip)")
     ap.add_argument("--solve-n", type=int, default=64, help="grid of the per-rhs solve section (0: skip)")
     ap.add_argument("--solve-dirs", type=int, default=32, help="incident directions (2 polarisations each)")
     ap.add_argument("--solve-exact", type=int, default=-1,
@@ -405,6 +509,9 @@ def main():
     }
     if args.n192:
         out["apply_192"] = apply_192(binding, I, torch, args.steps)
+    if args.two_d_n:
+        _progress("2-D variant")
+        out["two_d"] = two_d_section(binding, I, torch, args.steps, n=args.two_d_n, solve_n=args.two_d_solve_n)
     out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
     if args.solve_n:
         ex = (args.solve_n <= 48) if args.solve_exact < 0 else bool(args.solve_exact)

@@ -34,7 +34,7 @@ extern "C" {
 
 typedef struct ls2_plan ls2_plan;
 
-/* Create a plan for 3 <= n <= 1024 (padded FFT length P <= 2048, the
+/* Create a plan for 3 <= n <= 972 (padded FFT length P <= 1944, the
  * smallest even 2^a 3^b >= 2n - 1), wavenumber k > 0 and at most max_rhs
  * right-hand sides per internal launch set (any nrhs is accepted later).
  * Copies m (complex128 [n][n], device), computes p, samples the weights in
@@ -49,6 +49,14 @@ ls_status ls2_plan_create(int n, double k, int max_rhs, const void* m_dev, void*
  * [nrhs][2][n][n], complex128 for LS_C128 and LS_MIXED, complex64 for LS_C64;
  * x and y must not overlap.  Stream-ordered, no host sync. */
 ls_status ls2_apply(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream);
+
+/* ls2_apply for nrhs <= max_rhs, also returning the GPU time of each pass
+ * in pass_ms[0..2] (milliseconds; HIP events recorded on hip_stream between
+ * the launches): 0 row FFTs with the m and p scaling, 1 column FFTs + 2x3
+ * symbol multiply + inverse column FFTs, 2 inverse row FFTs with the
+ * identity term.  Synchronises.  For profiling and the roofline report. */
+ls_status ls2_apply_timed(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream,
+                          double* pass_ms);
 
 /* g = E^i - A E^i (FP64): the right-hand side of the equation for the
  * scattered field when the incident field E^i is given (complex128

@@ -74,6 +74,7 @@ SIGNATURES = [
     # the 2-D variant
     ("ls2_plan_create", _I, [_I, _D, _I, _VP, _VP, ctypes.POINTER(_VP)]),
     ("ls2_apply", _I, [_VP, _VP, _VP, _I, _I, _VP]),
+    ("ls2_apply_timed", _I, [_VP, _VP, _VP, _I, _I, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls2_rhs_from_incident", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls2_stencil_fit", _I, [_VP, _VP]),
     ("ls2_get_stencils", _I, [_VP, _VP, _VP, _VP]),
@@ -503,6 +504,17 @@ class Plan2:
         _field2(y, dt, self.n, "y")
         _check(_lib.ls2_apply(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream()), "ls2_apply")
         return y
+
+    def apply_timed(self, x, y, prec: str = "c128"):
+        """ls2_apply_timed: the three pass times in ms."""
+        import torch
+        dt = torch.complex64 if prec == "c64" else torch.complex128
+        _field2(x, dt, self.n, "x")
+        _field2(y, dt, self.n, "y")
+        ms = (ctypes.c_double * 3)()
+        _check(_lib.ls2_apply_timed(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream(), ms),
+               "ls2_apply_timed")
+        return list(ms)
 
     def rhs_from_incident(self, Ei, g=None):
         import torch

@@ -12,9 +12,9 @@ namespace ls {
 
 struct HostSolver;
 
-constexpr int kMaxP2 = 2048;       // largest padded FFT length of the 2-D apply (n <= 1024)
+constexpr int kMaxP2 = 1944;       // largest padded FFT length of the 2-D apply (n <= 972)
 
-struct Radices {                   // FFT stages: two bits each (0: radix 4, 1: 2, 2: 3)
+struct Radices {                   // FFT stages: three bits each (0: radix 4, 1: 2, 2: 3, 3: 8, 4: 9)
   unsigned long long code = 0;
   int nst = 0;
 };
@@ -43,6 +43,8 @@ struct Plan2 {
 
 int fft_size_2d(int n);
 ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev, hipStream_t s);
-ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv);
+// ev, when given, holds 4 events recorded around the three passes (nrhs <= max_rhs).
+ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv,
+                      hipEvent_t* ev = nullptr);
 
 }  // namespace ls

@@ -40,34 +40,60 @@ namespace {
 
 constexpr int kT2 = 256;                 // threads per workgroup of every 2-D kernel
 constexpr size_t kLds2 = 65536;          // LDS bytes a 2-D FFT workgroup may use
+constexpr size_t kLdsTarget = 32768;     // LDS bytes aimed for (five workgroups per CU)
 
 double wall_seconds() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// ---- FFT of runtime length P = 2^a 3^b in LDS (Stockham, radices 4, 2, 3) ----
-// The radices are packed two bits per stage (0: 4, 1: 2, 2: 3), first stage lowest.
+// ---- FFT of runtime length P = 2^a 3^b in LDS (Stockham, radices 8, 4, 2, 9, 3) ----
+// The radices are packed three bits per stage (0: 4, 1: 2, 2: 3, 3: 8, 4: 9),
+// first stage lowest.  Large radices first: fewer stages, fewer barriers.
 Radices factor_radices(int P) {
   Radices r;
   int m = P, st = 0;
-  auto push = [&](unsigned c) { r.code |= (unsigned long long)c << (2 * st); ++st; };
+  auto push = [&](unsigned c) { r.code |= (unsigned long long)c << (3 * st); ++st; };
+  while (m % 8 == 0) { push(3); m /= 8; }
   while (m % 4 == 0) { push(0); m /= 4; }
   while (m % 2 == 0) { push(1); m /= 2; }
+  while (m % 9 == 0) { push(4); m /= 9; }
   while (m % 3 == 0) { push(2); m /= 3; }
-  r.nst = (m == 1) ? st : -1;
+  r.nst = (m == 1 && st <= 21) ? st : -1;
   return r;
+}
+
+// Twiddles W^t = exp(-2 pi i t / P) from two short tables held in LDS:
+// W^t = hi[t / 64] lo[t % 64] (one extra rounding against a full table).
+constexpr int kTwLo = 64;
+template <typename R>
+struct Tw {
+  const C<R>* lo;   // W^t, t < 64
+  const C<R>* hi;   // W^(64 t), t < P / 64 + 1
+  __device__ __forceinline__ C<R> operator()(int t) const { return hi[t >> 6] * lo[t & (kTwLo - 1)]; }
+};
+__host__ __device__ constexpr int tw_entries(int P) { return kTwLo + P / kTwLo + 1; }
+
+// Fill the two twiddle tables (lo then hi) at t[0 .. tw_entries(P)) from the full table tw_g.
+template <typename R>
+__device__ Tw<R> load_twiddles(C<R>* t, const C<R>* __restrict__ tw_g, int P) {
+  const int nhi = P / kTwLo + 1;
+  for (int e = threadIdx.x; e < kTwLo + nhi; e += blockDim.x) {
+    const long idx = e < kTwLo ? e : (long)(e - kTwLo) * kTwLo;
+    t[e] = tw_g[idx % P];
+  }
+  return Tw<R>{t, t + kTwLo};
 }
 
 template <typename R, int DIR, int RR>
 __device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* __restrict__ dst, int j, int Ns,
-                                           int NR, int tstep, int es, const C<R>* __restrict__ tw) {
+                                           int NR, int tstep, int es, const Tw<R>& tw) {
   const int k = j % Ns;
   C<R> v[RR];
 #pragma unroll
   for (int r = 0; r < RR; ++r) v[r] = src[(j + r * NR) * es];
 #pragma unroll
   for (int r = 1; r < RR; ++r) {
-    C<R> w = tw[r * k * tstep];
+    C<R> w = tw(r * k * tstep);
     if (DIR > 0) w = cconj(w);
     v[r] = v[r] * w;
   }
@@ -82,12 +108,11 @@ __device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* _
 // threads take consecutive transforms (columns), else consecutive elements.
 // Returns the buffer that holds the result.  Ends with a barrier.
 template <typename R, int DIR, bool BFAST>
-__device__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs,
-                         const C<R>* __restrict__ tw) {
+__device__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs, const Tw<R>& tw) {
   int Ns = 1;
   for (int st = 0; st < rd.nst; ++st) {
-    const unsigned code = (unsigned)(rd.code >> (2 * st)) & 3u;
-    const int RR = code == 0 ? 4 : (code == 1 ? 2 : 3);
+    const unsigned code = (unsigned)(rd.code >> (3 * st)) & 7u;
+    const int RR = code == 0 ? 4 : (code == 1 ? 2 : (code == 2 ? 3 : (code == 3 ? 8 : 9)));
     const int NR = P / RR;
     const int tstep = P / (RR * Ns);
     const int total = nb * NR;
@@ -96,12 +121,13 @@ __device__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, in
       const int j = BFAST ? w / nb : w % NR;
       const C<R>* s = a + t * bs;
       C<R>* d = b + t * bs;
-      if (code == 0)
-        stage_bfly<R, DIR, 4>(s, d, j, Ns, NR, tstep, es, tw);
-      else if (code == 1)
-        stage_bfly<R, DIR, 2>(s, d, j, Ns, NR, tstep, es, tw);
-      else
-        stage_bfly<R, DIR, 3>(s, d, j, Ns, NR, tstep, es, tw);
+      switch (code) {
+        case 0: stage_bfly<R, DIR, 4>(s, d, j, Ns, NR, tstep, es, tw); break;
+        case 1: stage_bfly<R, DIR, 2>(s, d, j, Ns, NR, tstep, es, tw); break;
+        case 2: stage_bfly<R, DIR, 3>(s, d, j, Ns, NR, tstep, es, tw); break;
+        case 3: stage_bfly<R, DIR, 8>(s, d, j, Ns, NR, tstep, es, tw); break;
+        default: stage_bfly<R, DIR, 9>(s, d, j, Ns, NR, tstep, es, tw); break;
+      }
     }
     __syncthreads();
     C<R>* t = a;
@@ -162,13 +188,14 @@ __global__ __launch_bounds__(kT2) void fft_rows_kernel(C<R>* __restrict__ data, 
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* b = a + (size_t)nb * P;
+  const Tw<R> tws = load_twiddles(b + (size_t)nb * P, tw, P);
   const long r0 = (long)blockIdx.x * nb;
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
     const long r = r0 + e / P;
     a[e] = r < rows ? data[r * P + e % P] : cmk<R>(0, 0);
   }
   __syncthreads();
-  C<R>* x = lds_fft<R, DIR, false>(a, b, P, rd, nb, 1, P, tw);
+  C<R>* x = lds_fft<R, DIR, false>(a, b, P, rd, nb, 1, P, tws);
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
     const long r = r0 + e / P;
     if (r < rows) data[r * P + e % P] = x[e];
@@ -182,12 +209,13 @@ __global__ __launch_bounds__(kT2) void fft_cols_kernel(C<R>* __restrict__ data, 
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* b = a + (size_t)nb * P;
+  const Tw<R> tws = load_twiddles(b + (size_t)nb * P, tw, P);
   const int ncb = P / nb;
   const int plane = blockIdx.x / ncb, q0 = (blockIdx.x % ncb) * nb;
   C<R>* base = data + (size_t)plane * P * P + q0;
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) a[e] = base[(size_t)(e / nb) * P + e % nb];
   __syncthreads();
-  C<R>* x = lds_fft<R, DIR, true>(a, b, P, rd, nb, nb, 1, tw);
+  C<R>* x = lds_fft<R, DIR, true>(a, b, P, rd, nb, nb, 1, tws);
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) base[(size_t)(e / nb) * P + e % nb] = x[e];
 }
 
@@ -241,6 +269,7 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
+  const Tw<R> tws = load_twiddles(bb + (size_t)nb * P, tw, P);
   const int w = xcd_work_index(blockIdx.x, nwork);
   const int f = w % 3, rb = (w / 3) % nrb, b = w / (3 * nrb);
   const long nn = (long)n * n;
@@ -260,7 +289,7 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
     a[e] = v;
   }
   __syncthreads();
-  C<R>* X = lds_fft<R, -1, false>(a, bb, P, rd, nb, 1, P, tw);
+  C<R>* X = lds_fft<R, -1, false>(a, bb, P, rd, nb, 1, P, tws);
   C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
   for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
     const int i1 = rb * nb + e / P;
@@ -276,8 +305,12 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
+  const Tw<R> tws = load_twiddles(bb + (size_t)nb * P, tw, P);
   const int ncb = P / nb;
-  const int q0 = xcd_work_index(blockIdx.x, ncb) * nb;
+  // block -> (rhs, column block), column blocks of one rhs adjacent on an XCD
+  const int w = xcd_work_index(blockIdx.x, ncb * nrhs);
+  const int b = w / ncb;
+  const int q0 = (w % ncb) * nb;
   const int tot = nb * P;
   // symbol of the elements this thread owns: e = threadIdx.x + kT2 * u, q1 = e / nb, q2 = q0 + e % nb
   C<R> s0[EMAX], s1[EMAX], s2[EMAX];
@@ -294,7 +327,7 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
       s2[u] = f2 ? cmk<R>(-sp[2].re, -sp[2].im) : sp[2];
     }
   }
-  for (int b = 0; b < nrhs; ++b) {
+  {
     C<R> o0[EMAX], o1[EMAX];
     for (int f = 0; f < 3; ++f) {
       const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
@@ -303,7 +336,7 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
         a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
       }
       __syncthreads();
-      const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tw);
+      const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tws);
 #pragma unroll
       for (int u = 0; u < EMAX; ++u) {
         const int e = threadIdx.x + kT2 * u;
@@ -326,7 +359,7 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
         if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
       }
       __syncthreads();
-      const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tw);
+      const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tws);
       C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
       for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int i1 = e / nb;
@@ -345,6 +378,7 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
+  const Tw<R> tws = load_twiddles(bb + (size_t)nb * P, tw, P);
   const int w = xcd_work_index(blockIdx.x, nwork);
   const int rb = w % nrb, d = (w / nrb) % 2, b = w / (2 * nrb);
   const C<R>* in = T2 + ((size_t)(b * 2 + d) * n) * P;
@@ -353,7 +387,7 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
     a[e] = i1 < n ? in[(size_t)i1 * P + e % P] : cmk<R>(0, 0);
   }
   __syncthreads();
-  const C<R>* X = lds_fft<R, 1, false>(a, bb, P, rd, nb, 1, P, tw);
+  const C<R>* X = lds_fft<R, 1, false>(a, bb, P, rd, nb, 1, P, tws);
   const long nn = (long)n * n;
   const long base = ((long)b * 2 + d) * nn;
   C<IO>* yo = reinterpret_cast<C<IO>*>(y);
@@ -576,9 +610,9 @@ void herm_eig(int D, std::vector<std::complex<double>> A, std::vector<double>& e
 }
 
 template <typename R>
-int batch_for(int P) {
+int batch_for(int P, size_t budget = kLdsTarget) {
   const size_t per = 2 * (size_t)P * sizeof(C<R>);
-  int nb = (int)std::max<size_t>(1, kLds2 / per);
+  int nb = (int)std::max<size_t>(1, (budget - tw_entries(kMaxP2) * sizeof(C<R>)) / per);
   nb = std::min(nb, 16);
   // a power of two that divides P (the column blocks tile P exactly)
   int b = 1;
@@ -587,10 +621,11 @@ int batch_for(int P) {
 }
 
 template <typename R>
-size_t lds_bytes(int P, int nb) { return 2 * (size_t)nb * P * sizeof(C<R>); }
+size_t lds_bytes(int P, int nb) { return (2 * (size_t)nb * P + tw_entries(P)) * sizeof(C<R>); }
 
 template <typename R, typename IO>
-ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s) {
+ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s,
+                    hipEvent_t* ev = nullptr) {
   const int n = pl.n, P = pl.P;
   const C<R>* m = (const C<R>*)(std::is_same<R, double>::value ? pl.m64.p : pl.m32.p);
   const C<R>* p = (const C<R>*)(std::is_same<R, double>::value ? pl.p64.p : pl.p32.p);
@@ -601,23 +636,30 @@ ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv
   const int nb = batch_for<R>(P);
   const size_t lds = lds_bytes<R>(P, nb);
   const int nrb = (n + nb - 1) / nb;
+  // column pass: more adjacent columns per block (wider row segments per load)
+  const int nbc = batch_for<R>(P, kLds2);
+  const size_t ldsc = lds_bytes<R>(P, nbc);
   for (int r0 = 0; r0 < nrhs; r0 += pl.max_rhs) {
     const int nr = std::min(pl.max_rhs, nrhs - r0);
     const size_t off = (size_t)r0 * 2 * n * n * sizeof(C<IO>);
     const void* xr = (const unsigned char*)x + off;
     void* yr = (unsigned char*)y + off;
     const int wa = nr * nrb * 3;
+    if (ev) LS_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL((pass_a_kernel<R, IO>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
                        tw);
     LS_HIP(hipGetLastError());
     constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kT2);
-    hipLaunchKernelGGL((pass_b_kernel<R, EMAX>), dim3(P / nb), dim3(kT2), lds, s, T, T2, sym, n, P, pl.H, pl.rd,
-                       nb, nr, tw);
+    if (ev) LS_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL((pass_b_kernel<R, EMAX>), dim3((P / nbc) * nr), dim3(kT2), ldsc, s, T, T2, sym, n, P, pl.H,
+                       pl.rd, nbc, nr, tw);
     LS_HIP(hipGetLastError());
     const int wc = nr * 2 * nrb;
+    if (ev) LS_HIP(hipEventRecord(ev[2], s));
     hipLaunchKernelGGL((pass_c_kernel<R, IO>), dim3(wc), dim3(kT2), lds, s, T2, xr, yr, n, P, pl.rd, nb, nrb, wc,
                        minus_conv ? 1 : 0, tw);
     LS_HIP(hipGetLastError());
+    if (ev) LS_HIP(hipEventRecord(ev[3], s));
   }
   return LS_OK;
 }
@@ -837,12 +879,13 @@ ls_status plan2_solve(Plan2& pl, const void* g, void* x, int nrhs, double tol, i
   return st;
 }
 
-ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv) {
+ls_status plan2_apply(Plan2& pl, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s, bool minus_conv,
+                      hipEvent_t* ev) {
   if (nrhs < 1 || !x || !y) return LS_EINVAL;
   switch (prec) {
-    case LS_C128: return run_apply<double, double>(pl, x, y, nrhs, minus_conv, s);
-    case LS_C64: return run_apply<float, float>(pl, x, y, nrhs, minus_conv, s);
-    case LS_MIXED: return run_apply<float, double>(pl, x, y, nrhs, minus_conv, s);
+    case LS_C128: return run_apply<double, double>(pl, x, y, nrhs, minus_conv, s, ev);
+    case LS_C64: return run_apply<float, float>(pl, x, y, nrhs, minus_conv, s, ev);
+    case LS_MIXED: return run_apply<float, double>(pl, x, y, nrhs, minus_conv, s, ev);
   }
   return LS_EINVAL;
 }
@@ -887,6 +930,27 @@ ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev,
 }
 
 int ls2_plan_fft_size(const ls2_plan* plan) { return plan ? plan->pl.P : 0; }
+
+ls_status ls2_apply_timed(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream,
+                          double* pass_ms) {
+  if (!plan || !pass_ms || nrhs > plan->pl.max_rhs) return LS_EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      return LS_EHIP;
+    }
+  ls_status st = ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, s, false, ev);
+  if (st == LS_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = LS_EHIP;
+  for (int i = 0; i < 3 && st == LS_OK; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = LS_EHIP;
+    pass_ms[i] = ms;
+  }
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  return st;
+}
 
 ls_status ls2_stencil_fit(ls2_plan* plan, void* hip_stream) {
   if (!plan) return LS_EINVAL;

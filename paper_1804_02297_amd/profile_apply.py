@@ -1,9 +1,11 @@
 """Driver for rocprofv3 runs of the Nystrom apply (kernel trace and HBM counters).
 
     python -m paper_1804_02297_amd.profile_apply --n 128 --nrhs 8 --prec c64 --reps 5
+    python -m paper_1804_02297_amd.profile_apply --dim 2 --n 959 --nrhs 8 --prec c64 --reps 5
 
 Runs `reps` applies of the benchmark workload (seeded sum-of-Gaussians
-contrast, random fields) and then `reps` plain device copies of a known size
+contrast, random fields; with --dim 2 the 2-D variant on the perturbed-square
+analogue) and then `reps` plain device copies of a known size
 (torch's copy kernel, 1 GiB) that calibrate the FETCH_SIZE / WRITE_SIZE
 counters: a copy of S bytes must read S and write S.
 """
@@ -23,6 +25,7 @@ def main():
     ap.add_argument("--prec", default="c64", choices=["c64", "c128", "mixed"])
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--dim", type=int, default=3, choices=(2, 3))
     args = ap.parse_args()
     import torch
 
@@ -31,11 +34,16 @@ def main():
     binding.load()
     dev = torch.device("cuda:0")
     n, B = args.n, args.nrhs
-    m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
-    plan = binding.Plan(n, I.wavenumber_for(n), m, max_rhs=B)
     dt = torch.complex64 if args.prec == "c64" else torch.complex128
     g = torch.Generator(device=dev).manual_seed(7)
-    x = torch.randn((B, 3, n, n, n), dtype=dt, device=dev, generator=g)
+    if args.dim == 3:
+        m = torch.from_numpy(I.medium_bumps(n, 3)).to(dev)
+        plan = binding.Plan(n, I.wavenumber_for(n), m, max_rhs=B)
+        x = torch.randn((B, 3, n, n, n), dtype=dt, device=dev, generator=g)
+    else:
+        m = torch.from_numpy(I.medium2_perturbed_square(n, 3)).to(dev)
+        plan = binding.Plan2(n, I.paper_wavenumber(n), m, max_rhs=B)
+        x = torch.randn((B, 2, n, n), dtype=dt, device=dev, generator=g)
     y = torch.empty_like(x)
     for _ in range(args.reps):
         plan.apply(x, y, prec=args.prec)
@@ -46,7 +54,7 @@ def main():
     for _ in range(args.reps):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(f"profile_apply done: n={n} nrhs={B} prec={args.prec} reps={args.reps} copy={nbytes} B", flush=True)
+    print(f"profile_apply done: dim={args.dim} n={n} nrhs={B} prec={args.prec} reps={args.reps} copy={nbytes} B", flush=True)
     plan.close()
 
 

@@ -2,7 +2,7 @@
 Helmholtz kernel, two components).
 
 Bar: complex128 to 1e-12 of the output's size, FP32 (complex64 and mixed) to
-2e-5 (FFT rounding of length-P transforms, P <= 2048: a few 1e-7 per
+2e-5 (FFT rounding of length-P transforms, P <= 1944: a few 1e-7 per
 transform, with the symbol's spread of magnitudes), element by element, on
 grids spanning radix-4/2/3 lengths and ragged row and column blocks.
 """
@@ -173,3 +173,11 @@ def test_errors(lib):
         plan.solve(g)                             # before the factor
     with pytest.raises(ValueError):
         plan.apply(_dev(I.random_field2(1, n + 1, 1)))
+
+
+def test_size_limits(lib):
+    """n = 972 is the largest grid (P = 1944 keeps the FP64 transforms in
+    64 KiB of LDS); n = 973 is refused before any device work."""
+    from paper_1804_02297_amd.binding import LSError, Plan2
+    with pytest.raises(LSError):
+        Plan2(973, 5.0, torch.zeros((973, 973), dtype=torch.complex128, device="cuda:0"))
