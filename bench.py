@@ -42,16 +42,28 @@ MEASURED_TRAFFIC = {
     "profile": "profiles/ls_apply_n128_b8_c64.md",
 }
 
+# HBM bytes of one 2-D column-pass launch (pass_b_kernel, n = 959, 8 rhs,
+# complex64) from rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated as above;
+# reported only while the sources are the measured ones.
+MEASURED_TRAFFIC_2D = {
+    "sources": ["twod.hip", "twod.h", "cplx.h"],
+    "sha256": "89e4976d795411c0e9e4455d474225a7b4f22c09d5d27327e5952592aa76ecf8",
+    "workload": (959, 8, "c64"),
+    "bytes": 0.9916e9,
+    "profile": "profiles/ls2_apply_n959_b8_c64.md",
+}
 
-def measured_traffic(n: int, B: int, prec: str):
+
+def measured_traffic(n: int, B: int, prec: str, table=None):
     import hashlib
+    table = table or MEASURED_TRAFFIC
     h = hashlib.sha256()
-    for f in MEASURED_TRAFFIC["sources"]:
+    for f in table["sources"]:
         with open(os.path.join(ROOT, "paper_1804_02297_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != MEASURED_TRAFFIC["sha256"] or (n, B, prec) != MEASURED_TRAFFIC["workload"]:
+    if h.hexdigest() != table["sha256"] or (n, B, prec) != table["workload"]:
         return None
-    return MEASURED_TRAFFIC["bytes"]
+    return table["bytes"]
 
 
 def pass_bytes(n: int, P: int, B: int, s: int, s_io: int) -> list[float]:
@@ -341,7 +353,8 @@ def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve
            "whole_GBps": round(sum(pb) / (ms32 * 1e-3) / 1e9, 1),
            "roofline": {"bound": "hbm", "kernel": ["pass_a_kernel", "pass_b_kernel", "pass_c_kernel"][dom],
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(n, B, "c64", MEASURED_TRAFFIC_2D) if dom == 1 else None,
                         "algorithmic_bytes": round(pb[dom])}}
     if solve_n:
         import time
