@@ -181,3 +181,31 @@ def test_size_limits(lib):
     from paper_1804_02297_amd.binding import LSError, Plan2
     with pytest.raises(LSError):
         Plan2(973, 5.0, torch.zeros((973, 973), dtype=torch.complex128, device="cuda:0"))
+
+
+def test_paper_2d_claim(lib):
+    """The paper's 2-D claim (fewer than ten GMRES(20) iterations to 1e-6 at
+    six points per wavelength) on the analogues of its three 2-D media at its
+    smallest 2-D grid, n = 119, with the residual recomputed by the oracle."""
+    import json
+    import os
+    from paper_1804_02297_amd.binding import Plan2
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables_2d.json")))
+    n = 119
+    k = I.paper_wavenumber(n)
+    Ei = I.paper_incident2(n, k)
+    sym = o2.symbol2(n, k)
+    for name, gen in I.PAPER_MEDIA_2D.items():
+        m = gen(n)
+        plan = Plan2(n, k, _dev(m))
+        plan.stencil_fit()
+        plan.factor("c128")
+        g = plan.rhs_from_incident(_dev(Ei))
+        x, info, st = plan.solve(g, tol=1e-6, restart=20)
+        gh = o2.rhs2(n, k, m, Ei[0], sym)
+        r = gh - o2.apply_fft2(n, k, m, x.cpu().numpy()[0], sym)
+        rr = np.linalg.norm(r) / np.linalg.norm(gh)
+        print(name, "iterations", info[0]["iters"], "oracle residual", rr, flush=True)
+        assert st == 0 and rr <= 1.01e-6
+        assert info[0]["iters"] < gold["claim_max_iters"]
+        plan.close()
