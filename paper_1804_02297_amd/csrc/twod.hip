@@ -49,15 +49,17 @@ double wall_seconds() {
 // ---- FFT of runtime length P = 2^a 3^b in LDS (Stockham, radices 8, 4, 2, 9, 3) ----
 // The radices are packed three bits per stage (0: 4, 1: 2, 2: 3, 3: 8, 4: 9),
 // first stage lowest.  Large radices first: fewer stages, fewer barriers.
-Radices factor_radices(int P) {
-  Radices r;
+__host__ __device__ constexpr Radices factor_radices(int P) {
+  Radices r{};
   int m = P, st = 0;
-  auto push = [&](unsigned c) { r.code |= (unsigned long long)c << (3 * st); ++st; };
-  while (m % 8 == 0) { push(3); m /= 8; }
-  while (m % 4 == 0) { push(0); m /= 4; }
-  while (m % 2 == 0) { push(1); m /= 2; }
-  while (m % 9 == 0) { push(4); m /= 9; }
-  while (m % 3 == 0) { push(2); m /= 3; }
+  const int rad[5] = {8, 4, 2, 9, 3};
+  const unsigned codes[5] = {3, 0, 1, 4, 2};
+  for (int q = 0; q < 5; ++q)
+    while (m % rad[q] == 0) {
+      r.code |= (unsigned long long)codes[q] << (3 * st);
+      ++st;
+      m /= rad[q];
+    }
   r.nst = (m == 1 && st <= 21) ? st : -1;
   return r;
 }
@@ -108,15 +110,17 @@ __device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* _
 // threads take consecutive transforms (columns), else consecutive elements.
 // Returns the buffer that holds the result.  Ends with a barrier.
 template <typename R, int DIR, bool BFAST>
-__device__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs, const Tw<R>& tw) {
+__device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs,
+                                         const Tw<R>& tw) {
   int Ns = 1;
+#pragma unroll
   for (int st = 0; st < rd.nst; ++st) {
     const unsigned code = (unsigned)(rd.code >> (3 * st)) & 7u;
     const int RR = code == 0 ? 4 : (code == 1 ? 2 : (code == 2 ? 3 : (code == 3 ? 8 : 9)));
     const int NR = P / RR;
     const int tstep = P / (RR * Ns);
     const int total = nb * NR;
-    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    for (int w = threadIdx.x; w < total; w += kT2) {
       const int t = BFAST ? w % nb : w / NR;
       const int j = BFAST ? w / nb : w % NR;
       const C<R>* s = a + t * bs;
@@ -261,11 +265,14 @@ template <typename T>
 __device__ __forceinline__ C<T> ld_c(const void* p, long i) { return reinterpret_cast<const C<T>*>(p)[i]; }
 
 // pass A: block w -> (rhs b, row block rb, field f), f fastest.
-template <typename R, typename IO>
+template <typename R, typename IO, int PT, int NBT>
 __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x, const C<R>* __restrict__ m,
-                                                      const C<R>* __restrict__ p, C<R>* __restrict__ T, int n, int P,
-                                                      Radices rd, int nb, int nrb, int nwork,
+                                                      const C<R>* __restrict__ p, C<R>* __restrict__ T, int n, int P_,
+                                                      Radices rd_, int nb_, int nrb, int nwork,
                                                       const C<R>* __restrict__ tw) {
+  // PT, NBT > 0: the length and batch fixed at compile time (constant divisions, unrolled stages)
+  const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
+  const Radices rd = PT > 0 ? factor_radices(PT) : rd_;
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   const int f = w % 3, rb = (w / 3) % nrb, b = w / (3 * nrb);
   const long nn = (long)n * n;
   const long xb = (long)b * 2 * nn;
-  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nb * P; e += kT2) {
     const int t = e / P, j = e % P;
     const int i1 = rb * nb + t;
     C<R> v = cmk<R>(0, 0);
@@ -291,17 +298,19 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   __syncthreads();
   C<R>* X = lds_fft<R, -1, false>(a, bb, P, rd, nb, 1, P, tws);
   C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
-  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nb * P; e += kT2) {
     const int i1 = rb * nb + e / P;
     if (i1 < n) out[(size_t)i1 * P + e % P] = X[e];
   }
 }
 
 // pass B: block -> column block (CW = nb adjacent columns); loops over the rhs.
-template <typename R, int EMAX>
+template <typename R, int EMAX, int PT, int NBT>
 __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T, C<R>* __restrict__ T2,
-                                                      const C<R>* __restrict__ sym, int n, int P, int H, Radices rd,
-                                                      int nb, int nrhs, const C<R>* __restrict__ tw) {
+                                                      const C<R>* __restrict__ sym, int n, int P_, int H, Radices rd_,
+                                                      int nb_, int nrhs, const C<R>* __restrict__ tw) {
+  const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
+  const Radices rd = PT > 0 ? factor_radices(PT) : rd_;
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
@@ -312,69 +321,68 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
   const int b = w / ncb;
   const int q0 = (w % ncb) * nb;
   const int tot = nb * P;
-  // symbol of the elements this thread owns: e = threadIdx.x + kT2 * u, q1 = e / nb, q2 = q0 + e % nb
-  C<R> s0[EMAX], s1[EMAX], s2[EMAX];
-#pragma unroll
-  for (int u = 0; u < EMAX; ++u) {
-    const int e = threadIdx.x + kT2 * u;
-    if (e < tot) {
-      const int q1 = e / nb, q2 = q0 + e % nb;
-      const bool f1 = q1 > P / 2, f2 = q2 > P / 2;
-      const int a1 = f1 ? P - q1 : q1, a2 = f2 ? P - q2 : q2;
-      const C<R>* sp = sym + ((size_t)a1 * H + a2) * 3;
-      s0[u] = sp[0];
-      s1[u] = f1 ? cmk<R>(-sp[1].re, -sp[1].im) : sp[1];
-      s2[u] = f2 ? cmk<R>(-sp[2].re, -sp[2].im) : sp[2];
+  // symbol at the element e of the column block: q1 = e / nb, q2 = q0 + e % nb, read
+  // from the quadrant (L1/L2-resident: one block's columns share it over the rhs)
+  auto symv = [&](int e, int c) -> C<R> {
+    const int q1 = e / nb, q2 = q0 + e % nb;
+    const bool f1 = q1 > P / 2, f2 = q2 > P / 2;
+    const int a1 = f1 ? P - q1 : q1, a2 = f2 ? P - q2 : q2;
+    const C<R> v = sym[((size_t)a1 * H + a2) * 3 + c];
+    const bool neg = (c == 1 && f1) || (c == 2 && f2);
+    return neg ? cmk<R>(-v.re, -v.im) : v;
+  };
+  C<R> o0[EMAX], o1[EMAX];
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+    const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
+    for (int e = threadIdx.x; e < tot; e += kT2) {
+      const int i1 = e / nb;
+      a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
     }
-  }
-  {
-    C<R> o0[EMAX], o1[EMAX];
-    for (int f = 0; f < 3; ++f) {
-      const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
-      for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int i1 = e / nb;
-        a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
-      }
-      __syncthreads();
-      const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tws);
+    __syncthreads();
+    const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tws);
 #pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        const int e = threadIdx.x + kT2 * u;
-        if (e < tot) {
-          const C<R> v = X[e];
-          if (f == 0) o0[u] = s0[u] * v;
-          else if (f == 1) o1[u] = s0[u] * v;
-          else {
-            o0[u] = cfma(s1[u], v, o0[u]);
-            o1[u] = cfma(s2[u], v, o1[u]);
-          }
+    for (int u = 0; u < EMAX; ++u) {
+      const int e = threadIdx.x + kT2 * u;
+      if (e < tot) {
+        const C<R> v = X[e];
+        if (f == 0) {
+          o0[u] = symv(e, 0) * v;
+        } else if (f == 1) {
+          o1[u] = symv(e, 0) * v;
+        } else {
+          o0[u] = cfma(symv(e, 1), v, o0[u]);
+          o1[u] = cfma(symv(e, 2), v, o1[u]);
         }
       }
-      __syncthreads();
     }
-    for (int d = 0; d < 2; ++d) {
+    __syncthreads();
+  }
+#pragma unroll 1
+  for (int d = 0; d < 2; ++d) {
 #pragma unroll
-      for (int u = 0; u < EMAX; ++u) {
-        const int e = threadIdx.x + kT2 * u;
-        if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
-      }
-      __syncthreads();
-      const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tws);
-      C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
-      for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int i1 = e / nb;
-        if (i1 < n) out[(size_t)i1 * P + e % nb] = X[e];
-      }
-      __syncthreads();
+    for (int u = 0; u < EMAX; ++u) {
+      const int e = threadIdx.x + kT2 * u;
+      if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
     }
+    __syncthreads();
+    const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tws);
+    C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
+    for (int e = threadIdx.x; e < tot; e += kT2) {
+      const int i1 = e / nb;
+      if (i1 < n) out[(size_t)i1 * P + e % nb] = X[e];
+    }
+    __syncthreads();
   }
 }
 
 // pass C: block w -> (rhs b, component d, row block rb); y = x + v (or -v).
-template <typename R, typename IO>
+template <typename R, typename IO, int PT, int NBT>
 __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2, const void* __restrict__ x,
-                                                      void* __restrict__ y, int n, int P, Radices rd, int nb, int nrb,
+                                                      void* __restrict__ y, int n, int P_, Radices rd_, int nb_, int nrb,
                                                       int nwork, int minus_conv, const C<R>* __restrict__ tw) {
+  const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
+  const Radices rd = PT > 0 ? factor_radices(PT) : rd_;
   extern __shared__ unsigned char lds_raw[];
   C<R>* a = reinterpret_cast<C<R>*>(lds_raw);
   C<R>* bb = a + (size_t)nb * P;
@@ -382,7 +390,7 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
   const int w = xcd_work_index(blockIdx.x, nwork);
   const int rb = w % nrb, d = (w / nrb) % 2, b = w / (2 * nrb);
   const C<R>* in = T2 + ((size_t)(b * 2 + d) * n) * P;
-  for (int e = threadIdx.x; e < nb * P; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nb * P; e += kT2) {
     const int i1 = rb * nb + e / P;
     a[e] = i1 < n ? in[(size_t)i1 * P + e % P] : cmk<R>(0, 0);
   }
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
   const long nn = (long)n * n;
   const long base = ((long)b * 2 + d) * nn;
   C<IO>* yo = reinterpret_cast<C<IO>*>(y);
-  for (int e = threadIdx.x; e < nb * n; e += blockDim.x) {
+  for (int e = threadIdx.x; e < nb * n; e += kT2) {
     const int t = e / n, j = e % n;
     const int i1 = rb * nb + t;
     if (i1 < n) {
@@ -448,7 +456,7 @@ __global__ __launch_bounds__(256) void gram2_kernel(const C<double>* __restrict_
   const long ncols = (long)R1 * R2;
   C<double> acc[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
   for (long j0 = (long)blockIdx.x * kGramCols; j0 < ncols; j0 += (long)gridDim.x * kGramCols) {
-    for (int e = threadIdx.x; e < T * kGramCols; e += blockDim.x) {
+    for (int e = threadIdx.x; e < T * kGramCols; e += kT2) {
       const int t = e / kGramCols, col = e % kGramCols;
       const long j = j0 + col;
       C<double> v0 = cmk(0.0, 0.0), v1 = v0, v2 = v0;
@@ -610,10 +618,10 @@ void herm_eig(int D, std::vector<std::complex<double>> A, std::vector<double>& e
 }
 
 template <typename R>
-int batch_for(int P, size_t budget = kLdsTarget) {
+__host__ __device__ constexpr int batch_for(int P, size_t budget = kLdsTarget) {
   const size_t per = 2 * (size_t)P * sizeof(C<R>);
-  int nb = (int)std::max<size_t>(1, (budget - tw_entries(kMaxP2) * sizeof(C<R>)) / per);
-  nb = std::min(nb, 16);
+  const size_t avail = (budget - tw_entries(kMaxP2) * sizeof(C<R>)) / per;
+  int nb = avail > 16 ? 16 : (avail < 1 ? 1 : (int)avail);
   // a power of two that divides P (the column blocks tile P exactly)
   int b = 1;
   while (b * 2 <= nb && P % (b * 2) == 0) b *= 2;
@@ -623,9 +631,11 @@ int batch_for(int P, size_t budget = kLdsTarget) {
 template <typename R>
 size_t lds_bytes(int P, int nb) { return (2 * (size_t)nb * P + tw_entries(P)) * sizeof(C<R>); }
 
-template <typename R, typename IO>
-ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s,
-                    hipEvent_t* ev = nullptr) {
+template <typename R, typename IO, int PT>
+ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s,
+                      hipEvent_t* ev) {
+  constexpr int NBA = PT > 0 ? batch_for<R>(PT) : 0;
+  constexpr int NBB = PT > 0 ? batch_for<R>(PT, kLds2) : 0;
   const int n = pl.n, P = pl.P;
   const C<R>* m = (const C<R>*)(std::is_same<R, double>::value ? pl.m64.p : pl.m32.p);
   const C<R>* p = (const C<R>*)(std::is_same<R, double>::value ? pl.p64.p : pl.p32.p);
@@ -646,22 +656,36 @@ ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv
     void* yr = (unsigned char*)y + off;
     const int wa = nr * nrb * 3;
     if (ev) LS_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL((pass_a_kernel<R, IO>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
+    hipLaunchKernelGGL((pass_a_kernel<R, IO, PT, NBA>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
                        tw);
     LS_HIP(hipGetLastError());
     constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kT2);
     if (ev) LS_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((pass_b_kernel<R, EMAX>), dim3((P / nbc) * nr), dim3(kT2), ldsc, s, T, T2, sym, n, P, pl.H,
+    hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kT2), ldsc, s, T, T2, sym, n, P, pl.H,
                        pl.rd, nbc, nr, tw);
     LS_HIP(hipGetLastError());
     const int wc = nr * 2 * nrb;
     if (ev) LS_HIP(hipEventRecord(ev[2], s));
-    hipLaunchKernelGGL((pass_c_kernel<R, IO>), dim3(wc), dim3(kT2), lds, s, T2, xr, yr, n, P, pl.rd, nb, nrb, wc,
+    hipLaunchKernelGGL((pass_c_kernel<R, IO, PT, NBA>), dim3(wc), dim3(kT2), lds, s, T2, xr, yr, n, P, pl.rd, nb, nrb, wc,
                        minus_conv ? 1 : 0, tw);
     LS_HIP(hipGetLastError());
     if (ev) LS_HIP(hipEventRecord(ev[3], s));
   }
   return LS_OK;
+}
+
+// The paper's 2-D grids (n = 119, 239, 479, 959) use P = 256, 486, 972, 1944:
+// kernels compiled for those lengths; any other length takes the runtime path.
+template <typename R, typename IO>
+ls_status run_apply(Plan2& pl, const void* x, void* y, int nrhs, bool minus_conv, hipStream_t s,
+                    hipEvent_t* ev = nullptr) {
+  switch (pl.P) {
+    case 256: return run_apply_p<R, IO, 256>(pl, x, y, nrhs, minus_conv, s, ev);
+    case 486: return run_apply_p<R, IO, 486>(pl, x, y, nrhs, minus_conv, s, ev);
+    case 972: return run_apply_p<R, IO, 972>(pl, x, y, nrhs, minus_conv, s, ev);
+    case 1944: return run_apply_p<R, IO, 1944>(pl, x, y, nrhs, minus_conv, s, ev);
+    default: return run_apply_p<R, IO, 0>(pl, x, y, nrhs, minus_conv, s, ev);
+  }
 }
 
 }  // namespace
