@@ -316,10 +316,12 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
   C<R>* bb = a + (size_t)nb * P;
   const Tw<R> tws = load_twiddles(bb + (size_t)nb * P, tw, P);
   const int ncb = P / nb;
-  // block -> (rhs, column block), column blocks of one rhs adjacent on an XCD
+  // block -> (rhs, column block), the rhs fastest: the blocks of one column
+  // block (same symbol lines) and of its neighbours (same 128-byte lines of
+  // the intermediate) run together on one XCD and share its L2
   const int w = xcd_work_index(blockIdx.x, ncb * nrhs);
-  const int b = w / ncb;
-  const int q0 = (w % ncb) * nb;
+  const int b = w % nrhs;
+  const int q0 = (w / nrhs) * nb;
   const int tot = nb * P;
   // symbol at the element e of the column block: q1 = e / nb, q2 = q0 + e % nb, read
   // from the quadrant (L1/L2-resident: one block's columns share it over the rhs)
