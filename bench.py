@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "89e4976d795411c0e9e4455d474225a7b4f22c09d5d27327e5952592aa76ecf8",
+    "sha256": "5b6545defd60916416f337ce87eddf58f74831713ade4ac0e2dd1a8968750f99",
     "workload": (959, 8, "c64"),
-    "bytes": 0.9916e9,
+    "bytes": 1.1475e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
