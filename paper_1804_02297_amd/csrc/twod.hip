@@ -93,11 +93,14 @@ __device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* _
   C<R> v[RR];
 #pragma unroll
   for (int r = 0; r < RR; ++r) v[r] = src[(j + r * NR) * es];
+  // one table lookup per butterfly: W^(r k tstep) = (W^(k tstep))^r by recurrence
+  C<R> w1 = tw(k * tstep);
+  if (DIR > 0) w1 = cconj(w1);
+  C<R> w = w1;
 #pragma unroll
   for (int r = 1; r < RR; ++r) {
-    C<R> w = tw(r * k * tstep);
-    if (DIR > 0) w = cconj(w);
     v[r] = v[r] * w;
+    if (r + 1 < RR) w = w * w1;
   }
   Dft<RR, DIR, R>::run(v);
   const int d0 = (j - k) * RR + k;
