@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "5b6545defd60916416f337ce87eddf58f74831713ade4ac0e2dd1a8968750f99",
+    "sha256": "003c6c8a154fbb8e93717409f4c1529b9f1aa84cc93e0e6054938367796c33ad",
     "workload": (959, 8, "c64"),
-    "bytes": 1.1475e9,
+    "bytes": 1.1464e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
