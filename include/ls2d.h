@@ -93,16 +93,25 @@ ls_status ls2_get_stencils(const ls2_plan* plan, void* alpha_host, void* beta_ho
  * taken is written to *seconds_out when not NULL.  LS_ESTATE before a fit. */
 ls_status ls2_factor(ls2_plan* plan, ls_prec factor_prec, double* seconds_out);
 
+/* The same factorisation on the GPU (the multifrontal of ls_factor_gpu on
+ * the n x n x 1 grid with two unknowns per point): fronts and factor in
+ * HBM, pivots searched inside 48-row diagonal tiles (24 whole points);
+ * later preconditioner applies solve on the GPU.  factor_prec LS_C128 or
+ * LS_C64.  LS_ESTATE before a fit, LS_ENOMEM when HBM is short.
+ * Synchronises hip_stream. */
+ls_status ls2_factor_gpu(ls2_plan* plan, ls_prec factor_prec, void* hip_stream, double* seconds_out);
+
 /* z = S^-1 (Q v) for nrhs fields (device, complex128 [nrhs][2][n][n]; z may
- * equal v): Q v on the GPU, S^-1 on host cores over PCIe.  LS_ESTATE before
- * ls2_factor.  Synchronises. */
+ * equal v): Q v on the GPU, S^-1 by the latest factor (on the GPU after
+ * ls2_factor_gpu, on host cores over PCIe after ls2_factor).  LS_ESTATE
+ * before a factorisation.  Synchronises. */
 ls_status ls2_precond_apply(ls2_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream);
 
 /* Right-preconditioned FGMRES for A x = g, as ls_gmres_solve (restart,
  * maxit, tol on ||g - A x|| / ||g|| with the FP64 apply, x0 = 0, a lockstep
  * block of nrhs right-hand sides; apply_prec LS_C128 or LS_MIXED).  g, x:
  * device complex128 [nrhs][2][n][n]; info: host array of nrhs records.
- * LS_ESTATE before ls2_factor, LS_ENOCONV when maxit is reached. */
+ * LS_ESTATE before a factorisation, LS_ENOCONV when maxit is reached. */
 ls_status ls2_gmres_solve(ls2_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
                           int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream);
 

@@ -79,6 +79,7 @@ SIGNATURES = [
     ("ls2_stencil_fit", _I, [_VP, _VP]),
     ("ls2_get_stencils", _I, [_VP, _VP, _VP, _VP]),
     ("ls2_factor", _I, [_VP, _I, ctypes.POINTER(ctypes.c_double)]),
+    ("ls2_factor_gpu", _I, [_VP, _I, _VP, ctypes.POINTER(ctypes.c_double)]),
     ("ls2_precond_apply", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls2_gmres_solve", _I, [_VP, _VP, _VP, _I, _D, _I, _I, _I, _VP, _VP]),
     ("ls2_plan_fft_size", _I, [_VP]),
@@ -541,6 +542,11 @@ class Plan2:
     def factor(self, prec: str = "c128") -> float:
         t = ctypes.c_double()
         _check(_lib.ls2_factor(self._h, PREC[prec], ctypes.byref(t)), "ls2_factor")
+        return t.value
+
+    def factor_gpu(self, prec: str = "c128") -> float:
+        t = ctypes.c_double()
+        _check(_lib.ls2_factor_gpu(self._h, PREC[prec], _stream(), ctypes.byref(t)), "ls2_factor_gpu")
         return t.value
 
     def precond(self, v, z=None):

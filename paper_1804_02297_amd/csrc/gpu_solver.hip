@@ -105,13 +105,13 @@ __global__ void zero_kernel(R* __restrict__ a, long cnt) {
 
 // S's entries into the fronts of a level; each entry of S belongs to exactly
 // one front position, so plain additions do not collide.
-template <typename R>
+template <typename R, int NC>
 __global__ __launch_bounds__(256) void assemble_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                        int nlvl, const int* __restrict__ ib,
                                                        const C<double>* __restrict__ rows, R* __restrict__ buf) {
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
-    const int npp = d.np / 3, nbp = d.nb / 3;
+    const int npp = d.np / NC, nbp = d.nb / NC;
     const long nf = d.nf;
     R* Fr = buf + d.f;
     R* Fi = Fr + nf * nf;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const FrontDev* __restric
       const int a = (int)(w / 27), slot = (int)(w % 27);
       int pt, lj;
       if (a < npp) {
-        pt = ib[d.e0 + 3 * a];                         // perm (at offset 0): component 0 of point a
+        pt = ib[d.e0 + NC * a];                         // perm (at offset 0): component 0 of point a
         lj = ib[d.am + 27L * a + slot];
       } else {
         pt = ib[d.bp + (a - npp)];
@@ -128,11 +128,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(const FrontDev* __restric
       }
       if (lj < 0) continue;
 #pragma unroll
-      for (int r = 0; r < 3; ++r)
+      for (int r = 0; r < NC; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const C<double> v = rows[(((long)pt * 3 + r) * 27 + slot) * 3 + c];
-          const long o = (3L * a + r) * nf + 3L * lj + c;
+        for (int c = 0; c < NC; ++c) {
+          const C<double> v = rows[(((long)pt * NC + r) * 27 + slot) * NC + c];
+          const long o = ((long)NC * a + r) * nf + (long)NC * lj + c;
           Fr[o] += (R)v.re;
           Fi[o] += (R)v.im;
         }
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const FrontDev* __restric
 
 // F_parent += child's update block (rows and columns mapped through the child's
 // boundary-to-parent positions), for child `slot` of every front of a level.
-template <typename R>
+template <typename R, int NC>
 __global__ __launch_bounds__(256) void extend_add_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                          int nlvl, int slot, const int* __restrict__ ib,
                                                          const R* __restrict__ cbuf, R* __restrict__ buf) {
@@ -157,13 +157,13 @@ __global__ __launch_bounds__(256) void extend_add_kernel(const FrontDev* __restr
     const R* Cr = cbuf + c.f;
     const R* Ci = Cr + cnf * cnf;
     for (int r = blockIdx.x; r < cnb; r += gridDim.x) {
-      const long pr = 3L * ib[c.xm + r / 3] + r % 3;
+      const long pr = (long)NC * ib[c.xm + r / NC] + r % NC;
       const R* sr = Cr + (c.np + r) * cnf + c.np;
       const R* si = Ci + (c.np + r) * cnf + c.np;
       R* dr = Fr + pr * nf;
       R* di = Fi + pr * nf;
       for (int s = threadIdx.x; s < cnb; s += blockDim.x) {
-        const int ps = 3 * ib[c.xm + s / 3] + s % 3;
+        const int ps = NC * ib[c.xm + s / NC] + s % NC;
         dr[ps] += sr[s];
         di[ps] += si[s];
       }
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256) void sol_out_kernel(C<double>* __restrict__ b,
 
 // children's update vectors into the pivot rows (x) or the update vector (u)
 // of every front of a level, for child `slot`; four rows per workgroup pass
-template <typename R>
+template <typename R, int NC>
 __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                         int nlvl, int slot, const int* __restrict__ ib, int nrhs,
                                                         R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Ur,
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
     if (d.child[slot] < 0) continue;
     const FrontDev c = fr[d.child[slot]];
     for (int rr = blockIdx.x * 4 + (threadIdx.x >> 6); rr < c.nb; rr += gridDim.x * 4) {
-      const int pos = 3 * ib[c.xm + rr / 3] + rr % 3;
+      const int pos = NC * ib[c.xm + rr / NC] + rr % NC;
       const bool piv = pos < d.np;
       const long src = (c.u + rr) * nrhs;
       const long dst = piv ? (long)(d.e0 + pos) * nrhs : (d.u + pos - d.np) * nrhs;
@@ -1276,8 +1276,11 @@ inline unsigned grid_for(long work, long per = 256, long cap = 65535) {
 
 struct GpuSolver {
   int n = 0;
+  int dims[3] = {0, 0, 0};             // grid extents (n, n, n) in 3-D, (n, n, 1) in 2-D
+  int nc = 3;                          // unknowns per point (field components)
+  long npts = 0;
   bool fp32 = false;
-  long N = 0;                          // 3 n^3 unknowns
+  long N = 0;                          // nc * npts unknowns
   std::vector<FrontDev> fh;            // per node (host copy)
   std::vector<std::vector<int>> levels;   // node ids per depth
   std::vector<long> lvl_off;           // offset of each level's list in lvl_d
@@ -1296,11 +1299,12 @@ namespace {
 
 // Symbolic phase: dissection, elimination order, offsets and index maps.
 ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
-  const int n = g.n;
-  NdTree t = nd_build(n);
+  const int* dm = g.dims;
+  const int nc = g.nc;
+  NdTree t = nd_build_grid(dm, nc);
   const int nn = (int)t.nodes.size();
-  g.N = 3L * n * n * n;
-  const long n3 = (long)n * n * n;
+  const long n3 = g.npts;
+  g.N = (long)nc * n3;
   g.levels.assign(t.max_depth + 1, {});
   for (int i = 0; i < nn; ++i) g.levels[t.nodes[i].depth].push_back(i);
   g.fh.assign(nn, FrontDev{});
@@ -1317,7 +1321,7 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
       f.e0 = (int)e;
       f.child[0] = nd.child[0];
       f.child[1] = nd.child[1];
-      for (size_t a = 0; a < nd.piv.size(); ++a) elim_of_point[nd.piv[a]] = e + 3 * (long)a;
+      for (size_t a = 0; a < nd.piv.size(); ++a) elim_of_point[nd.piv[a]] = e + (long)nc * a;
       e += nd.np;
     }
   if (e != g.N) return LS_EINVAL;
@@ -1345,18 +1349,18 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
     const NdNode& nd = t.nodes[id];
     const FrontDev& f = g.fh[id];
     for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int c = 0; c < 3; ++c) ibh[f.e0 + 3 * a + c] = (int)(c * n3 + nd.piv[a]);
+      for (int c = 0; c < nc; ++c) ibh[f.e0 + nc * a + c] = (int)(c * n3 + nd.piv[a]);
     const int npp = (int)nd.piv.size();
     auto nb_map = [&](int p, long dst, bool pivot_row) {
-      const int i3 = p % n, i2 = (p / n) % n, i1 = p / (n * n);
+      const int i3 = p % dm[2], i2 = (p / dm[2]) % dm[1], i1 = p / (dm[1] * dm[2]);
       for (int s1 = -1; s1 <= 1; ++s1)
         for (int s2 = -1; s2 <= 1; ++s2)
           for (int s3 = -1; s3 <= 1; ++s3) {
             const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
             const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
             int v = -1;
-            if (j1 >= 0 && j1 < n && j2 >= 0 && j2 < n && j3 >= 0 && j3 < n) {
-              const int pj = (j1 * n + j2) * n + j3;
+            if (j1 >= 0 && j1 < dm[0] && j2 >= 0 && j2 < dm[1] && j3 >= 0 && j3 < dm[2]) {
+              const int pj = (j1 * dm[1] + j2) * dm[2] + j3;
               v = pivot_row ? nd_front_pos(nd, pj) : nd_pos_in(nd.piv, pj);
             }
             ibh[dst + slot] = v;
@@ -1368,7 +1372,7 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
       ibh[f.bp + b] = nd.bnd[b];
       const long eb = elim_of_point[nd.bnd[b]];
       if (eb < 0) return LS_EINVAL;
-      for (int c = 0; c < 3; ++c) ibh[f.bm + 3 * b + c] = (int)(eb + c);
+      for (int c = 0; c < nc; ++c) ibh[f.bm + nc * b + c] = (int)(eb + c);
     }
     if (nd.parent >= 0) {
       const NdNode& pa = t.nodes[nd.parent];
@@ -1430,12 +1434,12 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
     const FrontDev& f = g.fh[id];
     const NdNode& nd = t.nodes[id];
     for (long i = 0; i < 27L * (long)nd.piv.size(); ++i)
-      if (ibh[f.am + i] >= f.nf / 3) return LS_EINVAL;
+      if (ibh[f.am + i] >= f.nf / nc) return LS_EINVAL;
     for (long i = 0; i < 27L * (long)nd.bnd.size(); ++i)
-      if (ibh[f.ab + i] >= f.np / 3) return LS_EINVAL;
+      if (ibh[f.ab + i] >= f.np / nc) return LS_EINVAL;
     if (nd.parent >= 0)
       for (size_t b = 0; b < nd.bnd.size(); ++b)
-        if (ibh[f.xm + b] >= g.fh[nd.parent].nf / 3) return LS_EINVAL;
+        if (ibh[f.xm + b] >= g.fh[nd.parent].nf / nc) return LS_EINVAL;
   }
   return LS_OK;
 }
@@ -1460,16 +1464,24 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
     const long mnf = g.lvl_nf[dep], mnp = g.lvl_np[dep];
     hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for((long)g.lvl_elems[dep], 256, 1 << 20)), dim3(256), 0, s, buf,
                        (long)g.lvl_elems[dep]);
-    hipLaunchKernelGGL(assemble_kernel<R>, dim3(grid_for(mnf / 3 * 27), gy), dim3(256), 0, s, fr, lvl, nl, ib, rows,
-                       buf);
+    if (g.nc == 3)
+      hipLaunchKernelGGL((assemble_kernel<R, 3>), dim3(grid_for(mnf / 3 * 27), gy), dim3(256), 0, s, fr, lvl, nl, ib,
+                         rows, buf);
+    else
+      hipLaunchKernelGGL((assemble_kernel<R, 2>), dim3(grid_for(mnf / 2 * 27), gy), dim3(256), 0, s, fr, lvl, nl, ib,
+                         rows, buf);
     if (dep + 1 < L)
       for (int slot = 0; slot < 2; ++slot) {
         long mcnb = 0;
         for (int id : g.levels[dep])
           if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
         if (mcnb == 0) continue;
-        hipLaunchKernelGGL(extend_add_kernel<R>, dim3((unsigned)std::min(mcnb, 8192L), std::min(gy, 64u)),
-                           dim3(256), 0, s, fr, lvl, nl, slot, ib, cbuf, buf);
+        if (g.nc == 3)
+          hipLaunchKernelGGL((extend_add_kernel<R, 3>), dim3((unsigned)std::min(mcnb, 8192L), std::min(gy, 64u)),
+                             dim3(256), 0, s, fr, lvl, nl, slot, ib, cbuf, buf);
+        else
+          hipLaunchKernelGGL((extend_add_kernel<R, 2>), dim3((unsigned)std::min(mcnb, 8192L), std::min(gy, 64u)),
+                             dim3(256), 0, s, fr, lvl, nl, slot, ib, cbuf, buf);
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kOB) {
       const long kbe = std::min(mnp, kb0 + kOB);
@@ -1559,8 +1571,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
         if (mcnb == 0) continue;
         // one front per workgroup row (a front loop would chain descriptor loads)
         const long gxc = std::max(1L, std::min((mcnb + 3) / 4, std::max(1L, 65536L / nl)));
-        hipLaunchKernelGGL(fwd_child_kernel<R>, dim3((unsigned)gxc, gy), dim3(256), 0, s, fr, lvl, nl, slot, ib,
-                           nrhs, Xr, Xi, Ur, Ui);
+        if (g.nc == 3)
+          hipLaunchKernelGGL((fwd_child_kernel<R, 3>), dim3((unsigned)gxc, gy), dim3(256), 0, s, fr, lvl, nl, slot,
+                             ib, nrhs, Xr, Xi, Ur, Ui);
+        else
+          hipLaunchKernelGGL((fwd_child_kernel<R, 2>), dim3((unsigned)gxc, gy), dim3(256), 0, s, fr, lvl, nl, slot,
+                             ib, nrhs, Xr, Xi, Ur, Ui);
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kSB) {
       const unsigned gx = (unsigned)(kSB / kRB + std::max(0L, (mnf - kb0 - 1 + kRB - 1) / kRB));
@@ -1594,10 +1610,20 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
 }  // namespace
 
 ls_status gpu_factor(int n, const C<double>* rows_dev, bool fp32, hipStream_t s, GpuSolver** out) {
-  if (n < 1 || !rows_dev || !out) return LS_EINVAL;
+  const int dims[3] = {n, n, n};
+  return gpu_factor_grid(dims, 3, rows_dev, fp32, s, out);
+}
+
+ls_status gpu_factor_grid(const int dims[3], int nc, const C<double>* rows_dev, bool fp32, hipStream_t s,
+                          GpuSolver** out) {
+  if (!out) return LS_EINVAL;
   *out = nullptr;
+  if (!dims || dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || (nc != 2 && nc != 3) || !rows_dev) return LS_EINVAL;
   std::unique_ptr<GpuSolver> g(new GpuSolver());
-  g->n = n;
+  g->n = dims[0];
+  for (int d = 0; d < 3; ++d) g->dims[d] = dims[d];
+  g->nc = nc;
+  g->npts = (long)dims[0] * dims[1] * dims[2];
   g->fp32 = fp32;
   std::vector<int> ibh;
   long fac_elems = 0;

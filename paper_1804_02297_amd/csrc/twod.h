@@ -11,6 +11,7 @@
 namespace ls {
 
 struct HostSolver;
+struct GpuSolver;
 
 constexpr int kMaxP2 = 1944;       // largest padded FFT length of the 2-D apply (n <= 972)
 
@@ -34,8 +35,9 @@ struct Plan2 {
   std::vector<std::complex<double>> beta;    // [9][27][2]  (rows 3 t + f)
   std::vector<double> eig;                   // [9][18] Gram eigenvalues, ascending
   DevBuf qrows;                    // Q rows [n^2][2 rows][9 slots][2 comps] complex128
-  std::vector<std::complex<double>> srows;   // S rows, same layout, host
-  HostSolver* hs = nullptr;
+  DevBuf srows;                    // S rows [n^2][2 rows][27 slots][2 comps] complex128 (slots s3 = 0 used)
+  HostSolver* hs = nullptr;        // factor of S on host cores, or
+  GpuSolver* gs = nullptr;         // factor of S in HBM
   GmresContext gctx;
   DevBuf pbuf;                     // preconditioner staging
   ~Plan2();

@@ -30,6 +30,7 @@
 #include <new>
 #include <vector>
 
+#include "gpu_solver.h"
 #include "host_solver.h"
 
 #include <cstring>
@@ -767,6 +768,13 @@ ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev,
 }
 
 
+void plan2_drop_factor(Plan2& pl) {
+  if (pl.hs) host_free(pl.hs);
+  if (pl.gs) gpu_free(pl.gs);
+  pl.hs = nullptr;
+  pl.gs = nullptr;
+}
+
 ls_status plan2_fit(Plan2& pl, hipStream_t s) {
   const int n = pl.n;
   if (n < 4) return LS_EINVAL;   // the interior class needs a non-empty complement
@@ -829,48 +837,66 @@ ls_status plan2_fit(Plan2& pl, hipStream_t s) {
   }
   // rows
   const long nn = (long)n * n;
-  DevBuf dal, dbe, Sdev;
+  DevBuf dal, dbe;
   LS_TRY(dal.alloc(pl.alpha.size() * sizeof(cd)));
   LS_TRY(dbe.alloc(pl.beta.size() * sizeof(cd)));
   LS_TRY(pl.qrows.alloc((size_t)nn * 36 * sizeof(cd)));
-  LS_TRY(Sdev.alloc((size_t)nn * 108 * sizeof(cd)));
+  LS_TRY(pl.srows.alloc((size_t)nn * 108 * sizeof(cd)));
   LS_HIP(hipMemcpyAsync(dal.p, pl.alpha.data(), dal.bytes, hipMemcpyHostToDevice, s));
   LS_HIP(hipMemcpyAsync(dbe.p, pl.beta.data(), dbe.bytes, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(rows2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, dal.as<C<double>>(),
                      dbe.as<C<double>>(), pl.m64.as<C<double>>(), pl.p64.as<C<double>>(), pl.qrows.as<C<double>>(),
-                     Sdev.as<C<double>>(), n);
+                     pl.srows.as<C<double>>(), n);
   LS_HIP(hipGetLastError());
-  pl.srows.resize((size_t)nn * 108);
-  LS_HIP(hipMemcpyAsync(pl.srows.data(), Sdev.p, Sdev.bytes, hipMemcpyDeviceToHost, s));
   LS_HIP(hipStreamSynchronize(s));
   pl.fitted = true;
-  if (pl.hs) {
-    host_free(pl.hs);
-    pl.hs = nullptr;
-  }
+  plan2_drop_factor(pl);
   return LS_OK;
 }
 
-ls_status plan2_factor(Plan2& pl, bool fp32) {
+ls_status plan2_factor(Plan2& pl, bool fp32, hipStream_t s) {
   if (!pl.fitted) return LS_ESTATE;
-  if (pl.hs) {
-    host_free(pl.hs);
-    pl.hs = nullptr;
-  }
+  plan2_drop_factor(pl);
+  std::vector<std::complex<double>> rows(pl.srows.bytes / sizeof(std::complex<double>));
+  LS_HIP(hipMemcpyAsync(rows.data(), pl.srows.p, pl.srows.bytes, hipMemcpyDeviceToHost, s));
+  LS_HIP(hipStreamSynchronize(s));
   const int dims[3] = {pl.n, pl.n, 1};
-  return host_factor_grid(dims, 2, pl.srows.data(), 0, fp32, &pl.hs);
+  return host_factor_grid(dims, 2, rows.data(), 0, fp32, &pl.hs);
+}
+
+ls_status plan2_factor_gpu(Plan2& pl, bool fp32, hipStream_t s) {
+  if (!pl.fitted) return LS_ESTATE;
+  plan2_drop_factor(pl);
+  const int dims[3] = {pl.n, pl.n, 1};
+  LS_TRY(gpu_factor_grid(dims, 2, pl.srows.as<C<double>>(), fp32, s, &pl.gs));
+  LS_HIP(hipStreamSynchronize(s));
+  return LS_OK;
 }
 
 // z = S^-1 Q v for the listed fields (in place), S^-1 on host cores.
 ls_status plan2_precond(Plan2& pl, const std::vector<int>& lb, const std::function<C<double>*(int)>& ptr,
                         hipStream_t s, double* t_host) {
-  if (!pl.hs) return LS_ESTATE;
+  if (!pl.hs && !pl.gs) return LS_ESTATE;
   const long len = 2L * pl.n * pl.n;
   const size_t vb = (size_t)len * sizeof(C<double>);
   const int nb = (int)lb.size();
+  const long nn = (long)pl.n * pl.n;
+  if (pl.gs) {   // GPU factor: Q v into a contiguous block, S^-1 in HBM
+    if (t_host) *t_host = 0.0;
+    if (pl.pbuf.bytes < (size_t)nb * vb) LS_TRY(pl.pbuf.alloc((size_t)nb * vb));
+    C<double>* blk = pl.pbuf.as<C<double>>();
+    for (int q = 0; q < nb; ++q) {
+      hipLaunchKernelGGL(qapply2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                         pl.qrows.as<C<double>>(), ptr(lb[q]), blk + (size_t)q * len, pl.n, 1);
+      LS_HIP(hipGetLastError());
+    }
+    LS_TRY(gpu_solve(pl.gs, blk, blk, nb, s));
+    for (int q = 0; q < nb; ++q)
+      LS_HIP(hipMemcpyAsync(ptr(lb[q]), blk + (size_t)q * len, vb, hipMemcpyDeviceToDevice, s));
+    return LS_OK;
+  }
   if (pl.pbuf.bytes < vb) LS_TRY(pl.pbuf.alloc(vb));
   std::vector<std::complex<double>> hb((size_t)nb * len);
-  const long nn = (long)pl.n * pl.n;
   for (int q = 0; q < nb; ++q) {
     hipLaunchKernelGGL(qapply2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
                        pl.qrows.as<C<double>>(), ptr(lb[q]), pl.pbuf.as<C<double>>(), pl.n, 1);
@@ -891,7 +917,7 @@ ls_status plan2_solve(Plan2& pl, const void* g, void* x, int nrhs, double tol, i
                       ls_solve_info* info, hipStream_t s) {
   if (!g || !x || nrhs < 1 || !info || restart < 1 || maxit < 1 || !(tol > 0.0)) return LS_EINVAL;
   if (prec != LS_C128 && prec != LS_MIXED) return LS_EINVAL;
-  if (!pl.hs) return LS_ESTATE;
+  if (!pl.hs && !pl.gs) return LS_ESTATE;
   pl.gctx.len = 2L * pl.n * pl.n;
   GmresOps ops;
   Plan2* P = &pl;
@@ -929,6 +955,7 @@ struct ls2_plan {
 namespace ls {
 Plan2::~Plan2() {
   if (hs) host_free(hs);
+  if (gs) gpu_free(gs);
 }
 }  // namespace ls
 
@@ -998,7 +1025,15 @@ ls_status ls2_get_stencils(const ls2_plan* plan, void* alpha_host, void* beta_ho
 ls_status ls2_factor(ls2_plan* plan, ls_prec factor_prec, double* seconds_out) {
   if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
   const double t0 = ls::wall_seconds();
-  const ls_status st = ls::plan2_factor(plan->pl, factor_prec == LS_C64);
+  const ls_status st = ls::plan2_factor(plan->pl, factor_prec == LS_C64, nullptr);
+  if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
+  return st;
+}
+
+ls_status ls2_factor_gpu(ls2_plan* plan, ls_prec factor_prec, void* hip_stream, double* seconds_out) {
+  if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
+  const double t0 = ls::wall_seconds();
+  const ls_status st = ls::plan2_factor_gpu(plan->pl, factor_prec == LS_C64, (hipStream_t)hip_stream);
   if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
   return st;
 }

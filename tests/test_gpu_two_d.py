@@ -110,17 +110,25 @@ def test_class_stencils_match_oracle(lib, n):
         assert np.abs(b[kappa, :3 * len(tau)] - B.conj().T @ a[kappa, :D]).max() <= 1e-10 * np.abs(B).max()
 
 
-@pytest.mark.parametrize("n,prec,tol", [(12, "c128", 1e-10), (27, "c128", 1e-10), (27, "c64", 2e-4)])
-def test_preconditioner_matches_oracle(lib, n, prec, tol):
+@pytest.mark.parametrize("n,prec,tol,where", [(12, "c128", 1e-10, "host"), (27, "c128", 1e-10, "host"),
+                                              (27, "c64", 2e-4, "host"), (12, "c128", 1e-10, "gpu"),
+                                              (27, "c128", 1e-10, "gpu"), (61, "c128", 1e-10, "gpu"),
+                                              (27, "c64", 2e-4, "gpu")])
+def test_preconditioner_matches_oracle(lib, n, prec, tol, where):
     """z = S^-1 Q v is unique (independent of the unitary freedom in alpha):
-    element by element against the oracle's rows factored by SuperLU."""
+    element by element against the oracle's rows factored by SuperLU, with
+    S factored on host cores or on the GPU."""
     import oracle.sparse as osp
     from paper_1804_02297_amd.binding import Plan2
     k = I.paper_wavenumber(n)
     m = I.medium2_perturbed_square(n, 2)
     plan = Plan2(n, k, _dev(m), max_rhs=2)
     plan.stencil_fit()
-    plan.factor(prec)
+    print(f"n={n} {prec} {where}", flush=True)
+    if where == "gpu":
+        plan.factor_gpu(prec)
+    else:
+        plan.factor(prec)
     v = I.random_field2(2, n, 11)
     z = plan.precond(_dev(v)).cpu().numpy()
     al, be, _ = o2.fit_all_classes2(n, k)
@@ -156,6 +164,12 @@ def test_solve_paper_square(lib):
     assert st2 == 0
     r = gh - o2.apply_fft2(n, k, m, x2.cpu().numpy()[0])
     assert np.linalg.norm(r) / np.linalg.norm(gh) <= 1e-10
+    # the same solve with the factor in HBM: the same iteration count
+    plan.factor_gpu("c128")
+    x3, info3, st3 = plan.solve(g, tol=1e-6, restart=20)
+    assert st3 == 0 and info3[0]["iters"] == info[0]["iters"]
+    r = gh - o2.apply_fft2(n, k, m, x3.cpu().numpy()[0])
+    assert np.linalg.norm(r) / np.linalg.norm(gh) <= 1e-6
 
 
 def test_errors(lib):
