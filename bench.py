@@ -300,11 +300,12 @@ def pass_bytes_2d(n: int, P: int, H: int, B: int, s: int, s_io: int) -> list[flo
     return [a, b, c]
 
 
-def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve_n: int = 479):
+def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve_n: int = 959):
     """The 2-D variant at the paper's largest 2-D grid (n = 959, P = 1944,
     six points per wavelength): apply throughput, pass times and the
     roofline of the dominant pass; and the paper's 2-D lens example solved
-    with its settings (class stencils, complex128 factor, GMRES(20) to 1e-6)."""
+    with its settings (class stencils, complex128 factor in HBM, GMRES(20)
+    to 1e-6)."""
     import numpy as np
     dev = torch.device("cuda:0")
     k = I.paper_wavenumber(n)
@@ -365,7 +366,7 @@ def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan.stencil_fit()
-        t_fac = plan.factor("c128")
+        t_fac = plan.factor_gpu("c128")
         t_setup = time.perf_counter() - t0
         v = torch.randn_like(gg)
         z = torch.empty_like(gg)
@@ -422,7 +423,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
     ap.add_argument("--two-d-n", type=int, default=959, help="grid of the 2-D variant's apply line (0: skip)")
-    ap.add_argument("--two-d-solve-n", type=int, default=479, help="grid of the 2-D lens solve (0: skip)")
+    ap.add_argument("--two-d-solve-n", type=int, default=959, help="grid of the 2-D lens solve (0: skip)")
     ap.add_argument("--solve-n", type=int, default=64, help="grid of the per-rhs solve section (0: skip)")
     ap.add_argument("--solve-dirs", type=int, default=32, help="incident directions (2 polarisations each)")
     ap.add_argument("--solve-exact", type=int, default=-1,

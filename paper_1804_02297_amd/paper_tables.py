@@ -14,7 +14,8 @@ fixture of its tables.  Inputs are the seeded generators'; no oracle.
 
 With ``--dim 2`` the same for the 2-D variant: the analogues of the paper's
 2-D media (``inputs.PAPER_MEDIA_2D``), E^i = (0, e^{i k x_1}), the 9 class
-stencils and the nested-dissection factor of S on host cores (complex128).
+stencils and the nested-dissection factor of S (complex128) in HBM, or on
+host cores with ``--factor host``.
 
     python3 -m paper_1804_02297_amd.paper_tables --n 29 59
     python3 -m paper_1804_02297_amd.paper_tables --dim 2 --n 119 239 479 959
@@ -31,6 +32,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, nargs="+", default=[29, 59])
     ap.add_argument("--dim", type=int, choices=(2, 3), default=3)
+    ap.add_argument("--factor", choices=("gpu", "host"), default="gpu",
+                    help="2-D: factor S in HBM (default) or on host cores")
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--factor-prec", choices=("c128", "c64"), default="c128")
@@ -100,7 +103,10 @@ def run_2d(a, binding, I, dev, gold, timed):
             plan = binding.Plan2(n, k, m, max_rhs=1)
             g = plan.rhs_from_incident(torch.from_numpy(I.paper_incident2(n, k)).to(dev))
             t_fit, _ = timed(plan.stencil_fit)
-            t_fac, _ = timed(lambda: plan.factor(a.factor_prec))
+            if a.factor == "gpu":
+                t_fac, _ = timed(lambda: plan.factor_gpu(a.factor_prec))
+            else:
+                t_fac, _ = timed(lambda: plan.factor(a.factor_prec))
             v = torch.randn_like(g)
             z = torch.empty_like(g)
             plan.precond(v, z)
