@@ -65,6 +65,18 @@ __host__ __device__ constexpr Radices factor_radices(int P) {
   return r;
 }
 
+// The same stages in reverse order (an even radix last when P is even): the
+// inverse transforms, whose last stage then stores only the lower half.
+__host__ __device__ constexpr Radices reverse_radices(Radices r) {
+  Radices o{};
+  o.nst = r.nst;
+  for (int st = 0; st < r.nst; ++st) {
+    const unsigned long long c = (r.code >> (3 * st)) & 7ull;
+    o.code |= c << (3 * (r.nst - 1 - st));
+  }
+  return o;
+}
+
 // Twiddles W^t = exp(-2 pi i t / P) from two short tables held in LDS:
 // W^t = hi[t / 64] lo[t % 64] (one extra rounding against a full table).
 constexpr int kTwLo = 64;
@@ -87,33 +99,60 @@ __device__ Tw<R> load_twiddles(C<R>* t, const C<R>* __restrict__ tw_g, int P) {
   return Tw<R>{t, t + kTwLo};
 }
 
-template <typename R, int DIR, int RR>
+// One radix-RR butterfly of a Stockham stage.  FIRST: the first stage (all
+// twiddles 1).  ZIN: inputs r >= RR/2 are zero (the first stage of a
+// transform whose upper half is zero padding) and are not read.  HOUT: only
+// outputs r < RR/2 are stored (the last stage of a transform of which only
+// the lower half is used).
+template <typename R, int DIR, int RR, bool FIRST, bool ZIN, bool HOUT>
 __device__ __forceinline__ void stage_bfly(const C<R>* __restrict__ src, C<R>* __restrict__ dst, int j, int Ns,
                                            int NR, int tstep, int es, const Tw<R>& tw) {
-  const int k = j % Ns;
+  constexpr int NIN = ZIN ? RR / 2 : RR;
+  constexpr int NOUT = HOUT ? RR / 2 : RR;
+  const int k = FIRST ? 0 : j % Ns;
   C<R> v[RR];
 #pragma unroll
-  for (int r = 0; r < RR; ++r) v[r] = src[(j + r * NR) * es];
-  // one table lookup per butterfly: W^(r k tstep) = (W^(k tstep))^r by recurrence
-  C<R> w1 = tw(k * tstep);
-  if (DIR > 0) w1 = cconj(w1);
-  C<R> w = w1;
+  for (int r = 0; r < NIN; ++r) v[r] = src[(j + r * NR) * es];
+  if (!FIRST) {
+    // one table lookup per butterfly: W^(r k tstep) = (W^(k tstep))^r by recurrence
+    C<R> w1 = tw(k * tstep);
+    if (DIR > 0) w1 = cconj(w1);
+    C<R> w = w1;
 #pragma unroll
-  for (int r = 1; r < RR; ++r) {
-    v[r] = v[r] * w;
-    if (r + 1 < RR) w = w * w1;
+    for (int r = 1; r < NIN; ++r) {
+      v[r] = v[r] * w;
+      if (r + 1 < NIN) w = w * w1;
+    }
   }
-  Dft<RR, DIR, R>::run(v);
+  DftZ<RR, DIR, R, NIN>::run(v);
   const int d0 = (j - k) * RR + k;
 #pragma unroll
-  for (int r = 0; r < RR; ++r) dst[(d0 + r * Ns) * es] = v[r];
+  for (int r = 0; r < NOUT; ++r) dst[(d0 + r * Ns) * es] = v[r];
+}
+
+template <typename R, int DIR, int RR, bool ZIN, bool HOUT>
+__device__ __forceinline__ void stage_pick(const C<R>* s, C<R>* d, int j, int Ns, int NR, int tstep, int es,
+                                           const Tw<R>& tw, bool first, bool last) {
+  // pruning applies to even radices only (the first radix of a forward order, the last of a reversed one)
+  constexpr bool EV = RR % 2 == 0;
+  if (first) {
+    if (ZIN && EV) stage_bfly<R, DIR, RR, true, EV && ZIN, false>(s, d, j, Ns, NR, tstep, es, tw);
+    else if (last && HOUT && EV) stage_bfly<R, DIR, RR, true, false, EV && HOUT>(s, d, j, Ns, NR, tstep, es, tw);
+    else stage_bfly<R, DIR, RR, true, false, false>(s, d, j, Ns, NR, tstep, es, tw);
+  } else if (last && HOUT && EV) {
+    stage_bfly<R, DIR, RR, false, false, EV && HOUT>(s, d, j, Ns, NR, tstep, es, tw);
+  } else {
+    stage_bfly<R, DIR, RR, false, false, false>(s, d, j, Ns, NR, tstep, es, tw);
+  }
 }
 
 // nb transforms of length P held in LDS: element e of transform t at
 // a[t * bs + e * es].  b is scratch of the same extent.  BFAST: consecutive
 // threads take consecutive transforms (columns), else consecutive elements.
+// ZIN: the upper half of every input is zero (never read).  HOUT: only the
+// lower half of every output is used (the upper half is left unspecified).
 // Returns the buffer that holds the result.  Ends with a barrier.
-template <typename R, int DIR, bool BFAST>
+template <typename R, int DIR, bool BFAST, bool ZIN = false, bool HOUT = false>
 __device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs,
                                          const Tw<R>& tw) {
   int Ns = 1;
@@ -124,17 +163,18 @@ __device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, in
     const int NR = P / RR;
     const int tstep = P / (RR * Ns);
     const int total = nb * NR;
+    const bool first = st == 0, last = st + 1 == rd.nst;
     for (int w = threadIdx.x; w < total; w += kT2) {
       const int t = BFAST ? w % nb : w / NR;
       const int j = BFAST ? w / nb : w % NR;
       const C<R>* s = a + t * bs;
       C<R>* d = b + t * bs;
       switch (code) {
-        case 0: stage_bfly<R, DIR, 4>(s, d, j, Ns, NR, tstep, es, tw); break;
-        case 1: stage_bfly<R, DIR, 2>(s, d, j, Ns, NR, tstep, es, tw); break;
-        case 2: stage_bfly<R, DIR, 3>(s, d, j, Ns, NR, tstep, es, tw); break;
-        case 3: stage_bfly<R, DIR, 8>(s, d, j, Ns, NR, tstep, es, tw); break;
-        default: stage_bfly<R, DIR, 9>(s, d, j, Ns, NR, tstep, es, tw); break;
+        case 0: stage_pick<R, DIR, 4, ZIN, HOUT>(s, d, j, Ns, NR, tstep, es, tw, first, last); break;
+        case 1: stage_pick<R, DIR, 2, ZIN, HOUT>(s, d, j, Ns, NR, tstep, es, tw, first, last); break;
+        case 2: stage_pick<R, DIR, 3, ZIN, HOUT>(s, d, j, Ns, NR, tstep, es, tw, first, last); break;
+        case 3: stage_pick<R, DIR, 8, ZIN, HOUT>(s, d, j, Ns, NR, tstep, es, tw, first, last); break;
+        default: stage_pick<R, DIR, 9, ZIN, HOUT>(s, d, j, Ns, NR, tstep, es, tw, first, last); break;
       }
     }
     __syncthreads();
@@ -285,8 +325,10 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   const int f = w % 3, rb = (w / 3) % nrb, b = w / (3 * nrb);
   const long nn = (long)n * n;
   const long xb = (long)b * 2 * nn;
-  for (int e = threadIdx.x; e < nb * P; e += kT2) {
-    const int t = e / P, j = e % P;
+  // only the lower half of each row is read by the pruned first stage (n <= P/2)
+  const int Ph = P / 2;
+  for (int e = threadIdx.x; e < nb * Ph; e += kT2) {
+    const int t = e / Ph, j = e % Ph;
     const int i1 = rb * nb + t;
     C<R> v = cmk<R>(0, 0);
     if (i1 < n && j < n) {
@@ -297,10 +339,10 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
         v = p[o] * ccast<R>(ld_c<IO>(x, xb + o)) + p[nn + o] * ccast<R>(ld_c<IO>(x, xb + nn + o));
       }
     }
-    a[e] = v;
+    a[t * P + j] = v;
   }
   __syncthreads();
-  C<R>* X = lds_fft<R, -1, false>(a, bb, P, rd, nb, 1, P, tws);
+  C<R>* X = lds_fft<R, -1, false, true, false>(a, bb, P, rd, nb, 1, P, tws);
   C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
   for (int e = threadIdx.x; e < nb * P; e += kT2) {
     const int i1 = rb * nb + e / P;
@@ -341,12 +383,12 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
 #pragma unroll 1
   for (int f = 0; f < 3; ++f) {
     const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
-    for (int e = threadIdx.x; e < tot; e += kT2) {
+    for (int e = threadIdx.x; e < tot / 2; e += kT2) {   // rows below P/2 (the rest is never read)
       const int i1 = e / nb;
       a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, -1, true>(a, bb, P, rd, nb, nb, 1, tws);
+    const C<R>* X = lds_fft<R, -1, true, true, false>(a, bb, P, rd, nb, nb, 1, tws);
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
       const int e = threadIdx.x + kT2 * u;
@@ -372,7 +414,7 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
       if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, 1, true>(a, bb, P, rd, nb, nb, 1, tws);
+    const C<R>* X = lds_fft<R, 1, true, false, true>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
     C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
     for (int e = threadIdx.x; e < tot; e += kT2) {
       const int i1 = e / nb;
@@ -401,7 +443,7 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
     a[e] = i1 < n ? in[(size_t)i1 * P + e % P] : cmk<R>(0, 0);
   }
   __syncthreads();
-  const C<R>* X = lds_fft<R, 1, false>(a, bb, P, rd, nb, 1, P, tws);
+  const C<R>* X = lds_fft<R, 1, false, false, true>(a, bb, P, reverse_radices(rd), nb, 1, P, tws);
   const long nn = (long)n * n;
   const long base = ((long)b * 2 + d) * nn;
   C<IO>* yo = reinterpret_cast<C<IO>*>(y);
