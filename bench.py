@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "003c6c8a154fbb8e93717409f4c1529b9f1aa84cc93e0e6054938367796c33ad",
+    "sha256": "a92901dc08cd04cffee10877a53e3641567a074f3341d4b5f3a8d4ae2b82624e",
     "workload": (959, 8, "c64"),
-    "bytes": 1.1464e9,
+    "bytes": 1.1184e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
