@@ -39,7 +39,8 @@ namespace ls {
 
 namespace {
 
-constexpr int kT2 = 256;                 // threads per workgroup of every 2-D kernel
+constexpr int kT2 = 256;                 // threads per workgroup of the 2-D row and plan kernels
+constexpr int kTB = 512;                 // threads per workgroup of the column pass (fewer registers each)
 constexpr size_t kLds2 = 65536;          // LDS bytes a 2-D FFT workgroup may use
 constexpr size_t kLdsTarget = 32768;     // LDS bytes aimed for (five workgroups per CU)
 
@@ -152,7 +153,7 @@ __device__ __forceinline__ void stage_pick(const C<R>* s, C<R>* d, int j, int Ns
 // ZIN: the upper half of every input is zero (never read).  HOUT: only the
 // lower half of every output is used (the upper half is left unspecified).
 // Returns the buffer that holds the result.  Ends with a barrier.
-template <typename R, int DIR, bool BFAST, bool ZIN = false, bool HOUT = false>
+template <typename R, int DIR, bool BFAST, bool ZIN = false, bool HOUT = false, int NT = kT2>
 __device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, int nb, int es, int bs,
                                          const Tw<R>& tw) {
   int Ns = 1;
@@ -164,7 +165,7 @@ __device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, in
     const int tstep = P / (RR * Ns);
     const int total = nb * NR;
     const bool first = st == 0, last = st + 1 == rd.nst;
-    for (int w = threadIdx.x; w < total; w += kT2) {
+    for (int w = threadIdx.x; w < total; w += NT) {
       const int t = BFAST ? w % nb : w / NR;
       const int j = BFAST ? w / nb : w % NR;
       const C<R>* s = a + t * bs;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
 
 // pass B: block -> column block (CW = nb adjacent columns); loops over the rhs.
 template <typename R, int EMAX, int PT, int NBT>
-__global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T, C<R>* __restrict__ T2,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(const C<R>* __restrict__ T, C<R>* __restrict__ T2,
                                                       const C<R>* __restrict__ sym, int n, int P_, int H, Radices rd_,
                                                       int nb_, int nrhs, const C<R>* __restrict__ tw) {
   const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
@@ -383,15 +384,15 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
 #pragma unroll 1
   for (int f = 0; f < 3; ++f) {
     const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
-    for (int e = threadIdx.x; e < tot / 2; e += kT2) {   // rows below P/2 (the rest is never read)
+    for (int e = threadIdx.x; e < tot / 2; e += kTB) {   // rows below P/2 (the rest is never read)
       const int i1 = e / nb;
       a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, -1, true, true, false>(a, bb, P, rd, nb, nb, 1, tws);
+    const C<R>* X = lds_fft<R, -1, true, true, false, kTB>(a, bb, P, rd, nb, nb, 1, tws);
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
-      const int e = threadIdx.x + kT2 * u;
+      const int e = threadIdx.x + kTB * u;
       if (e < tot) {
         const C<R> v = X[e];
         if (f == 0) {
@@ -410,13 +411,13 @@ __global__ __launch_bounds__(kT2) void pass_b_kernel(const C<R>* __restrict__ T,
   for (int d = 0; d < 2; ++d) {
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
-      const int e = threadIdx.x + kT2 * u;
+      const int e = threadIdx.x + kTB * u;
       if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, 1, true, false, true>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
+    const C<R>* X = lds_fft<R, 1, true, false, true, kTB>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
     C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
-    for (int e = threadIdx.x; e < tot; e += kT2) {
+    for (int e = threadIdx.x; e < tot; e += kTB) {
       const int i1 = e / nb;
       if (i1 < n) out[(size_t)i1 * P + e % nb] = X[e];
     }
@@ -707,9 +708,9 @@ ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_co
     hipLaunchKernelGGL((pass_a_kernel<R, IO, PT, NBA>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
                        tw);
     LS_HIP(hipGetLastError());
-    constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kT2);
+    constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kTB);
     if (ev) LS_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kT2), ldsc, s, T, T2, sym, n, P, pl.H,
+    hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kTB), ldsc, s, T, T2, sym, n, P, pl.H,
                        pl.rd, nbc, nr, tw);
     LS_HIP(hipGetLastError());
     const int wc = nr * 2 * nrb;
