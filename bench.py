@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "a92901dc08cd04cffee10877a53e3641567a074f3341d4b5f3a8d4ae2b82624e",
+    "sha256": "795e1f9db47478c08cf0f143559e6f84ded6380e2179149e1a2bd246ad754221",
     "workload": (959, 8, "c64"),
-    "bytes": 1.1184e9,
+    "bytes": 1.1772e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 

@@ -355,9 +355,8 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
 template <typename R, int EMAX, int PT, int NBT>
 // Registers capped for four waves per SIMD (two workgroups of 62 KiB LDS per CU).
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(
-    const C<R>* __restrict__ T, C<R>* __restrict__ T2,
-                                                      const C<R>* __restrict__ sym, int n, int P_, int H, Radices rd_,
-                                                      int nb_, int nrhs, const C<R>* __restrict__ tw) {
+    const C<R>* __restrict__ T, C<R>* __restrict__ T2, const C<R>* __restrict__ sym, int n, int P_, int H,
+    Radices rd_, int nb_, int nrhs, const C<R>* __restrict__ tw) {
   const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
   const Radices rd = PT > 0 ? factor_radices(PT) : rd_;
   extern __shared__ unsigned char lds_raw[];
