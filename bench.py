@@ -109,6 +109,29 @@ def cpu_baseline(n: int, seconds: float = 15.0):
                       f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
 
 
+def cpu_baseline_2d(n: int = 959, seconds: float = 5.0):
+    """The oracle's 2-D FFT apply on the host, one rhs at a time (the 2-D
+    variant's counterpart of ``cpu_baseline``)."""
+    from oracle import two_d as o2
+    from paper_1804_02297_amd import inputs as I
+    k = I.paper_wavenumber(n)
+    m = I.medium2_perturbed_square(n, 3)
+    x = I.random_field2(1, n, 5)[0]
+    t0 = time.perf_counter()
+    sym = o2.symbol2(n, k)
+    t_setup = time.perf_counter() - t0
+    reps, t_apply = 0, 0.0
+    while t_apply < seconds and reps < 20:
+        t0 = time.perf_counter()
+        o2.apply_fft2(n, k, m, x, sym)
+        t_apply += time.perf_counter() - t0
+        reps += 1
+    per = t_apply / reps
+    return {"value": round(2 * n * n / per / 1e6, 3), "unit": "Munknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle 2-D FFT apply (scipy.fft, 1 worker, FP64, P = {2 * n}) of 1 rhs at n={n}, "
+                      f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
+
+
 def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, train_steps: int = 1500,
                   exact_iters: bool = True, host_factor_chosen: bool = False, host_factor_plain: bool = False):
     """Per-rhs time to a 1e-8 relative residual: plain FP64 against the chosen form.
@@ -534,6 +557,8 @@ def main():
                                      host_factor_chosen=hf, host_factor_plain=hf)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        if args.two_d_n:
+            out["cpu_baseline"]["two_d"] = cpu_baseline_2d(args.two_d_n)
     print(json.dumps(out), flush=True)
     plan.close()
 
