@@ -40,6 +40,27 @@ def test_apply_matches_oracle(lib, n):
     plan.close()
 
 
+@pytest.mark.parametrize("n", [119, 239, 479])
+def test_apply_paper_lengths(lib, n):
+    """The kernels compiled for the paper's FFT lengths (P = 256, 486, 972 at
+    n = 119, 239, 479), element by element against the oracle's FFT apply
+    (itself pinned to the double sum), two rhs, all three precisions."""
+    from paper_1804_02297_amd.binding import Plan2
+    k = I.paper_wavenumber(n)
+    m = I.medium2_perturbed_square(n, n)
+    x = I.random_field2(2, n, 7 + n)
+    print(f"n={n}", flush=True)
+    plan = Plan2(n, k, _dev(m), max_rhs=2)
+    assert plan.P == {119: 256, 239: 486, 479: 972}[n]
+    ref = o2.apply_fft2(n, k, m, x)
+    scale = np.abs(ref).max()
+    assert np.abs(plan.apply(_dev(x)).cpu().numpy() - ref).max() <= 1e-12 * scale
+    assert np.abs(plan.apply(_dev(x), prec="mixed").cpu().numpy() - ref).max() <= 2e-5 * scale
+    y = plan.apply(_dev(x.astype(np.complex64)), prec="c64").cpu().numpy()
+    assert np.abs(y - ref).max() <= 2e-5 * scale
+    plan.close()
+
+
 def test_rhs_and_dense_definition(lib):
     """The right-hand side, and the apply against the literal double sum."""
     from paper_1804_02297_amd.binding import Plan2
