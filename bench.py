@@ -47,7 +47,7 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "795e1f9db47478c08cf0f143559e6f84ded6380e2179149e1a2bd246ad754221",
+    "sha256": "e122519a46b570cd486166c04bf6e3af23766e59a67e0a9d363cb2418ca7d69a",
     "workload": (959, 8, "c64"),
     "bytes": 1.1772e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",

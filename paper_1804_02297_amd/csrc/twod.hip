@@ -13,27 +13,29 @@
 // P >= 2n - 1, even, 2^a 3^b) held in LDS.
 //   pass A  rows:    u_f = (m x_1, m x_2, p.x) per row, zero-padded, FFT
 //                    along i2; [rhs][3][n][P] in HBM;
-//   pass B  columns: per block of CW adjacent columns, for every rhs: FFT of
-//                    the three fields along i1, the 2x3 symbol multiply in
-//                    registers, two inverse FFTs, rows i1 < n kept;
+//   pass B  columns: per workgroup one rhs and a few adjacent columns: FFT
+//                    of the three fields along i1, the 2x3 symbol multiply
+//                    in registers, two inverse FFTs, rows i1 < n kept;
 //                    [rhs][2][n][P];
 //   pass C  rows:    inverse FFT along i2, the first n kept, + x.
 // The symbol (k^2 Ghat, Ghat^1, Ghat^2) / P^2 is stored on the quadrant
 // [H][H][3], H = P/2 + 1: k^2 Ghat is even in both frequencies, Ghat^1 is
-// odd in q1 and even in q2, Ghat^2 the reverse.
+// odd in q1 and even in q2, Ghat^2 the reverse.  The paper's lengths
+// (P = 256, 486, 972, 1944) have the passes compiled for them; forward
+// transforms skip their zero upper half, inverse ones the unused half of
+// their output.
 #include "twod.h"
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <new>
 #include <vector>
 
 #include "gpu_solver.h"
 #include "host_solver.h"
-
-#include <cstring>
 
 namespace ls {
 
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   }
 }
 
-// pass B: block -> column block (CW = nb adjacent columns); loops over the rhs.
+// pass B: block -> (rhs, block of nb adjacent columns).
 template <typename R, int EMAX, int PT, int NBT>
 // Registers capped for four waves per SIMD (two workgroups of 62 KiB LDS per CU).
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(
@@ -372,7 +374,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int q0 = (w / nrhs) * nb;
   const int tot = nb * P;
   // symbol at the element e of the column block: q1 = e / nb, q2 = q0 + e % nb, read
-  // from the quadrant (L1/L2-resident: one block's columns share it over the rhs)
+  // from the quadrant at use (the same columns' blocks of the other rhs read the
+  // same lines beside it on the XCD)
   auto symv = [&](int e, int c) -> C<R> {
     const int q1 = e / nb, q2 = q0 + e % nb;
     const bool f1 = q1 > P / 2, f2 = q2 > P / 2;
@@ -556,7 +559,7 @@ __global__ void gram2_reduce_kernel(const C<double>* __restrict__ partial, C<dou
 }
 
 // Rows of Q ([point][2 rows][9 slots][2 comps]) and of S in the 27-slot form of
-// the host factor ([point][2][27][2], slot 9 (s1+1) + 3 (s2+1) + 1):
+// the sparse factors ([point][2][27][2], slot 9 (s1+1) + 3 (s2+1) + 1):
 //   Q = conj(alpha[2t+c][r]),  S = Q + conj(beta[3t+c][r]) m_j + conj(beta[3t+2][r]) p^c_j,  j = i + tau[t]
 __global__ void rows2_kernel(const C<double>* __restrict__ alpha, const C<double>* __restrict__ beta,
                              const C<double>* __restrict__ m, const C<double>* __restrict__ p,
