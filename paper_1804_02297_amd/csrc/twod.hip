@@ -385,14 +385,30 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     return neg ? cmk<R>(-v.re, -v.im) : v;
   };
   C<R> o0[EMAX], o1[EMAX];
+  // the next field's column is loaded into registers while the current one
+  // is transformed (rows below P/2 only: the rest is never read)
+  constexpr int UL = (EMAX + 1) / 2;
+  C<R> pf[UL];
+  auto fetch = [&](int f) {
+    const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int e = threadIdx.x + kTB * u;
+      C<R> v = cmk<R>(0, 0);
+      if (e < tot / 2 && e / nb < n) v = in[(size_t)(e / nb) * P + e % nb];
+      pf[u] = v;
+    }
+  };
+  fetch(0);
 #pragma unroll 1
   for (int f = 0; f < 3; ++f) {
-    const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
-    for (int e = threadIdx.x; e < tot / 2; e += kTB) {   // rows below P/2 (the rest is never read)
-      const int i1 = e / nb;
-      a[e] = i1 < n ? in[(size_t)i1 * P + e % nb] : cmk<R>(0, 0);
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int e = threadIdx.x + kTB * u;
+      if (e < tot / 2) a[e] = pf[u];
     }
     __syncthreads();
+    if (f < 2) fetch(f + 1);
     const C<R>* X = lds_fft<R, -1, true, true, false, kTB>(a, bb, P, rd, nb, nb, 1, tws);
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
