@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "e122519a46b570cd486166c04bf6e3af23766e59a67e0a9d363cb2418ca7d69a",
+    "sha256": "eb10bcc6b9bf2abe9481e90901abdace63629ffddb8da1bfb33b83bfdf2c3c47",
     "workload": (959, 8, "c64"),
-    "bytes": 1.1772e9,
+    "bytes": 1.3456e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
