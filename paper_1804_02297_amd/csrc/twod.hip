@@ -311,7 +311,8 @@ __global__ void gradient_kernel(const C<double>* __restrict__ m, C<double>* __re
 template <typename T>
 __device__ __forceinline__ C<T> ld_c(const void* p, long i) { return reinterpret_cast<const C<T>*>(p)[i]; }
 
-// pass A: block w -> (rhs b, row block rb, field f), f fastest.
+// pass A: block w -> (rhs b, row block rb); the three fields of its rows in
+// turn, from x, m and p loaded once into registers.
 template <typename R, typename IO, int PT, int NBT>
 __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x, const C<R>* __restrict__ m,
                                                       const C<R>* __restrict__ p, C<R>* __restrict__ T, int n, int P_,
@@ -325,37 +326,56 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   C<R>* bb = a + (size_t)nb * P;
   const Tw<R> tws = load_twiddles(bb + (size_t)nb * P, tw, P);
   const int w = xcd_work_index(blockIdx.x, nwork);
-  const int f = w % 3, rb = (w / 3) % nrb, b = w / (3 * nrb);
+  const int rb = w % nrb, b = w / nrb;
   const long nn = (long)n * n;
   const long xb = (long)b * 2 * nn;
-  // only the lower half of each row is read by the pruned first stage (n <= P/2)
+  // only the lower half of each row is read by the pruned first stage (n <= P/2);
+  // nb P / 2 <= UA kT2: nb P is at most what two buffers of kLdsTarget hold, or
+  // one row of the largest P when a single row exceeds that
+  constexpr size_t kHalfMax = std::max<size_t>(kLdsTarget / (2 * sizeof(C<R>)), kMaxP2) / 2;
+  constexpr int UA = (int)((kHalfMax + kT2 - 1) / kT2);
   const int Ph = P / 2;
-  for (int e = threadIdx.x; e < nb * Ph; e += kT2) {
+  C<R> rx0[UA], rx1[UA], rm[UA], rp0[UA], rp1[UA];
+#pragma unroll
+  for (int u = 0; u < UA; ++u) {
+    const int e = threadIdx.x + kT2 * u;
     const int t = e / Ph, j = e % Ph;
     const int i1 = rb * nb + t;
-    C<R> v = cmk<R>(0, 0);
-    if (i1 < n && j < n) {
+    const C<R> z = cmk<R>(0, 0);
+    rx0[u] = rx1[u] = rm[u] = rp0[u] = rp1[u] = z;
+    if (e < nb * Ph && i1 < n && j < n) {
       const long o = (long)i1 * n + j;
-      if (f < 2) {
-        v = m[o] * ccast<R>(ld_c<IO>(x, xb + f * nn + o));
-      } else {
-        v = p[o] * ccast<R>(ld_c<IO>(x, xb + o)) + p[nn + o] * ccast<R>(ld_c<IO>(x, xb + nn + o));
+      rx0[u] = ccast<R>(ld_c<IO>(x, xb + o));
+      rx1[u] = ccast<R>(ld_c<IO>(x, xb + nn + o));
+      rm[u] = m[o];
+      rp0[u] = p[o];
+      rp1[u] = p[nn + o];
+    }
+  }
+#pragma unroll 1
+  for (int f = 0; f < 3; ++f) {
+#pragma unroll
+    for (int u = 0; u < UA; ++u) {
+      const int e = threadIdx.x + kT2 * u;
+      if (e < nb * Ph) {
+        const C<R> v = f == 0 ? rm[u] * rx0[u] : (f == 1 ? rm[u] * rx1[u] : rp0[u] * rx0[u] + rp1[u] * rx1[u]);
+        a[(e / Ph) * P + e % Ph] = v;
       }
     }
-    a[t * P + j] = v;
-  }
-  __syncthreads();
-  C<R>* X = lds_fft<R, -1, false, true, false>(a, bb, P, rd, nb, 1, P, tws);
-  C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
-  for (int e = threadIdx.x; e < nb * P; e += kT2) {
-    const int i1 = rb * nb + e / P;
-    if (i1 < n) out[(size_t)i1 * P + e % P] = X[e];
+    __syncthreads();
+    const C<R>* X = lds_fft<R, -1, false, true, false>(a, bb, P, rd, nb, 1, P, tws);
+    C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
+    for (int e = threadIdx.x; e < nb * P; e += kT2) {
+      const int i1 = rb * nb + e / P;
+      if (i1 < n) out[(size_t)i1 * P + e % P] = X[e];
+    }
+    __syncthreads();   // X may be the buffer the next field is written to
   }
 }
 
-// pass B: block -> (rhs, block of nb adjacent columns).
+// pass B: block -> (rhs, block of nb adjacent columns).  Registers capped for
+// four waves per SIMD (two workgroups of 62 KiB LDS per CU).
 template <typename R, int EMAX, int PT, int NBT>
-// Registers capped for four waves per SIMD (two workgroups of 62 KiB LDS per CU).
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(
     const C<R>* __restrict__ T, C<R>* __restrict__ T2, const C<R>* __restrict__ sym, int n, int P_, int H,
     Radices rd_, int nb_, int nrhs, const C<R>* __restrict__ tw) {
@@ -723,7 +743,7 @@ ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_co
     const size_t off = (size_t)r0 * 2 * n * n * sizeof(C<IO>);
     const void* xr = (const unsigned char*)x + off;
     void* yr = (unsigned char*)y + off;
-    const int wa = nr * nrb * 3;
+    const int wa = nr * nrb;
     if (ev) LS_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL((pass_a_kernel<R, IO, PT, NBA>), dim3(wa), dim3(kT2), lds, s, xr, m, p, T, n, P, pl.rd, nb, nrb, wa,
                        tw);
