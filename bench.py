@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "eb10bcc6b9bf2abe9481e90901abdace63629ffddb8da1bfb33b83bfdf2c3c47",
+    "sha256": "e2cc0aeb03286e34794e11781e9da0c352709fcbbedfdd711512e93e509eeabe",
     "workload": (959, 8, "c64"),
-    "bytes": 1.3456e9,
+    "bytes": 1.3758e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
