@@ -561,13 +561,23 @@ __global__ __launch_bounds__(256) void copyout_kernel(const FrontDev* __restrict
 
 // b (complex128 [nrhs][N]) -> X ([N][nrhs] in elimination order, split planes);
 // four unknowns per workgroup pass, the right-hand sides across 64 lanes
+// Lanes of a 256-thread workgroup given to one row's right-hand sides (the
+// smallest power of two >= nrhs, at most 64); the workgroup covers 256 / lanes
+// rows per pass.  One rhs: a row per thread.
+__host__ __device__ inline int rhs_lanes(int nrhs) {
+  int l = 1;
+  while (l < nrhs && l < 64) l *= 2;
+  return l;
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void sol_in_kernel(const C<double>* __restrict__ b, long N, int nrhs,
                                                      const int* __restrict__ perm, R* __restrict__ Xr,
                                                      R* __restrict__ Xi) {
-  for (long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6); e < N; e += (long)gridDim.x * 4) {
+  const int lanes = rhs_lanes(nrhs), rpp = 256 / lanes;
+  for (long e = (long)blockIdx.x * rpp + threadIdx.x / lanes; e < N; e += (long)gridDim.x * rpp) {
     const long pe = perm[e];
-    for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+    for (int r = threadIdx.x % lanes; r < nrhs; r += lanes) {
       const C<double> v = b[r * N + pe];
       Xr[e * nrhs + r] = (R)v.re;
       Xi[e * nrhs + r] = (R)v.im;
@@ -579,15 +589,16 @@ template <typename R>
 __global__ __launch_bounds__(256) void sol_out_kernel(C<double>* __restrict__ b, long N, int nrhs,
                                                       const int* __restrict__ perm, const R* __restrict__ Xr,
                                                       const R* __restrict__ Xi) {
-  for (long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6); e < N; e += (long)gridDim.x * 4) {
+  const int lanes = rhs_lanes(nrhs), rpp = 256 / lanes;
+  for (long e = (long)blockIdx.x * rpp + threadIdx.x / lanes; e < N; e += (long)gridDim.x * rpp) {
     const long pe = perm[e];
-    for (int r = threadIdx.x & 63; r < nrhs; r += 64)
+    for (int r = threadIdx.x % lanes; r < nrhs; r += lanes)
       b[r * N + pe] = cmk((double)Xr[e * nrhs + r], (double)Xi[e * nrhs + r]);
   }
 }
 
 // children's update vectors into the pivot rows (x) or the update vector (u)
-// of every front of a level, for child `slot`; four rows per workgroup pass
+// of every front of a level, for child `slot`; 256 / rhs_lanes(nrhs) rows per workgroup pass
 template <typename R, int NC>
 __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                         int nlvl, int slot, const int* __restrict__ ib, int nrhs,
@@ -597,14 +608,15 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
     const FrontDev d = fr[lvl[q]];
     if (d.child[slot] < 0) continue;
     const FrontDev c = fr[d.child[slot]];
-    for (int rr = blockIdx.x * 4 + (threadIdx.x >> 6); rr < c.nb; rr += gridDim.x * 4) {
+    const int lanes = rhs_lanes(nrhs), rpp = 256 / lanes;
+    for (int rr = blockIdx.x * rpp + threadIdx.x / lanes; rr < c.nb; rr += gridDim.x * rpp) {
       const int pos = NC * ib[c.xm + rr / NC] + rr % NC;
       const bool piv = pos < d.np;
       const long src = (c.u + rr) * nrhs;
       const long dst = piv ? (long)(d.e0 + pos) * nrhs : (d.u + pos - d.np) * nrhs;
       R* Tr = piv ? Xr : Ur;
       R* Ti = piv ? Xi : Ui;
-      for (int r = threadIdx.x & 63; r < nrhs; r += 64) {
+      for (int r = threadIdx.x % lanes; r < nrhs; r += lanes) {
         Tr[dst + r] += Ur[src + r];
         Ti[dst + r] += Ui[src + r];
       }
@@ -1555,7 +1567,8 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
   const int* ib = g.ib.as<int>();
   const R* fac = g.fac.as<R>();
   const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
-  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
+  const int rpp = 256 / rhs_lanes(nrhs);     // rows per workgroup pass of the gather kernels
+  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
   hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
                      s, Ur, 2 * std::max(1L, g.u_rows) * nrhs);
   for (int dep = L - 1; dep >= 0; --dep) {
@@ -1570,7 +1583,7 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
           if (g.fh[id].child[slot] >= 0) mcnb = std::max(mcnb, (long)g.fh[g.fh[id].child[slot]].nb);
         if (mcnb == 0) continue;
         // one front per workgroup row (a front loop would chain descriptor loads)
-        const long gxc = std::max(1L, std::min((mcnb + 3) / 4, std::max(1L, 65536L / nl)));
+        const long gxc = std::max(1L, std::min((mcnb + rpp - 1) / rpp, std::max(1L, 65536L / nl)));
         if (g.nc == 3)
           hipLaunchKernelGGL((fwd_child_kernel<R, 3>), dim3((unsigned)gxc, gy), dim3(256), 0, s, fr, lvl, nl, slot,
                              ib, nrhs, Xr, Xi, Ur, Ui);
@@ -1601,7 +1614,7 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                          Xi, Zr, Zi);
     }
   }
-  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, 4, 65535)), dim3(256), 0, s, xo, N, nrhs, ib, (const R*)Xr,
+  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, xo, N, nrhs, ib, (const R*)Xr,
                      (const R*)Xi);
   LS_HIP(hipGetLastError());
   return LS_OK;
