@@ -1279,6 +1279,117 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
   }
 }
 
+// Few right-hand sides (at most kGemvRhs): the products of fwd_sb_kernel
+// (FWD) and bwd_sb_kernel as matrix-vector products, a wave per row with the
+// block's vector in LDS (the 64-rhs MFMA tiles would compute mostly zero
+// columns).  Same grid and the same rows read and written as those kernels.
+constexpr int kGemvRhs = 4;
+template <typename R, bool FWD>
+__global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
+                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
+                                                      R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
+  constexpr int NZB = kSB / kRB;
+  __shared__ R vr_[kSB * kGemvRhs], vi_[kSB * kGemvRhs];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool brole = (int)blockIdx.x < NZB;      // rows of the block (M or H) or rows outside it
+  // the block's vector: x rows (forward) or y rows (backward) of the block
+  const R* Vr = FWD ? Xr : Zr;
+  const R* Vi = FWD ? Xi : Zi;
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    if (kb0 >= d.np) continue;
+    const int sw = min(kSB, d.np - kb0);
+    const long nf = d.nf, np = d.np;
+    long i0;
+    int cnt;
+    if (brole) {
+      i0 = (long)blockIdx.x * kRB;
+      if (i0 >= sw) continue;
+      cnt = (int)min((long)kRB, sw - i0);
+    } else if (FWD) {
+      i0 = kb0 + sw + (long)(blockIdx.x - NZB) * kRB;   // rows below the block
+      if (i0 >= nf) continue;
+      cnt = (int)min((long)kRB, nf - i0);
+    } else {
+      i0 = (long)(blockIdx.x - NZB) * kRB;              // rows above the block
+      if (i0 >= kb0) continue;
+      cnt = (int)min((long)kRB, kb0 - i0);
+    }
+    for (int e = tid; e < sw * nrhs; e += 256) {
+      const int k = e / nrhs, r = e % nrhs;
+      vr_[k * kGemvRhs + r] = Vr[(d.e0 + kb0 + k) * (long)nrhs + r];
+      vi_[k * kGemvRhs + r] = Vi[(d.e0 + kb0 + k) * (long)nrhs + r];
+    }
+    __syncthreads();
+    const R* Br = fac + (FWD ? d.m : d.h) + (long)(kb0 / kSB) * 2 * kSB * kSB;   // M (forward) or H
+    const R* Bi = Br + kSB * kSB;
+    for (int row = wave; row < cnt; row += 4) {
+      const long gi = i0 + row;
+      const R* ar;
+      const R* ai;
+      if (brole) {
+        ar = Br + gi * kSB;
+        ai = Bi + gi * kSB;
+      } else if (!FWD || gi < np) {
+        ar = fac + d.p + gi * nf + kb0;
+        ai = fac + d.p + np * nf + gi * nf + kb0;
+      } else {
+        ar = fac + d.l + (gi - np) * np + kb0;
+        ai = fac + d.l + (long)d.nb * np + (gi - np) * np + kb0;
+      }
+      R sr[kGemvRhs], si[kGemvRhs];
+#pragma unroll
+      for (int r = 0; r < kGemvRhs; ++r) sr[r] = si[r] = R(0);
+      for (int k = lane; k < sw; k += 64) {
+        const R a = ar[k], b = ai[k];
+#pragma unroll
+        for (int r = 0; r < kGemvRhs; ++r) {
+          if (r < nrhs) {
+            const R xr = vr_[k * kGemvRhs + r], xi = vi_[k * kGemvRhs + r];
+            sr[r] += a * xr - b * xi;
+            si[r] += a * xi + b * xr;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kGemvRhs; ++r)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          sr[r] += __shfl_xor(sr[r], off);
+          si[r] += __shfl_xor(si[r], off);
+        }
+      if (lane < nrhs) {
+        R vr = sr[0], vi = si[0];
+#pragma unroll
+        for (int r = 1; r < kGemvRhs; ++r)
+          if (lane == r) {
+            vr = sr[r];
+            vi = si[r];
+          }
+        const int r = lane;
+        if (brole) {
+          // z (forward) or x (backward) rows of the block
+          R* Or = FWD ? Zr : Xr;
+          R* Oi = FWD ? Zi : Xi;
+          Or[(d.e0 + kb0 + gi) * nrhs + r] = vr;
+          Oi[(d.e0 + kb0 + gi) * nrhs + r] = vi;
+        } else if (FWD) {
+          const long dst = gi < np ? (d.e0 + gi) * nrhs + r : (d.u + gi - np) * nrhs + r;
+          R* Tr = gi < np ? Xr : Ur;
+          R* Ti = gi < np ? Xi : Ui;
+          Tr[dst] -= vr;
+          Ti[dst] -= vi;
+        } else {
+          Zr[(d.e0 + gi) * nrhs + r] -= vr;
+          Zi[(d.e0 + gi) * nrhs + r] -= vi;
+        }
+      }
+    }
+    __syncthreads();   // the vector is restaged for the next front
+  }
+}
+
 inline unsigned grid_for(long work, long per = 256, long cap = 65535) {
   long g = (work + per - 1) / per;
   return (unsigned)std::max(1L, std::min(g, cap));
@@ -1593,8 +1704,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kSB) {
       const unsigned gx = (unsigned)(kSB / kRB + std::max(0L, (mnf - kb0 - 1 + kRB - 1) / kRB));
-      hipLaunchKernelGGL(fwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs, Xr,
-                         Xi, Zr, Zi, Ur, Ui);
+      if (nrhs <= kGemvRhs)
+        hipLaunchKernelGGL((sb_gemv_kernel<R, true>), dim3(gx, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
+                           nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
+      else
+        hipLaunchKernelGGL(fwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
+                           Xr, Xi, Zr, Zi, Ur, Ui);
     }
   }
   for (int dep = 0; dep < L; ++dep) {
@@ -1610,8 +1725,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                          nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
     for (long kb0 = ((mnp - 1) / kSB) * kSB; kb0 >= 0; kb0 -= kSB) {
       const unsigned gx = (unsigned)(kSB / kRB + (kb0 + kRB - 1) / kRB);
-      hipLaunchKernelGGL(bwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs, Xr,
-                         Xi, Zr, Zi);
+      if (nrhs <= kGemvRhs)
+        hipLaunchKernelGGL((sb_gemv_kernel<R, false>), dim3(gx, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
+                           nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
+      else
+        hipLaunchKernelGGL(bwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
+                           Xr, Xi, Zr, Zi);
     }
   }
   hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, xo, N, nrhs, ib, (const R*)Xr,

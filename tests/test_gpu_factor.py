@@ -6,8 +6,11 @@ LU solve: a complex128 factor to 1e-10 of the solution's size (the host
 factor's bar), a complex64 factor to single precision.  Larger grids, where
 splu is too slow for a test: the residual ||S x - b|| / ||b|| with S applied
 from its rows by a plain numpy stencil sum (a property that holds at any
-size).  Block solves must equal one-at-a-time solves bitwise (every right-hand
-side takes the same arithmetic).
+size).  Solves of up to four right-hand sides take the matrix-vector path
+and equal one-at-a-time solves bitwise; larger blocks take the MFMA path,
+bitwise equal among themselves (every right-hand side takes the same
+arithmetic) and equal to the single solves to rounding (another summation
+order).
 """
 import ctypes
 
@@ -108,16 +111,22 @@ def test_gpu_factor_equals_host_factor(lib):
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_block_solve_equals_single_solves(lib, prec):
     """nrhs across the 64-rhs workgroup chunks of the solve kernels, ragged
-    last chunk: bitwise."""
+    last chunk: bitwise within each path (matrix-vector up to four rhs, MFMA
+    above), and the two paths equal to rounding."""
     from paper_1804_02297_amd.binding import SparseGpu
     n = 9
     _, rows = _oracle_system(n, 6)
     sp = SparseGpu(n, rows, prec=prec)
     b = I.random_field(70, n, 80)
     single = np.stack([sp.solve(_dev(b[i:i + 1])).cpu().numpy()[0] for i in range(len(b))])
-    for nr in (2, 17, 33, 64, 65, 70):
+    for nr in (2, 3, 4):
+        assert np.array_equal(sp.solve(_dev(b[:nr])).cpu().numpy(), single[:nr]), nr
+    full = sp.solve(_dev(b)).cpu().numpy()
+    tol = 1e-12 if prec == "c128" else 2e-5
+    assert np.abs(full - single).max() <= tol * np.abs(single).max()
+    for nr in (5, 17, 33, 64, 65):
         xb = sp.solve(_dev(b[:nr])).cpu().numpy()
-        assert np.array_equal(xb, single[:nr]), nr
+        assert np.array_equal(xb, full[:nr]), nr
 
 
 @pytest.mark.parametrize("n", [32, 48])
