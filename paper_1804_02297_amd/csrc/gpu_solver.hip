@@ -1390,6 +1390,83 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
   }
 }
 
+// Few right-hand sides: bwd_u12_kernel as matrix-vector products, a wave per
+// pivot row over the split's kKS boundary columns (gathered x in LDS); the
+// same outputs (in place with one split, else the split's partial sums).
+template <typename R>
+__global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+                                                       int nlvl, int nks_max, long np_max,
+                                                       const R* __restrict__ fac, const int* __restrict__ ib, int nrhs,
+                                                       const R* __restrict__ Xr, const R* __restrict__ Xi,
+                                                       R* __restrict__ Zr, R* __restrict__ Zi, R* __restrict__ Pr,
+                                                       R* __restrict__ Pi) {
+  __shared__ R vr_[kKS * kGemvRhs], vi_[kKS * kGemvRhs];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ks = blockIdx.z;
+  for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    const FrontDev d = fr[lvl[q]];
+    const long np = d.np, nf = d.nf, nb = d.nb;
+    const int nks = (int)((nb + kKS - 1) / kKS);
+    if (ks >= nks) continue;
+    const long i0 = (long)blockIdx.x * kRB;
+    if (i0 >= np) continue;
+    const int cnt = (int)min((long)kRB, np - i0);
+    const long j0 = (long)ks * kKS;
+    const int nj = (int)min((long)kKS, nb - j0);
+    for (int e = tid; e < nj * nrhs; e += 256) {
+      const int j = e / nrhs, r = e % nrhs;
+      const long x = ib[d.bm + j0 + j];
+      vr_[j * kGemvRhs + r] = Xr[x * nrhs + r];
+      vi_[j * kGemvRhs + r] = Xi[x * nrhs + r];
+    }
+    __syncthreads();
+    for (int row = wave; row < cnt; row += 4) {
+      const long gi = i0 + row;
+      const R* ar = fac + d.p + gi * nf + np + j0;
+      const R* ai = fac + d.p + np * nf + gi * nf + np + j0;
+      R sr[kGemvRhs], si[kGemvRhs];
+#pragma unroll
+      for (int r = 0; r < kGemvRhs; ++r) sr[r] = si[r] = R(0);
+      for (int j = lane; j < nj; j += 64) {
+        const R a = ar[j], b = ai[j];
+#pragma unroll
+        for (int r = 0; r < kGemvRhs; ++r) {
+          if (r < nrhs) {
+            const R xr = vr_[j * kGemvRhs + r], xi = vi_[j * kGemvRhs + r];
+            sr[r] += a * xr - b * xi;
+            si[r] += a * xi + b * xr;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kGemvRhs; ++r)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          sr[r] += __shfl_xor(sr[r], off);
+          si[r] += __shfl_xor(si[r], off);
+        }
+      if (lane < nrhs) {
+        R vr = sr[0], vi = si[0];
+#pragma unroll
+        for (int r = 1; r < kGemvRhs; ++r)
+          if (lane == r) {
+            vr = sr[r];
+            vi = si[r];
+          }
+        if (nks == 1) {
+          Zr[(d.e0 + gi) * nrhs + lane] -= vr;
+          Zi[(d.e0 + gi) * nrhs + lane] -= vi;
+        } else {
+          const long o = (((long)q * nks_max + ks) * np_max + gi) * nrhs + lane;
+          Pr[o] = vr;
+          Pi[o] = vi;
+        }
+      }
+    }
+    __syncthreads();   // the gathered vector is restaged for the next front
+  }
+}
+
 inline unsigned grid_for(long work, long per = 256, long cap = 65535) {
   long g = (work + per - 1) / per;
   return (unsigned)std::max(1L, std::min(g, cap));
@@ -1718,8 +1795,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
     const unsigned gy = (unsigned)std::min(nl, 65535);
     const long mnp = g.lvl_np[dep];
     const unsigned gu = (unsigned)std::max(1L, (mnp + kRB - 1) / kRB);
-    hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
-                       fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
+    if (nrhs <= kGemvRhs)
+      hipLaunchKernelGGL(u12_gemv_kernel<R>, dim3(gu, gy, nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
+                         fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
+    else
+      hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep],
+                         mnp, fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
     if (nks[dep] > 1)
       hipLaunchKernelGGL(u12_reduce_kernel<R>, dim3(grid_for(mnp, 4, 4096), gy), dim3(256), 0, s, fr, lvl, nl,
                          nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
