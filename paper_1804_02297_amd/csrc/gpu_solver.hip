@@ -1280,10 +1280,11 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
 }
 
 // Few right-hand sides (at most kGemvRhs): the products of fwd_sb_kernel
-// (FWD) and bwd_sb_kernel as matrix-vector products, a wave per row with the
-// block's vector in LDS (the 64-rhs MFMA tiles would compute mostly zero
+// (FWD) and bwd_sb_kernel as matrix-vector products, kGemvLanes lanes per
+// row with the block's vector in LDS (the 64-rhs MFMA tiles would compute mostly zero
 // columns).  Same grid and the same rows read and written as those kernels.
 constexpr int kGemvRhs = 4;
+constexpr int kGemvLanes = 16;   // lanes per row: four rows per wave, 128-byte row segments per load
 template <typename R, bool FWD>
 __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                       int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
@@ -1291,7 +1292,7 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
                                                       R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
   constexpr int NZB = kSB / kRB;
   __shared__ R vr_[kSB * kGemvRhs], vi_[kSB * kGemvRhs];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, sub = tid % kGemvLanes;
   const bool brole = (int)blockIdx.x < NZB;      // rows of the block (M or H) or rows outside it
   // the block's vector: x rows (forward) or y rows (backward) of the block
   const R* Vr = FWD ? Xr : Zr;
@@ -1324,7 +1325,7 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
     __syncthreads();
     const R* Br = fac + (FWD ? d.m : d.h) + (long)(kb0 / kSB) * 2 * kSB * kSB;   // M (forward) or H
     const R* Bi = Br + kSB * kSB;
-    for (int row = wave; row < cnt; row += 4) {
+    for (int row = tid / kGemvLanes; row < cnt; row += 256 / kGemvLanes) {
       const long gi = i0 + row;
       const R* ar;
       const R* ai;
@@ -1341,7 +1342,7 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
       R sr[kGemvRhs], si[kGemvRhs];
 #pragma unroll
       for (int r = 0; r < kGemvRhs; ++r) sr[r] = si[r] = R(0);
-      for (int k = lane; k < sw; k += 64) {
+      for (int k = sub; k < sw; k += kGemvLanes) {
         const R a = ar[k], b = ai[k];
 #pragma unroll
         for (int r = 0; r < kGemvRhs; ++r) {
@@ -1354,20 +1355,21 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
       }
 #pragma unroll
       for (int r = 0; r < kGemvRhs; ++r)
+        if (r < nrhs)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          sr[r] += __shfl_xor(sr[r], off);
-          si[r] += __shfl_xor(si[r], off);
-        }
-      if (lane < nrhs) {
+          for (int off = kGemvLanes / 2; off > 0; off >>= 1) {
+            sr[r] += __shfl_xor(sr[r], off);
+            si[r] += __shfl_xor(si[r], off);
+          }
+      if (sub < nrhs) {
         R vr = sr[0], vi = si[0];
 #pragma unroll
         for (int r = 1; r < kGemvRhs; ++r)
-          if (lane == r) {
+          if (sub == r) {
             vr = sr[r];
             vi = si[r];
           }
-        const int r = lane;
+        const int r = sub;
         if (brole) {
           // z (forward) or x (backward) rows of the block
           R* Or = FWD ? Zr : Xr;
@@ -1390,8 +1392,8 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
   }
 }
 
-// Few right-hand sides: bwd_u12_kernel as matrix-vector products, a wave per
-// pivot row over the split's kKS boundary columns (gathered x in LDS); the
+// Few right-hand sides: bwd_u12_kernel as matrix-vector products,
+// kGemvLanes lanes per pivot row over the split's kKS boundary columns (gathered x in LDS); the
 // same outputs (in place with one split, else the split's partial sums).
 template <typename R>
 __global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
@@ -1401,7 +1403,7 @@ __global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restric
                                                        R* __restrict__ Zr, R* __restrict__ Zi, R* __restrict__ Pr,
                                                        R* __restrict__ Pi) {
   __shared__ R vr_[kKS * kGemvRhs], vi_[kKS * kGemvRhs];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, sub = tid % kGemvLanes;
   const int ks = blockIdx.z;
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
@@ -1420,14 +1422,14 @@ __global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restric
       vi_[j * kGemvRhs + r] = Xi[x * nrhs + r];
     }
     __syncthreads();
-    for (int row = wave; row < cnt; row += 4) {
+    for (int row = tid / kGemvLanes; row < cnt; row += 256 / kGemvLanes) {
       const long gi = i0 + row;
       const R* ar = fac + d.p + gi * nf + np + j0;
       const R* ai = fac + d.p + np * nf + gi * nf + np + j0;
       R sr[kGemvRhs], si[kGemvRhs];
 #pragma unroll
       for (int r = 0; r < kGemvRhs; ++r) sr[r] = si[r] = R(0);
-      for (int j = lane; j < nj; j += 64) {
+      for (int j = sub; j < nj; j += kGemvLanes) {
         const R a = ar[j], b = ai[j];
 #pragma unroll
         for (int r = 0; r < kGemvRhs; ++r) {
@@ -1440,24 +1442,25 @@ __global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restric
       }
 #pragma unroll
       for (int r = 0; r < kGemvRhs; ++r)
+        if (r < nrhs)
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          sr[r] += __shfl_xor(sr[r], off);
-          si[r] += __shfl_xor(si[r], off);
-        }
-      if (lane < nrhs) {
+          for (int off = kGemvLanes / 2; off > 0; off >>= 1) {
+            sr[r] += __shfl_xor(sr[r], off);
+            si[r] += __shfl_xor(si[r], off);
+          }
+      if (sub < nrhs) {
         R vr = sr[0], vi = si[0];
 #pragma unroll
         for (int r = 1; r < kGemvRhs; ++r)
-          if (lane == r) {
+          if (sub == r) {
             vr = sr[r];
             vi = si[r];
           }
         if (nks == 1) {
-          Zr[(d.e0 + gi) * nrhs + lane] -= vr;
-          Zi[(d.e0 + gi) * nrhs + lane] -= vi;
+          Zr[(d.e0 + gi) * nrhs + sub] -= vr;
+          Zi[(d.e0 + gi) * nrhs + sub] -= vi;
         } else {
-          const long o = (((long)q * nks_max + ks) * np_max + gi) * nrhs + lane;
+          const long o = (((long)q * nks_max + ks) * np_max + gi) * nrhs + sub;
           Pr[o] = vr;
           Pi[o] = vi;
         }
