@@ -34,7 +34,7 @@ struct Plan2 {
   std::vector<std::complex<double>> alpha;   // [9][18][2]  (rows 2 t + c of tau, columns r)
   std::vector<std::complex<double>> beta;    // [9][27][2]  (rows 3 t + f)
   std::vector<double> eig;                   // [9][18] Gram eigenvalues, ascending
-  DevBuf qrows;                    // Q rows [n^2][2 rows][9 slots][2 comps] complex128
+  DevBuf alpha_dev;                // the class stencils on the device (Q v is formed from them)
   DevBuf srows;                    // S rows [n^2][2 rows][27 slots][2 comps] complex128 (slots s3 = 0 used)
   HostSolver* hs = nullptr;        // factor of S on host cores, or
   GpuSolver* gs = nullptr;         // factor of S in HBM

@@ -594,12 +594,12 @@ __global__ void gram2_reduce_kernel(const C<double>* __restrict__ partial, C<dou
   gram[kappa * 324 + e] = s;
 }
 
-// Rows of Q ([point][2 rows][9 slots][2 comps]) and of S in the 27-slot form of
-// the sparse factors ([point][2][27][2], slot 9 (s1+1) + 3 (s2+1) + 1):
-//   Q = conj(alpha[2t+c][r]),  S = Q + conj(beta[3t+c][r]) m_j + conj(beta[3t+2][r]) p^c_j,  j = i + tau[t]
+// Rows of S in the 27-slot form of the sparse factors ([point][2 rows][27
+// slots][2 comps], slot 9 (s1+1) + 3 (s2+1) + 1):
+//   S = conj(alpha[2t+c][r]) + conj(beta[3t+c][r]) m_j + conj(beta[3t+2][r]) p^c_j,  j = i + tau[t]
 __global__ void rows2_kernel(const C<double>* __restrict__ alpha, const C<double>* __restrict__ beta,
                              const C<double>* __restrict__ m, const C<double>* __restrict__ p,
-                             C<double>* __restrict__ Q, C<double>* __restrict__ S, int n) {
+                             C<double>* __restrict__ S, int n) {
   const long nn = (long)n * n;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nn) return;
@@ -607,9 +607,7 @@ __global__ void rows2_kernel(const C<double>* __restrict__ alpha, const C<double
   const int c1 = dim_class(i1, n), c2 = dim_class(i2, n), kappa = 3 * c1 + c2, T2 = tau_len(c2);
   const C<double>* al = alpha + (size_t)kappa * 36;
   const C<double>* be = beta + (size_t)kappa * 54;
-  C<double>* q = Q + idx * 36;
   C<double>* sr = S + idx * 108;
-  for (int e = 0; e < 36; ++e) q[e] = cmk(0.0, 0.0);
   for (int e = 0; e < 108; ++e) sr[e] = cmk(0.0, 0.0);
   for (int s1 = -1; s1 <= 1; ++s1)
     for (int s2 = -1; s2 <= 1; ++s2) {
@@ -617,36 +615,42 @@ __global__ void rows2_kernel(const C<double>* __restrict__ alpha, const C<double
       if (t1 < 0 || t1 >= tau_len(c1) || t2 < 0 || t2 >= T2) continue;
       const int t = t1 * T2 + t2;
       const long j = idx + (long)s1 * n + s2;
-      const int slot9 = 3 * (s1 + 1) + (s2 + 1), slot27 = 9 * (s1 + 1) + 3 * (s2 + 1) + 1;
+      const int slot27 = 9 * (s1 + 1) + 3 * (s2 + 1) + 1;
       for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) {
           const C<double> qa = cconj(al[(2 * t + c) * 2 + r]);
-          const C<double> sv = qa + cconj(be[(3 * t + c) * 2 + r]) * m[j] + cconj(be[(3 * t + 2) * 2 + r]) * p[c * nn + j];
-          q[(r * 9 + slot9) * 2 + c] = qa;
-          sr[(r * 27 + slot27) * 2 + c] = sv;
+          sr[(r * 27 + slot27) * 2 + c] =
+              qa + cconj(be[(3 * t + c) * 2 + r]) * m[j] + cconj(be[(3 * t + 2) * 2 + r]) * p[c * nn + j];
         }
     }
 }
 
-// w = Q v for nrhs fields [rhs][2][n][n]
-__global__ void qapply2_kernel(const C<double>* __restrict__ Q, const C<double>* __restrict__ v,
-                               C<double>* __restrict__ w, int n, int nrhs) {
+// w = Q v for nrhs fields [rhs][2][n][n].  Q's rows depend only on the
+// point's class: Q[(r, i), (c, i + a)] = conj(alpha[2t + c][r]), a = tau[t];
+// the nine class stencils sit in LDS.
+__global__ __launch_bounds__(256) void qapply2_kernel(const C<double>* __restrict__ alpha,
+                                                      const C<double>* __restrict__ v, C<double>* __restrict__ w,
+                                                      int n, int nrhs) {
+  __shared__ C<double> al[9 * 36];
+  for (int e = threadIdx.x; e < 9 * 36; e += blockDim.x) al[e] = alpha[e];
+  __syncthreads();
   const long nn = (long)n * n;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nn * nrhs) return;
   const long b = idx / nn, i = idx % nn;
   const int i1 = (int)(i / n), i2 = (int)(i % n);
-  const C<double>* q = Q + i * 36;
+  const int c1 = dim_class(i1, n), c2 = dim_class(i2, n), T2 = tau_len(c2);
+  const C<double>* ak = al + (3 * c1 + c2) * 36;
   const C<double>* vb = v + b * 2 * nn;
   C<double> acc[2] = {cmk(0.0, 0.0), cmk(0.0, 0.0)};
   for (int s1 = -1; s1 <= 1; ++s1)
     for (int s2 = -1; s2 <= 1; ++s2) {
-      const int j1 = i1 + s1, j2 = i2 + s2;
-      if (j1 < 0 || j1 >= n || j2 < 0 || j2 >= n) continue;
-      const long j = (long)j1 * n + j2;
-      const int slot = 3 * (s1 + 1) + (s2 + 1);
+      const int t1 = s1 - tau_lo(c1), t2 = s2 - tau_lo(c2);
+      if (t1 < 0 || t1 >= tau_len(c1) || t2 < 0 || t2 >= T2) continue;
+      const int t = t1 * T2 + t2;
+      const long j = i + (long)s1 * n + s2;
       for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c) acc[r] = cfma(q[(r * 9 + slot) * 2 + c], vb[c * nn + j], acc[r]);
+        for (int c = 0; c < 2; ++c) acc[r] = cfma(cconj(ak[(2 * t + c) * 2 + r]), vb[c * nn + j], acc[r]);
     }
   w[b * 2 * nn + i] = acc[0];
   w[b * 2 * nn + nn + i] = acc[1];
@@ -920,16 +924,15 @@ ls_status plan2_fit(Plan2& pl, hipStream_t s) {
   }
   // rows
   const long nn = (long)n * n;
-  DevBuf dal, dbe;
-  LS_TRY(dal.alloc(pl.alpha.size() * sizeof(cd)));
+  DevBuf dbe;
+  LS_TRY(pl.alpha_dev.alloc(pl.alpha.size() * sizeof(cd)));
   LS_TRY(dbe.alloc(pl.beta.size() * sizeof(cd)));
-  LS_TRY(pl.qrows.alloc((size_t)nn * 36 * sizeof(cd)));
   LS_TRY(pl.srows.alloc((size_t)nn * 108 * sizeof(cd)));
-  LS_HIP(hipMemcpyAsync(dal.p, pl.alpha.data(), dal.bytes, hipMemcpyHostToDevice, s));
+  LS_HIP(hipMemcpyAsync(pl.alpha_dev.p, pl.alpha.data(), pl.alpha_dev.bytes, hipMemcpyHostToDevice, s));
   LS_HIP(hipMemcpyAsync(dbe.p, pl.beta.data(), dbe.bytes, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(rows2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, dal.as<C<double>>(),
-                     dbe.as<C<double>>(), pl.m64.as<C<double>>(), pl.p64.as<C<double>>(), pl.qrows.as<C<double>>(),
-                     pl.srows.as<C<double>>(), n);
+  hipLaunchKernelGGL(rows2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
+                     pl.alpha_dev.as<C<double>>(), dbe.as<C<double>>(), pl.m64.as<C<double>>(),
+                     pl.p64.as<C<double>>(), pl.srows.as<C<double>>(), n);
   LS_HIP(hipGetLastError());
   LS_HIP(hipStreamSynchronize(s));
   pl.fitted = true;
@@ -970,7 +973,7 @@ ls_status plan2_precond(Plan2& pl, const std::vector<int>& lb, const std::functi
     C<double>* blk = pl.pbuf.as<C<double>>();
     for (int q = 0; q < nb; ++q) {
       hipLaunchKernelGGL(qapply2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
-                         pl.qrows.as<C<double>>(), ptr(lb[q]), blk + (size_t)q * len, pl.n, 1);
+                         pl.alpha_dev.as<C<double>>(), ptr(lb[q]), blk + (size_t)q * len, pl.n, 1);
       LS_HIP(hipGetLastError());
     }
     LS_TRY(gpu_solve(pl.gs, blk, blk, nb, s));
@@ -982,7 +985,7 @@ ls_status plan2_precond(Plan2& pl, const std::vector<int>& lb, const std::functi
   std::vector<std::complex<double>> hb((size_t)nb * len);
   for (int q = 0; q < nb; ++q) {
     hipLaunchKernelGGL(qapply2_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s,
-                       pl.qrows.as<C<double>>(), ptr(lb[q]), pl.pbuf.as<C<double>>(), pl.n, 1);
+                       pl.alpha_dev.as<C<double>>(), ptr(lb[q]), pl.pbuf.as<C<double>>(), pl.n, 1);
     LS_HIP(hipGetLastError());
     LS_HIP(hipMemcpyAsync(hb.data() + (size_t)q * len, pl.pbuf.p, vb, hipMemcpyDeviceToHost, s));
   }
