@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "e2cc0aeb03286e34794e11781e9da0c352709fcbbedfdd711512e93e509eeabe",
+    "sha256": "d523535783ece3387c8e9743bb9d51f27409d091de1484b4ff8737a290ac08de",
     "workload": (959, 8, "c64"),
-    "bytes": 1.3758e9,
+    "bytes": 1.3420e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 
