@@ -1285,12 +1285,13 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
 // columns).  Same grid and the same rows read and written as those kernels.
 constexpr int kGemvRhs = 4;
 constexpr int kGemvLanes = 16;   // lanes per row: four rows per wave, 128-byte row segments per load
+constexpr int kGemvRows = 256 / kGemvLanes;   // rows per workgroup (one pass): more workgroups per front
 template <typename R, bool FWD>
 __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                       int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                       R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                       R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
-  constexpr int NZB = kSB / kRB;
+  constexpr int NZB = kSB / kGemvRows;
   __shared__ R vr_[kSB * kGemvRhs], vi_[kSB * kGemvRhs];
   const int tid = threadIdx.x, sub = tid % kGemvLanes;
   const bool brole = (int)blockIdx.x < NZB;      // rows of the block (M or H) or rows outside it
@@ -1305,17 +1306,17 @@ __global__ __launch_bounds__(256) void sb_gemv_kernel(const FrontDev* __restrict
     long i0;
     int cnt;
     if (brole) {
-      i0 = (long)blockIdx.x * kRB;
+      i0 = (long)blockIdx.x * kGemvRows;
       if (i0 >= sw) continue;
-      cnt = (int)min((long)kRB, sw - i0);
+      cnt = (int)min((long)kGemvRows, sw - i0);
     } else if (FWD) {
-      i0 = kb0 + sw + (long)(blockIdx.x - NZB) * kRB;   // rows below the block
+      i0 = kb0 + sw + (long)(blockIdx.x - NZB) * kGemvRows;   // rows below the block
       if (i0 >= nf) continue;
-      cnt = (int)min((long)kRB, nf - i0);
+      cnt = (int)min((long)kGemvRows, nf - i0);
     } else {
-      i0 = (long)(blockIdx.x - NZB) * kRB;              // rows above the block
+      i0 = (long)(blockIdx.x - NZB) * kGemvRows;              // rows above the block
       if (i0 >= kb0) continue;
-      cnt = (int)min((long)kRB, kb0 - i0);
+      cnt = (int)min((long)kGemvRows, kb0 - i0);
     }
     for (int e = tid; e < sw * nrhs; e += 256) {
       const int k = e / nrhs, r = e % nrhs;
@@ -1410,9 +1411,9 @@ __global__ __launch_bounds__(256) void u12_gemv_kernel(const FrontDev* __restric
     const long np = d.np, nf = d.nf, nb = d.nb;
     const int nks = (int)((nb + kKS - 1) / kKS);
     if (ks >= nks) continue;
-    const long i0 = (long)blockIdx.x * kRB;
+    const long i0 = (long)blockIdx.x * kGemvRows;
     if (i0 >= np) continue;
-    const int cnt = (int)min((long)kRB, np - i0);
+    const int cnt = (int)min((long)kGemvRows, np - i0);
     const long j0 = (long)ks * kKS;
     const int nj = (int)min((long)kKS, nb - j0);
     for (int e = tid; e < nj * nrhs; e += 256) {
@@ -1784,9 +1785,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
       }
     for (long kb0 = 0; kb0 < mnp; kb0 += kSB) {
       const unsigned gx = (unsigned)(kSB / kRB + std::max(0L, (mnf - kb0 - 1 + kRB - 1) / kRB));
-      if (nrhs <= kGemvRhs)
-        hipLaunchKernelGGL((sb_gemv_kernel<R, true>), dim3(gx, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
+      if (nrhs <= kGemvRhs) {
+        const unsigned gxg =
+            (unsigned)(kSB / kGemvRows + std::max(0L, (mnf - kb0 - 1 + kGemvRows - 1) / kGemvRows));
+        hipLaunchKernelGGL((sb_gemv_kernel<R, true>), dim3(gxg, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
                            nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
+      }
       else
         hipLaunchKernelGGL(fwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
                            Xr, Xi, Zr, Zi, Ur, Ui);
@@ -1799,8 +1803,10 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
     const long mnp = g.lvl_np[dep];
     const unsigned gu = (unsigned)std::max(1L, (mnp + kRB - 1) / kRB);
     if (nrhs <= kGemvRhs)
-      hipLaunchKernelGGL(u12_gemv_kernel<R>, dim3(gu, gy, nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp,
-                         fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
+      hipLaunchKernelGGL(u12_gemv_kernel<R>, dim3((unsigned)std::max(1L, (mnp + kGemvRows - 1) / kGemvRows), gy,
+                                                  nks[dep]),
+                         dim3(256), 0, s, fr, lvl, nl, nks[dep], mnp, fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr,
+                         Zi, Pr, Pi);
     else
       hipLaunchKernelGGL(bwd_u12_kernel<R>, dim3(gu, gy, gz * nks[dep]), dim3(256), 0, s, fr, lvl, nl, nks[dep],
                          mnp, fac, ib, nrhs, (const R*)Xr, (const R*)Xi, Zr, Zi, Pr, Pi);
@@ -1809,9 +1815,11 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                          nks[dep], mnp, nrhs, (const R*)Pr, (const R*)Pi, Zr, Zi);
     for (long kb0 = ((mnp - 1) / kSB) * kSB; kb0 >= 0; kb0 -= kSB) {
       const unsigned gx = (unsigned)(kSB / kRB + (kb0 + kRB - 1) / kRB);
-      if (nrhs <= kGemvRhs)
-        hipLaunchKernelGGL((sb_gemv_kernel<R, false>), dim3(gx, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
+      if (nrhs <= kGemvRhs) {
+        const unsigned gxg = (unsigned)(kSB / kGemvRows + (kb0 + kGemvRows - 1) / kGemvRows);
+        hipLaunchKernelGGL((sb_gemv_kernel<R, false>), dim3(gxg, gy), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac,
                            nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
+      }
       else
         hipLaunchKernelGGL(bwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
                            Xr, Xi, Zr, Zi);
