@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "d523535783ece3387c8e9743bb9d51f27409d091de1484b4ff8737a290ac08de",
+    "sha256": "06de3420c07089ed52ee638ee268f869f9d3fda8d7bad603f63bf9fb552819b6",
     "workload": (959, 8, "c64"),
-    "bytes": 1.3420e9,
+    "bytes": 1.3758e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 

@@ -452,7 +452,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
       const int e = threadIdx.x + kTB * u;
-      if (e < tot) a[e] = d == 0 ? o0[u] : o1[u];
+      if (e < tot) {   // two stores, not a select between the arrays (that puts them on the stack)
+        if (d == 0) a[e] = o0[u];
+        else a[e] = o1[u];
+      }
     }
     __syncthreads();
     const C<R>* X = lds_fft<R, 1, true, false, true, kTB>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
