@@ -147,9 +147,12 @@ __global__ __launch_bounds__(256) void extend_add_kernel(const FrontDev* __restr
                                                          int nlvl, int slot, const int* __restrict__ ib,
                                                          const R* __restrict__ cbuf, R* __restrict__ buf) {
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    // the child index read from global memory: indexing the copy's child[]
+    // with the runtime slot would put the whole FrontDev copy on the stack
+    const int cid = fr[lvl[q]].child[slot];
+    if (cid < 0) continue;
     const FrontDev d = fr[lvl[q]];
-    if (d.child[slot] < 0) continue;
-    const FrontDev c = fr[d.child[slot]];
+    const FrontDev c = fr[cid];
     const long nf = d.nf, cnf = c.nf;
     const int cnb = c.nb;
     R* Fr = buf + d.f;
@@ -605,9 +608,12 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
                                                         R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Ur,
                                                         R* __restrict__ Ui) {
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
+    // the child index read from global memory: indexing the copy's child[]
+    // with the runtime slot would put the whole FrontDev copy on the stack
+    const int cid = fr[lvl[q]].child[slot];
+    if (cid < 0) continue;
     const FrontDev d = fr[lvl[q]];
-    if (d.child[slot] < 0) continue;
-    const FrontDev c = fr[d.child[slot]];
+    const FrontDev c = fr[cid];
     const int lanes = rhs_lanes(nrhs), rpp = 256 / lanes;
     for (int rr = blockIdx.x * rpp + threadIdx.x / lanes; rr < c.nb; rr += gridDim.x * rpp) {
       const int pos = NC * ib[c.xm + rr / NC] + rr % NC;
