@@ -25,7 +25,10 @@ tensor over that ball plus the -1/3 depolarisation term:
 
 Pins (tests/test_oracle_kernel.py): closed form against mpmath finite
 differences of G; ball integral against mpmath quadrature; symmetry,
-evenness and cubic covariance; the Helmholtz equation away from 0.
+evenness and cubic covariance; the Helmholtz equation away from 0.  With the
+operator (tests/test_oracle_physics.py): the total field inside a small
+homogeneous sphere is the static 3 E0 / (eps + 2), eps = 1 - m, to first order
+in h, which fixes the self term's -1/3 depolarisation.
 """
 from __future__ import annotations
 
