@@ -36,9 +36,14 @@
 #include "gpu_solver.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <limits>
+#include <functional>
 #include <memory>
+#include <system_error>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "nd_tree.h"
@@ -1507,8 +1512,46 @@ struct GpuSolver {
 
 namespace {
 
+// fn() on the calling thread and up to nthr - 1 more; fn takes its work from a
+// shared counter, so fewer threads (when one cannot be started) still finish it
+// Leaves ints uninitialised on resize: the index maps (hundreds of MB at the
+// largest grids) are cleared by several threads instead of one.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
+  }
+};
+using IntMap = std::vector<int, NoInitAlloc<int>>;
+
+template <typename F>
+void run_on_threads(int nthr, F& fn) {
+  std::vector<std::thread> pool;
+  for (int i = 1; i < nthr; ++i) {
+    try {
+      pool.emplace_back(std::ref(fn));
+    } catch (const std::system_error&) {
+      break;
+    }
+  }
+  fn();
+  for (auto& th : pool) th.join();
+}
+
 // Symbolic phase: dissection, elimination order, offsets and index maps.
-ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
+ls_status symbolic(GpuSolver& g, IntMap& ibh, long& fac_elems) {
   const int* dm = g.dims;
   const int nc = g.nc;
   NdTree t = nd_build_grid(dm, nc);
@@ -1554,45 +1597,71 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
     io += nd.nb;
   }
   if (io > (long)std::numeric_limits<int>::max()) return LS_ENOMEM;
-  ibh.assign(io, -1);
-  for (int id = 0; id < nn; ++id) {
-    const NdNode& nd = t.nodes[id];
-    const FrontDev& f = g.fh[id];
-    for (size_t a = 0; a < nd.piv.size(); ++a)
-      for (int c = 0; c < nc; ++c) ibh[f.e0 + nc * a + c] = (int)(c * n3 + nd.piv[a]);
-    const int npp = (int)nd.piv.size();
-    auto nb_map = [&](int p, long dst, bool pivot_row) {
-      const int i3 = p % dm[2], i2 = (p / dm[2]) % dm[1], i1 = p / (dm[1] * dm[2]);
-      for (int s1 = -1; s1 <= 1; ++s1)
-        for (int s2 = -1; s2 <= 1; ++s2)
-          for (int s3 = -1; s3 <= 1; ++s3) {
-            const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
-            const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
-            int v = -1;
-            if (j1 >= 0 && j1 < dm[0] && j2 >= 0 && j2 < dm[1] && j3 >= 0 && j3 < dm[2]) {
-              const int pj = (j1 * dm[1] + j2) * dm[2] + j3;
-              v = pivot_row ? nd_front_pos(nd, pj) : nd_pos_in(nd.piv, pj);
+  const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  ibh.resize(io);
+  std::atomic<long> next_chunk{0};
+  constexpr long kChunk = 1L << 20;
+  auto clear_maps = [&]() {
+    for (long c = next_chunk.fetch_add(1); c * kChunk < io; c = next_chunk.fetch_add(1))
+      std::fill(ibh.begin() + c * kChunk, ibh.begin() + std::min(io, (c + 1) * kChunk), -1);
+  };
+  run_on_threads(nthr, clear_maps);
+  // The maps of a front depend only on that front, so fronts are taken from a
+  // shared counter by host threads; each front writes its own ranges of ibh.
+  // A thread keeps a point -> front-position table (pivots first, then the
+  // boundary; -1 elsewhere), set for the current front and cleared after it,
+  // so the 27 neighbour lookups per point are direct loads.
+  std::atomic<int> next_front{0};
+  std::atomic<bool> bad{false};
+  auto fill_fronts = [&]() {
+    std::vector<int> pos(n3, -1);
+    for (int id = next_front.fetch_add(1); id < nn && !bad.load(std::memory_order_relaxed);
+         id = next_front.fetch_add(1)) {
+      const NdNode& nd = t.nodes[id];
+      const FrontDev& f = g.fh[id];
+      const int npp = (int)nd.piv.size();
+      for (size_t b = 0; b < nd.bnd.size(); ++b) pos[nd.bnd[b]] = npp + (int)b;
+      for (int a = 0; a < npp; ++a) pos[nd.piv[a]] = a;   // a pivot position wins, as in nd_front_pos
+      for (int a = 0; a < npp; ++a)
+        for (int c = 0; c < nc; ++c) ibh[f.e0 + nc * a + c] = (int)(c * n3 + nd.piv[a]);
+      // neighbours of point p: their front positions (pivot rows) or pivot positions (boundary rows)
+      auto nb_map = [&](int p, long dst, bool pivot_row) {
+        const int i3 = p % dm[2], i2 = (p / dm[2]) % dm[1], i1 = p / (dm[1] * dm[2]);
+        for (int s1 = -1; s1 <= 1; ++s1)
+          for (int s2 = -1; s2 <= 1; ++s2)
+            for (int s3 = -1; s3 <= 1; ++s3) {
+              const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
+              const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
+              int v = -1;
+              if (j1 >= 0 && j1 < dm[0] && j2 >= 0 && j2 < dm[1] && j3 >= 0 && j3 < dm[2]) {
+                const int q = pos[(j1 * dm[1] + j2) * dm[2] + j3];
+                v = (pivot_row || q < npp) ? q : -1;
+              }
+              ibh[dst + slot] = v;
             }
-            ibh[dst + slot] = v;
-          }
-    };
-    for (int a = 0; a < npp; ++a) nb_map(nd.piv[a], f.am + 27L * a, true);
-    for (size_t b = 0; b < nd.bnd.size(); ++b) {
-      nb_map(nd.bnd[b], f.ab + 27L * b, false);
-      ibh[f.bp + b] = nd.bnd[b];
-      const long eb = elim_of_point[nd.bnd[b]];
-      if (eb < 0) return LS_EINVAL;
-      for (int c = 0; c < nc; ++c) ibh[f.bm + nc * b + c] = (int)(eb + c);
-    }
-    if (nd.parent >= 0) {
-      const NdNode& pa = t.nodes[nd.parent];
+      };
+      for (int a = 0; a < npp; ++a) nb_map(nd.piv[a], f.am + 27L * a, true);
       for (size_t b = 0; b < nd.bnd.size(); ++b) {
-        const int fp = nd_front_pos(pa, nd.bnd[b]);
-        if (fp < 0) return LS_EINVAL;           // a child's shell lies in its parent's front
-        ibh[f.xm + b] = fp;
+        nb_map(nd.bnd[b], f.ab + 27L * b, false);
+        ibh[f.bp + b] = nd.bnd[b];
+        const long eb = elim_of_point[nd.bnd[b]];
+        if (eb < 0) bad = true;
+        for (int c = 0; c < nc; ++c) ibh[f.bm + nc * b + c] = (int)(eb + c);
       }
+      if (nd.parent >= 0) {
+        const NdNode& pa = t.nodes[nd.parent];
+        for (size_t b = 0; b < nd.bnd.size(); ++b) {
+          const int fp = nd_front_pos(pa, nd.bnd[b]);
+          if (fp < 0) bad = true;               // a child's shell lies in its parent's front
+          ibh[f.xm + b] = fp;
+        }
+      }
+      for (int a = 0; a < npp; ++a) pos[nd.piv[a]] = -1;
+      for (size_t b = 0; b < nd.bnd.size(); ++b) pos[nd.bnd[b]] = -1;
     }
-  }
+  };
+  run_on_threads(nthr, fill_fronts);
+  if (bad) return LS_EINVAL;
   // factor offsets (R elements) and solve update rows
   long fo = 0, uo = 0;
   double fl = 0.0;
@@ -1639,18 +1708,22 @@ ls_status symbolic(GpuSolver& g, std::vector<int>& ibh, long& fac_elems) {
     }
     g.lvl_elems[dep] = off;
   }
-  // every map entry in range (checked once here; the kernels trust them)
-  for (int id = 0; id < nn; ++id) {
-    const FrontDev& f = g.fh[id];
-    const NdNode& nd = t.nodes[id];
-    for (long i = 0; i < 27L * (long)nd.piv.size(); ++i)
-      if (ibh[f.am + i] >= f.nf / nc) return LS_EINVAL;
-    for (long i = 0; i < 27L * (long)nd.bnd.size(); ++i)
-      if (ibh[f.ab + i] >= f.np / nc) return LS_EINVAL;
-    if (nd.parent >= 0)
-      for (size_t b = 0; b < nd.bnd.size(); ++b)
-        if (ibh[f.xm + b] >= g.fh[nd.parent].nf / nc) return LS_EINVAL;
-  }
+  // every map entry in range (checked once here, after the fill; the kernels trust them)
+  next_front = 0;
+  auto check_fronts = [&]() {
+    for (int id = next_front.fetch_add(1); id < nn; id = next_front.fetch_add(1)) {
+      const FrontDev& f = g.fh[id];
+      const NdNode& nd = t.nodes[id];
+      bool ok = true;
+      for (long i = 0; i < 27L * (long)nd.piv.size(); ++i) ok &= ibh[f.am + i] < f.nf / nc;
+      for (long i = 0; i < 27L * (long)nd.bnd.size(); ++i) ok &= ibh[f.ab + i] < f.np / nc;
+      if (nd.parent >= 0)
+        for (size_t b = 0; b < nd.bnd.size(); ++b) ok &= ibh[f.xm + b] < g.fh[nd.parent].nf / nc;
+      if (!ok) bad = true;
+    }
+  };
+  run_on_threads(nthr, check_fronts);
+  if (bad) return LS_EINVAL;
   return LS_OK;
 }
 
@@ -1855,7 +1928,7 @@ ls_status gpu_factor_grid(const int dims[3], int nc, const C<double>* rows_dev, 
   g->nc = nc;
   g->npts = (long)dims[0] * dims[1] * dims[2];
   g->fp32 = fp32;
-  std::vector<int> ibh;
+  IntMap ibh;
   long fac_elems = 0;
   LS_TRY(symbolic(*g, ibh, fac_elems));
   const size_t rs = fp32 ? sizeof(float) : sizeof(double);
