@@ -1538,16 +1538,16 @@ using IntMap = std::vector<int, NoInitAlloc<int>>;
 
 template <typename F>
 void run_on_threads(int nthr, F& fn) {
-  std::vector<std::thread> pool;
+  std::vector<std::thread> workers;
   for (int i = 1; i < nthr; ++i) {
     try {
-      pool.emplace_back(std::ref(fn));
+      workers.emplace_back(std::ref(fn));
     } catch (const std::system_error&) {
       break;
     }
   }
   fn();
-  for (auto& th : pool) th.join();
+  for (auto& th : workers) th.join();
 }
 
 // Symbolic phase: dissection, elimination order, offsets and index maps.
