@@ -41,6 +41,7 @@
 #include <limits>
 #include <functional>
 #include <memory>
+#include <new>
 #include <system_error>
 #include <thread>
 #include <utility>
@@ -1598,7 +1599,11 @@ ls_status symbolic(GpuSolver& g, IntMap& ibh, long& fac_elems) {
   }
   if (io > (long)std::numeric_limits<int>::max()) return LS_ENOMEM;
   const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  ibh.resize(io);
+  try {
+    ibh.resize(io);
+  } catch (const std::bad_alloc&) {
+    return LS_ENOMEM;
+  }
   std::atomic<long> next_chunk{0};
   constexpr long kChunk = 1L << 20;
   auto clear_maps = [&]() {
@@ -1614,7 +1619,12 @@ ls_status symbolic(GpuSolver& g, IntMap& ibh, long& fac_elems) {
   std::atomic<int> next_front{0};
   std::atomic<bool> bad{false};
   auto fill_fronts = [&]() {
-    std::vector<int> pos(n3, -1);
+    std::vector<int> pos;
+    try {
+      pos.assign(n3, -1);
+    } catch (const std::bad_alloc&) {
+      return;   // the other threads take the fronts; none left untaken is checked below
+    }
     for (int id = next_front.fetch_add(1); id < nn && !bad.load(std::memory_order_relaxed);
          id = next_front.fetch_add(1)) {
       const NdNode& nd = t.nodes[id];
@@ -1662,6 +1672,7 @@ ls_status symbolic(GpuSolver& g, IntMap& ibh, long& fac_elems) {
   };
   run_on_threads(nthr, fill_fronts);
   if (bad) return LS_EINVAL;
+  if (next_front.load() < nn) return LS_ENOMEM;   // no thread could allocate its table
   // factor offsets (R elements) and solve update rows
   long fo = 0, uo = 0;
   double fl = 0.0;
