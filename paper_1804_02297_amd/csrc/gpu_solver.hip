@@ -434,8 +434,8 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__
 // step; the rest of the trailing matrix is read by nothing inside the block,
 // so its update waits and is applied once with K up to kOB.  Registers are
 // capped for two waves per SIMD: uncapped, the FP64 kernel took 214 VGPRs and
-// 64 AGPRs (one wave); capped it fits 220 VGPRs without spills (the FP32 one
-// keeps three waves either way).
+// 64 AGPRs (one wave); capped it fits 220 VGPRs without spills.  The FP32
+// one keeps three waves (capped for four it spills 28 VGPRs and runs slower).
 template <typename R>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void schur_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                     int nlvl, int kb, int kb0, int mode, R* __restrict__ buf) {
