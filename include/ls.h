@@ -270,6 +270,15 @@ void ls_mlp_destroy(ls_mlp* mlp);
  * assembles the rows, like ls_stencil_fit.  Synchronises. */
 ls_status ls_stencil_fit_learned(ls_plan* plan, ls_mlp* mlp, int* n_fallback_out, void* hip_stream);
 
+/* Outcome of the last learned fit, per grid point (host arrays of n^3 entries,
+ * linear index (i1 n + i2) n + i3): accept_host 1 where the prediction was
+ * accepted, 0 where the point fell back to the exact per-point fit, -1 at
+ * boundary points (no prediction); ratio_host the locality ratio
+ * tr(Q^H Gram_i Q) / tr(alpha_c^H Gram_i alpha_c) of the prediction (0 at
+ * boundary points).  Either pointer may be NULL.  LS_ESTATE unless the last
+ * fit of the plan was ls_stencil_fit_learned. */
+ls_status ls_get_learned_info(const ls_plan* plan, int* accept_host, double* ratio_host);
+
 /* ---- the sparse solver on its own (host or GPU factor) --------------------- */
 typedef struct ls_sparse ls_sparse;
 

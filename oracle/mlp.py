@@ -105,6 +105,23 @@ def forward(params, x):
     return y, (x, z1, h1, z2, h2)
 
 
+def forward_bf16(params, x):
+    """Forward pass with every product's operands rounded to bfloat16.
+
+    The network's products take BF16 operands (weights, inputs and the GELU
+    activations feeding the next layer) with wide accumulation; biases and
+    the pre-activations stay wide.  Here the operands are rounded with
+    round_bf16 and the sums are FP64.  Where the network's output decides an
+    integer (accepting a predicted stencil or not), this is the precision the
+    decision is taken in.  Returns y of shape (B, 468).
+    """
+    xb = round_bf16(x)
+    W1, W2, W3 = (round_bf16(params[k]) for k in ("W1", "W2", "W3"))
+    h1 = round_bf16(gelu(xb @ W1 + params["b1"]))
+    h2 = round_bf16(gelu(h1 @ W2 + params["b2"]))
+    return h2 @ W3 + params["b3"]
+
+
 def loss(y, t):
     return float(np.mean((y - t) ** 2))
 

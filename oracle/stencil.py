@@ -237,6 +237,51 @@ def weighted_gram(m: np.ndarray, i0, k: float, m0: float = 0.1) -> np.ndarray:
     return Mw @ Mw.conj().T
 
 
+def interior_gram_parts(n: int, k: float):
+    """The pieces of every interior point's weighted Gram.
+
+    The weighted objective sums w_j^2 K_{tau,j} K_{tau,j}^H over the columns j
+    of the complement, and w_j = 1 off the 5^3 shell, so
+
+      Gram_i = M M^H + sum_{s in shell} (w_s^2 - 1) K_{tau,s} K_{tau,s}^H
+
+    with M the interior class's non-local block.  Returns (M M^H, shell
+    offsets, [K_{tau,s} K_{tau,s}^H for each shell offset]).
+    """
+    M = nonlocal_block(13, n, k)
+    sh = shell_offsets()
+    Ks = nonlocal_block(13, n, k, cols=sh)              # 81 x 3*98
+    H = [Ks[:, 3 * t:3 * t + 3] @ Ks[:, 3 * t:3 * t + 3].conj().T for t in range(len(sh))]
+    return M @ M.conj().T, sh, H
+
+
+def weighted_gram_from_parts(parts, m: np.ndarray, i0, m0: float = 0.1) -> np.ndarray:
+    """weighted_gram of an interior point from interior_gram_parts."""
+    G0, sh, H = parts
+    sh2, w = shell_weights(m, i0, m0)
+    assert np.array_equal(sh, sh2)
+    G = G0.copy()
+    for t in range(len(sh)):
+        G += (w[t] ** 2 - 1.0) * H[t]
+    return G
+
+
+# A predicted stencil is accepted only when it is more local than the class
+# stencil on the point's own objective by more than this relative amount, so
+# that a prediction equal to the class stencil falls back to the exact fit.
+ACCEPT_RTOL = 1e-9
+
+
+def locality_ratio(alpha_hat: np.ndarray, gram: np.ndarray, alpha_class: np.ndarray) -> float:
+    """rho = tr(Q^H Gram Q) / tr(Q_c^H Gram Q_c) over the spans of the prediction and the class stencil."""
+    return locality(alpha_hat, gram) / locality(alpha_class, gram)
+
+
+def accept_prediction(rho: float) -> bool:
+    """The acceptance rule of the learned fit: rho < 1 - ACCEPT_RTOL."""
+    return rho < 1.0 - ACCEPT_RTOL
+
+
 def centre_index(kappa: int) -> int:
     """Position of offset (0,0,0) in tau_offsets(kappa)."""
     tau = tau_offsets(kappa)

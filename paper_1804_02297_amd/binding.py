@@ -61,6 +61,7 @@ SIGNATURES = [
     ("ls_mlp_load", _I, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
     ("ls_mlp_destroy", None, [_VP]),
     ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
+    ("ls_get_learned_info", _I, [_VP, _VP, _VP]),
     ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
     ("ls_sparse_factor_gpu", _I, [_I, _VP, _I, _VP, ctypes.POINTER(_VP)]),
@@ -369,6 +370,15 @@ class Plan:
         nf = ctypes.c_int()
         _check(_lib.ls_stencil_fit_learned(self._h, mlp._h, ctypes.byref(nf), _stream()), "ls_stencil_fit_learned")
         return nf.value
+
+    def learned_info(self):
+        """(accept (n^3,) int32: 1 accepted, 0 fell back, -1 boundary; ratio (n^3,) float64)."""
+        import numpy as np
+        acc = np.zeros(self.n ** 3, np.int32)
+        rat = np.zeros(self.n ** 3, np.float64)
+        _check(_lib.ls_get_learned_info(self._h, acc.ctypes.data_as(ctypes.c_void_p),
+                                        rat.ctypes.data_as(ctypes.c_void_p)), "ls_get_learned_info")
+        return acc, rat
 
     def class_stencils(self, gram: bool = False):
         """(alpha, beta, eig[, gram]): alpha, beta (27, 81, 3) complex128; eig (27, 3);

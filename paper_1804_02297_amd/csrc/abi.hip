@@ -179,6 +179,7 @@ ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
   plan->gs = nullptr;
   plan->sd.have_point = false;
   plan->sd.have_rows = false;
+  plan->sd.have_learned = false;
   // the class stencils depend on (n, k) only: computed once per plan
   if (!plan->sd.have_class) LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
   if (mode == LS_FIT_POINT)
@@ -194,6 +195,16 @@ ls_status ls_get_point_stencils(const ls_plan* plan, void* alpha_host, double* e
   if (!plan->sd.have_point) return LS_ESTATE;
   if (alpha_host) LS_HIP(hipMemcpy(alpha_host, plan->sd.palpha.p, plan->sd.palpha.bytes, hipMemcpyDeviceToHost));
   if (eig_host) LS_HIP(hipMemcpy(eig_host, plan->sd.peval.p, plan->sd.peval.bytes, hipMemcpyDeviceToHost));
+  return LS_OK;
+}
+
+ls_status ls_get_learned_info(const ls_plan* plan, int* accept_host, double* ratio_host) {
+  if (!plan) return LS_EINVAL;
+  if (!plan->sd.have_learned || !plan->sd.have_point) return LS_ESTATE;
+  const auto& a = plan->sd.learned_accept;
+  const auto& r = plan->sd.learned_ratio;
+  if (accept_host) std::memcpy(accept_host, a.data(), a.size() * sizeof(int));
+  if (ratio_host) std::memcpy(ratio_host, r.data(), r.size() * sizeof(double));
   return LS_OK;
 }
 

@@ -359,6 +359,11 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
   LS_TRY(rat.alloc((size_t)B * sizeof(double)));
   LS_TRY(dfail.alloc((size_t)B * sizeof(int)));
   std::vector<int> accept(B), fail;
+  std::vector<double> ratio(B);
+  const long N3 = (long)n * n * n;
+  sd.have_learned = false;
+  sd.learned_accept.assign(N3, -1);
+  sd.learned_ratio.assign(N3, 0.0);
   int nfb = 0;
   for (int p0 = 0; p0 < npts; p0 += B) {
     const int cnt = std::min(B, npts - p0);
@@ -376,10 +381,14 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
                        rat.as<double>());
     LS_HIP(hipGetLastError());
     LS_HIP(hipMemcpyAsync(accept.data(), acc.p, cnt * sizeof(int), hipMemcpyDeviceToHost, s));
+    LS_HIP(hipMemcpyAsync(ratio.data(), rat.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
     LS_HIP(hipStreamSynchronize(s));
     fail.clear();
-    for (int q = 0; q < cnt; ++q)
+    for (int q = 0; q < cnt; ++q) {
+      sd.learned_accept[pts[p0 + q]] = accept[q] ? 1 : 0;
+      sd.learned_ratio[pts[p0 + q]] = ratio[q];
       if (!accept[q]) fail.push_back(pts[p0 + q]);
+    }
     nfb += (int)fail.size();
     if (!fail.empty()) {
       // exact fit for the rejected points: their Grams again, in the order of the list
@@ -392,6 +401,7 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
   LS_HIP(hipStreamSynchronize(s));
   if (n_fallback) *n_fallback = nfb;
   sd.have_point = true;
+  sd.have_learned = true;
   return LS_OK;
 }
 

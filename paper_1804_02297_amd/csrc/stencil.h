@@ -33,6 +33,12 @@ struct StencilData {
   bool have_class = false;
   bool have_point = false;
   bool have_rows = false;
+  // outcome of the last learned fit, per grid point (host): 1 the prediction was
+  // accepted, 0 the point fell back to the exact fit, -1 a boundary point; the
+  // locality ratio of the prediction (0 at boundary points)
+  std::vector<int> learned_accept;
+  std::vector<double> learned_ratio;
+  bool have_learned = false;
 };
 
 ls_status class_fit(StencilData& sd, int n, double k, hipStream_t s);

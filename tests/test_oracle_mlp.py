@@ -94,3 +94,35 @@ def test_patch_features_layout():
     assert math.isclose(f[0, 2 * 62 + 1], m[2, 3, 2].imag / 0.3)
     # off-grid entries are zero; first in-grid entry of the corner patch is (0,0,0)
     assert f[1, 0] == 0.0 and math.isclose(f[1, 2 * 62], m[0, 0, 0].real / 0.3)
+
+
+def test_forward_bf16_differs_by_the_activation_rounding_only():
+    """forward_bf16 = forward on BF16-rounded weights and inputs, up to the BF16
+    rounding of the two hidden activations: each rounded activation moves by at
+    most 2^-8 of itself, which propagates to y through |W2| (with GELU's slope,
+    at most 1.13) and |W3|.  A first-order bound, with 10 % for the rest."""
+    params = mlp.init_params(7)
+    g = np.random.default_rng(3)
+    for k in ("b1", "b2", "b3"):
+        params[k] = 0.05 * g.standard_normal(params[k].shape)
+    x = g.standard_normal((16, mlp.D_IN))
+    pr = {k: (mlp.round_bf16(v) if k.startswith("W") else v) for k, v in params.items()}
+    y, (xx, z1, h1, z2, h2) = mlp.forward(pr, mlp.round_bf16(x))
+    yb = mlp.forward_bf16(params, x)
+    u = 2.0 ** -8
+    dh1 = u * np.abs(h1)
+    dh2 = u * np.abs(h2) + 1.13 * dh1 @ np.abs(pr["W2"])
+    bound = 1.1 * dh2 @ np.abs(pr["W3"])
+    d = np.abs(yb - y)
+    assert np.all(d <= bound)
+    assert d.max() > 0.0          # the activations are rounded
+
+
+def test_forward_bf16_is_exact_on_representable_values():
+    """With W2 = W3 = 0 only the biases reach y: forward_bf16 == forward exactly."""
+    params = mlp.init_params(2)
+    params["W2"][:] = 0.0
+    params["W3"][:] = 0.0
+    params["b3"] = np.linspace(-1.0, 1.0, mlp.D_OUT)
+    x = np.random.default_rng(0).standard_normal((3, mlp.D_IN))
+    assert np.array_equal(mlp.forward_bf16(params, x), mlp.forward(params, x)[0])

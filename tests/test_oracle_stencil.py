@@ -197,3 +197,30 @@ def test_locality_ratio_bounds_of_the_learned_acceptance():
     assert abs(st.locality(rec, G) / ta - bound) <= 1e-10
     rnd = np.random.default_rng(1).standard_normal(om.D_OUT)
     assert st.locality(om.decode_output(rnd, cal), G) / ta >= bound - 1e-12
+
+
+def test_weighted_gram_from_parts_equals_the_direct_sum():
+    """The split Gram_class + sum (w^2 - 1) H_s equals M diag(w^2) M^H built column by column."""
+    n = 8
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 5)
+    parts = st.interior_gram_parts(n, k)
+    for i0 in [(4, 3, 4), (1, 1, 1), (6, 2, 5)]:
+        G1 = st.weighted_gram(m, i0, k)
+        G2 = st.weighted_gram_from_parts(parts, m, i0)
+        assert np.abs(G1 - G2).max() <= 1e-12 * np.abs(G1).max(), i0
+
+
+def test_acceptance_rule_rejects_the_class_stencil_and_takes_the_exact_fit():
+    n = 8
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 5)
+    i0 = (4, 3, 4)
+    G = st.weighted_gram(m, i0, k)
+    ac = st.fit_class(13, n, k)[0]
+    al = st.fit_point_weighted(m, i0, k)[0]
+    assert not st.accept_prediction(st.locality_ratio(ac, G, ac))
+    assert not st.accept_prediction(st.locality_ratio(st.gauge_fix(ac), G, ac))
+    rho = st.locality_ratio(al, G, ac)
+    assert rho < 1.0 - 1e-6
+    assert st.accept_prediction(rho)
