@@ -299,6 +299,12 @@ ls_status ls_sparse_solve_gpu(ls_sparse* sp, void* b_dev, int nrhs, void* hip_st
 ls_status ls_sparse_info(const ls_sparse* sp, size_t* bytes, double* flops);
 void ls_sparse_destroy(ls_sparse* sp);
 
+/* Measurement helper: a streaming device-to-device copy of `bytes` bytes
+ * (dst and src device pointers, 16-byte aligned, not overlapping), the
+ * achievable HBM bandwidth against which the apply's passes are read.
+ * Stream-ordered; LS_EINVAL for a NULL or misaligned pointer. */
+ls_status ls_hbm_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
+
 /* Operator form of the plan's apply (ls_apply, ls_apply_timed,
  * ls_rhs_from_incident and the FGMRES solves). */
 typedef enum {

@@ -62,6 +62,7 @@ SIGNATURES = [
     ("ls_mlp_destroy", None, [_VP]),
     ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
     ("ls_get_learned_info", _I, [_VP, _VP, _VP]),
+    ("ls_hbm_copy", _I, [_VP, _VP, ctypes.c_size_t, _VP]),
     ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
     ("ls_sparse_factor_gpu", _I, [_I, _VP, _I, _VP, ctypes.POINTER(_VP)]),
@@ -288,6 +289,13 @@ def load(path: str = LIB_PATH):
 def _check(code: int, what: str):
     if code != 0:
         raise LSError(code, what)
+
+
+def hbm_copy(dst, src, nbytes: int):
+    """Streaming device copy of nbytes from src to dst (device tensors) on the current stream."""
+    load()
+    _check(_lib.ls_hbm_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, _stream()),
+           "ls_hbm_copy")
 
 
 def _ptr(t):

@@ -53,6 +53,32 @@ __host__ __device__ __forceinline__ C<R> cfma(C<R> b, C<R> c, C<R> a) {
 template <typename To, typename Ti>
 __host__ __device__ __forceinline__ C<To> ccast(C<Ti> a) { return cmk((To)a.re, (To)a.im); }
 
+// Streaming global loads and stores (non-temporal: data read or written once
+// per pass is not kept in the caches).
+#ifndef LS_NT
+#define LS_NT 1
+#endif
+template <typename R>
+__device__ __forceinline__ C<R> ld_stream(const C<R>* p) {
+  if constexpr (LS_NT) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return cmk<R>(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void st_stream(C<R>* p, C<R> z) {
+  if constexpr (LS_NT) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 v = {z.re, z.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+  } else {
+    *p = z;
+  }
+}
+
 // ---- compile-time twiddles -------------------------------------------------
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
@@ -106,6 +132,20 @@ constexpr double ct_sin2pi(long k, long N) {
 template <typename R, int N, int DIR>
 __device__ __forceinline__ C<R> ctw(int k) {
   return cmk<R>((R)ct_cos2pi(k, N), (R)(DIR * ct_sin2pi(k, N)));
+}
+
+// a * W_N^k with k a compile-time constant after unrolling: the quarter turns
+// are sign swaps (free as operand modifiers), the rest a complex multiply by
+// the constant.  An IEEE multiply by 0 or -1 cannot be folded by the
+// compiler, so these cases are spelt out.
+template <typename R, int N, int DIR>
+__device__ __forceinline__ C<R> twmul(C<R> a, int k) {
+  k %= N;
+  if (k == 0) return a;
+  if (2 * k == N) return cmk<R>(-a.re, -a.im);
+  if (4 * k == N) return (DIR < 0) ? mul_mi(a) : mul_pi(a);
+  if (4 * k == 3 * N) return (DIR < 0) ? mul_pi(a) : mul_mi(a);
+  return a * ctw<R, N, DIR>(k);
 }
 
 // ---- in-register DFTs --------------------------------------------------------
@@ -184,7 +224,7 @@ struct Dft {
     for (int q = 0; q < M; ++q) {
       C<R> t[F];
 #pragma unroll
-      for (int f = 0; f < F; ++f) t[f] = (f * q == 0) ? sub[f][q] : sub[f][q] * ctw<R, N, DIR>(f * q);
+      for (int f = 0; f < F; ++f) t[f] = twmul<R, N, DIR>(sub[f][q], f * q);
       Dft<F, DIR, R>::run(t);
 #pragma unroll
       for (int s = 0; s < F; ++s) v[q + M * s] = t[s];
@@ -245,7 +285,7 @@ struct DftZ {
       for (int q = 0; q < M; ++q) {
         C<R> t[F];
 #pragma unroll
-        for (int f = 0; f < FIN; ++f) t[f] = (f * q == 0) ? sub[f][q] : sub[f][q] * ctw<R, N, DIR>(f * q);
+        for (int f = 0; f < FIN; ++f) t[f] = twmul<R, N, DIR>(sub[f][q], f * q);
         DftZ<F, DIR, R, FIN>::run(t);
 #pragma unroll
         for (int s = 0; s < F; ++s) v[q + M * s] = t[s];

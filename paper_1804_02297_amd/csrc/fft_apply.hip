@@ -127,10 +127,10 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
       if (live && row < rows_in) {
         const long off = batch * in_bstride + (long)row * L + line;
         if (MODE == COL_P1) {
-          C<IO> xv = reinterpret_cast<const C<IO>*>(in_)[off];
+          C<IO> xv = ld_stream(reinterpret_cast<const C<IO>*>(in_) + off);
           z = ccast<R>(xv) * mfac[(long)row * L + line];
         } else {
-          z = reinterpret_cast<const C<R>*>(in_)[off];
+          z = ld_stream(reinterpret_cast<const C<R>*>(in_) + off);
         }
       }
       v[k] = z;
@@ -158,10 +158,10 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
           if (MODE == COL_P5) {
             C<IO>* y = reinterpret_cast<C<IO>*>(out_);
             const C<IO>* x = reinterpret_cast<const C<IO>*>(mfac);  // identity term, or none
-            C<IO> xv = x ? x[off] : cmk<IO>(0, 0);
-            y[off] = cmk<IO>(xv.re + (IO)(w[q1].re * scale), xv.im + (IO)(w[q1].im * scale));
+            C<IO> xv = x ? ld_stream(x + off) : cmk<IO>(0, 0);
+            st_stream(y + off, cmk<IO>(xv.re + (IO)(w[q1].re * scale), xv.im + (IO)(w[q1].im * scale)));
           } else {
-            reinterpret_cast<C<R>*>(out_)[off] = w[q1];
+            st_stream(reinterpret_cast<C<R>*>(out_) + off, w[q1]);
           }
         }
       }
@@ -198,7 +198,23 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
   constexpr bool WAVE_TEAM = (TEAM == 64);
   static_assert(WAVE_TEAM || W == 1, "multi-team workgroups need one-wave teams");
   constexpr int EXS = N1 * N2 + N2;          // padded exchange stride of one job
-  __shared__ C<R> kl[6 * H];
+  // Frequencies q3 = j + N2 a: with N1 even, a < N1/2 gives q3 < P/2 and
+  // a >= N1/2 gives q3 >= P/2 (mirrored, f3 = P - q3), both known at compile
+  // time.  The odd components of a mirrored line change sign (xy: q1 or q2
+  // mirrored, xz: q1 or q3, yz: q2 or q3); the q1 and q2 signs of each of the
+  // four lines are folded into its own copy of the odd components in LDS,
+  // and the q3 sign into the multiply's operand modifiers, so the symbol
+  // multiply has no sign arithmetic left.  With the fused multiply-adds of
+  // the 3x3 product this cut the FP32 pass at 128^3, 8 rhs, from 1.023 to
+  // 0.804 ms (2954 instead of 3405 VALU instructions per rhs and lane); the
+  // same code with the signs applied by multiplies took 0.817 ms, and
+  // without the load prefetch 0.866 ms.  The larger LDS footprint (35 KB per
+  // two-team workgroup) caps the kernel at two waves per SIMD, as its
+  // registers already did.
+  constexpr bool SPLIT3 = (N1 % 2 == 0);
+  constexpr bool SIGNED = SPLIT3;
+  __shared__ C<R> ke[3 * H];                    // xx, yy, zz
+  __shared__ C<R> ko[(SIGNED ? 4 : 1) * 3 * H]; // xy, xz, yz (per line when SIGNED)
   __shared__ C<R> twl[P];
   __shared__ C<R> ex[W * 4 * EXS];
   const int f1 = blockIdx.x / H;
@@ -218,15 +234,30 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
   const long lineoff = ((long)q1 * P + q2) * n;
 
   const C<R>* kg = Kh + ((long)f1 * H + f2) * 6 * H;
-  for (int e = tid; e < 6 * H; e += W * TEAM) kl[e] = kg[e];
+  for (int e = tid; e < 3 * H; e += W * TEAM) {
+    ke[e] = kg[e];
+    const C<R> o = kg[3 * H + e];
+    if constexpr (SIGNED) {
+      const int comp = e / H;                 // 0 xy, 1 xz, 2 yz
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const bool m1 = l & 1, m2 = l >> 1;
+        const bool neg = (comp == 0) ? (m1 != m2) : (comp == 1 ? m1 : m2);
+        ko[l * 3 * H + e] = neg ? cmk<R>(-o.re, -o.im) : o;
+      }
+    } else {
+      ko[e] = o;
+    }
+  }
   for (int e = tid; e < P; e += W * TEAM) twl[e] = tw[e];
-  // sign flips of the odd components for a mirrored line
+  // sign flips of the odd components for a mirrored line (runtime path only)
   const R sxy = (s1 != s2) ? (R)-1 : (R)1;   // xy odd in q1 and q2
   const R sx = s1 ? (R)-1 : (R)1;            // xz odd in q1 (and q3)
   const R sy = s2 ? (R)-1 : (R)1;            // yz odd in q2 (and q3)
   __syncthreads();
 
   C<R>* myex = ex + (team * 4 + job) * EXS;
+  const C<R>* kol = ko + (SIGNED ? job * 3 * H : 0);
   auto tsync = [&]() {
     if (WAVE_TEAM)
       wave_lds_sync();
@@ -251,7 +282,7 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
 #pragma unroll
         for (int k = 0; k < KIN; ++k) {
           const int tt = j + N1 * k;
-          pre[c][k] = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+          pre[c][k] = (tt < n) ? ld_stream(base + c * plane + tt) : cmk<R>(0, 0);
         }
     }
     C<R> u[3][N1];
@@ -263,12 +294,12 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
 #pragma unroll
         for (int k = 0; k < KIN; ++k) {
           const int tt = j + N1 * k;
-          v[k] = PREFETCH ? pre[c][k] : ((tt < n) ? base[c * plane + tt] : cmk<R>(0, 0));
+          v[k] = PREFETCH ? pre[c][k] : ((tt < n) ? ld_stream(base + c * plane + tt) : cmk<R>(0, 0));
         }
         DftZ<N2, -1, R, KIN>::run(v);
+        // twl[0] = 1 exactly, so lane j = 0 needs no exception
 #pragma unroll
-        for (int q = 0; q < N2; ++q)
-          myex[q * (N1 + 1) + j] = (j * q == 0) ? v[q] : v[q] * twl[j * q];
+        for (int q = 0; q < N2; ++q) myex[q * (N1 + 1) + j] = (q == 0) ? v[q] : v[q] * twl[j * q];
       }
       tsync();
       // forward step 3: thread q2 = j < N2 gets X[j + N2 a], a in [0, N1)
@@ -282,18 +313,42 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
     if (active && j < N2) {
 #pragma unroll
       for (int a = 0; a < N1; ++a) {
-        const int q3 = j + N2 * a;
-        const bool fl3 = 2 * q3 > P;
-        const int f3 = fl3 ? P - q3 : q3;
-        const R s3 = fl3 ? (R)-1 : (R)1;
-        const C<R> kxx = kl[0 * H + f3], kyy = kl[1 * H + f3], kzz = kl[2 * H + f3];
-        const C<R> kxy = cscale(kl[3 * H + f3], sxy);
-        const C<R> kxz = cscale(kl[4 * H + f3], sx * s3);
-        const C<R> kyz = cscale(kl[5 * H + f3], sy * s3);
+        C<R> kxx, kyy, kzz, kxy, kxz, kyz;
+        if constexpr (SPLIT3) {
+          const bool hi = 2 * a >= N1;                       // q3 >= P/2
+          const int f3 = hi ? P - N2 * a - j : N2 * a + j;
+          kxx = ke[f3];
+          kyy = ke[H + f3];
+          kzz = ke[2 * H + f3];
+          kxy = kol[f3];
+          kxz = kol[H + f3];
+          kyz = kol[2 * H + f3];
+          if (!SIGNED) {
+            kxy = cscale(kxy, sxy);
+            kxz = cscale(kxz, sx);
+            kyz = cscale(kyz, sy);
+          }
+          if (hi) {
+            kxz = cmk<R>(-kxz.re, -kxz.im);
+            kyz = cmk<R>(-kyz.re, -kyz.im);
+          }
+        } else {
+          const int q3 = j + N2 * a;
+          const bool fl3 = 2 * q3 > P;
+          const int f3 = fl3 ? P - q3 : q3;
+          const R s3 = fl3 ? (R)-1 : (R)1;
+          kxx = ke[f3];
+          kyy = ke[H + f3];
+          kzz = ke[2 * H + f3];
+          kxy = cscale(ko[f3], sxy);
+          kxz = cscale(ko[H + f3], sx * s3);
+          kyz = cscale(ko[2 * H + f3], sy * s3);
+        }
+        // one multiply and five fused multiply-adds per real part
         const C<R> ux = u[0][a], uy = u[1][a], uz = u[2][a];
-        u[0][a] = kxx * ux + kxy * uy + kxz * uz;
-        u[1][a] = kxy * ux + kyy * uy + kyz * uz;
-        u[2][a] = kxz * ux + kyz * uy + kzz * uz;
+        u[0][a] = cfma(kxz, uz, cfma(kxy, uy, kxx * ux));
+        u[1][a] = cfma(kyz, uz, cfma(kyy, uy, kxy * ux));
+        u[2][a] = cfma(kzz, uz, cfma(kyz, uy, kxz * ux));
         if ((a & 3) == 3) asm volatile("" ::: "memory");   // bound the LDS prefetch depth
       }
     }
@@ -304,7 +359,7 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
         Dft<N1, 1, R>::run(u[c]);
 #pragma unroll
         for (int t2 = 0; t2 < N1; ++t2)
-          myex[j * (N1 + 1) + t2] = (j * t2 == 0) ? u[c][t2] : u[c][t2] * cconj(twl[j * t2]);
+          myex[j * (N1 + 1) + t2] = (t2 == 0) ? u[c][t2] : u[c][t2] * cconj(twl[j * t2]);
       }
       tsync();
       // inverse step 3': thread t2 = j < N1 produces t = j + N1 t1
@@ -316,7 +371,7 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
 #pragma unroll
         for (int t1 = 0; t1 < (N2 + 1) / 2; ++t1) {
           const int tt = j + N1 * t1;
-          if (tt < n) base[c * plane + tt] = v[t1];
+          if (tt < n) st_stream(base + c * plane + tt, v[t1]);
         }
       }
       tsync();
@@ -403,7 +458,7 @@ __global__ __launch_bounds__(W * 128) void kmul2_kernel(C<R>* __restrict__ X, co
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const int tt = col + N * k;
-          const C<R> x = (tt < n) ? base[c * plane + tt] : cmk<R>(0, 0);
+          const C<R> x = (tt < n) ? ld_stream(base + c * plane + tt) : cmk<R>(0, 0);
           v[k] = (k == 0) ? x : hf(x, k);
         }
         Dft<8, -1, R>::run(v);
@@ -477,7 +532,7 @@ __global__ __launch_bounds__(W * 128) void kmul2_kernel(C<R>* __restrict__ X, co
 #pragma unroll
         for (int t1 = 0; t1 < 4; ++t1) {
           const int tt = col + N * (2 * t1 + h);
-          if (tt < n) base[c * plane + tt] = v[t1];
+          if (tt < n) st_stream(base + c * plane + tt, v[t1]);
         }
       }
       wave_lds_sync();
