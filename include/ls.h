@@ -102,12 +102,14 @@ typedef struct {
 } ls_tune_info;
 
 /* Autotune the apply of prec for batches of nrhs: look the key (GPU, n, P,
- * prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time every
+ * form, prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time every
  * choice on the plan's operator (scratch fields of nrhs, allocated and freed
  * here), keep the fastest and append it to the cache file (a JSON array, one
  * object per line; rewritten through a temporary file).  The choice then holds
  * for every later apply and solve of that precision.  A cache that cannot be
- * written is not an error.  Synchronises hip_stream.  info may be NULL. */
+ * written is not an error.  The choices are those of the dyadic form:
+ * LS_ESTATE while the plan's form is LS_FORM_PAPER, whose apply has a single
+ * launch choice.  Synchronises hip_stream.  info may be NULL. */
 ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, ls_tune_info* info);
 
 /* Set the launch choice of prec by hand (chunk 0 / kmul_w 0 = default).

@@ -1516,8 +1516,6 @@ struct GpuSolver {
 
 namespace {
 
-// fn() on the calling thread and up to nthr - 1 more; fn takes its work from a
-// shared counter, so fewer threads (when one cannot be started) still finish it
 // Leaves ints uninitialised on resize: the index maps (hundreds of MB at the
 // largest grids) are cleared by several threads instead of one.
 template <typename T>
@@ -1540,6 +1538,8 @@ struct NoInitAlloc : std::allocator<T> {
 };
 using IntMap = std::vector<int, NoInitAlloc<int>>;
 
+// fn() on the calling thread and up to nthr - 1 more; fn takes its work from a
+// shared counter, so fewer threads (when one cannot be started) still finish it
 template <typename F>
 void run_on_threads(int nthr, F& fn) {
   std::vector<std::thread> workers;

@@ -9,7 +9,7 @@
 // warm up, then 3 times between HIP events.
 //
 // Cache: a JSON array, one object per line,
-//   {"key": "<arch>|cu=<CUs>|n=<n>|P=<P>|prec=<p>|nrhs=<b>|max_rhs=<m>", "chunk": c, "kmul_w": w, "ms_per_rhs": t}
+//   {"key": "<arch>|cu=<CUs>|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>", "chunk": c, "kmul_w": w, "ms_per_rhs": t}
 // read before timing (a hit skips it) and rewritten with the new entry after.
 #include <algorithm>
 #include <cstdio>
@@ -36,8 +36,8 @@ std::string tune_key(const ApplyPlan& ap, int nrhs, ls_prec prec) {
     cus = prop.multiProcessorCount;
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s|cu=%d|n=%d|P=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus, ap.n, ap.P,
-                (int)prec, nrhs, ap.max_rhs);
+  std::snprintf(buf, sizeof buf, "%s|cu=%d|n=%d|P=%d|form=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus, ap.n,
+                ap.P, ap.form, (int)prec, nrhs, ap.max_rhs);
   return buf;
 }
 
@@ -112,6 +112,7 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
                      TuneOutcome* out) {
   if (nrhs < 1) return LS_EINVAL;
   if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
+  if (ap.form != 0) return LS_ESTATE;       // the paper's form has a single launch choice
   TuneOutcome res;
   const std::string key = tune_key(ap, nrhs, prec);
   std::vector<Entry> entries;

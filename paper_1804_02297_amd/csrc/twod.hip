@@ -32,6 +32,7 @@
 #include <cstring>
 #include <functional>
 #include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "gpu_solver.h"
@@ -1048,102 +1049,135 @@ Plan2::~Plan2() {
 }
 }  // namespace ls
 
+// Host allocations inside an entry point (the symbolic phase of the factor,
+// host staging) may throw; no exception crosses the C boundary.
+template <typename F>
+static ls_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return LS_ENOMEM;
+  } catch (const std::length_error&) {
+    return LS_ENOMEM;
+  }
+}
+
 extern "C" {
 
 ls_status ls2_plan_create(int n, double k, int max_rhs, const void* m_dev, void* hip_stream, ls2_plan** out) {
-  if (!out) return LS_EINVAL;
-  *out = nullptr;
-  ls2_plan* p = new (std::nothrow) ls2_plan;
-  if (!p) return LS_ENOMEM;
-  const ls_status st = ls::plan2_init(p->pl, n, k, max_rhs, m_dev, (hipStream_t)hip_stream);
-  if (st != LS_OK) {
-    delete p;
-    return st;
-  }
-  *out = p;
-  return LS_OK;
+  return guarded([&]() -> ls_status {
+    if (!out) return LS_EINVAL;
+    *out = nullptr;
+    ls2_plan* p = new (std::nothrow) ls2_plan;
+    if (!p) return LS_ENOMEM;
+    const ls_status st = ls::plan2_init(p->pl, n, k, max_rhs, m_dev, (hipStream_t)hip_stream);
+    if (st != LS_OK) {
+      delete p;
+      return st;
+    }
+    *out = p;
+    return LS_OK;
+  });
 }
 
 ls_status ls2_apply(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream) {
-  if (!plan) return LS_EINVAL;
-  return ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, (hipStream_t)hip_stream, false);
+  return guarded([&]() -> ls_status {
+    if (!plan) return LS_EINVAL;
+    return ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, (hipStream_t)hip_stream, false);
+  });
 }
 
 ls_status ls2_rhs_from_incident(ls2_plan* plan, const void* Ei_dev, void* g_dev, int nrhs, void* hip_stream) {
-  if (!plan) return LS_EINVAL;
-  return ls::plan2_apply(plan->pl, Ei_dev, g_dev, nrhs, LS_C128, (hipStream_t)hip_stream, true);
+  return guarded([&]() -> ls_status {
+    if (!plan) return LS_EINVAL;
+    return ls::plan2_apply(plan->pl, Ei_dev, g_dev, nrhs, LS_C128, (hipStream_t)hip_stream, true);
+  });
 }
 
 int ls2_plan_fft_size(const ls2_plan* plan) { return plan ? plan->pl.P : 0; }
 
 ls_status ls2_apply_timed(ls2_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec, void* hip_stream,
                           double* pass_ms) {
-  if (!plan || !pass_ms || nrhs > plan->pl.max_rhs) return LS_EINVAL;
-  hipStream_t s = (hipStream_t)hip_stream;
-  hipEvent_t ev[4];
-  for (int i = 0; i < 4; ++i)
-    if (hipEventCreate(&ev[i]) != hipSuccess) {
-      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
-      return LS_EHIP;
+  return guarded([&]() -> ls_status {
+    if (!plan || !pass_ms || nrhs > plan->pl.max_rhs) return LS_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t ev[4];
+    for (int i = 0; i < 4; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+        return LS_EHIP;
+      }
+    ls_status st = ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, s, false, ev);
+    if (st == LS_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = LS_EHIP;
+    for (int i = 0; i < 3 && st == LS_OK; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = LS_EHIP;
+      pass_ms[i] = ms;
     }
-  ls_status st = ls::plan2_apply(plan->pl, x_dev, y_dev, nrhs, prec, s, false, ev);
-  if (st == LS_OK && hipEventSynchronize(ev[3]) != hipSuccess) st = LS_EHIP;
-  for (int i = 0; i < 3 && st == LS_OK; ++i) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = LS_EHIP;
-    pass_ms[i] = ms;
-  }
-  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
-  return st;
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+    return st;
+  });
 }
 
 ls_status ls2_stencil_fit(ls2_plan* plan, void* hip_stream) {
-  if (!plan) return LS_EINVAL;
-  return ls::plan2_fit(plan->pl, (hipStream_t)hip_stream);
+  return guarded([&]() -> ls_status {
+    if (!plan) return LS_EINVAL;
+    return ls::plan2_fit(plan->pl, (hipStream_t)hip_stream);
+  });
 }
 
 ls_status ls2_get_stencils(const ls2_plan* plan, void* alpha_host, void* beta_host, double* eig_host) {
-  if (!plan || !alpha_host || !beta_host || !eig_host) return LS_EINVAL;
-  if (!plan->pl.fitted) return LS_ESTATE;
-  std::memcpy(alpha_host, plan->pl.alpha.data(), plan->pl.alpha.size() * sizeof(std::complex<double>));
-  std::memcpy(beta_host, plan->pl.beta.data(), plan->pl.beta.size() * sizeof(std::complex<double>));
-  std::memcpy(eig_host, plan->pl.eig.data(), plan->pl.eig.size() * sizeof(double));
-  return LS_OK;
+  return guarded([&]() -> ls_status {
+    if (!plan || !alpha_host || !beta_host || !eig_host) return LS_EINVAL;
+    if (!plan->pl.fitted) return LS_ESTATE;
+    std::memcpy(alpha_host, plan->pl.alpha.data(), plan->pl.alpha.size() * sizeof(std::complex<double>));
+    std::memcpy(beta_host, plan->pl.beta.data(), plan->pl.beta.size() * sizeof(std::complex<double>));
+    std::memcpy(eig_host, plan->pl.eig.data(), plan->pl.eig.size() * sizeof(double));
+    return LS_OK;
+  });
 }
 
 ls_status ls2_factor(ls2_plan* plan, ls_prec factor_prec, double* seconds_out) {
-  if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
-  const double t0 = ls::wall_seconds();
-  const ls_status st = ls::plan2_factor(plan->pl, factor_prec == LS_C64, nullptr);
-  if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
-  return st;
+  return guarded([&]() -> ls_status {
+    if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
+    const double t0 = ls::wall_seconds();
+    const ls_status st = ls::plan2_factor(plan->pl, factor_prec == LS_C64, nullptr);
+    if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
+    return st;
+  });
 }
 
 ls_status ls2_factor_gpu(ls2_plan* plan, ls_prec factor_prec, void* hip_stream, double* seconds_out) {
-  if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
-  const double t0 = ls::wall_seconds();
-  const ls_status st = ls::plan2_factor_gpu(plan->pl, factor_prec == LS_C64, (hipStream_t)hip_stream);
-  if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
-  return st;
+  return guarded([&]() -> ls_status {
+    if (!plan || (factor_prec != LS_C128 && factor_prec != LS_C64)) return LS_EINVAL;
+    const double t0 = ls::wall_seconds();
+    const ls_status st = ls::plan2_factor_gpu(plan->pl, factor_prec == LS_C64, (hipStream_t)hip_stream);
+    if (seconds_out) *seconds_out = ls::wall_seconds() - t0;
+    return st;
+  });
 }
 
 ls_status ls2_precond_apply(ls2_plan* plan, const void* v_dev, void* z_dev, int nrhs, void* hip_stream) {
-  if (!plan || !v_dev || !z_dev || nrhs < 1) return LS_EINVAL;
-  const long len = 2L * plan->pl.n * plan->pl.n;
-  hipStream_t s = (hipStream_t)hip_stream;
-  if (v_dev != z_dev)
-    LS_HIP(hipMemcpyAsync(z_dev, v_dev, (size_t)nrhs * len * sizeof(ls::C<double>), hipMemcpyDeviceToDevice, s));
-  std::vector<int> lb(nrhs);
-  for (int b = 0; b < nrhs; ++b) lb[b] = b;
-  ls::C<double>* z = static_cast<ls::C<double>*>(z_dev);
-  return ls::plan2_precond(plan->pl, lb, [&](int b) { return z + (long)b * len; }, s, nullptr);
+  return guarded([&]() -> ls_status {
+    if (!plan || !v_dev || !z_dev || nrhs < 1) return LS_EINVAL;
+    const long len = 2L * plan->pl.n * plan->pl.n;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (v_dev != z_dev)
+      LS_HIP(hipMemcpyAsync(z_dev, v_dev, (size_t)nrhs * len * sizeof(ls::C<double>), hipMemcpyDeviceToDevice, s));
+    std::vector<int> lb(nrhs);
+    for (int b = 0; b < nrhs; ++b) lb[b] = b;
+    ls::C<double>* z = static_cast<ls::C<double>*>(z_dev);
+    return ls::plan2_precond(plan->pl, lb, [&](int b) { return z + (long)b * len; }, s, nullptr);
+  });
 }
 
 ls_status ls2_gmres_solve(ls2_plan* plan, const void* g_dev, void* x_dev, int nrhs, double tol, int restart,
                           int maxit, ls_prec apply_prec, ls_solve_info* info, void* hip_stream) {
-  if (!plan) return LS_EINVAL;
-  return ls::plan2_solve(plan->pl, g_dev, x_dev, nrhs, tol, restart, maxit, apply_prec, info,
-                         (hipStream_t)hip_stream);
+  return guarded([&]() -> ls_status {
+    if (!plan) return LS_EINVAL;
+    return ls::plan2_solve(plan->pl, g_dev, x_dev, nrhs, tol, restart, maxit, apply_prec, info,
+                           (hipStream_t)hip_stream);
+  });
 }
 
 void ls2_plan_destroy(ls2_plan* plan) { delete plan; }

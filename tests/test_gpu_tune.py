@@ -59,7 +59,7 @@ def test_tune_picks_valid_choice_and_caches(lib, tmp_path):
     assert 0 < info["ms_per_rhs"] <= info["ms_default_per_rhs"] * 1.05
     with open(cache) as f:
         entries = json.load(f)
-    assert len(entries) == 1 and f"n={n}|P=128|prec=1|nrhs={B}" in entries[0]["key"]
+    assert len(entries) == 1 and f"n={n}|P=128|form=0|prec=1|nrhs={B}" in entries[0]["key"]
     # the tuned apply still matches the oracle (FP32 bar) on every rhs
     x = I.random_field(B, n, 12)
     y = plan.apply(torch.from_numpy(x).to("cuda:0").to(torch.complex64), prec="c64").cpu().numpy()
@@ -79,3 +79,20 @@ def test_tune_picks_valid_choice_and_caches(lib, tmp_path):
     with open(cache) as f:
         assert len(json.load(f)) == 2
     plan2.close()
+
+
+def test_tune_refuses_the_paper_form(lib, tmp_path):
+    """The launch choices are the dyadic form's: tuning a plan in the paper's
+    form is LS_ESTATE and writes no cache entry."""
+    from paper_1804_02297_amd.binding import LSError
+    cache = str(tmp_path / "tune.json")
+    plan = _plan(12, 4, cache)
+    plan.set_form("paper")
+    with pytest.raises(LSError) as e:
+        plan.tune(4, "c64")
+    assert e.value.code == -6
+    import os
+    assert not os.path.exists(cache)
+    plan.set_form("dyadic")
+    assert plan.tune(4, "c64")["from_cache"] == 0
+    plan.close()
