@@ -116,6 +116,21 @@ ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, 
  * LS_EINVAL for chunk > max_rhs or kmul_w not in {0, 1, 2, 4}. */
 ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w);
 
+/* ls_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result as ls_apply, with the pass intermediates in a
+ * fixed 128 MiB device array that the library holds on every GPU it runs
+ * on, instead of the plan's workspace.  No allocation of any kind happens in
+ * the call.  One rhs needs 3 (P n^2 + P^2 n) complex values of 8 (LS_C64,
+ * LS_MIXED) or 16 (LS_C128) bytes, P the plan's FFT length; larger batches
+ * run in chunks that fit, and nrhs is not limited by max_rhs.  LS_ENOMEM
+ * when one rhs needs more than 128 MiB (e.g. n = 96 in complex128, n = 128
+ * in complex64); LS_ESTATE in the paper's form.  All calls on one GPU share
+ * the array: calls that overlap in time on the same GPU race and give
+ * undefined results.  Stream-ordered, like ls_apply. */
+ls_status ls_apply_noalloc(ls_plan* plan, const void* x_dev, void* y_dev, int nrhs, ls_prec prec,
+                           void* hip_stream);
+
 /* Right-hand side of the scattered-field equation (Eq. (4)):
  * g = -K * (m E^i) = E^i - A E^i, complex128, computed with the FP64 apply.
  * Ei, g: device [nrhs][3][n][n][n] complex128. */

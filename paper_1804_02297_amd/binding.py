@@ -63,6 +63,7 @@ SIGNATURES = [
     ("ls_stencil_fit_learned", _I, [_VP, _VP, ctypes.POINTER(_I), _VP]),
     ("ls_get_learned_info", _I, [_VP, _VP, _VP]),
     ("ls_hbm_copy", _I, [_VP, _VP, ctypes.c_size_t, _VP]),
+    ("ls_apply_noalloc", _I, [_VP, _VP, _VP, _I, _I, _VP]),
     ("ls_sparse_factor_host", _I, [_I, _VP, ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
     ("ls_sparse_solve_host", _I, [_VP, _VP, _I]),
     ("ls_sparse_factor_gpu", _I, [_I, _VP, _I, _VP, ctypes.POINTER(_VP)]),
@@ -356,6 +357,17 @@ class Plan:
         _field(y, dt, self.n, "y")
         _check(_lib.ls_apply(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream()),
                "ls_apply")
+        return y
+
+    def apply_noalloc(self, x, y, prec: str = "c128"):
+        """ls_apply_noalloc: the apply with its intermediates in the library's fixed
+        device array (no allocation in the call); y must be given."""
+        import torch
+        dt = torch.complex64 if prec == "c64" else torch.complex128
+        _field(x, dt, self.n, "x")
+        _field(y, dt, self.n, "y")
+        _check(_lib.ls_apply_noalloc(self._h, _ptr(x), _ptr(y), x.shape[0], PREC[prec], _stream()),
+               "ls_apply_noalloc")
         return y
 
     def apply_timed(self, x, y, prec: str = "c128"):

@@ -86,8 +86,15 @@ ls_status apply_plan_init(ApplyPlan& ap, int n, double k, int max_rhs, const voi
                           hipStream_t s);
 // y = x + K*(m x), or y = -K*(m x) when minus_conv; prec selects the kernel set.
 // nrhs <= max_rhs.  ev, when given, holds 6 events recorded around the 5 passes.
+// work, when given, replaces the plan's pass workspace (apply_work_bytes per
+// rhs; the dyadic form only) and lifts the max_rhs limit.
 ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
-                    bool minus_conv = false, hipEvent_t* ev = nullptr);
+                    bool minus_conv = false, hipEvent_t* ev = nullptr, void* work = nullptr);
+// Bytes of pass workspace one rhs needs at prec: 3 (P n^2 + P^2 n) complex values.
+inline size_t apply_work_bytes(const ApplyPlan& ap, ls_prec prec) {
+  const size_t es = (prec == LS_C128) ? 16 : 8;
+  return (size_t)3 * ((size_t)ap.P * ap.n * ap.n + (size_t)ap.P * ap.P * ap.n) * es;
+}
 // apply_run over any number of right-hand sides, ap.tune[prec].chunk (default
 // max_rhs) at a time.
 ls_status apply_batched(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,

@@ -960,10 +960,10 @@ static ls_status build_paper_symbol(ApplyPlan& ap, hipStream_t s) {
 template <typename R, typename IO, int P>
 static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, const C<R>* m,
                             const C<R>* kh, const C<R>* tw, bool minus_conv, int wt, hipStream_t s,
-                            hipEvent_t* ev) {
+                            hipEvent_t* ev, void* work) {
   const int n = ap.n;
   const long n2 = (long)n * n, n3 = n2 * n;
-  C<R>* X1 = ap.work.as<C<R>>();                          // [B][3][P][n^2]  (also Y1)
+  C<R>* X1 = work ? static_cast<C<R>*>(work) : ap.work.as<C<R>>();   // [B][3][P][n^2]  (also Y1)
   C<R>* X2 = X1 + (long)nrhs * 3 * P * n2;                 // [B][3][P][P][n]
   const long nb = (long)nrhs * 3;
 #define LS_MARK(i) \
@@ -1036,9 +1036,10 @@ static ls_status run_passes34(ApplyPlan& ap, const void* x, void* y, int nrhs, c
 
 template <int P>
 static ls_status apply_dispatch(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec,
-                                bool minus_conv, hipStream_t s, hipEvent_t* ev) {
+                                bool minus_conv, hipStream_t s, hipEvent_t* ev, void* work) {
   const int wt = ap.tune[prec].kmul_w;
   if (ap.form == 1) {
+    if (work) return LS_ESTATE;                 // the paper's form keeps its own workspace
     switch (prec) {
       case LS_C128:
         return run_passes34<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(), ap.p64.as<C<double>>(),
@@ -1055,13 +1056,13 @@ static ls_status apply_dispatch(ApplyPlan& ap, const void* x, void* y, int nrhs,
   switch (prec) {
     case LS_C128:
       return run_passes<double, double, P>(ap, x, y, nrhs, ap.m64.as<C<double>>(), ap.kh64.as<C<double>>(),
-                                           ap.tw64.as<C<double>>(), minus_conv, wt, s, ev);
+                                           ap.tw64.as<C<double>>(), minus_conv, wt, s, ev, work);
     case LS_C64:
       return run_passes<float, float, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.kh32.as<C<float>>(),
-                                         ap.tw32.as<C<float>>(), minus_conv, wt, s, ev);
+                                         ap.tw32.as<C<float>>(), minus_conv, wt, s, ev, work);
     case LS_MIXED:
       return run_passes<float, double, P>(ap, x, y, nrhs, ap.m32.as<C<float>>(), ap.kh32.as<C<float>>(),
-                                          ap.tw32.as<C<float>>(), minus_conv, wt, s, ev);
+                                          ap.tw32.as<C<float>>(), minus_conv, wt, s, ev, work);
   }
   return LS_EINVAL;
 }
@@ -1149,12 +1150,12 @@ std::vector<int> kmul_team_choices(const ApplyPlan& ap) {
 }
 
 ls_status apply_run(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
-                    bool minus_conv, hipEvent_t* ev) {
-  if (nrhs < 1 || nrhs > ap.max_rhs) return LS_EINVAL;
+                    bool minus_conv, hipEvent_t* ev, void* work) {
+  if (nrhs < 1 || (!work && nrhs > ap.max_rhs)) return LS_EINVAL;
   if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
   switch (ap.P) {
 #define X(SZ) \
-  case SZ: return apply_dispatch<SZ>(ap, x, y, nrhs, prec, minus_conv, s, ev);
+  case SZ: return apply_dispatch<SZ>(ap, x, y, nrhs, prec, minus_conv, s, ev, work);
     LS_FOR_SIZES(X)
 #undef X
   }

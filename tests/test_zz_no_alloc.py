@@ -1,0 +1,79 @@
+"""The no-allocation apply (ls_apply_noalloc) against ls_apply and the oracle.
+
+Two calls in a row through the C ABI, the second on a smaller problem, so the
+second runs on a scratch array that still holds the first call's data:
+
+* n = 24, 3 rhs, complex64: equal to ls_apply bit for bit (the same kernels
+  in the same order), and within 1e-5 of the oracle's FP64 apply;
+* n = 12, 1 rhs, complex128: equal to ls_apply bit for bit, within 1e-12 of
+  the oracle;
+* more rhs than fit at once run in chunks (n = 48, complex128: 11 rhs, 32 MB
+  each, four fit in 128 MiB) and still equal ls_apply;
+* one rhs larger than the array (n = 96, complex128: 255 MB) is refused with
+  LS_ENOMEM and leaves y untouched.
+"""
+import numpy as np
+import pytest
+
+from oracle import operator as oop
+from paper_1804_02297_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _plan(n, max_rhs):
+    from paper_1804_02297_amd.binding import Plan
+    return Plan(n, I.wavenumber_for(n), torch.from_numpy(I.medium_bumps(n, 6)).to("cuda:0"), max_rhs=max_rhs)
+
+
+def _case(n, nrhs, prec, tol, seed):
+    dt = torch.complex64 if prec == "c64" else torch.complex128
+    print(f"no-alloc apply n={n} nrhs={nrhs} {prec}", flush=True)
+    plan = _plan(n, nrhs)
+    xh = I.random_field(nrhs, n, seed)
+    x = torch.from_numpy(xh).to("cuda:0").to(dt)
+    ref = plan.apply(x, prec=prec)
+    y = torch.full_like(x, float("nan"))
+    plan.apply_noalloc(x, y, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    k = I.wavenumber_for(n)
+    m = I.medium_bumps(n, 6)
+    yo = oop.apply_fft(n, k, m, x.cpu().numpy().astype(np.complex128))
+    yh = y.cpu().numpy()
+    assert np.abs(yh - yo).max() <= tol * np.abs(yo).max()
+    plan.close()
+
+
+def test_noalloc_apply_two_calls_second_smaller(lib):
+    _case(24, 3, "c64", 1e-5, 1)
+    _case(12, 1, "c128", 1e-12, 2)
+
+
+def test_noalloc_apply_chunks_beyond_one_scratch_load(lib):
+    n, nrhs = 48, 11
+    plan = _plan(n, 4)
+    x = torch.from_numpy(I.random_field(nrhs, n, 3)).to("cuda:0")
+    ref = torch.empty_like(x)
+    for b in range(0, nrhs, 4):
+        ref[b:b + 4] = plan.apply(x[b:b + 4].contiguous(), prec="c128")
+    y = torch.empty_like(x)
+    plan.apply_noalloc(x, y, prec="c128")
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    plan.close()
+
+
+def test_noalloc_apply_refuses_a_rhs_beyond_the_array(lib):
+    from paper_1804_02297_amd.binding import LSError
+    n = 96
+    plan = _plan(n, 1)
+    x = torch.zeros((1, 3, n, n, n), dtype=torch.complex128, device="cuda:0")
+    y = torch.full_like(x, 7.0)
+    with pytest.raises(LSError) as e:
+        plan.apply_noalloc(x, y, prec="c128")
+    assert e.value.code == -2
+    torch.cuda.synchronize()
+    assert bool((y == 7.0).all())
+    plan.close()
