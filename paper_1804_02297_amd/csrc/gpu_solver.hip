@@ -34,6 +34,7 @@
 // node's update vector).  Backward from the root: subtract U12 x_boundary,
 // then per tile (last first) x = U^-1 z and the update of the rows above.
 #include "gpu_solver.h"
+#include "gpu_symbolic.h"
 
 #include <algorithm>
 #include <atomic>
@@ -53,31 +54,11 @@ namespace ls {
 
 namespace {
 
-constexpr int kT = 48;     // diagonal tile (pivot search window)
 constexpr int kRB = 64;    // rows or columns per workgroup in the panel and solve kernels
 constexpr int kSR = 64;    // right-hand sides per workgroup in the solve kernels
 constexpr int kKC = 32;    // boundary columns per LDS chunk of the U12 product
 constexpr int kKS = 512;   // boundary columns per workgroup of the U12 product (split over workgroups)
-constexpr int kTileElems = kT * kT;
-constexpr int kOB = 4 * kT;   // outer block: the trailing matrix is updated once per kOB pivot columns
 
-struct FrontDev {
-  int np, nb, nf, e0;   // pivot / boundary / front unknowns; first elimination index
-  int child[2];
-  long f;    // front in its level buffer: re plane [nf][nf], then the im plane
-  long p;    // factor: pivot rows [np][nf] (re plane, then im plane)
-  long l;    // factor: boundary rows' pivot columns [nb][np] (re, then im)
-  long t;    // factor: per tile Linv re, Linv im, Uinv re, Uinv im, each [kT][kT]
-  long pv;   // ints: per pivot, the tile row it was taken from
-  long am;   // ints: pivot rows, 27 front point positions per pivot point (-1: none)
-  long ab;   // ints: boundary rows, 27 pivot point positions per boundary point
-  long bp;   // ints: boundary point list (global point indices)
-  long xm;   // ints: boundary point a -> parent front point position
-  long bm;   // ints: boundary unknown j -> elimination index
-  long u;    // solve: first row of the node's update vector
-  long m;    // factor: per super-block forward map M (z = M x on the block), [kSB][kSB] re, then im
-  long h;    // factor: per super-block backward map H = U_block^-1, same layout
-};
 
 // ---- MFMA operand conventions -------------------------------------------------------
 // v_mfma_{f32,f64}_16x16x4 (wave64): A lane l holds A[l % 16][l / 16], B lane l holds
@@ -708,7 +689,6 @@ __device__ __forceinline__ void mma48_gl(const R* __restrict__ Agr, const R* __r
 
 constexpr int kLX = kSR + 1;                 // row stride of right-hand-side blocks in LDS
 constexpr int kLL = kT + 1;                  // row stride of a 64 x 48 factor block in LDS
-constexpr int kSB = kOB;                     // solve super-tile: four factor tiles
 template <typename R>
 struct SolveCfg {
   static constexpr int RZ = sizeof(R) == 4 ? 64 : 32;   // rhs per super-tile workgroup (LDS: 192 x RZ)
@@ -1516,231 +1496,6 @@ struct GpuSolver {
 
 namespace {
 
-// Leaves ints uninitialised on resize: the index maps (hundreds of MB at the
-// largest grids) are cleared by several threads instead of one.
-template <typename T>
-struct NoInitAlloc : std::allocator<T> {
-  template <typename U>
-  struct rebind {
-    using other = NoInitAlloc<U>;
-  };
-  NoInitAlloc() = default;
-  template <typename U>
-  NoInitAlloc(const NoInitAlloc<U>&) {}
-  template <typename U>
-  void construct(U* p) noexcept {
-    ::new (static_cast<void*>(p)) U;
-  }
-  template <typename U, typename... A>
-  void construct(U* p, A&&... a) {
-    ::new (static_cast<void*>(p)) U(std::forward<A>(a)...);
-  }
-};
-using IntMap = std::vector<int, NoInitAlloc<int>>;
-
-// fn() on the calling thread and up to nthr - 1 more; fn takes its work from a
-// shared counter, so fewer threads (when one cannot be started) still finish it
-template <typename F>
-void run_on_threads(int nthr, F& fn) {
-  std::vector<std::thread> workers;
-  for (int i = 1; i < nthr; ++i) {
-    try {
-      workers.emplace_back(std::ref(fn));
-    } catch (const std::system_error&) {
-      break;
-    }
-  }
-  fn();
-  for (auto& th : workers) th.join();
-}
-
-// Symbolic phase: dissection, elimination order, offsets and index maps.
-ls_status symbolic(GpuSolver& g, IntMap& ibh, long& fac_elems) {
-  const int* dm = g.dims;
-  const int nc = g.nc;
-  NdTree t = nd_build_grid(dm, nc);
-  const int nn = (int)t.nodes.size();
-  const long n3 = g.npts;
-  g.N = (long)nc * n3;
-  g.levels.assign(t.max_depth + 1, {});
-  for (int i = 0; i < nn; ++i) g.levels[t.nodes[i].depth].push_back(i);
-  g.fh.assign(nn, FrontDev{});
-  // elimination order: deepest level first
-  std::vector<long> elim_of_point(n3, -1);
-  long e = 0;
-  for (int dep = t.max_depth; dep >= 0; --dep)
-    for (int id : g.levels[dep]) {
-      const NdNode& nd = t.nodes[id];
-      FrontDev& f = g.fh[id];
-      f.np = nd.np;
-      f.nb = nd.nb;
-      f.nf = nd.np + nd.nb;
-      f.e0 = (int)e;
-      f.child[0] = nd.child[0];
-      f.child[1] = nd.child[1];
-      for (size_t a = 0; a < nd.piv.size(); ++a) elim_of_point[nd.piv[a]] = e + (long)nc * a;
-      e += nd.np;
-    }
-  if (e != g.N) return LS_EINVAL;
-  // int maps: perm [N], then per node pv, am, ab, bp, xm, bm
-  long io = g.N;
-  for (int id = 0; id < nn; ++id) {
-    const NdNode& nd = t.nodes[id];
-    FrontDev& f = g.fh[id];
-    f.pv = io;
-    io += nd.np;
-    f.am = io;
-    io += 27L * (long)nd.piv.size();
-    f.ab = io;
-    io += 27L * (long)nd.bnd.size();
-    f.bp = io;
-    io += (long)nd.bnd.size();
-    f.xm = io;
-    io += (long)nd.bnd.size();
-    f.bm = io;
-    io += nd.nb;
-  }
-  if (io > (long)std::numeric_limits<int>::max()) return LS_ENOMEM;
-  const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  try {
-    ibh.resize(io);
-  } catch (const std::bad_alloc&) {
-    return LS_ENOMEM;
-  }
-  std::atomic<long> next_chunk{0};
-  constexpr long kChunk = 1L << 20;
-  auto clear_maps = [&]() {
-    for (long c = next_chunk.fetch_add(1); c * kChunk < io; c = next_chunk.fetch_add(1))
-      std::fill(ibh.begin() + c * kChunk, ibh.begin() + std::min(io, (c + 1) * kChunk), -1);
-  };
-  run_on_threads(nthr, clear_maps);
-  // The maps of a front depend only on that front, so fronts are taken from a
-  // shared counter by host threads; each front writes its own ranges of ibh.
-  // A thread keeps a point -> front-position table (pivots first, then the
-  // boundary; -1 elsewhere), set for the current front and cleared after it,
-  // so the 27 neighbour lookups per point are direct loads.
-  std::atomic<int> next_front{0};
-  std::atomic<bool> bad{false};
-  auto fill_fronts = [&]() {
-    std::vector<int> pos;
-    try {
-      pos.assign(n3, -1);
-    } catch (const std::bad_alloc&) {
-      return;   // the other threads take the fronts; none left untaken is checked below
-    }
-    for (int id = next_front.fetch_add(1); id < nn && !bad.load(std::memory_order_relaxed);
-         id = next_front.fetch_add(1)) {
-      const NdNode& nd = t.nodes[id];
-      const FrontDev& f = g.fh[id];
-      const int npp = (int)nd.piv.size();
-      for (size_t b = 0; b < nd.bnd.size(); ++b) pos[nd.bnd[b]] = npp + (int)b;
-      for (int a = 0; a < npp; ++a) pos[nd.piv[a]] = a;   // a pivot position wins, as in nd_front_pos
-      for (int a = 0; a < npp; ++a)
-        for (int c = 0; c < nc; ++c) ibh[f.e0 + nc * a + c] = (int)(c * n3 + nd.piv[a]);
-      // neighbours of point p: their front positions (pivot rows) or pivot positions (boundary rows)
-      auto nb_map = [&](int p, long dst, bool pivot_row) {
-        const int i3 = p % dm[2], i2 = (p / dm[2]) % dm[1], i1 = p / (dm[1] * dm[2]);
-        for (int s1 = -1; s1 <= 1; ++s1)
-          for (int s2 = -1; s2 <= 1; ++s2)
-            for (int s3 = -1; s3 <= 1; ++s3) {
-              const int slot = 9 * (s1 + 1) + 3 * (s2 + 1) + (s3 + 1);
-              const int j1 = i1 + s1, j2 = i2 + s2, j3 = i3 + s3;
-              int v = -1;
-              if (j1 >= 0 && j1 < dm[0] && j2 >= 0 && j2 < dm[1] && j3 >= 0 && j3 < dm[2]) {
-                const int q = pos[(j1 * dm[1] + j2) * dm[2] + j3];
-                v = (pivot_row || q < npp) ? q : -1;
-              }
-              ibh[dst + slot] = v;
-            }
-      };
-      for (int a = 0; a < npp; ++a) nb_map(nd.piv[a], f.am + 27L * a, true);
-      for (size_t b = 0; b < nd.bnd.size(); ++b) {
-        nb_map(nd.bnd[b], f.ab + 27L * b, false);
-        ibh[f.bp + b] = nd.bnd[b];
-        const long eb = elim_of_point[nd.bnd[b]];
-        if (eb < 0) bad = true;
-        for (int c = 0; c < nc; ++c) ibh[f.bm + nc * b + c] = (int)(eb + c);
-      }
-      if (nd.parent >= 0) {
-        const NdNode& pa = t.nodes[nd.parent];
-        for (size_t b = 0; b < nd.bnd.size(); ++b) {
-          const int fp = nd_front_pos(pa, nd.bnd[b]);
-          if (fp < 0) bad = true;               // a child's shell lies in its parent's front
-          ibh[f.xm + b] = fp;
-        }
-      }
-      for (int a = 0; a < npp; ++a) pos[nd.piv[a]] = -1;
-      for (size_t b = 0; b < nd.bnd.size(); ++b) pos[nd.bnd[b]] = -1;
-    }
-  };
-  run_on_threads(nthr, fill_fronts);
-  if (bad) return LS_EINVAL;
-  if (next_front.load() < nn) return LS_ENOMEM;   // no thread could allocate its table
-  // factor offsets (R elements) and solve update rows
-  long fo = 0, uo = 0;
-  double fl = 0.0;
-  for (int id = 0; id < nn; ++id) {
-    FrontDev& f = g.fh[id];
-    const long np = f.np, nb = f.nb, nf = f.nf;
-    f.p = fo;
-    fo += 2 * np * nf;
-    f.l = fo;
-    fo += 2 * nb * np;
-    f.t = fo;
-    fo += 4L * kTileElems * ((np + kT - 1) / kT);
-    f.m = fo;
-    fo += 2L * kSB * kSB * ((np + kSB - 1) / kSB);
-    f.h = fo;
-    fo += 2L * kSB * kSB * ((np + kSB - 1) / kSB);
-    f.u = uo;
-    uo += nb;
-    for (long kb = 0; kb < np; kb += kT) {
-      const long ke = std::min(np, kb + kT), rows = nf - ke;
-      fl += 8.0 * (double)rows * (double)rows * (double)(ke - kb);
-    }
-  }
-  fac_elems = fo;
-  g.u_rows = uo;
-  g.flops = fl;
-  // level buffers and per-level extents
-  const int L = (int)g.levels.size();
-  g.lvl_off.assign(L, 0);
-  g.lvl_np.assign(L, 0);
-  g.lvl_nf.assign(L, 0);
-  g.lvl_elems.assign(L, 0);
-  long lo = 0;
-  for (int dep = 0; dep < L; ++dep) {
-    g.lvl_off[dep] = lo;
-    lo += (long)g.levels[dep].size();
-    size_t off = 0;
-    for (int id : g.levels[dep]) {
-      FrontDev& f = g.fh[id];
-      f.f = (long)off;
-      off += 2 * (size_t)f.nf * f.nf;
-      g.lvl_np[dep] = std::max(g.lvl_np[dep], f.np);
-      g.lvl_nf[dep] = std::max(g.lvl_nf[dep], f.nf);
-    }
-    g.lvl_elems[dep] = off;
-  }
-  // every map entry in range (checked once here, after the fill; the kernels trust them)
-  next_front = 0;
-  auto check_fronts = [&]() {
-    for (int id = next_front.fetch_add(1); id < nn; id = next_front.fetch_add(1)) {
-      const FrontDev& f = g.fh[id];
-      const NdNode& nd = t.nodes[id];
-      bool ok = true;
-      for (long i = 0; i < 27L * (long)nd.piv.size(); ++i) ok &= ibh[f.am + i] < f.nf / nc;
-      for (long i = 0; i < 27L * (long)nd.bnd.size(); ++i) ok &= ibh[f.ab + i] < f.np / nc;
-      if (nd.parent >= 0)
-        for (size_t b = 0; b < nd.bnd.size(); ++b) ok &= ibh[f.xm + b] < g.fh[nd.parent].nf / nc;
-      if (!ok) bad = true;
-    }
-  };
-  run_on_threads(nthr, check_fronts);
-  if (bad) return LS_EINVAL;
-  return LS_OK;
-}
-
 template <typename R>
 ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
   const int L = (int)g.levels.size();
@@ -1942,9 +1697,19 @@ ls_status gpu_factor_grid(const int dims[3], int nc, const C<double>* rows_dev, 
   g->nc = nc;
   g->npts = (long)dims[0] * dims[1] * dims[2];
   g->fp32 = fp32;
-  IntMap ibh;
-  long fac_elems = 0;
-  LS_TRY(symbolic(*g, ibh, fac_elems));
+  GpuSymbolic sym;
+  LS_TRY(gpu_symbolic(dims, nc, sym));
+  g->N = sym.N;
+  g->fh = std::move(sym.fh);
+  g->levels = std::move(sym.levels);
+  g->lvl_off = std::move(sym.lvl_off);
+  g->lvl_np = std::move(sym.lvl_np);
+  g->lvl_nf = std::move(sym.lvl_nf);
+  g->lvl_elems = std::move(sym.lvl_elems);
+  g->u_rows = sym.u_rows;
+  g->flops = sym.flops;
+  const long fac_elems = sym.fac_elems;
+  const IntMap& ibh = sym.ibh;
   const size_t rs = fp32 ? sizeof(float) : sizeof(double);
   LS_TRY(g->fac.alloc((size_t)fac_elems * rs));
   LS_TRY(g->ib.alloc(ibh.size() * sizeof(int)));

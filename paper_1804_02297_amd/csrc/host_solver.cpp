@@ -35,7 +35,9 @@
 #include <xmmintrin.h>
 #endif
 
-#if defined(__x86_64__)
+// LS_NO_TARGET_CLONES: one code path, for the ThreadSanitizer build (the
+// ifunc resolvers of target clones run before its runtime starts)
+#if defined(__x86_64__) && !defined(LS_NO_TARGET_CLONES)
 #define LS_CLONES __attribute__((target_clones("avx512f", "avx2", "default")))
 #else
 #define LS_CLONES
@@ -557,17 +559,21 @@ void factor_node(HostSolver& hs, int id, const std::complex<double>* rows, std::
   v.l21i.resize(nb * np);
   v.updr.resize(nb * nb);
   v.updi.resize(nb * nb);
+  // the root has no boundary (nb = 0): its U12, L21 and update blocks are
+  // empty vectors, which are never indexed
   for (long i = 0; i < np; ++i) {
-    std::memcpy(&v.l11r[i * np], &Fr[i * nf], np * sizeof(R));
-    std::memcpy(&v.l11i[i * np], &Fi[i * nf], np * sizeof(R));
-    std::memcpy(&v.u12r[i * nb], &Fr[i * nf + np], nb * sizeof(R));
-    std::memcpy(&v.u12i[i * nb], &Fi[i * nf + np], nb * sizeof(R));
+    std::memcpy(v.l11r.data() + i * np, Fr.data() + i * nf, np * sizeof(R));
+    std::memcpy(v.l11i.data() + i * np, Fi.data() + i * nf, np * sizeof(R));
+    if (nb > 0) {
+      std::memcpy(v.u12r.data() + i * nb, Fr.data() + i * nf + np, nb * sizeof(R));
+      std::memcpy(v.u12i.data() + i * nb, Fi.data() + i * nf + np, nb * sizeof(R));
+    }
   }
   for (long i = 0; i < nb; ++i) {
-    std::memcpy(&v.l21r[i * np], &Fr[(np + i) * nf], np * sizeof(R));
-    std::memcpy(&v.l21i[i * np], &Fi[(np + i) * nf], np * sizeof(R));
-    std::memcpy(&v.updr[i * nb], &Fr[(np + i) * nf + np], nb * sizeof(R));
-    std::memcpy(&v.updi[i * nb], &Fi[(np + i) * nf + np], nb * sizeof(R));
+    std::memcpy(v.l21r.data() + i * np, Fr.data() + (np + i) * nf, np * sizeof(R));
+    std::memcpy(v.l21i.data() + i * np, Fi.data() + (np + i) * nf, np * sizeof(R));
+    std::memcpy(v.updr.data() + i * nb, Fr.data() + (np + i) * nf + np, nb * sizeof(R));
+    std::memcpy(v.updi.data() + i * nb, Fi.data() + (np + i) * nf + np, nb * sizeof(R));
   }
 }
 
@@ -703,10 +709,11 @@ void fwd_node(HostSolver& hs, int id, int nrhs, const R* Br, const R* Bi, R* Zr,
       }
   W.ur[id].resize((size_t)nrhs * nb);
   W.ui[id].resize((size_t)nrhs * nb);
-  for (int r = 0; r < nrhs; ++r) {
-    std::memcpy(&W.ur[id][(size_t)r * nb], &wr[(size_t)r * nf + np], nb * sizeof(R));
-    std::memcpy(&W.ui[id][(size_t)r * nb], &wi[(size_t)r * nf + np], nb * sizeof(R));
-  }
+  if (nb > 0)   // the root has no update vector
+    for (int r = 0; r < nrhs; ++r) {
+      std::memcpy(W.ur[id].data() + (size_t)r * nb, wr.data() + (size_t)r * nf + np, nb * sizeof(R));
+      std::memcpy(W.ui[id].data() + (size_t)r * nb, wi.data() + (size_t)r * nf + np, nb * sizeof(R));
+    }
 }
 
 template <typename R>
