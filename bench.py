@@ -36,9 +36,9 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "4677f5972485c3a1652019bdd8e4fb98c78c1f97a3933c7b785595061258a863",
+    "sha256": "1c3b70ca131482ce74f40435738ad2eb0dc9390ff2a98e1a0a84ce2a84b0a9f2",
     "workload": (128, 8, "c64"),
-    "bytes": 3.3268e9,
+    "bytes": 3.3265e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
 }
 
@@ -85,9 +85,20 @@ def pass_bytes(n: int, P: int, B: int, s: int, s_io: int) -> list[float]:
     ]
 
 
-def cpu_baseline(n: int, seconds: float = 15.0):
-    """The oracle's FFT apply on the host, one rhs at a time, ~seconds of work."""
+def host_cores() -> int:
+    """Host threads available to this process (the machine's CPU share, at most 16)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(16, c))
+
+
+def cpu_baseline(n: int, seconds: float = 8.0):
+    """The oracle's FFT apply on the host, one rhs at a time, ~seconds of work,
+    with one FFT worker (the headline value) and with every host core."""
     import numpy as np
+    import scipy.fft
     from oracle import operator as op
     from paper_1804_02297_amd import inputs as I
     k = I.wavenumber_for(n)
@@ -96,17 +107,61 @@ def cpu_baseline(n: int, seconds: float = 15.0):
     t0 = time.perf_counter()
     Kh = op.kernel_symbol(n, k)
     t_setup = time.perf_counter() - t0
-    reps, t_apply = 0, 0.0
-    while t_apply < seconds and reps < 20:
-        t0 = time.perf_counter()
-        op.apply_fft(n, k, m, x, Kh)
-        t_apply += time.perf_counter() - t0
-        reps += 1
-    per = t_apply / reps
+
+    def run(workers):
+        reps, t_apply = 0, 0.0
+        with scipy.fft.set_workers(workers):
+            while t_apply < seconds and reps < 20:
+                t0 = time.perf_counter()
+                op.apply_fft(n, k, m, x, Kh)
+                t_apply += time.perf_counter() - t0
+                reps += 1
+        return reps, t_apply / reps
+
+    reps, per = run(1)
+    cores = host_cores()
+    reps_all, per_all = run(cores)
     return {"value": round(3 * n ** 3 / per / 1e6, 3), "unit": "Munknowns/s", "cores": 1,
             "kind": "oracle",
             "sample": f"oracle FFT apply (scipy.fft, 1 worker, FP64) of 1 rhs at n={n}, "
-                      f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed"}
+                      f"{reps} repetitions, {per:.2f} s each; symbol setup {t_setup:.1f} s untimed",
+            "all_cores": {"value": round(3 * n ** 3 / per_all / 1e6, 3), "unit": "Munknowns/s",
+                          "cores": cores, "kind": "oracle",
+                          "sample": f"the same apply with scipy.fft workers={cores} (the 3x3 symbol "
+                                    f"product stays on one thread), {reps_all} repetitions, "
+                                    f"{per_all:.2f} s each"}}
+
+
+def cpu_baseline_solve(n: int = 16):
+    """Per-rhs time to a 1e-8 residual of the oracle's plain FP64 path on the host
+    (the paper's class fit by thin SVD, SciPy's sparse LU of S, the oracle's
+    FGMRES(30) with its FFT apply), on one seeded plane wave: the CPU
+    counterpart of the per-rhs solve metric.  Set-up is timed apart."""
+    from oracle import fgmres as ofg
+    from oracle import operator as op
+    from oracle import sparse as osp
+    from oracle import stencil as ost
+    from paper_1804_02297_amd import inputs as I
+    k = I.wavenumber_for(n)
+    m = I.medium_single_bump(n, 0) if n == 16 else I.medium_bumps(n, 1)
+    d, p = I.random_direction_and_polarisation(0)
+    Ei = I.plane_waves(n, k, [d], [p])
+    t0 = time.perf_counter()
+    Kh = op.kernel_symbol(n, k)
+    g = op.rhs_from_incident(n, k, m, Ei, Kh)[0]
+    al, be, _ = ost.fit_all_classes(n, k)
+    S, Q = osp.assemble(n, m, al, be)
+    P = osp.Preconditioner(S, Q)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, info = ofg.fgmres(lambda v: op.apply_fft(n, k, m, v, Kh), g, P, tol=1e-8, restart=30)
+    t_solve = time.perf_counter() - t0
+    return {"value": round(t_solve, 3), "unit": "s per rhs", "cores": 1, "kind": "oracle",
+            "n": n, "iters": info["iters"], "rel_resid": float(f"{info['rel_resid']:.3e}"),
+            "setup_s": round(t_setup, 2),
+            "sample": f"oracle plain FP64 solve at n={n} ({3 * n ** 3} unknowns), 1 plane wave: "
+                      f"FGMRES(30) to 1e-8 with SciPy splu of S (one thread) and the FFT apply "
+                      f"(1 worker); set-up (symbol, 27 class SVDs, assembly, splu) {t_setup:.1f} s untimed"}
 
 
 def cpu_baseline_2d(n: int = 959, seconds: float = 5.0):
@@ -254,6 +309,127 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
                     "factor_class_c128_gpu": round(t_fac_cls, 3), "factor_learned_c64_gpu": round(t_fac_lrn, 3)},
         "tuned_apply": {k2: tune[k2] for k2 in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
     }
+
+
+def config4_section(binding, I, torch, n_eval: int = 5, media: int = 200, points: int = 4096,
+                    train_steps: int = 8000, n_eval_grid: int = 96):
+    """The learned-stencil workload: a network trained on exact per-point fits
+    (the medium-weighted fit) of `media` seeded six-bump media at n = 32, 48 and
+    64 (seeds 1000, 1001, ...; n cycling), `points` random interior points of
+    each, then evaluated on unseen media (seeds 2000, ...) at n = 96 (2.65M
+    unknowns) against the exact per-point fit and the paper's class fit.  Each
+    of the three stencil sets gets its own complex64 factor of S in HBM and
+    the same FGMRES (FP32 apply inside FP64, restart 30, to 1e-8) on one
+    seeded plane wave; iterations, fit, factor and solve times are reported,
+    with the FP64 residual recomputed by the library's FP64 apply."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4)
+    net = binding.Mlp(binding.Mlp.flat(_init_params(11)))
+    sizes = (32, 48, 64)
+    t0 = time.perf_counter()
+    for i in range(media):
+        n = sizes[i % 3]
+        interior = np.array([(a * n + b) * n + c for a in range(1, n - 1) for b in range(1, n - 1)
+                             for c in range(1, n - 1)])
+        pts = rng.choice(interior, min(points, len(interior)), replace=False)
+        pt = binding.Plan(n, I.wavenumber_for(n), torch.from_numpy(I.medium_bumps(n, 1000 + i)).to(dev))
+        net.add_samples(pt, pts)
+        pt.close()
+        if (i + 1) % 50 == 0:
+            _progress(f"config 4: samples of {i + 1} media")
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = net.train(train_steps, batch=1024, lr=1e-3, seed=0)
+    t_train = time.perf_counter() - t0
+    nsamp = net.num_samples()
+    _progress(f"config 4: {nsamp} samples in {t_samples:.1f} s, training {t_train:.1f} s")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    n = n_eval_grid
+    k = I.wavenumber_for(n)
+    evals = []
+    for e in range(n_eval):
+        seed = 2000 + e
+        m = torch.from_numpy(I.medium_bumps(n, seed)).to(dev)
+        plan = binding.Plan(n, k, m, max_rhs=1)
+        d, p = I.random_direction_and_polarisation(seed)
+        g = plan.rhs_from_incident(torch.from_numpy(I.plane_waves(n, k, [d], [p])).to(dev))
+        row = {"seed": seed}
+        for name in ("class", "exact", "learned"):
+            if name == "class":
+                t_fit, _ = timed(lambda: plan.stencil_fit(0))
+                extra = {}
+            elif name == "exact":
+                t_fit, _ = timed(lambda: plan.stencil_fit(1))
+                extra = {}
+            else:
+                t_fit, nfb = timed(lambda: plan.stencil_fit_learned(net))
+                extra = {"fallback_points": int(nfb), "interior_points": (n - 2) ** 3}
+            t_fac, _ = timed(lambda: plan.factor_gpu("c64"))
+            t_sol, (x, info, st) = timed(lambda: plan.solve(g, tol=1e-8, prec="mixed"))
+            r = torch.empty_like(g)
+            plan.apply(x, r, prec="c128")
+            rel = (torch.linalg.vector_norm(g - r) / torch.linalg.vector_norm(g)).item()
+            row[name] = {"iters": info[0]["iters"], "fit_s": round(t_fit, 3), "factor_s": round(t_fac, 2),
+                         "solve_s": round(t_sol, 3), "rel_resid_fp64": float(f"{rel:.3e}"), "status": st, **extra}
+            _progress(f"config 4: seed {seed} {name}: {info[0]['iters']} iterations, fit {t_fit:.2f} s, "
+                      f"factor {t_fac:.1f} s, solve {t_sol:.2f} s")
+        plan.close()
+        del m, g
+        torch.cuda.empty_cache()
+        evals.append(row)
+    net.close()
+
+    def mean(key, field):
+        return round(float(np.mean([r[key][field] for r in evals])), 3)
+
+    return {"train": {"media": media, "grids": list(sizes), "points_per_medium": points,
+                      "samples": int(nsamp), "samples_s": round(t_samples, 2),
+                      "train_steps": train_steps, "batch": 1024, "train_s": round(t_train, 2),
+                      "loss_first_last": [round(float(loss[0]), 4), round(float(np.mean(loss[-50:])), 4)]},
+            "eval_n": n, "eval_unknowns": 3 * n ** 3, "eval": evals,
+            "mean": {v: {"iters": mean(v, "iters"), "fit_s": mean(v, "fit_s"), "solve_s": mean(v, "solve_s")}
+                     for v in ("class", "exact", "learned")},
+            "learned_fallback_fraction": round(float(np.mean([r["learned"]["fallback_points"] /
+                                                              r["learned"]["interior_points"] for r in evals])), 4)}
+
+
+def solve_config1(n: int, binding, I, torch):
+    """The plain FP64 path on the GPU for the oracle's solve baseline: the same
+    medium and plane wave, class stencils, complex128 factor of S in HBM, FP64
+    apply, FGMRES(30) to 1e-8, one rhs (median of 5 solves after a warm-up)."""
+    dev = torch.device("cuda:0")
+    k = I.wavenumber_for(n)
+    m = I.medium_single_bump(n, 0) if n == 16 else I.medium_bumps(n, 1)
+    d, p = I.random_direction_and_polarisation(0)
+    plan = binding.Plan(n, k, torch.from_numpy(m).to(dev), max_rhs=1)
+    g = plan.rhs_from_incident(torch.from_numpy(I.plane_waves(n, k, [d], [p])).to(dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.stencil_fit(0)
+    plan.factor_gpu("c128")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    plan.solve(g, tol=1e-8, prec="c128")
+    ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, st = plan.solve(g, tol=1e-8, prec="c128")
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    plan.close()
+    ts.sort()
+    return {"n": n, "plain_fp64_s_per_rhs": round(ts[2], 5), "iters": info[0]["iters"],
+            "rel_resid": info[0]["rel_resid"], "status": st, "setup_s": round(t_setup, 3)}
 
 
 def _progress(msg: str):
@@ -428,25 +604,28 @@ def two_d_section(binding, I, torch, steps: int, n: int = 959, B: int = 8, solve
     return out
 
 
-def hbm_copy_gbps(torch, gib: float = 2.0) -> float:
-    """Device-to-device copy bandwidth (read + write bytes / time) of a torch copy."""
+def hbm_copy_gbps(torch, binding, gib: float = 2.0):
+    """Device-to-device copy bandwidth (read + write bytes / time): torch's copy
+    and the library's streaming copy (ls_hbm_copy), the achievable ceiling."""
     n = int(gib * (1 << 30)) // 4
     a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(2):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    gbps = 2 * a.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9
+    out = []
+    for fn in (lambda: b.copy_(a), lambda: binding.hbm_copy(b, a, n * 4)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(round(2 * a.numel() * 4 / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9, 1))
     del a, b
     torch.cuda.empty_cache()
-    return round(gbps, 1)
+    return out
 
 
 def main():
@@ -457,7 +636,12 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--config4", type=int, default=0,
+                    help="learned-stencil workload: unseen media evaluated at 96^3 (0: skip; ~70 s each)")
+    ap.add_argument("--config4-media", type=int, default=200, help="training media of the learned workload")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-solve-n", type=int, default=16,
+                    help="grid of the oracle's per-rhs solve baseline (0: skip; 32 takes ~7 min of set-up)")
     ap.add_argument("--no-n192", dest="n192", action="store_false", help="skip the 192^3 apply line")
     ap.add_argument("--two-d-n", type=int, default=959, help="grid of the 2-D variant's apply line (0: skip)")
     ap.add_argument("--two-d-solve-n", type=int, default=959, help="grid of the 2-D lens solve (0: skip)")
@@ -563,14 +747,28 @@ def main():
     if args.two_d_n:
         _progress("2-D variant")
         out["two_d"] = two_d_section(binding, I, torch, args.steps, n=args.two_d_n, solve_n=args.two_d_solve_n)
-    out["hbm_copy_GBps"] = hbm_copy_gbps(torch)
+    torch_copy, stream_copy = hbm_copy_gbps(torch, binding)
+    out["hbm_copy_GBps"] = torch_copy
+    out["hbm_stream_copy_GBps"] = stream_copy
+    out["roofline"]["copy_ceiling_GBps"] = stream_copy
+    out["apply_whole_frac_of_copy"] = round(whole / stream_copy, 4)
     if args.solve_n:
         ex = (args.solve_n <= 48) if args.solve_exact < 0 else bool(args.solve_exact)
         hf = (args.solve_n <= 32) if args.solve_host_factor < 0 else bool(args.solve_host_factor)
         out["solve"] = solve_section(args.solve_n, args.solve_dirs, binding, I, torch, exact_iters=ex,
                                      host_factor_chosen=hf, host_factor_plain=hf)
+    if args.config4:
+        out["config4"] = config4_section(binding, I, torch, n_eval=args.config4, media=args.config4_media)
+    if args.cpu_solve_n and not args.no_cpu:
+        out["solve_config1"] = solve_config1(args.cpu_solve_n, binding, I, torch)
     if not args.no_cpu:
+        _progress("CPU oracle baselines")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        if args.cpu_solve_n:
+            out["cpu_baseline"]["solve"] = cpu_baseline_solve(args.cpu_solve_n)
+            if "solve_config1" in out:
+                out["cpu_baseline"]["solve"]["gpu_over_cpu_per_rhs"] = round(
+                    out["cpu_baseline"]["solve"]["value"] / out["solve_config1"]["plain_fp64_s_per_rhs"], 1)
         if args.two_d_n:
             out["cpu_baseline"]["two_d"] = cpu_baseline_2d(args.two_d_n)
     print(json.dumps(out), flush=True)

@@ -68,17 +68,15 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 #ifndef LS_COL_RUN_BYTES
 #define LS_COL_RUN_BYTES 256
 #endif
-// The dim-2 inverse (mode COL_INV) reads twice what it writes; it runs with
-// half-length runs, whose smaller LDS tile fits more workgroups per CU to
-// cover its read latency (measured at 128^3 and 64^3: 8 % faster, while the
-// other passes are fastest with full runs).  The tile is capped at 64 KB of
-// LDS, except in the dim-1 passes (modes 0 and 3, whose rows lie n^2 apart)
-// which may use 96 KB so that P = 384 keeps full runs (192^3: 0.29 ms faster
-// over the two passes; the dim-2 forward is slower with 96 KB).
+// Every pass uses full runs (with non-temporal loads and stores, halving the
+// run of any one pass at 128^3 was 1-11 % slower, and the dim-2 inverse
+// gained 2 % from full runs).  The tile is capped at 64 KB of LDS, except
+// in the dim-1 passes (modes 0 and 3, whose rows lie n^2 apart) which may
+// use 96 KB so that P = 384 keeps full runs (192^3: 0.29 ms faster over the
+// two passes; the dim-2 forward is slower with 96 KB).
 template <typename R>
 constexpr int col_tile(int P, int mode) {
   int t = LS_COL_RUN_BYTES / (2 * (int)sizeof(R));
-  if (mode == 2 && t > 8) t /= 2;
   const long cap = (mode == 0 || mode == 3) ? 98304 : 65536;
   while (t > 8 && (long)P * t * 2 * (long)sizeof(R) > cap) t /= 2;
   return t;
