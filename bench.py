@@ -150,7 +150,9 @@ def cpu_baseline_solve(n: int = 16):
     Kh = op.kernel_symbol(n, k)
     g = op.rhs_from_incident(n, k, m, Ei, Kh)[0]
     al, be, _ = ost.fit_all_classes(n, k)
+    _progress(f"oracle solve n={n}: class fit done at {time.perf_counter() - t0:.0f} s")
     S, Q = osp.assemble(n, m, al, be)
+    _progress(f"oracle solve n={n}: assembly done at {time.perf_counter() - t0:.0f} s, sparse LU next")
     P = osp.Preconditioner(S, Q)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()

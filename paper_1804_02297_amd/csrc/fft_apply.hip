@@ -275,13 +275,20 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
     constexpr bool PREFETCH = sizeof(R) == 4 && P == 256;
     C<R> pre[3][KIN];
     if (PREFETCH && active && j < N1) {
+      if (2 * n == P) {     // every t = j + N1 k < P/2 is a grid point: no bounds, no zero fill
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int k = 0; k < KIN; ++k) {
-          const int tt = j + N1 * k;
-          pre[c][k] = (tt < n) ? ld_stream(base + c * plane + tt) : cmk<R>(0, 0);
-        }
+          for (int k = 0; k < KIN; ++k) pre[c][k] = ld_stream(base + c * plane + j + N1 * k);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < KIN; ++k) {
+            const int tt = j + N1 * k;
+            pre[c][k] = (tt < n) ? ld_stream(base + c * plane + tt) : cmk<R>(0, 0);
+          }
+      }
     }
     C<R> u[3][N1];
 #pragma unroll
