@@ -469,6 +469,146 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 }
 
+// pass B held in registers (FP32 at the paper's lengths P = 972 and 486).
+// Each column transform of length P = N1 N2 is a four-step FFT: N1 threads
+// each take a length-N2 DFT of the rows t = j + N1 k (only rows below P/2
+// hold data), a twiddle by W_P^{j q}, one LDS exchange, then N2 threads each
+// take a length-N1 DFT; the inverse runs the same steps backwards.  A
+// workgroup owns NB adjacent columns of one rhs (consecutive lanes take
+// consecutive columns, so every row access is a run of NB values) and keeps
+// one exchange buffer of NB P values in LDS, with the twiddle table.
+// The two steps run on different waves: "row" waves (the length-N2 DFTs,
+// HBM loads and stores) and "frequency" waves (the length-N1 DFTs and the
+// symbol multiply), so each holds only its own values.  The fields are
+// transformed in the order p.x, m x_1, m x_2: the spectrum of p.x is kept in
+// LDS, and each of the other two is multiplied by the symbol together with
+// it and inverse-transformed at once, so no output accumulator lives across
+// the three forward transforms.
+// Measured at 8 rhs: P = 972 (n = 479) 0.135 against 0.167 ms for the LDS
+// kernel, P = 486 (n = 239) 0.030 against 0.042 ms.  At P = 1944 (36 x 54,
+// four columns per workgroup, 229 VGPRs, 140 KB of LDS: one workgroup of
+// seven waves per CU) it took 0.82 against 0.76 ms, so that length keeps the
+// LDS kernel.
+template <int P>
+struct ColRegCfg {
+  static constexpr int N1 = P == 972 ? 27 : (P == 486 ? 18 : 0);
+  static constexpr int N2 = P / (N1 > 0 ? N1 : 1);
+  static constexpr int NB = P == 972 ? 8 : 16;          // columns per workgroup
+  static constexpr int RPW = 64 / NB;                   // DFT indices per wavefront
+  static constexpr int RA = (N1 + RPW - 1) / RPW * RPW; // row-wave threads per column
+  static constexpr int RB = (N2 + RPW - 1) / RPW * RPW; // frequency-wave threads per column
+  static constexpr int THREADS = NB * (RA + RB);
+  static constexpr int EXS = P + 8;                     // exchange stride of one column (complex)
+};
+
+template <int P>
+__global__ __launch_bounds__(ColRegCfg<P>::THREADS) void pass_b_reg_kernel(
+    const C<float>* __restrict__ T, C<float>* __restrict__ T2, const C<float>* __restrict__ sym, int n, int H,
+    int nrhs, const C<float>* __restrict__ tw) {
+  using Cfg = ColRegCfg<P>;
+  constexpr int N1 = Cfg::N1, N2 = Cfg::N2, NB = Cfg::NB, EXS = Cfg::EXS, RA = Cfg::RA;
+  constexpr int KIN = (P / 2 + N1 - 1) / N1;       // rows t = j + N1 k < P/2
+  constexpr int KOUT = (P / 2 + N1 - 1) / N1;      // outputs t = j + N1 t1 < P/2
+  __shared__ C<float> ex[NB * EXS];
+  __shared__ C<float> x2l[NB * P];         // spectrum of p.x, [column][a][j]
+  __shared__ C<float> twl[P];
+  for (int e = threadIdx.x; e < P; e += blockDim.x) twl[e] = tw[e];
+  const int ncb = (P + NB - 1) / NB;       // the last block may hang over the last column
+  const int w = xcd_work_index(blockIdx.x, ncb * nrhs);
+  const int b = w % nrhs;
+  const int q0 = (w / nrhs) * NB;
+  const int c = threadIdx.x % NB;          // column within the block
+  const int r = threadIdx.x / NB;          // wave-uniform role: r < RA row waves
+  const bool live = q0 + c < P;            // columns past the last are computed on zeros, never stored
+  const int q2 = live ? q0 + c : 0;
+  C<float>* myex = ex + (size_t)c * EXS;
+  __syncthreads();
+  if (r < RA) {
+    // row waves: forward step 1 of the three fields, inverse step 3' of the two outputs
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+      const int fld = f == 0 ? 2 : f - 1;
+      // the row offsets are recomputed per field rather than kept live
+      // across the loop (27 of them would not fit beside the transform)
+      int j = r, col = q2;
+      asm volatile("" : "+v"(j), "+v"(col));
+      if (j < N1) {
+        // a uniform base and 32-bit element offsets (the field is < 2^31 bytes)
+        const C<float>* in = T + ((size_t)(b * 3 + fld) * n) * P;
+        C<float> v[N2];
+#pragma unroll
+        for (int k = 0; k < KIN; ++k) {
+          const int t = j + N1 * k;
+          v[k] = (live && t < n) ? ld_stream(in + (col + t * P)) : cmk<float>(0.f, 0.f);
+        }
+        DftZ<N2, -1, float, KIN>::run(v);
+#pragma unroll
+        for (int q = 0; q < N2; ++q) myex[q * N1 + j] = (q == 0) ? v[q] : v[q] * twl[j * q];
+      }
+      __syncthreads();   // exchange written
+      __syncthreads();   // exchange read by the frequency waves
+      if (f == 0) continue;
+      __syncthreads();   // inverse exchange written
+      if (j < N1) {
+        C<float> v[N2];
+#pragma unroll
+        for (int q = 0; q < N2; ++q) v[q] = myex[q * N1 + j];
+        Dft<N2, 1, float>::run(v);
+        C<float>* out = T2 + ((size_t)(b * 2 + fld) * n) * P;
+#pragma unroll
+        for (int t1 = 0; t1 < KOUT; ++t1) {
+          const int t = j + N1 * t1;
+          if (live && t < n) st_stream(out + (col + t * P), v[t1]);
+        }
+      }
+      __syncthreads();   // inverse exchange read
+    }
+  } else {
+    // frequency waves: forward step 3, the symbol multiply, inverse step 1'
+    const bool f2 = 2 * q2 > P;
+    C<float>* x2 = x2l + (size_t)c * P + (r - RA);   // this thread's frequencies, stride N2 (read back by itself only)
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+      const int d = f - 1;
+      // symbol offsets are recomputed per output rather than kept live across the loop
+      int j = r - RA, a2 = f2 ? P - q2 : q2;
+      asm volatile("" : "+v"(j), "+v"(a2));
+      __syncthreads();   // exchange written
+      C<float> u[N1];
+      if (j < N2) {
+#pragma unroll
+        for (int a = 0; a < N1; ++a) u[a] = myex[j * N1 + a];
+        Dft<N1, -1, float>::run(u);
+      }
+      __syncthreads();   // exchange read
+      if (f == 0) {
+        if (j < N2)
+#pragma unroll
+          for (int a = 0; a < N1; ++a) x2[a * N2] = u[a];
+        continue;
+      }
+      if (j < N2) {
+#pragma unroll
+        for (int a = 0; a < N1; ++a) {
+          const int q1 = j + N2 * a;
+          const bool f1 = 2 * q1 > P;
+          const int a1 = f1 ? P - q1 : q1;
+          const int so = (a1 * H + a2) * 3;
+          const C<float> s0 = sym[so];
+          C<float> sd = sym[so + 1 + d];
+          if (d == 0 ? f1 : f2) sd = cmk<float>(-sd.re, -sd.im);   // G^1 odd in q1, G^2 odd in q2
+          u[a] = cfma(sd, x2[a * N2], s0 * u[a]);
+        }
+        Dft<N1, 1, float>::run(u);
+#pragma unroll
+        for (int t2 = 0; t2 < N1; ++t2) myex[j * N1 + t2] = (t2 == 0) ? u[t2] : u[t2] * cconj(twl[j * t2]);
+      }
+      __syncthreads();   // inverse exchange written
+      __syncthreads();   // inverse exchange read
+    }
+  }
+}
+
 // pass C: block w -> (rhs b, component d, row block rb); y = x + v (or -v).
 template <typename R, typename IO, int PT, int NBT>
 __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2, const void* __restrict__ x,
@@ -758,8 +898,14 @@ ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_co
     LS_HIP(hipGetLastError());
     constexpr int EMAX = (int)(kLds2 / (2 * sizeof(C<R>)) / kTB);
     if (ev) LS_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kTB), ldsc, s, T, T2, sym, n, P, pl.H,
-                       pl.rd, nbc, nr, tw);
+    if constexpr (std::is_same<R, float>::value && PT > 0 && ColRegCfg<(PT > 0 ? PT : 1)>::N1 > 0) {
+      using Cfg = ColRegCfg<PT>;
+      hipLaunchKernelGGL((pass_b_reg_kernel<PT>), dim3(((PT + Cfg::NB - 1) / Cfg::NB) * nr), dim3(Cfg::THREADS), 0, s, T,
+                         T2, sym, n, pl.H, nr, tw);
+    } else {
+      hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kTB), ldsc, s, T, T2, sym, n, P,
+                         pl.H, pl.rd, nbc, nr, tw);
+    }
     LS_HIP(hipGetLastError());
     const int wc = nr * 2 * nrb;
     if (ev) LS_HIP(hipEventRecord(ev[2], s));
