@@ -116,6 +116,21 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
   const long line = (long)tile * T + t;
   const bool live = line < L;
 
+  // the identity term of the last pass is loaded with the transform's input
+  // rather than after the transform (its latency would otherwise end every
+  // workgroup)
+  C<IO> xid[QOUT];
+  if (MODE == COL_P5) {
+    const C<IO>* x = reinterpret_cast<const C<IO>*>(mfac);
+#pragma unroll
+    for (int q1 = 0; q1 < QOUT; ++q1) {
+      const int row = j + N2 * q1;
+      xid[q1] = (x && live && j < N2 && row < rows_out)
+                    ? ld_stream(x + batch * out_bstride + (long)row * L + line)
+                    : cmk<IO>(0, 0);
+    }
+  }
+
   if (j < N1) {
     C<R> v[N2];
 #pragma unroll
@@ -155,8 +170,7 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
           const long off = batch * out_bstride + (long)row * L + line;
           if (MODE == COL_P5) {
             C<IO>* y = reinterpret_cast<C<IO>*>(out_);
-            const C<IO>* x = reinterpret_cast<const C<IO>*>(mfac);  // identity term, or none
-            C<IO> xv = x ? ld_stream(x + off) : cmk<IO>(0, 0);
+            const C<IO> xv = xid[q1];                                // identity term, or zero
             st_stream(y + off, cmk<IO>(xv.re + (IO)(w[q1].re * scale), xv.im + (IO)(w[q1].im * scale)));
           } else {
             st_stream(reinterpret_cast<C<R>*>(out_) + off, w[q1]);
