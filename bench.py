@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "1c3b70ca131482ce74f40435738ad2eb0dc9390ff2a98e1a0a84ce2a84b0a9f2",
+    "sha256": "2f7392698e6d3eeda75e3dd64abb58c99332f224b38250fb53935431ea5befdf",
     "workload": (128, 8, "c64"),
     "bytes": 3.3265e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
