@@ -271,7 +271,7 @@ ls_status mlp_add_samples(MlpState& st, StencilData& sd, int n, double k, const 
     const int cnt = std::min(B, npts - p0);
     const int* dp = dpts.as<int>() + p0;
     LS_TRY(pointfit_grams(ctx, m, m0, dp, cnt, s));
-    LS_TRY(pointfit_solve(ctx, sd, dp, cnt, 12, s));
+    LS_TRY(pointfit_solve(ctx, sd, dp, cnt, kPointIters, s));
     hipLaunchKernelGGL(gauge_kernel, dim3(nbl(cnt, 64)), dim3(64), 0, s, sd.palpha.as<C<double>>(), dp, cnt,
                        gt.as<C<double>>(), dok.as<int>());
     LS_HIP(hipGetLastError());
@@ -394,7 +394,7 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
       // exact fit for the rejected points: their Grams again, in the order of the list
       LS_HIP(hipMemcpyAsync(dfail.p, fail.data(), fail.size() * sizeof(int), hipMemcpyHostToDevice, s));
       LS_TRY(pointfit_grams(ctx, m, m0, dfail.as<int>(), (int)fail.size(), s));
-      LS_TRY(pointfit_solve(ctx, sd, dfail.as<int>(), (int)fail.size(), 12, s));
+      LS_TRY(pointfit_solve(ctx, sd, dfail.as<int>(), (int)fail.size(), kPointIters, s));
     }
     LS_TRY(pointfit_beta(ctx, sd, dp, cnt, s));
   }

@@ -151,15 +151,17 @@ __device__ __forceinline__ void wsync() {
 // One workgroup of four wavefronts per point.  G: packed lower triangles
 // [np][3321] complex; X0: [81][8] warm start (class Ritz vectors).  Writes
 // alpha [pts[p]][81][3] and the three smallest Ritz values:
-//   1. Cholesky G + shift I = L L^H, right-looking, packed in LDS;
+//   1. Cholesky G + shift I = L L^H in 9 x 9 blocks, packed in LDS;
 //   2. W = L^-1 in place, eight rows per step;
-//   3. `iters` block inverse iterations X <- W^H (W X), each followed by
-//      modified Gram-Schmidt twice (wavefront 0);
-//   4. Rayleigh-Ritz with the unshifted G and an 8x8 cyclic Jacobi (wavefront 0).
+//   3. `iters` block inverse iterations X <- W^H (W X), each followed by a
+//      Cholesky QR of the 8 columns (twice after the last);
+//   4. Rayleigh-Ritz with the unshifted G and an 8x8 parallel cyclic Jacobi
+//      (wavefront 0).
 // The products of step 3 have no sequential dependency, so all four SIMDs of
 // the CU share them; only the factorisation and the 8x8 work are sequential.
 constexpr int HB = 256;           // threads per point
 constexpr int RBW = 8;            // rows per step of the triangular inverse
+constexpr int CB = 9;             // block size of the Cholesky factorisation
 __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restrict__ Gall, int np,
                                                         const C<double>* __restrict__ X0, int iters,
                                                         const int* __restrict__ pts,
@@ -186,27 +188,56 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   if (t < R81) L[LI(t, t)].re += 1e-15 * trace;
   __syncthreads();
 
-  // 1. Cholesky.  Step kk updates the trailing triangle from the unscaled
-  // column kk (scaled by 1/d^2 on use), then scales the column; the next
-  // step reads neither column kk nor entries this step's scaling writes.
-  for (int kk = 0; kk < R81; ++kk) {
-    const double dkk = sqrt(fmax(L[LI(kk, kk)].re, 1e-300));
-    const double dinv = 1.0 / dkk;
-    const double d2 = dinv * dinv;
-    const int m = R81 - kk - 1;
-    const int tot = m * (m + 1) / 2;
+  // 1. Cholesky in 9 x 9 blocks: (a) the diagonal block on wavefront 0,
+  // one lane per entry of its lower triangle; (b) the block column below by
+  // substitution, one thread per row; (c) the trailing triangle, K = 9.
+  for (int k0 = 0; k0 < R81; k0 += CB) {
+    if (t < 64) {
+      int ii = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      while (ii * (ii + 1) / 2 > t) --ii;
+      const int jj = t - ii * (ii + 1) / 2;
+      const bool own = t < CB * (CB + 1) / 2;
+      for (int j = 0; j < CB; ++j) {
+        if (own && ii == j && jj == j) L[LI(k0 + j, k0 + j)] = cmk(sqrt(fmax(L[LI(k0 + j, k0 + j)].re, 1e-300)), 0.0);
+        wsync();
+        if (own && jj == j && ii > j) L[LI(k0 + ii, k0 + j)] = cscale(L[LI(k0 + ii, k0 + j)], 1.0 / L[LI(k0 + j, k0 + j)].re);
+        wsync();
+        if (own && jj > j) L[LI(k0 + ii, k0 + jj)] = L[LI(k0 + ii, k0 + jj)] - L[LI(k0 + ii, k0 + j)] * cconj(L[LI(k0 + jj, k0 + j)]);
+        wsync();
+      }
+    }
+    __syncthreads();
+    const int nbl = R81 - k0 - CB;
+    if (t < nbl) {
+      const int i = k0 + CB + t;
+      C<double> row[CB];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) row[q] = L[LI(i, k0 + q)];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {
+        C<double> s = row[j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) s = s - row[q] * cconj(L[LI(k0 + j, k0 + q)]);
+        row[j] = cscale(s, 1.0 / L[LI(k0 + j, k0 + j)].re);
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) L[LI(i, k0 + q)] = row[q];
+    }
+    __syncthreads();
+    const int tot = nbl * (nbl + 1) / 2;
     for (int e = t; e < tot; e += HB) {
       int ii = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
       while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
       while (ii * (ii + 1) / 2 > e) --ii;
-      const int i = kk + 1 + ii, j = kk + 1 + (e - ii * (ii + 1) / 2);
-      L[LI(i, j)] = L[LI(i, j)] - cscale(L[LI(i, kk)] * cconj(L[LI(j, kk)]), d2);
+      const int i = k0 + CB + ii, j = k0 + CB + (e - ii * (ii + 1) / 2);
+      C<double> acc = L[LI(i, j)];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) acc = acc - L[LI(i, k0 + q)] * cconj(L[LI(j, k0 + q)]);
+      L[LI(i, j)] = acc;
     }
     __syncthreads();
-    for (int i = kk + 1 + t; i < R81; i += HB) L[LI(i, kk)] = cscale(L[LI(i, kk)], dinv);
-    if (t == 0) L[LI(kk, kk)] = cmk(dkk, 0.0);
   }
-  __syncthreads();
 
   // 2. W = L^-1 in place, rows [i0, i1) per step: (a) every thread forms
   // partial sums acc[r][j] = sum_{j <= k < i0} L[i0+r][k] W[k][j] over the
@@ -254,60 +285,79 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
     __syncthreads();
   }
 
-  // 3. block inverse iteration with (G + shift)^-1 = W^H W
-  for (int e = t; e < R81 * EBW; e += HB) X[e / EBW][e % EBW] = X0[e];
+  // 3. block inverse iteration with (G + shift)^-1 = W^H W; after each step
+  // the block is orthonormalised by Cholesky QR: the 8 x 8 Gram from four
+  // partial sums, its Cholesky factor R and R^-1 on wavefront 0, then
+  // X R^-1 into the other buffer.  One step scales the columns by at most
+  // lambda_8 / lambda_1 (about 1e2 on these Grams), so a single Cholesky QR
+  // keeps them orthonormal to about 1e-12 between steps; the last step
+  // orthonormalises twice for the Rayleigh-Ritz.
+  C<double>(*PX)[EBW + 1] = X;
+  C<double>(*PY)[EBW + 1] = Y;
+  for (int e = t; e < R81 * EBW; e += HB) PX[e / EBW][e % EBW] = X0[e];
   __syncthreads();
   const int c = t & (EBW - 1), rg = t / EBW;      // column, row group (32 groups)
   const int l = t;                                 // lane index inside wavefront 0
   for (int it = 0; it < iters; ++it) {
     for (int i = rg; i < R81; i += HB / EBW) {
       C<double> acc = cmk(0.0, 0.0);
-      for (int k = 0; k <= i; ++k) acc = acc + L[LI(i, k)] * X[k][c];
-      Y[i][c] = acc;
+      for (int k = 0; k <= i; ++k) acc = acc + L[LI(i, k)] * PX[k][c];
+      PY[i][c] = acc;
     }
     __syncthreads();
     for (int i = rg; i < R81; i += HB / EBW) {
       C<double> acc = cmk(0.0, 0.0);
-      for (int k = i; k < R81; ++k) acc = acc + cconj(L[LI(k, i)]) * Y[k][c];
-      X[i][c] = acc;
+      for (int k = i; k < R81; ++k) acc = acc + cconj(L[LI(k, i)]) * PY[k][c];
+      PX[i][c] = acc;
     }
     __syncthreads();
-    // classical Gram-Schmidt with one reorthogonalisation, column by column,
-    // on all four wavefronts: thread (part, d) sums conj(X[i][d]) X[i][cc]
-    // over the rows i = part (mod 32), the partial sums meet in LDS
-    for (int cc = 0; cc < EBW; ++cc) {
-      for (int pass = 0; pass < 2 && cc > 0; ++pass) {
-        {
-          const int d = t % EBW, part = t / EBW;
-          C<double> h = cmk(0.0, 0.0);
-          if (d < cc)
-            for (int i = part; i < R81; i += HB / EBW) h = h + cconj(X[i][d]) * X[i][cc];
-          Y[part][d] = h;                                   // Y: 32 x 8 partial sums
-        }
-        __syncthreads();
-        if (t < cc) {
-          C<double> h = cmk(0.0, 0.0);
-          for (int part = 0; part < HB / EBW; ++part) h = h + Y[part][t];
-          T[0][t] = h;
-        }
-        __syncthreads();
-        if (t < R81) {
-          C<double> v = X[t][cc];
-          for (int d = 0; d < cc; ++d) v = v - X[t][d] * T[0][d];
-          X[t][cc] = v;
-        }
-        __syncthreads();
+    const int npass = (it + 1 == iters) ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+      {
+        const int pq = t & 63, part = t >> 6, pp = pq >> 3, qq = pq & 7;
+        C<double> h = cmk(0.0, 0.0);
+        for (int i = part; i < R81; i += 4) h = h + cconj(PX[i][pp]) * PX[i][qq];
+        (&PY[0][0])[part * 64 + pq] = h;
       }
-      if (t < R81) red[t] = X[t][cc].re * X[t][cc].re + X[t][cc].im * X[t][cc].im;
       __syncthreads();
-      double nr = 0.0;
-      for (int q = 0; q < R81; ++q) nr += red[q];
-      const double sc = 1.0 / sqrt(nr);
-      __syncthreads();                                      // red is reused next column
-      if (t < R81) X[t][cc] = cscale(X[t][cc], sc);
+      if (t < 64) {
+        const int pp = l >> 3, qq = l & 7;
+        const C<double>* pa = &PY[0][0];
+        T[pp][qq] = pa[l] + pa[64 + l] + pa[128 + l] + pa[192 + l];
+        wsync();
+        // T = R^H R, R upper in the upper triangle of T
+        for (int j = 0; j < EBW; ++j) {
+          if (pp == j && qq == j) T[j][j] = cmk(sqrt(fmax(T[j][j].re, 1e-300)), 0.0);
+          wsync();
+          if (pp == j && qq > j) T[j][qq] = cscale(T[j][qq], 1.0 / T[j][j].re);
+          wsync();
+          if (pp > j && qq >= pp) T[pp][qq] = T[pp][qq] - cconj(T[j][pp]) * T[j][qq];
+          wsync();
+        }
+        // V = R^-1 (upper), one column per lane
+        if (l < EBW) {
+          const int q = l;
+          for (int r = EBW - 1; r >= 0; --r) {
+            C<double> s = cmk(r == q ? 1.0 : 0.0, 0.0);
+            for (int k = r + 1; k <= q; ++k) s = s - T[r][k] * V[k][q];
+            V[r][q] = (r <= q) ? cscale(s, 1.0 / T[r][r].re) : cmk(0.0, 0.0);
+          }
+        }
+        wsync();
+      }
       __syncthreads();
+      for (int i = rg; i < R81; i += HB / EBW) {
+        C<double> acc = cmk(0.0, 0.0);
+        for (int d = 0; d <= c; ++d) acc = acc + PX[i][d] * V[d][c];
+        PY[i][c] = acc;
+      }
+      __syncthreads();
+      C<double>(*sw)[EBW + 1] = PX;
+      PX = PY;
+      PY = sw;
     }
   }
+
 
   // 4. Rayleigh-Ritz with the unshifted G (reloaded into L): GX (81 x 8)
   // into Y, T = X^H (G X)
@@ -315,16 +365,16 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   __syncthreads();
   for (int i = rg; i < R81; i += HB / EBW) {
     C<double> acc = cmk(0.0, 0.0);
-    for (int j = 0; j <= i; ++j) acc = acc + L[LI(i, j)] * X[j][c];
-    for (int j = i + 1; j < R81; ++j) acc = acc + cconj(L[LI(j, i)]) * X[j][c];
-    Y[i][c] = acc;
+    for (int j = 0; j <= i; ++j) acc = acc + L[LI(i, j)] * PX[j][c];
+    for (int j = i + 1; j < R81; ++j) acc = acc + cconj(L[LI(j, i)]) * PX[j][c];
+    PY[i][c] = acc;
   }
   __syncthreads();
   if (t >= 64) return;                              // the 8x8 work is one wavefront's
   {
     const int pp = l / EBW, qq = l % EBW;
     C<double> sacc = cmk(0.0, 0.0);
-    for (int i = 0; i < R81; ++i) sacc = sacc + cconj(X[i][pp]) * Y[i][qq];
+    for (int i = 0; i < R81; ++i) sacc = sacc + cconj(PX[i][pp]) * PY[i][qq];
     T[pp][qq] = sacc;
     V[pp][qq] = cmk(pp == qq ? 1.0 : 0.0, 0.0);
   }
@@ -336,7 +386,13 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
     T[pp][qq] = cmk(0.5 * (a.re + b.re), 0.5 * (a.im + b.im));
     wsync();
   }
-  // cyclic Jacobi, one rotation at a time, every lane owns one entry (i, j)
+  // parallel cyclic Jacobi: a sweep is seven rounds of four disjoint
+  // rotations (round r pairs 7 with r and i with (2r - i) mod 7), which
+  // commute, so a round is one update T <- U^H T U, V <- V U.  Lanes 0..7
+  // form the column of U of their index (U[i][i] and U[partner][i]), then
+  // every lane updates its entry (i, j).
+  __shared__ double Ud[EBW];
+  __shared__ C<double> Uo[EBW];
   for (int sweep = 0; sweep < 12; ++sweep) {
     {
       // converged: off-diagonal mass below 1e-30 of the diagonal's (uniform)
@@ -352,59 +408,45 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
       dia = __shfl(dia, 0);
       if (off <= 1e-30 * dia) break;
     }
-    for (int p1 = 0; p1 < EBW; ++p1)
-      for (int q1 = p1 + 1; q1 < EBW; ++q1) {
+    for (int r = 0; r < EBW - 1; ++r) {
+      auto partner = [r](int i) { return i == EBW - 1 ? r : (i == r ? EBW - 1 : (2 * r - i + 2 * (EBW - 1)) % (EBW - 1)); };
+      if (l < EBW) {
+        // both lanes of a pair compute its rotation from the same entries
+        const int pi = partner(l), p1 = min(l, pi), q1 = max(l, pi);
         const C<double> apq = T[p1][q1];
         const double ab = sqrt(apq.re * apq.re + apq.im * apq.im);
-        if (ab <= 1e-300) continue;                       // uniform across the wave
-        const C<double> ph = cmk(apq.re / ab, apq.im / ab);
-        const double tau = (T[q1][q1].re - T[p1][p1].re) / (2.0 * ab);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-        const int i = l / EBW, j = l % EBW;
-        // T' = U^H T U with U = identity except columns p1, q1:
-        //   U[:,p1] = c e_p1 - sn conj(ph) e_q1 ,  U[:,q1] = sn ph e_p1 + c e_q1
-        auto ucol = [&](int col, int row) -> C<double> {
-          if (col == p1) return row == p1 ? cmk(c, 0.0) : (row == q1 ? cscale(cconj(ph), -sn) : cmk(0.0, 0.0));
-          if (col == q1) return row == p1 ? cscale(ph, sn) : (row == q1 ? cmk(c, 0.0) : cmk(0.0, 0.0));
-          return cmk(row == col ? 1.0 : 0.0, 0.0);
-        };
-        // (T U)[r][j] for r in {i, p1, q1} needed: compute new entry directly
-        C<double> tu_i, tu_p, tu_q;
-        // column j of T U, rows i, p1, q1
-        auto tu = [&](int r, int cj) -> C<double> {
-          if (cj == p1) return T[r][p1] * ucol(p1, p1) + T[r][q1] * ucol(p1, q1);
-          if (cj == q1) return T[r][p1] * ucol(q1, p1) + T[r][q1] * ucol(q1, q1);
-          return T[r][cj];
-        };
-        tu_i = tu(i, j);
-        tu_p = tu(p1, j);
-        tu_q = tu(q1, j);
-        C<double> nv;
-        if (i == p1)
-          nv = cconj(ucol(p1, p1)) * tu_p + cconj(ucol(p1, q1)) * tu_q;
-        else if (i == q1)
-          nv = cconj(ucol(q1, p1)) * tu_p + cconj(ucol(q1, q1)) * tu_q;
-        else
-          nv = tu_i;
-        // V U
-        C<double> vnew;
-        if (j == p1)
-          vnew = V[i][p1] * ucol(p1, p1) + V[i][q1] * ucol(p1, q1);
-        else if (j == q1)
-          vnew = V[i][p1] * ucol(q1, p1) + V[i][q1] * ucol(q1, q1);
-        else
-          vnew = V[i][j];
-        wsync();
-        T[i][j] = nv;
-        V[i][j] = vnew;
-        wsync();
-        if (l == 0) {
-          T[p1][q1] = cmk(0.0, 0.0);
-          T[q1][p1] = cmk(0.0, 0.0);
+        double ud = 1.0;
+        C<double> uo = cmk(0.0, 0.0);
+        if (ab > 1e-300) {
+          const C<double> ph = cmk(apq.re / ab, apq.im / ab);
+          const double tau = (T[q1][q1].re - T[p1][p1].re) / (2.0 * ab);
+          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+          // U[:,p1] = c e_p1 - sn conj(ph) e_q1 ,  U[:,q1] = sn ph e_p1 + c e_q1
+          ud = c;
+          uo = (l == p1) ? cscale(cconj(ph), -sn) : cscale(ph, sn);
         }
-        wsync();
+        Ud[l] = ud;
+        Uo[l] = uo;
       }
+      wsync();
+      const int i = l / EBW, j = l % EBW, pi = partner(i), pj = partner(j);
+      const double di = Ud[i], dj = Ud[j];
+      const C<double> oi = Uo[i], oj = Uo[j];
+      C<double> nv;
+      if (j == pi && (oi.re != 0.0 || oi.im != 0.0)) {
+        nv = cmk(0.0, 0.0);                                 // the rotated pair's entry
+      } else {
+        const C<double> ri = cscale(T[i][j], dj) + T[i][pj] * oj;
+        const C<double> rp = cscale(T[pi][j], dj) + T[pi][pj] * oj;
+        nv = cscale(ri, di) + cconj(oi) * rp;
+      }
+      const C<double> vnew = cscale(V[i][j], dj) + V[i][pj] * oj;
+      wsync();
+      T[i][j] = nv;
+      V[i][j] = vnew;
+      wsync();
+    }
   }
   // the three smallest Ritz values
   int idx[EBW];
@@ -421,7 +463,7 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   for (int e = l; e < R81 * 3; e += 64) {
     const int i = e / 3, v = e % 3;
     C<double> s = cmk(0.0, 0.0);
-    for (int q = 0; q < EBW; ++q) s = s + X[i][q] * V[q][idx[v]];
+    for (int q = 0; q < EBW; ++q) s = s + PX[i][q] * V[q][idx[v]];
     out[e] = s;
   }
   if (eval_out && l < 3) eval_out[pt * 3 + l] = T[idx[l]][idx[l]].re;
