@@ -309,7 +309,7 @@ def solve_section(n: int, ndirs: int, binding, I, torch, train_media: int = 4, t
                     "class_fit": round(t_fit_cls, 3), "point_fit_exact": round(t_fit_pt, 3),
                     "learned_fit": round(t_fit_lrn, 3),
                     "factor_class_c128_gpu": round(t_fac_cls, 3), "factor_learned_c64_gpu": round(t_fac_lrn, 3)},
-        "tuned_apply": {k2: tune[k2] for k2 in ("chunk", "kmul_w", "ms_per_rhs", "ms_default_per_rhs")},
+        "tuned_apply": _tune_choice(tune),
     }
 
 
@@ -450,6 +450,10 @@ def _init_params(seed: int):
     return p
 
 
+def _tune_choice(t: dict) -> dict:
+    return {k: t[k] for k in ("chunk", "kmul_w", "half_runs", "persist", "ms_per_rhs", "ms_default_per_rhs")}
+
+
 def apply_192(binding, I, torch, steps: int, B: int = 8):
     """The apply at n = 192 (padded 384^3 FFTs), FP32, 8 rhs: throughput and pass rates."""
     import numpy as np
@@ -461,6 +465,7 @@ def apply_192(binding, I, torch, steps: int, B: int = 8):
     g = torch.Generator(device=dev).manual_seed(99)
     x = torch.randn((B, 3, n, n, n), dtype=torch.complex64, device=dev, generator=g)
     y = torch.empty_like(x)
+    tune = plan.tune(B, "c64")                # launch choices (set-up, outside the timed region)
     for _ in range(3):
         plan.apply(x, y, prec="c64")
     torch.cuda.synchronize()
@@ -481,7 +486,7 @@ def apply_192(binding, I, torch, steps: int, B: int = 8):
     plan.close()
     del x, y
     torch.cuda.empty_cache()
-    return {"n": n, "fft_size": P, "nrhs": B, "ms_per_apply": round(ms, 3),
+    return {"n": n, "fft_size": P, "nrhs": B, "tuned": _tune_choice(tune), "ms_per_apply": round(ms, 3),
             "Munknowns_per_s": round(B * 3 * n ** 3 / (ms * 1e-3) / 1e6, 1),
             "whole_GBps": round(sum(pb) / (ms * 1e-3) / 1e9, 1),
             "pass_ms": [round(v, 4) for v in pms],
@@ -676,6 +681,8 @@ def main():
     x32 = x64.to(torch.complex64)
     y32 = torch.empty_like(x32)
     y64 = torch.empty_like(x64)
+    # launch choices of the FP32 apply from the autotuner (set-up, untimed)
+    tune32 = plan.tune(B, "c64")
     torch.cuda.synchronize()
 
     def timed(prec, x, y, steps, warmup):
@@ -729,6 +736,7 @@ def main():
         "data": "synthetic: seeded sum-of-6-Gaussians contrast, random complex fields",
         "config": {"workload": f"LS apply, n={n} (P={P}), {B} rhs, FP32 FFTs",
                    "n": n, "fft_size": P, "nrhs": B, "unknowns_per_rhs": 3 * n ** 3},
+        "tuned": _tune_choice(tune32),
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "pass": PASS_NAMES[dom],
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

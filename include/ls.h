@@ -99,22 +99,31 @@ typedef struct {
   double ms_default_per_rhs;  /* the same for the built-in default (0 on a cache hit)   */
   int from_cache;             /* 1: read from desc.tune_cache, nothing was timed        */
   int n_tried;                /* choices timed                                          */
+  int half_runs;              /* bit i: strided pass i (dim-1 forward, dim-2 forward,
+                                 dim-2 inverse, dim-1 inverse) reads and writes rows in
+                                 128-byte runs (its FFT tile halved) instead of 256     */
+  int persist;                /* 1: persistent launches (grids of the resident
+                                 workgroups, which stride over the work items)          */
 } ls_tune_info;
 
 /* Autotune the apply of prec for batches of nrhs: look the key (GPU, n, P,
- * form, prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time every
- * choice on the plan's operator (scratch fields of nrhs, allocated and freed
- * here), keep the fastest and append it to the cache file (a JSON array, one
- * object per line; rewritten through a temporary file).  The choice then holds
+ * form, prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time the
+ * choices on the plan's operator (scratch fields of nrhs, allocated and freed
+ * here): every chunk x team count, then each strided pass with half runs in
+ * turn (kept where faster), then persistent launches; keep the fastest and
+ * append it to the cache file (a JSON array, one object per line; rewritten
+ * through a temporary file).  The choice then holds
  * for every later apply and solve of that precision.  A cache that cannot be
  * written is not an error.  The choices are those of the dyadic form:
  * LS_ESTATE while the plan's form is LS_FORM_PAPER, whose apply has a single
  * launch choice.  Synchronises hip_stream.  info may be NULL. */
 ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, ls_tune_info* info);
 
-/* Set the launch choice of prec by hand (chunk 0 / kmul_w 0 = default).
- * LS_EINVAL for chunk > max_rhs or kmul_w not in {0, 1, 2, 4}. */
-ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w);
+/* Set the launch choice of prec by hand (chunk 0 / kmul_w 0 = default;
+ * half_runs and persist as in ls_tune_info, 0 = default).  LS_EINVAL for
+ * chunk > max_rhs, kmul_w not in {0, 1, 2, 4}, half_runs outside 0..15 or
+ * persist not 0 or 1. */
+ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w, int half_runs, int persist);
 
 /* ls_apply for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -72,7 +72,7 @@ SIGNATURES = [
     ("ls_sparse_destroy", None, [_VP]),
     ("ls_plan_fft_size", _I, [_VP]),
     ("ls_plan_set_form", _I, [_VP, _I, _VP]),
-    ("ls_plan_tune", _I, [_VP, _I, _I, _VP, _VP]), ("ls_plan_set_tune", _I, [_VP, _I, _I, _I]),
+    ("ls_plan_tune", _I, [_VP, _I, _I, _VP, _VP]), ("ls_plan_set_tune", _I, [_VP, _I, _I, _I, _I, _I]),
     ("ls_plan_destroy", None, [_VP]),
     # the 2-D variant
     ("ls2_plan_create", _I, [_I, _D, _I, _VP, _VP, ctypes.POINTER(_VP)]),
@@ -92,7 +92,8 @@ SIGNATURES = [
 
 class TuneInfo(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("kmul_w", ctypes.c_int), ("ms_per_rhs", ctypes.c_double),
-                ("ms_default_per_rhs", ctypes.c_double), ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int)]
+                ("ms_default_per_rhs", ctypes.c_double), ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int),
+                ("half_runs", ctypes.c_int), ("persist", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -477,8 +478,8 @@ class Plan:
         _check(_lib.ls_plan_tune(self._h, nrhs, PREC[prec], _stream(), ctypes.byref(info)), "ls_plan_tune")
         return info.as_dict()
 
-    def set_tune(self, prec: str, chunk: int = 0, kmul_w: int = 0):
-        _check(_lib.ls_plan_set_tune(self._h, PREC[prec], chunk, kmul_w), "ls_plan_set_tune")
+    def set_tune(self, prec: str, chunk: int = 0, kmul_w: int = 0, half_runs: int = 0, persist: int = 0):
+        _check(_lib.ls_plan_set_tune(self._h, PREC[prec], chunk, kmul_w, half_runs, persist), "ls_plan_set_tune")
 
     def rhs_from_incident(self, Ei, g=None):
         """g = -K * (m E^i) (right-hand side of Eq. (4)), complex128."""

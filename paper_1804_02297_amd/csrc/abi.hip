@@ -162,8 +162,10 @@ ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, 
     TuneOutcome r;
     LS_TRY(apply_tune(plan->ap, plan->tune_cache, nrhs, prec, as_stream(hip_stream), &r));
     if (info) {
-      info->chunk = r.chunk;
-      info->kmul_w = r.kmul_w;
+      info->chunk = r.t.chunk;
+      info->kmul_w = r.t.kmul_w;
+      info->half_runs = r.t.half_runs;
+      info->persist = r.t.persist;
       info->ms_per_rhs = r.ms_per_rhs;
       info->ms_default_per_rhs = r.ms_default_per_rhs;
       info->from_cache = r.from_cache;
@@ -173,14 +175,17 @@ ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, 
   });
 }
 
-ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w) {
+ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w, int half_runs, int persist) {
   return guarded([&]() -> ls_status {
     if (!plan) return LS_EINVAL;
     if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
     if (chunk < 0 || chunk > plan->ap.max_rhs) return LS_EINVAL;
     if (kmul_w != 0 && kmul_w != 1 && kmul_w != 2 && kmul_w != 4) return LS_EINVAL;
+    if (half_runs < 0 || half_runs > 15 || (persist != 0 && persist != 1)) return LS_EINVAL;
     plan->ap.tune[prec].chunk = chunk;
     plan->ap.tune[prec].kmul_w = kmul_w;
+    plan->ap.tune[prec].half_runs = half_runs;
+    plan->ap.tune[prec].persist = persist;
     return LS_OK;
   });
 }
@@ -208,7 +213,7 @@ ls_status ls_stencil_fit(ls_plan* plan, ls_fit_mode mode, void* hip_stream) {
     // the class stencils depend on (n, k) only: computed once per plan
     if (!plan->sd.have_class) LS_TRY(class_fit(plan->sd, plan->ap.n, plan->ap.k, s));
     if (mode == LS_FIT_POINT)
-      LS_TRY(point_fit(plan->sd, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0, 16384, 12, s));
+      LS_TRY(point_fit(plan->sd, plan->ap.n, plan->ap.k, plan->ap.m64.as<C<double>>(), kPointFitM0, 16384, kPointIters, s));
     LS_TRY(assemble_rows(plan->sd, plan->ap.n, plan->ap.m64.as<C<double>>(), s));
     LS_HIP(hipStreamSynchronize(s));
     plan->sd.have_rows = true;

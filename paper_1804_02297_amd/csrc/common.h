@@ -63,6 +63,11 @@ struct DevBuf {
 struct ApplyTune {
   int chunk = 0;                 // right-hand sides per apply launch set (<= max_rhs)
   int kmul_w = 0;                // pass-3 teams per workgroup (1, 2, 4)
+  int half_runs = 0;             // bit i set: strided pass i (0 dim-1 forward, 1 dim-2
+                                 // forward, 2 dim-2 inverse, 3 dim-1 inverse) works on
+                                 // half-length row runs (128 bytes instead of 256)
+  int persist = 0;               // 1: every pass launches only the workgroups the device
+                                 // holds at once, and each takes work items grid-stride
 };
 
 struct ApplyPlan {

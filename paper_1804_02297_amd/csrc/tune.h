@@ -7,7 +7,7 @@
 namespace ls {
 
 struct TuneOutcome {
-  int chunk = 0, kmul_w = 0;
+  ApplyTune t;
   double ms_per_rhs = 0.0, ms_default_per_rhs = 0.0;
   int from_cache = 0, n_tried = 0, cache_write_failed = 0;
 };

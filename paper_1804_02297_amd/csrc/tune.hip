@@ -1,15 +1,25 @@
 // Autotuner of the batched apply: for one (n, precision, batch) it times every
 // launch choice on the plan's own operator and keeps the fastest.
 //
-// Choices: the right-hand sides per launch set (chunk: 1, 2, 4, ... up to the
-// batch) and the pass-3 teams per workgroup (1, 2, 4 where a team is one
-// wavefront).  A smaller chunk trades launch count for a working set that can
-// stay in the last-level cache between passes; the team count trades
-// workgroup size against phase overlap on a CU.  Each candidate runs once to
-// warm up, then 3 times between HIP events.
+// Choices:
+//   * the right-hand sides per launch set (chunk: 1, 2, 4, ... up to the
+//     batch): a smaller chunk trades launch count for a working set that can
+//     stay in the last-level cache between passes;
+//   * the pass-3 teams per workgroup (1, 2, 4 where a team is one wavefront):
+//     workgroup size against phase overlap on a CU;
+//   * the row-run length of each strided pass (256 or 128 bytes, the FFT tile
+//     of the pass): a half tile halves the workgroup's LDS and fits more
+//     workgroups per CU to cover its latency;
+//   * persistent launches: every pass launches only the workgroups the device
+//     holds at once, which stride over the work items.
+// The first two are searched jointly, then each pass's run length is halved
+// in turn and kept where it is faster, then the persistent launch is tried on
+// the result.  Each candidate runs once to warm up, then 3 times between HIP
+// events.
 //
 // Cache: a JSON array, one object per line,
-//   {"key": "<arch>|cu=<CUs>|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>", "chunk": c, "kmul_w": w, "ms_per_rhs": t}
+//   {"key": "<arch>|cu=<CUs>|v=2|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>",
+//    "chunk": c, "kmul_w": w, "half_runs": r, "persist": q, "ms_per_rhs": t}
 // read before timing (a hit skips it) and rewritten with the new entry after.
 #include <algorithm>
 #include <cstdio>
@@ -36,14 +46,14 @@ std::string tune_key(const ApplyPlan& ap, int nrhs, ls_prec prec) {
     cus = prop.multiProcessorCount;
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s|cu=%d|n=%d|P=%d|form=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus, ap.n,
-                ap.P, ap.form, (int)prec, nrhs, ap.max_rhs);
+  std::snprintf(buf, sizeof buf, "%s|cu=%d|v=2|n=%d|P=%d|form=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus,
+                ap.n, ap.P, ap.form, (int)prec, nrhs, ap.max_rhs);
   return buf;
 }
 
 struct Entry {
   std::string key;
-  int chunk = 0, kmul_w = 0;
+  ApplyTune t;
   double ms = 0.0;
 };
 
@@ -65,7 +75,9 @@ std::vector<Entry> read_cache(const std::string& path) {
     if (k1 == std::string::npos) continue;
     Entry e;
     e.key = line.substr(k0, k1 - k0);
-    if (!parse_int_field(line, "chunk", &e.chunk) || !parse_int_field(line, "kmul_w", &e.kmul_w)) continue;
+    if (!parse_int_field(line, "chunk", &e.t.chunk) || !parse_int_field(line, "kmul_w", &e.t.kmul_w) ||
+        !parse_int_field(line, "half_runs", &e.t.half_runs) || !parse_int_field(line, "persist", &e.t.persist))
+      continue;
     const size_t t = line.find("\"ms_per_rhs\":");
     if (t != std::string::npos) std::sscanf(line.c_str() + t + 13, " %lf", &e.ms);
     out.push_back(e);
@@ -81,8 +93,11 @@ bool write_cache(const std::string& path, const std::vector<Entry>& es) {
     f << "[\n";
     for (size_t i = 0; i < es.size(); ++i) {
       char buf[512];
-      std::snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"chunk\": %d, \"kmul_w\": %d, \"ms_per_rhs\": %.6g}%s\n",
-                    es[i].key.c_str(), es[i].chunk, es[i].kmul_w, es[i].ms, i + 1 < es.size() ? "," : "");
+      std::snprintf(buf, sizeof buf,
+                    "{\"key\": \"%s\", \"chunk\": %d, \"kmul_w\": %d, \"half_runs\": %d, \"persist\": %d, "
+                    "\"ms_per_rhs\": %.6g}%s\n",
+                    es[i].key.c_str(), es[i].t.chunk, es[i].t.kmul_w, es[i].t.half_runs, es[i].t.persist, es[i].ms,
+                    i + 1 < es.size() ? "," : "");
       f << buf;
     }
     f << "]\n";
@@ -119,11 +134,10 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
   if (!cache.empty()) {
     entries = read_cache(cache);
     for (const Entry& e : entries)
-      if (e.key == key && e.chunk >= 1 && e.chunk <= ap.max_rhs && e.kmul_w >= 1) {
-        ap.tune[prec].chunk = e.chunk;
-        ap.tune[prec].kmul_w = e.kmul_w;
-        res.chunk = e.chunk;
-        res.kmul_w = e.kmul_w;
+      if (e.key == key && e.t.chunk >= 1 && e.t.chunk <= ap.max_rhs && e.t.kmul_w >= 1 && e.t.half_runs >= 0 &&
+          e.t.half_runs <= 15 && (e.t.persist == 0 || e.t.persist == 1)) {
+        ap.tune[prec] = e.t;
+        res.t = e.t;
         res.ms_per_rhs = e.ms;
         res.from_cache = 1;
         if (out) *out = res;
@@ -155,19 +169,38 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
   ap.tune[prec] = ApplyTune{};
   st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &res.ms_default_per_rhs);
   res.ms_default_per_rhs /= nrhs;
-  for (size_t ci = 0; ci < chunks.size() && st == LS_OK; ++ci)
-    for (size_t wi = 0; wi < teams.size() && st == LS_OK; ++wi) {
-      if (teams[wi] > chunks[ci]) continue;       // a team needs its own right-hand side
-      ap.tune[prec].chunk = chunks[ci];
-      ap.tune[prec].kmul_w = teams[wi];
-      double ms = 0.0;
-      st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &ms);
-      ++res.n_tried;
-      if (st == LS_OK && ms < best) {
-        best = ms;
-        pick = ap.tune[prec];
-      }
+  auto trial = [&](const ApplyTune& t) {
+    if (st != LS_OK) return;
+    ap.tune[prec] = t;
+    double ms = 0.0;
+    st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &ms);
+    ++res.n_tried;
+    if (st == LS_OK && ms < best) {
+      best = ms;
+      pick = t;
     }
+  };
+  // 1. rhs per launch set x pass-3 teams
+  for (size_t ci = 0; ci < chunks.size(); ++ci)
+    for (size_t wi = 0; wi < teams.size(); ++wi) {
+      if (teams[wi] > chunks[ci]) continue;       // a team needs its own right-hand side
+      ApplyTune t;
+      t.chunk = chunks[ci];
+      t.kmul_w = teams[wi];
+      trial(t);
+    }
+  // 2. half runs, one strided pass at a time
+  for (int bit = 1; bit <= 8; bit <<= 1) {
+    ApplyTune t = pick;
+    t.half_runs |= bit;
+    trial(t);
+  }
+  // 3. persistent launches
+  {
+    ApplyTune t = pick;
+    t.persist = 1;
+    trial(t);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != LS_OK) {
@@ -175,14 +208,12 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
     return st;
   }
   ap.tune[prec] = pick;
-  res.chunk = pick.chunk;
-  res.kmul_w = pick.kmul_w;
+  res.t = pick;
   res.ms_per_rhs = best / nrhs;
   if (!cache.empty()) {
     Entry e;
     e.key = key;
-    e.chunk = pick.chunk;
-    e.kmul_w = pick.kmul_w;
+    e.t = pick;
     e.ms = res.ms_per_rhs;
     entries.push_back(e);
     if (!write_cache(cache, entries)) res.cache_write_failed = 1;

@@ -1,9 +1,10 @@
 """Block right-hand sides and the apply autotuner on the GPU.
 
 Every launch choice (right-hand sides per launch set, pass-3 teams per
-workgroup) runs the same arithmetic in the same order, so results must be
-bitwise identical across choices; the tuned batch apply must also match the
-oracle within the FP32 bar.  The tuner's cache file must round-trip.
+workgroup, the row-run length of each strided pass, persistent launches)
+runs the same arithmetic in the same order, so results must be bitwise
+identical across choices; the tuned batch apply must also match the oracle
+within the FP32 bar.  The tuner's cache file must round-trip.
 """
 import json
 
@@ -31,20 +32,37 @@ def test_launch_choices_bitwise_identical(lib, prec):
     dt = torch.complex64 if prec == "c64" else torch.complex128
     x = torch.from_numpy(I.random_field(B, n, 11)).to("cuda:0").to(dt)
     ref = plan.apply(x, prec=prec)
-    for chunk, w in [(1, 1), (2, 2), (4, 4), (4, 1), (3, 2), (1, 4)]:
-        plan.set_tune(prec, chunk, w)
+    for choice in [(1, 1, 0, 0), (2, 2, 0, 0), (4, 4, 0, 0), (4, 1, 0, 0), (3, 2, 0, 0), (1, 4, 0, 0),
+                   (4, 2, 15, 0), (4, 2, 5, 1), (2, 4, 0, 1), (3, 1, 10, 1)]:
+        plan.set_tune(prec, *choice)
         y = plan.apply(x, prec=prec)
-        assert torch.equal(y, ref), (chunk, w)
+        assert torch.equal(y, ref), choice
     plan.set_tune(prec, 0, 0)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_launch_choices_bitwise_identical_p256(lib, prec):
+    """P = 256: the paired-lane FP64 pass 3 and the prefetching FP32 one, with
+    ordinary and persistent grids, full and half runs."""
+    n, B = 97, 2
+    plan = _plan(n, B)
+    assert plan.P == 256
+    x = torch.from_numpy(I.random_field(B, n, 13)).to("cuda:0")
+    ref = plan.apply(x, prec=prec)
+    for choice in [(1, 1, 0, 0), (2, 2, 0, 1), (2, 1, 15, 1), (1, 2, 6, 0)]:
+        plan.set_tune(prec, *choice)
+        assert torch.equal(plan.apply(x, prec=prec), ref), choice
     plan.close()
 
 
 def test_set_tune_rejects_bad_choices(lib):
     from paper_1804_02297_amd.binding import LSError
     plan = _plan(8, 2)
-    for chunk, w in [(3, 0), (-1, 0), (0, 3), (0, 8)]:
+    for choice in [(3, 0, 0, 0), (-1, 0, 0, 0), (0, 3, 0, 0), (0, 8, 0, 0), (0, 0, 16, 0), (0, 0, -1, 0),
+                   (0, 0, 0, 2)]:
         with pytest.raises(LSError):
-            plan.set_tune("c64", chunk, w)
+            plan.set_tune("c64", *choice)
     plan.close()
 
 
@@ -54,12 +72,14 @@ def test_tune_picks_valid_choice_and_caches(lib, tmp_path):
     plan = _plan(n, B, cache)
     info = plan.tune(B, "c64")
     print("tune", info, flush=True)
-    assert info["from_cache"] == 0 and info["n_tried"] >= 4
+    assert info["from_cache"] == 0 and info["n_tried"] >= 4 + 5
     assert 1 <= info["chunk"] <= B and info["kmul_w"] in (1, 2, 4)
+    assert 0 <= info["half_runs"] <= 15 and info["persist"] in (0, 1)
     assert 0 < info["ms_per_rhs"] <= info["ms_default_per_rhs"] * 1.05
     with open(cache) as f:
         entries = json.load(f)
     assert len(entries) == 1 and f"n={n}|P=128|form=0|prec=1|nrhs={B}" in entries[0]["key"]
+    assert (entries[0]["half_runs"], entries[0]["persist"]) == (info["half_runs"], info["persist"])
     # the tuned apply still matches the oracle (FP32 bar) on every rhs
     x = I.random_field(B, n, 12)
     y = plan.apply(torch.from_numpy(x).to("cuda:0").to(torch.complex64), prec="c64").cpu().numpy()
@@ -73,7 +93,8 @@ def test_tune_picks_valid_choice_and_caches(lib, tmp_path):
     plan2 = _plan(n, B, cache)
     info2 = plan2.tune(B, "c64")
     assert info2["from_cache"] == 1 and info2["n_tried"] == 0
-    assert (info2["chunk"], info2["kmul_w"]) == (info["chunk"], info["kmul_w"])
+    keys = ("chunk", "kmul_w", "half_runs", "persist")
+    assert [info2[k] for k in keys] == [info[k] for k in keys]
     # another precision adds a second entry
     plan2.tune(B, "mixed")
     with open(cache) as f:
