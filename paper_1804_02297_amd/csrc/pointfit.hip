@@ -148,13 +148,70 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Y = op(A) X for the 81 x 8 complex blocks X, Y in LDS (rows padded to EBW + 1)
+// and A given by its packed lower triangle Lp: OP 0 A = Lp (lower triangular),
+// 1 A = Lp^H (upper triangular), 2 A = the Hermitian matrix with lower
+// triangle Lp.  On FP64 MFMA (16x16x4) in realified form: a 16-row tile of
+// [Re Y | Im Y] (16 columns) accumulates Re A [Re X | Im X] + Im A [-Im X | Re X]
+// over k in steps of 4 (lane l holds A(row l%16, k l/16) and B(k l/16, col
+// l%16); result D(4r + l/16, l%16) in register r).  The six row tiles are
+// shared by the four wavefronts so that each does about the same number of
+// nonzero k steps.
+template <int OP>
+__device__ __forceinline__ void mm81x8(const C<double>* __restrict__ Lp, const C<double> (*X)[EBW + 1],
+                                       C<double> (*Y)[EBW + 1], int wave, int lane) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  // tiles of each wave: OP 0 needs (mt + 1) k blocks, OP 1 (6 - mt), OP 2 six
+  constexpr int T0[3][4][2] = {{{5, -1}, {4, 0}, {3, 1}, {2, -1}},
+                               {{0, -1}, {1, 5}, {2, 4}, {3, -1}},
+                               {{0, 4}, {1, 5}, {2, -1}, {3, -1}}};
+  const int col = lane & 15, c8 = col & 7, kl = lane >> 4;
+  for (int ti = 0; ti < 2; ++ti) {
+    const int mt = T0[OP][wave][ti];
+    if (mt < 0) break;                                  // uniform over the wave
+    const int row = 16 * mt + (lane & 15);
+    const int kb = (OP == 1) ? 16 * mt : 0;
+    const int ke = (OP == 0) ? min(R81, 16 * mt + 16) : R81;
+    v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k4 = kb; k4 < ke; k4 += 4) {
+      const int k = k4 + kl;
+      C<double> a = cmk(0.0, 0.0);
+      if (row < R81 && k < R81) {
+        if (OP == 0) {
+          if (k <= row) a = Lp[LI(row, k)];
+        } else if (OP == 1) {
+          if (k >= row) a = cconj(Lp[LI(k, row)]);
+        } else {
+          a = (k <= row) ? Lp[LI(row, k)] : cconj(Lp[LI(k, row)]);
+        }
+      }
+      const C<double> x = (k < R81) ? X[k][c8] : cmk(0.0, 0.0);
+      const double b1 = (col < EBW) ? x.re : x.im;
+      const double b2 = (col < EBW) ? -x.im : x.re;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b2, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 16 * mt + 4 * r + kl;
+      if (rr < R81) {
+        if (col < EBW)
+          Y[rr][c8].re = acc[r];
+        else
+          Y[rr][c8].im = acc[r];
+      }
+    }
+  }
+}
+
 // One workgroup of four wavefronts per point.  G: packed lower triangles
 // [np][3321] complex; X0: [81][8] warm start (class Ritz vectors).  Writes
 // alpha [pts[p]][81][3] and the three smallest Ritz values:
 //   1. Cholesky G + shift I = L L^H in 9 x 9 blocks, packed in LDS;
 //   2. W = L^-1 in place, eight rows per step;
-//   3. `iters` block inverse iterations X <- W^H (W X), each followed by a
-//      Cholesky QR of the 8 columns (twice after the last);
+//   3. `iters` block inverse iterations X <- W^H (W X) (products on FP64
+//      MFMA), each followed by a Cholesky QR of the 8 columns (twice after
+//      the last);
 //   4. Rayleigh-Ritz with the unshifted G and an 8x8 parallel cyclic Jacobi
 //      (wavefront 0).
 // The products of step 3 have no sequential dependency, so all four SIMDs of
@@ -298,18 +355,11 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   __syncthreads();
   const int c = t & (EBW - 1), rg = t / EBW;      // column, row group (32 groups)
   const int l = t;                                 // lane index inside wavefront 0
+  const int wave = t >> 6, lane = t & 63;
   for (int it = 0; it < iters; ++it) {
-    for (int i = rg; i < R81; i += HB / EBW) {
-      C<double> acc = cmk(0.0, 0.0);
-      for (int k = 0; k <= i; ++k) acc = acc + L[LI(i, k)] * PX[k][c];
-      PY[i][c] = acc;
-    }
+    mm81x8<0>(L, PX, PY, wave, lane);              // Y = W X
     __syncthreads();
-    for (int i = rg; i < R81; i += HB / EBW) {
-      C<double> acc = cmk(0.0, 0.0);
-      for (int k = i; k < R81; ++k) acc = acc + cconj(L[LI(k, i)]) * PY[k][c];
-      PX[i][c] = acc;
-    }
+    mm81x8<1>(L, PY, PX, wave, lane);              // X = W^H Y
     __syncthreads();
     const int npass = (it + 1 == iters) ? 2 : 1;
     for (int pass = 0; pass < npass; ++pass) {
@@ -363,12 +413,7 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   // into Y, T = X^H (G X)
   for (int e = t; e < NPK; e += HB) L[e] = G[e];
   __syncthreads();
-  for (int i = rg; i < R81; i += HB / EBW) {
-    C<double> acc = cmk(0.0, 0.0);
-    for (int j = 0; j <= i; ++j) acc = acc + L[LI(i, j)] * PX[j][c];
-    for (int j = i + 1; j < R81; ++j) acc = acc + cconj(L[LI(j, i)]) * PX[j][c];
-    PY[i][c] = acc;
-  }
+  mm81x8<2>(L, PX, PY, wave, lane);
   __syncthreads();
   if (t >= 64) return;                              // the 8x8 work is one wavefront's
   {
