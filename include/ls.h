@@ -262,6 +262,12 @@ ls_status ls_mlp_get_params(const ls_mlp* mlp, float* params_host);
  * mean((y - t)^2), loss_out the loss.  Outputs may be NULL.  Synchronises. */
 ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float* t_host, int B, float* y_host,
                                   float* grad_host, double* loss_out, void* hip_stream);
+/* The network's inference on host data: x_host [B][250] (float32, rounded to
+ * BF16 as the features are), y_host [B][468] outputs.  The same evaluation the
+ * learned fit makes (ls_stencil_fit_learned): the three layers fused per tile
+ * of rows; it agrees with the forward pass of ls_mlp_forward_backward to FP32
+ * rounding (the order of the sums differs).  Synchronises. */
+ls_status ls_mlp_forward(ls_mlp* mlp, const float* x_host, int B, float* y_host, void* hip_stream);
 /* One Adam step (learning rate lr > 0) with the gradient of the last backward
  * pass; LS_ESTATE before any backward pass (ls_mlp_forward_backward or
  * ls_mlp_train). */

@@ -52,6 +52,7 @@ SIGNATURES = [
     ("ls_mlp_create", _I, [_VP, ctypes.POINTER(_VP)]),
     ("ls_mlp_get_params", _I, [_VP, _VP]),
     ("ls_mlp_forward_backward", _I, [_VP, _VP, _VP, _I, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    ("ls_mlp_forward", _I, [_VP, _VP, _I, _VP, _VP]),
     ("ls_mlp_adam_step", _I, [_VP, _D, _VP]),
     ("ls_mlp_add_samples", _I, [_VP, _VP, _VP, _I, _VP]),
     ("ls_mlp_num_samples", ctypes.c_long, [_VP]),
@@ -231,6 +232,14 @@ class Mlp:
         _check(_lib.ls_mlp_forward_backward(self._h, _fp(x), _fp(t), B, _fp(y), _fp(g), ctypes.byref(loss),
                                             _stream()), "ls_mlp_forward_backward")
         return y, g, loss.value
+
+    def forward(self, x):
+        """y (B, 468) for host x (B, 250): the inference the learned fit runs."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], 468), np.float32)
+        _check(_lib.ls_mlp_forward(self._h, _fp(x), x.shape[0], _fp(y), _stream()), "ls_mlp_forward")
+        return y
 
     def adam_step(self, lr: float):
         _check(_lib.ls_mlp_adam_step(self._h, float(lr), _stream()), "ls_mlp_adam_step")

@@ -406,6 +406,30 @@ ls_status ls_mlp_forward_backward(ls_mlp* mlp, const float* x_host, const float*
   });
 }
 
+ls_status ls_mlp_forward(ls_mlp* mlp, const float* x_host, int B, float* y_host, void* hip_stream) {
+  return guarded([&]() -> ls_status {
+    if (!mlp || !x_host || !y_host || B < 1) return LS_EINVAL;
+    hipStream_t s = as_stream(hip_stream);
+    std::vector<unsigned short> xb((size_t)B * MLP_IP, 0);
+    for (int b = 0; b < B; ++b)
+      for (int f = 0; f < MLP_I; ++f) {
+        unsigned u;
+        std::memcpy(&u, &x_host[(size_t)b * MLP_I + f], 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);            // to bf16, nearest, ties to even
+        xb[(size_t)b * MLP_IP + f] = (unsigned short)(u >> 16);
+      }
+    DevBuf dx;
+    LS_TRY(dx.alloc(xb.size() * 2));
+    LS_HIP(hipMemcpyAsync(dx.p, xb.data(), xb.size() * 2, hipMemcpyHostToDevice, s));
+    LS_TRY(mlp_infer(mlp->st, dx.as<unsigned short>(), B, s));
+    std::vector<float> y((size_t)B * MLP_OP);
+    LS_HIP(hipMemcpyAsync(y.data(), mlp->st.y.p, y.size() * 4, hipMemcpyDeviceToHost, s));
+    LS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b) std::memcpy(y_host + (size_t)b * MLP_O, y.data() + (size_t)b * MLP_OP, MLP_O * 4);
+    return LS_OK;
+  });
+}
+
 ls_status ls_mlp_adam_step(ls_mlp* mlp, double lr, void* hip_stream) {
   return guarded([&]() -> ls_status {
     if (!mlp || !(lr > 0.0) || !std::isfinite(lr)) return LS_EINVAL;

@@ -350,7 +350,7 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
   const int B = std::min(npts, 8192);
   PointFitCtx ctx;
   LS_TRY(pointfit_prepare(ctx, sd, n, k, B, s));
-  DevBuf dpts, gclass, xb, acc, rat, dfail;
+  DevBuf dpts, gclass, xb, acc, rat, dfail, dslot;
   LS_TRY(dpts.alloc((size_t)npts * sizeof(int)));
   LS_HIP(hipMemcpyAsync(dpts.p, pts.data(), (size_t)npts * sizeof(int), hipMemcpyHostToDevice, s));
   LS_TRY(class_gauge(sd, gclass, s));
@@ -358,7 +358,8 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
   LS_TRY(acc.alloc((size_t)B * sizeof(int)));
   LS_TRY(rat.alloc((size_t)B * sizeof(double)));
   LS_TRY(dfail.alloc((size_t)B * sizeof(int)));
-  std::vector<int> accept(B), fail;
+  LS_TRY(dslot.alloc((size_t)B * sizeof(int)));
+  std::vector<int> accept(B), fail, fslot;
   std::vector<double> ratio(B);
   const long N3 = (long)n * n * n;
   sd.have_learned = false;
@@ -371,7 +372,7 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
     hipLaunchKernelGGL(features_kernel, dim3(nbl((long)cnt * MLP_IP, 256)), dim3(256), 0, s, n, m, dp, nullptr,
                        cnt, xb.as<unsigned short>());
     LS_HIP(hipGetLastError());
-    LS_TRY(mlp_forward(st, xb.as<unsigned short>(), cnt, s));
+    LS_TRY(mlp_infer(st, xb.as<unsigned short>(), cnt, s));
     hipLaunchKernelGGL(decode_kernel, dim3(nbl((long)cnt * 243, 256)), dim3(256), 0, s, st.y.as<float>(),
                        gclass.as<C<double>>(), dp, cnt, sd.palpha.as<C<double>>());
     LS_HIP(hipGetLastError());
@@ -384,17 +385,21 @@ ls_status learned_fit(StencilData& sd, MlpState& st, int n, double k, const C<do
     LS_HIP(hipMemcpyAsync(ratio.data(), rat.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
     LS_HIP(hipStreamSynchronize(s));
     fail.clear();
+    fslot.clear();
     for (int q = 0; q < cnt; ++q) {
       sd.learned_accept[pts[p0 + q]] = accept[q] ? 1 : 0;
       sd.learned_ratio[pts[p0 + q]] = ratio[q];
-      if (!accept[q]) fail.push_back(pts[p0 + q]);
+      if (!accept[q]) {
+        fail.push_back(pts[p0 + q]);
+        fslot.push_back(q);
+      }
     }
     nfb += (int)fail.size();
     if (!fail.empty()) {
-      // exact fit for the rejected points: their Grams again, in the order of the list
+      // exact fit for the rejected points from the Grams already in the batch
       LS_HIP(hipMemcpyAsync(dfail.p, fail.data(), fail.size() * sizeof(int), hipMemcpyHostToDevice, s));
-      LS_TRY(pointfit_grams(ctx, m, m0, dfail.as<int>(), (int)fail.size(), s));
-      LS_TRY(pointfit_solve(ctx, sd, dfail.as<int>(), (int)fail.size(), kPointIters, s));
+      LS_HIP(hipMemcpyAsync(dslot.p, fslot.data(), fslot.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      LS_TRY(pointfit_solve(ctx, sd, dfail.as<int>(), (int)fail.size(), kPointIters, s, dslot.as<int>()));
     }
     LS_TRY(pointfit_beta(ctx, sd, dp, cnt, s));
   }

@@ -24,6 +24,8 @@ constexpr double MLP_T_SCALE = 3e-3;  // target normalisation: correction = T_SC
 struct MlpState {
   DevBuf w, m, v, grad;              // FP32 masters, Adam moments, gradient
   DevBuf w1b, w2b, w3b;              // BF16 copies, zero-padded
+  DevBuf w1t, w2t, w3t;              // their transposes [n][k], for inference
+  int wver = 0, tver = -1;           // version of the BF16 copies / of the transposes
   int t = 0;                         // Adam step count
   bool have_grad = false;            // a backward pass has filled grad
   // activations / gradients workspace
@@ -38,6 +40,8 @@ ls_status mlp_init(MlpState& st, const float* params_host, hipStream_t s);
 ls_status mlp_refresh_bf16(MlpState& st, hipStream_t s);
 ls_status mlp_workspace(MlpState& st, int Bm);
 ls_status mlp_forward(MlpState& st, const unsigned short* xb, int Bm, hipStream_t s);
+// inference only: st.y (Bm x 480) from xb, the three layers fused per tile of rows
+ls_status mlp_infer(MlpState& st, const unsigned short* xb, int Bm, hipStream_t s);
 ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, int Bm, double* loss, hipStream_t s);
 ls_status mlp_bias3_grad(MlpState& st, const float* T, int Bm, float* db, hipStream_t s);
 ls_status mlp_adam(MlpState& st, double lr, hipStream_t s);

@@ -10,7 +10,9 @@
 //   (S^-1 Q is invariant under alpha -> alpha X, so the gauge costs nothing).
 //
 // Weights are FP32 masters with BF16 copies; every product runs on
-// v_mfma_f32_16x16x16_bf16 with BF16 operands and FP32 accumulation.  GELU is
+// v_mfma_f32_16x16x16_bf16 with BF16 operands and FP32 accumulation.
+// Training runs the layers as separate products (the backward pass needs the
+// pre-activations); inference fuses the three layers per tile of rows.  GELU is
 // the exact x Phi(x) (device erf).  Loss: mean squared error; optimiser: Adam.
 //
 // The learned fit predicts alpha for every interior point, orthonormalises it,
@@ -233,6 +235,102 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+
+// ---- inference: the three layers fused per tile of rows ------------------------
+// y (rows x 480, FP32) = W3^T GELU(W2^T GELU(W1^T x + b1) + b2) + b3 for FR rows
+// per workgroup: the tile's activations stay in LDS (BF16, as the separate
+// layers round them) and the weights stream from L2 in transposed BF16
+// copies wNt [n][k] (k contiguous, so a lane's four k values of an MFMA B
+// operand are one 8-byte load).  Four waves split the output columns; a
+// hidden layer is 2 x 4 tiles of 16 x 16 per wave, 16 k steps of
+// v_mfma_f32_16x16x16bf16_1k.
+constexpr int FR = 32;                 // rows per workgroup
+constexpr int FLD = MLP_IP + 8;        // LDS row stride (bf16): 528 bytes, spreads the banks
+
+template <bool HIDDEN>
+__device__ __forceinline__ void infer_layer(const unsigned short* __restrict__ hin, unsigned short* __restrict__ hout,
+                                            const unsigned short* __restrict__ wt, const float* __restrict__ bias,
+                                            float* __restrict__ y, int r0, int Bm, int ct0, int ctstep, int nct,
+                                            int lane) {
+  // column tiles ct0, ct0 + ctstep, ... (< nct), four at a time
+  for (int cb = ct0; cb < nct; cb += 4 * ctstep) {
+    v4f acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
+    int nn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) nn[u] = cb + u * ctstep;        // column tile of slot u (may be >= nct)
+#pragma unroll 4
+    for (int k0 = 0; k0 < MLP_IP; k0 += 16) {
+      const int kk = k0 + 4 * (lane >> 4);
+      v4s af[2], bf[4];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const v4s*>(hin + (16 * a + (lane & 15)) * FLD + kk);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        bf[u] = (nn[u] < nct) ? *reinterpret_cast<const v4s*>(wt + (long)(16 * nn[u] + (lane & 15)) * MLP_IP + kk)
+                              : v4s{0, 0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[u], acc[a][u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (nn[u] >= nct) continue;
+        const int n = 16 * nn[u] + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * a + 4 * (lane >> 4) + r;
+          if (HIDDEN) {
+            hout[row * FLD + n] = f2bf(gelu(acc[a][u][r] + bias[n]));
+          } else if (r0 + row < Bm) {
+            y[(long)(r0 + row) * MLP_OP + n] = (n < MLP_O) ? acc[a][u][r] + bias[n] : 0.f;
+          }
+        }
+      }
+  }
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const unsigned short* __restrict__ xb, int Bm,
+                                                        const unsigned short* __restrict__ w1t,
+                                                        const unsigned short* __restrict__ w2t,
+                                                        const unsigned short* __restrict__ w3t,
+                                                        const float* __restrict__ b1, const float* __restrict__ b2,
+                                                        const float* __restrict__ b3, float* __restrict__ y) {
+  __shared__ __attribute__((aligned(16))) unsigned short hs[2][FR * FLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = blockIdx.x * FR;
+  // the tile's inputs, 16 bytes per load; rows past Bm are zero
+  for (int e = tid; e < FR * (MLP_IP / 8); e += 256) {
+    const int r = e / (MLP_IP / 8), c = e % (MLP_IP / 8);
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (r0 + r < Bm) v = *reinterpret_cast<const uint4*>(xb + (long)(r0 + r) * MLP_IP + 8 * c);
+    *reinterpret_cast<uint4*>(&hs[0][r * FLD + 8 * c]) = v;
+  }
+  __syncthreads();
+  // hidden layers: wave w owns column tiles w, w + 4, w + 8, w + 12 (of 16)
+  infer_layer<true>(hs[0], hs[1], w1t, b1, nullptr, r0, Bm, wave, 4, MLP_H / 16, lane);
+  __syncthreads();
+  infer_layer<true>(hs[1], hs[0], w2t, b2, nullptr, r0, Bm, wave, 4, MLP_H / 16, lane);
+  __syncthreads();
+  // output layer: 30 column tiles, wave w owns w, w + 4, ...
+  infer_layer<false>(hs[0], nullptr, w3t, b3, y, r0, Bm, wave, 4, MLP_OP / 16, lane);
+}
+
+// b [C][R] = a [R][C] (BF16)
+__global__ void transpose_bf16_kernel(const unsigned short* __restrict__ a, int R, int C,
+                                      unsigned short* __restrict__ b) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)R * C) return;
+  const int c = (int)(i / R), r = (int)(i % R);
+  b[i] = a[(long)r * C + c];
+}
+
 inline unsigned nbk(long len, int t) { return (unsigned)((len + t - 1) / t); }
 
 }  // namespace
@@ -264,6 +362,32 @@ ls_status mlp_refresh_bf16(MlpState& st, hipStream_t s) {
                      MLP_H, st.w2b.as<unsigned short>(), MLP_H, MLP_H);
   hipLaunchKernelGGL(pad_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s, w + MLP_OFF_W3, MLP_H,
                      MLP_O, st.w3b.as<unsigned short>(), MLP_H, MLP_OP);
+  LS_HIP(hipGetLastError());
+  ++st.wver;                           // the transposed inference copies are stale
+  return LS_OK;
+}
+
+ls_status mlp_infer(MlpState& st, const unsigned short* xb, int Bm, hipStream_t s) {
+  LS_TRY(mlp_workspace(st, Bm));
+  if (st.tver != st.wver) {
+    if (!st.w1t.p) {
+      LS_TRY(st.w1t.alloc((size_t)MLP_H * MLP_IP * 2));
+      LS_TRY(st.w2t.alloc((size_t)MLP_H * MLP_H * 2));
+      LS_TRY(st.w3t.alloc((size_t)MLP_OP * MLP_H * 2));
+    }
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_IP * MLP_H, 256)), dim3(256), 0, s,
+                       st.w1b.as<unsigned short>(), MLP_IP, MLP_H, st.w1t.as<unsigned short>());
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s,
+                       st.w2b.as<unsigned short>(), MLP_H, MLP_H, st.w2t.as<unsigned short>());
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s,
+                       st.w3b.as<unsigned short>(), MLP_H, MLP_OP, st.w3t.as<unsigned short>());
+    LS_HIP(hipGetLastError());
+    st.tver = st.wver;
+  }
+  const float* w = st.w.as<float>();
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(nbk(Bm, FR)), dim3(256), 0, s, xb, Bm, st.w1t.as<unsigned short>(),
+                     st.w2t.as<unsigned short>(), st.w3t.as<unsigned short>(), w + MLP_OFF_B1, w + MLP_OFF_B2,
+                     w + MLP_OFF_B3, st.y.as<float>());
   LS_HIP(hipGetLastError());
   return LS_OK;
 }

@@ -28,8 +28,10 @@ struct PointFitCtx {
 ls_status pointfit_prepare(PointFitCtx& ctx, StencilData& sd, int n, double k, int batch, hipStream_t s);
 // weighted Grams of cnt <= batch interior points (device list) into ctx.Gb
 ls_status pointfit_grams(PointFitCtx& ctx, const C<double>* m, double m0, const int* dpts, int cnt, hipStream_t s);
-// exact stencils of those points into sd.palpha
-ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s);
+// exact stencils of those points into sd.palpha; the Gram of point q is ctx.Gb's
+// entry dslots[q] (device list) when dslots is given, else entry q
+ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s,
+                         const int* dslots = nullptr);
 // beta = B^H alpha of those points into sd.pbeta
 ls_status pointfit_beta(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, hipStream_t s);
 

@@ -222,6 +222,7 @@ constexpr int CB = 9;             // block size of the Cholesky factorisation
 __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restrict__ Gall, int np,
                                                         const C<double>* __restrict__ X0, int iters,
                                                         const int* __restrict__ pts,
+                                                        const int* __restrict__ slots,
                                                         C<double>* __restrict__ alpha_out,
                                                         double* __restrict__ eval_out) {
   // rows of X and Y padded to 9 entries: lanes that walk rows then hit
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   const int p = blockIdx.x;
   if (p >= np) return;                 // uniform over the workgroup
   const int t = threadIdx.x;
-  const C<double>* G = Gall + (long)p * NPK;
+  const C<double>* G = Gall + (long)(slots ? slots[p] : p) * NPK;   // point p's Gram
 
   if (t < R81) red[t] = G[LI(t, t)].re;
   for (int e = t; e < NPK; e += HB) L[e] = G[e];
@@ -617,7 +618,7 @@ ls_status point_fit(StencilData& sd, int n, double k, const C<double>* m, double
                        Hr.as<double>(), Gcls.as<double>(), cnt, Gb.as<double>());
     LS_HIP(hipGetLastError());
     hipLaunchKernelGGL(heev_block_kernel, dim3(cnt), dim3(HB), 0, s, Gb.as<C<double>>(), cnt, X0, iters, dp,
-                       sd.palpha.as<C<double>>(), sd.peval.as<double>());
+                       (const int*)nullptr, sd.palpha.as<C<double>>(), sd.peval.as<double>());
     LS_HIP(hipGetLastError());
     hipLaunchKernelGGL(point_beta_kernel, dim3(nb((long)cnt * 243, 256)), dim3(256), 0, s, Bint.as<C<double>>(), dp,
                        cnt, sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
@@ -673,10 +674,11 @@ ls_status pointfit_grams(PointFitCtx& ctx, const C<double>* m, double m0, const 
 }
 
 // exact per-point stencils for cnt points whose Grams are in ctx.Gb
-ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s) {
+ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, int iters, hipStream_t s,
+                         const int* dslots) {
   const C<double>* X0 = sd.ritz8.as<C<double>>() + 13L * R81 * EBW;
   hipLaunchKernelGGL(heev_block_kernel, dim3(cnt), dim3(HB), 0, s, ctx.Gb.as<C<double>>(), cnt, X0, iters, dpts,
-                     sd.palpha.as<C<double>>(), sd.peval.as<double>());
+                     dslots, sd.palpha.as<C<double>>(), sd.peval.as<double>());
   LS_HIP(hipGetLastError());
   return LS_OK;
 }

@@ -64,6 +64,30 @@ def test_forward_backward_matches_oracle(lib):
         assert err <= 2e-2, (k, err)
 
 
+def test_inference_matches_oracle_and_training_forward(lib):
+    """The fused inference (the learned fit's network evaluation) over a
+    ragged number of rows (1000 = 31 tiles of 32 + 8) against the oracle's
+    forward with BF16 operands and against the training forward pass: both
+    round the same BF16 operands and differ only in the order of the FP32
+    sums (bound 2^-10 of the largest output, the BF16 rounding of one
+    activation)."""
+    from paper_1804_02297_amd.binding import Mlp
+    p = _params(7)
+    flat = Mlp.flat(p)
+    net = Mlp(flat)
+    g = np.random.default_rng(8)
+    B = 1000
+    x = g.standard_normal((B, 250)).astype(np.float32)
+    y = net.forward(x)
+    yt, _, _ = net.forward_backward(x, np.zeros((B, 468), np.float32))
+    yo = omlp.forward_bf16(Mlp.unflat(flat.astype(np.float64)), x.astype(np.float64))
+    scale = np.abs(yo).max()
+    assert np.abs(y - yo).max() <= 2.0 ** -10 * scale
+    assert np.abs(y - yt).max() <= 2.0 ** -10 * scale
+    # the same rows alone give the same outputs (the tiling does not matter)
+    assert np.array_equal(net.forward(x[992:]), y[992:])
+
+
 def test_adam_step_matches_oracle(lib):
     from paper_1804_02297_amd.binding import Mlp
     p = _params(5)
