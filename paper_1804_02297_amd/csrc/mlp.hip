@@ -62,7 +62,10 @@ struct EpiArgs {
 
 // C (M x N) = A (M x K) B (K x N), BF16 operands, FP32 accumulation.
 // A(m, k) = TA ? A[k lda + m] : A[m lda + k];  B(k, n) = TB ? B[n ldb + k] : B[k ldb + n].
-// Workgroup: 4 waves, 64 x 64 output tile, K in steps of 32 through LDS.
+// Workgroup: 4 waves, 64 x 64 output tile, K in steps of 32 through LDS; each
+// operand is read along its contiguous index (consecutive threads, consecutive
+// addresses).  Split K (EPI_STORE only): workgroup z of gridDim.z takes the K
+// range [z Kc, (z + 1) Kc) and writes its partial sums to cf + z M ld.
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const unsigned short* __restrict__ A, int lda,
                                                         const unsigned short* __restrict__ B, int ldb, int M, int N,
@@ -72,18 +75,22 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const unsigned short* __
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int Kc = (K + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int kbeg = (int)blockIdx.z * Kc, kend = min(K, kbeg + Kc);
   v4f acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
     for (int e = tid; e < 64 * 32; e += 256) {
-      const int r = e / 32, c = e % 32;        // r: m or n within the tile, c: k
-      const int m = m0 + r, n = n0 + r, k = k0 + c;
+      // A: m fastest when A is stored k-major (TA), else k fastest; B likewise
+      const int ra = TA ? e % 64 : e / 32, ca = TA ? e / 64 : e % 32;
+      const int rb = TB ? e / 32 : e % 64, cb = TB ? e % 32 : e / 64;
+      const int m = m0 + ra, ka = k0 + ca, n = n0 + rb, kb = k0 + cb;
       unsigned short av = 0, bv = 0;
-      if (m < M && k < K) av = TA ? A[(long)k * lda + m] : A[(long)m * lda + k];
-      if (n < N && k < K) bv = TB ? B[(long)n * ldb + k] : B[(long)k * ldb + n];
-      As[r][c] = av;
-      Bs[r][c] = bv;
+      if (m < M && ka < kend) av = TA ? A[(long)ka * lda + m] : A[(long)m * lda + ka];
+      if (n < N && kb < kend) bv = TB ? B[(long)n * ldb + kb] : B[(long)kb * ldb + n];
+      As[ra][ca] = av;
+      Bs[rb][cb] = bv;
     }
     __syncthreads();
 #pragma unroll
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const unsigned short* __
         const int m = m0 + wm + 16 * a + 4 * (lane >> 4) + r;
         const int n = n0 + wn + 16 * b + (lane & 15);
         if (m >= M || n >= N) continue;
-        const long o = (long)m * ep.ld + n;
+        const long o = (long)m * ep.ld + n + (long)blockIdx.z * M * ep.ld;
         const bool pad = n >= ep.nvalid;
         float v = acc[a][b][r];
         if (EPI == EPI_STORE) {
@@ -138,8 +145,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const unsigned short* __
 
 template <bool TA, bool TB, int EPI>
 ls_status gemm(const unsigned short* A, int lda, const unsigned short* B, int ldb, int M, int N, int K,
-               const EpiArgs& ep, hipStream_t s) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
+               const EpiArgs& ep, hipStream_t s, int splitk = 1) {
+  if (splitk > 1 && EPI != EPI_STORE) return LS_EINVAL;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, splitk);
   hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, ep);
   return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
 }
@@ -215,12 +223,20 @@ static ls_status colsum(const float* A, int lda, const float* B, int ldb, int ro
   return hipGetLastError() == hipSuccess ? LS_OK : LS_EHIP;
 }
 
-// gather a row-major block of FP32 dW (rows x cols, ld) into the flat gradient
-__global__ void gather_grad_kernel(const float* __restrict__ src, int rows, int cols, int ld, float* __restrict__ dst) {
+// gather a row-major block of FP32 dW (rows x cols, ld) into the flat gradient,
+// summing the nsplit split-K partial blocks (each Mfull x ld) in order
+__global__ void gather_grad_kernel(const float* __restrict__ src, int rows, int cols, int ld, int Mfull, int nsplit,
+                                   float* __restrict__ dst) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long)rows * cols) return;
-  dst[i] = src[(i / cols) * ld + i % cols];
+  const long o = (i / cols) * ld + i % cols;
+  float v = 0.f;
+  for (int z = 0; z < nsplit; ++z) v += src[o + (long)z * Mfull * ld];
+  dst[i] = v;
 }
+// split of the batch dimension in the weight-gradient products (K = batch rows):
+// 16-32 output tiles alone leave most of the chip idle
+constexpr int kGradSplit = 8;
 
 __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, long cnt, float lr, float b1, float b2, float eps, float c1,
@@ -245,6 +261,7 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 // hidden layer is 2 x 4 tiles of 16 x 16 per wave, 16 k steps of
 // v_mfma_f32_16x16x16bf16_1k.
 constexpr int FR = 32;                 // rows per workgroup
+constexpr int FRT = FR / 16;           // 16-row tiles per workgroup
 constexpr int FLD = MLP_IP + 8;        // LDS row stride (bf16): 528 bytes, spreads the banks
 
 template <bool HIDDEN>
@@ -254,31 +271,39 @@ __device__ __forceinline__ void infer_layer(const unsigned short* __restrict__ h
                                             int lane) {
   // column tiles ct0, ct0 + ctstep, ... (< nct), four at a time
   for (int cb = ct0; cb < nct; cb += 4 * ctstep) {
-    v4f acc[2][4];
+    v4f acc[FRT][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FRT; ++a)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
     int nn[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) nn[u] = cb + u * ctstep;        // column tile of slot u (may be >= nct)
-#pragma unroll 4
-    for (int k0 = 0; k0 < MLP_IP; k0 += 16) {
-      const int kk = k0 + 4 * (lane >> 4);
-      v4s af[2], bf[4];
+    // every weight fragment of the four column tiles over the whole K is
+    // loaded before the first product (128 VGPRs): one L2 latency per layer
+    // instead of one per k step
+    v4s bw[4][MLP_IP / 16];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const v4s*>(hin + (16 * a + (lane & 15)) * FLD + kk);
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        bf[u] = (nn[u] < nct) ? *reinterpret_cast<const v4s*>(wt + (long)(16 * nn[u] + (lane & 15)) * MLP_IP + kk)
-                              : v4s{0, 0, 0, 0};
+      for (int ks = 0; ks < MLP_IP / 16; ++ks)
+        bw[u][ks] = (nn[u] < nct) ? *reinterpret_cast<const v4s*>(wt + (long)(16 * nn[u] + (lane & 15)) * MLP_IP +
+                                                                   16 * ks + 4 * (lane >> 4))
+                                  : v4s{0, 0, 0, 0};
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+    for (int ks = 0; ks < MLP_IP / 16; ++ks) {
+      const int kk = 16 * ks + 4 * (lane >> 4);
+      v4s af[FRT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bf[u], acc[a][u], 0, 0, 0);
+      for (int a = 0; a < FRT; ++a) af[a] = *reinterpret_cast<const v4s*>(hin + (16 * a + (lane & 15)) * FLD + kk);
+#pragma unroll
+      for (int a = 0; a < FRT; ++a)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bw[u][ks], acc[a][u], 0, 0, 0);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FRT; ++a)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (nn[u] >= nct) continue;
@@ -404,7 +429,7 @@ ls_status mlp_workspace(MlpState& st, int Bm) {
   LS_TRY(st.dz2b.alloc((size_t)Bm * MLP_H * 2));
   LS_TRY(st.dz1.alloc((size_t)Bm * MLP_H * 4));
   LS_TRY(st.dz1b.alloc((size_t)Bm * MLP_H * 2));
-  LS_TRY(st.dw.alloc((size_t)MLP_H * MLP_OP * 4));
+  LS_TRY(st.dw.alloc((size_t)kGradSplit * MLP_IP * MLP_OP * 4));
   LS_TRY(st.sq.alloc(256 * 4));
   LS_TRY(st.part.alloc((size_t)kColChunks * MLP_OP * 4));
   st.ws_rows = Bm;
@@ -437,9 +462,9 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
   // layer 3: dW3 = h2^T dY (256 x 468), db3, dh2 = dY W3^T -> dZ2
   EpiArgs es{nullptr, nullptr, nullptr, nullptr, st.dw.as<float>(), MLP_OP, MLP_O};
   LS_TRY((gemm<true, false, EPI_STORE>(st.h2b.as<unsigned short>(), MLP_H, st.dyb.as<unsigned short>(), MLP_OP, MLP_H,
-                                       MLP_OP, Bm, es, s)));
+                                       MLP_OP, Bm, es, s, kGradSplit)));
   hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_H * MLP_O, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_H,
-                     MLP_O, MLP_OP, g + MLP_OFF_W3);
+                     MLP_O, MLP_OP, MLP_H, kGradSplit, g + MLP_OFF_W3);
   // db3 from dY: reuse dz2 (f32) as scratch is not possible (bf16 dY); recompute from Y - T
   EpiArgs ed2{nullptr, st.dz2.as<float>(), st.z2.as<float>(), st.dz2b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
   LS_TRY((gemm<false, true, EPI_DACT>(st.dyb.as<unsigned short>(), MLP_OP, st.w3b.as<unsigned short>(), MLP_OP, Bm,
@@ -449,18 +474,19 @@ ls_status mlp_backward(MlpState& st, const unsigned short* xb, const float* T, i
   es.ld = MLP_H;
   es.nvalid = MLP_H;
   LS_TRY((gemm<true, false, EPI_STORE>(st.h1b.as<unsigned short>(), MLP_H, st.dz2b.as<unsigned short>(), MLP_H, MLP_H,
-                                       MLP_H, Bm, es, s)));
+                                       MLP_H, Bm, es, s, kGradSplit)));
   hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_H,
-                     MLP_H, MLP_H, g + MLP_OFF_W2);
+                     MLP_H, MLP_H, MLP_H, kGradSplit, g + MLP_OFF_W2);
   LS_TRY(colsum(st.dz2.as<float>(), MLP_H, nullptr, 0, Bm, MLP_H, 1.0f, st.part.as<float>(), g + MLP_OFF_B2, s));
   EpiArgs ed1{nullptr, st.dz1.as<float>(), st.z1.as<float>(), st.dz1b.as<unsigned short>(), nullptr, MLP_H, MLP_H};
   LS_TRY((gemm<false, true, EPI_DACT>(st.dz2b.as<unsigned short>(), MLP_H, st.w2b.as<unsigned short>(), MLP_H, Bm,
                                       MLP_H, MLP_H, ed1, s)));
   // layer 1
   es.cf = st.dw.as<float>();
-  LS_TRY((gemm<true, false, EPI_STORE>(xb, MLP_IP, st.dz1b.as<unsigned short>(), MLP_H, MLP_IP, MLP_H, Bm, es, s)));
+  LS_TRY((gemm<true, false, EPI_STORE>(xb, MLP_IP, st.dz1b.as<unsigned short>(), MLP_H, MLP_IP, MLP_H, Bm, es, s,
+                                       kGradSplit)));
   hipLaunchKernelGGL(gather_grad_kernel, dim3(nbk((long)MLP_I * MLP_H, 256)), dim3(256), 0, s, st.dw.as<float>(), MLP_I,
-                     MLP_H, MLP_H, g + MLP_OFF_W1);
+                     MLP_H, MLP_H, MLP_IP, kGradSplit, g + MLP_OFF_W1);
   LS_TRY(colsum(st.dz1.as<float>(), MLP_H, nullptr, 0, Bm, MLP_H, 1.0f, st.part.as<float>(), g + MLP_OFF_B1, s));
   LS_HIP(hipGetLastError());
   // db3 = column sums of dY in FP32: dY = 2 (Y - T) / (B 468)

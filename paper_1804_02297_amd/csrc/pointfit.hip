@@ -148,6 +148,44 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// accb[r][j] = sum_{j <= k < i0} Lp[LI(i0 + r, k)] Lp[LI(k, j)] for r < rows and
+// j < i0 (i0 a multiple of 8): the block rows i0.. of the Cholesky factor times
+// the finished rows of W = L^-1 (Lp rows < i0 already hold W), on FP64 MFMA
+// in realified form as in mm81x8 below.  A 16-row band (rows >= `rows` zero)
+// times 8-column groups of W, the groups shared round-robin by the four
+// waves; group g starts at k = 8 g, where W's lower-triangular columns start.
+__device__ __forceinline__ void band_times_w(const C<double>* __restrict__ Lp, int i0, int rows,
+                                             C<double>* __restrict__ accb, int wave, int lane) {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  const int col = lane & 15, c8 = col & 7, kl = lane >> 4, rr = lane & 15;
+  for (int g = wave; 8 * g < i0; g += 4) {
+    const int j = 8 * g + c8;
+    v4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k4 = 8 * g; k4 < i0; k4 += 4) {
+      const int k = k4 + kl;
+      C<double> a = cmk(0.0, 0.0), w = cmk(0.0, 0.0);
+      if (k < i0) {
+        if (rr < rows) a = Lp[LI(i0 + rr, k)];
+        if (j <= k) w = Lp[LI(k, j)];
+      }
+      const double b1 = (col < EBW) ? w.re : w.im;
+      const double b2 = (col < EBW) ? -w.im : w.re;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b2, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * r + kl;
+      if (row < rows) {
+        if (col < EBW)
+          accb[row * R81 + j].re = acc[r];
+        else
+          accb[row * R81 + j].im = acc[r];
+      }
+    }
+  }
+}
+
 // Y = op(A) X for the 81 x 8 complex blocks X, Y in LDS (rows padded to EBW + 1)
 // and A given by its packed lower triangle Lp: OP 0 A = Lp (lower triangular),
 // 1 A = Lp^H (upper triangular), 2 A = the Hermitian matrix with lower
@@ -208,10 +246,11 @@ __device__ __forceinline__ void mm81x8(const C<double>* __restrict__ Lp, const C
 // [np][3321] complex; X0: [81][8] warm start (class Ritz vectors).  Writes
 // alpha [pts[p]][81][3] and the three smallest Ritz values:
 //   1. Cholesky G + shift I = L L^H in 9 x 9 blocks, packed in LDS;
-//   2. W = L^-1 in place, eight rows per step;
+//   2. W = L^-1 in place, eight rows per step (the products with the
+//      finished rows on FP64 MFMA);
 //   3. `iters` block inverse iterations X <- W^H (W X) (products on FP64
-//      MFMA), each followed by a Cholesky QR of the 8 columns (twice after
-//      the last);
+//      MFMA), every second one followed by a Cholesky QR of the 8 columns
+//      (twice after the last);
 //   4. Rayleigh-Ritz with the unshifted G and an 8x8 parallel cyclic Jacobi
 //      (wavefront 0).
 // The products of step 3 have no sequential dependency, so all four SIMDs of
@@ -297,20 +336,16 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
     __syncthreads();
   }
 
-  // 2. W = L^-1 in place, rows [i0, i1) per step: (a) every thread forms
-  // partial sums acc[r][j] = sum_{j <= k < i0} L[i0+r][k] W[k][j] over the
-  // finished rows of W; (b) thread j runs the block rows in order; (c) the
-  // block rows of W replace those of L.  X holds acc, Y the new rows.
+  // 2. W = L^-1 in place, rows [i0, i1) per step: (a) the partial sums
+  // acc[r][j] = sum_{j <= k < i0} L[i0+r][k] W[k][j] over the finished rows
+  // of W (MFMA); (b) thread j runs the block rows in order; (c) the block
+  // rows of W replace those of L.  X holds acc, Y the new rows.
+  const int wave = t >> 6, lane = t & 63;
   C<double>* accb = &X[0][0];                       // RBW x 81
   C<double>* tmp = &Y[0][0];                        // RBW x 81
   for (int i0 = 0; i0 < R81; i0 += RBW) {
     const int i1 = min(R81, i0 + RBW);
-    for (int e = t; e < (i1 - i0) * R81; e += HB) {
-      const int r = e / R81, j = e % R81;
-      C<double> acc = cmk(0.0, 0.0);
-      for (int k = j; k < i0; ++k) acc = acc + L[LI(i0 + r, k)] * L[LI(k, j)];
-      accb[e] = acc;
-    }
+    band_times_w(L, i0, i1 - i0, accb, wave, lane);
     __syncthreads();
     if (t < i1) {
       const int j = t;
@@ -343,26 +378,27 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
     __syncthreads();
   }
 
-  // 3. block inverse iteration with (G + shift)^-1 = W^H W; after each step
-  // the block is orthonormalised by Cholesky QR: the 8 x 8 Gram from four
-  // partial sums, its Cholesky factor R and R^-1 on wavefront 0, then
-  // X R^-1 into the other buffer.  One step scales the columns by at most
-  // lambda_8 / lambda_1 (about 1e2 on these Grams), so a single Cholesky QR
-  // keeps them orthonormal to about 1e-12 between steps; the last step
-  // orthonormalises twice for the Rayleigh-Ritz.
+  // 3. block inverse iteration with (G + shift)^-1 = W^H W; after every
+  // second step the block is orthonormalised by Cholesky QR: the 8 x 8 Gram
+  // from four partial sums, its Cholesky factor R and R^-1 on wavefront 0,
+  // then X R^-1 into the other buffer.  Two steps scale the columns apart by
+  // at most (lambda_8 / lambda_1)^2, about 1e4 on these Grams, so the
+  // Cholesky of their Gram (condition 1e8) is safe and leaves them
+  // orthonormal to about 1e-8, which the next steps do not need better (the
+  // span is what they refine); the last step orthonormalises twice for the
+  // Rayleigh-Ritz.
   C<double>(*PX)[EBW + 1] = X;
   C<double>(*PY)[EBW + 1] = Y;
   for (int e = t; e < R81 * EBW; e += HB) PX[e / EBW][e % EBW] = X0[e];
   __syncthreads();
   const int c = t & (EBW - 1), rg = t / EBW;      // column, row group (32 groups)
   const int l = t;                                 // lane index inside wavefront 0
-  const int wave = t >> 6, lane = t & 63;
   for (int it = 0; it < iters; ++it) {
     mm81x8<0>(L, PX, PY, wave, lane);              // Y = W X
     __syncthreads();
     mm81x8<1>(L, PY, PX, wave, lane);              // X = W^H Y
     __syncthreads();
-    const int npass = (it + 1 == iters) ? 2 : 1;
+    const int npass = (it + 1 == iters) ? 2 : (it & 1);
     for (int pass = 0; pass < npass; ++pass) {
       {
         const int pq = t & 63, part = t >> 6, pp = pq >> 3, qq = pq & 7;
