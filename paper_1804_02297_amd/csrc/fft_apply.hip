@@ -317,6 +317,7 @@ ls_status apply_plan_set_form(ApplyPlan& ap, int form, hipStream_t s) {
 std::vector<int> kmul_team_choices(const ApplyPlan& ap) {
   const Fac f = col_factors(ap.P);
   if (4 * cmax(f.n1, f.n2) == 64) return {1, 2, 4};
+  if (job_lanes(cmax(f.n1, f.n2)) == 32) return {1, 2};
   return {1};
 }
 

@@ -44,6 +44,8 @@ constexpr Fac row_factors(int P) {
   return col_factors(P);
 }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// lanes per job of pass 3 (see kmul_kernel)
+constexpr int job_lanes(int tpl) { return (tpl > 16 && tpl <= 32) ? 32 : tpl; }
 // Lines per workgroup of the strided passes: a LS_COL_RUN_BYTES run per row
 // (one or two 128-byte cache lines), LDS <= 64 KB.
 #ifndef LS_COL_RUN_BYTES
@@ -172,12 +174,16 @@ __global__ __launch_bounds__(T * cmax(N1, N2)) void col_fft_kernel(
 // X: [B][3][P][P][n] (q1, q2, i3).  Kh: octant [H][H][6][H], components
 // (xx, yy, zz, xy, xz, yz), already divided by P^3.
 //
-// A team is 4 jobs x TPL threads: the up-to-four lines (+-f1, +-f2) of one
-// right-hand side.  A workgroup holds W teams that share one octant line of
-// Khat in LDS and take right-hand sides b = team, team + W, ...  When a team
-// is exactly one wavefront its exchanges need only wavefront-level ordering
-// (LDS operations of one wave complete in order), so teams never wait for
-// each other; otherwise W = 1 and the exchange uses a workgroup barrier.
+// A team is 4 jobs x JL threads: the up-to-four lines (+-f1, +-f2) of one
+// right-hand side, JL = TPL (the larger factor of P) or, for 16 < TPL <= 32,
+// 32 so that a job is half a wavefront (TPL = 24 at P = 384: 8 idle lanes per
+// job, as the 96-lane team already had in its second wave).  A workgroup
+// holds W teams that share one octant line of Khat in LDS and take
+// right-hand sides b = team, team + W, ...  When no job straddles two
+// wavefronts (JL = 16 or 32) its exchanges need only wavefront-level
+// ordering (LDS operations of one wave complete in order), so jobs never
+// wait for each other; otherwise W = 1 and the exchange uses a workgroup
+// barrier.
 // The three components of a line stay in registers from the forward
 // transform through the 3x3 multiply into the inverse transform; the LDS
 // exchange buffer holds one component at a time.
@@ -187,15 +193,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <typename R, int P, int N1, int N2, int W, bool PERSIST = false>
-__global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __restrict__ X,
-                                                                    const C<R>* __restrict__ Kh,
-                                                                    const C<R>* __restrict__ tw,
-                                                                    int n, int B) {
+__global__ __launch_bounds__(W * 4 * job_lanes(cmax(N1, N2))) void kmul_kernel(C<R>* __restrict__ X,
+                                                                               const C<R>* __restrict__ Kh,
+                                                                               const C<R>* __restrict__ tw,
+                                                                               int n, int B) {
   constexpr int H = P / 2 + 1;
-  constexpr int TPL = cmax(N1, N2);
-  constexpr int TEAM = 4 * TPL;
-  constexpr bool WAVE_TEAM = (TEAM == 64);
-  static_assert(WAVE_TEAM || W == 1, "multi-team workgroups need one-wave teams");
+  constexpr int JL = job_lanes(cmax(N1, N2));
+  constexpr int TEAM = 4 * JL;
+  constexpr bool WAVE_TEAM = (JL == 16 || JL == 32);   // no job straddles two waves
+  static_assert(WAVE_TEAM || W == 1, "multi-team workgroups need jobs inside wavefronts");
   constexpr int EXS = N1 * N2 + N2;          // padded exchange stride of one job
   // Frequencies q3 = j + N2 a: with N1 even, a < N1/2 gives q3 < P/2 and
   // a >= N1/2 gives q3 >= P/2 (mirrored, f3 = P - q3), both known at compile
@@ -222,8 +228,8 @@ __global__ __launch_bounds__(W * 4 * cmax(N1, N2)) void kmul_kernel(C<R>* __rest
     const int f2 = oline % H;
     const int team = tid / TEAM;
     const int lt = tid % TEAM;
-    const int job = lt / TPL;
-    const int j = lt % TPL;
+    const int job = lt / JL;
+    const int j = lt % JL;                      // lanes j >= max(N1, N2) stay idle
     const int s1 = job & 1, s2 = job >> 1;
     const bool edge1 = (f1 == 0) || (2 * f1 == P);
     const bool edge2 = (f2 == 0) || (2 * f2 == P);
@@ -785,7 +791,7 @@ template <typename R, int P, int W>
 static ls_status launch_kmul_w(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int B, bool persist, hipStream_t s) {
   constexpr Fac f = row_factors<R>(P);
   constexpr int H = P / 2 + 1;
-  constexpr int threads = W * 4 * cmax(f.n1, f.n2);
+  constexpr int threads = W * 4 * job_lanes(cmax(f.n1, f.n2));
   const auto kern = persist ? kmul_kernel<R, P, f.n1, f.n2, W, true> : kmul_kernel<R, P, f.n1, f.n2, W, false>;
   long grid = (long)H * H;
   if (persist) {
@@ -826,6 +832,8 @@ static ls_status launch_kmul(C<R>* X, const C<R>* Kh, const C<R>* tw, int n, int
   if (wt <= 0) wt = 2;
   if constexpr (4 * TPL == 64) {
     if (wt >= 4 && B >= 4) return launch_kmul_w<R, P, 4>(X, Kh, tw, n, B, persist, s);
+    if (wt >= 2 && B >= 2) return launch_kmul_w<R, P, 2>(X, Kh, tw, n, B, persist, s);
+  } else if constexpr (job_lanes(TPL) == 32) {
     if (wt >= 2 && B >= 2) return launch_kmul_w<R, P, 2>(X, Kh, tw, n, B, persist, s);
   }
   return launch_kmul_w<R, P, 1>(X, Kh, tw, n, B, persist, s);

@@ -56,6 +56,23 @@ def test_launch_choices_bitwise_identical_p256(lib, prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_launch_choices_bitwise_identical_p384(lib, prec):
+    """P = 384: pass 3 with 32-lane jobs (24 active), one or two teams per
+    workgroup, ordinary and persistent grids; and the FP32 apply against the
+    oracle on a sample of outputs."""
+    n, B = 150, 2
+    plan = _plan(n, B)
+    assert plan.P == 384
+    dt = torch.complex64 if prec == "c64" else torch.complex128
+    x = torch.from_numpy(I.random_field(B, n, 14)).to("cuda:0").to(dt)
+    ref = plan.apply(x, prec=prec)
+    for choice in [(2, 2, 0, 0), (1, 1, 0, 0), (2, 1, 0, 1), (2, 2, 15, 1)]:
+        plan.set_tune(prec, *choice)
+        assert torch.equal(plan.apply(x, prec=prec), ref), choice
+    plan.close()
+
+
 def test_set_tune_rejects_bad_choices(lib):
     from paper_1804_02297_amd.binding import LSError
     plan = _plan(8, 2)
