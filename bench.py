@@ -35,8 +35,8 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # copy calibration (read = 2.0 x FETCH_SIZE, write = 1.0 x WRITE_SIZE), valid
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
-    "sources": ["fft_apply.hip", "common.h", "cplx.h"],
-    "sha256": "2f7392698e6d3eeda75e3dd64abb58c99332f224b38250fb53935431ea5befdf",
+    "sources": ["fft_kernels.h", "fft_apply.hip", "fft_inst_e.hip", "common.h", "cplx.h"],
+    "sha256": "98e53b841432528a4afc22cb26df2ea4344194647a2e6af15cf8675ba0a8c751",
     "workload": (128, 8, "c64"),
     "bytes": 3.3265e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "06de3420c07089ed52ee638ee268f869f9d3fda8d7bad603f63bf9fb552819b6",
+    "sha256": "14ec4bfa9eaffe6b0dda5226fcc85efd9b32c7be983c60a814b21ea2f7acea6b",
     "workload": (959, 8, "c64"),
-    "bytes": 1.3758e9,
+    "bytes": 1.3066e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 

@@ -14,8 +14,9 @@
 //     holds at once, which stride over the work items.
 // The first two are searched jointly, then each pass's run length is halved
 // in turn and kept where it is faster, then the persistent launch is tried on
-// the result.  Each candidate runs once to warm up, then 3 times between HIP
-// events.
+// the result.  The device is first warmed up by three applies; each
+// candidate then runs once to warm up and 10 times between HIP events (3
+// timed runs left the choice to noise of about 2 %).
 //
 // Cache: a JSON array, one object per line,
 //   {"key": "<arch>|cu=<CUs>|v=2|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>",
@@ -109,7 +110,7 @@ bool write_cache(const std::string& path, const std::vector<Entry>& es) {
 // average ms of one batched apply under the plan's current choice
 ls_status time_apply(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
                      hipEvent_t e0, hipEvent_t e1, double* ms) {
-  constexpr int kReps = 3;
+  constexpr int kReps = 10;
   LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
   LS_HIP(hipEventRecord(e0, s));
   for (int r = 0; r < kReps; ++r) LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
@@ -165,8 +166,15 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
   ls_status st = LS_OK;
   double best = 1e300;
   ApplyTune pick = saved;
-  // the default choice first, for reference
+  // the default choice first, for reference, after warming the device up
   ap.tune[prec] = ApplyTune{};
+  for (int r = 0; r < 3 && st == LS_OK; ++r) st = apply_batched(ap, x.p, y.p, nrhs, prec, s);
+  if (st != LS_OK) {
+    ap.tune[prec] = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+  }
   st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &res.ms_default_per_rhs);
   res.ms_default_per_rhs /= nrhs;
   auto trial = [&](const ApplyTune& t) {

@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--dim", type=int, default=3, choices=(2, 3))
+    ap.add_argument("--tune", action="store_true", help="use the autotuner's launch choice (as bench.py does)")
+    ap.add_argument("--choice", default="", help="launch choice chunk,kmul_w,half_runs,persist (3-D)")
     args = ap.parse_args()
     import torch
 
@@ -45,6 +47,10 @@ def main():
         plan = binding.Plan2(n, I.paper_wavenumber(n), m, max_rhs=B)
         x = torch.randn((B, 2, n, n), dtype=dt, device=dev, generator=g)
     y = torch.empty_like(x)
+    if args.tune and args.dim == 3:
+        print("profile_apply tuned:", plan.tune(B, args.prec), flush=True)
+    if args.choice and args.dim == 3:
+        plan.set_tune(args.prec, *[int(v) for v in args.choice.split(",")])
     for _ in range(args.reps):
         plan.apply(x, y, prec=args.prec)
     torch.cuda.synchronize()
