@@ -175,22 +175,26 @@ __global__ __launch_bounds__(64) void locality_kernel(const C<double>* __restric
       for (int i = l; i < R81; i += 64) Q[i][c] = cscale(Q[i][c], sc);
       wsync_l();
     }
-  // traces tr(X^H G X) for X = Q and X = A (the class stencil, orthonormal)
+  // traces tr(X^H G X) for X = Q and X = A (the class stencil, orthonormal),
+  // walking the packed lower triangle of G in order (lane l takes entries
+  // l, l + 64, ..., so every load of the wave is one contiguous kilobyte):
+  // the entry (i, j), j < i, and its mirror (j, i) = conj(G_ij) contribute
+  // 2 Re(sum_v conj(X_iv) G_ij X_jv), the diagonal once
   double tq = 0.0, ta = 0.0;
-  for (int i = l; i < R81; i += 64) {
-    C<double> gq[3] = {cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0)};
-    C<double> ga[3] = {cmk(0.0, 0.0), cmk(0.0, 0.0), cmk(0.0, 0.0)};
-    for (int j = 0; j < R81; ++j) {
-      const C<double> g = (j <= i) ? G[i * (i + 1) / 2 + j] : cconj(G[j * (j + 1) / 2 + i]);
-      for (int v = 0; v < 3; ++v) {
-        gq[v] = gq[v] + g * Q[j][v];
-        ga[v] = ga[v] + g * A[j][v];
-      }
-    }
+  int i = 0;
+  for (int e = l; e < 3321; e += 64) {
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;           // row of entry e (advances monotonically)
+    const int j = e - i * (i + 1) / 2;
+    const C<double> g = G[e];
+    const double w = (j < i) ? 2.0 : 1.0;
+    double sq = 0.0, sa = 0.0;
+#pragma unroll
     for (int v = 0; v < 3; ++v) {
-      tq += (cconj(Q[i][v]) * gq[v]).re;
-      ta += (cconj(A[i][v]) * ga[v]).re;
+      sq += (cconj(Q[i][v]) * (g * Q[j][v])).re;
+      sa += (cconj(A[i][v]) * (g * A[j][v])).re;
     }
+    tq += w * sq;
+    ta += w * sa;
   }
   for (int o = 32; o > 0; o >>= 1) {
     tq += __shfl_xor(tq, o);

@@ -551,17 +551,34 @@ __global__ __launch_bounds__(HB) void heev_block_kernel(const C<double>* __restr
   if (eval_out && l < 3) eval_out[pt * 3 + l] = T[idx[l]][idx[l]].re;
 }
 
-// beta_p = B^H alpha_p for the listed points; B: interior local block (81 x 81, row-major)
-__global__ void point_beta_kernel(const C<double>* __restrict__ B, const int* __restrict__ pts, int np,
-                                  const C<double>* __restrict__ alpha, C<double>* __restrict__ beta) {
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= (long)np * 243) return;
-  const long pt = pts[id / 243];
-  const int e = (int)(id % 243), row = e / 3, v = e % 3;
-  const C<double>* al = alpha + pt * 243;
-  C<double> s = cmk(0.0, 0.0);
-  for (int a = 0; a < R81; ++a) s = s + cconj(B[a * R81 + row]) * al[a * 3 + v];
-  beta[pt * 243 + e] = s;
+// beta_p = B^H alpha_p for the listed points; B: interior local block (81 x 81,
+// row-major).  A workgroup takes BPTS points: their alpha in LDS, thread e <
+// 243 forms entry e = (row, v) of all of them, so each B entry is loaded once
+// per BPTS points (one thread per entry and point re-read B and alpha 81 times
+// each from the caches).
+constexpr int BPTS = 8;
+__global__ __launch_bounds__(256) void point_beta_kernel(const C<double>* __restrict__ B,
+                                                         const int* __restrict__ pts, int np,
+                                                         const C<double>* __restrict__ alpha,
+                                                         C<double>* __restrict__ beta) {
+  __shared__ C<double> al[BPTS][243];
+  const int p0 = blockIdx.x * BPTS, t = threadIdx.x;
+  const int npb = min(BPTS, np - p0);
+  for (int e = t; e < npb * 243; e += 256) al[e / 243][e % 243] = alpha[(long)pts[p0 + e / 243] * 243 + e % 243];
+  __syncthreads();
+  if (t >= 243) return;
+  const int row = t / 3, v = t % 3;
+  C<double> acc[BPTS];
+#pragma unroll
+  for (int q = 0; q < BPTS; ++q) acc[q] = cmk(0.0, 0.0);
+  for (int a = 0; a < R81; ++a) {
+    const C<double> b = cconj(B[a * R81 + row]);
+#pragma unroll
+    for (int q = 0; q < BPTS; ++q) acc[q] = acc[q] + b * al[q][a * 3 + v];
+  }
+#pragma unroll
+  for (int q = 0; q < BPTS; ++q)
+    if (q < npb) beta[(long)pts[p0 + q] * 243 + t] = acc[q];
 }
 
 __global__ void interior_block_kernel(double k, double h, C<double>* __restrict__ B) {
@@ -656,8 +673,8 @@ ls_status point_fit(StencilData& sd, int n, double k, const C<double>* m, double
     hipLaunchKernelGGL(heev_block_kernel, dim3(cnt), dim3(HB), 0, s, Gb.as<C<double>>(), cnt, X0, iters, dp,
                        (const int*)nullptr, sd.palpha.as<C<double>>(), sd.peval.as<double>());
     LS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(point_beta_kernel, dim3(nb((long)cnt * 243, 256)), dim3(256), 0, s, Bint.as<C<double>>(), dp,
-                       cnt, sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
+    hipLaunchKernelGGL(point_beta_kernel, dim3(nb(cnt, BPTS)), dim3(256), 0, s, Bint.as<C<double>>(), dp, cnt,
+                       sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
     LS_HIP(hipGetLastError());
   }
   LS_HIP(hipStreamSynchronize(s));
@@ -720,8 +737,8 @@ ls_status pointfit_solve(PointFitCtx& ctx, StencilData& sd, const int* dpts, int
 }
 
 ls_status pointfit_beta(PointFitCtx& ctx, StencilData& sd, const int* dpts, int cnt, hipStream_t s) {
-  hipLaunchKernelGGL(point_beta_kernel, dim3(nb((long)cnt * 243, 256)), dim3(256), 0, s, ctx.Bint.as<C<double>>(),
-                     dpts, cnt, sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
+  hipLaunchKernelGGL(point_beta_kernel, dim3(nb(cnt, BPTS)), dim3(256), 0, s, ctx.Bint.as<C<double>>(), dpts, cnt,
+                     sd.palpha.as<C<double>>(), sd.pbeta.as<C<double>>());
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
