@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_kernels.h", "fft_apply.hip", "fft_inst_e.hip", "common.h", "cplx.h"],
-    "sha256": "98e53b841432528a4afc22cb26df2ea4344194647a2e6af15cf8675ba0a8c751",
+    "sha256": "84fc46bda5308d8f2f1389a349fe68168d80fca23bdc41957bae3c472b91948e",
     "workload": (128, 8, "c64"),
     "bytes": 3.3265e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",

@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <map>
 #include <mutex>
 #include <utility>
 
@@ -724,22 +723,30 @@ __global__ __launch_bounds__(4 * cmax(N1, N2)) void kmul34_kernel(C<R>* __restri
 // ---- launch helpers -----------------------------------------------------------
 // Workgroups of `kern` (with `threads` threads) that the current device holds at
 // once: the grid of a persistent launch.  Occupancy is queried once per kernel
-// and device.
+// and device and kept in a fixed table (no allocation, so that the apply that
+// allocates nothing can use persistent launches too); a full table just
+// queries again.
 inline long resident_workgroups(const void* kern, int threads) {
+  struct Slot {
+    const void* kern;
+    int dev;
+    long value;
+  };
+  static constexpr int kSlots = 256;
+  static Slot table[kSlots];
+  static int used = 0;
   static std::mutex mu;
-  static std::map<std::pair<const void*, int>, long> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_pair(kern, dev);
-  const auto it = cache.find(key);
-  if (it != cache.end()) return it->second;
+  for (int i = 0; i < used; ++i)
+    if (table[i].kern == kern && table[i].dev == dev) return table[i].value;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   const long r = (long)std::max(per_cu, 1) * std::max(cus, 1);
-  cache[key] = r;
+  if (used < kSlots) table[used++] = Slot{kern, dev, r};
   return r;
 }
 

@@ -65,6 +65,23 @@ def test_noalloc_apply_chunks_beyond_one_scratch_load(lib):
     plan.close()
 
 
+def test_noalloc_apply_under_other_launch_choices(lib):
+    """The no-allocation apply runs the plan's launch choice (teams, row runs,
+    persistent grids) on the fixed array: still equal to ls_apply bit for bit,
+    and equal across the choices."""
+    n, nrhs = 40, 3
+    plan = _plan(n, nrhs)
+    x = torch.from_numpy(I.random_field(nrhs, n, 4)).to("cuda:0").to(torch.complex64)
+    ref = plan.apply(x, prec="c64")
+    for choice in [(2, 4, 15, 1), (3, 1, 6, 0), (1, 2, 0, 1)]:
+        plan.set_tune("c64", *choice)
+        y = torch.full_like(x, float("nan"))
+        plan.apply_noalloc(x, y, prec="c64")
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), choice
+    plan.close()
+
+
 def test_noalloc_apply_refuses_a_rhs_beyond_the_array(lib):
     from paper_1804_02297_amd.binding import LSError
     n = 96
