@@ -59,8 +59,8 @@ def test_launch_choices_bitwise_identical_p256(lib, prec):
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_launch_choices_bitwise_identical_p384(lib, prec):
     """P = 384: pass 3 with 32-lane jobs (24 active), one or two teams per
-    workgroup, ordinary and persistent grids; and the FP32 apply against the
-    oracle on a sample of outputs."""
+    workgroup, ordinary and persistent grids (the default choice's outputs
+    are checked against the oracle at P = 384 in test_gpu_apply.py)."""
     n, B = 150, 2
     plan = _plan(n, B)
     assert plan.P == 384
