@@ -24,8 +24,8 @@ constexpr double MLP_T_SCALE = 3e-3;  // target normalisation: correction = T_SC
 struct MlpState {
   DevBuf w, m, v, grad;              // FP32 masters, Adam moments, gradient
   DevBuf w1b, w2b, w3b;              // BF16 copies, zero-padded
-  DevBuf w1t, w2t, w3t;              // their transposes [n][k], for inference
-  int wver = 0, tver = -1;           // version of the BF16 copies / of the transposes
+  DevBuf w1f, w2f, w3f;              // the same in MFMA fragment order, for inference
+  int wver = 0, fver = -1;           // version of the BF16 copies / of the fragment-ordered ones
   int t = 0;                         // Adam step count
   bool have_grad = false;            // a backward pass has filled grad
   // activations / gradients workspace

@@ -9,11 +9,12 @@
 //   alpha~ = alpha (alpha_centre)^-1 is the gauge with the identity as centre block
 //   (S^-1 Q is invariant under alpha -> alpha X, so the gauge costs nothing).
 //
-// Weights are FP32 masters with BF16 copies; every product runs on
-// v_mfma_f32_16x16x16_bf16 with BF16 operands and FP32 accumulation.
+// Weights are FP32 masters with BF16 copies; every product runs on BF16 MFMA
+// (16x16x16 in training, 16x16x32 in inference) with FP32 accumulation.
 // Training runs the layers as separate products (the backward pass needs the
 // pre-activations); inference fuses the three layers per tile of rows.  GELU is
-// the exact x Phi(x) (device erf).  Loss: mean squared error; optimiser: Adam.
+// x Phi(x) with Phi from an erfc fit good to 1.5e-7 (far below the BF16
+// rounding of the activations).  Loss: mean squared error; optimiser: Adam.
 //
 // The learned fit predicts alpha for every interior point, orthonormalises it,
 // and accepts it when its locality tr(Q^H Gram_i Q) is no larger than the
@@ -43,9 +44,26 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erfc(z) for z >= 0 to 1.5e-7 absolute, from the rational-exponential fit of
+// Abramowitz and Stegun (eq. 7.1.26), and e^{-z^2} with it
+__device__ __forceinline__ float erfc_pos(float z, float& ez2) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+  ez2 = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);
+  const float q = fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f),
+                       0.254829592f);
+  return t * q * ez2;
+}
+// GELU(x) = x Phi(x), Phi(x) = erfc(-x / sqrt 2) / 2
+__device__ __forceinline__ float gelu(float x) {
+  float e;
+  const float q = erfc_pos(fabsf(x) * 0.70710678118654752f, e);
+  return x >= 0.f ? x * (1.0f - 0.5f * q) : 0.5f * x * q;
+}
+// GELU'(x) = Phi(x) + x phi(x)
 __device__ __forceinline__ float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+  float e;
+  const float q = erfc_pos(fabsf(x) * 0.70710678118654752f, e);
+  return (x >= 0.f ? 1.0f - 0.5f * q : 0.5f * q) + x * e * 0.39894228040143268f;
 }
 
 enum Epi { EPI_STORE = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_DACT = 3 };
@@ -254,106 +272,145 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
 
 // ---- inference: the three layers fused per tile of rows ------------------------
 // y (rows x 480, FP32) = W3^T GELU(W2^T GELU(W1^T x + b1) + b2) + b3 for FR rows
-// per workgroup: the tile's activations stay in LDS (BF16, as the separate
-// layers round them) and the weights stream from L2 in transposed BF16
-// copies wNt [n][k] (k contiguous, so a lane's four k values of an MFMA B
-// operand are one 8-byte load).  Four waves split the output columns; a
-// hidden layer is 2 x 4 tiles of 16 x 16 per wave, 16 k steps of
-// v_mfma_f32_16x16x16bf16_1k.
+// per workgroup of IW waves.  The tile's activations stay in LDS (BF16, as the
+// separate layers round them); the weights stream from L2 in copies laid out
+// in MFMA fragment order, so the 64 lanes' B operands of one 16-column tile
+// and one k step are 1 KB contiguous (whole lines per load).  A wave owns two
+// column tiles at a time and loads the fragments of its next pair while it
+// multiplies the current one.  Products on v_mfma_f32_16x16x32_bf16: lane l
+// gives A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j < 8, and
+// receives D[4 (l / 16) + r][l % 16], r < 4.  Every layer has K = 256.
 constexpr int FR = 32;                 // rows per workgroup
 constexpr int FRT = FR / 16;           // 16-row tiles per workgroup
 constexpr int FLD = MLP_IP + 8;        // LDS row stride (bf16): 528 bytes, spreads the banks
+constexpr int IW = 8;                  // waves per workgroup
+constexpr int KS = MLP_IP / 32;        // k steps per product
+constexpr int CTP = 2;                 // column tiles per wave and step
+static_assert(MLP_H == MLP_IP, "every inference product has K = 256");
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// wf[((nt KS + ks) 64 + l) 8 + j] = wb[(32 ks + 8 (l / 16) + j) N + 16 nt + l % 16]
+// for a K = 256 by N row-major BF16 weight (N a multiple of 16)
+__global__ void frag_bf16_kernel(const unsigned short* __restrict__ wb, int N, unsigned short* __restrict__ wf) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)MLP_IP * N) return;
+  const int j = (int)(i & 7), l = (int)((i >> 3) & 63);
+  const long f = i >> 9;
+  const int ks = (int)(f % KS), nt = (int)(f / KS);
+  wf[i] = wb[(long)(32 * ks + 8 * (l >> 4) + j) * N + 16 * nt + (l & 15)];
+}
+
+struct Frags {
+  uint4 b[CTP][KS];
+};
+
+// the fragments of column tiles nt0 and nt0 + IW (zero past nct)
+__device__ __forceinline__ void load_pair(Frags& F, const uint4* __restrict__ wf, int nt0, int nct, int lane) {
+#pragma unroll
+  for (int u = 0; u < CTP; ++u) {
+    const int nt = nt0 + u * IW;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      F.b[u][ks] = nt < nct ? wf[(nt * KS + ks) * 64 + lane] : uint4{0u, 0u, 0u, 0u};
+  }
+}
+
+// the biases of column tiles nt0 and nt0 + IW at this lane's column (0 past nout)
+__device__ __forceinline__ void load_bias(float* bn, const float* __restrict__ bias, int nt0, int nout, int lane) {
+#pragma unroll
+  for (int u = 0; u < CTP; ++u) {
+    const int n = 16 * (nt0 + u * IW) + (lane & 15);
+    bn[u] = n < nout ? bias[n] : 0.f;
+  }
+}
 
 template <bool HIDDEN>
-__device__ __forceinline__ void infer_layer(const unsigned short* __restrict__ hin, unsigned short* __restrict__ hout,
-                                            const unsigned short* __restrict__ wt, const float* __restrict__ bias,
-                                            float* __restrict__ y, int r0, int Bm, int ct0, int ctstep, int nct,
-                                            int lane) {
-  // column tiles ct0, ct0 + ctstep, ... (< nct), four at a time
-  for (int cb = ct0; cb < nct; cb += 4 * ctstep) {
-    v4f acc[FRT][4];
+__device__ __forceinline__ void infer_pair(const Frags& F, const float* bn, const unsigned short* __restrict__ hin,
+                                           unsigned short* __restrict__ hout, float* __restrict__ y, int r0, int Bm,
+                                           int nt0, int nct, int lane) {
+  v4f acc[FRT][CTP];
+#pragma unroll
+  for (int a = 0; a < FRT; ++a)
+#pragma unroll
+    for (int u = 0; u < CTP; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kk = 32 * ks + 8 * (lane >> 4);
+    uint4 af[FRT];
+#pragma unroll
+    for (int a = 0; a < FRT; ++a) af[a] = *reinterpret_cast<const uint4*>(hin + (16 * a + (lane & 15)) * FLD + kk);
 #pragma unroll
     for (int a = 0; a < FRT; ++a)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[a][u] = v4f{0.f, 0.f, 0.f, 0.f};
-    int nn[4];
+      for (int u = 0; u < CTP; ++u)
+        acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, af[a]),
+                                                            __builtin_bit_cast(v8bf, F.b[u][ks]), acc[a][u], 0, 0,
+                                                            0);
+  }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) nn[u] = cb + u * ctstep;        // column tile of slot u (may be >= nct)
-    // every weight fragment of the four column tiles over the whole K is
-    // loaded before the first product (128 VGPRs): one L2 latency per layer
-    // instead of one per k step
-    v4s bw[4][MLP_IP / 16];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int ks = 0; ks < MLP_IP / 16; ++ks)
-        bw[u][ks] = (nn[u] < nct) ? *reinterpret_cast<const v4s*>(wt + (long)(16 * nn[u] + (lane & 15)) * MLP_IP +
-                                                                   16 * ks + 4 * (lane >> 4))
-                                  : v4s{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < MLP_IP / 16; ++ks) {
-      const int kk = 16 * ks + 4 * (lane >> 4);
-      v4s af[FRT];
-#pragma unroll
-      for (int a = 0; a < FRT; ++a) af[a] = *reinterpret_cast<const v4s*>(hin + (16 * a + (lane & 15)) * FLD + kk);
-#pragma unroll
-      for (int a = 0; a < FRT; ++a)
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          acc[a][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[a], bw[u][ks], acc[a][u], 0, 0, 0);
-    }
+  for (int u = 0; u < CTP; ++u) {
+    const int nt = nt0 + u * IW;
+    if (nt >= nct) continue;
+    const int n = 16 * nt + (lane & 15);
 #pragma unroll
     for (int a = 0; a < FRT; ++a)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (nn[u] >= nct) continue;
-        const int n = 16 * nn[u] + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * a + 4 * (lane >> 4) + r;
-          if (HIDDEN) {
-            hout[row * FLD + n] = f2bf(gelu(acc[a][u][r] + bias[n]));
-          } else if (r0 + row < Bm) {
-            y[(long)(r0 + row) * MLP_OP + n] = (n < MLP_O) ? acc[a][u][r] + bias[n] : 0.f;
-          }
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * a + 4 * (lane >> 4) + r;
+        if (HIDDEN) {
+          hout[row * FLD + n] = f2bf(gelu(acc[a][u][r] + bn[u]));
+        } else if (r0 + row < Bm) {
+          y[(long)(r0 + row) * MLP_OP + n] = (n < MLP_O) ? acc[a][u][r] + bn[u] : 0.f;
         }
       }
   }
 }
 
-__global__ __launch_bounds__(256) void mlp_infer_kernel(const unsigned short* __restrict__ xb, int Bm,
-                                                        const unsigned short* __restrict__ w1t,
-                                                        const unsigned short* __restrict__ w2t,
-                                                        const unsigned short* __restrict__ w3t,
-                                                        const float* __restrict__ b1, const float* __restrict__ b2,
-                                                        const float* __restrict__ b3, float* __restrict__ y) {
+__global__ __launch_bounds__(64 * IW) void mlp_infer_kernel(const unsigned short* __restrict__ xb, int Bm,
+                                                            const uint4* __restrict__ w1f,
+                                                            const uint4* __restrict__ w2f,
+                                                            const uint4* __restrict__ w3f,
+                                                            const float* __restrict__ b1,
+                                                            const float* __restrict__ b2,
+                                                            const float* __restrict__ b3, float* __restrict__ y) {
   __shared__ __attribute__((aligned(16))) unsigned short hs[2][FR * FLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = blockIdx.x * FR;
   // the tile's inputs, 16 bytes per load; rows past Bm are zero
-  for (int e = tid; e < FR * (MLP_IP / 8); e += 256) {
-    const int r = e / (MLP_IP / 8), c = e % (MLP_IP / 8);
-    uint4 v = {0u, 0u, 0u, 0u};
-    if (r0 + r < Bm) v = *reinterpret_cast<const uint4*>(xb + (long)(r0 + r) * MLP_IP + 8 * c);
-    *reinterpret_cast<uint4*>(&hs[0][r * FLD + 8 * c]) = v;
+  constexpr int XL = FR * (MLP_IP / 8) / (64 * IW);
+  static_assert(XL * 64 * IW == FR * (MLP_IP / 8), "the input tile splits evenly over the threads");
+  uint4 xv[XL];
+#pragma unroll
+  for (int q = 0; q < XL; ++q) {
+    const int e = tid + 64 * IW * q, r = e / (MLP_IP / 8), c = e % (MLP_IP / 8);
+    xv[q] = r0 + r < Bm ? *reinterpret_cast<const uint4*>(xb + (long)(r0 + r) * MLP_IP + 8 * c)
+                        : uint4{0u, 0u, 0u, 0u};
+  }
+  // every bias this wave adds, loaded before the weights so that no wait for
+  // a bias also waits for the weight fragments in flight
+  float bs[4][CTP];
+  load_bias(bs[0], b1, wave, MLP_H, lane);
+  load_bias(bs[1], b2, wave, MLP_H, lane);
+  load_bias(bs[2], b3, wave, MLP_O, lane);
+  load_bias(bs[3], b3, wave + 2 * IW, MLP_O, lane);
+  Frags P, Q;
+  load_pair(P, w1f, wave, MLP_H / 16, lane);                // layer 1: tiles wave, wave + 8
+#pragma unroll
+  for (int q = 0; q < XL; ++q) {
+    const int e = tid + 64 * IW * q, r = e / (MLP_IP / 8), c = e % (MLP_IP / 8);
+    *reinterpret_cast<uint4*>(&hs[0][r * FLD + 8 * c]) = xv[q];
   }
   __syncthreads();
-  // hidden layers: wave w owns column tiles w, w + 4, w + 8, w + 12 (of 16)
-  infer_layer<true>(hs[0], hs[1], w1t, b1, nullptr, r0, Bm, wave, 4, MLP_H / 16, lane);
+  load_pair(Q, w2f, wave, MLP_H / 16, lane);                // layer 2, loaded during layer 1
+  infer_pair<true>(P, bs[0], hs[0], hs[1], nullptr, r0, Bm, wave, MLP_H / 16, lane);
   __syncthreads();
-  infer_layer<true>(hs[1], hs[0], w2t, b2, nullptr, r0, Bm, wave, 4, MLP_H / 16, lane);
+  load_pair(P, w3f, wave, MLP_OP / 16, lane);               // layer 3: tiles wave, wave + 8
+  infer_pair<true>(Q, bs[1], hs[1], hs[0], nullptr, r0, Bm, wave, MLP_H / 16, lane);
   __syncthreads();
-  // output layer: 30 column tiles, wave w owns w, w + 4, ...
-  infer_layer<false>(hs[0], nullptr, w3t, b3, y, r0, Bm, wave, 4, MLP_OP / 16, lane);
-}
-
-// b [C][R] = a [R][C] (BF16)
-__global__ void transpose_bf16_kernel(const unsigned short* __restrict__ a, int R, int C,
-                                      unsigned short* __restrict__ b) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long)R * C) return;
-  const int c = (int)(i / R), r = (int)(i % R);
-  b[i] = a[(long)r * C + c];
+  load_pair(Q, w3f, wave + 2 * IW, MLP_OP / 16, lane);      // tiles wave + 16, wave + 24 (< 30)
+  infer_pair<false>(P, bs[2], hs[0], nullptr, y, r0, Bm, wave, MLP_OP / 16, lane);
+  infer_pair<false>(Q, bs[3], hs[0], nullptr, y, r0, Bm, wave + 2 * IW, MLP_OP / 16, lane);
 }
 
 inline unsigned nbk(long len, int t) { return (unsigned)((len + t - 1) / t); }
@@ -388,31 +445,31 @@ ls_status mlp_refresh_bf16(MlpState& st, hipStream_t s) {
   hipLaunchKernelGGL(pad_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s, w + MLP_OFF_W3, MLP_H,
                      MLP_O, st.w3b.as<unsigned short>(), MLP_H, MLP_OP);
   LS_HIP(hipGetLastError());
-  ++st.wver;                           // the transposed inference copies are stale
+  ++st.wver;                           // the fragment-ordered inference copies are stale
   return LS_OK;
 }
 
 ls_status mlp_infer(MlpState& st, const unsigned short* xb, int Bm, hipStream_t s) {
   LS_TRY(mlp_workspace(st, Bm));
-  if (st.tver != st.wver) {
-    if (!st.w1t.p) {
-      LS_TRY(st.w1t.alloc((size_t)MLP_H * MLP_IP * 2));
-      LS_TRY(st.w2t.alloc((size_t)MLP_H * MLP_H * 2));
-      LS_TRY(st.w3t.alloc((size_t)MLP_OP * MLP_H * 2));
+  if (st.fver != st.wver) {
+    if (!st.w1f.p) {
+      LS_TRY(st.w1f.alloc((size_t)MLP_IP * MLP_H * 2));
+      LS_TRY(st.w2f.alloc((size_t)MLP_H * MLP_H * 2));
+      LS_TRY(st.w3f.alloc((size_t)MLP_H * MLP_OP * 2));
     }
-    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_IP * MLP_H, 256)), dim3(256), 0, s,
-                       st.w1b.as<unsigned short>(), MLP_IP, MLP_H, st.w1t.as<unsigned short>());
-    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s,
-                       st.w2b.as<unsigned short>(), MLP_H, MLP_H, st.w2t.as<unsigned short>());
-    hipLaunchKernelGGL(transpose_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s,
-                       st.w3b.as<unsigned short>(), MLP_H, MLP_OP, st.w3t.as<unsigned short>());
+    hipLaunchKernelGGL(frag_bf16_kernel, dim3(nbk((long)MLP_IP * MLP_H, 256)), dim3(256), 0, s,
+                       st.w1b.as<unsigned short>(), MLP_H, st.w1f.as<unsigned short>());
+    hipLaunchKernelGGL(frag_bf16_kernel, dim3(nbk((long)MLP_H * MLP_H, 256)), dim3(256), 0, s,
+                       st.w2b.as<unsigned short>(), MLP_H, st.w2f.as<unsigned short>());
+    hipLaunchKernelGGL(frag_bf16_kernel, dim3(nbk((long)MLP_H * MLP_OP, 256)), dim3(256), 0, s,
+                       st.w3b.as<unsigned short>(), MLP_OP, st.w3f.as<unsigned short>());
     LS_HIP(hipGetLastError());
-    st.tver = st.wver;
+    st.fver = st.wver;
   }
   const float* w = st.w.as<float>();
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3(nbk(Bm, FR)), dim3(256), 0, s, xb, Bm, st.w1t.as<unsigned short>(),
-                     st.w2t.as<unsigned short>(), st.w3t.as<unsigned short>(), w + MLP_OFF_B1, w + MLP_OFF_B2,
-                     w + MLP_OFF_B3, st.y.as<float>());
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3(nbk(Bm, FR)), dim3(64 * IW), 0, s, xb, Bm, st.w1f.as<uint4>(),
+                     st.w2f.as<uint4>(), st.w3f.as<uint4>(), w + MLP_OFF_B1, w + MLP_OFF_B2, w + MLP_OFF_B3,
+                     st.y.as<float>());
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
