@@ -36,7 +36,7 @@ KERNEL_NAMES = ["col_fft_kernel (mode 0)", "col_fft_kernel (mode 1)", "kmul_kern
 # only while the apply sources are the ones that were profiled.
 MEASURED_TRAFFIC = {
     "sources": ["fft_kernels.h", "fft_apply.hip", "fft_inst_e.hip", "common.h", "cplx.h"],
-    "sha256": "84fc46bda5308d8f2f1389a349fe68168d80fca23bdc41957bae3c472b91948e",
+    "sha256": "0a5f922aa79cf46908be21d9e0d170265055a3eede956f350db5b0f55b453bf4",
     "workload": (128, 8, "c64"),
     "bytes": 3.3265e9,
     "profile": "profiles/ls_apply_n128_b8_c64.md",
@@ -47,7 +47,7 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "14ec4bfa9eaffe6b0dda5226fcc85efd9b32c7be983c60a814b21ea2f7acea6b",
+    "sha256": "39d5c53db81f16d2c5d5210ba80aa338a93ef375a18c40cbdb0c259267c4ba40",
     "workload": (959, 8, "c64"),
     "bytes": 1.3066e9,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",

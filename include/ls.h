@@ -102,15 +102,17 @@ typedef struct {
   int half_runs;              /* bit i: strided pass i (dim-1 forward, dim-2 forward,
                                  dim-2 inverse, dim-1 inverse) reads and writes rows in
                                  128-byte runs (its FFT tile halved) instead of 256     */
-  int persist;                /* 1: persistent launches (grids of the resident
-                                 workgroups, which stride over the work items)          */
+  int persist;                /* persistent launches (grids of the resident
+                                 workgroups, which stride over the work items):
+                                 bit 0 the four strided passes, bit 1 pass 3            */
 } ls_tune_info;
 
 /* Autotune the apply of prec for batches of nrhs: look the key (GPU, n, P,
  * form, prec, nrhs, max_rhs) up in the plan's tune_cache file; on a miss time the
  * choices on the plan's operator (scratch fields of nrhs, allocated and freed
  * here): every chunk x team count, then each strided pass with half runs in
- * turn (kept where faster), then persistent launches; keep the fastest and
+ * turn (kept where faster), then persistent launches of the strided passes, of
+ * pass 3 and of both; keep the fastest and
  * append it to the cache file (a JSON array, one object per line; rewritten
  * through a temporary file).  The choice then holds
  * for every later apply and solve of that precision.  A cache that cannot be
@@ -122,7 +124,7 @@ ls_status ls_plan_tune(ls_plan* plan, int nrhs, ls_prec prec, void* hip_stream, 
 /* Set the launch choice of prec by hand (chunk 0 / kmul_w 0 = default;
  * half_runs and persist as in ls_tune_info, 0 = default).  LS_EINVAL for
  * chunk > max_rhs, kmul_w not in {0, 1, 2, 4}, half_runs outside 0..15 or
- * persist not 0 or 1. */
+ * persist outside 0..3. */
 ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w, int half_runs, int persist);
 
 /* ls_apply for callers that cannot allocate device memory (code under HIP

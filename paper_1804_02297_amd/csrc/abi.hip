@@ -181,7 +181,7 @@ ls_status ls_plan_set_tune(ls_plan* plan, ls_prec prec, int chunk, int kmul_w, i
     if (prec != LS_C128 && prec != LS_C64 && prec != LS_MIXED) return LS_EINVAL;
     if (chunk < 0 || chunk > plan->ap.max_rhs) return LS_EINVAL;
     if (kmul_w != 0 && kmul_w != 1 && kmul_w != 2 && kmul_w != 4) return LS_EINVAL;
-    if (half_runs < 0 || half_runs > 15 || (persist != 0 && persist != 1)) return LS_EINVAL;
+    if (half_runs < 0 || half_runs > 15 || persist < 0 || persist > 3) return LS_EINVAL;
     plan->ap.tune[prec].chunk = chunk;
     plan->ap.tune[prec].kmul_w = kmul_w;
     plan->ap.tune[prec].half_runs = half_runs;

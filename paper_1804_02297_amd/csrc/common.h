@@ -66,8 +66,9 @@ struct ApplyTune {
   int half_runs = 0;             // bit i set: strided pass i (0 dim-1 forward, 1 dim-2
                                  // forward, 2 dim-2 inverse, 3 dim-1 inverse) works on
                                  // half-length row runs (128 bytes instead of 256)
-  int persist = 0;               // 1: every pass launches only the workgroups the device
-                                 // holds at once, and each takes work items grid-stride
+  int persist = 0;               // bit 0: the four strided passes, bit 1: pass 3 launch
+                                 // only the workgroups the device holds at once, and
+                                 // each takes work items grid-stride
 };
 
 struct ApplyPlan {

@@ -232,6 +232,90 @@ struct Dft {
   }
 };
 
+// Length 16 (4 x 4): the four sub-transforms of inputs f + 4m, then per output
+// column q a radix-4 butterfly over f of sub[f][q] W^(fq).  The twiddles are
+// folded into fused multiply-adds: W^(fq) s is written as a real scale times
+// s + t rot(s) or t s + rot(s) (t = tan(pi/8), rot = multiplication by the
+// direction's quarter turn), and the columns q = 1, 3 pair terms whose
+// scales are both cos(pi/8), q = 1, 2, 3 terms with scale cos(pi/4), so each
+// scale is applied once in the final multiply-adds.  144 real operations for
+// the full transform instead of 160 with the twiddles multiplied out.
+template <int DIR, typename R>
+__device__ __forceinline__ C<R> qrot(C<R> a) {   // a * W^4 = a * (DIR i)
+  return (DIR < 0) ? mul_mi(a) : mul_pi(a);
+}
+// c * x + a, c a real constant
+template <typename R>
+__device__ __forceinline__ C<R> rfma(R c, C<R> x, C<R> a) {
+  return cmk<R>(c * x.re + a.re, c * x.im + a.im);
+}
+template <int DIR, typename R>
+__device__ __forceinline__ void dft16_finish(const C<R> (&sub)[4][4], C<R>* v) {
+  constexpr R Cp8 = (R)0.92387953251128675612818318939678829;   // cos(pi/8)
+  constexpr R Tp8 = (R)0.41421356237309504880168872420969808;   // tan(pi/8)
+  constexpr R Cp4 = (R)0.70710678118654752440084436210484903;   // cos(pi/4)
+  // q = 0: no twiddles
+  {
+    const C<R> a0 = sub[0][0] + sub[2][0], a1 = sub[0][0] - sub[2][0];
+    const C<R> b0 = sub[1][0] + sub[3][0], b1 = qrot<DIR>(sub[1][0] - sub[3][0]);
+    v[0] = a0 + b0;
+    v[8] = a0 - b0;
+    v[4] = a1 + b1;
+    v[12] = a1 - b1;
+  }
+  // s + t rot(s) and t s + rot(s)
+  auto zt = [](C<R> s) { return s + cscale(qrot<DIR>(s), Tp8); };
+  auto yt = [](C<R> s) { return cscale(s, Tp8) + qrot<DIR>(s); };
+  // q = 1: W^1 s1 = Cp8 z(s1), W^2 s2 = Cp4 (s2 + rot s2), W^3 s3 = Cp8 y(s3)
+  {
+    const C<R> p2 = sub[2][1] + qrot<DIR>(sub[2][1]);
+    const C<R> a0 = rfma(Cp4, p2, sub[0][1]), a1 = rfma(-Cp4, p2, sub[0][1]);
+    const C<R> z1 = zt(sub[1][1]), y3 = yt(sub[3][1]);
+    const C<R> e = z1 + y3, d = qrot<DIR>(z1 - y3);
+    v[1] = rfma(Cp8, e, a0);
+    v[9] = rfma(-Cp8, e, a0);
+    v[5] = rfma(Cp8, d, a1);
+    v[13] = rfma(-Cp8, d, a1);
+  }
+  // q = 2: W^2 s1 = Cp4 (s1 + rot s1), W^4 s2 = rot s2, W^6 s3 = Cp4 (rot s3 - s3)
+  {
+    const C<R> r2 = qrot<DIR>(sub[2][2]);
+    const C<R> a0 = sub[0][2] + r2, a1 = sub[0][2] - r2;
+    const C<R> u = sub[1][2] - sub[3][2], w = sub[1][2] + sub[3][2];
+    const C<R> e = u + qrot<DIR>(w);                 // (s1 + rot s1) + (rot s3 - s3)
+    const C<R> d = qrot<DIR>(w + qrot<DIR>(u));      // rot of (s1 + rot s1) - (rot s3 - s3)
+    v[2] = rfma(Cp4, e, a0);
+    v[10] = rfma(-Cp4, e, a0);
+    v[6] = rfma(Cp4, d, a1);
+    v[14] = rfma(-Cp4, d, a1);
+  }
+  // q = 3: W^3 s1 = Cp8 y(s1), W^6 s2 = Cp4 (rot s2 - s2), W^9 s3 = -Cp8 z(s3)
+  {
+    const C<R> p2 = qrot<DIR>(sub[2][3]) - sub[2][3];
+    const C<R> a0 = rfma(Cp4, p2, sub[0][3]), a1 = rfma(-Cp4, p2, sub[0][3]);
+    const C<R> y1 = yt(sub[1][3]), z3 = zt(sub[3][3]);
+    const C<R> e = y1 - z3, d = qrot<DIR>(y1 + z3);
+    v[3] = rfma(Cp8, e, a0);
+    v[11] = rfma(-Cp8, e, a0);
+    v[7] = rfma(Cp8, d, a1);
+    v[15] = rfma(-Cp8, d, a1);
+  }
+}
+
+template <int DIR, typename R>
+struct Dft<16, DIR, R> {
+  static __device__ __forceinline__ void run(C<R>* v) {
+    C<R> sub[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) sub[f][m] = v[f + 4 * m];
+      Dft<4, DIR, R>::run(sub[f]);
+    }
+    dft16_finish<DIR>(sub, v);
+  }
+};
+
 // ---- DFTs with known-zero inputs ---------------------------------------------
 // DftZ<N, DIR, R, NIN>: the same transform when v[k] = 0 for k >= NIN (those
 // entries are never read).  The zero-padded halves of the circulant
@@ -269,6 +353,16 @@ struct DftZ {
 #pragma unroll
       for (int k = NIN; k < N; ++k) v[k] = cmk<R>(0, 0);
       Dft<N, DIR, R>::run(v);
+    } else if constexpr (N == 16 && NIN >= 4) {
+      C<R> sub[4][4];
+      static_for<0, 4>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        constexpr int nin = (NIN > f) ? (NIN - f + 3) / 4 : 0;
+#pragma unroll
+        for (int m = 0; m < nin; ++m) sub[f][m] = v[f + 4 * m];
+        DftZ<4, DIR, R, nin>::run(sub[f]);
+      });
+      dft16_finish<DIR>(sub, v);
     } else {
       constexpr int F = FirstFactor<N>::value;
       constexpr int M = N / F;

@@ -880,7 +880,7 @@ static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, con
 #define LS_MARK(i) \
   if (ev) LS_HIP(hipEventRecord(ev[i], s))
   LS_MARK(0);
-  const bool pe = tn.persist != 0;
+  const bool pe = (tn.persist & 1) != 0, pe3 = (tn.persist & 2) != 0;
   // pass 1: along dim 1, lines = n^2
   LS_TRY((launch_col_rt<R, IO, P, COL_P1>(tn.half_runs & 1, pe, x, X1, m, tw, n, P, n2, n3, (long)P * n2, nb, (R)1,
                                           s)));
@@ -890,7 +890,7 @@ static ls_status run_passes(ApplyPlan& ap, const void* x, void* y, int nrhs, con
                                           nb * P, (R)1, s)));
   LS_MARK(2);
   // pass 3: along dim 3 with the 3x3 multiply
-  LS_TRY((launch_kmul<R, P>(X2, kh, tw, n, nrhs, tn.kmul_w, pe, s)));
+  LS_TRY((launch_kmul<R, P>(X2, kh, tw, n, nrhs, tn.kmul_w, pe3, s)));
   LS_MARK(3);
   // pass 4: inverse along dim 2
   LS_TRY((launch_col_rt<R, R, P, COL_INV>(tn.half_runs & 4, pe, X2, X1, nullptr, tw, P, n, n, (long)P * n, n2,

@@ -10,16 +10,22 @@
 //   * the row-run length of each strided pass (256 or 128 bytes, the FFT tile
 //     of the pass): a half tile halves the workgroup's LDS and fits more
 //     workgroups per CU to cover its latency;
-//   * persistent launches: every pass launches only the workgroups the device
-//     holds at once, which stride over the work items.
+//   * persistent launches, for the strided passes and for pass 3 apart: a
+//     pass launches only the workgroups the device holds at once, which
+//     stride over the work items (pass 3 reloads its symbol line per work
+//     item, and a workgroup that waits for it idles its CU unless other
+//     workgroups are resident there, so it can prefer the ordinary grid
+//     where the strided passes gain).
 // The first two are searched jointly, then each pass's run length is halved
-// in turn and kept where it is faster, then the persistent launch is tried on
-// the result.  The device is first warmed up by three applies; each
-// candidate then runs once to warm up and 10 times between HIP events (3
-// timed runs left the choice to noise of about 2 %).
+// in turn and kept where it is faster, then the three persistent settings are
+// tried on the result; the three fastest choices are finally timed again,
+// interleaved and longer, and the fastest of that round is kept.  The device
+// is first warmed up by three applies; each candidate then runs once to warm
+// up and 10 times between HIP events (3 timed runs left the choice to noise
+// of about 2 %), the final three 2 x 30 times.
 //
 // Cache: a JSON array, one object per line,
-//   {"key": "<arch>|cu=<CUs>|v=2|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>",
+//   {"key": "<arch>|cu=<CUs>|v=3|n=<n>|P=<P>|form=<f>|prec=<p>|nrhs=<b>|max_rhs=<m>",
 //    "chunk": c, "kmul_w": w, "half_runs": r, "persist": q, "ms_per_rhs": t}
 // read before timing (a hit skips it) and rewritten with the new entry after.
 #include <algorithm>
@@ -47,7 +53,7 @@ std::string tune_key(const ApplyPlan& ap, int nrhs, ls_prec prec) {
     cus = prop.multiProcessorCount;
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s|cu=%d|v=2|n=%d|P=%d|form=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus,
+  std::snprintf(buf, sizeof buf, "%s|cu=%d|v=3|n=%d|P=%d|form=%d|prec=%d|nrhs=%d|max_rhs=%d", arch.c_str(), cus,
                 ap.n, ap.P, ap.form, (int)prec, nrhs, ap.max_rhs);
   return buf;
 }
@@ -107,10 +113,10 @@ bool write_cache(const std::string& path, const std::vector<Entry>& es) {
   return std::rename(tmp.c_str(), path.c_str()) == 0;
 }
 
-// average ms of one batched apply under the plan's current choice
+// average ms of one batched apply under the plan's current choice (one
+// untimed apply first, then reps between events)
 ls_status time_apply(ApplyPlan& ap, const void* x, void* y, int nrhs, ls_prec prec, hipStream_t s,
-                     hipEvent_t e0, hipEvent_t e1, double* ms) {
-  constexpr int kReps = 10;
+                     hipEvent_t e0, hipEvent_t e1, double* ms, int kReps = 10) {
   LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
   LS_HIP(hipEventRecord(e0, s));
   for (int r = 0; r < kReps; ++r) LS_TRY(apply_batched(ap, x, y, nrhs, prec, s));
@@ -136,7 +142,7 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
     entries = read_cache(cache);
     for (const Entry& e : entries)
       if (e.key == key && e.t.chunk >= 1 && e.t.chunk <= ap.max_rhs && e.t.kmul_w >= 1 && e.t.half_runs >= 0 &&
-          e.t.half_runs <= 15 && (e.t.persist == 0 || e.t.persist == 1)) {
+          e.t.half_runs <= 15 && e.t.persist >= 0 && e.t.persist <= 3) {
         ap.tune[prec] = e.t;
         res.t = e.t;
         res.ms_per_rhs = e.ms;
@@ -177,12 +183,14 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
   }
   st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &res.ms_default_per_rhs);
   res.ms_default_per_rhs /= nrhs;
+  std::vector<std::pair<double, ApplyTune>> tried;
   auto trial = [&](const ApplyTune& t) {
     if (st != LS_OK) return;
     ap.tune[prec] = t;
     double ms = 0.0;
     st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &ms);
     ++res.n_tried;
+    if (st == LS_OK) tried.push_back({ms, t});
     if (st == LS_OK && ms < best) {
       best = ms;
       pick = t;
@@ -203,11 +211,37 @@ ls_status apply_tune(ApplyPlan& ap, const std::string& cache, int nrhs, ls_prec 
     t.half_runs |= bit;
     trial(t);
   }
-  // 3. persistent launches
+  // 3. persistent launches: strided passes, pass 3, both
   {
-    ApplyTune t = pick;
-    t.persist = 1;
-    trial(t);
+    const ApplyTune base = pick;
+    for (int q = 1; q <= 3; ++q) {
+      ApplyTune t = base;
+      t.persist = q;
+      trial(t);
+    }
+  }
+  // 4. the three fastest again, interleaved over two rounds of 3 x the reps:
+  // the candidates differ by about 1 %, as much as the drift of the device
+  // clock over the search
+  if (st == LS_OK && tried.size() > 1) {
+    std::stable_sort(tried.begin(), tried.end(),
+                     [](const std::pair<double, ApplyTune>& a, const std::pair<double, ApplyTune>& b) {
+                       return a.first < b.first;
+                     });
+    const size_t nf = std::min<size_t>(3, tried.size());
+    std::vector<double> tot(nf, 0.0);
+    for (int round = 0; round < 2 && st == LS_OK; ++round)
+      for (size_t i = 0; i < nf && st == LS_OK; ++i) {
+        ap.tune[prec] = tried[i].second;
+        double ms = 0.0;
+        st = time_apply(ap, x.p, y.p, nrhs, prec, s, e0, e1, &ms, 30);
+        tot[i] += ms;
+      }
+    if (st == LS_OK) {
+      const size_t bi = std::min_element(tot.begin(), tot.end()) - tot.begin();
+      pick = tried[bi].second;
+      best = tot[bi] / 2;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

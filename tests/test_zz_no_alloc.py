@@ -73,7 +73,7 @@ def test_noalloc_apply_under_other_launch_choices(lib):
     plan = _plan(n, nrhs)
     x = torch.from_numpy(I.random_field(nrhs, n, 4)).to("cuda:0").to(torch.complex64)
     ref = plan.apply(x, prec="c64")
-    for choice in [(2, 4, 15, 1), (3, 1, 6, 0), (1, 2, 0, 1)]:
+    for choice in [(2, 4, 15, 1), (3, 1, 6, 0), (1, 2, 0, 3), (2, 2, 0, 2)]:
         plan.set_tune("c64", *choice)
         y = torch.full_like(x, float("nan"))
         plan.apply_noalloc(x, y, prec="c64")
