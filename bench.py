@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {
 # reported only while the sources are the measured ones.
 MEASURED_TRAFFIC_2D = {
     "sources": ["twod.hip", "twod.h", "cplx.h"],
-    "sha256": "39d5c53db81f16d2c5d5210ba80aa338a93ef375a18c40cbdb0c259267c4ba40",
+    "sha256": "cf6e2a189cd9b62519a9921a5757e0a3f4e7ffea85c18c279ef83f30936b6f2f",
     "workload": (959, 8, "c64"),
-    "bytes": 1.3066e9,
+    "bytes": 9.343e8,
     "profile": "profiles/ls2_apply_n959_b8_c64.md",
 }
 

@@ -27,6 +27,7 @@ struct Plan2 {
   DevBuf m64, m32;                 // contrast [n][n]
   DevBuf p64, p32;                 // p^d, [2][n][n]
   DevBuf sym64, sym32;             // symbol quadrant / P^2, [H][H][3]
+  DevBuf symc64, symc32;           // the same column-major, [3][H (q2)][H (q1)]
   DevBuf tw64, tw32;               // exp(-2 pi i t / P)
   DevBuf work;                     // pass intermediates, max_rhs x 5 x n x P
   // stencils (class fit) and the sparse system

@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <vector>
@@ -190,6 +191,52 @@ __device__ __forceinline__ C<R>* lds_fft(C<R>* a, C<R>* b, int P, Radices rd, in
   return a;
 }
 
+// The same transforms for a compile-time length P (the paper's lengths): the
+// stages are unrolled at compile time, so each stage's radix, span and
+// twiddle step are constants and the index arithmetic has no runtime
+// division and no switch over the radix.  REV: the reversed stage order.
+template <int P, bool REV>
+struct CtStages {
+  static constexpr Radices rd = REV ? reverse_radices(factor_radices(P)) : factor_radices(P);
+  static constexpr int nst = rd.nst;
+  static constexpr int radix(int st) {
+    const unsigned c = (unsigned)(rd.code >> (3 * st)) & 7u;
+    return c == 0 ? 4 : (c == 1 ? 2 : (c == 2 ? 3 : (c == 3 ? 8 : 9)));
+  }
+  static constexpr int span(int st) {   // product of the radices of the stages before st
+    int v = 1;
+    for (int q = 0; q < st; ++q) v *= radix(q);
+    return v;
+  }
+};
+
+template <typename R, int DIR, bool BFAST, bool ZIN, bool HOUT, int NT, int P, bool REV>
+__device__ __forceinline__ C<R>* lds_fft_ct(C<R>* a, C<R>* b, int nb, int es, int bs, const Tw<R>& tw) {
+  using S = CtStages<P, REV>;
+  static_assert(S::nst > 1, "a compile-time length has at least two stages");
+  static_for<0, S::nst>([&](auto sc) {
+    constexpr int st = decltype(sc)::value;
+    constexpr int RR = S::radix(st);
+    constexpr int Ns = S::span(st);
+    constexpr int NR = P / RR;
+    constexpr int tstep = P / (RR * Ns);
+    constexpr bool EV = RR % 2 == 0;
+    constexpr bool first = st == 0, last = st + 1 == S::nst;
+    const int total = nb * NR;
+    for (int w = threadIdx.x; w < total; w += NT) {
+      const int t = BFAST ? w % nb : w / NR;
+      const int j = BFAST ? w / nb : w % NR;
+      stage_bfly<R, DIR, RR, first, first && ZIN && EV, last && HOUT && EV>(a + t * bs, b + t * bs, j, Ns, NR,
+                                                                              tstep, es, tw);
+    }
+    __syncthreads();
+    C<R>* tmp = a;
+    a = b;
+    b = tmp;
+  });
+  return a;
+}
+
 // Work index of a block: consecutive indices stay on one XCD (blocks are
 // dispatched round-robin over the 8 XCDs), so blocks that share rows or
 // symbol lines share that XCD's L2.
@@ -272,8 +319,11 @@ __global__ __launch_bounds__(kT2) void fft_cols_kernel(C<R>* __restrict__ data, 
 }
 
 // Quadrant of the transformed embedding / P^2: sym[a1][a2][c].
+// The quadrant twice: [a1][a2][3] (the register column pass) and column-major
+// [3][a2][a1] (the LDS column pass, whose workgroups walk one column's a1).
 __global__ void quadrant_kernel(const C<double>* __restrict__ emb, C<double>* __restrict__ s64,
-                                C<float>* __restrict__ s32, int P, int H) {
+                                C<float>* __restrict__ s32, C<double>* __restrict__ c64,
+                                C<float>* __restrict__ c32, int P, int H) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)H * H) return;
   const int a1 = (int)(idx / H), a2 = (int)(idx % H);
@@ -282,6 +332,9 @@ __global__ void quadrant_kernel(const C<double>* __restrict__ emb, C<double>* __
     const C<double> v = cscale(emb[(size_t)c * P * P + (size_t)a1 * P + a2], sc);
     s64[idx * 3 + c] = v;
     s32[idx * 3 + c] = ccast<float>(v);
+    const size_t t = ((size_t)c * H + a2) * H + a1;
+    c64[t] = v;
+    c32[t] = ccast<float>(v);
   }
 }
 
@@ -364,7 +417,9 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
       }
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, -1, false, true, false>(a, bb, P, rd, nb, 1, P, tws);
+    const C<R>* X;
+    if constexpr (PT > 0) X = lds_fft_ct<R, -1, false, true, false, kT2, PT, false>(a, bb, nb, 1, P, tws);
+    else X = lds_fft<R, -1, false, true, false>(a, bb, P, rd, nb, 1, P, tws);
     C<R>* out = T + ((size_t)(b * 3 + f) * n) * P;
     for (int e = threadIdx.x; e < nb * P; e += kT2) {
       const int i1 = rb * nb + e / P;
@@ -374,11 +429,14 @@ __global__ __launch_bounds__(kT2) void pass_a_kernel(const void* __restrict__ x,
   }
 }
 
-// pass B: block -> (rhs, block of nb adjacent columns).  Registers capped for
-// four waves per SIMD (two workgroups of 62 KiB LDS per CU).
-template <typename R, int EMAX, int PT, int NBT>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(
-    const C<R>* __restrict__ T, C<R>* __restrict__ T2, const C<R>* __restrict__ sym, int n, int P_, int H,
+// pass B: block -> (rhs, block of nb adjacent columns), NTH threads.
+// Registers capped for four waves per SIMD (two workgroups of 512 threads and
+// 62 KiB LDS, or one of 1024 threads and 125 KiB, per CU).  symc: the
+// symbol quadrant column-major ([3][a2][a1]), so the rows of a column block
+// read whole lines of it.
+template <typename R, int EMAX, int PT, int NBT, int NTH = kTB>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(4, 8))) void pass_b_kernel(
+    const C<R>* __restrict__ T, C<R>* __restrict__ T2, const C<R>* __restrict__ symc, int n, int P_, int H,
     Radices rd_, int nb_, int nrhs, const C<R>* __restrict__ tw) {
   const int P = PT > 0 ? PT : P_, nb = NBT > 0 ? NBT : nb_;
   const Radices rd = PT > 0 ? factor_radices(PT) : rd_;
@@ -401,7 +459,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int q1 = e / nb, q2 = q0 + e % nb;
     const bool f1 = q1 > P / 2, f2 = q2 > P / 2;
     const int a1 = f1 ? P - q1 : q1, a2 = f2 ? P - q2 : q2;
-    const C<R> v = sym[((size_t)a1 * H + a2) * 3 + c];
+    const C<R> v = symc[((size_t)c * H + a2) * H + a1];
     const bool neg = (c == 1 && f1) || (c == 2 && f2);
     return neg ? cmk<R>(-v.re, -v.im) : v;
   };
@@ -414,34 +472,61 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const C<R>* in = T + ((size_t)(b * 3 + f) * n) * P + q0;
 #pragma unroll
     for (int u = 0; u < UL; ++u) {
-      const int e = threadIdx.x + kTB * u;
+      const int e = threadIdx.x + NTH * u;
       C<R> v = cmk<R>(0, 0);
       if (e < tot / 2 && e / nb < n) v = in[(size_t)(e / nb) * P + e % nb];
       pf[u] = v;
     }
   };
+  // FP32: the symbol component a field is multiplied by is loaded before the
+  // field's transform, so its latency is hidden behind the transform (FP64
+  // has no registers to spare for it and loads at use)
+  constexpr bool SPRE = sizeof(R) == 4;
+  C<R> sv[SPRE ? EMAX : 1];
+  auto load_sym = [&](int c) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int u = 0; u < EMAX; ++u) {
+      const int e = tid + NTH * u;
+      sv[u] = e < tot ? symv(e, c) : cmk<R>(0, 0);
+    }
+  };
   fetch(0);
+  if constexpr (SPRE) load_sym(0);    // fields 0 and 1 take component 0
 #pragma unroll 1
   for (int f = 0; f < 3; ++f) {
 #pragma unroll
     for (int u = 0; u < UL; ++u) {
-      const int e = threadIdx.x + kTB * u;
+      const int e = threadIdx.x + NTH * u;
       if (e < tot / 2) a[e] = pf[u];
     }
     __syncthreads();
     if (f < 2) fetch(f + 1);
-    const C<R>* X = lds_fft<R, -1, true, true, false, kTB>(a, bb, P, rd, nb, nb, 1, tws);
+    if constexpr (SPRE)
+      if (f == 2) load_sym(1);
+    const C<R>* X;
+    if constexpr (PT > 0) X = lds_fft_ct<R, -1, true, true, false, NTH, PT, false>(a, bb, nb, nb, 1, tws);
+    else X = lds_fft<R, -1, true, true, false, NTH>(a, bb, P, rd, nb, nb, 1, tws);
+    // the symbol addresses are formed per field from an opaque thread index
+    // rather than kept across the loop (they would not fit beside the
+    // accumulators without spilling)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
-      const int e = threadIdx.x + kTB * u;
+      const int e = tid + NTH * u;
       if (e < tot) {
         const C<R> v = X[e];
+        C<R> s01;
+        if constexpr (SPRE) s01 = sv[u];
+        else s01 = symv(e, f == 2 ? 1 : 0);
         if (f == 0) {
-          o0[u] = symv(e, 0) * v;
+          o0[u] = s01 * v;
         } else if (f == 1) {
-          o1[u] = symv(e, 0) * v;
+          o1[u] = s01 * v;
         } else {
-          o0[u] = cfma(symv(e, 1), v, o0[u]);
+          o0[u] = cfma(s01, v, o0[u]);
           o1[u] = cfma(symv(e, 2), v, o1[u]);
         }
       }
@@ -452,16 +537,18 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   for (int d = 0; d < 2; ++d) {
 #pragma unroll
     for (int u = 0; u < EMAX; ++u) {
-      const int e = threadIdx.x + kTB * u;
+      const int e = threadIdx.x + NTH * u;
       if (e < tot) {   // two stores, not a select between the arrays (that puts them on the stack)
         if (d == 0) a[e] = o0[u];
         else a[e] = o1[u];
       }
     }
     __syncthreads();
-    const C<R>* X = lds_fft<R, 1, true, false, true, kTB>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
+    const C<R>* X;
+    if constexpr (PT > 0) X = lds_fft_ct<R, 1, true, false, true, NTH, PT, true>(a, bb, nb, nb, 1, tws);
+    else X = lds_fft<R, 1, true, false, true, NTH>(a, bb, P, reverse_radices(rd), nb, nb, 1, tws);
     C<R>* out = T2 + ((size_t)(b * 2 + d) * n) * P + q0;
-    for (int e = threadIdx.x; e < tot; e += kTB) {
+    for (int e = threadIdx.x; e < tot; e += NTH) {
       const int i1 = e / nb;
       if (i1 < n) out[(size_t)i1 * P + e % nb] = X[e];
     }
@@ -628,7 +715,9 @@ __global__ __launch_bounds__(kT2) void pass_c_kernel(const C<R>* __restrict__ T2
     a[e] = i1 < n ? in[(size_t)i1 * P + e % P] : cmk<R>(0, 0);
   }
   __syncthreads();
-  const C<R>* X = lds_fft<R, 1, false, false, true>(a, bb, P, reverse_radices(rd), nb, 1, P, tws);
+  const C<R>* X;
+  if constexpr (PT > 0) X = lds_fft_ct<R, 1, false, false, true, kT2, PT, true>(a, bb, nb, 1, P, tws);
+  else X = lds_fft<R, 1, false, false, true>(a, bb, P, reverse_radices(rd), nb, 1, P, tws);
   const long nn = (long)n * n;
   const long base = ((long)b * 2 + d) * nn;
   C<IO>* yo = reinterpret_cast<C<IO>*>(y);
@@ -877,6 +966,7 @@ ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_co
   const C<R>* m = (const C<R>*)(std::is_same<R, double>::value ? pl.m64.p : pl.m32.p);
   const C<R>* p = (const C<R>*)(std::is_same<R, double>::value ? pl.p64.p : pl.p32.p);
   const C<R>* sym = (const C<R>*)(std::is_same<R, double>::value ? pl.sym64.p : pl.sym32.p);
+  const C<R>* symc = (const C<R>*)(std::is_same<R, double>::value ? pl.symc64.p : pl.symc32.p);
   const C<R>* tw = (const C<R>*)(std::is_same<R, double>::value ? pl.tw64.p : pl.tw32.p);
   C<R>* T = pl.work.as<C<R>>();
   C<R>* T2 = T + (size_t)pl.max_rhs * 3 * n * P;
@@ -902,9 +992,22 @@ ls_status run_apply_p(Plan2& pl, const void* x, void* y, int nrhs, bool minus_co
       using Cfg = ColRegCfg<PT>;
       hipLaunchKernelGGL((pass_b_reg_kernel<PT>), dim3(((PT + Cfg::NB - 1) / Cfg::NB) * nr), dim3(Cfg::THREADS), 0, s, T,
                          T2, sym, n, pl.H, nr, tw);
+    } else if constexpr (std::is_same<R, float>::value && PT == 1944) {
+      // four columns (32-byte row runs) per workgroup of 1024 threads, one
+      // workgroup per CU (125 KiB of LDS): half the partial-line reads of
+      // two columns per 512-thread workgroup, at the same four waves per SIMD
+      constexpr int NBW = 4, NTW = 1024, EMW = (NBW * PT + NTW - 1) / NTW;
+      const auto kern = pass_b_kernel<R, EMW, PT, NBW, NTW>;
+      const size_t ldsw = lds_bytes<R>(PT, NBW);
+      static std::once_flag attr_once;
+      std::call_once(attr_once, [&]() {
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsw);
+      });
+      hipLaunchKernelGGL(kern, dim3((PT / NBW) * nr), dim3(NTW), ldsw, s, T, T2, symc, n, P, pl.H, pl.rd, NBW, nr,
+                         tw);
     } else {
-      hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kTB), ldsc, s, T, T2, sym, n, P,
-                         pl.H, pl.rd, nbc, nr, tw);
+      hipLaunchKernelGGL((pass_b_kernel<R, EMAX, PT, NBB>), dim3((P / nbc) * nr), dim3(kTB), ldsc, s, T, T2, symc, n,
+                         P, pl.H, pl.rd, nbc, nr, tw);
     }
     LS_HIP(hipGetLastError());
     const int wc = nr * 2 * nrb;
@@ -964,6 +1067,8 @@ ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev,
   LS_TRY(pl.p32.alloc(2 * nn * sizeof(C<float>)));
   LS_TRY(pl.sym64.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<double>)));
   LS_TRY(pl.sym32.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<float>)));
+  LS_TRY(pl.symc64.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<double>)));
+  LS_TRY(pl.symc32.alloc((size_t)pl.H * pl.H * 3 * sizeof(C<float>)));
   LS_TRY(pl.tw64.alloc(P * sizeof(C<double>)));
   LS_TRY(pl.tw32.alloc(P * sizeof(C<float>)));
   // workspace: three transformed fields and two products per rhs, in FP64 (FP32 uses half)
@@ -998,7 +1103,8 @@ ls_status plan2_init(Plan2& pl, int n, double k, int max_rhs, const void* m_dev,
   LS_HIP(hipGetLastError());
   const long HH = (long)pl.H * pl.H;
   hipLaunchKernelGGL(quadrant_kernel, dim3((unsigned)((HH + 255) / 256)), dim3(256), 0, s, emb.as<C<double>>(),
-                     pl.sym64.as<C<double>>(), pl.sym32.as<C<float>>(), P, pl.H);
+                     pl.sym64.as<C<double>>(), pl.sym32.as<C<float>>(), pl.symc64.as<C<double>>(),
+                     pl.symc32.as<C<float>>(), P, pl.H);
   LS_HIP(hipGetLastError());
   LS_HIP(hipStreamSynchronize(s));   // emb is released on return
   return LS_OK;
