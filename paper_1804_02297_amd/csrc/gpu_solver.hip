@@ -648,6 +648,69 @@ __device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const 
   }
 }
 
+// The same 64 x 64 complex product for the solve kernels, accumulated in a
+// form chosen by precision: FP32 takes three real products per complex
+// multiply-add (ArBr, AiBi and (Ar + Ai)(Br + Bi); re = ArBr - AiBi, im = the
+// third minus the other two), three quarters of the MFMAs; FP64 keeps the
+// four products of cmma64 (and its rounding).
+template <typename R>
+struct CAcc {
+  typedef typename Mma<R>::v4 v4;
+  static constexpr bool G3 = sizeof(R) == 4;
+  v4 p[3][2][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) p[q][a][b] = v4{R(0), R(0), R(0), R(0)};
+  }
+  __device__ __forceinline__ void mma(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
+                                      int wm, int wn, int lane) {
+    if constexpr (!G3) {
+      cmma64<R>(Ar, Ai, lda, Br, Bi, ldb, K, wm, wn, lane, p[0], p[1]);
+    } else {
+      // two k steps at a time: a full unroll hoists every LDS load of the
+      // chunk and leaves no registers for a second wave per SIMD
+#pragma unroll 2
+      for (int k4 = 0; k4 < K; k4 += 4) {
+        const int kr = k4 + (lane >> 4);
+        R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
+          ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
+          br[a] = Br[kr * ldb + wn + 16 * a + (lane & 15)];
+          bi[a] = Bi[kr * ldb + wn + 16 * a + (lane & 15)];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            p[0][a][b] = Mma<R>::op(ar[a], br[b], p[0][a][b]);
+            p[1][a][b] = Mma<R>::op(ai[a], bi[b], p[1][a][b]);
+            p[2][a][b] = Mma<R>::op(ar[a] + ai[a], br[b] + bi[b], p[2][a][b]);
+          }
+      }
+    }
+  }
+  __device__ __forceinline__ void result(v4 (&cr)[2][2], v4 (&ci)[2][2]) const {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if constexpr (G3) {
+          cr[a][b] = p[0][a][b] - p[1][a][b];
+          ci[a][b] = p[2][a][b] - p[0][a][b] - p[1][a][b];
+        } else {
+          cr[a][b] = p[0][a][b];
+          ci[a][b] = p[1][a][b];
+        }
+      }
+  }
+};
+
 // acc[rt] (rows 16 rt.., rt < 3; the 16 columns col0..col0+15) = A B for a
 // 48 x 48 block A read from global memory (A(i, k) = Ag[i * lda + k] for
 // i < arows and k < acols, zero elsewhere) and B rows of an LDS array
@@ -900,7 +963,7 @@ __global__ __launch_bounds__(256) void hat_kernel(const FrontDev* __restrict__ f
 // rows in X, boundary rows in the node's update vector).  Both read only the
 // block's x rows, which no workgroup writes.  64 rhs per workgroup.
 template <typename R>
-__global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1, 8))) void fwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                      R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
@@ -931,18 +994,15 @@ __global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict_
     }
     const R* Mr = fac + d.m + (long)(kb0 / kSB) * 2 * kSB * kSB;
     const R* Mi = Mr + kSB * kSB;
-    v4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
-      }
+    CAcc<R> acc;
+    acc.zero();
     // the next K chunk is loaded into registers while the MFMAs consume the current one
     constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
     R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
     auto fetch = [&](int kc) {
+      // addresses formed per chunk from an opaque thread index, not kept live
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
       const int kw = min(kT, sw - kc);
 #pragma unroll
       for (int u = 0; u < NUA; ++u) {
@@ -996,9 +1056,11 @@ __global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict_
       }
       __syncthreads();
       if (kc + kT < sw) fetch(kc + kT);
-      cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
+      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane);
       __syncthreads();
     }
+    v4 cr[2][2], ci[2][2];
+    acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1028,7 +1090,7 @@ __global__ __launch_bounds__(256) void fwd_sb_kernel(const FrontDev* __restrict_
 // one split subtracts in place; with more, each split writes its partial sum
 // and u12_reduce_kernel adds them in split order.
 template <typename R>
-__global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1, 8))) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                       int nlvl, int nks_max, long np_max,
                                                       const R* __restrict__ fac, const int* __restrict__ ib, int nrhs,
                                                       const R* __restrict__ Xr, const R* __restrict__ Xi,
@@ -1052,67 +1114,63 @@ __global__ __launch_bounds__(256) void bwd_u12_kernel(const FrontDev* __restrict
     if (i0 >= np) continue;
     const int cnt = (int)min((long)kRB, np - i0);
     const long j0 = (long)ks * kKS, j1 = min(nb, j0 + kKS);
-    v4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
-      }
-    for (long jc = j0; jc < j1; jc += kKC) {
+    CAcc<R> acc;
+    acc.zero();
+    // the next chunk is loaded into registers while the MFMAs consume the current one
+    constexpr int NUA = (kRB * kKC) / 256, NUB = (kKC * kSR) / 256;
+    R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
+    auto fetch = [&](long jc) {
+      // addresses formed per chunk from an opaque thread index, not kept live
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
       const int nj = (int)min((long)kKC, j1 - jc);
-      {  // all loads issued before the LDS stores
-        constexpr int NU = (kRB * kKC) / 256;
-        R ld0_[NU], ld1_[NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int o = tid + 256 * u;
-          const int i = o / kKC, j = o % kKC;
-          R vr = R(0), vi = R(0);
-          if (i < cnt && j < nj) {
-            vr = fac[d.p + (i0 + i) * nf + np + jc + j];
-            vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
-          }
-          ld0_[u] = vr;
-          ld1_[u] = vi;
+      for (int u = 0; u < NUA; ++u) {
+        const int o = tid + 256 * u;
+        const int i = o / kKC, j = o % kKC;
+        R vr = R(0), vi = R(0);
+        if (i < cnt && j < nj) {
+          vr = fac[d.p + (i0 + i) * nf + np + jc + j];
+          vi = fac[d.p + np * nf + (i0 + i) * nf + np + jc + j];
         }
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int o = tid + 256 * u;
-          const int i = o / kKC, j = o % kKC;
-          Ar_[i * LA + j] = ld0_[u];
-          Ai_[i * LA + j] = ld1_[u];
-        }
+        pa0[u] = vr;
+        pa1[u] = vi;
       }
-      {  // all loads issued before the LDS stores
-        constexpr int NU = (kKC * kSR) / 256;
-        R ld0_[NU], ld1_[NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int o = tid + 256 * u;
-          const int j = o / kSR, r = o % kSR;
-          R vr = R(0), vi = R(0);
-          if (j < nj && r < nr) {
-            const long e = ib[d.bm + jc + j];
-            vr = Xr[e * nrhs + r0 + r];
-            vi = Xi[e * nrhs + r0 + r];
-          }
-          ld0_[u] = vr;
-          ld1_[u] = vi;
+      for (int u = 0; u < NUB; ++u) {
+        const int o = tid + 256 * u;
+        const int j = o / kSR, r = o % kSR;
+        R vr = R(0), vi = R(0);
+        if (j < nj && r < nr) {
+          const long e = ib[d.bm + jc + j];
+          vr = Xr[e * nrhs + r0 + r];
+          vi = Xi[e * nrhs + r0 + r];
         }
+        pb0[u] = vr;
+        pb1[u] = vi;
+      }
+    };
+    fetch(j0);
+    for (long jc = j0; jc < j1; jc += kKC) {
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int o = tid + 256 * u;
-          const int j = o / kSR, r = o % kSR;
-          Br_[j * kLX + r] = ld0_[u];
-          Bi_[j * kLX + r] = ld1_[u];
-        }
+      for (int u = 0; u < NUA; ++u) {
+        const int o = tid + 256 * u;
+        Ar_[(o / kKC) * LA + o % kKC] = pa0[u];
+        Ai_[(o / kKC) * LA + o % kKC] = pa1[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NUB; ++u) {
+        const int o = tid + 256 * u;
+        Br_[(o / kSR) * kLX + o % kSR] = pb0[u];
+        Bi_[(o / kSR) * kLX + o % kSR] = pb1[u];
       }
       __syncthreads();
-      cmma64<R>(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane, cr, ci);
+      if (jc + kKC < j1) fetch(jc + kKC);
+      acc.mma(Ar_, Ai_, LA, Br_, Bi_, kLX, kKC, wm, wn, lane);
       __syncthreads();
     }
+    v4 cr[2][2], ci[2][2];
+    acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1161,7 +1219,7 @@ __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restr
 // x_block (64 rows each) = H y_block, written to X.  The others: 64 rows
 // i < kb0: y_i -= Uhat[i][block] y_block.  Both read only the block's y rows.
 template <typename R>
-__global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1, 8))) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                      R* __restrict__ Zi) {
@@ -1192,18 +1250,15 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
     }
     const R* Hr = fac + d.h + (long)(kb0 / kSB) * 2 * kSB * kSB;
     const R* Hi = Hr + kSB * kSB;
-    v4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
-      }
+    CAcc<R> acc;
+    acc.zero();
     // the next K chunk is loaded into registers while the MFMAs consume the current one
     constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
     R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
     auto fetch = [&](int kc) {
+      // addresses formed per chunk from an opaque thread index, not kept live
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
       const int kw = min(kT, sw - kc);
 #pragma unroll
       for (int u = 0; u < NUA; ++u) {
@@ -1251,9 +1306,11 @@ __global__ __launch_bounds__(256) void bwd_sb_kernel(const FrontDev* __restrict_
       }
       __syncthreads();
       if (kc + kT < sw) fetch(kc + kT);
-      cmma64<R>(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane, cr, ci);
+      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane);
       __syncthreads();
     }
+    v4 cr[2][2], ci[2][2];
+    acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
