@@ -15,6 +15,7 @@
 // apply accuracy, so a cycle ends once its estimated residual fell by the
 // factor `mixed_drop`, and the restart recomputes the true residual with the
 // FP64 apply (iterative refinement on top of FGMRES).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -102,6 +103,102 @@ __global__ void residual_kernel(const C<double>* __restrict__ g, C<double>* __re
 
 inline unsigned blocks_for(long len, int t) { return (unsigned)((len + t - 1) / t); }
 
+// ---- fused Gram-Schmidt passes over a run of right-hand sides ----------------
+// The two classical Gram-Schmidt passes and the norm of one Arnoldi step read
+// each Krylov vector three times instead of four and the new vector once per
+// pass instead of once per Krylov vector, and one launch covers every rhs of
+// a contiguous run.  The sums are the same as multidot's, in another order.
+constexpr int kOrthBlk = 64;    // blocks per rhs
+constexpr int kMaxV = 32;       // Krylov vectors a fused pass handles
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// For rhs b = b0 + blockIdx.y (V_q of rhs b at V + q qstride + b len, w at
+// W + b len):
+//   SUB = false:            h_q = sum conj(V_q) w, q < nv;
+//   SUB = true, NORM = false: w -= sum_q V_q hin_q, then h_q = sum conj(V_q) w;
+//   SUB = true, NORM = true:  w -= sum_q V_q hin_q, then h_0 = sum |w|^2.
+// Block partial sums go to partial[(b kOrthBlk + blk) kMaxV + q].
+template <bool SUB, bool NORM>
+__global__ __launch_bounds__(256) void orth_pass_kernel(const C<double>* __restrict__ V, long qstride, int nv,
+                                                        C<double>* __restrict__ W, long len, int b0,
+                                                        const C<double>* __restrict__ hin, long hstride,
+                                                        C<double>* __restrict__ partial) {
+  __shared__ C<double> hl[kMaxV];
+  __shared__ double red[4][2 * kMaxV];
+  const int b = b0 + blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  const C<double>* Vb = V + (long)b * len;
+  C<double>* w = W + (long)b * len;
+  if (SUB && tid < nv) hl[tid] = hin[(long)b * hstride + tid];
+  __syncthreads();
+  constexpr int NA = NORM ? 1 : kMaxV;
+  double ar[NA], ai[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ar[q] = ai[q] = 0.0;
+  for (long e = (long)blk * 256 + tid; e < len; e += (long)kOrthBlk * 256) {
+    C<double> we = w[e];
+    if constexpr (SUB) {
+#pragma unroll
+      for (int q = 0; q < kMaxV; ++q)
+        if (q < nv) we = we - Vb[q * qstride + e] * hl[q];
+      w[e] = we;
+    }
+    if constexpr (NORM) {
+      ar[0] += we.re * we.re + we.im * we.im;
+    } else {
+      // after a subtraction the Krylov values are loaded again (from the
+      // cache) rather than kept: nv of them beside the accumulators would not
+      // fit the registers
+      long e2 = e;
+      if constexpr (SUB) asm volatile("" : "+v"(e2));
+#pragma unroll
+      for (int q = 0; q < kMaxV; ++q)
+        if (q < nv) {
+          const C<double> v = Vb[q * qstride + e2];
+          ar[q] += v.re * we.re + v.im * we.im;
+          ai[q] += v.re * we.im - v.im * we.re;
+        }
+    }
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+    if (q < nv) {
+      const double sr = wave_sum(ar[q]), si = wave_sum(ai[q]);
+      if (lane == 0) {
+        red[wv][2 * q] = sr;
+        red[wv][2 * q + 1] = si;
+      }
+    }
+  __syncthreads();
+  if (tid < (NORM ? 1 : nv)) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      sr += red[k][2 * tid];
+      si += red[k][2 * tid + 1];
+    }
+    partial[((long)b * kOrthBlk + blk) * kMaxV + tid] = cmk(sr, si);
+  }
+}
+
+// out[b hstride + q] = the block partials of rhs b0 + blockIdx.x added in block order
+__global__ void orth_sum_kernel(const C<double>* __restrict__ partial, int nv, int b0, C<double>* __restrict__ out,
+                                long hstride) {
+  const int b = b0 + blockIdx.x, q = threadIdx.x;
+  if (q >= nv) return;
+  double r = 0.0, i = 0.0;
+  for (int k = 0; k < kOrthBlk; ++k) {
+    const C<double> v = partial[((long)b * kOrthBlk + k) * kMaxV + q];
+    r += v.re;
+    i += v.im;
+  }
+  out[(long)b * hstride + q] = cmk(r, i);
+}
+
 }  // namespace
 
 // sums conj(V_q) . w for q < nv into hout (device), blocking
@@ -124,7 +221,7 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
   LS_TRY(ctx.V.alloc(vbytes * (size_t)(m + 1) * nrhs));
   LS_TRY(ctx.Z.alloc(vbytes * (size_t)m * nrhs));
   LS_TRY(ctx.W.alloc(vbytes * (size_t)nrhs));
-  LS_TRY(ctx.partial.alloc(sizeof(C<double>) * 64 * (m + 1)));
+  LS_TRY(ctx.partial.alloc(sizeof(C<double>) * std::max((size_t)64 * (m + 1), (size_t)kOrthBlk * kMaxV * nrhs)));
   // per rhs: h1, h2 (the two Gram-Schmidt passes) and the norm, m + 1 each
   const size_t hslot = (size_t)3 * (m + 1);
   if (ctx.hdev.bytes < sizeof(C<double>) * hslot * nrhs) LS_TRY(ctx.hdev.alloc(sizeof(C<double>) * hslot * nrhs));
@@ -210,7 +307,33 @@ ls_status gmres_solve(GmresContext& ctx, const GmresOps& ops, const C<double>* g
       ++total;
       // classical Gram-Schmidt, two passes, for every live rhs: the
       // coefficients stay on the device for the subtractions; one copy and
-      // one wait bring all of them (and the norms) to the host
+      // one wait bring all of them (and the norms) to the host.  Up to kMaxV
+      // Krylov vectors the fused passes take each contiguous run of live rhs
+      // in one launch per pass.
+      if (j + 1 <= kMaxV) {
+        C<double>* part = ctx.partial.as<C<double>>();
+        const int nv = j + 1;
+        for (size_t i0 = 0; i0 < lb.size();) {
+          size_t i1 = i0 + 1;
+          while (i1 < lb.size() && lb[i1] == lb[i1 - 1] + 1) ++i1;
+          const int b0 = lb[i0], nb = (int)(i1 - i0);
+          const dim3 g(kOrthBlk, nb);
+          hipLaunchKernelGGL((orth_pass_kernel<false, false>), g, dim3(256), 0, s, V, qstride, nv, W, len, b0,
+                             (const C<double>*)nullptr, 0L, part);
+          hipLaunchKernelGGL(orth_sum_kernel, dim3(nb), dim3(kMaxV), 0, s, (const C<double>*)part, nv, b0, hd,
+                             (long)hslot);
+          hipLaunchKernelGGL((orth_pass_kernel<true, false>), g, dim3(256), 0, s, V, qstride, nv, W, len, b0,
+                             (const C<double>*)hd, (long)hslot, part);
+          hipLaunchKernelGGL(orth_sum_kernel, dim3(nb), dim3(kMaxV), 0, s, (const C<double>*)part, nv, b0,
+                             hd + (m + 1), (long)hslot);
+          hipLaunchKernelGGL((orth_pass_kernel<true, true>), g, dim3(256), 0, s, V, qstride, nv, W, len, b0,
+                             (const C<double>*)(hd + (m + 1)), (long)hslot, part);
+          hipLaunchKernelGGL(orth_sum_kernel, dim3(nb), dim3(kMaxV), 0, s, (const C<double>*)part, 1, b0,
+                             hd + 2 * (m + 1), (long)hslot);
+          LS_HIP(hipGetLastError());
+          i0 = i1;
+        }
+      } else
       for (int b : lb) {
         C<double>* h1d = hd + (size_t)b * hslot;
         C<double>* h2d = h1d + (m + 1);
