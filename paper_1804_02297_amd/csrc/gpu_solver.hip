@@ -590,6 +590,74 @@ __global__ __launch_bounds__(256) void sol_out_kernel(C<double>* __restrict__ b,
   }
 }
 
+// The same two copies as tiled transposes through LDS, for many right-hand
+// sides: a workgroup takes 64 natural unknowns p and 64 rhs r, reads b[r][p]
+// along p and writes row ipm[p] of X along r, so both sides are whole runs
+// (the per-row kernels above read or write 64 separate lines per row).
+// ipm is the inverse of the elimination order: ipm[ib[e]] = e.
+constexpr int kTP = 64;
+constexpr int kSolTileRhs = 16;    // from this many rhs on the copies take the tiled kernels
+__global__ void inv_perm_kernel(const int* __restrict__ perm, long N, int* __restrict__ ipm) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x)
+    ipm[perm[e]] = (int)e;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void sol_in_tile_kernel(const C<double>* __restrict__ b, long N, int nrhs,
+                                                          const int* __restrict__ ipm, R* __restrict__ Xr,
+                                                          R* __restrict__ Xi) {
+  __shared__ R tr[kTP][kTP + 1], ti[kTP][kTP + 1];   // [p][r]
+  const long p0 = (long)blockIdx.x * kTP;
+  const int r0 = blockIdx.y * kTP;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int rr = wv; rr < kTP; rr += 4) {
+    const int r = r0 + rr;
+    const long p = p0 + lane;
+    C<double> v = cmk(0.0, 0.0);
+    if (r < nrhs && p < N) v = b[(long)r * N + p];
+    tr[lane][rr] = (R)v.re;
+    ti[lane][rr] = (R)v.im;
+  }
+  __syncthreads();
+  for (int pp = wv; pp < kTP; pp += 4) {
+    const long p = p0 + pp;
+    const int r = r0 + lane;
+    if (p < N && r < nrhs) {
+      const long e = ipm[p];
+      Xr[e * nrhs + r] = tr[pp][lane];
+      Xi[e * nrhs + r] = ti[pp][lane];
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void sol_out_tile_kernel(C<double>* __restrict__ b, long N, int nrhs,
+                                                           const int* __restrict__ ipm, const R* __restrict__ Xr,
+                                                           const R* __restrict__ Xi) {
+  __shared__ R tr[kTP][kTP + 1], ti[kTP][kTP + 1];   // [p][r]
+  const long p0 = (long)blockIdx.x * kTP;
+  const int r0 = blockIdx.y * kTP;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int pp = wv; pp < kTP; pp += 4) {
+    const long p = p0 + pp;
+    const int r = r0 + lane;
+    R vr = R(0), vi = R(0);
+    if (p < N && r < nrhs) {
+      const long e = ipm[p];
+      vr = Xr[e * nrhs + r];
+      vi = Xi[e * nrhs + r];
+    }
+    tr[pp][lane] = vr;
+    ti[pp][lane] = vi;
+  }
+  __syncthreads();
+  for (int rr = wv; rr < kTP; rr += 4) {
+    const int r = r0 + rr;
+    const long p = p0 + lane;
+    if (r < nrhs && p < N) b[(long)r * N + p] = cmk((double)tr[lane][rr], (double)ti[lane][rr]);
+  }
+}
+
 // children's update vectors into the pivot rows (x) or the update vector (u)
 // of every front of a level, for child `slot`; 256 / rhs_lanes(nrhs) rows per workgroup pass
 template <typename R, int NC>
@@ -1543,6 +1611,7 @@ struct GpuSolver {
   std::vector<int> lvl_np, lvl_nf;     // largest np / nf per level
   std::vector<size_t> lvl_elems;       // level buffer elements (R) per level
   DevBuf fd, lvl_d, ib, fac;
+  DevBuf ipm;                          // inverse of the final elimination order (natural -> position)
   long u_rows = 0;                     // sum of nb over the nodes
   DevBuf X, Z, U;                      // solve work, sized for cap_rhs
   DevBuf P;                            // split-K partial sums of the U12 products
@@ -1628,6 +1697,10 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
     hipLaunchKernelGGL((hat_kernel<R, 1>), dim3(hx, hy, gy), dim3(256), 0, s, fr, lvl, nl, (const R*)buf, fac);
     LS_HIP(hipGetLastError());
   }
+  // the elimination order is final once the pivots are chosen
+  hipLaunchKernelGGL(inv_perm_kernel, dim3(grid_for(g.N, 256, 1 << 16)), dim3(256), 0, s, (const int*)ib, g.N,
+                     g.ipm.as<int>());
+  LS_HIP(hipGetLastError());
   LS_HIP(hipStreamSynchronize(s));
   return LS_OK;
 }
@@ -1665,7 +1738,11 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
   const R* fac = g.fac.as<R>();
   const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
   const int rpp = 256 / rhs_lanes(nrhs);     // rows per workgroup pass of the gather kernels
-  hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
+  if (nrhs >= kSolTileRhs)
+    hipLaunchKernelGGL(sol_in_tile_kernel<R>, dim3((unsigned)((N + kTP - 1) / kTP), (unsigned)((nrhs + kTP - 1) / kTP)),
+                       dim3(256), 0, s, b, N, nrhs, (const int*)g.ipm.as<int>(), Xr, Xi);
+  else
+    hipLaunchKernelGGL(sol_in_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, b, N, nrhs, ib, Xr, Xi);
   hipLaunchKernelGGL(zero_kernel<R>, dim3(grid_for(2 * std::max(1L, g.u_rows) * nrhs, 256, 1 << 16)), dim3(256), 0,
                      s, Ur, 2 * std::max(1L, g.u_rows) * nrhs);
   for (int dep = L - 1; dep >= 0; --dep) {
@@ -1730,8 +1807,12 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                            Xr, Xi, Zr, Zi);
     }
   }
-  hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, xo, N, nrhs, ib, (const R*)Xr,
-                     (const R*)Xi);
+  if (nrhs >= kSolTileRhs)
+    hipLaunchKernelGGL(sol_out_tile_kernel<R>, dim3((unsigned)((N + kTP - 1) / kTP), (unsigned)((nrhs + kTP - 1) / kTP)),
+                       dim3(256), 0, s, xo, N, nrhs, (const int*)g.ipm.as<int>(), (const R*)Xr, (const R*)Xi);
+  else
+    hipLaunchKernelGGL(sol_out_kernel<R>, dim3(grid_for(N, rpp, 65535)), dim3(256), 0, s, xo, N, nrhs, ib,
+                       (const R*)Xr, (const R*)Xi);
   LS_HIP(hipGetLastError());
   return LS_OK;
 }
@@ -1770,6 +1851,7 @@ ls_status gpu_factor_grid(const int dims[3], int nc, const C<double>* rows_dev, 
   const size_t rs = fp32 ? sizeof(float) : sizeof(double);
   LS_TRY(g->fac.alloc((size_t)fac_elems * rs));
   LS_TRY(g->ib.alloc(ibh.size() * sizeof(int)));
+  LS_TRY(g->ipm.alloc((size_t)std::max(1L, g->N) * sizeof(int)));
   LS_TRY(g->fd.alloc(g->fh.size() * sizeof(FrontDev)));
   std::vector<int> lv;
   for (const auto& l : g->levels) lv.insert(lv.end(), l.begin(), l.end());
