@@ -721,18 +721,19 @@ __device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const 
 // multiply-add (ArBr, AiBi and (Ar + Ai)(Br + Bi); re = ArBr - AiBi, im = the
 // third minus the other two), three quarters of the MFMAs; FP64 keeps the
 // four products of cmma64 (and its rounding).
-template <typename R>
+template <typename R, int NBW = 2>   // NBW: 16-column B tiles per wave
 struct CAcc {
   typedef typename Mma<R>::v4 v4;
   static constexpr bool G3 = sizeof(R) == 4;
-  v4 p[3][2][2];
+  static_assert(G3 || NBW == 2, "the four-product form is cmma64's 2 x 2 tiles");
+  v4 p[3][2][NBW];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) p[q][a][b] = v4{R(0), R(0), R(0), R(0)};
+        for (int b = 0; b < NBW; ++b) p[q][a][b] = v4{R(0), R(0), R(0), R(0)};
   }
   __device__ __forceinline__ void mma(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
                                       int wm, int wn, int lane) {
@@ -744,18 +745,21 @@ struct CAcc {
 #pragma unroll 2
       for (int k4 = 0; k4 < K; k4 += 4) {
         const int kr = k4 + (lane >> 4);
-        R ar[2], ai[2], br[2], bi[2];
+        R ar[2], ai[2], br[NBW], bi[NBW];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
           ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
-          br[a] = Br[kr * ldb + wn + 16 * a + (lane & 15)];
-          bi[a] = Bi[kr * ldb + wn + 16 * a + (lane & 15)];
+        }
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+          br[b] = Br[kr * ldb + wn + 16 * b + (lane & 15)];
+          bi[b] = Bi[kr * ldb + wn + 16 * b + (lane & 15)];
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < NBW; ++b) {
             p[0][a][b] = Mma<R>::op(ar[a], br[b], p[0][a][b]);
             p[1][a][b] = Mma<R>::op(ai[a], bi[b], p[1][a][b]);
             p[2][a][b] = Mma<R>::op(ar[a] + ai[a], br[b] + bi[b], p[2][a][b]);
@@ -763,11 +767,11 @@ struct CAcc {
       }
     }
   }
-  __device__ __forceinline__ void result(v4 (&cr)[2][2], v4 (&ci)[2][2]) const {
+  __device__ __forceinline__ void result(v4 (&cr)[2][NBW], v4 (&ci)[2][NBW]) const {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < NBW; ++b) {
         if constexpr (G3) {
           cr[a][b] = p[0][a][b] - p[1][a][b];
           ci[a][b] = p[2][a][b] - p[0][a][b] - p[1][a][b];
@@ -1029,20 +1033,22 @@ __global__ __launch_bounds__(256) void hat_kernel(const FrontDev* __restrict__ f
 // level.  Workgroups [0, 3): z_block (64 rows each) = M x_block, written to Z.
 // The others: 64 rows i below the block: x_i -= Lhat[i][block] x_block (pivot
 // rows in X, boundary rows in the node's update vector).  Both read only the
-// block's x rows, which no workgroup writes.  64 rhs per workgroup.
-template <typename R>
+// block's x rows, which no workgroup writes.  SR rhs per workgroup (64, or
+// 32 in FP32 launches of few workgroups).
+template <typename R, int SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1, 8))) void fwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                      R* __restrict__ Zi, R* __restrict__ Ur, R* __restrict__ Ui) {
   typedef typename Mma<R>::v4 v4;
+  constexpr int LX = SR + 1, NBW = SR / 32;
   constexpr int NZB = kSB / kRB;
   __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
-  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
+  __shared__ R Br_[kT * LX], Bi_[kT * LX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int r0 = blockIdx.z * kSR;
-  const int nr = min(kSR, nrhs - r0);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * (SR / 2);
+  const int r0 = blockIdx.z * SR;
+  const int nr = min(SR, nrhs - r0);
   const bool zrole = (int)blockIdx.x < NZB;
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
@@ -1062,10 +1068,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     }
     const R* Mr = fac + d.m + (long)(kb0 / kSB) * 2 * kSB * kSB;
     const R* Mi = Mr + kSB * kSB;
-    CAcc<R> acc;
+    CAcc<R, NBW> acc;
     acc.zero();
     // the next K chunk is loaded into registers while the MFMAs consume the current one
-    constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
+    constexpr int NUA = (kRB * kT) / 256, NUB = (kT * SR) / 256;
     R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
     auto fetch = [&](int kc) {
       // addresses formed per chunk from an opaque thread index, not kept live
@@ -1098,7 +1104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 #pragma unroll
       for (int u = 0; u < NUB; ++u) {
         const int o = tid + 256 * u;
-        const int k = o / kSR, r = o % kSR;
+        const int k = o / SR, r = o % SR;
         R vr = R(0), vi = R(0);
         if (k < kw && r < nr) {
           vr = Xr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
@@ -1119,20 +1125,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 #pragma unroll
       for (int u = 0; u < NUB; ++u) {
         const int o = tid + 256 * u;
-        Br_[(o / kSR) * kLX + o % kSR] = pb0[u];
-        Bi_[(o / kSR) * kLX + o % kSR] = pb1[u];
+        Br_[(o / SR) * LX + o % SR] = pb0[u];
+        Bi_[(o / SR) * LX + o % SR] = pb1[u];
       }
       __syncthreads();
       if (kc + kT < sw) fetch(kc + kT);
-      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane);
+      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, LX, kT, wm, wn, lane);
       __syncthreads();
     }
-    v4 cr[2][2], ci[2][2];
+    v4 cr[2][NBW], ci[2][NBW];
     acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
@@ -1286,19 +1292,21 @@ __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restr
 // Backward solve step of super-block [kb0, kb0 + sw).  Workgroups [0, 3):
 // x_block (64 rows each) = H y_block, written to X.  The others: 64 rows
 // i < kb0: y_i -= Uhat[i][block] y_block.  Both read only the block's y rows.
-template <typename R>
+// SR rhs per workgroup, as in fwd_sb_kernel.
+template <typename R, int SR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1, 8))) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                      R* __restrict__ Zi) {
   typedef typename Mma<R>::v4 v4;
+  constexpr int LX = SR + 1, NBW = SR / 32;
   constexpr int NZB = kSB / kRB;
   __shared__ R Ar_[kRB * kLL], Ai_[kRB * kLL];
-  __shared__ R Br_[kT * kLX], Bi_[kT * kLX];
+  __shared__ R Br_[kT * LX], Bi_[kT * LX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int r0 = blockIdx.z * kSR;
-  const int nr = min(kSR, nrhs - r0);
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * (SR / 2);
+  const int r0 = blockIdx.z * SR;
+  const int nr = min(SR, nrhs - r0);
   const bool xrole = (int)blockIdx.x < NZB;
   for (int q = blockIdx.y; q < nlvl; q += gridDim.y) {
     const FrontDev d = fr[lvl[q]];
@@ -1318,10 +1326,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
     }
     const R* Hr = fac + d.h + (long)(kb0 / kSB) * 2 * kSB * kSB;
     const R* Hi = Hr + kSB * kSB;
-    CAcc<R> acc;
+    CAcc<R, NBW> acc;
     acc.zero();
     // the next K chunk is loaded into registers while the MFMAs consume the current one
-    constexpr int NUA = (kRB * kT) / 256, NUB = (kT * kSR) / 256;
+    constexpr int NUA = (kRB * kT) / 256, NUB = (kT * SR) / 256;
     R pa0[NUA], pa1[NUA], pb0[NUB], pb1[NUB];
     auto fetch = [&](int kc) {
       // addresses formed per chunk from an opaque thread index, not kept live
@@ -1348,7 +1356,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 #pragma unroll
       for (int u = 0; u < NUB; ++u) {
         const int o = tid + 256 * u;
-        const int k = o / kSR, r = o % kSR;
+        const int k = o / SR, r = o % SR;
         R vr = R(0), vi = R(0);
         if (k < kw && r < nr) {
           vr = Zr[(d.e0 + kb0 + kc + k) * (long)nrhs + r0 + r];
@@ -1369,20 +1377,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 #pragma unroll
       for (int u = 0; u < NUB; ++u) {
         const int o = tid + 256 * u;
-        Br_[(o / kSR) * kLX + o % kSR] = pb0[u];
-        Bi_[(o / kSR) * kLX + o % kSR] = pb1[u];
+        Br_[(o / SR) * LX + o % SR] = pb0[u];
+        Bi_[(o / SR) * LX + o % SR] = pb1[u];
       }
       __syncthreads();
       if (kc + kT < sw) fetch(kc + kT);
-      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, kLX, kT, wm, wn, lane);
+      acc.mma(Ar_, Ai_, kLL, Br_, Bi_, LX, kT, wm, wn, lane);
       __syncthreads();
     }
-    v4 cr[2][2], ci[2][2];
+    v4 cr[2][NBW], ci[2][NBW];
     acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < NBW; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = wm + 16 * a + Mma<R>::row(lane, r), col = wn + 16 * b + (lane & 15);
@@ -1705,6 +1713,35 @@ ls_status factor_numeric(GpuSolver& g, const C<double>* rows, hipStream_t s) {
   return LS_OK;
 }
 
+// FP32 super-block launches with fewer than this many 64-rhs workgroups (the
+// few large fronts at the top of the tree) take 32-rhs tiles on twice the
+// workgroups; the factor blocks are then read once per 32 rhs.
+constexpr long kSplitWg = 512;
+
+template <typename R>
+void launch_sb(bool fwd, unsigned gx, unsigned gy, int nrhs, hipStream_t s, const FrontDev* fr, const int* lvl,
+               int nl, int kb0, const R* fac, R* Xr, R* Xi, R* Zr, R* Zi, R* Ur, R* Ui) {
+  const unsigned gz = (unsigned)((nrhs + kSR - 1) / kSR);
+  if constexpr (sizeof(R) == 4) {
+    if ((long)gx * gy * gz < kSplitWg) {
+      const unsigned gz2 = (unsigned)((nrhs + 31) / 32);
+      if (fwd)
+        hipLaunchKernelGGL((fwd_sb_kernel<R, 32>), dim3(gx, gy, gz2), dim3(256), 0, s, fr, lvl, nl, kb0, fac, nrhs,
+                           Xr, Xi, Zr, Zi, Ur, Ui);
+      else
+        hipLaunchKernelGGL((bwd_sb_kernel<R, 32>), dim3(gx, gy, gz2), dim3(256), 0, s, fr, lvl, nl, kb0, fac, nrhs,
+                           Xr, Xi, Zr, Zi);
+      return;
+    }
+  }
+  if (fwd)
+    hipLaunchKernelGGL((fwd_sb_kernel<R, kSR>), dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, kb0, fac, nrhs, Xr,
+                       Xi, Zr, Zi, Ur, Ui);
+  else
+    hipLaunchKernelGGL((bwd_sb_kernel<R, kSR>), dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, kb0, fac, nrhs, Xr,
+                       Xi, Zr, Zi);
+}
+
 template <typename R>
 ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrhs, hipStream_t s) {
   const int L = (int)g.levels.size();
@@ -1774,8 +1811,7 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                            nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
       }
       else
-        hipLaunchKernelGGL(fwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
-                           Xr, Xi, Zr, Zi, Ur, Ui);
+        launch_sb<R>(true, gx, gy, nrhs, s, fr, lvl, nl, (int)kb0, fac, Xr, Xi, Zr, Zi, Ur, Ui);
     }
   }
   for (int dep = 0; dep < L; ++dep) {
@@ -1803,8 +1839,7 @@ ls_status solve_numeric(GpuSolver& g, const C<double>* b, C<double>* xo, int nrh
                            nrhs, Xr, Xi, Zr, Zi, Ur, Ui);
       }
       else
-        hipLaunchKernelGGL(bwd_sb_kernel<R>, dim3(gx, gy, gz), dim3(256), 0, s, fr, lvl, nl, (int)kb0, fac, nrhs,
-                           Xr, Xi, Zr, Zi);
+        launch_sb<R>(false, gx, gy, nrhs, s, fr, lvl, nl, (int)kb0, fac, Xr, Xi, Zr, Zi, Ur, Ui);
     }
   }
   if (nrhs >= kSolTileRhs)
