@@ -404,9 +404,104 @@ __global__ __launch_bounds__(256) void panel_kernel(const FrontDev* __restrict__
   }
 }
 
+// 64 x 64 complex tile product acc += A B on MFMA: A [64][lda] (rows x K) and
+// B [K][ldb] in LDS, K a multiple of 4; wave (wm, wn) owns a 32 x 32 quarter.
+template <typename R>
+__device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
+                                       int wm, int wn, int lane, typename Mma<R>::v4 (&cr)[2][2],
+                                       typename Mma<R>::v4 (&ci)[2][2]) {
+  for (int k4 = 0; k4 < K; k4 += 4) {
+    const int kr = k4 + (lane >> 4);
+    R ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
+      ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
+      br[a] = Br[kr * ldb + wn + 16 * a + (lane & 15)];
+      bi[a] = Bi[kr * ldb + wn + 16 * a + (lane & 15)];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = Mma<R>::op(ar[a], br[b], cr[a][b]);
+        cr[a][b] = Mma<R>::op(-ai[a], bi[b], cr[a][b]);
+        ci[a][b] = Mma<R>::op(ar[a], bi[b], ci[a][b]);
+        ci[a][b] = Mma<R>::op(ai[a], br[b], ci[a][b]);
+      }
+  }
+}
+
+// The same 64 x 64 complex product for the solve kernels, accumulated in a
+// form chosen by precision: FP32 takes three real products per complex
+// multiply-add (ArBr, AiBi and (Ar + Ai)(Br + Bi); re = ArBr - AiBi, im = the
+// third minus the other two), three quarters of the MFMAs; FP64 keeps the
+// four products of cmma64 (and its rounding).
+template <typename R, int NBW = 2>   // NBW: 16-column B tiles per wave
+struct CAcc {
+  typedef typename Mma<R>::v4 v4;
+  static constexpr bool G3 = sizeof(R) == 4;
+  static_assert(G3 || NBW == 2, "the four-product form is cmma64's 2 x 2 tiles");
+  v4 p[3][2][NBW];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) p[q][a][b] = v4{R(0), R(0), R(0), R(0)};
+  }
+  __device__ __forceinline__ void mma(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
+                                      int wm, int wn, int lane) {
+    if constexpr (!G3) {
+      cmma64<R>(Ar, Ai, lda, Br, Bi, ldb, K, wm, wn, lane, p[0], p[1]);
+    } else {
+      // two k steps at a time: a full unroll hoists every LDS load of the
+      // chunk and leaves no registers for a second wave per SIMD
+#pragma unroll 2
+      for (int k4 = 0; k4 < K; k4 += 4) {
+        const int kr = k4 + (lane >> 4);
+        R ar[2], ai[2], br[NBW], bi[NBW];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
+          ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
+        }
+#pragma unroll
+        for (int b = 0; b < NBW; ++b) {
+          br[b] = Br[kr * ldb + wn + 16 * b + (lane & 15)];
+          bi[b] = Bi[kr * ldb + wn + 16 * b + (lane & 15)];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < NBW; ++b) {
+            p[0][a][b] = Mma<R>::op(ar[a], br[b], p[0][a][b]);
+            p[1][a][b] = Mma<R>::op(ai[a], bi[b], p[1][a][b]);
+            p[2][a][b] = Mma<R>::op(ar[a] + ai[a], br[b] + bi[b], p[2][a][b]);
+          }
+      }
+    }
+  }
+  __device__ __forceinline__ void result(v4 (&cr)[2][NBW], v4 (&ci)[2][NBW]) const {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        if constexpr (G3) {
+          cr[a][b] = p[0][a][b] - p[1][a][b];
+          ci[a][b] = p[2][a][b] - p[0][a][b] - p[1][a][b];
+        } else {
+          cr[a][b] = p[0][a][b];
+          ci[a][b] = p[1][a][b];
+        }
+      }
+  }
+};
+
 // Schur updates F[rows][cols] -= F[rows][K] F[K][cols] on a 64 x 64 tile per
-// workgroup (four waves of 32 x 32, the complex product as four real MFMA
-// products).  With the 48-column step kb inside the outer block starting at
+// workgroup (four waves of 32 x 32, the complex product as CAcc forms it:
+// three real MFMA products in FP32, four in FP64).  With the 48-column step kb inside the outer block starting at
 // kb0 (obe = min(kb0 + kOB, np)):
 //   mode 0: rows [ke, nf), cols [ke, obe), K = the step's columns
 //   mode 1: rows [ke, obe), cols [obe, nf), K = the step's columns
@@ -450,14 +545,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
     const long kb_ = k0;
     R* Fr = buf + d.f;
     R* Fi = Fr + nf * nf;
-    v4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = v4{R(0), R(0), R(0), R(0)};
-        ci[a][b] = v4{R(0), R(0), R(0), R(0)};
-      }
+    CAcc<R> acc;
+    acc.zero();
     // the next 16-deep K chunk is loaded into registers while the MFMAs
     // consume the current one from LDS
     R par[4], pai[4], pbr[4], pbi[4];
@@ -489,29 +578,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
       }
       __syncthreads();
       if (kc + 16 < tw) fetch(kc + 16);
-#pragma unroll
-      for (int k4 = 0; k4 < 16; k4 += 4) {
-        const int kr = k4 + (lane >> 4);
-        R ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          ar[a] = Ar[wm + 16 * a + (lane & 15)][kr];
-          ai[a] = Ai[wm + 16 * a + (lane & 15)][kr];
-          br[a] = Br[kr][wn + 16 * a + (lane & 15)];
-          bi[a] = Bi[kr][wn + 16 * a + (lane & 15)];
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            cr[a][b] = Mma<R>::op(ar[a], br[b], cr[a][b]);
-            cr[a][b] = Mma<R>::op(-ai[a], bi[b], cr[a][b]);
-            ci[a][b] = Mma<R>::op(ar[a], bi[b], ci[a][b]);
-            ci[a][b] = Mma<R>::op(ai[a], br[b], ci[a][b]);
-          }
-      }
+      acc.mma(&Ar[0][0], &Ai[0][0], 17, &Br[0][0], &Bi[0][0], 65, 16, wm, wn, lane);
       __syncthreads();
     }
+    v4 cr[2][2], ci[2][2];
+    acc.result(cr, ci);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -687,101 +758,6 @@ __global__ __launch_bounds__(256) void fwd_child_kernel(const FrontDev* __restri
     }
   }
 }
-
-// 64 x 64 complex tile product acc += A B on MFMA: A [64][lda] (rows x K) and
-// B [K][ldb] in LDS, K a multiple of 4; wave (wm, wn) owns a 32 x 32 quarter.
-template <typename R>
-__device__ __forceinline__ void cmma64(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
-                                       int wm, int wn, int lane, typename Mma<R>::v4 (&cr)[2][2],
-                                       typename Mma<R>::v4 (&ci)[2][2]) {
-  for (int k4 = 0; k4 < K; k4 += 4) {
-    const int kr = k4 + (lane >> 4);
-    R ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
-      ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
-      br[a] = Br[kr * ldb + wn + 16 * a + (lane & 15)];
-      bi[a] = Bi[kr * ldb + wn + 16 * a + (lane & 15)];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        cr[a][b] = Mma<R>::op(ar[a], br[b], cr[a][b]);
-        cr[a][b] = Mma<R>::op(-ai[a], bi[b], cr[a][b]);
-        ci[a][b] = Mma<R>::op(ar[a], bi[b], ci[a][b]);
-        ci[a][b] = Mma<R>::op(ai[a], br[b], ci[a][b]);
-      }
-  }
-}
-
-// The same 64 x 64 complex product for the solve kernels, accumulated in a
-// form chosen by precision: FP32 takes three real products per complex
-// multiply-add (ArBr, AiBi and (Ar + Ai)(Br + Bi); re = ArBr - AiBi, im = the
-// third minus the other two), three quarters of the MFMAs; FP64 keeps the
-// four products of cmma64 (and its rounding).
-template <typename R, int NBW = 2>   // NBW: 16-column B tiles per wave
-struct CAcc {
-  typedef typename Mma<R>::v4 v4;
-  static constexpr bool G3 = sizeof(R) == 4;
-  static_assert(G3 || NBW == 2, "the four-product form is cmma64's 2 x 2 tiles");
-  v4 p[3][2][NBW];
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < NBW; ++b) p[q][a][b] = v4{R(0), R(0), R(0), R(0)};
-  }
-  __device__ __forceinline__ void mma(const R* Ar, const R* Ai, int lda, const R* Br, const R* Bi, int ldb, int K,
-                                      int wm, int wn, int lane) {
-    if constexpr (!G3) {
-      cmma64<R>(Ar, Ai, lda, Br, Bi, ldb, K, wm, wn, lane, p[0], p[1]);
-    } else {
-      // two k steps at a time: a full unroll hoists every LDS load of the
-      // chunk and leaves no registers for a second wave per SIMD
-#pragma unroll 2
-      for (int k4 = 0; k4 < K; k4 += 4) {
-        const int kr = k4 + (lane >> 4);
-        R ar[2], ai[2], br[NBW], bi[NBW];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          ar[a] = Ar[(wm + 16 * a + (lane & 15)) * lda + kr];
-          ai[a] = Ai[(wm + 16 * a + (lane & 15)) * lda + kr];
-        }
-#pragma unroll
-        for (int b = 0; b < NBW; ++b) {
-          br[b] = Br[kr * ldb + wn + 16 * b + (lane & 15)];
-          bi[b] = Bi[kr * ldb + wn + 16 * b + (lane & 15)];
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < NBW; ++b) {
-            p[0][a][b] = Mma<R>::op(ar[a], br[b], p[0][a][b]);
-            p[1][a][b] = Mma<R>::op(ai[a], bi[b], p[1][a][b]);
-            p[2][a][b] = Mma<R>::op(ar[a] + ai[a], br[b] + bi[b], p[2][a][b]);
-          }
-      }
-    }
-  }
-  __device__ __forceinline__ void result(v4 (&cr)[2][NBW], v4 (&ci)[2][NBW]) const {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < NBW; ++b) {
-        if constexpr (G3) {
-          cr[a][b] = p[0][a][b] - p[1][a][b];
-          ci[a][b] = p[2][a][b] - p[0][a][b] - p[1][a][b];
-        } else {
-          cr[a][b] = p[0][a][b];
-          ci[a][b] = p[1][a][b];
-        }
-      }
-  }
-};
 
 // acc[rt] (rows 16 rt.., rt < 3; the 16 columns col0..col0+15) = A B for a
 // 48 x 48 block A read from global memory (A(i, k) = Ag[i * lda + k] for
