@@ -58,16 +58,19 @@ def test_point_fit_zero_medium_is_class_fit(lib):
         assert np.abs(ost.projector(al[p]) - ost.projector(cal[13])).max() <= 1e-9
 
 
-def test_point_fit_preconditioner_matches_oracle(lib):
-    """S^-1 Q v with the per-point stencils against the oracle's sparse LU on the same stencils."""
+@pytest.mark.parametrize("nrhs", [1, 5, 11])
+def test_point_fit_preconditioner_matches_oracle(lib, nrhs):
+    """S^-1 Q v with the per-point stencils against the oracle's sparse LU on
+    the same stencils, for every rhs (Q v takes one, four or eight rhs per
+    thread by batch size; 5 and 11 leave a partial group)."""
     n = 8
     k = I.wavenumber_for(n)
     m = I.medium_bumps(n, 3)
-    plan = _plan(n, m)
+    plan = _plan(n, m, max_rhs=nrhs)
     plan.stencil_fit(LS_FIT_POINT)
     plan.factor()
     al, _ = plan.point_stencils()
-    v = I.random_field(1, n, 4)
+    v = I.random_field(nrhs, n, 4)
     z = plan.precond(torch.from_numpy(v).to("cuda:0")).cpu().numpy()
     B13 = ost.local_block(13, n, k)
     cal, cbe, _ = plan.class_stencils()
@@ -81,5 +84,7 @@ def test_point_fit_preconditioner_matches_oracle(lib):
         return a, cbe[kappa, :R]
 
     S, Q = osp.assemble_pointwise(n, m, stencil_of)
-    ref = osp.Preconditioner(S, Q)(v[0])
-    assert np.abs(z[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+    pre = osp.Preconditioner(S, Q)
+    for r in range(nrhs):
+        ref = pre(v[r])
+        assert np.abs(z[r] - ref).max() <= 1e-9 * np.abs(ref).max(), r
