@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 // one split subtracts in place; with more, each split writes its partial sum
 // and u12_reduce_kernel adds them in split order.
 template <typename R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1, 8))) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1, 8))) void bwd_u12_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                       int nlvl, int nks_max, long np_max,
                                                       const R* __restrict__ fac, const int* __restrict__ ib, int nrhs,
                                                       const R* __restrict__ Xr, const R* __restrict__ Xi,
@@ -1270,7 +1270,7 @@ __global__ __launch_bounds__(256) void u12_reduce_kernel(const FrontDev* __restr
 // i < kb0: y_i -= Uhat[i][block] y_block.  Both read only the block's y rows.
 // SR rhs per workgroup, as in fwd_sb_kernel.
 template <typename R, int SR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1, 8))) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (SR == 32 ? 4 : 3) : 1, 8))) void bwd_sb_kernel(const FrontDev* __restrict__ fr, const int* __restrict__ lvl,
                                                      int nlvl, int kb0, const R* __restrict__ fac, int nrhs,
                                                      R* __restrict__ Xr, R* __restrict__ Xi, R* __restrict__ Zr,
                                                      R* __restrict__ Zi) {
